@@ -1,0 +1,945 @@
+/*
+ * heat_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, serial, deliberately unoptimised FP64 implementation of the
+ * space-time heat solver of Speck, Ruprecht, Emmett, Bolten and Krause,
+ * "A space-time parallel solver for the three-dimensional heat equation"
+ * (arXiv 1307.7867).  It exists so that the GPU library can be checked
+ * against something written straight from the mathematics.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it; the GPU library never links against it and shares no code with it.
+ *
+ * Every function names the passage of the paper (section / equation) it
+ * follows.  Where the paper is silent (multigrid components, stopping rules,
+ * wall closure of the wide 4th-order stencil, predictor) the reading used is
+ * stated at the function.
+ *
+ * Grid convention (section 1, eqs. (1)-(2)): n interior points per axis,
+ * h = 1/(n+1), interior point (i,j,k), 0-based, sits at x = ((i+1)h,
+ * (j+1)h, (k+1)h); u = 0 on the walls.  Arrays are [k][j][i] with i fastest.
+ *
+ * Compile with -ffp-contract=off: no fused multiply-adds, so every
+ * expression is rounded exactly as written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOCONV (-3)
+#define OR_ENONFINITE (-4)
+
+#define OR_MAXM 8
+
+typedef struct {
+    int32_t nu1, nu2;     /* pre / post smoothing sweeps */
+    double omega;         /* Jacobi weight */
+    int32_t n_coarsest;   /* grid solved exactly (1 or 3) */
+    double tol;           /* relative max-norm residual target */
+    int32_t max_cycles;   /* cap on V-cycles when iterating to tol */
+    int32_t fixed_cycles; /* > 0: exactly this many V-cycles, no test */
+} or_mg;
+
+typedef struct {
+    int32_t n;      /* interior points per axis */
+    int32_t order;  /* 2 or 4 */
+    int32_t M;      /* collocation nodes including both ends */
+} or_level;
+
+typedef struct {
+    double nu, t0, dt, forcing_c;
+    int32_t nsteps;
+    int32_t sweeps;      /* fixed sweeps / MLSDC iterations; 0 = iterate to sdc_tol */
+    double sdc_tol;
+    int32_t max_sweeps;
+    int32_t nlevels;     /* 1 = SDC, 2 = MLSDC */
+    or_level lev[2];     /* lev[0] fine, lev[1] coarse */
+    or_mg mg;
+} or_problem;
+
+typedef struct {
+    int32_t status;
+    int32_t sweeps;          /* sweeps (or MLSDC iterations) of the last step */
+    int32_t total_sweeps;
+    int32_t total_solves;
+    int64_t total_cycles;    /* V-cycles over all solves */
+    int32_t max_cycles_seen;
+    double last_residual;    /* collocation residual after the last sweep */
+} or_stats;
+
+/* ------------------------------------------------------------------ */
+/* Grid helpers                                                        */
+/* ------------------------------------------------------------------ */
+
+static size_t cube(int n) { return (size_t)n * (size_t)n * (size_t)n; }
+
+static int valid_n(int n)
+{
+    /* n = 2^k - 1 with 1 <= n <= 1023 */
+    if (n < 1 || n > 1023) return 0;
+    return ((n + 1) & n) == 0;
+}
+
+double or_grid_h(int n) { return 1.0 / (double)(n + 1); }
+
+static double *alloc0(size_t count)
+{
+    double *p = (double *)calloc(count ? count : 1, sizeof(double));
+    if (!p) abort();
+    return p;
+}
+
+/*
+ * Value of u along one axis at 0-based index q of a line whose other two
+ * indices are fixed.  Indices 0..n-1 are interior points; -1 and n are the
+ * walls where u = 0 (eq. (2)).  The wide 4th-order stencil also reaches -2
+ * and n+1: there the odd reflection u(-2) = -u(0), u(n+1) = -u(n-1) is used
+ * (the paper gives no wall closure for its 4th-order operator; the odd
+ * reflection keeps the discrete sine modes exact eigenvectors).
+ */
+static double line_val(const double *u, int n, int i, int j, int k, int axis, int q)
+{
+    int sign = 1;
+    if (q == -1 || q == n) return 0.0;
+    if (q == -2) { q = 0; sign = -1; }
+    if (q == n + 1) { q = n - 1; sign = -1; }
+    if (q < 0 || q >= n) return 0.0;
+    if (axis == 0) i = q;
+    else if (axis == 1) j = q;
+    else k = q;
+    return sign * u[((size_t)k * n + j) * n + i];
+}
+
+/*
+ * Discrete Laplacian L_h (section 1: method of lines; the coarse level uses
+ * the classical second-order 7-point stencil, the fine level a fourth-order
+ * stencil).  order 2: (u_{-1} - 2 u_0 + u_{+1}) / h^2 per axis.
+ * order 4: (-u_{-2} + 16 u_{-1} - 30 u_0 + 16 u_{+1} - u_{+2}) / (12 h^2)
+ * per axis (the wide 13-point stencil).  Axis sums are taken x, then y,
+ * then z.
+ */
+void or_laplacian(int n, int order, const double *u, double *Lu)
+{
+    double h = or_grid_h(n);
+    double ih2 = 1.0 / (h * h);
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                int c[3] = {i, j, k};
+                double sum = 0.0;
+                for (int ax = 0; ax < 3; ax++) {
+                    int q = c[ax];
+                    double d;
+                    if (order == 2) {
+                        d = line_val(u, n, i, j, k, ax, q - 1)
+                          - 2.0 * line_val(u, n, i, j, k, ax, q)
+                          + line_val(u, n, i, j, k, ax, q + 1);
+                        d = d * ih2;
+                    } else {
+                        d = -line_val(u, n, i, j, k, ax, q - 2)
+                          + 16.0 * line_val(u, n, i, j, k, ax, q - 1)
+                          - 30.0 * line_val(u, n, i, j, k, ax, q)
+                          + 16.0 * line_val(u, n, i, j, k, ax, q + 1)
+                          - line_val(u, n, i, j, k, ax, q + 2);
+                        d = d * ih2 / 12.0;
+                    }
+                    sum += d;
+                }
+                Lu[((size_t)k * n + j) * n + i] = sum;
+            }
+}
+
+/* y = alpha u + beta L_h u (method of lines, section 1). */
+void or_lap_apply(int n, int order, double alpha, double beta, const double *u, double *y)
+{
+    size_t N = cube(n);
+    double *L = alloc0(N);
+    or_laplacian(n, order, u, L);
+    for (size_t p = 0; p < N; p++) y[p] = alpha * u[p] + beta * L[p];
+    free(L);
+}
+
+/*
+ * The implicit-Euler substep operator A_a = I - a L_h with a = nu * dt_m
+ * (eq. (7): the implicit part of the IMEX sweep moved to the left).
+ */
+void or_heat_op(int n, int order, double a, const double *u, double *y)
+{
+    or_lap_apply(n, order, 1.0, -a, u, y);
+}
+
+/*
+ * Diagonal of A_a, from the stencil weights: the centre weight of L_h per
+ * axis is -2/h^2 (order 2) and -30/(12 h^2) (order 4), except that with the
+ * odd reflection a wall-adjacent point also picks up +1/(12 h^2) from its
+ * reflected far neighbour.
+ */
+static double diag_op(int n, int order, double a, int i, int j, int k)
+{
+    double h = or_grid_h(n);
+    double ih2 = 1.0 / (h * h);
+    int c[3] = {i, j, k};
+    double centre = 0.0;
+    for (int ax = 0; ax < 3; ax++) {
+        if (order == 2) {
+            centre += -2.0 * ih2;
+        } else {
+            double w = -30.0;
+            if (c[ax] == 0) w += 1.0;
+            if (c[ax] == n - 1) w += 1.0;
+            centre += w * ih2 / 12.0;
+        }
+    }
+    return 1.0 - a * centre;
+}
+
+/* r = b - A_a u */
+void or_residual(int n, int order, double a, const double *u, const double *b, double *r)
+{
+    size_t N = cube(n);
+    double *Au = alloc0(N);
+    or_heat_op(n, order, a, u, Au);
+    for (size_t p = 0; p < N; p++) r[p] = b[p] - Au[p];
+    free(Au);
+}
+
+/* Weighted Jacobi: u_new = u + omega D^{-1} (b - A_a u).  The paper names
+ * no smoother (section 1.2); weighted Jacobi is the reading used here. */
+void or_jacobi(int n, int order, double a, double omega, const double *u, const double *b,
+               double *u_new)
+{
+    size_t N = cube(n);
+    double *r = alloc0(N);
+    or_residual(n, order, a, u, b, r);
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                size_t p = ((size_t)k * n + j) * n + i;
+                u_new[p] = u[p] + omega * r[p] / diag_op(n, order, a, i, j, k);
+            }
+    free(r);
+}
+
+/*
+ * Full-weighting restriction: coarse point I (0-based) coincides with fine
+ * point 2I+1; weights are the tensor product of (1/4, 1/2, 1/4).
+ */
+void or_restrict_fw(int nf, const double *rf, double *rc)
+{
+    int nc = (nf - 1) / 2;
+    const double w[3] = {0.25, 0.5, 0.25};
+    for (int K = 0; K < nc; K++)
+        for (int J = 0; J < nc; J++)
+            for (int I = 0; I < nc; I++) {
+                double s = 0.0;
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++) {
+                            int i = 2 * I + 1 + dx, j = 2 * J + 1 + dy, k = 2 * K + 1 + dz;
+                            s += w[dx + 1] * w[dy + 1] * w[dz + 1]
+                               * rf[((size_t)k * nf + j) * nf + i];
+                        }
+                rc[((size_t)K * nc + J) * nc + I] = s;
+            }
+}
+
+/* weight and coarse index pair for one fine index along one axis */
+static void prolong_weights(int nc, int i, int idx[2], double wt[2], int *cnt)
+{
+    if (i % 2 == 1) {            /* coincides with coarse (i-1)/2 */
+        idx[0] = (i - 1) / 2; wt[0] = 1.0; *cnt = 1;
+    } else {                     /* halfway between coarse i/2-1 and i/2 */
+        idx[0] = i / 2 - 1; wt[0] = 0.5;
+        idx[1] = i / 2;     wt[1] = 0.5;
+        *cnt = 2;
+    }
+    (void)nc;
+}
+
+/* Trilinear prolongation added to a fine field: uf += P ec (walls are 0). */
+void or_prolong_add(int nc, const double *ec, double *uf)
+{
+    int nf = 2 * nc + 1;
+    for (int k = 0; k < nf; k++)
+        for (int j = 0; j < nf; j++)
+            for (int i = 0; i < nf; i++) {
+                int ix[2], iy[2], iz[2], cx, cy, cz;
+                double wx[2], wy[2], wz[2];
+                prolong_weights(nc, i, ix, wx, &cx);
+                prolong_weights(nc, j, iy, wy, &cy);
+                prolong_weights(nc, k, iz, wz, &cz);
+                double s = 0.0;
+                for (int c = 0; c < cz; c++)
+                    for (int b = 0; b < cy; b++)
+                        for (int a = 0; a < cx; a++) {
+                            int I = ix[a], J = iy[b], K = iz[c];
+                            if (I < 0 || I >= nc || J < 0 || J >= nc || K < 0 || K >= nc) continue;
+                            s += wx[a] * wy[b] * wz[c] * ec[((size_t)K * nc + J) * nc + I];
+                        }
+                uf[((size_t)k * nf + j) * nf + i] += s;
+            }
+}
+
+/*
+ * Exact solve of A_a x = b by assembling the dense matrix column by column
+ * (A applied to unit vectors) and Gaussian elimination with partial
+ * pivoting.  Used on the coarsest multigrid grid and, in tests, as the
+ * brute-force reference on tiny grids.
+ */
+int or_dense_solve(int n, int order, double a, const double *b, double *x)
+{
+    size_t N = cube(n);
+    if (N > 4096) return OR_EINVAL;
+    double *A = alloc0(N * N);
+    double *e = alloc0(N);
+    double *col = alloc0(N);
+    for (size_t q = 0; q < N; q++) {
+        memset(e, 0, N * sizeof(double));
+        e[q] = 1.0;
+        or_heat_op(n, order, a, e, col);
+        for (size_t p = 0; p < N; p++) A[p * N + q] = col[p];
+    }
+    double *rhs = alloc0(N);
+    memcpy(rhs, b, N * sizeof(double));
+    for (size_t c = 0; c < N; c++) {
+        size_t piv = c;
+        for (size_t p = c + 1; p < N; p++)
+            if (fabs(A[p * N + c]) > fabs(A[piv * N + c])) piv = p;
+        if (piv != c) {
+            for (size_t q = 0; q < N; q++) {
+                double t = A[c * N + q]; A[c * N + q] = A[piv * N + q]; A[piv * N + q] = t;
+            }
+            double t = rhs[c]; rhs[c] = rhs[piv]; rhs[piv] = t;
+        }
+        for (size_t p = c + 1; p < N; p++) {
+            double f = A[p * N + c] / A[c * N + c];
+            if (f == 0.0) continue;
+            for (size_t q = c; q < N; q++) A[p * N + q] -= f * A[c * N + q];
+            rhs[p] -= f * rhs[c];
+        }
+    }
+    for (size_t c = N; c-- > 0;) {
+        double s = rhs[c];
+        for (size_t q = c + 1; q < N; q++) s -= A[c * N + q] * x[q];
+        x[c] = s / A[c * N + c];
+    }
+    free(A); free(e); free(col); free(rhs);
+    return OR_OK;
+}
+
+/*
+ * One multigrid V(nu1,nu2) cycle for A_a u = b (section 1.2 says only that
+ * a parallel geometric multigrid method is used; the components here are
+ * the reading: same-order rediscretisation on every grid, weighted Jacobi,
+ * full weighting, trilinear prolongation, exact solve on the coarsest grid).
+ */
+static void vcycle(int n, int order, double a, const or_mg *p, double *u, const double *b)
+{
+    size_t N = cube(n);
+    if (n <= p->n_coarsest) {
+        or_dense_solve(n, order, a, b, u);
+        return;
+    }
+    double *t = alloc0(N);
+    for (int s = 0; s < p->nu1; s++) {
+        or_jacobi(n, order, a, p->omega, u, b, t);
+        memcpy(u, t, N * sizeof(double));
+    }
+    double *r = alloc0(N);
+    or_residual(n, order, a, u, b, r);
+    int nc = (n - 1) / 2;
+    double *bc = alloc0(cube(nc));
+    double *ec = alloc0(cube(nc));
+    or_restrict_fw(n, r, bc);
+    vcycle(nc, order, a, p, ec, bc);
+    or_prolong_add(nc, ec, u);
+    for (int s = 0; s < p->nu2; s++) {
+        or_jacobi(n, order, a, p->omega, u, b, t);
+        memcpy(u, t, N * sizeof(double));
+    }
+    free(t); free(r); free(bc); free(ec);
+}
+
+static double maxabs(const double *v, size_t N)
+{
+    double m = 0.0;
+    for (size_t p = 0; p < N; p++) {
+        double x = fabs(v[p]);
+        if (x > m || x != x) m = x;
+        if (m != m) return m;
+    }
+    return m;
+}
+
+/*
+ * Solve A_a u = b by V-cycles from the initial guess in u.  Stopping rule
+ * (not given in the paper): before each cycle rho = |b - A u|_inf / |b|_inf
+ * (|b|_inf replaced by 1 when b = 0); stop when rho <= tol, fail after
+ * max_cycles cycles.  With fixed_cycles > 0 exactly that many cycles run.
+ */
+int or_mg_solve(int n, int order, double a, const or_mg *p, double *u, const double *b,
+                int *cycles_out, double *rho_out)
+{
+    if (!valid_n(n) || (order != 2 && order != 4)) return OR_EINVAL;
+    size_t N = cube(n);
+    double *r = alloc0(N);
+    double bn = maxabs(b, N);
+    double scale = bn > 0.0 ? bn : 1.0;
+    int status = OR_OK, c = 0;
+    double rho = 0.0;
+    if (p->fixed_cycles > 0) {
+        for (c = 0; c < p->fixed_cycles; c++) vcycle(n, order, a, p, u, b);
+        or_residual(n, order, a, u, b, r);
+        rho = maxabs(r, N) / scale;
+        if (rho != rho) status = OR_ENONFINITE;
+    } else {
+        for (c = 0;; c++) {
+            or_residual(n, order, a, u, b, r);
+            rho = maxabs(r, N) / scale;
+            if (rho != rho) { status = OR_ENONFINITE; break; }
+            if (rho <= p->tol) break;
+            if (c >= p->max_cycles) { status = OR_ENOCONV; break; }
+            vcycle(n, order, a, p, u, b);
+        }
+    }
+    if (cycles_out) *cycles_out = c;
+    if (rho_out) *rho_out = rho;
+    free(r);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Collocation nodes and weights (section 1.1, eqs. (5)-(6))           */
+/* ------------------------------------------------------------------ */
+
+/* Legendre P_N(x) and P_N'(x) by the three-term recurrence. */
+static void legendre(int N, long double x, long double *P, long double *dP)
+{
+    long double p0 = 1.0L, p1 = x;
+    if (N == 0) { *P = 1.0L; *dP = 0.0L; return; }
+    for (int k = 2; k <= N; k++) {
+        long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1; p1 = p2;
+    }
+    *P = p1;
+    *dP = N * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+/* Gauss-Lobatto nodes on [0,1] in long double (see or_lobatto_nodes). */
+static void lobatto_nodes_ld(int M, long double *t)
+{
+    int N = M - 1;
+    t[0] = 0.0L; t[N] = 1.0L;
+    for (int j = 1; j < N; j++) {
+        long double z = -cosl(3.14159265358979323846264338327950288L * j / N);
+        for (int it = 0; it < 100; it++) {
+            long double P, dP;
+            legendre(N, z, &P, &dP);
+            /* P'' from the Legendre differential equation */
+            long double d2P = (2.0L * z * dP - N * (N + 1) * P) / (1.0L - z * z);
+            long double dz = dP / d2P;
+            z -= dz;
+            if (fabsl(dz) < 1e-30L) break;
+        }
+        t[j] = (z + 1.0L) / 2.0L;
+    }
+}
+
+/*
+ * Gauss-Lobatto nodes on [0,1]: the two end points plus the roots of
+ * P'_{M-1} (so that T^n and T^{n+1} are nodes, section 1.1).  M counts all
+ * nodes including both ends.
+ */
+int or_lobatto_nodes(int M, double *tau)
+{
+    if (M < 2 || M > OR_MAXM) return OR_EINVAL;
+    long double t[OR_MAXM];
+    lobatto_nodes_ld(M, t);
+    for (int j = 0; j < M; j++) tau[j] = (double)t[j];
+    return OR_OK;
+}
+
+/* Lagrange basis polynomial l_j of the nodes t at s. */
+static long double lagrange(int M, const long double *t, int j, long double s)
+{
+    long double v = 1.0L;
+    for (int i = 0; i < M; i++)
+        if (i != j) v *= (s - t[i]) / (t[j] - t[i]);
+    return v;
+}
+
+/*
+ * Collocation matrix of eq. (6): Q[m*M + j] = integral from 0 to tau_m of
+ * l_j(s) ds (row m = node, column j = source node), on the unit interval.
+ * Integrated with 8-point Gauss-Legendre quadrature in long double, exact
+ * for the degree M-1 <= 15 integrands.
+ */
+int or_collocation_matrix(int M, double *Q)
+{
+    if (M < 2 || M > OR_MAXM) return OR_EINVAL;
+    long double t[OR_MAXM];
+    lobatto_nodes_ld(M, t);
+    const int G = 8;
+    long double gx[8], gw[8];
+    for (int g = 0; g < G; g++) {
+        long double z = cosl(3.14159265358979323846264338327950288L * (g + 0.75L) / (G + 0.5L));
+        for (int it = 0; it < 100; it++) {
+            long double P, dP;
+            legendre(G, z, &P, &dP);
+            long double dz = P / dP;
+            z -= dz;
+            if (fabsl(dz) < 1e-30L) break;
+        }
+        long double P, dP;
+        legendre(G, z, &P, &dP);
+        gx[g] = z;
+        gw[g] = 2.0L / ((1.0L - z * z) * dP * dP);
+    }
+    for (int m = 0; m < M; m++)
+        for (int j = 0; j < M; j++) {
+            long double s = 0.0L;
+            for (int g = 0; g < G; g++)
+                s += gw[g] * lagrange(M, t, j, t[m] * (1.0L + gx[g]) / 2.0L);
+            Q[m * M + j] = (double)(s * t[m] / 2.0L);
+        }
+    return OR_OK;
+}
+
+/* Lagrange interpolation weights from the coarse nodes to one point s. */
+static void interp_weights(int Mc, double s, double *w)
+{
+    long double t[OR_MAXM];
+    lobatto_nodes_ld(Mc, t);
+    for (int j = 0; j < Mc; j++) w[j] = (double)lagrange(Mc, t, j, (long double)s);
+}
+
+/* ------------------------------------------------------------------ */
+/* Right-hand side (eqs. (1)-(4))                                      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Forcing of eq. (3): f(x,t) = -s(x) (sin t - c nu pi^2 cos t) with
+ * s(x) = sin(pi x1) sin(pi x2) sin(pi x3).  As printed, c = 1; the stated
+ * analytic solution u = s(x) cos t (eq. (4)) needs c = 3 in three
+ * dimensions, so c is a parameter.
+ */
+void or_forcing(int n, double nu, double c, double t, double *f)
+{
+    double h = or_grid_h(n);
+    double g = -(sin(t) - c * nu * M_PI * M_PI * cos(t));
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                double s = sin(M_PI * (i + 1) * h) * sin(M_PI * (j + 1) * h) * sin(M_PI * (k + 1) * h);
+                f[((size_t)k * n + j) * n + i] = s * g;
+            }
+}
+
+/* Implicit part f^I(U) = nu L_h U (diffusion, treated implicitly). */
+void or_heat_rhs(int n, int order, double nu, double c, double t, const double *u,
+                 double *f_impl, double *f_expl)
+{
+    if (f_impl) or_lap_apply(n, order, 0.0, nu, u, f_impl);
+    if (f_expl) or_forcing(n, nu, c, t, f_expl);
+}
+
+/* ------------------------------------------------------------------ */
+/* SDC (section 1.1, eqs. (5)-(9))                                     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Predictor (the paper defers it to its references): copy U_0 to every
+ * node and evaluate f^I there.
+ */
+void or_spread(const or_level *L, double nu, const double *u0, double *U, double *FI)
+{
+    size_t N = cube(L->n);
+    for (int m = 0; m < L->M; m++) {
+        memcpy(U + (size_t)m * N, u0, N * sizeof(double));
+        or_lap_apply(L->n, L->order, 0.0, nu, u0, FI + (size_t)m * N);
+    }
+}
+
+/*
+ * Collocation residual (eq. (6) moved to one side), max over nodes
+ * m = 1..M-1 and grid points of |U_0 + dt sum_j q_{m,j} f(U_j, t_j)
+ * (+ tau_m) - U_m|.  Absolute, max norm (the paper does not define the
+ * residual it thresholds at 1e-10).
+ */
+double or_sdc_residual(const or_level *L, double nu, double tn, double dt, double c,
+                       const double *U, const double *FI, const double *tau)
+{
+    int M = L->M;
+    size_t N = cube(L->n);
+    double Q[OR_MAXM * OR_MAXM], nodes[OR_MAXM];
+    or_collocation_matrix(M, Q);
+    or_lobatto_nodes(M, nodes);
+    double **FE = (double **)malloc(M * sizeof(double *));
+    for (int j = 0; j < M; j++) {
+        FE[j] = alloc0(N);
+        or_forcing(L->n, nu, c, tn + dt * nodes[j], FE[j]);
+    }
+    double R = 0.0;
+    for (int m = 1; m < M; m++)
+        for (size_t p = 0; p < N; p++) {
+            double integral = 0.0;
+            for (int j = 0; j < M; j++)
+                integral += Q[m * M + j] * (FI[(size_t)j * N + p] + FE[j][p]);
+            double v = U[p] + dt * integral;
+            if (tau) v += tau[(size_t)m * N + p];
+            v -= U[(size_t)m * N + p];
+            double x = fabs(v);
+            if (x > R || x != x) R = x;
+        }
+    for (int j = 0; j < M; j++) free(FE[j]);
+    free(FE);
+    return R;
+}
+
+/*
+ * One IMEX-Euler SDC sweep, eq. (7).  With f^I = nu L_h U and f^E = f(x,t)
+ * (independent of U), the explicit difference term of eq. (7) vanishes and
+ * each substep is
+ *   (I - dt_m nu L_h) U^{k+1}_{m+1} = U^{k+1}_m - dt_m nu L_h U^k_{m+1}
+ *                                     + dt S^k_m (+ tau_{m+1} - tau_m)
+ * with dt S^k_m = dt sum_j (q_{m+1,j} - q_{m,j}) f(U^k_j, t_j) (eq. (8)),
+ * built from iterate k before any node is updated.  Each substep is solved
+ * by or_mg_solve from the initial guess U^k_{m+1}.  tau (may be NULL) is the
+ * FAS correction of a coarse MLSDC level.
+ */
+int or_sdc_sweep(const or_level *L, const or_mg *mg, double nu, double tn, double dt, double c,
+                 double *U, double *FI, const double *tau, or_stats *st)
+{
+    int M = L->M, n = L->n;
+    size_t N = cube(n);
+    double Q[OR_MAXM * OR_MAXM], nodes[OR_MAXM];
+    or_collocation_matrix(M, Q);
+    or_lobatto_nodes(M, nodes);
+    double *FE = alloc0((size_t)M * N);
+    for (int j = 0; j < M; j++) or_forcing(n, nu, c, tn + dt * nodes[j], FE + (size_t)j * N);
+    /* node-to-node integrals from iterate k */
+    double *SF = alloc0((size_t)(M - 1) * N);
+    for (int m = 0; m < M - 1; m++)
+        for (size_t p = 0; p < N; p++) {
+            double s = 0.0;
+            for (int j = 0; j < M; j++)
+                s += (Q[(m + 1) * M + j] - Q[m * M + j]) * (FI[(size_t)j * N + p] + FE[(size_t)j * N + p]);
+            SF[(size_t)m * N + p] = dt * s;
+        }
+    double *rhs = alloc0(N);
+    int status = OR_OK;
+    for (int m = 0; m < M - 1; m++) {
+        double dtm = dt * (nodes[m + 1] - nodes[m]);
+        for (size_t p = 0; p < N; p++) {
+            double v = U[(size_t)m * N + p] - dtm * FI[(size_t)(m + 1) * N + p] + SF[(size_t)m * N + p];
+            if (tau) v += tau[(size_t)(m + 1) * N + p] - tau[(size_t)m * N + p];
+            rhs[p] = v;
+        }
+        int cyc = 0;
+        double rho = 0.0;
+        int s = or_mg_solve(n, L->order, nu * dtm, mg, U + (size_t)(m + 1) * N, rhs, &cyc, &rho);
+        if (s != OR_OK && status == OR_OK) status = s;
+        if (st) {
+            st->total_solves++;
+            st->total_cycles += cyc;
+            if (cyc > st->max_cycles_seen) st->max_cycles_seen = cyc;
+        }
+        or_lap_apply(n, L->order, 0.0, nu, U + (size_t)(m + 1) * N, FI + (size_t)(m + 1) * N);
+    }
+    if (st) st->total_sweeps++;
+    free(FE); free(SF); free(rhs);
+    return status;
+}
+
+/*
+ * One single-level SDC time step [t_n, t_n + dt] from u (overwritten with
+ * the end value U_{M-1}, i.e. the last collocation node, eq. (9)).
+ */
+static int sdc_step(const or_problem *pb, double tn, double *u, or_stats *st)
+{
+    const or_level *L = &pb->lev[0];
+    size_t N = cube(L->n);
+    double *U = alloc0((size_t)L->M * N), *FI = alloc0((size_t)L->M * N);
+    or_spread(L, pb->nu, u, U, FI);
+    int status = OR_OK, k = 0;
+    for (k = 0;; k++) {
+        if (pb->sweeps > 0) {
+            if (k >= pb->sweeps) break;
+        } else {
+            double R = or_sdc_residual(L, pb->nu, tn, pb->dt, pb->forcing_c, U, FI, NULL);
+            if (st) st->last_residual = R;
+            if (R != R) { status = OR_ENONFINITE; break; }
+            if (R <= pb->sdc_tol) break;
+            if (k >= pb->max_sweeps) { status = OR_ENOCONV; break; }
+        }
+        int s = or_sdc_sweep(L, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, U, FI, NULL, st);
+        if (s != OR_OK && status == OR_OK) status = s;
+    }
+    if (pb->sweeps > 0 && st)
+        st->last_residual = or_sdc_residual(L, pb->nu, tn, pb->dt, pb->forcing_c, U, FI, NULL);
+    if (st) st->sweeps = k;
+    memcpy(u, U + (size_t)(L->M - 1) * N, N * sizeof(double));
+    free(U); free(FI);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* MLSDC with FAS (section 1.1; space-time coarsening in the intro)    */
+/* ------------------------------------------------------------------ */
+
+/* Injection: coarse point I takes the fine value at 2I+1. */
+void or_inject(int nf, const double *uf, double *uc)
+{
+    int nc = (nf - 1) / 2;
+    for (int K = 0; K < nc; K++)
+        for (int J = 0; J < nc; J++)
+            for (int I = 0; I < nc; I++)
+                uc[((size_t)K * nc + J) * nc + I] =
+                    uf[((size_t)(2 * K + 1) * nf + (2 * J + 1)) * nf + (2 * I + 1)];
+}
+
+/* index of the fine node that coincides with coarse node m (nested nodes) */
+static int fine_node_of(int Mf, int Mc, int m) { return m * ((Mf - 1) / (Mc - 1)); }
+
+/*
+ * Restriction to the coarse MLSDC level plus FAS correction.
+ * Ut[m] = inj(Uf[fine node of m]) (space: injection; time: node subset),
+ * Uc = Ut, FIc = nu L_c Ut, and
+ *   tau_m = inj(dt sum_j qf_{m',j} f^f_j) - dt sum_j qc_{m,j} f^c(Ut_j)
+ * where m' is the fine node of coarse node m.
+ */
+void or_fas_restrict(const or_level *Lf, const or_level *Lc, double nu, double tn, double dt,
+                     double c, const double *Uf, const double *FIf, double *Uc, double *FIc,
+                     double *Ut, double *tau)
+{
+    int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
+    size_t Nf = cube(nf), Nc = cube(nc);
+    double Qf[OR_MAXM * OR_MAXM], Qc[OR_MAXM * OR_MAXM], tf[OR_MAXM], tc[OR_MAXM];
+    or_collocation_matrix(Mf, Qf);
+    or_collocation_matrix(Mc, Qc);
+    or_lobatto_nodes(Mf, tf);
+    or_lobatto_nodes(Mc, tc);
+    double *FEf = alloc0((size_t)Mf * Nf), *FEc = alloc0((size_t)Mc * Nc);
+    for (int j = 0; j < Mf; j++) or_forcing(nf, nu, c, tn + dt * tf[j], FEf + (size_t)j * Nf);
+    for (int j = 0; j < Mc; j++) or_forcing(nc, nu, c, tn + dt * tc[j], FEc + (size_t)j * Nc);
+    for (int m = 0; m < Mc; m++) {
+        or_inject(nf, Uf + (size_t)fine_node_of(Mf, Mc, m) * Nf, Ut + (size_t)m * Nc);
+        memcpy(Uc + (size_t)m * Nc, Ut + (size_t)m * Nc, Nc * sizeof(double));
+        or_lap_apply(nc, Lc->order, 0.0, nu, Ut + (size_t)m * Nc, FIc + (size_t)m * Nc);
+    }
+    double *fint = alloc0(Nf), *cint = alloc0(Nc);
+    for (int m = 0; m < Mc; m++) {
+        int mf = fine_node_of(Mf, Mc, m);
+        for (size_t p = 0; p < Nf; p++) {
+            double s = 0.0;
+            for (int j = 0; j < Mf; j++)
+                s += Qf[mf * Mf + j] * (FIf[(size_t)j * Nf + p] + FEf[(size_t)j * Nf + p]);
+            fint[p] = dt * s;
+        }
+        or_inject(nf, fint, cint);
+        for (size_t p = 0; p < Nc; p++) {
+            double s = 0.0;
+            for (int j = 0; j < Mc; j++)
+                s += Qc[m * Mc + j] * (FIc[(size_t)j * Nc + p] + FEc[(size_t)j * Nc + p]);
+            tau[(size_t)m * Nc + p] = cint[p] - dt * s;
+        }
+    }
+    free(FEf); free(FEc); free(fint); free(cint);
+}
+
+/*
+ * Interpolation of the coarse correction back to the fine MLSDC level.
+ * dU_m = Uc_m - Ut_m at every coarse node; a fine node coinciding with a
+ * coarse node takes P dU (trilinear in space), the others take
+ * P(sum_j l_j(tau_f) dU_j) (Lagrange in time on the coarse nodes).  Then
+ * f^I is recomputed on the fine level at every node.
+ */
+void or_fas_interp(const or_level *Lf, const or_level *Lc, double nu, double *Uf, double *FIf,
+                   const double *Uc, const double *Ut)
+{
+    int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
+    size_t Nf = cube(nf), Nc = cube(nc);
+    double tf[OR_MAXM];
+    or_lobatto_nodes(Mf, tf);
+    double *dU = alloc0((size_t)Mc * Nc), *ec = alloc0(Nc);
+    for (size_t p = 0; p < (size_t)Mc * Nc; p++) dU[p] = Uc[p] - Ut[p];
+    for (int mf = 0; mf < Mf; mf++) {
+        double w[OR_MAXM];
+        interp_weights(Mc, tf[mf], w);
+        int stride = (Mf - 1) / (Mc - 1);
+        if (mf % stride == 0) {
+            memcpy(ec, dU + (size_t)(mf / stride) * Nc, Nc * sizeof(double));
+        } else {
+            for (size_t p = 0; p < Nc; p++) {
+                double s = 0.0;
+                for (int j = 0; j < Mc; j++) s += w[j] * dU[(size_t)j * Nc + p];
+                ec[p] = s;
+            }
+        }
+        or_prolong_add(nc, ec, Uf + (size_t)mf * Nf);
+    }
+    for (int mf = 0; mf < Mf; mf++)
+        or_lap_apply(nf, Lf->order, 0.0, nu, Uf + (size_t)mf * Nf, FIf + (size_t)mf * Nf);
+    free(dU); free(ec);
+}
+
+/*
+ * One MLSDC iteration: fine sweep, restriction + FAS correction, coarse
+ * sweep with tau, interpolation of the coarse correction.
+ */
+int or_mlsdc_iter(const or_problem *pb, double tn, double *Uf, double *FIf, double *Uc,
+                  double *FIc, double *Ut, double *tau, or_stats *st)
+{
+    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
+    int status = or_sdc_sweep(Lf, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, NULL, st);
+    or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, Uc, FIc, Ut, tau);
+    int s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc, FIc, tau, NULL);
+    if (s != OR_OK && status == OR_OK) status = s;
+    or_fas_interp(Lf, Lc, pb->nu, Uf, FIf, Uc, Ut);
+    return status;
+}
+
+static int mlsdc_step(const or_problem *pb, double tn, double *u, or_stats *st)
+{
+    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
+    size_t Nf = cube(Lf->n), Nc = cube(Lc->n);
+    double *Uf = alloc0((size_t)Lf->M * Nf), *FIf = alloc0((size_t)Lf->M * Nf);
+    double *Uc = alloc0((size_t)Lc->M * Nc), *FIc = alloc0((size_t)Lc->M * Nc);
+    double *Ut = alloc0((size_t)Lc->M * Nc), *tau = alloc0((size_t)Lc->M * Nc);
+    or_spread(Lf, pb->nu, u, Uf, FIf);
+    int status = OR_OK, k;
+    for (k = 0;; k++) {
+        if (pb->sweeps > 0) {
+            if (k >= pb->sweeps) break;
+        } else {
+            double R = or_sdc_residual(Lf, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, NULL);
+            if (st) st->last_residual = R;
+            if (R != R) { status = OR_ENONFINITE; break; }
+            if (R <= pb->sdc_tol) break;
+            if (k >= pb->max_sweeps) { status = OR_ENOCONV; break; }
+        }
+        int s = or_mlsdc_iter(pb, tn, Uf, FIf, Uc, FIc, Ut, tau, st);
+        if (s != OR_OK && status == OR_OK) status = s;
+    }
+    if (pb->sweeps > 0 && st)
+        st->last_residual = or_sdc_residual(Lf, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, NULL);
+    if (st) st->sweeps = k;
+    memcpy(u, Uf + (size_t)(Lf->M - 1) * Nf, Nf * sizeof(double));
+    free(Uf); free(FIf); free(Uc); free(FIc); free(Ut); free(tau);
+    return status;
+}
+
+static int check_problem(const or_problem *pb)
+{
+    if (pb->nlevels < 1 || pb->nlevels > 2) return OR_EINVAL;
+    for (int l = 0; l < pb->nlevels; l++) {
+        const or_level *L = &pb->lev[l];
+        if (!valid_n(L->n) || (L->order != 2 && L->order != 4)) return OR_EINVAL;
+        if (L->M < 2 || L->M > OR_MAXM) return OR_EINVAL;
+    }
+    if (pb->nlevels == 2) {
+        if (pb->lev[1].n != (pb->lev[0].n - 1) / 2) return OR_EINVAL;
+        if ((pb->lev[0].M - 1) % (pb->lev[1].M - 1) != 0) return OR_EINVAL;
+    }
+    if (!(pb->dt > 0.0) || !(pb->nu > 0.0) || pb->nsteps < 0) return OR_EINVAL;
+    return OR_OK;
+}
+
+/*
+ * Run nsteps time steps from u (overwritten with the final value), single
+ * level SDC or two-level MLSDC depending on nlevels.  t_n = t0 + n dt.
+ */
+int or_run(const or_problem *pb, double *u, or_stats *st)
+{
+    int s = check_problem(pb);
+    if (s != OR_OK) return s;
+    if (st) memset(st, 0, sizeof(*st));
+    int status = OR_OK;
+    for (int step = 0; step < pb->nsteps; step++) {
+        double tn = pb->t0 + step * pb->dt;
+        s = pb->nlevels == 1 ? sdc_step(pb, tn, u, st) : mlsdc_step(pb, tn, u, st);
+        if (s != OR_OK && status == OR_OK) status = s;
+    }
+    if (st) st->status = status;
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* PFASST over P time slices (section 1.1), run serially               */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The paper gives PFASST only in outline (MLSDC iterations run
+ * concurrently on P time slices; new values are passed forward after each
+ * level's sweep; the coarse level hands over in a blocking pipeline).  This
+ * is the reading used, one block of P consecutive steps starting at t0 from
+ * u; iterations fixed at pb->sweeps:
+ *  - every slice starts with u spread over all of its fine nodes;
+ *  - iteration: (i) for p >= 1, fine node 0 of slice p takes the fine end
+ *    value of slice p-1 as it stood at the end of the previous iteration;
+ *    fine sweep on every slice; (ii) restriction + tau on every slice;
+ *    (iii) slices in order p = 0..P-1: for p >= 1 coarse node 0 takes the
+ *    coarse end value slice p-1 has just computed, then the coarse sweep;
+ *    (iv) interpolation on every slice, node 0 included.
+ *  - the result is the fine end value of slice P-1.
+ * nsteps must be a multiple of P; blocks run one after the other.
+ */
+int or_pfasst_run(const or_problem *pb, int P, double *u, or_stats *st)
+{
+    int s = check_problem(pb);
+    if (s != OR_OK) return s;
+    if (pb->nlevels != 2 || P < 1 || pb->nsteps % P != 0 || pb->sweeps <= 0) return OR_EINVAL;
+    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
+    int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
+    size_t Nf = cube(nf), Nc = cube(nc);
+    size_t SF = (size_t)Mf * Nf, SC = (size_t)Mc * Nc;
+    double *Uf = alloc0(P * SF), *FIf = alloc0(P * SF);
+    double *Uc = alloc0(P * SC), *FIc = alloc0(P * SC), *Ut = alloc0(P * SC), *tau = alloc0(P * SC);
+    double *ends = alloc0((size_t)P * Nf);
+    if (st) memset(st, 0, sizeof(*st));
+    int status = OR_OK;
+    for (int blk = 0; blk < pb->nsteps / P; blk++) {
+        double tb = pb->t0 + (double)(blk * P) * pb->dt;
+        for (int p = 0; p < P; p++) or_spread(Lf, pb->nu, u, Uf + p * SF, FIf + p * SF);
+        for (int k = 0; k < pb->sweeps; k++) {
+            /* (i) fine hand-off from the previous iteration's end values */
+            for (int p = 0; p < P; p++)
+                memcpy(ends + (size_t)p * Nf, Uf + p * SF + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
+            for (int p = 1; p < P; p++) {
+                memcpy(Uf + p * SF, ends + (size_t)(p - 1) * Nf, Nf * sizeof(double));
+                or_lap_apply(nf, Lf->order, 0.0, pb->nu, Uf + p * SF, FIf + p * SF);
+            }
+            for (int p = 0; p < P; p++) {
+                double tn = tb + p * pb->dt;
+                s = or_sdc_sweep(Lf, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uf + p * SF, FIf + p * SF, NULL, st);
+                if (s != OR_OK && status == OR_OK) status = s;
+            }
+            /* (ii) restriction and tau */
+            for (int p = 0; p < P; p++) {
+                double tn = tb + p * pb->dt;
+                or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf + p * SF, FIf + p * SF,
+                                Uc + p * SC, FIc + p * SC, Ut + p * SC, tau + p * SC);
+            }
+            /* (iii) coarse pipeline */
+            for (int p = 0; p < P; p++) {
+                double tn = tb + p * pb->dt;
+                if (p >= 1) {
+                    memcpy(Uc + p * SC, Uc + (p - 1) * SC + (size_t)(Mc - 1) * Nc, Nc * sizeof(double));
+                    or_lap_apply(nc, Lc->order, 0.0, pb->nu, Uc + p * SC, FIc + p * SC);
+                }
+                s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc + p * SC, FIc + p * SC,
+                                 tau + p * SC, NULL);
+                if (s != OR_OK && status == OR_OK) status = s;
+            }
+            /* (iv) interpolation */
+            for (int p = 0; p < P; p++)
+                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC);
+        }
+        memcpy(u, Uf + (size_t)(P - 1) * SF + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
+    }
+    if (st) { st->status = status; st->sweeps = pb->sweeps; }
+    free(Uf); free(FIf); free(Uc); free(FIc); free(Ut); free(tau); free(ends);
+    return status;
+}

@@ -1,0 +1,536 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself.
+
+Each test names the passage of the paper, or the mathematical fact, that it
+checks.  Together they are chosen so that a dropped term, a wrong sign, a
+wrong index or a transposed operand anywhere in the oracle fails one of them:
+
+* discrete Laplacians: closed-form eigenvalues on sine modes, exactness on
+  low-degree polynomials (section 1, method of lines);
+* multigrid parts: brute-force dense solves, closed-form solves on sine
+  modes, full weighting on sine modes, R = P^T / 8, Jacobi's per-mode
+  multiplier (section 1.2);
+* collocation weights: exact rational / sqrt(21) values, polynomial
+  exactness (section 1.1, eq. (6));
+* SDC: converged sweeps give the Lobatto IIIA stability function (the
+  diagonal Pade approximant) and the collocation solution of eq. (6); k
+  sweeps give local order k+1 (section 1.1); the manufactured solution of
+  eqs. (3)-(4) is met with the expected h^2 / h^4 spatial order;
+* FAS / MLSDC / PFASST: the FAS fixed point, convergence to the fine
+  collocation solution, and PFASST on one slice = MLSDC.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import sympy as sp
+
+import oracle
+from paper_1307_7867_amd import inputs
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def lam2(n, k):
+    h = 1.0 / (n + 1)
+    return -(4.0 / h**2) * sum(math.sin(kk * math.pi * h / 2) ** 2 for kk in k)
+
+
+def lam4(n, k):
+    h = 1.0 / (n + 1)
+    return -(1.0 / (12 * h * h)) * sum(30 - 32 * math.cos(kk * math.pi * h) + 2 * math.cos(2 * kk * math.pi * h)
+                                        for kk in k)
+
+
+def lam(order, n, k):
+    return lam2(n, k) if order == 2 else lam4(n, k)
+
+
+def project(u, k):
+    phi = inputs.sine_mode(u.shape[0], k)
+    return float((u * phi).sum() / (phi * phi).sum())
+
+
+# ----------------------------------------------------------------------------
+# Discrete Laplacians (section 1)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("n,k", [(15, (1, 1, 1)), (15, (1, 2, 3)), (31, (5, 1, 7)), (31, (31, 30, 1)),
+                                 (7, (7, 7, 7)), (3, (1, 3, 2)), (1, (1, 1, 1))])
+def test_laplacian_sine_eigenvalues(order, n, k):
+    u = inputs.sine_mode(n, k)
+    L = oracle.laplacian(u, order)
+    lm = lam(order, n, k)
+    assert np.abs(L - lm * u).max() <= 1e-13 * abs(lm)
+
+
+def test_laplacian2_exact_on_quadratics_with_walls():
+    # p(x) = x(1-x) vanishes on both walls, so the zero wall values are exact
+    # and the 3-point second difference reproduces p'' = -2 everywhere.
+    n = 15
+    x = inputs.coords(n)
+    p = x * (1 - x)
+    u = p[:, None, None] * p[None, :, None] * p[None, None, :]
+    ex = -2 * (p[:, None, None] * p[None, :, None] * np.ones(n)[None, None, :]
+               + p[:, None, None] * np.ones(n)[None, :, None] * p[None, None, :]
+               + np.ones(n)[:, None, None] * p[None, :, None] * p[None, None, :])
+    assert np.abs(oracle.laplacian(u, 2) - ex).max() < 1e-12
+
+
+def test_laplacian4_exact_on_quintics_away_from_walls():
+    n = 15
+    x = inputs.coords(n)
+    X = x[None, None, :]
+    Y = x[None, :, None]
+    Z = x[:, None, None]
+    u = X**5 + 2 * Y**4 * X - Z**3 * Y**2 + 0.5 * Z**5
+    lap = 20 * X**3 + 24 * Y**2 * X - 2 * Z**3 + (-6 * Z * Y**2) + 10 * Z**3
+    L = oracle.laplacian(u, 4)
+    s = slice(2, n - 2)
+    assert np.abs(L[s, s, s] - lap[s, s, s]).max() < 1e-8
+
+
+def test_lap_apply_and_heat_op_linear_combination():
+    u = inputs.random_field(7, 3)
+    L = oracle.laplacian(u, 4)
+    assert np.array_equal(oracle.lap_apply(u, 4, 0.0, 1.0), L)
+    y = oracle.heat_op(u, 4, 0.3)
+    assert np.abs(y - (u - 0.3 * L)).max() < 1e-12 * np.abs(L).max()
+
+
+# ----------------------------------------------------------------------------
+# Multigrid parts (section 1.2)
+# ----------------------------------------------------------------------------
+
+def kron_matrix(n, order, a):
+    """Dense A = I - a L assembled from 1-D difference matrices (Kronecker sums)."""
+    h = 1.0 / (n + 1)
+    w = [1.0, -2.0, 1.0] if order == 2 else [-1.0, 16.0, -30.0, 16.0, -1.0]
+    r = len(w) // 2
+    T = np.zeros((n, n))
+    for i in range(n):
+        for d in range(-r, r + 1):
+            j = i + d
+            if 0 <= j < n:
+                T[i, j] += w[d + r]
+            elif j == -2:            # odd reflection: u(-2) = -u(0)
+                T[i, 0] -= w[d + r]
+            elif j == n + 1:         # u(n+1) = -u(n-1)
+                T[i, n - 1] -= w[d + r]
+    T = T / (h * h) if order == 2 else T / (12 * h * h)
+    Id = np.eye(n)
+    Lm = np.kron(np.kron(Id, Id), T) + np.kron(np.kron(Id, T), Id) + np.kron(np.kron(T, Id), Id)
+    return np.eye(n**3) - a * Lm
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("n", [1, 3, 7])
+@pytest.mark.parametrize("a", [1e-4, 1e-2, 1.0])
+def test_dense_solve_matches_numpy(order, n, a):
+    b = inputs.random_field(n, 11)
+    x = oracle.dense_solve(b, order, a)
+    ref = np.linalg.solve(kron_matrix(n, order, a), b.ravel()).reshape(b.shape)
+    assert np.abs(x - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_heat_op_is_symmetric_positive_definite(order):
+    n = 3
+    A = np.empty((27, 27))
+    for q in range(27):
+        e = np.zeros(27); e[q] = 1
+        A[:, q] = oracle.heat_op(e.reshape(3, 3, 3), order, 0.7).ravel()
+    assert np.abs(A - A.T).max() < 1e-12
+    assert np.linalg.eigvalsh(A).min() >= 1.0 - 1e-12
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_dense_solve_sine_modes_closed_form(order):
+    n, a = 7, 0.05
+    modes = [(1, 1, 1, 0.7), (2, 5, 3, -1.3), (7, 1, 4, 0.25)]
+    b = inputs.modes_field(n, modes)
+    x = oracle.dense_solve(b, order, a)
+    ex = sum(amp / (1 - a * lam(order, n, (kx, ky, kz))) * inputs.sine_mode(n, (kx, ky, kz))
+             for kx, ky, kz, amp in modes)
+    assert np.abs(x - ex).max() < 1e-13
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("a", [1e-4, 1e-2, 1.0])
+def test_mg_solve_matches_dense(order, a):
+    n = 7
+    b = inputs.random_field(n, 5)
+    u, st, cyc, rho = oracle.mg_solve(b, order, a, mg=oracle.mg_params(tol=1e-14, max_cycles=200))
+    assert st == oracle.OK and rho <= 1e-14
+    ref = oracle.dense_solve(b, order, a)
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_mg_solve_sine_modes_closed_form(order):
+    n, a = 31, 0.004
+    modes = [(1, 1, 1, 1.0), (3, 8, 2, -0.5), (30, 2, 17, 0.2)]
+    b = inputs.modes_field(n, modes)
+    u, st, cyc, rho = oracle.mg_solve(b, order, a, mg=oracle.mg_params(tol=1e-13))
+    assert st == oracle.OK
+    ex = sum(amp / (1 - a * lam(order, n, (kx, ky, kz))) * inputs.sine_mode(n, (kx, ky, kz))
+             for kx, ky, kz, amp in modes)
+    assert np.abs(u - ex).max() <= 1e-11
+
+
+def test_mg_nonconvergence_reported():
+    b = inputs.random_field(15, 2)
+    u, st, cyc, rho = oracle.mg_solve(b, 2, 0.01, mg=oracle.mg_params(tol=1e-14, max_cycles=2))
+    assert st == oracle.ENOCONV and cyc == 2 and rho > 1e-14
+
+
+def test_mg_fixed_cycles_count():
+    b = inputs.random_field(15, 2)
+    u, st, cyc, rho = oracle.mg_solve(b, 2, 0.01, mg=oracle.mg_params(fixed_cycles=3))
+    assert cyc == 3 and st == oracle.OK
+    # contraction of V(2,1): informative bound only
+    assert rho < 0.5**3
+
+
+def test_mg_zero_rhs_gives_zero():
+    b = np.zeros((15, 15, 15))
+    u, st, cyc, rho = oracle.mg_solve(b, 4, 0.01)
+    assert st == oracle.OK and cyc == 0 and not u.any()
+
+
+@pytest.mark.parametrize("n", [7, 15, 31])
+def test_full_weighting_on_sine_modes(n):
+    nc = (n - 1) // 2
+    hf = 1.0 / (n + 1)
+    for k in [(1, 1, 1), (2, 3, 1), (nc, 1, nc)]:
+        rc = oracle.restrict_fw(inputs.sine_mode(n, k))
+        fac = np.prod([math.cos(kk * math.pi * hf / 2) ** 2 for kk in k])
+        assert np.abs(rc - fac * inputs.sine_mode(nc, k)).max() < 1e-14
+
+
+@pytest.mark.parametrize("n", [3, 7, 15])
+def test_restriction_is_prolongation_transpose_over_8(n):
+    nc = (n - 1) // 2
+    rng = np.random.default_rng(n)
+    rf = rng.standard_normal((n, n, n))
+    ec = rng.standard_normal((nc, nc, nc))
+    lhs = (oracle.restrict_fw(rf) * ec).sum()
+    rhs = (rf * oracle.prolong_add(ec, np.zeros((n, n, n)))).sum() / 8.0
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_prolongation_of_constant():
+    nc = 7
+    n = 2 * nc + 1
+    p = np.ones(n)
+    p[0] = p[-1] = 0.5
+    ex = p[:, None, None] * p[None, :, None] * p[None, None, :]
+    assert np.array_equal(oracle.prolong_add(np.ones((nc, nc, nc)), np.zeros((n, n, n))), ex)
+    base = inputs.random_field(n, 1)
+    assert np.abs(oracle.prolong_add(np.ones((nc, nc, nc)), base) - (base + ex)).max() < 1e-15
+
+
+def test_injection_picks_odd_points():
+    n = 15
+    u = inputs.random_field(n, 9)
+    assert np.array_equal(oracle.inject(u), u[1::2, 1::2, 1::2])
+
+
+def test_jacobi_on_sine_mode_multiplier():
+    n, a, om = 15, 0.01, 6 / 7
+    h = 1.0 / (n + 1)
+    k = (3, 1, 6)
+    u = inputs.sine_mode(n, k)
+    D = 1 + a * 6 / h**2
+    mult = 1 - om * (1 - a * lam2(n, k)) / D
+    out = oracle.jacobi(u, np.zeros_like(u), 2, a, om)
+    assert np.abs(out - mult * u).max() < 1e-14
+
+
+def test_jacobi4_diagonal_at_walls():
+    # The 4th-order diagonal per axis is 30/12 inside and 29/12 next to a wall.
+    n, a, om = 7, 0.02, 1.0
+    h = 1.0 / (n + 1)
+    for idx in [(0, 3, 3), (3, 3, 3), (0, 0, 6), (6, 6, 6)]:
+        e = np.zeros((n, n, n)); e[idx] = 1.0
+        A = oracle.heat_op(e, 4, a)
+        D = A[idx]
+        w = sum((30 - (i == 0) - (i == n - 1)) / 12 for i in idx)
+        assert abs(D - (1 + a * w / h**2)) < 1e-12 * D
+        # one Jacobi sweep with omega = 1 from u = 0 gives b / D
+        out = oracle.jacobi(np.zeros((n, n, n)), e, 4, a, om)
+        assert abs(out[idx] - 1 / D) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# Collocation weights (section 1.1, eq. (6))
+# ----------------------------------------------------------------------------
+
+def exact_q(M):
+    s = sp.Symbol("s")
+    if M == 3:
+        t = [sp.Integer(0), sp.Rational(1, 2), sp.Integer(1)]
+    else:
+        r = sp.sqrt(21) / 14
+        t = [sp.Integer(0), sp.Rational(1, 2) - r, sp.Rational(1, 2), sp.Rational(1, 2) + r, sp.Integer(1)]
+    Q = sp.zeros(M, M)
+    for j in range(M):
+        lj = sp.Integer(1)
+        for i in range(M):
+            if i != j:
+                lj *= (s - t[i]) / (t[j] - t[i])
+        for m in range(M):
+            Q[m, j] = sp.integrate(sp.expand(lj), (s, 0, t[m]))
+    return t, Q
+
+
+def test_lobatto_nodes_exact():
+    assert np.array_equal(oracle.lobatto_nodes(3), [0.0, 0.5, 1.0])
+    r = math.sqrt(21) / 14
+    assert np.abs(oracle.lobatto_nodes(5) - [0, 0.5 - r, 0.5, 0.5 + r, 1]).max() < 2e-16
+
+
+def test_collocation_matrix_m3_rational():
+    Q = oracle.collocation_matrix(3)
+    ex = [[Fraction(0), Fraction(0), Fraction(0)],
+          [Fraction(5, 24), Fraction(1, 3), Fraction(-1, 24)],
+          [Fraction(1, 6), Fraction(2, 3), Fraction(1, 6)]]
+    assert np.abs(Q - np.array(ex, dtype=float)).max() < 1e-16
+
+
+def test_collocation_matrix_m5_exact_sqrt21():
+    t, Qex = exact_q(5)
+    Q = oracle.collocation_matrix(5)
+    Qf = np.array(Qex.evalf(30).tolist(), dtype=float)
+    assert np.abs(Q - Qf).max() < 4e-16
+    # the printed closed forms of the last and middle rows
+    assert np.abs(Q[4] - [1 / 20, 49 / 180, 16 / 45, 49 / 180, 1 / 20]).max() < 1e-16
+    r = 7 * math.sqrt(21) / 192
+    assert np.abs(Q[2] - [13 / 320, 49 / 360 + r, 8 / 45, 49 / 360 - r, 3 / 320]).max() < 1e-16
+
+
+@pytest.mark.parametrize("M", [3, 5])
+def test_collocation_matrix_polynomial_exactness(M):
+    Q = oracle.collocation_matrix(M)
+    t = oracle.lobatto_nodes(M)
+    for p in range(M):
+        assert np.abs(Q @ t**p - t ** (p + 1) / (p + 1)).max() < 1e-15
+    # the end-point row is the Lobatto quadrature, exact to degree 2M-3
+    for p in range(2 * M - 2):
+        assert abs(Q[-1] @ t**p - 1 / (p + 1)) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# SDC (section 1.1, eqs. (5)-(9))
+# ----------------------------------------------------------------------------
+
+def pade_diag(m, z):
+    num = sum(math.factorial(2 * m - j) * math.factorial(m) / (math.factorial(2 * m) * math.factorial(j)
+              * math.factorial(m - j)) * z**j for j in range(m + 1))
+    den = sum(math.factorial(2 * m - j) * math.factorial(m) / (math.factorial(2 * m) * math.factorial(j)
+              * math.factorial(m - j)) * (-z) ** j for j in range(m + 1))
+    return num / den
+
+
+TIGHT = oracle.mg_params(tol=1e-14, max_cycles=200)
+
+
+@pytest.mark.parametrize("M,order", [(3, 2), (5, 4), (5, 2)])
+def test_converged_sdc_is_lobatto_iiia(M, order):
+    """Many sweeps reach the collocation solution; on an unforced sine mode
+    its amplification is the diagonal Pade approximant R_{M-1,M-1}(z)."""
+    n, nu, dt = 7, 0.1, 0.1
+    k = (2, 1, 3)
+    pb = oracle.problem([(n, order, M)], nu=nu, dt=dt, nsteps=1, sweeps=40, mg=TIGHT)
+    u, st, stats = oracle.run(pb, inputs.sine_mode(n, k))
+    assert st == oracle.OK
+    z = dt * nu * lam(order, n, k)
+    assert abs(project(u, k) - pade_diag(M - 1, z)) < 1e-12
+    assert stats.last_residual < 1e-13
+
+
+@pytest.mark.parametrize("M", [3, 5])
+def test_converged_sdc_forced_mode_is_collocation_solution(M):
+    """Forced mode (1,1,1): the collocation system of eq. (6), solved densely."""
+    n, nu, dt, c, t0 = 7, 0.1, 0.2, 3.0, 0.3
+    pb = oracle.problem([(n, 2, M)], nu=nu, t0=t0, dt=dt, nsteps=1, sweeps=60, forcing_c=c, mg=TIGHT)
+    u, st, _ = oracle.run(pb, inputs.sine_product(n))
+    t, Qex = exact_q(M)
+    Q = np.array(Qex.evalf(30).tolist(), dtype=float)
+    tau = np.array([float(x) for x in t])
+    mu = nu * lam2(n, (1, 1, 1))
+    g = -(np.sin(t0 + dt * tau) - c * nu * math.pi**2 * np.cos(t0 + dt * tau))
+    A = np.eye(M) - dt * mu * Q
+    a = np.linalg.solve(A, np.ones(M) + dt * Q @ g)
+    assert abs(project(u, (1, 1, 1)) - a[-1]) < 1e-12
+
+
+def semi_discrete_exact(mu, C, a0, t):
+    """a' = -mu a - (sin t - C cos t), a(0) = a0, closed form."""
+    A = (1 + C * mu) / (1 + mu * mu)
+    B = (C - mu) / (1 + mu * mu)
+    return A * math.cos(t) + B * math.sin(t) + (a0 - A) * math.exp(-mu * t)
+
+
+@pytest.mark.parametrize("order,c", [(2, 3.0), (4, 3.0), (2, 1.0)])
+def test_sdc_matches_semi_discrete_exact_solution(order, c):
+    """Several converged steps follow the exact solution of the semi-discrete
+    ODE for the forced mode (both the consistent c=3 and the printed c=1)."""
+    n, nu, dt, nsteps = 7, 0.1, 0.05, 6
+    pb = oracle.problem([(n, order, 5)], nu=nu, dt=dt, nsteps=nsteps, sweeps=12, forcing_c=c, mg=TIGHT)
+    u, st, _ = oracle.run(pb, inputs.sine_product(n))
+    mu = -nu * lam(order, n, (1, 1, 1))
+    ex = semi_discrete_exact(mu, c * nu * math.pi**2, 1.0, nsteps * dt)
+    assert abs(project(u, (1, 1, 1)) - ex) < 1e-11
+    # no other mode is excited
+    resid = u - project(u, (1, 1, 1)) * inputs.sine_product(n)
+    assert np.abs(resid).max() < 1e-12
+
+
+def test_sdc_sweeps_gain_one_order_each():
+    """k sweeps from the spread predictor: local error O(dt^(k+1)) (section 1.1)."""
+    n, nu = 7, 0.1
+    k = (1, 2, 1)
+    z_rate = nu * lam2(n, k)
+    for sweeps in (1, 2, 3):
+        errs = []
+        dts = [0.02, 0.01, 0.005]
+        for dt in dts:
+            pb = oracle.problem([(n, 2, 5)], nu=nu, dt=dt, nsteps=1, sweeps=sweeps, mg=TIGHT)
+            u, _, _ = oracle.run(pb, inputs.sine_mode(n, k))
+            errs.append(abs(project(u, k) - math.exp(dt * z_rate)))
+        slopes = [math.log(errs[i] / errs[i + 1]) / math.log(2) for i in range(2)]
+        assert abs(slopes[-1] - (sweeps + 1)) < 0.3, (sweeps, slopes)
+
+
+@pytest.mark.parametrize("order,expect", [(2, 4.0), (4, 16.0)])
+def test_manufactured_solution_spatial_order(order, expect):
+    """u = s(x) cos t with the consistent forcing (c = 3): error ratio per
+    halving of h is 4 (2nd order) and 16 (4th order)."""
+    errs = []
+    for n in (7, 15):
+        pb = oracle.problem([(n, order, 5)], nu=0.1, dt=0.1, nsteps=3, sweeps=10, forcing_c=3.0, mg=TIGHT)
+        u, st, _ = oracle.run(pb, inputs.sine_product(n))
+        ex = inputs.sine_product(n) * math.cos(0.3)
+        errs.append(np.abs(u - ex).max() / np.abs(ex).max())
+    ratio = errs[0] / errs[1]
+    assert abs(ratio - expect) / expect < 0.1, (errs, ratio)
+
+
+def test_sdc_residual_stopping_rule():
+    n = 7
+    pb = oracle.problem([(n, 2, 3)], nu=0.1, dt=0.1, nsteps=1, sweeps=0, sdc_tol=1e-10, max_sweeps=30,
+                        mg=TIGHT)
+    u, st, stats = oracle.run(pb, inputs.random_smooth(n, 0))
+    assert st == oracle.OK and stats.last_residual <= 1e-10 and 1 <= stats.sweeps < 30
+    pb.max_sweeps = 1
+    u, st, stats = oracle.run(pb, inputs.random_smooth(n, 0))
+    assert st == oracle.ENOCONV
+
+
+# ----------------------------------------------------------------------------
+# MLSDC / FAS / PFASST
+# ----------------------------------------------------------------------------
+
+def two_level(nf=15, nsteps=1, sweeps=3, dt=0.05, c=3.0, mg=None, t0=0.0):
+    return oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, t0=t0, dt=dt, nsteps=nsteps,
+                          sweeps=sweeps, forcing_c=c, mg=mg if mg is not None else TIGHT)
+
+
+def fine_collocation(pb, u0, tn):
+    lf = pb.lev[0]
+    U, FI = oracle.spread(lf, pb.nu, u0)
+    for _ in range(70):
+        oracle.sdc_sweep(lf, pb.mg, pb.nu, tn, pb.dt, pb.forcing_c, U, FI)
+    return U, FI
+
+
+def test_fas_fixed_point():
+    """If the fine level holds its collocation solution, the coarse sweep
+    with tau leaves the restricted values unchanged and the correction is 0."""
+    pb = two_level(nf=15, dt=0.1)
+    u0 = inputs.random_smooth(15, 4)
+    tn = 0.2
+    Uf, FIf = fine_collocation(pb, u0, tn)
+    lf, lc = pb.lev[0], pb.lev[1]
+    Uc, FIc, Ut, tau = oracle.fas_restrict(lf, lc, pb.nu, tn, pb.dt, pb.forcing_c, Uf, FIf)
+    assert np.abs(tau[0]).max() == 0.0
+    assert np.abs(tau[1:]).max() > 1e-6          # tau is not trivially zero
+    # the restricted values satisfy the coarse FAS collocation equation
+    assert oracle.sdc_residual(lc, pb.nu, tn, pb.dt, pb.forcing_c, Uc, FIc, tau) < 1e-12
+    assert oracle.sdc_residual(lc, pb.nu, tn, pb.dt, pb.forcing_c, Uc, FIc, None) > 1e-6
+    st, _ = oracle.sdc_sweep(lc, pb.mg, pb.nu, tn, pb.dt, pb.forcing_c, Uc, FIc, tau)
+    assert np.abs(Uc - Ut).max() < 1e-12
+    U2, F2 = Uf.copy(), FIf.copy()
+    oracle.fas_interp(lf, lc, pb.nu, U2, F2, Uc, Ut)
+    assert np.abs(U2 - Uf).max() < 1e-12
+
+
+def test_fas_coarse_sweep_without_tau_moves():
+    """Control for the fixed-point test: dropping tau breaks it."""
+    pb = two_level(nf=15, dt=0.1)
+    u0 = inputs.random_smooth(15, 4)
+    Uf, FIf = fine_collocation(pb, u0, 0.0)
+    Uc, FIc, Ut, tau = oracle.fas_restrict(pb.lev[0], pb.lev[1], pb.nu, 0.0, pb.dt, pb.forcing_c, Uf, FIf)
+    oracle.sdc_sweep(pb.lev[1], pb.mg, pb.nu, 0.0, pb.dt, pb.forcing_c, Uc, FIc, np.zeros_like(tau))
+    assert np.abs(Uc - Ut).max() > 1e-6
+
+
+def test_fas_interp_time_is_quadratic_exact():
+    """Coarse corrections that are quadratic in time are reproduced exactly at
+    the fine nodes (Lagrange interpolation on the 3 coarse nodes)."""
+    pb = two_level(nf=7)
+    lf, lc = pb.lev[0], pb.lev[1]
+    phi = inputs.random_field(3, 8)
+    q = lambda s: 0.3 - 1.7 * s + 2.2 * s * s
+    tc = oracle.lobatto_nodes(3)
+    tf = oracle.lobatto_nodes(5)
+    Ut = np.zeros((3, 3, 3, 3))
+    Uc = np.stack([q(t) * phi for t in tc])
+    Uf = np.zeros((5, 7, 7, 7)); FIf = np.zeros_like(Uf)
+    oracle.fas_interp(lf, lc, pb.nu, Uf, FIf, Uc, Ut)
+    Pphi = oracle.prolong_add(phi, np.zeros((7, 7, 7)))
+    for m in range(5):
+        assert np.abs(Uf[m] - q(tf[m]) * Pphi).max() < 1e-14
+        assert np.abs(FIf[m] - pb.nu * oracle.laplacian(Uf[m], 4)).max() < 1e-12
+
+
+def test_mlsdc_converges_to_fine_collocation():
+    pb = two_level(nf=7, sweeps=50, dt=0.1)
+    u0 = inputs.random_smooth(7, 6)
+    u, st, _ = oracle.run(pb, u0)
+    Uf, _ = fine_collocation(pb, u0, 0.0)
+    assert np.abs(u - Uf[-1]).max() < 1e-11
+
+
+def test_pfasst_one_slice_is_mlsdc():
+    pb = two_level(nf=15, nsteps=2, sweeps=3)
+    u0 = inputs.random_smooth(15, 7)
+    a, s1, _ = oracle.run(pb, u0)
+    b, s2, _ = oracle.pfasst_run(pb, 1, u0)
+    assert s1 == s2 == oracle.OK
+    assert np.array_equal(a, b)
+
+
+def test_pfasst_converges_to_serial_composite_collocation():
+    P = 4
+    pb = two_level(nf=7, nsteps=P, sweeps=60, dt=0.05)
+    u0 = inputs.random_smooth(7, 8)
+    u, st, _ = oracle.pfasst_run(pb, P, u0)
+    ref = u0.copy()
+    for p in range(P):
+        Uf, _ = fine_collocation(pb, ref, p * pb.dt)
+        ref = Uf[-1].copy()
+    assert np.abs(u - ref).max() < 1e-11
+
+
+def test_pfasst_few_iterations_differs_from_serial():
+    """Control: with 2 iterations the slices have not converged."""
+    P = 4
+    pb = two_level(nf=7, nsteps=P, sweeps=2, dt=0.05)
+    u0 = inputs.random_smooth(7, 8)
+    u, st, _ = oracle.pfasst_run(pb, P, u0)
+    pb2 = two_level(nf=7, nsteps=P, sweeps=30, dt=0.05)
+    v, _, _ = oracle.pfasst_run(pb2, P, u0)
+    assert np.abs(u - v).max() > 1e-9
