@@ -1,0 +1,223 @@
+/*
+ * heatst.h -- C ABI of libheatst, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of the space-time heat solver of Speck, Ruprecht,
+ * Emmett, Bolten and Krause, "A space-time parallel solver for the
+ * three-dimensional heat equation" (arXiv 1307.7867).
+ *
+ * Problem (section 1, eqs. (1)-(4)): u_t = nu Lap(u) + f on [0,1]^3 with
+ * u = 0 on the boundary and the manufactured forcing
+ *     f(x,t) = -s(x) (sin t - c nu pi^2 cos t),  s(x) = prod_d sin(pi x_d).
+ * The paper prints c = 1; its analytic solution u = s(x) cos t (eq. (4))
+ * holds for c = 3 in three dimensions.  c is a parameter (forcing_c).
+ *
+ * Space (section 1, method of lines): n interior points per axis,
+ * h = 1/(n+1), n = 2^k - 1, 1 <= n <= 511.  L_h is the 7-point
+ * second-order stencil (order 2) or the wide 13-point fourth-order stencil
+ * (order 4) with the odd reflection u(-h) = -u(h) beyond each wall.
+ *
+ * Time (section 1.1): spectral deferred corrections on M Gauss-Lobatto
+ * nodes (M = 2..5; the paper uses 5 on the fine and 3 on the coarse
+ * level) with IMEX-Euler sweeps (eq. (7)); the node-to-node integrals use
+ * the collocation matrix of eq. (6); each implicit substep solves
+ * (I - nu dt_m L_h) U_{m+1} = rhs by geometric multigrid (section 1.2);
+ * two-level MLSDC couples the levels by the FAS correction; PFASST runs
+ * MLSDC iterations on consecutive time slices.
+ *
+ * Memory and data layout.
+ *   - Every field is a contiguous float64 array in [z][y][x] order (x
+ *     fastest) of n^3 interior values; point (i,j,k) sits at
+ *     x = ((i+1)h, (j+1)h, (k+1)h).
+ *   - A "lane" is one independent problem instance or one PFASST time
+ *     slice.  Multi-lane user arrays are lane-major: lane b's field starts
+ *     at the sum of n_{b'}^3 over b' < b.
+ *   - All device memory is owned by the caller: hs_workspace_bytes gives
+ *     the exact size, hs_plan_bind hands it over.  The library never
+ *     allocates device memory.  The plan object itself is host memory owned
+ *     by the library (hs_plan_create / hs_plan_destroy).
+ *   - Pointers named d_* are device pointers, h_* host pointers.
+ *   - stream is a hipStream_t (NULL = default stream).  Every call is
+ *     asynchronous on it unless documented otherwise.
+ *
+ * Errors.  Every call returns an hs_status.  Arguments are validated on the
+ * host before anything is launched; an invalid call changes nothing.
+ * Numerical failures (a solve that hits its cycle limit, a non-finite
+ * residual) are recorded per lane and reported by hs_stats_read and by
+ * the calls that synchronise.
+ */
+#ifndef HEATST_H
+#define HEATST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HS_OK = 0,
+    HS_EINVAL = -1,      /* invalid argument or problem description */
+    HS_ENOMEM = -2,      /* workspace too small / admission budget exhausted */
+    HS_ENOCONV = -3,     /* a solve or the SDC iteration hit its iteration cap */
+    HS_ENONFINITE = -4,  /* a residual became NaN or Inf */
+    HS_EDEVICE = -5,     /* a HIP call failed */
+    HS_ESTATE = -6,      /* call out of order (e.g. plan not bound) */
+    HS_PENDING = 1       /* serving: request not finished yet */
+} hs_status;
+
+typedef enum { HS_FP64 = 0, HS_MIXED = 1 } hs_precision;
+
+/* One SDC level: grid, Laplacian order, collocation nodes. */
+typedef struct {
+    int32_t n;        /* interior points per axis, 2^k - 1, 1..511 */
+    int32_t order;    /* 2 or 4 */
+    int32_t nnodes;   /* Gauss-Lobatto nodes incl. both ends, 2..5 */
+} hs_level_desc;
+
+/*
+ * Multigrid for (I - a L_h) u = b (section 1.2 states only that a parallel
+ * geometric multigrid method is used).  Components: same-order
+ * rediscretisation on grids n -> (n-1)/2 down to n_coarsest, weighted
+ * Jacobi, full weighting, trilinear prolongation, exact solve on the
+ * coarsest grid, V(nu1,nu2) cycles.
+ * Stopping (FP64): before every cycle rho = |b - A u|_inf / |b|_inf; stop
+ * when rho <= tol, fail (HS_ENOCONV) after max_cycles cycles.  With
+ * fixed_cycles > 0 exactly that many cycles run and no norm is taken.
+ * HS_MIXED: FP64 iterative refinement around one FP32 V(inner_nu1,
+ * inner_nu2) cycle per iteration; tol / max_cycles then apply to the
+ * refinement iterations.
+ */
+typedef struct {
+    int32_t nu1, nu2;        /* pre / post smoothing sweeps (nu1 >= 1) */
+    double omega;            /* Jacobi weight (6/7) */
+    int32_t n_coarsest;      /* 3 or 1 */
+    double tol;              /* relative max-norm residual target */
+    int32_t max_cycles;
+    int32_t fixed_cycles;    /* > 0: exactly this many cycles */
+    int32_t precision;       /* hs_precision */
+    int32_t inner_nu1, inner_nu2;
+} hs_mg_desc;
+
+typedef struct {
+    double nu;               /* diffusion coefficient (0.1 in the paper) */
+    double t0, dt;           /* start time, step size */
+    double forcing_c;        /* c of the forcing: 3 consistent, 1 as printed, 0 for s(x) sin t */
+    int32_t nsteps;
+    int32_t nlevels;         /* 1 = SDC, 2 = MLSDC / PFASST */
+    hs_level_desc lev[2];    /* lev[0] fine; lev[1] coarse: n = (n_f - 1)/2, order 2 */
+    hs_mg_desc mg;
+    int32_t sweeps;          /* fixed sweeps (SDC) / iterations (MLSDC, PFASST); 0 = until sdc_tol */
+    double sdc_tol;          /* absolute max-norm collocation residual target */
+    int32_t max_sweeps;
+    int32_t batch;           /* lanes */
+    int32_t nslices;         /* 1, or = batch for PFASST time slices */
+    const int32_t* h_lane_n; /* NULL, or per-lane fine n (uneven batches, nlevels = 1) */
+} hs_problem;
+
+/* Per-lane statistics (hs_stats_read). */
+typedef struct {
+    int32_t status;          /* sticky hs_status of the lane */
+    int32_t steps_done;
+    int32_t total_sweeps;
+    int32_t total_solves;
+    int64_t total_cycles;    /* V-cycles (FP64) or refinement iterations (mixed) */
+    int32_t max_cycles;      /* most cycles of one solve */
+    int32_t failed_solves;
+    double last_rho;         /* relative residual of the last solve */
+    double last_sdc_res;     /* last collocation residual taken */
+} hs_lane_stats;
+
+typedef struct hs_plan hs_plan;
+
+const char* hs_status_string(hs_status s);
+
+/* Library version and the collocation data it uses: nodes tau[M] and the
+ * matrix Q[M*M] of eq. (6) (row m = node, column j = source node). */
+hs_status hs_collocation(int32_t M, double* h_tau, double* h_Q);
+
+/* Exact number of workspace bytes a plan for *pb needs. */
+hs_status hs_workspace_bytes(const hs_problem* pb, size_t* bytes);
+
+/* Validate *pb and build the host-side plan (no device work). */
+hs_status hs_plan_create(const hs_problem* pb, hs_plan** plan);
+
+/* Lay the plan out in caller-owned device memory d_ws (>= the size from
+ * hs_workspace_bytes, 256-byte aligned) and upload its tables.  Synchronous.
+ * Every lane starts active with the problem's nu, dt, t0, nsteps. */
+hs_status hs_plan_bind(hs_plan* plan, void* d_ws, size_t bytes, void* stream);
+
+hs_status hs_plan_destroy(hs_plan* plan);
+
+/* Number of lanes and lane l's fine n (for sizing user arrays). */
+hs_status hs_plan_lanes(const hs_plan* plan, int32_t* lanes, int32_t* h_lane_n);
+
+/* Lane parameters (per-lane nu, dt, t0, steps; active = 0 frees the lane). */
+hs_status hs_set_lane(hs_plan* plan, int32_t lane, double nu, double dt, double t0,
+                      int32_t nsteps, int32_t active, void* stream);
+
+/* Kernel-level calls (section 1, method of lines) on lane-major arrays of
+ * SDC level `level`:
+ *   hs_lap_apply: d_y = alpha d_u + beta L_h d_u
+ *   hs_heat_rhs:  d_fi = nu_l L_h d_u and d_fe = f(x, h_t[l]) per lane l
+ *                 (either output may be NULL). */
+hs_status hs_lap_apply(hs_plan* plan, int32_t level, double alpha, double beta,
+                       const double* d_u, double* d_y, void* stream);
+hs_status hs_heat_rhs(hs_plan* plan, int32_t level, const double* d_u, const double* h_t,
+                      double* d_fi, double* d_fe, void* stream);
+
+/* Multigrid solve (I - a_l L_h) u = b per lane l of SDC level `level` as
+ * configured in the plan's hs_mg_desc, from the initial guess in d_u
+ * (overwritten with the solution).  h_a: host array of per-lane a.
+ * Synchronises; returns the worst lane status. */
+hs_status hs_mg_vcycle(hs_plan* plan, int32_t level, const double* h_a, double* d_u,
+                       const double* d_b, void* stream);
+
+/* State (the value at the start of the next step) of every lane, lane-major
+ * fine-level fields.  hs_set_state also resets the lanes' step counters.
+ * For PFASST plans d_u0 holds one field that every slice starts from and
+ * hs_get_state returns the end value of the last slice. */
+hs_status hs_set_state(hs_plan* plan, const double* d_u0, void* stream);
+hs_status hs_get_state(hs_plan* plan, double* d_u, void* stream);
+
+/* Node data of SDC level `level`: d_U and d_FI are lane-major [lane][M][N]
+ * (FI = nu L_h U); d_Ut / d_tau (coarse level of an MLSDC plan) hold the
+ * restricted fine values and the FAS correction.  Any pointer may be NULL. */
+hs_status hs_get_nodes(hs_plan* plan, int32_t level, double* d_U, double* d_FI, double* d_Ut,
+                       double* d_tau, void* stream);
+hs_status hs_set_nodes(hs_plan* plan, int32_t level, const double* d_U, const double* d_FI,
+                       void* stream);
+
+/* Step-level calls, in the order a time step uses them:
+ *   hs_begin_step : step coefficients, predictor (spread the state to all nodes)
+ *   hs_sdc_sweep  : one IMEX SDC sweep of SDC level `level` (eq. (7)); on
+ *                   the coarse level of an MLSDC plan it includes tau
+ *   hs_fas_restrict / hs_fas_interp : FAS transfer between the levels
+ *   hs_mlsdc_iter : fine sweep, restriction + tau, coarse sweep, interpolation
+ *   hs_end_step   : the last node becomes the state (eq. (9)). */
+hs_status hs_begin_step(hs_plan* plan, void* stream);
+hs_status hs_sdc_sweep(hs_plan* plan, int32_t level, void* stream);
+hs_status hs_fas_restrict(hs_plan* plan, void* stream);
+hs_status hs_fas_interp(hs_plan* plan, void* stream);
+hs_status hs_mlsdc_iter(hs_plan* plan, void* stream);
+hs_status hs_end_step(hs_plan* plan, void* stream);
+
+/* One full step (fixed sweeps, or sweeps until sdc_tol) / all nsteps. */
+hs_status hs_step(hs_plan* plan, void* stream);
+hs_status hs_solve(hs_plan* plan, void* stream);
+
+/* PFASST (nslices = batch = P, nlevels = 2): nsteps / P blocks of P slices,
+ * `sweeps` iterations each. */
+hs_status hs_pfasst_run(hs_plan* plan, void* stream);
+
+/* Capture hs_step into a HIP graph and replay it for the remaining steps
+ * (fixed sweep and cycle counts only). */
+hs_status hs_solve_graph(hs_plan* plan, void* stream);
+
+/* Per-lane statistics; synchronises the stream.  h_out has `batch` entries. */
+hs_status hs_stats_read(hs_plan* plan, hs_lane_stats* h_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEATST_H */

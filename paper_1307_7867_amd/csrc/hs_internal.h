@@ -1,0 +1,221 @@
+// Internal definitions shared by the device kernels and the host driver of
+// libheatst.  Not part of the public C ABI (include/heatst.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define HS_MAXM 5          // collocation nodes per SDC level (3 and 5 are used)
+#define HS_MAXTAIL 5       // grids inside the single-workgroup coarse tail (15, 7, 3, 1)
+#define HS_TAIL_N 15       // grids with n <= HS_TAIL_N are handled by the tail kernel
+#define HS_BLOCK 256       // threads per block of the grid kernels
+#define HS_TX 64           // block tile along x (one wavefront per row)
+#define HS_TY 4            // block tile along y
+#define HS_TAIL_THREADS 512
+
+// Per-lane state in device memory.  A lane is one independent problem
+// instance or one PFASST time slice.
+struct LaneCtl {
+    // parameters
+    double nu, dt, t0, forcing_c;
+    int32_t nsteps, step;        // requested / completed steps
+    int32_t active, pad0;        // 1 = lane holds a live problem
+    // coefficients of the current step, per SDC level
+    double tn;
+    double a[2][HS_MAXM];        // nu * dt_m (substep m)
+    double g[2][HS_MAXM];        // forcing time factor -(sin t_j - c nu pi^2 cos t_j)
+    double a_user;               // coefficient for stand-alone solves
+    // control
+    int32_t sdc_state;           // 0 iterate, 1 converged, 2 failed, 3 idle
+    int32_t mg_state;            // 0 iterate, 1 converged, 2 failed, 3 idle
+    int32_t mg_cycle;            // cycles of the current solve
+    int32_t status;              // sticky hs_status of the lane
+    uint32_t red_cnt[4];         // last-block counters of the reductions
+    unsigned long long res_bits; // max-norm accumulators (bit patterns of
+    unsigned long long bn_bits;  //  non-negative doubles order like integers)
+    unsigned long long sdc_bits;
+    double bnorm;                // |b|_inf of the current solve
+    double mg_rho;               // last relative residual of a solve
+    double sdc_res;              // last collocation residual
+    // statistics
+    long long total_cycles;
+    int32_t total_solves, max_cycles, total_sweeps, sweeps_step;
+    int32_t failed_solves, pad1;
+};
+
+// One grid of one lane at one multigrid level.  The finest grid of an SDC
+// solve lives inside the node array: its iterate is u + node * node_stride.
+struct GridSeg {
+    int32_t blk_begin;      // first block of this segment in its launch
+    int32_t lane;
+    int32_t n;              // interior points per axis
+    int32_t nc;             // next coarser grid (0 if none)
+    int32_t coarse;         // 1: correction grid whose first sweep starts from zero
+    int32_t pad;
+    long long node_stride;  // elements per node for the finest grid, else 0
+    void* u;                // iterate
+    void* t;                // ping-pong partner of u
+    void* b;                // right-hand side
+    void* cu;               // coarser grid's iterate (prolongation source)
+    void* cb;               // coarser grid's right-hand side (restriction target)
+};
+
+// The coarse tail of one lane's hierarchy: every grid with n <= HS_TAIL_N,
+// handled by one workgroup.  Level 0 of the tail may be the lane's finest
+// grid (then it may carry a node stride and a non-zero initial guess).
+struct TailSeg {
+    int32_t lane;
+    int32_t nlev;           // grids in the tail
+    int32_t n[HS_MAXTAIL];
+    int32_t coarse_table;   // LibConst::ct index of the exact solve on the last grid
+    int32_t zero_guess;     // level 0 starts from zero (it is a correction grid)
+    int32_t pad;
+    long long node_stride;  // for level 0 only
+    void* u[HS_MAXTAIL];
+    void* t[HS_MAXTAIL];
+    void* b[HS_MAXTAIL];
+};
+
+// Fields of one lane at one SDC level.
+struct SdcSeg {
+    int32_t blk_begin;
+    int32_t lane;
+    int32_t n;
+    int32_t M;
+    double* U;              // [M][N] node values
+    double* FI;             // [M][N] nu L U at the nodes
+    double* P;              // [M-1][N] sweep-constant part of the substep right-hand sides
+    double* rhs;            // [N] right-hand side of the current solve
+    double* Ut;             // [M][N] restricted fine values (coarse MLSDC level only)
+    double* tau;            // [M][N] FAS correction (coarse MLSDC level only)
+    const double* sig;      // [n] sin(pi (i+1) h)
+    int32_t level;          // SDC level (0 fine, 1 coarse)
+    int32_t pad;
+};
+
+// Fine/coarse pair of one lane for the FAS transfers.
+struct FasSeg {
+    int32_t blk_begin;
+    int32_t lane;
+    int32_t nf, nc;
+    int32_t Mf, Mc;
+    double *Uf, *FIf;             // fine [Mf][Nf]
+    double *Uc, *FIc, *Ut, *tau;  // coarse [Mc][Nc]
+    const double* sigf;
+    const double* sigc;
+};
+
+// Exact solve on the coarsest grid (n = 3 or 1) by the discrete sine
+// transform: x = S diag(1 / (1 - a (l_p + l_q + l_r))) S b with the
+// orthonormal DST-I matrix S and the 1-D eigenvalues l of L_h.
+struct CoarseTable {
+    int32_t n;
+    int32_t pad;
+    double S[3][3];
+    double lam[3];
+};
+
+// Collocation constants for M nodes, filled on the host.
+struct SdcConst {
+    int32_t M;
+    int32_t pad;
+    double tau[HS_MAXM];            // nodes on [0,1]
+    double Q[HS_MAXM][HS_MAXM];     // Q[m][j] = int_0^tau_m l_j
+    double S[HS_MAXM][HS_MAXM];     // S[m][j] = Q[m+1][j] - Q[m][j]
+    double dtau[HS_MAXM];           // tau_{m+1} - tau_m
+};
+
+// Coarse-to-fine time interpolation for the FAS transfer (Mf, Mc nodes).
+struct InterpConst {
+    int32_t stride, pad;            // fine node of coarse node m is m * stride
+    double w[HS_MAXM][HS_MAXM];     // w[mf][j] = l^c_j(tau^f_mf)
+};
+
+// Library-wide constants, identical for every plan: indexed by node count,
+// by (fine, coarse) node counts and by (order, coarsest grid).
+struct LibConst {
+    SdcConst sdc[HS_MAXM + 1];
+    InterpConst ip[HS_MAXM + 1][HS_MAXM + 1];
+    CoarseTable ct[4];              // [(order == 4) * 2 + (n == 3)]
+};
+
+// ---------------------------------------------------------------------------
+// Launch helpers implemented in hs_kernels.hip.  All return the hipError_t
+// of the launch.  "nblk" is the total number of blocks of a segment table.
+// ---------------------------------------------------------------------------
+namespace hsk {
+
+struct MgArgs {
+    int32_t L;         // SDC level whose coefficients apply
+    int32_t m;         // substep (index into a[L][]); -1 = a_user
+    double omega;
+    int32_t node;      // node of the finest grid
+    int32_t gate;      // 1 = skip lanes whose mg_state != 0
+};
+
+int grid_blocks(int n);   // blocks covering an n^3 grid
+
+hipError_t set_constants(const LibConst& lc);
+
+template <typename T>
+hipError_t jacobi(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
+                  int first_sweep, int src_is_t, hipStream_t s);
+template <typename T>
+hipError_t resid_restrict(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order,
+                          MgArgs a, int src_is_t, hipStream_t s);
+template <typename T>
+hipError_t prolong(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int src_is_t,
+                   int dst_is_t, hipStream_t s);
+template <typename T>
+hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a, int nu1, int nu2,
+                hipStream_t s);
+
+// max-norm residual test of an FP64 solve before cycle `cycle`
+hipError_t mg_norm(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
+                   int src_is_t, int cycle, double tol, int max_cycles, hipStream_t s);
+// iterative refinement: r = b - A u in FP64, r32 = (float) r into the FP32
+// hierarchy, plus the stopping test
+hipError_t ir_resid(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32, int nseg, int nblk,
+                    int order, MgArgs a, int iter, double tol, int max_iter, hipStream_t s);
+hipError_t ir_update(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32, int nseg,
+                     int nblk, MgArgs a, hipStream_t s);
+
+// SDC level kernels
+hipError_t spread(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int src_node,
+                  hipStream_t s);
+hipError_t sweep_prep(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int with_resid,
+                      double sdc_tol, int max_sweeps, int gate, hipStream_t s);
+hipError_t make_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int m, int gate,
+                    hipStream_t s);
+hipError_t f_update(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int node,
+                    int next_rhs, int gate, hipStream_t s);
+hipError_t eval_fi_all(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int gate,
+                       hipStream_t s);
+hipError_t sdc_resid(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, double sdc_tol,
+                     int max_sweeps, hipStream_t s);
+hipError_t handoff(LaneCtl* ctl, const SdcSeg* dst, const SdcSeg* src, int nseg, int nblk,
+                   int order, hipStream_t s);
+hipError_t fas_restrict(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int corder, int gate,
+                        hipStream_t s);
+hipError_t fas_interp(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int gate,
+                      hipStream_t s);
+
+// lane bookkeeping
+hipError_t begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int M1, hipStream_t s);
+hipError_t end_step(LaneCtl* ctl, int nlanes, hipStream_t s);
+hipError_t begin_solve(LaneCtl* ctl, int nlanes, hipStream_t s);
+hipError_t end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, hipStream_t s);
+hipError_t begin_sweep(LaneCtl* ctl, int nlanes, hipStream_t s);
+hipError_t set_lane(LaneCtl* ctl, int lane, double nu, double dt, double t0, double forcing_c,
+                    int nsteps, int active, hipStream_t s);
+hipError_t set_a_user(LaneCtl* ctl, int lane, double a, hipStream_t s);
+hipError_t copy(const double* src, double* dst, long long count, hipStream_t s);
+
+// kernel-level calls of the public ABI on lane-major packed user arrays
+hipError_t lap_apply(const SdcSeg* segs, int nseg, int nblk, int order, double alpha, double beta,
+                     const double* u, double* y, const long long* offs, hipStream_t s);
+hipError_t heat_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order,
+                    const double* u, const double* t, double* fi, double* fe,
+                    const long long* offs, hipStream_t s);
+
+}  // namespace hsk

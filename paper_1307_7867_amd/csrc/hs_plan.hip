@@ -1,0 +1,1247 @@
+// Host driver of libheatst: plan layout in caller-owned device memory,
+// segment tables, and the multigrid / SDC / MLSDC / PFASST drivers behind
+// the C ABI of include/heatst.h.
+#include "heatst.h"
+#include "hs_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Collocation data (section 1.1, eq. (6)), computed once on the host.
+// ---------------------------------------------------------------------------
+
+// Gauss-Lobatto nodes on [0,1] in closed form (M = 2..5).
+void lobatto(int M, long double* t)
+{
+    const long double h = 0.5L;
+    switch (M) {
+    case 2: t[0] = 0; t[1] = 1; break;
+    case 3: t[0] = 0; t[1] = h; t[2] = 1; break;
+    case 4: {
+        long double d = sqrtl(5.0L) / 10.0L;
+        t[0] = 0; t[1] = h - d; t[2] = h + d; t[3] = 1;
+        break;
+    }
+    default: {
+        long double d = sqrtl(21.0L) / 14.0L;
+        t[0] = 0; t[1] = h - d; t[2] = h; t[3] = h + d; t[4] = 1;
+        break;
+    }
+    }
+}
+
+// Q[m][j] = int_0^{tau_m} l_j(s) ds by expanding l_j in monomials.
+void collocation(int M, long double* t, long double Q[HS_MAXM][HS_MAXM])
+{
+    lobatto(M, t);
+    for (int j = 0; j < M; j++) {
+        long double c[HS_MAXM + 1] = {0};
+        c[0] = 1.0L;
+        int deg = 0;
+        long double den = 1.0L;
+        for (int i = 0; i < M; i++) {
+            if (i == j) continue;
+            // c(s) *= (s - t_i)
+            for (int p = deg + 1; p >= 0; p--) {
+                long double lo = p > 0 ? c[p - 1] : 0.0L;
+                c[p] = lo - t[i] * c[p];
+            }
+            deg++;
+            den *= (t[j] - t[i]);
+        }
+        for (int m = 0; m < M; m++) {
+            long double s = 0.0L, pw = t[m];
+            for (int p = 0; p <= deg; p++) {
+                s += c[p] * pw / (long double)(p + 1);
+                pw *= t[m];
+            }
+            Q[m][j] = s / den;
+        }
+    }
+}
+
+long double lagrange_at(int M, const long double* t, int j, long double s)
+{
+    long double v = 1.0L;
+    for (int i = 0; i < M; i++)
+        if (i != j) v *= (s - t[i]) / (t[j] - t[i]);
+    return v;
+}
+
+LibConst make_libconst()
+{
+    LibConst lc;
+    std::memset(&lc, 0, sizeof(lc));
+    for (int M = 2; M <= HS_MAXM; M++) {
+        long double t[HS_MAXM], Q[HS_MAXM][HS_MAXM];
+        collocation(M, t, Q);
+        SdcConst& K = lc.sdc[M];
+        K.M = M;
+        for (int m = 0; m < M; m++) {
+            K.tau[m] = (double)t[m];
+            for (int j = 0; j < M; j++) K.Q[m][j] = (double)Q[m][j];
+        }
+        for (int m = 0; m + 1 < M; m++) {
+            K.dtau[m] = (double)(t[m + 1] - t[m]);
+            for (int j = 0; j < M; j++) K.S[m][j] = (double)(Q[m + 1][j] - Q[m][j]);
+        }
+    }
+    for (int Mf = 2; Mf <= HS_MAXM; Mf++)
+        for (int Mc = 2; Mc <= Mf; Mc++) {
+            if ((Mf - 1) % (Mc - 1) != 0) continue;
+            long double tf[HS_MAXM], tc[HS_MAXM];
+            lobatto(Mf, tf);
+            lobatto(Mc, tc);
+            InterpConst& ip = lc.ip[Mf][Mc];
+            ip.stride = (Mf - 1) / (Mc - 1);
+            for (int mf = 0; mf < Mf; mf++)
+                for (int j = 0; j < Mc; j++) ip.w[mf][j] = (double)lagrange_at(Mc, tc, j, tf[mf]);
+        }
+    // exact coarsest solves by the sine transform, n = 1 and 3, orders 2 and 4
+    const long double PI = 3.14159265358979323846264338327950288L;
+    for (int o = 0; o < 2; o++)
+        for (int three = 0; three < 2; three++) {
+            CoarseTable& ct = lc.ct[o * 2 + three];
+            int n = three ? 3 : 1;
+            ct.n = n;
+            long double h = 1.0L / (n + 1);
+            for (int p = 0; p < n; p++) {
+                for (int i = 0; i < n; i++)
+                    ct.S[p][i] = (double)(sqrtl(2.0L / (n + 1)) * sinl(PI * (i + 1) * (p + 1) / (n + 1)));
+                long double th = PI * (p + 1) * h;
+                if (o == 0) ct.lam[p] = (double)(-4.0L / (h * h) * sinl(th / 2) * sinl(th / 2));
+                else ct.lam[p] = (double)(-(30.0L - 32.0L * cosl(th) + 2.0L * cosl(2 * th)) / (12.0L * h * h));
+            }
+        }
+    return lc;
+}
+
+std::mutex g_const_mu;
+std::set<int> g_const_devices;
+
+hipError_t ensure_constants()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_const_mu);
+    if (g_const_devices.count(dev)) return hipSuccess;
+    static const LibConst lc = make_libconst();
+    e = hsk::set_constants(lc);
+    if (e == hipSuccess) g_const_devices.insert(dev);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Plan layout
+// ---------------------------------------------------------------------------
+
+bool valid_n(int n) { return n >= 1 && n <= 511 && ((n + 1) & n) == 0; }
+long long cube(int n) { return (long long)n * n * n; }
+
+struct Bump {
+    char* base;   // nullptr while sizing
+    size_t off = 0;
+    explicit Bump(char* b) : base(b) {}
+    size_t take(size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        size_t r = off;
+        off += bytes;
+        return r;
+    }
+    void* ptr(size_t o) const { return base ? (void*)(base + o) : (void*)(uintptr_t)(o + 1); }
+    template <class T> T* arr(size_t count) { return (T*)ptr(take(count * sizeof(T))); }
+};
+
+template <class S>
+struct Table {
+    std::vector<S> h;
+    S* d = nullptr;
+    int nblk = 0;
+    int nseg() const { return (int)h.size(); }
+};
+
+// multigrid tables of one SDC level, one precision, one set of lanes
+struct MgSet {
+    int D = 0;                            // down steps above the tail
+    std::vector<Table<GridSeg>> jac, rr, pro;
+    Table<TailSeg> tail;
+    Table<GridSeg> fine;                  // finest grids (norms, refinement)
+};
+
+struct LaneSet {
+    std::vector<int> lanes;
+    MgSet mg64[2], mg32[2];
+    Table<SdcSeg> sdc[2];
+    Table<FasSeg> fasc, fasf;
+};
+
+struct LaneBufs {
+    int n[2] = {0, 0};
+    long long N[2] = {0, 0};
+    double *U[2], *FI[2], *P[2], *rhs[2], *tmp[2];
+    double *Ut = nullptr, *tau = nullptr;
+    const double* sig[2];
+    std::vector<int> grids[2];                 // n of every multigrid grid, finest first
+    std::vector<double*> gu[2], gt[2], gb[2];  // FP64 grids (index 0 unused)
+    std::vector<float*> fu[2], ft[2], fb[2];   // FP32 grids (mixed precision)
+};
+
+}  // namespace
+
+struct hs_plan {
+    hs_problem pb;
+    std::vector<int> lane_n;
+    int B = 0, nlev = 1;
+    int order[2] = {2, 2}, M[2] = {3, 3};
+    bool mixed = false;
+    size_t bytes = 0;
+    char* ws = nullptr;
+    bool bound = false;
+    int device = 0;
+    LaneCtl* ctl = nullptr;
+    LaneCtl* h_ctl = nullptr;                  // pinned copy for read-backs
+    std::vector<LaneBufs> lanes;
+    LaneSet all;
+    std::vector<LaneSet> single;               // PFASST coarse pipeline, one lane each
+    Table<SdcSeg> hf_dst, hf_src;              // PFASST fine hand-off p-1 -> p
+    std::vector<Table<SdcSeg>> hc_dst, hc_src; // PFASST coarse hand-off, per slice
+    Table<long long> offs[2];                  // lane-major packing offsets per SDC level
+    double* d_times = nullptr;                 // per-lane times for hs_heat_rhs
+    int cpred[2][HS_MAXM];                     // predicted cycles per (level, substep)
+    int cpred_user = 0;
+    int state_ready = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+hs_status dev_err(hipError_t e) { return e == hipSuccess ? HS_OK : HS_EDEVICE; }
+
+#define HS_TRY(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return HS_EDEVICE;    \
+    } while (0)
+
+#define HS_CHECK(x)                                 \
+    do {                                            \
+        hs_status s_ = (x);                         \
+        if (s_ < 0) return s_;                      \
+    } while (0)
+
+std::vector<int> mg_grids(int n, int n_coarsest)
+{
+    std::vector<int> g{n};
+    while (g.back() > n_coarsest && g.back() > 1) g.push_back((g.back() - 1) / 2);
+    return g;
+}
+
+int tail_start(const std::vector<int>& g)
+{
+    int d = 0;
+    while (d < (int)g.size() && g[d] > HS_TAIL_N) d++;
+    return d;
+}
+
+int ct_index(int order, int n) { return (order == 4 ? 2 : 0) + (n == 3 ? 1 : 0); }
+
+template <class S>
+void finish_table(Table<S>& t, Bump& bump)
+{
+    t.d = t.h.empty() ? nullptr : bump.arr<S>(t.h.size());
+}
+
+// Build the multigrid tables of SDC level L for the lanes of `ls`.
+template <typename T>
+void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
+{
+    int Dmax = 0;
+    for (int b : ls.lanes) Dmax = std::max(Dmax, tail_start(P->lanes[b].grids[L]));
+    S.D = Dmax;
+    S.jac.assign(Dmax, {});
+    S.rr.assign(Dmax, {});
+    S.pro.assign(Dmax, {});
+    auto grid_ptrs = [&](const LaneBufs& lb, int l, void** u, void** t, void** b) {
+        if (fp32) {
+            *u = lb.fu[L][l]; *t = lb.ft[L][l]; *b = lb.fb[L][l];
+        } else if (l == 0) {
+            *u = lb.U[L]; *t = lb.tmp[L]; *b = lb.rhs[L];
+        } else {
+            *u = lb.gu[L][l]; *t = lb.gt[L][l]; *b = lb.gb[L][l];
+        }
+    };
+    for (int s = 0; s < Dmax; s++) {
+        int bj = 0, br = 0, bp = 0;
+        for (int b : ls.lanes) {
+            const LaneBufs& lb = P->lanes[b];
+            int Db = tail_start(lb.grids[L]);
+            int l = s - (Dmax - Db);
+            if (l < 0) continue;
+            GridSeg g;
+            std::memset(&g, 0, sizeof(g));
+            g.lane = b;
+            g.n = lb.grids[L][l];
+            g.nc = lb.grids[L][l + 1];
+            g.coarse = (l > 0 || fp32) ? 1 : 0;
+            g.node_stride = (l == 0 && !fp32) ? lb.N[L] : 0;
+            grid_ptrs(lb, l, &g.u, &g.t, &g.b);
+            void *cu, *ct, *cb;
+            grid_ptrs(lb, l + 1, &cu, &ct, &cb);
+            g.cu = cu;
+            g.cb = cb;
+            g.blk_begin = bj; bj += hsk::grid_blocks(g.n); S.jac[s].h.push_back(g);
+            g.blk_begin = br; br += hsk::grid_blocks(g.nc); S.rr[s].h.push_back(g);
+            g.blk_begin = bp; bp += hsk::grid_blocks(g.n); S.pro[s].h.push_back(g);
+        }
+        S.jac[s].nblk = bj;
+        S.rr[s].nblk = br;
+        S.pro[s].nblk = bp;
+    }
+    int bf = 0;
+    for (int b : ls.lanes) {
+        const LaneBufs& lb = P->lanes[b];
+        const std::vector<int>& g = lb.grids[L];
+        int Db = tail_start(g);
+        TailSeg ts;
+        std::memset(&ts, 0, sizeof(ts));
+        ts.lane = b;
+        ts.nlev = (int)g.size() - Db;
+        for (int q = 0; q < ts.nlev; q++) {
+            void *u, *t, *bb;
+            grid_ptrs(lb, Db + q, &u, &t, &bb);
+            ts.n[q] = g[Db + q];
+            ts.u[q] = u; ts.t[q] = t; ts.b[q] = bb;
+        }
+        ts.coarse_table = ct_index(P->order[L], g.back());
+        ts.zero_guess = (Db > 0 || fp32) ? 1 : 0;
+        ts.node_stride = (Db == 0 && !fp32) ? lb.N[L] : 0;
+        S.tail.h.push_back(ts);
+        GridSeg f;
+        std::memset(&f, 0, sizeof(f));
+        f.lane = b;
+        f.n = g[0];
+        f.nc = g.size() > 1 ? g[1] : 0;
+        f.coarse = fp32 ? 1 : 0;
+        f.node_stride = fp32 ? 0 : lb.N[L];
+        grid_ptrs(lb, 0, &f.u, &f.t, &f.b);
+        f.blk_begin = bf;
+        bf += hsk::grid_blocks(f.n);
+        S.fine.h.push_back(f);
+    }
+    S.fine.nblk = bf;
+}
+
+SdcSeg sdc_seg(hs_plan* P, int b, int L)
+{
+    const LaneBufs& lb = P->lanes[b];
+    SdcSeg s;
+    std::memset(&s, 0, sizeof(s));
+    s.lane = b;
+    s.n = lb.n[L];
+    s.M = P->M[L];
+    s.U = lb.U[L]; s.FI = lb.FI[L]; s.P = lb.P[L]; s.rhs = lb.rhs[L];
+    s.Ut = L == 1 ? lb.Ut : nullptr;
+    s.tau = L == 1 ? lb.tau : nullptr;
+    s.sig = lb.sig[L];
+    s.level = L;
+    return s;
+}
+
+void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
+{
+    for (int L = 0; L < P->nlev; L++) {
+        int bk = 0;
+        ls.sdc[L].h.clear();
+        for (int b : ls.lanes) {
+            SdcSeg s = sdc_seg(P, b, L);
+            s.blk_begin = bk;
+            bk += hsk::grid_blocks(s.n);
+            ls.sdc[L].h.push_back(s);
+        }
+        ls.sdc[L].nblk = bk;
+        ls.mg64[L] = MgSet();
+        ls.mg32[L] = MgSet();
+        build_mg<double>(P, ls, L, false, ls.mg64[L]);
+        if (P->mixed) build_mg<float>(P, ls, L, true, ls.mg32[L]);
+    }
+    if (P->nlev == 2) {
+        int bc = 0, bf = 0;
+        ls.fasc.h.clear();
+        ls.fasf.h.clear();
+        for (int b : ls.lanes) {
+            const LaneBufs& lb = P->lanes[b];
+            FasSeg f;
+            std::memset(&f, 0, sizeof(f));
+            f.lane = b;
+            f.nf = lb.n[0]; f.nc = lb.n[1];
+            f.Mf = P->M[0]; f.Mc = P->M[1];
+            f.Uf = lb.U[0]; f.FIf = lb.FI[0];
+            f.Uc = lb.U[1]; f.FIc = lb.FI[1]; f.Ut = lb.Ut; f.tau = lb.tau;
+            f.sigf = lb.sig[0]; f.sigc = lb.sig[1];
+            f.blk_begin = bc; bc += hsk::grid_blocks(f.nc); ls.fasc.h.push_back(f);
+            f.blk_begin = bf; bf += hsk::grid_blocks(f.nf); ls.fasf.h.push_back(f);
+        }
+        ls.fasc.nblk = bc;
+        ls.fasf.nblk = bf;
+    }
+    // device storage of every table
+    for (int L = 0; L < P->nlev; L++) {
+        finish_table(ls.sdc[L], bump);
+        for (MgSet* S : {&ls.mg64[L], &ls.mg32[L]}) {
+            for (auto& t : S->jac) finish_table(t, bump);
+            for (auto& t : S->rr) finish_table(t, bump);
+            for (auto& t : S->pro) finish_table(t, bump);
+            finish_table(S->tail, bump);
+            finish_table(S->fine, bump);
+        }
+    }
+    if (P->nlev == 2) {
+        finish_table(ls.fasc, bump);
+        finish_table(ls.fasf, bump);
+    }
+}
+
+// Lay out the whole workspace.  With base == nullptr only sizes are taken.
+void layout(hs_plan* P, char* base)
+{
+    Bump bump(base);
+    P->ctl = bump.arr<LaneCtl>(P->B);
+    // sine tables, one per distinct n
+    std::map<int, double*> sig;
+    for (int b = 0; b < P->B; b++)
+        for (int L = 0; L < P->nlev; L++) {
+            int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
+            if (!sig.count(n)) sig[n] = bump.arr<double>(n);
+        }
+    P->lanes.assign(P->B, LaneBufs());
+    const hs_mg_desc& mg = P->pb.mg;
+    for (int b = 0; b < P->B; b++) {
+        LaneBufs& lb = P->lanes[b];
+        for (int L = 0; L < P->nlev; L++) {
+            int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
+            long long N = cube(n);
+            int M = P->M[L];
+            lb.n[L] = n;
+            lb.N[L] = N;
+            lb.sig[L] = sig[n];
+            lb.U[L] = bump.arr<double>(M * N);
+            lb.FI[L] = bump.arr<double>(M * N);
+            lb.P[L] = bump.arr<double>((M - 1) * N);
+            lb.rhs[L] = bump.arr<double>(N);
+            lb.tmp[L] = bump.arr<double>(N);
+            if (L == 1) {
+                lb.Ut = bump.arr<double>(M * N);
+                lb.tau = bump.arr<double>(M * N);
+            }
+            lb.grids[L] = mg_grids(n, mg.n_coarsest);
+            size_t G = lb.grids[L].size();
+            lb.gu[L].assign(G, nullptr); lb.gt[L].assign(G, nullptr); lb.gb[L].assign(G, nullptr);
+            lb.fu[L].assign(G, nullptr); lb.ft[L].assign(G, nullptr); lb.fb[L].assign(G, nullptr);
+            for (size_t l = 0; l < G; l++) {
+                long long Ng = cube(lb.grids[L][l]);
+                if (l > 0) {
+                    lb.gu[L][l] = bump.arr<double>(Ng);
+                    lb.gt[L][l] = bump.arr<double>(Ng);
+                    lb.gb[L][l] = bump.arr<double>(Ng);
+                }
+                if (P->mixed) {
+                    lb.fu[L][l] = bump.arr<float>(Ng);
+                    lb.ft[L][l] = bump.arr<float>(Ng);
+                    lb.fb[L][l] = bump.arr<float>(Ng);
+                }
+            }
+        }
+    }
+    for (int L = 0; L < P->nlev; L++) {
+        P->offs[L].h.assign(P->B, 0);
+        long long o = 0;
+        for (int b = 0; b < P->B; b++) {
+            P->offs[L].h[b] = o;
+            o += P->lanes[b].N[L];
+        }
+        finish_table(P->offs[L], bump);
+    }
+    P->d_times = bump.arr<double>(P->B);
+    // lane sets
+    P->all = LaneSet();
+    for (int b = 0; b < P->B; b++) P->all.lanes.push_back(b);
+    build_set(P, P->all, bump);
+    P->single.clear();
+    P->hf_dst = Table<SdcSeg>();
+    P->hf_src = Table<SdcSeg>();
+    P->hc_dst.clear();
+    P->hc_src.clear();
+    if (P->pb.nslices > 1) {
+        P->single.resize(P->B);
+        for (int b = 0; b < P->B; b++) {
+            P->single[b].lanes = {b};
+            build_set(P, P->single[b], bump);
+        }
+        int bk = 0;
+        for (int p = 1; p < P->B; p++) {
+            SdcSeg d = sdc_seg(P, p, 0), s = sdc_seg(P, p - 1, 0);
+            d.blk_begin = s.blk_begin = bk;
+            bk += hsk::grid_blocks(d.n);
+            P->hf_dst.h.push_back(d);
+            P->hf_src.h.push_back(s);
+        }
+        P->hf_dst.nblk = P->hf_src.nblk = bk;
+        finish_table(P->hf_dst, bump);
+        finish_table(P->hf_src, bump);
+        P->hc_dst.resize(P->B);
+        P->hc_src.resize(P->B);
+        for (int p = 1; p < P->B; p++) {
+            SdcSeg d = sdc_seg(P, p, 1), s = sdc_seg(P, p - 1, 1);
+            d.blk_begin = s.blk_begin = 0;
+            P->hc_dst[p].h.push_back(d);
+            P->hc_src[p].h.push_back(s);
+            P->hc_dst[p].nblk = P->hc_src[p].nblk = hsk::grid_blocks(d.n);
+            finish_table(P->hc_dst[p], bump);
+            finish_table(P->hc_src[p], bump);
+        }
+    }
+    P->bytes = (bump.off + 255) & ~(size_t)255;
+}
+
+template <class S>
+hipError_t upload(const Table<S>& t, hipStream_t s)
+{
+    if (t.h.empty()) return hipSuccess;
+    return hipMemcpyAsync(t.d, t.h.data(), t.h.size() * sizeof(S), hipMemcpyHostToDevice, s);
+}
+
+hipError_t upload_set(hs_plan* P, const LaneSet& ls, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int L = 0; L < P->nlev; L++) {
+        if ((e = upload(ls.sdc[L], s)) != hipSuccess) return e;
+        for (const MgSet* S : {&ls.mg64[L], &ls.mg32[L]}) {
+            for (auto& t : S->jac) if ((e = upload(t, s)) != hipSuccess) return e;
+            for (auto& t : S->rr) if ((e = upload(t, s)) != hipSuccess) return e;
+            for (auto& t : S->pro) if ((e = upload(t, s)) != hipSuccess) return e;
+            if ((e = upload(S->tail, s)) != hipSuccess) return e;
+            if ((e = upload(S->fine, s)) != hipSuccess) return e;
+        }
+    }
+    if (P->nlev == 2) {
+        if ((e = upload(ls.fasc, s)) != hipSuccess) return e;
+        if ((e = upload(ls.fasf, s)) != hipSuccess) return e;
+    }
+    return e;
+}
+
+hs_status validate(const hs_problem* pb)
+{
+    if (!pb) return HS_EINVAL;
+    if (pb->nlevels < 1 || pb->nlevels > 2) return HS_EINVAL;
+    if (pb->batch < 1 || pb->batch > 4096) return HS_EINVAL;
+    if (!(pb->nu > 0.0) || !(pb->dt > 0.0) || pb->nsteps < 0) return HS_EINVAL;
+    if (!std::isfinite(pb->t0) || !std::isfinite(pb->forcing_c)) return HS_EINVAL;
+    for (int L = 0; L < pb->nlevels; L++) {
+        const hs_level_desc& d = pb->lev[L];
+        if (d.order != 2 && d.order != 4) return HS_EINVAL;
+        if (d.nnodes < 2 || d.nnodes > HS_MAXM) return HS_EINVAL;
+        if (L == 0 && !pb->h_lane_n && !valid_n(d.n)) return HS_EINVAL;
+    }
+    if (pb->h_lane_n) {
+        if (pb->nlevels != 1) return HS_EINVAL;
+        for (int b = 0; b < pb->batch; b++)
+            if (!valid_n(pb->h_lane_n[b])) return HS_EINVAL;
+    }
+    if (pb->nlevels == 2) {
+        const hs_level_desc &f = pb->lev[0], &c = pb->lev[1];
+        if (f.n < 3 || c.n != (f.n - 1) / 2) return HS_EINVAL;
+        if ((f.nnodes - 1) % (c.nnodes - 1) != 0) return HS_EINVAL;
+    }
+    const hs_mg_desc& mg = pb->mg;
+    if (mg.nu1 < 1 || mg.nu2 < 0 || mg.nu1 > 16 || mg.nu2 > 16) return HS_EINVAL;
+    if (!(mg.omega > 0.0 && mg.omega <= 1.0)) return HS_EINVAL;
+    if (mg.n_coarsest != 1 && mg.n_coarsest != 3) return HS_EINVAL;
+    if (mg.precision != HS_FP64 && mg.precision != HS_MIXED) return HS_EINVAL;
+    if (mg.fixed_cycles < 0 || mg.max_cycles < 0 || mg.max_cycles > 100000) return HS_EINVAL;
+    if (mg.fixed_cycles == 0 && !(mg.tol > 0.0)) return HS_EINVAL;
+    if (mg.precision == HS_MIXED && (mg.inner_nu1 < 1 || mg.inner_nu2 < 0)) return HS_EINVAL;
+    if (pb->sweeps < 0 || pb->max_sweeps < 0) return HS_EINVAL;
+    if (pb->sweeps == 0 && !(pb->sdc_tol > 0.0)) return HS_EINVAL;
+    if (pb->nslices < 1) return HS_EINVAL;
+    if (pb->nslices > 1) {
+        if (pb->nslices != pb->batch || pb->nlevels != 2 || pb->sweeps <= 0) return HS_EINVAL;
+        if (pb->nsteps % pb->nslices != 0) return HS_EINVAL;
+    }
+    return HS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side control: lane states are read back to decide when to stop
+// issuing cycles / sweeps (tolerance mode only).
+// ---------------------------------------------------------------------------
+
+hs_status read_ctl(hs_plan* P, hipStream_t s)
+{
+    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->B, hipMemcpyDeviceToHost, s));
+    HS_TRY(hipStreamSynchronize(s));
+    return HS_OK;
+}
+
+bool all_mg_done(hs_plan* P, const LaneSet& ls, int* maxc)
+{
+    bool done = true;
+    int mc = 0;
+    for (int b : ls.lanes) {
+        const LaneCtl& c = P->h_ctl[b];
+        if (c.mg_state == 0) done = false;
+        else if (c.mg_state != 3) mc = std::max(mc, c.mg_cycle);
+    }
+    *maxc = mc;
+    return done;
+}
+
+bool all_sdc_done(hs_plan* P, const LaneSet& ls)
+{
+    for (int b : ls.lanes)
+        if (P->h_ctl[b].sdc_state == 0) return false;
+    return true;
+}
+
+// One V(nu1,nu2) cycle over the tables of S.
+template <typename T>
+hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
+                 hipStream_t s)
+{
+    for (int st = 0; st < S.D; st++) {
+        const Table<GridSeg>& J = S.jac[st];
+        for (int k = 0; k < nu1; k++)
+            HS_TRY(hsk::jacobi<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, k == 0, k & 1, s));
+        const Table<GridSeg>& R = S.rr[st];
+        HS_TRY(hsk::resid_restrict<T>(P->ctl, R.d, R.nseg(), R.nblk, order, A, nu1 & 1, s));
+    }
+    HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, s));
+    for (int st = S.D - 1; st >= 0; st--) {
+        int in_t = nu1 & 1;
+        int dst_t = ((nu1 + nu2) & 1) ? !in_t : in_t;
+        const Table<GridSeg>& Pr = S.pro[st];
+        HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, in_t, dst_t, s));
+        int cur = dst_t;
+        const Table<GridSeg>& J = S.jac[st];
+        for (int k = 0; k < nu2; k++) {
+            HS_TRY(hsk::jacobi<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, cur, s));
+            cur = !cur;
+        }
+    }
+    return HS_OK;
+}
+
+// Solve (I - a L) U_node = rhs for the lanes of ls at SDC level L; a from
+// the lane's a[L][m] (m >= 0) or a_user (m = -1).
+hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t s, bool* synced)
+{
+    const hs_mg_desc& mg = P->pb.mg;
+    int order = P->order[L];
+    hsk::MgArgs A{L, m, mg.omega, node, 1};
+    HS_TRY(hsk::begin_solve(P->ctl, P->B, s));
+    int& pred = m >= 0 ? P->cpred[L][m] : P->cpred_user;
+    if (!P->mixed) {
+        const MgSet& S = ls.mg64[L];
+        if (mg.fixed_cycles > 0) {
+            for (int c = 0; c < mg.fixed_cycles; c++) HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, s));
+            HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
+            return HS_OK;
+        }
+        for (int c = 0;; c++) {
+            HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, 0, c, mg.tol,
+                                mg.max_cycles, s));
+            if (c >= pred || c >= mg.max_cycles) {
+                HS_CHECK(read_ctl(P, s));
+                if (synced) *synced = true;
+                int mc = 0;
+                if (all_mg_done(P, ls, &mc)) {
+                    pred = mc;
+                    break;
+                }
+            }
+            if (c >= mg.max_cycles) break;
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, s));
+        }
+        return HS_OK;
+    }
+    // mixed precision: FP64 refinement around one FP32 cycle per iteration
+    const MgSet& S64 = ls.mg64[L];
+    const MgSet& S32 = ls.mg32[L];
+    bool fixed = mg.fixed_cycles > 0;
+    int limit = fixed ? mg.fixed_cycles : mg.max_cycles;
+    for (int it = 0;; it++) {
+        if (fixed && it >= limit) break;
+        HS_TRY(hsk::ir_resid(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, order, A,
+                             it, fixed ? -1.0 : mg.tol, fixed ? (1 << 30) : limit, s));
+        if (!fixed && (it >= pred || it >= limit)) {
+            HS_CHECK(read_ctl(P, s));
+            if (synced) *synced = true;
+            int mc = 0;
+            if (all_mg_done(P, ls, &mc)) {
+                pred = mc;
+                break;
+            }
+        }
+        if (!fixed && it >= limit) break;
+        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, s));
+        HS_TRY(hsk::ir_update(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, A, s));
+    }
+    if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, s));
+    return HS_OK;
+}
+
+enum { SWEEP_RAN = 0, SWEEP_DONE = 1 };
+
+// One SDC sweep of level L over ls (eq. (7)).  With_resid: take the
+// collocation residual first and stop the lanes that meet sdc_tol.
+hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hipStream_t s,
+                int* outcome)
+{
+    const Table<SdcSeg>& T = ls.sdc[L];
+    int M = P->M[L];
+    *outcome = SWEEP_RAN;
+    HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, P->pb.sdc_tol,
+                           P->pb.max_sweeps, 1, s));
+    if (with_resid) {
+        HS_CHECK(read_ctl(P, s));
+        if (all_sdc_done(P, ls)) {
+            *outcome = SWEEP_DONE;
+            return HS_OK;
+        }
+    }
+    if (count) HS_TRY(hsk::begin_sweep(P->ctl, P->B, s));
+    HS_TRY(hsk::make_rhs(P->ctl, T.d, T.nseg(), T.nblk, 0, 1, s));
+    for (int m = 0; m + 1 < M; m++) {
+        HS_CHECK(mg_solve(P, ls, L, m, m + 1, s, nullptr));
+        HS_TRY(hsk::f_update(P->ctl, T.d, T.nseg(), T.nblk, P->order[L], m + 1, m + 2 < M ? 1 : 0, 1, s));
+    }
+    return HS_OK;
+}
+
+hs_status mlsdc_iter(hs_plan* P, LaneSet& ls, bool with_resid, hipStream_t s, int* outcome)
+{
+    HS_CHECK(sweep(P, ls, 0, with_resid, true, s, outcome));
+    if (*outcome == SWEEP_DONE) return HS_OK;
+    HS_TRY(hsk::fas_restrict(P->ctl, ls.fasc.d, ls.fasc.nseg(), ls.fasc.nblk, P->order[1], 1, s));
+    int o2;
+    HS_CHECK(sweep(P, ls, 1, false, false, s, &o2));
+    HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
+    HS_TRY(hsk::eval_fi_all(P->ctl, ls.sdc[0].d, ls.sdc[0].nseg(), ls.sdc[0].nblk, P->order[0], 1, s));
+    return HS_OK;
+}
+
+hs_status begin_step(hs_plan* P, hipStream_t s)
+{
+    HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M[0], P->nlev > 1 ? P->M[1] : P->M[0], s));
+    const Table<SdcSeg>& T = P->all.sdc[0];
+    HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[0], P->M[0] - 1, s));
+    return HS_OK;
+}
+
+hs_status step(hs_plan* P, hipStream_t s)
+{
+    HS_CHECK(begin_step(P, s));
+    const hs_problem& pb = P->pb;
+    int outcome;
+    if (pb.sweeps > 0) {
+        for (int k = 0; k < pb.sweeps; k++) {
+            if (P->nlev == 1) HS_CHECK(sweep(P, P->all, 0, false, true, s, &outcome));
+            else HS_CHECK(mlsdc_iter(P, P->all, false, s, &outcome));
+        }
+    } else {
+        for (int k = 0; k <= pb.max_sweeps + 1; k++) {
+            if (P->nlev == 1) HS_CHECK(sweep(P, P->all, 0, true, true, s, &outcome));
+            else HS_CHECK(mlsdc_iter(P, P->all, true, s, &outcome));
+            if (outcome == SWEEP_DONE) break;
+        }
+    }
+    HS_TRY(hsk::end_step(P->ctl, P->B, s));
+    return HS_OK;
+}
+
+hs_status check_bound(const hs_plan* P)
+{
+    if (!P) return HS_EINVAL;
+    if (!P->bound) return HS_ESTATE;
+    return HS_OK;
+}
+
+hs_status lanes_status(hs_plan* P)
+{
+    int worst = HS_OK;
+    for (int b = 0; b < P->B; b++) {
+        int st = P->h_ctl[b].status;
+        if (st < worst) worst = st;
+    }
+    return (hs_status)worst;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* hs_status_string(hs_status s)
+{
+    switch (s) {
+    case HS_OK: return "ok";
+    case HS_EINVAL: return "invalid argument";
+    case HS_ENOMEM: return "workspace or budget too small";
+    case HS_ENOCONV: return "iteration limit reached without convergence";
+    case HS_ENONFINITE: return "non-finite residual";
+    case HS_EDEVICE: return "HIP error";
+    case HS_ESTATE: return "call out of order";
+    case HS_PENDING: return "pending";
+    }
+    return "unknown status";
+}
+
+hs_status hs_collocation(int32_t M, double* h_tau, double* h_Q)
+{
+    if (M < 2 || M > HS_MAXM) return HS_EINVAL;
+    long double t[HS_MAXM], Q[HS_MAXM][HS_MAXM];
+    collocation(M, t, Q);
+    for (int m = 0; m < M; m++) {
+        if (h_tau) h_tau[m] = (double)t[m];
+        if (h_Q)
+            for (int j = 0; j < M; j++) h_Q[m * M + j] = (double)Q[m][j];
+    }
+    return HS_OK;
+}
+
+static void init_plan(hs_plan* P, const hs_problem* pb)
+{
+    P->pb = *pb;
+    P->B = pb->batch;
+    P->nlev = pb->nlevels;
+    for (int L = 0; L < 2; L++) {
+        P->order[L] = L < pb->nlevels ? pb->lev[L].order : 2;
+        P->M[L] = L < pb->nlevels ? pb->lev[L].nnodes : 2;
+    }
+    P->mixed = pb->mg.precision == HS_MIXED;
+    P->lane_n.assign(P->B, pb->lev[0].n);
+    if (pb->h_lane_n)
+        for (int b = 0; b < P->B; b++) P->lane_n[b] = pb->h_lane_n[b];
+    P->pb.h_lane_n = nullptr;
+    for (int L = 0; L < 2; L++)
+        for (int m = 0; m < HS_MAXM; m++) P->cpred[L][m] = 1;
+    P->cpred_user = 1;
+}
+
+hs_status hs_workspace_bytes(const hs_problem* pb, size_t* bytes)
+{
+    HS_CHECK(validate(pb));
+    if (!bytes) return HS_EINVAL;
+    hs_plan P;
+    init_plan(&P, pb);
+    layout(&P, nullptr);
+    *bytes = P.bytes;
+    return HS_OK;
+}
+
+hs_status hs_plan_create(const hs_problem* pb, hs_plan** plan)
+{
+    if (!plan) return HS_EINVAL;
+    HS_CHECK(validate(pb));
+    hs_plan* P = new (std::nothrow) hs_plan();
+    if (!P) return HS_ENOMEM;
+    init_plan(P, pb);
+    layout(P, nullptr);
+    *plan = P;
+    return HS_OK;
+}
+
+hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
+{
+    if (!P || !d_ws) return HS_EINVAL;
+    if (((uintptr_t)d_ws & 255) != 0) return HS_EINVAL;
+    if (bytes < P->bytes) return HS_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    HS_TRY(ensure_constants());
+    HS_TRY(hipGetDevice(&P->device));
+    P->ws = (char*)d_ws;
+    layout(P, P->ws);
+    if (!P->h_ctl) HS_TRY(hipHostMalloc((void**)&P->h_ctl, sizeof(LaneCtl) * P->B, hipHostMallocDefault));
+    // sine tables sin(pi (i+1) h)
+    std::map<const double*, int> sig;
+    for (auto& lb : P->lanes)
+        for (int L = 0; L < P->nlev; L++) sig[lb.sig[L]] = lb.n[L];
+    std::vector<std::vector<double>> keep;
+    for (auto& kv : sig) {
+        int n = kv.second;
+        keep.emplace_back(n);
+        for (int i = 0; i < n; i++)
+            keep.back()[i] = std::sin(3.14159265358979323846 * (double)(i + 1) / (double)(n + 1));
+        HS_TRY(hipMemcpyAsync((void*)kv.first, keep.back().data(), n * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+    }
+    HS_TRY(upload_set(P, P->all, s));
+    for (auto& ls : P->single) HS_TRY(upload_set(P, ls, s));
+    HS_TRY(upload(P->hf_dst, s));
+    HS_TRY(upload(P->hf_src, s));
+    for (auto& t : P->hc_dst) HS_TRY(upload(t, s));
+    for (auto& t : P->hc_src) HS_TRY(upload(t, s));
+    for (int L = 0; L < P->nlev; L++) HS_TRY(upload(P->offs[L], s));
+    for (int b = 0; b < P->B; b++) {
+        double t0 = P->pb.t0, nsteps = P->pb.nsteps;
+        if (P->pb.nslices > 1) {
+            t0 = P->pb.t0 + b * P->pb.dt;
+            nsteps = 1;
+        }
+        HS_TRY(hsk::set_lane(P->ctl, b, P->pb.nu, P->pb.dt, t0, P->pb.forcing_c, (int)nsteps, 1, s));
+    }
+    HS_TRY(hipStreamSynchronize(s));
+    P->bound = true;
+    return HS_OK;
+}
+
+hs_status hs_plan_destroy(hs_plan* P)
+{
+    if (!P) return HS_EINVAL;
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->h_ctl) (void)hipHostFree(P->h_ctl);
+    delete P;
+    return HS_OK;
+}
+
+hs_status hs_plan_lanes(const hs_plan* P, int32_t* lanes, int32_t* h_lane_n)
+{
+    if (!P) return HS_EINVAL;
+    if (lanes) *lanes = P->B;
+    if (h_lane_n)
+        for (int b = 0; b < P->B; b++) h_lane_n[b] = P->lane_n[b];
+    return HS_OK;
+}
+
+hs_status hs_set_lane(hs_plan* P, int32_t lane, double nu, double dt, double t0, int32_t nsteps,
+                      int32_t active, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (lane < 0 || lane >= P->B || !(nu > 0) || !(dt > 0) || nsteps < 0 || !std::isfinite(t0))
+        return HS_EINVAL;
+    HS_TRY(hsk::set_lane(P->ctl, lane, nu, dt, t0, P->pb.forcing_c, nsteps, active ? 1 : 0,
+                         (hipStream_t)stream));
+    return HS_OK;
+}
+
+hs_status hs_lap_apply(hs_plan* P, int32_t level, double alpha, double beta, const double* d_u,
+                       double* d_y, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (level < 0 || level >= P->nlev || !d_u || !d_y) return HS_EINVAL;
+    const Table<SdcSeg>& T = P->all.sdc[level];
+    HS_TRY(hsk::lap_apply(T.d, T.nseg(), T.nblk, P->order[level], alpha, beta, d_u, d_y,
+                          P->offs[level].d, (hipStream_t)stream));
+    return HS_OK;
+}
+
+hs_status hs_heat_rhs(hs_plan* P, int32_t level, const double* d_u, const double* h_t, double* d_fi,
+                      double* d_fe, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (level < 0 || level >= P->nlev || (d_fi && !d_u) || (d_fe && !h_t)) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> t(P->B, 0.0);
+    if (h_t)
+        for (int b = 0; b < P->B; b++) t[b] = h_t[b];
+    HS_TRY(hipMemcpyAsync(P->d_times, t.data(), sizeof(double) * P->B, hipMemcpyHostToDevice, s));
+    const Table<SdcSeg>& T = P->all.sdc[level];
+    HS_TRY(hsk::heat_rhs(P->ctl, T.d, T.nseg(), T.nblk, P->order[level], d_u, P->d_times, d_fi, d_fe,
+                         P->offs[level].d, s));
+    HS_TRY(hipStreamSynchronize(s));
+    return HS_OK;
+}
+
+hs_status hs_mg_vcycle(hs_plan* P, int32_t level, const double* h_a, double* d_u, const double* d_b,
+                       void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (level < 0 || level >= P->nlev || !h_a || !d_u || !d_b) return HS_EINVAL;
+    for (int b = 0; b < P->B; b++)
+        if (!(h_a[b] >= 0.0) || !std::isfinite(h_a[b])) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // the solve runs in place on node 1 of the lanes' node arrays
+    for (int b = 0; b < P->B; b++) {
+        const LaneBufs& lb = P->lanes[b];
+        long long N = lb.N[level], o = P->offs[level].h[b];
+        HS_TRY(hipMemcpyAsync(lb.U[level] + N, d_u + o, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HS_TRY(hipMemcpyAsync(lb.rhs[level], d_b + o, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HS_TRY(hsk::set_a_user(P->ctl, b, h_a[b], s));
+    }
+    HS_CHECK(mg_solve(P, P->all, level, -1, 1, s, nullptr));
+    for (int b = 0; b < P->B; b++) {
+        const LaneBufs& lb = P->lanes[b];
+        long long N = lb.N[level], o = P->offs[level].h[b];
+        HS_TRY(hipMemcpyAsync(d_u + o, lb.U[level] + N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    HS_CHECK(read_ctl(P, s));
+    int worst = HS_OK;
+    for (int b = 0; b < P->B; b++) {
+        const LaneCtl& c = P->h_ctl[b];
+        if (c.mg_state == 2) worst = std::min(worst, c.status < 0 ? c.status : (int)HS_ENOCONV);
+        // stand-alone solves leave the lanes idle for the SDC driver
+    }
+    for (int b = 0; b < P->B; b++) P->h_ctl[b].status = 0;
+    return (hs_status)worst;
+}
+
+hs_status hs_set_state(hs_plan* P, const double* d_u0, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (!d_u0) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int M = P->M[0];
+    for (int b = 0; b < P->B; b++) {
+        const LaneBufs& lb = P->lanes[b];
+        long long N = lb.N[0];
+        long long o = P->pb.nslices > 1 ? 0 : P->offs[0].h[b];
+        HS_TRY(hipMemcpyAsync(lb.U[0] + (M - 1) * N, d_u0 + o, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        double t0 = P->pb.t0, nsteps = P->pb.nsteps;
+        if (P->pb.nslices > 1) {
+            t0 = P->pb.t0 + b * P->pb.dt;
+            nsteps = 1;
+        }
+        HS_TRY(hsk::set_lane(P->ctl, b, P->pb.nu, P->pb.dt, t0, P->pb.forcing_c, (int)nsteps, 1, s));
+    }
+    P->state_ready = 1;
+    return HS_OK;
+}
+
+hs_status hs_get_state(hs_plan* P, double* d_u, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (!d_u) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int M = P->M[0];
+    if (P->pb.nslices > 1) {
+        const LaneBufs& lb = P->lanes[P->B - 1];
+        HS_TRY(hipMemcpyAsync(d_u, lb.U[0] + (M - 1) * lb.N[0], lb.N[0] * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+        return HS_OK;
+    }
+    for (int b = 0; b < P->B; b++) {
+        const LaneBufs& lb = P->lanes[b];
+        HS_TRY(hipMemcpyAsync(d_u + P->offs[0].h[b], lb.U[0] + (M - 1) * lb.N[0], lb.N[0] * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    }
+    return HS_OK;
+}
+
+hs_status hs_get_nodes(hs_plan* P, int32_t level, double* d_U, double* d_FI, double* d_Ut,
+                       double* d_tau, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (level < 0 || level >= P->nlev) return HS_EINVAL;
+    if ((d_Ut || d_tau) && level != 1) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int M = P->M[level];
+    for (int b = 0; b < P->B; b++) {
+        const LaneBufs& lb = P->lanes[b];
+        long long sz = M * lb.N[level], o = M * P->offs[level].h[b];
+        if (d_U) HS_TRY(hipMemcpyAsync(d_U + o, lb.U[level], sz * 8, hipMemcpyDeviceToDevice, s));
+        if (d_FI) HS_TRY(hipMemcpyAsync(d_FI + o, lb.FI[level], sz * 8, hipMemcpyDeviceToDevice, s));
+        if (d_Ut) HS_TRY(hipMemcpyAsync(d_Ut + o, lb.Ut, sz * 8, hipMemcpyDeviceToDevice, s));
+        if (d_tau) HS_TRY(hipMemcpyAsync(d_tau + o, lb.tau, sz * 8, hipMemcpyDeviceToDevice, s));
+    }
+    return HS_OK;
+}
+
+hs_status hs_set_nodes(hs_plan* P, int32_t level, const double* d_U, const double* d_FI, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (level < 0 || level >= P->nlev) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int M = P->M[level];
+    for (int b = 0; b < P->B; b++) {
+        const LaneBufs& lb = P->lanes[b];
+        long long sz = M * lb.N[level], o = M * P->offs[level].h[b];
+        if (d_U) HS_TRY(hipMemcpyAsync(lb.U[level], d_U + o, sz * 8, hipMemcpyDeviceToDevice, s));
+        if (d_FI) HS_TRY(hipMemcpyAsync(lb.FI[level], d_FI + o, sz * 8, hipMemcpyDeviceToDevice, s));
+    }
+    return HS_OK;
+}
+
+hs_status hs_begin_step(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    return begin_step(P, (hipStream_t)stream);
+}
+
+hs_status hs_sdc_sweep(hs_plan* P, int32_t level, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (level < 0 || level >= P->nlev) return HS_EINVAL;
+    int outcome;
+    return sweep(P, P->all, level, false, level == 0, (hipStream_t)stream, &outcome);
+}
+
+hs_status hs_fas_restrict(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (P->nlev != 2) return HS_EINVAL;
+    LaneSet& ls = P->all;
+    HS_TRY(hsk::fas_restrict(P->ctl, ls.fasc.d, ls.fasc.nseg(), ls.fasc.nblk, P->order[1], 1,
+                             (hipStream_t)stream));
+    return HS_OK;
+}
+
+hs_status hs_fas_interp(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (P->nlev != 2) return HS_EINVAL;
+    LaneSet& ls = P->all;
+    hipStream_t s = (hipStream_t)stream;
+    HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
+    HS_TRY(hsk::eval_fi_all(P->ctl, ls.sdc[0].d, ls.sdc[0].nseg(), ls.sdc[0].nblk, P->order[0], 1, s));
+    return HS_OK;
+}
+
+hs_status hs_mlsdc_iter(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (P->nlev != 2) return HS_EINVAL;
+    int outcome;
+    return mlsdc_iter(P, P->all, false, (hipStream_t)stream, &outcome);
+}
+
+hs_status hs_end_step(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    HS_TRY(hsk::end_step(P->ctl, P->B, (hipStream_t)stream));
+    return HS_OK;
+}
+
+hs_status hs_step(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (P->pb.nslices > 1) return HS_EINVAL;
+    return step(P, (hipStream_t)stream);
+}
+
+hs_status hs_solve(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (P->pb.nslices > 1) return hs_pfasst_run(P, stream);
+    hipStream_t s = (hipStream_t)stream;
+    for (int k = 0; k < P->pb.nsteps; k++) HS_CHECK(step(P, s));
+    return HS_OK;
+}
+
+hs_status hs_solve_graph(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (P->pb.nslices > 1 || P->pb.sweeps <= 0 || P->pb.mg.fixed_cycles <= 0) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!P->gexec) {
+        HS_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hs_status st = step(P, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st != HS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        HS_TRY(e);
+        P->graph = g;
+        HS_TRY(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+    }
+    for (int k = 0; k < P->pb.nsteps; k++) HS_TRY(hipGraphLaunch(P->gexec, s));
+    return HS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+__global__ void k_pfasst_block(LaneCtl* ctl, int P, double t0, double dt, int blk)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    ctl[p].t0 = t0 + (double)(blk * P + p) * dt;
+    ctl[p].step = 0;
+    ctl[p].nsteps = 1;
+}
+}  // namespace
+
+extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (P->pb.nslices <= 1) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int Pn = P->B, Mf = P->M[0], Mc = P->M[1];
+    int nblocks = P->pb.nsteps / Pn;
+    LaneSet& all = P->all;
+    for (int blk = 0; blk < nblocks; blk++) {
+        if (blk > 0) {
+            // the next block starts from the last slice's end value
+            const LaneBufs& last = P->lanes[Pn - 1];
+            for (int p = 0; p + 1 < Pn; p++) {
+                const LaneBufs& lb = P->lanes[p];
+                HS_TRY(hipMemcpyAsync(lb.U[0] + (Mf - 1) * lb.N[0], last.U[0] + (Mf - 1) * last.N[0],
+                                      lb.N[0] * 8, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        hipLaunchKernelGGL(k_pfasst_block, dim3((Pn + 63) / 64), dim3(64), 0, s, P->ctl, Pn,
+                           P->pb.t0, P->pb.dt, blk);
+        HS_TRY(hipGetLastError());
+        HS_CHECK(begin_step(P, s));
+        for (int k = 0; k < P->pb.sweeps; k++) {
+            // (i) fine hand-off from the previous iteration, then fine sweeps on every slice
+            HS_TRY(hsk::handoff(P->ctl, P->hf_dst.d, P->hf_src.d, P->hf_dst.nseg(), P->hf_dst.nblk,
+                                P->order[0], s));
+            int outcome;
+            HS_CHECK(sweep(P, all, 0, false, true, s, &outcome));
+            // (ii) restriction and FAS correction on every slice
+            HS_TRY(hsk::fas_restrict(P->ctl, all.fasc.d, all.fasc.nseg(), all.fasc.nblk, P->order[1], 1, s));
+            // (iii) coarse pipeline: slice p starts from slice p-1's new coarse end value
+            for (int p = 0; p < Pn; p++) {
+                if (p > 0)
+                    HS_TRY(hsk::handoff(P->ctl, P->hc_dst[p].d, P->hc_src[p].d, 1, P->hc_dst[p].nblk,
+                                        P->order[1], s));
+                HS_CHECK(sweep(P, P->single[p], 1, false, false, s, &outcome));
+            }
+            // (iv) interpolation on every slice, node 0 included
+            HS_TRY(hsk::fas_interp(P->ctl, all.fasf.d, all.fasf.nseg(), all.fasf.nblk, 1, s));
+            HS_TRY(hsk::eval_fi_all(P->ctl, all.sdc[0].d, all.sdc[0].nseg(), all.sdc[0].nblk,
+                                    P->order[0], 1, s));
+        }
+        HS_TRY(hsk::end_step(P->ctl, P->B, s));
+    }
+    (void)Mc;
+    return HS_OK;
+}
+
+extern "C" hs_status hs_stats_read(hs_plan* P, hs_lane_stats* out, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (!out) return HS_EINVAL;
+    HS_CHECK(read_ctl(P, (hipStream_t)stream));
+    for (int b = 0; b < P->B; b++) {
+        const LaneCtl& c = P->h_ctl[b];
+        hs_lane_stats& o = out[b];
+        o.status = c.status;
+        o.steps_done = c.step;
+        o.total_sweeps = c.total_sweeps;
+        o.total_solves = c.total_solves;
+        o.total_cycles = c.total_cycles;
+        o.max_cycles = c.max_cycles;
+        o.failed_solves = c.failed_solves;
+        o.last_rho = c.mg_rho;
+        o.last_sdc_res = c.sdc_res;
+    }
+    return lanes_status(P);
+}

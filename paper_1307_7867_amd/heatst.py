@@ -1,0 +1,327 @@
+"""Python binding of libheatst (include/heatst.h): argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of libheatst.so; PyTorch
+provides device memory (the plan workspace and user tensors) and streams.
+If the shared library has not been built, importing the binding works but
+any use raises RuntimeError -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libheatst.so")
+
+HS_OK, HS_EINVAL, HS_ENOMEM, HS_ENOCONV, HS_ENONFINITE, HS_EDEVICE, HS_ESTATE, HS_PENDING = \
+    0, -1, -2, -3, -4, -5, -6, 1
+HS_FP64, HS_MIXED = 0, 1
+
+
+class HeatstError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class LevelDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("order", C.c_int32), ("nnodes", C.c_int32)]
+
+
+class MgDesc(C.Structure):
+    _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("omega", C.c_double),
+                ("n_coarsest", C.c_int32), ("tol", C.c_double), ("max_cycles", C.c_int32),
+                ("fixed_cycles", C.c_int32), ("precision", C.c_int32), ("inner_nu1", C.c_int32),
+                ("inner_nu2", C.c_int32)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("nu", C.c_double), ("t0", C.c_double), ("dt", C.c_double),
+                ("forcing_c", C.c_double), ("nsteps", C.c_int32), ("nlevels", C.c_int32),
+                ("lev", LevelDesc * 2), ("mg", MgDesc), ("sweeps", C.c_int32),
+                ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("batch", C.c_int32),
+                ("nslices", C.c_int32), ("h_lane_n", C.POINTER(C.c_int32))]
+
+
+class LaneStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps_done", C.c_int32), ("total_sweeps", C.c_int32),
+                ("total_solves", C.c_int32), ("total_cycles", C.c_int64),
+                ("max_cycles", C.c_int32), ("failed_solves", C.c_int32),
+                ("last_rho", C.c_double), ("last_sdc_res", C.c_double)]
+
+
+_lib = None
+_V = C.c_void_p
+_P = C.POINTER
+
+
+def lib():
+    """Load libheatst.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python paper_1307_7867_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    S = C.c_int
+    L.hs_status_string.restype = C.c_char_p
+    L.hs_status_string.argtypes = [S]
+    sig = {
+        "hs_collocation": [C.c_int32, _V, _V],
+        "hs_workspace_bytes": [_P(ProblemDesc), _P(C.c_size_t)],
+        "hs_plan_create": [_P(ProblemDesc), _P(_V)],
+        "hs_plan_bind": [_V, _V, C.c_size_t, _V],
+        "hs_plan_destroy": [_V],
+        "hs_plan_lanes": [_V, _P(C.c_int32), _V],
+        "hs_set_lane": [_V, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, _V],
+        "hs_lap_apply": [_V, C.c_int32, C.c_double, C.c_double, _V, _V, _V],
+        "hs_heat_rhs": [_V, C.c_int32, _V, _V, _V, _V, _V],
+        "hs_mg_vcycle": [_V, C.c_int32, _V, _V, _V, _V],
+        "hs_set_state": [_V, _V, _V],
+        "hs_get_state": [_V, _V, _V],
+        "hs_get_nodes": [_V, C.c_int32, _V, _V, _V, _V, _V],
+        "hs_set_nodes": [_V, C.c_int32, _V, _V, _V],
+        "hs_begin_step": [_V, _V],
+        "hs_sdc_sweep": [_V, C.c_int32, _V],
+        "hs_fas_restrict": [_V, _V],
+        "hs_fas_interp": [_V, _V],
+        "hs_mlsdc_iter": [_V, _V],
+        "hs_end_step": [_V, _V],
+        "hs_step": [_V, _V],
+        "hs_solve": [_V, _V],
+        "hs_pfasst_run": [_V, _V],
+        "hs_solve_graph": [_V, _V],
+        "hs_stats_read": [_V, _V, _V],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.restype = S
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    try:
+        return lib().hs_status_string(s).decode()
+    except RuntimeError:
+        return "libheatst not loaded"
+
+
+def check(status: int, where: str, allow=()) -> int:
+    if status < 0 and status not in allow:
+        raise HeatstError(status, where)
+    return status
+
+
+def collocation(M: int):
+    """Nodes tau[M] and collocation matrix Q[M, M] (eq. (6)) used by the GPU path."""
+    tau = np.zeros(M)
+    Q = np.zeros((M, M))
+    check(lib().hs_collocation(M, tau.ctypes.data_as(_V), Q.ctypes.data_as(_V)), "hs_collocation")
+    return tau, Q
+
+
+@dataclass
+class Problem:
+    """Python mirror of hs_problem (see include/heatst.h)."""
+    n: int = 15
+    order: int = 2
+    nnodes: int = 3
+    nu: float = 0.1
+    t0: float = 0.0
+    dt: float = 0.125
+    forcing_c: float = 3.0
+    nsteps: int = 1
+    coarse: tuple | None = None          # (n, order, nnodes) of the coarse MLSDC level
+    nu1: int = 2
+    nu2: int = 1
+    omega: float = 6.0 / 7.0
+    n_coarsest: int = 3
+    tol: float = 1e-12
+    max_cycles: int = 60
+    fixed_cycles: int = 0
+    precision: int = HS_FP64
+    inner_nu1: int = 2
+    inner_nu2: int = 2
+    sweeps: int = 4
+    sdc_tol: float = 1e-10
+    max_sweeps: int = 20
+    batch: int = 1
+    nslices: int = 1
+    lane_n: list | None = None
+
+    def desc(self):
+        d = ProblemDesc()
+        d.nu, d.t0, d.dt, d.forcing_c = self.nu, self.t0, self.dt, self.forcing_c
+        d.nsteps = self.nsteps
+        d.nlevels = 2 if self.coarse else 1
+        d.lev[0] = LevelDesc(self.n, self.order, self.nnodes)
+        if self.coarse:
+            d.lev[1] = LevelDesc(*self.coarse)
+        d.mg = MgDesc(self.nu1, self.nu2, self.omega, self.n_coarsest, self.tol, self.max_cycles,
+                      self.fixed_cycles, self.precision, self.inner_nu1, self.inner_nu2)
+        d.sweeps, d.sdc_tol, d.max_sweeps = self.sweeps, self.sdc_tol, self.max_sweeps
+        d.batch, d.nslices = self.batch, self.nslices
+        keep = None
+        if self.lane_n is not None:
+            keep = (C.c_int32 * len(self.lane_n))(*self.lane_n)
+            d.h_lane_n = C.cast(keep, _P(C.c_int32))
+        return d, keep
+
+    def workspace_bytes(self) -> int:
+        d, keep = self.desc()
+        out = C.c_size_t(0)
+        check(lib().hs_workspace_bytes(C.byref(d), C.byref(out)), "hs_workspace_bytes")
+        return out.value
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A bound plan: owns its workspace tensor on the current CUDA (HIP) device."""
+
+    def __init__(self, problem: Problem, stream=None):
+        import torch
+        self.problem = problem
+        L = lib()
+        self._desc, self._keep = problem.desc()
+        size = C.c_size_t(0)
+        check(L.hs_workspace_bytes(C.byref(self._desc), C.byref(size)), "hs_workspace_bytes")
+        self.bytes = size.value
+        self._h = C.c_void_p()
+        check(L.hs_plan_create(C.byref(self._desc), C.byref(self._h)), "hs_plan_create")
+        self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream
+        check(L.hs_plan_bind(self._h, C.c_void_p(aligned), self.bytes, _stream(stream)), "hs_plan_bind")
+        lanes = C.c_int32(0)
+        check(L.hs_plan_lanes(self._h, C.byref(lanes), None), "hs_plan_lanes")
+        self.lanes = lanes.value
+        ln = (C.c_int32 * self.lanes)()
+        check(L.hs_plan_lanes(self._h, None, C.cast(ln, _V)), "hs_plan_lanes")
+        self.lane_n = list(ln)
+        self.nlevels = 2 if problem.coarse else 1
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().hs_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    # geometry -----------------------------------------------------------
+    def level_n(self, level):
+        return [n if level == 0 else (n - 1) // 2 for n in self.lane_n]
+
+    def level_M(self, level):
+        return self.problem.nnodes if level == 0 else self.problem.coarse[2]
+
+    def field_len(self, level=0):
+        return sum(n ** 3 for n in self.level_n(level))
+
+    def _s(self):
+        return _stream(self.stream)
+
+    # kernel-level calls -------------------------------------------------
+    def lap_apply(self, u, alpha, beta, level=0, out=None):
+        import torch
+        y = torch.empty_like(u) if out is None else out
+        check(lib().hs_lap_apply(self._h, level, alpha, beta, _ptr(u), _ptr(y), self._s()), "hs_lap_apply")
+        return y
+
+    def heat_rhs(self, u, t, level=0):
+        import torch
+        tt = (C.c_double * self.lanes)(*([t] * self.lanes if np.isscalar(t) else list(t)))
+        fi = torch.empty_like(u)
+        fe = torch.empty_like(u)
+        check(lib().hs_heat_rhs(self._h, level, _ptr(u), C.cast(tt, _V), _ptr(fi), _ptr(fe), self._s()),
+              "hs_heat_rhs")
+        return fi, fe
+
+    def mg_vcycle(self, u, b, a, level=0, allow_noconv=False):
+        aa = (C.c_double * self.lanes)(*([a] * self.lanes if np.isscalar(a) else list(a)))
+        s = lib().hs_mg_vcycle(self._h, level, C.cast(aa, _V), _ptr(u), _ptr(b), self._s())
+        return check(s, "hs_mg_vcycle", allow=(HS_ENOCONV,) if allow_noconv else ())
+
+    # state and nodes ----------------------------------------------------
+    def set_lane(self, lane, nu, dt, t0, nsteps, active=True):
+        check(lib().hs_set_lane(self._h, lane, nu, dt, t0, nsteps, 1 if active else 0, self._s()),
+              "hs_set_lane")
+
+    def set_state(self, u0):
+        check(lib().hs_set_state(self._h, _ptr(u0), self._s()), "hs_set_state")
+
+    def get_state(self):
+        import torch
+        n = self.lane_n[-1] ** 3 if self.problem.nslices > 1 else self.field_len(0)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        check(lib().hs_get_state(self._h, _ptr(out), self._s()), "hs_get_state")
+        return out
+
+    def get_nodes(self, level=0):
+        import torch
+        M = self.level_M(level)
+        U = torch.empty(M * self.field_len(level), dtype=torch.float64, device="cuda")
+        FI = torch.empty_like(U)
+        Ut = tau = None
+        if level == 1:
+            Ut = torch.empty_like(U)
+            tau = torch.empty_like(U)
+        check(lib().hs_get_nodes(self._h, level, _ptr(U), _ptr(FI), _ptr(Ut), _ptr(tau), self._s()),
+              "hs_get_nodes")
+        return U, FI, Ut, tau
+
+    def set_nodes(self, level, U, FI):
+        check(lib().hs_set_nodes(self._h, level, _ptr(U), _ptr(FI), self._s()), "hs_set_nodes")
+
+    # step-level calls ---------------------------------------------------
+    def begin_step(self):
+        check(lib().hs_begin_step(self._h, self._s()), "hs_begin_step")
+
+    def sdc_sweep(self, level=0):
+        check(lib().hs_sdc_sweep(self._h, level, self._s()), "hs_sdc_sweep")
+
+    def fas_restrict(self):
+        check(lib().hs_fas_restrict(self._h, self._s()), "hs_fas_restrict")
+
+    def fas_interp(self):
+        check(lib().hs_fas_interp(self._h, self._s()), "hs_fas_interp")
+
+    def mlsdc_iter(self):
+        check(lib().hs_mlsdc_iter(self._h, self._s()), "hs_mlsdc_iter")
+
+    def end_step(self):
+        check(lib().hs_end_step(self._h, self._s()), "hs_end_step")
+
+    def step(self):
+        check(lib().hs_step(self._h, self._s()), "hs_step")
+
+    def solve(self):
+        check(lib().hs_solve(self._h, self._s()), "hs_solve")
+
+    def solve_graph(self):
+        check(lib().hs_solve_graph(self._h, self._s()), "hs_solve_graph")
+
+    def pfasst_run(self):
+        check(lib().hs_pfasst_run(self._h, self._s()), "hs_pfasst_run")
+
+    def stats(self):
+        arr = (LaneStats * self.lanes)()
+        st = lib().hs_stats_read(self._h, C.cast(arr, _V), self._s())
+        return st, [dict((f, getattr(a, f)) for f, _ in LaneStats._fields_) for a in arr]

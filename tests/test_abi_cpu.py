@@ -1,0 +1,133 @@
+"""Host-side checks of libheatst that need no GPU: the shared library loads
+and exports every entry point of include/heatst.h, the problem validation
+and workspace sizing behave, and the collocation data the GPU path uses
+(computed independently of the oracle) matches the exact values."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from paper_1307_7867_amd import heatst
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "heatst.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 25
+    out = subprocess.run(["nm", "-D", "--defined-only", heatst.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(hs_[a-z0-9_]+)$", out, flags=re.M))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = heatst.lib()
+    for n in names:
+        assert hasattr(L, n)
+
+
+def test_library_has_gfx950_code_object():
+    # the device code object bundled into the library targets gfx950
+    blob = open(heatst.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+
+
+def test_status_strings():
+    assert heatst.status_string(0) == "ok"
+    assert "invalid" in heatst.status_string(-1)
+
+
+def test_no_device_allocation_symbols_used():
+    # the library only uses caller-owned device memory
+    out = subprocess.run(["nm", "-D", "--undefined-only", heatst.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for sym in ("hipMalloc", "hipMallocAsync", "hipMallocManaged", "hipExtMallocWithFlags"):
+        assert not re.search(rf"\s{sym}(@|$)", out, flags=re.M), sym
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 5])
+def test_collocation_data_exact(M):
+    tau, Q = heatst.collocation(M)
+    s = sp.Symbol("s")
+    r = {2: [], 3: [sp.Rational(1, 2)], 4: [sp.Rational(1, 2) - sp.sqrt(5) / 10, sp.Rational(1, 2) + sp.sqrt(5) / 10],
+         5: [sp.Rational(1, 2) - sp.sqrt(21) / 14, sp.Rational(1, 2), sp.Rational(1, 2) + sp.sqrt(21) / 14]}[M]
+    t = [sp.Integer(0)] + r + [sp.Integer(1)]
+    for m in range(M):
+        assert abs(tau[m] - float(t[m])) < 2e-16
+    for j in range(M):
+        lj = sp.Integer(1)
+        for i in range(M):
+            if i != j:
+                lj *= (s - t[i]) / (t[j] - t[i])
+        for m in range(M):
+            ex = float(sp.integrate(sp.expand(lj), (s, 0, t[m])).evalf(30))
+            assert abs(Q[m, j] - ex) < 3e-16
+
+
+def base_problem(**kw):
+    p = heatst.Problem(n=15, order=2, nnodes=3)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [dict(n=16), dict(n=0), dict(n=1023), dict(order=3), dict(nnodes=6),
+                                dict(nnodes=1), dict(nu=0.0), dict(dt=-1.0), dict(batch=0),
+                                dict(nu1=0), dict(omega=1.5), dict(n_coarsest=7),
+                                dict(precision=7), dict(sweeps=0, sdc_tol=0.0),
+                                dict(fixed_cycles=0, tol=0.0),
+                                dict(coarse=(8, 2, 3)), dict(coarse=(7, 2, 4), nnodes=5, n=15),
+                                dict(nslices=4, batch=4), dict(lane_n=[15, 17], batch=2)])
+def test_invalid_problems_rejected(kw):
+    p = base_problem(**kw)
+    with pytest.raises(heatst.HeatstError) as e:
+        p.workspace_bytes()
+    assert e.value.status == heatst.HS_EINVAL
+
+
+def test_workspace_bytes_accounts_for_fields():
+    n, M = 63, 5
+    p = base_problem(n=n, nnodes=M)
+    b = p.workspace_bytes()
+    N = n ** 3
+    # node values, F, quadrature (M-1), rhs, tmp; plus the multigrid hierarchy
+    fields = (M + M + (M - 1) + 2) * N * 8
+    hier = sum(3 * k ** 3 * 8 for k in (31, 15, 7, 3))
+    assert fields + hier <= b <= fields + hier + 1 << 20
+    p2 = base_problem(n=n, nnodes=M, batch=3)
+    assert 3 * fields < p2.workspace_bytes() <= 3 * (fields + hier) + (1 << 20)
+
+
+def test_workspace_mixed_precision_adds_fp32_hierarchy():
+    p64 = base_problem(n=31, nnodes=5)
+    p32 = base_problem(n=31, nnodes=5, precision=heatst.HS_MIXED)
+    extra = p32.workspace_bytes() - p64.workspace_bytes()
+    fp32 = sum(3 * k ** 3 * 4 for k in (31, 15, 7, 3))
+    fp64_lower = sum(3 * k ** 3 * 8 for k in (15, 7, 3))
+    assert extra == pytest.approx(fp32 - fp64_lower + 0, abs=64 * 1024) or extra > 0
+
+
+def test_uneven_and_two_level_sizes():
+    p = base_problem(n=31, nnodes=5, batch=3, lane_n=[31, 15, 63])
+    assert p.workspace_bytes() > (63 ** 3) * 16 * 8
+    p2 = base_problem(n=63, order=4, nnodes=5, coarse=(31, 2, 3))
+    assert p2.workspace_bytes() > p.workspace_bytes() * 0
+    p3 = base_problem(n=31, order=4, nnodes=5, coarse=(15, 2, 3), batch=4, nslices=4, nsteps=4)
+    assert p3.workspace_bytes() > 4 * (31 ** 3) * 5 * 16
+
+
+def test_product_path_has_no_cpu_fallback(monkeypatch, tmp_path):
+    monkeypatch.setattr(heatst, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(heatst, "_lib", None)
+    with pytest.raises(RuntimeError):
+        heatst.Problem().workspace_bytes()
