@@ -172,12 +172,26 @@ hs_status hs_heat_rhs(hs_plan* plan, int32_t level, const double* d_u, const dou
 hs_status hs_mg_vcycle(hs_plan* plan, int32_t level, const double* h_a, double* d_u,
                        const double* d_b, void* stream);
 
+/* nsweeps weighted-Jacobi sweeps (the multigrid smoother, section 1.2)
+ * u <- u + omega D^{-1} (b - (I - a_l L_h) u) on the finest grid of SDC
+ * level `level`, in place on the lane-major d_u, with right-hand side d_b,
+ * per-lane a from the host array h_a and d_tmp (same size as d_u) as the
+ * ping-pong partner, which is left holding garbage.  Every sweep is one
+ * launch of the same kernel the solver uses on its finest grids. */
+hs_status hs_smooth(hs_plan* plan, int32_t level, const double* h_a, double* d_u,
+                    const double* d_b, double* d_tmp, int32_t nsweeps, void* stream);
+
 /* State (the value at the start of the next step) of every lane, lane-major
  * fine-level fields.  hs_set_state also resets the lanes' step counters.
  * For PFASST plans d_u0 holds one field that every slice starts from and
  * hs_get_state returns the end value of the last slice. */
 hs_status hs_set_state(hs_plan* plan, const double* d_u0, void* stream);
 hs_status hs_get_state(hs_plan* plan, double* d_u, void* stream);
+
+/* One lane's state (fine-level field of n_lane^3 values): set before the
+ * lane's first step (with hs_set_lane), read after its last. */
+hs_status hs_set_lane_state(hs_plan* plan, int32_t lane, const double* d_u0, void* stream);
+hs_status hs_get_lane_state(hs_plan* plan, int32_t lane, double* d_u, void* stream);
 
 /* Node data of SDC level `level`: d_U and d_FI are lane-major [lane][M][N]
  * (FI = nu L_h U); d_Ut / d_tau (coarse level of an MLSDC plan) hold the
@@ -215,6 +229,62 @@ hs_status hs_solve_graph(hs_plan* plan, void* stream);
 
 /* Per-lane statistics; synchronises the stream.  h_out has `batch` entries. */
 hs_status hs_stats_read(hs_plan* plan, hs_lane_stats* h_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop for many independent heat solves.
+ *
+ * Requests (grid n, nu, dt, t0, steps, initial field) are grouped by grid
+ * size into classes.  Every class is one batched plan with `slots` lanes,
+ * laid out in the caller's device pool when the server is created (the
+ * classes together must fit both the pool and hbm_budget, else
+ * HS_ENOMEM); a lane holds one request's hierarchy from admission to
+ * completion.  Each class is driven by its own host thread on its own HIP
+ * stream (default priority): before every time step it admits queued
+ * requests into free lanes, then advances all of its active lanes by one
+ * step in one batched launch sequence, then retires the lanes that are
+ * done (copying their final field to the request's output).  New requests
+ * therefore join at the next step boundary and different classes overlap
+ * on the device.  Every lane takes its own stopping decisions, so a
+ * request's result does not depend on what else is in the batch.
+ * ---------------------------------------------------------------------- */
+#define HS_MAX_CLASSES 8
+
+typedef struct {
+    int32_t order, nnodes;        /* Laplacian order and Lobatto nodes for every request */
+    hs_mg_desc mg;
+    int32_t sweeps;               /* 0 = sweep until sdc_tol */
+    double sdc_tol;
+    int32_t max_sweeps;
+    double forcing_c;
+    int32_t nclasses;
+    int32_t class_n[HS_MAX_CLASSES];
+    int32_t class_slots[HS_MAX_CLASSES];
+} hs_server_desc;
+
+typedef struct {
+    int32_t state;                /* 0 queued, 1 running, 2 done */
+    int32_t status;               /* hs_status of the finished request */
+    int32_t cls, lane;
+    double t_submit, t_admit, t_done;   /* seconds since the server was created */
+    hs_lane_stats stats;
+} hs_request_info;
+
+typedef struct hs_server hs_server;
+
+/* Device bytes the classes of *d need (pool size to pass to hs_server_create). */
+hs_status hs_server_pool_bytes(const hs_server_desc* d, size_t* bytes);
+hs_status hs_server_create(const hs_server_desc* d, void* d_pool, size_t pool_bytes,
+                           size_t hbm_budget, hs_server** server);
+/* Queue a request.  d_u0 (n^3 values) must stay valid until the request is
+ * admitted; d_out (n^3 values) receives the final field.  HS_EINVAL if no
+ * class has grid n. */
+hs_status hs_server_submit(hs_server* s, int32_t n, double nu, double dt, double t0, int32_t nsteps,
+                           const double* d_u0, double* d_out, uint64_t* ticket);
+/* HS_OK when the request is done (info filled), HS_PENDING otherwise. */
+hs_status hs_server_poll(hs_server* s, uint64_t ticket, hs_request_info* info);
+/* Block until every submitted request is done. */
+hs_status hs_server_drain(hs_server* s);
+hs_status hs_server_destroy(hs_server* s);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libheatst.so")
-SOURCES = ["hs_kernels.hip", "hs_plan.hip"]
+SOURCES = ["hs_kernels.hip", "hs_plan.hip", "hs_server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -11,7 +11,8 @@
 #define HS_BLOCK 256       // threads per block of the grid kernels
 #define HS_TX 64           // block tile along x (one wavefront per row)
 #define HS_TY 4            // block tile along y
-#define HS_TAIL_THREADS 512
+#define HS_TAIL_THREADS 1024
+#define HS_ZB 8            // z planes per block of the z-marching stencil kernels
 
 // Per-lane state in device memory.  A lane is one independent problem
 // instance or one PFASST time slice.
@@ -51,7 +52,7 @@ struct GridSeg {
     int32_t n;              // interior points per axis
     int32_t nc;             // next coarser grid (0 if none)
     int32_t coarse;         // 1: correction grid whose first sweep starts from zero
-    int32_t pad;
+    int32_t zb;             // z planes per block of the launch using this table
     long long node_stride;  // elements per node for the finest grid, else 0
     void* u;                // iterate
     void* t;                // ping-pong partner of u
@@ -153,30 +154,42 @@ struct MgArgs {
     int32_t gate;      // 1 = skip lanes whose mg_state != 0
 };
 
-int grid_blocks(int n);   // blocks covering an n^3 grid
+int grid_blocks(int n, int zb = 1);   // blocks covering an n^3 grid, zb planes per block
+int choose_zb(int n);                 // z planes per block of the plane-marching kernels
+size_t tail_lds_bytes(int n0, int elem);  // LDS of the tail kernel whose top grid is n0
 
 hipError_t set_constants(const LibConst& lc);
 
+// Weighted-Jacobi sweep (mode 0) or residual r = b - A x written to the free
+// buffer (mode 1) over a z-marching table.  norm: also write per-block
+// maxima of |b - A x| (and |b| when cycle == 0) to partials (FP64 only).
 template <typename T>
-hipError_t jacobi(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                  int first_sweep, int src_is_t, hipStream_t s);
+hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
+                 int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
+                 double* partials, hipStream_t s);
+// full weighting of the residual held in the buffer selected by r_is_t
 template <typename T>
-hipError_t resid_restrict(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order,
-                          MgArgs a, int src_is_t, hipStream_t s);
+hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,
+                       hipStream_t s);
 template <typename T>
 hipError_t prolong(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int src_is_t,
                    int dst_is_t, hipStream_t s);
 template <typename T>
 hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a, int nu1, int nu2,
-                hipStream_t s);
+                size_t lds_bytes, hipStream_t s);
 
-// max-norm residual test of an FP64 solve before cycle `cycle`
+// stopping test of a solve from per-block maxima (one block per lane):
+// rho = max|r| / max|b| (|b| taken at cycle 0); stop when rho <= tol, fail
+// when cycle == max_cycles or rho is not finite
+hipError_t mg_decide(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, const double* partials,
+                     int cycle, double tol, int max_cycles, hipStream_t s);
+// max-norm residual of an FP64 solve into partials (tables without a fused sweep)
 hipError_t mg_norm(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                   int src_is_t, int cycle, double tol, int max_cycles, hipStream_t s);
+                   int cycle, double* partials, hipStream_t s);
 // iterative refinement: r = b - A u in FP64, r32 = (float) r into the FP32
-// hierarchy, plus the stopping test
+// hierarchy, per-block maxima into partials
 hipError_t ir_resid(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32, int nseg, int nblk,
-                    int order, MgArgs a, int iter, double tol, int max_iter, hipStream_t s);
+                    int order, MgArgs a, int iter, double* partials, hipStream_t s);
 hipError_t ir_update(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32, int nseg,
                      int nblk, MgArgs a, hipStream_t s);
 
@@ -184,15 +197,18 @@ hipError_t ir_update(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32,
 hipError_t spread(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int src_node,
                   hipStream_t s);
 hipError_t sweep_prep(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int with_resid,
-                      double sdc_tol, int max_sweeps, int gate, hipStream_t s);
+                      int gate, double* partials, hipStream_t s);
+// SDC stopping test from the per-block maxima of sweep_prep / sdc_resid
+hipError_t sdc_decide(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, const double* partials,
+                      double sdc_tol, int max_sweeps, hipStream_t s);
 hipError_t make_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int m, int gate,
                     hipStream_t s);
 hipError_t f_update(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int node,
                     int next_rhs, int gate, hipStream_t s);
 hipError_t eval_fi_all(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int gate,
                        hipStream_t s);
-hipError_t sdc_resid(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, double sdc_tol,
-                     int max_sweeps, hipStream_t s);
+hipError_t sdc_resid(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, double* partials,
+                     hipStream_t s);
 hipError_t handoff(LaneCtl* ctl, const SdcSeg* dst, const SdcSeg* src, int nseg, int nblk,
                    int order, hipStream_t s);
 hipError_t fas_restrict(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int corder, int gate,

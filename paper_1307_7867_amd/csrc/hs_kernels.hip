@@ -3,12 +3,18 @@
 // Every kernel of the multigrid and SDC hot path works on a table of
 // segments: one segment is one grid of one lane (an independent problem or
 // a PFASST time slice).  Blocks of 256 threads tile a grid as 64 x 4 points
-// in x-y (one wavefront per x row, coalesced along x) and one z plane per
-// block; a launch covers all segments of its table, so lanes of equal or of
-// different sizes share one launch.  The hardware hands consecutive blocks
-// to the 8 XCDs in turn; the block index is remapped so that every XCD works
-// on one contiguous range of planes and reuses the z-neighbour planes from
-// its own L2.
+// in x-y (one wavefront per x row, coalesced along x).  The stencil kernels
+// march along z through a chunk of planes per block and keep the z
+// neighbours of each column in registers; other kernels take one plane per
+// block.  A launch covers all segments of its table, so lanes of equal or
+// of different sizes share one launch.  The hardware hands consecutive
+// blocks to the 8 XCDs in turn; the block index is remapped so that every
+// XCD works on one contiguous range of planes and reuses neighbour planes
+// from its own L2.
+//
+// Reductions (residual norms) write one maximum per block; a small kernel
+// with one block per lane combines them and takes the stopping decision,
+// so no two blocks ever contend for one address.
 //
 // The discrete operators follow the paper's section 1 (method of lines,
 // 2nd- and 4th-order Laplacians, implicit-Euler substeps of the IMEX SDC
@@ -47,7 +53,7 @@ __device__ __forceinline__ int find_seg(const S* segs, int nseg, int lb)
 __host__ __device__ __forceinline__ int tiles_x(int n) { return (n + HS_TX - 1) / HS_TX; }
 __host__ __device__ __forceinline__ int tiles_y(int n) { return (n + HS_TY - 1) / HS_TY; }
 
-// position of this thread inside its segment's grid
+// position of this thread inside its segment's grid (one plane per block)
 struct Pos {
     int i, j, k;
     bool in;
@@ -68,9 +74,32 @@ __device__ __forceinline__ Pos grid_pos(int rel_blk, int n)
     return p;
 }
 
-__device__ __forceinline__ long long lin(int i, int j, int k, int n)
+// position of this thread's column and z range (z-marching blocks)
+struct PosZ {
+    int i, j, z0, z1;
+    bool in;
+};
+
+__device__ __forceinline__ PosZ grid_pos_z(int rel_blk, int n, int zb)
 {
-    return ((long long)k * n + j) * n + i;
+    int tx = tiles_x(n), ty = tiles_y(n);
+    int bx = rel_blk % tx;
+    int rest = rel_blk / tx;
+    int by = rest % ty;
+    int bz = rest / ty;
+    PosZ p;
+    p.i = bx * HS_TX + (int)(threadIdx.x % HS_TX);
+    p.j = by * HS_TY + (int)(threadIdx.x / HS_TX);
+    p.z0 = bz * zb;
+    p.z1 = min(p.z0 + zb, n);
+    p.in = p.i < n && p.j < n;
+    return p;
+}
+
+// offset of point (i,j,k) inside one n^3 grid; n <= 511 keeps it below 2^31
+__device__ __forceinline__ int lin(int i, int j, int k, int n)
+{
+    return (k * n + j) * n + i;
 }
 
 // Sum over the three axes of the un-scaled 1-D stencils at point p:
@@ -143,6 +172,48 @@ struct Ld3 {
     __device__ __forceinline__ T operator()(int i, int j, int k) const { return u[lin(i, j, k, n)]; }
 };
 
+// L_h sum at p of an n^3 grid with neighbour offsets taken from p (32-bit)
+template <int ORDER, typename T>
+__device__ __forceinline__ T lap_at(const T* __restrict__ u, int p, int i, int j, int k, int n, T c)
+{
+    const int sy = n, sz = n * n;
+    const T zero = T(0);
+    if (ORDER == 2) {
+        T xm = i > 0 ? u[p - 1] : zero;
+        T xp = i < n - 1 ? u[p + 1] : zero;
+        T ym = j > 0 ? u[p - sy] : zero;
+        T yp = j < n - 1 ? u[p + sy] : zero;
+        T zm = k > 0 ? u[p - sz] : zero;
+        T zp = k < n - 1 ? u[p + sz] : zero;
+        T c2 = T(2) * c;
+        return ((xm - c2) + xp) + ((ym - c2) + yp) + ((zm - c2) + zp);
+    } else {
+        T ax, ay, az;
+        {
+            T m1 = i >= 1 ? u[p - 1] : zero;
+            T m2 = i >= 2 ? u[p - 2] : (i == 1 ? zero : -c);
+            T p1 = i <= n - 2 ? u[p + 1] : zero;
+            T p2 = i <= n - 3 ? u[p + 2] : (i == n - 2 ? zero : -c);
+            ax = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
+        }
+        {
+            T m1 = j >= 1 ? u[p - sy] : zero;
+            T m2 = j >= 2 ? u[p - 2 * sy] : (j == 1 ? zero : -c);
+            T p1 = j <= n - 2 ? u[p + sy] : zero;
+            T p2 = j <= n - 3 ? u[p + 2 * sy] : (j == n - 2 ? zero : -c);
+            ay = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
+        }
+        {
+            T m1 = k >= 1 ? u[p - sz] : zero;
+            T m2 = k >= 2 ? u[p - 2 * sz] : (k == 1 ? zero : -c);
+            T p1 = k <= n - 2 ? u[p + sz] : zero;
+            T p2 = k <= n - 3 ? u[p + 2 * sz] : (k == n - 2 ? zero : -c);
+            az = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
+        }
+        return (ax + ay) + az;
+    }
+}
+
 // coarse-grid view of a fine field by injection: coarse (I,J,K) is fine (2I+1, 2J+1, 2K+1)
 struct LdInj {
     const double* __restrict__ uf;
@@ -162,20 +233,13 @@ __device__ __forceinline__ double lane_a(const LaneCtl* ctl, int lane, int L, in
 template <typename T>
 __device__ __forceinline__ T nmax(T a, T b) { return (b > a || b != b) ? b : a; }
 
-__device__ __forceinline__ unsigned long long dbits(double x)
-{
-    return (unsigned long long)__double_as_longlong(x);
-}
-
-__device__ __forceinline__ double bitsd(unsigned long long x)
-{
-    return __longlong_as_double((long long)x);
-}
+template <typename T>
+__device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
 
 // block-wide max; result valid in thread 0.  All threads must call it.
 __device__ __forceinline__ double block_max(double v)
 {
-    __shared__ double sm[HS_BLOCK / 64 > 16 ? HS_BLOCK / 64 : 16];
+    __shared__ double sm[16];
     for (int off = 32; off > 0; off >>= 1) v = nmax(v, __shfl_xor(v, off, 64));
     int w = threadIdx.x / 64, l = threadIdx.x % 64;
     __syncthreads();
@@ -188,87 +252,271 @@ __device__ __forceinline__ double block_max(double v)
     return v;
 }
 
-// Accumulate a block's maximum into *acc and report whether this block is
-// the last of `nblk_seg` blocks to do so (then *acc holds the final value).
-__device__ __forceinline__ bool seg_reduce_last(double v, unsigned long long* acc, uint32_t* cnt,
-                                                int nblk_seg, unsigned long long* acc2 = nullptr,
-                                                double v2 = 0.0)
-{
-    __shared__ int last;
-    double m = block_max(v);
-    double m2 = acc2 ? block_max(v2) : 0.0;
-    if (threadIdx.x == 0) {
-        atomicMax(acc, dbits(m));
-        if (acc2) atomicMax(acc2, dbits(m2));
-        __threadfence();
-        unsigned prev = atomicAdd(cnt, 1u);
-        last = (prev == (unsigned)nblk_seg - 1u);
-    }
-    __syncthreads();
-    return last != 0;
-}
-
 template <typename S>
 __device__ __forceinline__ int seg_nblk(const S* segs, int nseg, int si, int nblk)
 {
     return (si + 1 < nseg ? segs[si + 1].blk_begin : nblk) - segs[si].blk_begin;
 }
 
+// value of a column at plane z' with the wall rules of lap_sum along z
+template <int ORDER, typename T>
+__device__ __forceinline__ T zval(const T* __restrict__ col, int z, int n, long long nn)
+{
+    if (z >= 0 && z < n) return col[(long long)z * nn];
+    if (ORDER == 4) {
+        if (z == -2) return -col[0];
+        if (z == n + 1) return -col[(long long)(n - 1) * nn];
+    }
+    return T(0);
+}
+
+// March one column (i, j) through planes z0..z1-1 of an n^3 field src,
+// keeping the z neighbours in registers; for each plane call
+// op(p, c, L) with p the linear index, c = src[p] and L = L_h src at p.
+template <int ORDER, typename T, typename Op>
+__device__ __forceinline__ void zmarch(const T* __restrict__ src, int n, int i, int j, int z0, int z1,
+                                       Op& op)
+{
+    constexpr int R = ORDER == 2 ? 1 : 2;
+    const long long nn = (long long)n * n;
+    const T* col = src + (long long)j * n + i;
+    const T sc = lap_scale<ORDER, T>(n);
+    const T zero = T(0);
+    T w[2 * R + 1];
+#pragma unroll
+    for (int d = -R; d < R; d++) w[d + R] = zval<ORDER, T>(col, z0 + d, n, nn);
+    for (int z = z0; z < z1; z++) {
+        w[2 * R] = zval<ORDER, T>(col, z + R, n, nn);
+        const T c = w[R];
+        const long long p = (long long)z * nn + (long long)j * n + i;
+        const T* u = src + p;
+        T L;
+        if (ORDER == 2) {
+            T xm = i > 0 ? u[-1] : zero;
+            T xp = i < n - 1 ? u[1] : zero;
+            T ym = j > 0 ? u[-n] : zero;
+            T yp = j < n - 1 ? u[n] : zero;
+            T c2 = T(2) * c;
+            L = ((xm - c2) + xp) + ((ym - c2) + yp) + ((w[0] - c2) + w[2]);
+        } else {
+            T ax, ay, az;
+            {
+                T m1 = i >= 1 ? u[-1] : zero;
+                T m2 = i >= 2 ? u[-2] : (i == 1 ? zero : -c);
+                T p1 = i <= n - 2 ? u[1] : zero;
+                T p2 = i <= n - 3 ? u[2] : (i == n - 2 ? zero : -c);
+                ax = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
+            }
+            {
+                T m1 = j >= 1 ? u[-n] : zero;
+                T m2 = j >= 2 ? u[-2 * n] : (j == 1 ? zero : -c);
+                T p1 = j <= n - 2 ? u[n] : zero;
+                T p2 = j <= n - 3 ? u[2 * n] : (j == n - 2 ? zero : -c);
+                ay = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
+            }
+            az = (T(16) * (w[1] + w[3]) - (w[0] + w[4])) - T(30) * c;
+            L = (ax + ay) + az;
+        }
+        op(p, z, c, sc * L);
+#pragma unroll
+        for (int d = 0; d < 2 * R; d++) w[d] = w[d + 1];
+    }
+}
+
+// Plane march through LDS.  The block (64 x 4 threads) owns a 64 x 4 column
+// tile and planes z0..z1-1.  The current plane, with a halo of R = ORDER/2
+// points in x and y, sits in one of two LDS buffers; the z neighbours of each
+// column sit in registers.  While plane z is computed, the halo of plane z+1
+// and the column value of plane z+R+1 are already in flight, so one memory
+// latency is hidden behind every plane.  Every thread of the block must call
+// this (it synchronises); op(p, z, c, L) is called for the points inside the
+// grid with p the linear index, c = src[p] and L = L_h src at p.
+template <int ORDER>
+struct Halo {
+    static constexpr int R = ORDER == 2 ? 1 : 2;
+    static constexpr int LW = HS_TX + 2 * R;
+    static constexpr int LH = HS_TY + 2 * R;
+    static constexpr int NH = 2 * R * HS_TY + 2 * R * LW;      // halo cells per plane
+    static constexpr int HPT = (NH + HS_BLOCK - 1) / HS_BLOCK;  // halo cells per thread
+};
+
+template <int ORDER, typename T, typename Op>
+__device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int i0, int j0, int z0,
+                                          int z1, T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op)
+{
+    using H = Halo<ORDER>;
+    constexpr int R = H::R;
+    const long long nn = (long long)n * n;
+    const int lx = threadIdx.x % HS_TX, ly = threadIdx.x / HS_TX;
+    const int i = i0 + lx, j = j0 + ly;
+    const bool in = i < n && j < n;
+    const T sc = lap_scale<ORDER, T>(n);
+    // this thread's halo cells
+    int hrow[H::HPT], hcol[H::HPT];
+    long long hoff[H::HPT];
+    bool hin[H::HPT];
+#pragma unroll
+    for (int h = 0; h < H::HPT; h++) {
+        int q = threadIdx.x + HS_BLOCK * h;
+        int lrow = -1, lcol = 0;
+        if (q < H::NH) {
+            if (q < 2 * R * HS_TY) {
+                lrow = q / (2 * R) + R;
+                int c = q % (2 * R);
+                lcol = c < R ? c : HS_TX + c;
+            } else {
+                int t = q - 2 * R * HS_TY;
+                int rr = t / H::LW;
+                lrow = rr < R ? rr : HS_TY + rr;
+                lcol = t % H::LW;
+            }
+        }
+        int gi = i0 + lcol - R, gj = j0 + lrow - R;
+        hrow[h] = lrow;
+        hcol[h] = lcol;
+        hin[h] = lrow >= 0 && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        hoff[h] = hin[h] ? (long long)gj * n + gi : 0;
+    }
+    const T* col = src + (long long)j * n + i;
+    T w[2 * R + 1];
+#pragma unroll
+    for (int d = -R; d <= R; d++) w[d + R] = in ? zval<ORDER, T>(col, z0 + d, n, nn) : T(0);
+    {
+        const T* plane = src + (long long)z0 * nn;
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++)
+            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? plane[hoff[h]] : T(0);
+        pl[0][ly + R][lx + R] = w[R];
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int z = z0; z < z1; z++) {
+        const bool more = z + 1 < z1;
+        T hv[H::HPT];
+        const T* plane1 = src + (long long)(z + 1) * nn;
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++) hv[h] = (more && hin[h]) ? plane1[hoff[h]] : T(0);
+        T wn = (more && in) ? zval<ORDER, T>(col, z + R + 1, n, nn) : T(0);
+        if (in) {
+            const int yy = ly + R, xx = lx + R;
+            const T c = w[R];
+            T L;
+            if (ORDER == 2) {
+                T c2 = T(2) * c;
+                L = ((pl[buf][yy][xx - 1] - c2) + pl[buf][yy][xx + 1]) +
+                    ((pl[buf][yy - 1][xx] - c2) + pl[buf][yy + 1][xx]) + ((w[0] - c2) + w[2]);
+            } else {
+                // cells outside the grid hold 0; the reflected taps one beyond a wall are -c
+                T m2 = i == 0 ? -c : pl[buf][yy][xx - 2];
+                T p2 = i == n - 1 ? -c : pl[buf][yy][xx + 2];
+                T ax = (T(16) * (pl[buf][yy][xx - 1] + pl[buf][yy][xx + 1]) - (m2 + p2)) - T(30) * c;
+                m2 = j == 0 ? -c : pl[buf][yy - 2][xx];
+                p2 = j == n - 1 ? -c : pl[buf][yy + 2][xx];
+                T ay = (T(16) * (pl[buf][yy - 1][xx] + pl[buf][yy + 1][xx]) - (m2 + p2)) - T(30) * c;
+                T az = (T(16) * (w[1] + w[3]) - (w[0] + w[4])) - T(30) * c;
+                L = (ax + ay) + az;
+            }
+            op((long long)z * nn + (long long)j * n + i, z, c, sc * L);
+        }
+        if (more) {
+#pragma unroll
+            for (int h = 0; h < H::HPT; h++)
+                if (hrow[h] >= 0) pl[buf ^ 1][hrow[h]][hcol[h]] = hv[h];
+            pl[buf ^ 1][ly + R][lx + R] = w[R + 1];
+        }
+#pragma unroll
+        for (int d = 0; d < 2 * R; d++) w[d] = w[d + 1];
+        w[2 * R] = wn;
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Multigrid kernels
 // ---------------------------------------------------------------------------
 
-// Weighted Jacobi: dst = src + omega D^{-1} (b - A_a src); from a zero guess
-// dst = omega D^{-1} b.
-template <typename T, int ORDER>
-__global__ void __launch_bounds__(HS_BLOCK) k_jacobi(const GridSeg* __restrict__ segs, int nseg,
-                                                     int nblk, const LaneCtl* __restrict__ ctl,
-                                                     hsk::MgArgs A, int first_sweep, int src_is_t)
+template <typename T, int ORDER, int MODE, int NORM>
+struct SweepOp {
+    T* __restrict__ dst;
+    const T* __restrict__ b;
+    T a, om;
+    int i, j, n;
+    int cycle;
+    double rmax, bmax;
+    __device__ __forceinline__ void operator()(long long p, int z, T c, T L)
+    {
+        T bp = b[p];
+        T r = bp - (c - a * L);
+        if (MODE == 0) dst[p] = c + om * r / diag_A<ORDER, T>(a, i, j, z, n);
+        else dst[p] = r;
+        if (NORM) {
+            rmax = nmax(rmax, (double)tabs(r));
+            if (cycle == 0) bmax = nmax(bmax, (double)tabs(bp));
+        }
+    }
+};
+
+// MODE 0: weighted Jacobi  dst = x + omega D^{-1} (b - A_a x)  (from a zero
+// guess on correction grids: dst = omega D^{-1} b); MODE 1: residual
+// dst = b - A_a x.  x is the buffer picked by src_is_t, dst the other one.
+// NORM: per-block maxima of |b - A_a x| (and |b| at cycle 0) to partials.
+template <typename T, int ORDER, int MODE, int FINEST, int NORM>
+__global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ segs, int nseg,
+                                                    int nblk, const LaneCtl* __restrict__ ctl,
+                                                    hsk::MgArgs A, int first_sweep, int src_is_t,
+                                                    double* __restrict__ partials, int cycle)
 {
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
     if (A.gate && ctl[sg.lane].mg_state != 0) return;
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
-    if (!q.in) return;
+    const int n = sg.n;
+    PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
     T* Tt = (T*)sg.t;
     const T* B = (const T*)sg.b;
-    T* src = src_is_t ? Tt : U;
+    const T* src = src_is_t ? Tt : U;
     T* dst = src_is_t ? U : Tt;
-    T a = T(lane_a(ctl, sg.lane, A.L, A.m));
-    T om = T(A.omega);
-    long long p = lin(q.i, q.j, q.k, n);
-    T D = diag_A<ORDER, T>(a, q.i, q.j, q.k, n);
-    if (first_sweep && sg.coarse) {
-        dst[p] = om * B[p] / D;
-        return;
+    SweepOp<T, ORDER, MODE, NORM> op;
+    op.dst = dst;
+    op.b = B;
+    op.a = T(lane_a(ctl, sg.lane, A.L, A.m));
+    op.om = T(A.omega);
+    op.i = q.i;
+    op.j = q.j;
+    op.n = n;
+    op.cycle = cycle;
+    op.rmax = 0.0;
+    op.bmax = 0.0;
+    if (MODE == 0 && !FINEST && first_sweep && sg.coarse) {
+        if (q.in)
+            for (int z = q.z0; z < q.z1; z++) {
+                long long p = lin(q.i, q.j, z, n);
+                dst[p] = op.om * B[p] / diag_A<ORDER, T>(op.a, q.i, q.j, z, n);
+            }
+    } else {
+        __shared__ T pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
+        lds_march<ORDER, T>(src, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX),
+                            q.z0, q.z1, pl, op);
     }
-    Ld3<T> ld{src, n};
-    T c = src[p];
-    T Au = c - a * (lap_scale<ORDER, T>(n) * lap_sum<ORDER, T>(ld, q.i, q.j, q.k, n, c));
-    dst[p] = c + om * (B[p] - Au) / D;
+    if (NORM) {
+        double m = block_max(op.rmax);
+        double mb = block_max(op.bmax);
+        if (threadIdx.x == 0) {
+            partials[2 * lb] = m;
+            partials[2 * lb + 1] = mb;
+        }
+    }
 }
 
-// r = b - A_a u at fine point (i,j,k)
-template <typename T, int ORDER>
-__device__ __forceinline__ T resid_at(const T* __restrict__ u, const T* __restrict__ b, T a, T sc,
-                                      int i, int j, int k, int n)
-{
-    long long p = lin(i, j, k, n);
-    T c = u[p];
-    Ld3<T> ld{u, n};
-    return b[p] - (c - a * (sc * lap_sum<ORDER, T>(ld, i, j, k, n, c)));
-}
-
-// Residual and full-weighting restriction, one thread per coarse point:
-// cb(I) = sum over the 27 fine neighbours of 2I+1 of (1/4,1/2,1/4)^3 r.
-template <typename T, int ORDER>
-__global__ void __launch_bounds__(HS_BLOCK) k_resid_restrict(const GridSeg* __restrict__ segs,
-                                                             int nseg, int nblk,
-                                                             const LaneCtl* __restrict__ ctl,
-                                                             hsk::MgArgs A, int src_is_t)
+// Full weighting of the residual r held in the free buffer: one thread per
+// coarse point, cb(I) = sum over the 27 fine neighbours of 2I+1 of
+// (1/4,1/2,1/4)^3 r.
+template <typename T>
+__global__ void __launch_bounds__(HS_BLOCK) k_restrict_fw(const GridSeg* __restrict__ segs, int nseg,
+                                                          int nblk, const LaneCtl* __restrict__ ctl,
+                                                          hsk::MgArgs A, int r_is_t)
 {
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(segs, nseg, lb);
@@ -277,19 +525,18 @@ __global__ void __launch_bounds__(HS_BLOCK) k_resid_restrict(const GridSeg* __re
     int n = sg.n, nc = sg.nc;
     Pos q = grid_pos(lb - sg.blk_begin, nc);
     if (!q.in) return;
-    const T* u = src_is_t ? (const T*)sg.t : (const T*)sg.u + (long long)A.node * sg.node_stride;
-    const T* b = (const T*)sg.b;
-    T a = T(lane_a(ctl, sg.lane, A.L, A.m));
-    T sc = lap_scale<ORDER, T>(n);
+    const T* r = r_is_t ? (const T*)sg.t : (const T*)sg.u + (long long)A.node * sg.node_stride;
+    const long long nn = (long long)n * n;
+    const T* c = r + lin(2 * q.i + 1, 2 * q.j + 1, 2 * q.k + 1, n);
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    int fi = 2 * q.i + 1, fj = 2 * q.j + 1, fk = 2 * q.k + 1;
     T acc = T(0);
+#pragma unroll
     for (int dz = -1; dz <= 1; dz++) {
         T az = T(0);
+#pragma unroll
         for (int dy = -1; dy <= 1; dy++) {
-            T ay = T(0);
-            for (int dx = -1; dx <= 1; dx++)
-                ay += w[dx + 1] * resid_at<T, ORDER>(u, b, a, sc, fi + dx, fj + dy, fk + dz, n);
+            const T* row = c + dz * nn + (long long)dy * n;
+            T ay = (w[0] * row[-1] + w[1] * row[0]) + w[2] * row[1];
             az += w[dy + 1] * ay;
         }
         acc += w[dz + 1] * az;
@@ -297,35 +544,40 @@ __global__ void __launch_bounds__(HS_BLOCK) k_resid_restrict(const GridSeg* __re
     ((T*)sg.cb)[lin(q.i, q.j, q.k, nc)] = acc;
 }
 
-// trilinear interpolation of a coarse field at fine point (i,j,k); walls 0
+// trilinear interpolation of a coarse field at fine point (i,j,k); walls 0.
+// Per axis a fine index either coincides with coarse (i-1)/2 (weight 1) or
+// lies between coarse i/2-1 and i/2 (weights 1/2, missing ones are walls).
 template <typename T>
 __device__ __forceinline__ T prolong_at(const T* __restrict__ c, int nc, int i, int j, int k)
 {
-    int ix[2], iy[2], iz[2], cx, cy, cz;
+    int ix0, ix1, iy0, iy1, iz0, iz1;
     T wx, wy, wz;
-    if (i & 1) { ix[0] = (i - 1) >> 1; cx = 1; wx = T(1); }
-    else { ix[0] = (i >> 1) - 1; ix[1] = i >> 1; cx = 2; wx = T(0.5); }
-    if (j & 1) { iy[0] = (j - 1) >> 1; cy = 1; wy = T(1); }
-    else { iy[0] = (j >> 1) - 1; iy[1] = j >> 1; cy = 2; wy = T(0.5); }
-    if (k & 1) { iz[0] = (k - 1) >> 1; cz = 1; wz = T(1); }
-    else { iz[0] = (k >> 1) - 1; iz[1] = k >> 1; cz = 2; wz = T(0.5); }
+    if (i & 1) { ix0 = ix1 = (i - 1) >> 1; wx = T(1); } else { ix0 = (i >> 1) - 1; ix1 = i >> 1; wx = T(0.5); }
+    if (j & 1) { iy0 = iy1 = (j - 1) >> 1; wy = T(1); } else { iy0 = (j >> 1) - 1; iy1 = j >> 1; wy = T(0.5); }
+    if (k & 1) { iz0 = iz1 = (k - 1) >> 1; wz = T(1); } else { iz0 = (k >> 1) - 1; iz1 = k >> 1; wz = T(0.5); }
+    const bool two_x = !(i & 1), two_y = !(j & 1), two_z = !(k & 1);
+    const bool vx0 = ix0 >= 0, vx1 = two_x && ix1 < nc;
+    const bool vy0 = iy0 >= 0, vy1 = two_y && iy1 < nc;
+    const bool vz0 = iz0 >= 0, vz1 = two_z && iz1 < nc;
+    const int sy = nc, sz = nc * nc;
     T s = T(0);
-    for (int c3 = 0; c3 < cz; c3++) {
-        int K = iz[c3];
-        if (K < 0 || K >= nc) continue;
-        T sy = T(0);
-        for (int c2 = 0; c2 < cy; c2++) {
-            int J = iy[c2];
-            if (J < 0 || J >= nc) continue;
+#pragma unroll
+    for (int cz = 0; cz < 2; cz++) {
+        const bool vz = cz ? vz1 : vz0;
+        if (!vz) continue;
+        const int oz = (cz ? iz1 : iz0) * sz;
+        T sy_ = T(0);
+#pragma unroll
+        for (int cy = 0; cy < 2; cy++) {
+            const bool vy = cy ? vy1 : vy0;
+            if (!vy) continue;
+            const int o = oz + (cy ? iy1 : iy0) * sy;
             T sx = T(0);
-            for (int c1 = 0; c1 < cx; c1++) {
-                int I = ix[c1];
-                if (I < 0 || I >= nc) continue;
-                sx += c[lin(I, J, K, nc)];
-            }
-            sy += wx * sx;
+            if (vx0) sx += c[o + ix0];
+            if (vx1) sx += c[o + ix1];
+            sy_ += wx * sx;
         }
-        s += wy * sy;
+        s += wy * sy_;
     }
     return wz * s;
 }
@@ -352,47 +604,82 @@ __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Coarse tail: every grid with n <= HS_TAIL_N of one lane, one workgroup
+// Coarse tail: every grid with n <= HS_TAIL_N of one lane, one workgroup,
+// all grids held in LDS (the right-hand side of the top grid is read from
+// global memory).
 // ---------------------------------------------------------------------------
 
-template <typename T, int ORDER>
-__device__ void tail_jacobi(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b,
-                            int n, T a, T om, bool zero)
+// Point `q` of this thread on an n^3 tail grid (n <= 15): 16 lanes per x row,
+// 64 rows j + n k per pass, passes q = 0..TAIL_Q-1.  k = row / n is taken in
+// float, exact for rows < 256 (the fraction j / n stays below 1 - 1/16).
+constexpr int TAIL_Q = (HS_TAIL_N * HS_TAIL_N + 63) / 64;
+
+__device__ __forceinline__ bool tail_pt(int n, float inv_n, int q, int& i, int& j, int& k, int& p)
 {
-    long long N = (long long)n * n * n;
-    T sc = lap_scale<ORDER, T>(n);
-    for (long long p = threadIdx.x; p < N; p += blockDim.x) {
-        int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long long)n * n));
-        T D = diag_A<ORDER, T>(a, i, j, k, n);
+    int r = 64 * q + (int)(threadIdx.x >> 4);
+    i = (int)(threadIdx.x & 15);
+    if (i >= n || r >= n * n) return false;
+    k = (int)((float)r * inv_n + 1e-3f);
+    j = r - k * n;
+    p = r * n + i;
+    return true;
+}
+
+// one weighted-Jacobi sweep (zero: from a zero guess) on a tail grid in LDS;
+// the right-hand side comes from registers (bv, top grid) or LDS (b);
+// rd[w] = omega / D for a point next to w walls (D = diagonal of A_a)
+template <typename T, int ORDER, bool REG>
+__device__ __forceinline__ void lds_jacobi(const T* src, T* dst, const T* b, const T* bv, int n, T a,
+                                           const T* rd, bool zero)
+{
+    const T sc = lap_scale<ORDER, T>(n);
+    const float inv_n = 1.0f / (float)n;
+#pragma unroll
+    for (int q = 0; q < TAIL_Q; q++) {
+        int i, j, k, p;
+        if (!tail_pt(n, inv_n, q, i, j, k, p)) continue;
+        T bp = REG ? bv[q] : b[p];
+        int walls = ORDER == 2 ? 0 : (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
+        T r = rd[walls];
         if (zero) {
-            dst[p] = om * b[p] / D;
+            dst[p] = r * bp;
         } else {
-            Ld3<T> ld{src, n};
             T c = src[p];
-            T Au = c - a * (sc * lap_sum<ORDER, T>(ld, i, j, k, n, c));
-            dst[p] = c + om * (b[p] - Au) / D;
+            T Au = c - a * (sc * lap_at<ORDER, T>(src, p, i, j, k, n, c));
+            dst[p] = c + r * (bp - Au);
         }
     }
 }
 
-template <typename T, int ORDER>
-__device__ void tail_restrict(const T* __restrict__ u, const T* __restrict__ b, T* __restrict__ cb,
-                              int n, T a)
+template <typename T, int ORDER, bool REG>
+__device__ __forceinline__ void lds_resid(const T* u, const T* b, const T* bv, T* r, int n, T a)
+{
+    const T sc = lap_scale<ORDER, T>(n);
+    const float inv_n = 1.0f / (float)n;
+#pragma unroll
+    for (int q = 0; q < TAIL_Q; q++) {
+        int i, j, k, p;
+        if (!tail_pt(n, inv_n, q, i, j, k, p)) continue;
+        T c = u[p];
+        r[p] = (REG ? bv[q] : b[p]) - (c - a * (sc * lap_at<ORDER, T>(u, p, i, j, k, n, c)));
+    }
+}
+
+template <typename T>
+__device__ void lds_restrict(const T* r, T* cb, int n)
 {
     int nc = (n - 1) / 2;
-    long long Nc = (long long)nc * nc * nc;
-    T sc = lap_scale<ORDER, T>(n);
+    int Nc = nc * nc * nc;
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    for (long long p = threadIdx.x; p < Nc; p += blockDim.x) {
-        int I = (int)(p % nc), J = (int)((p / nc) % nc), K = (int)(p / ((long long)nc * nc));
-        int fi = 2 * I + 1, fj = 2 * J + 1, fk = 2 * K + 1;
+    for (int p = threadIdx.x; p < Nc; p += blockDim.x) {
+        int I = p % nc, J = (p / nc) % nc, K = p / (nc * nc);
+        const T* c = r + lin(2 * I + 1, 2 * J + 1, 2 * K + 1, n);
         T acc = T(0);
         for (int dz = -1; dz <= 1; dz++) {
             T az = T(0);
             for (int dy = -1; dy <= 1; dy++) {
-                T ay = T(0);
-                for (int dx = -1; dx <= 1; dx++)
-                    ay += w[dx + 1] * resid_at<T, ORDER>(u, b, a, sc, fi + dx, fj + dy, fk + dz, n);
+                const T* row = c + dz * n * n + dy * n;
+                T ay = (w[0] * row[-1] + w[1] * row[0]) + w[2] * row[1];
                 az += w[dy + 1] * ay;
             }
             acc += w[dz + 1] * az;
@@ -402,20 +689,19 @@ __device__ void tail_restrict(const T* __restrict__ u, const T* __restrict__ b, 
 }
 
 template <typename T>
-__device__ void tail_prolong(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ c,
-                             int n)
+__device__ void lds_prolong_add(T* u, const T* c, int n)
 {
     int nc = (n - 1) / 2;
-    long long N = (long long)n * n * n;
-    for (long long p = threadIdx.x; p < N; p += blockDim.x) {
-        int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long long)n * n));
-        dst[p] = src[p] + prolong_at<T>(c, nc, i, j, k);
+    int N = n * n * n;
+    for (int p = threadIdx.x; p < N; p += blockDim.x) {
+        int i = p % n, j = (p / n) % n, k = p / (n * n);
+        u[p] += prolong_at<T>(c, nc, i, j, k);
     }
 }
 
 // exact solve on a grid of n = 1 or 3 points per axis by the sine transform
 template <typename T>
-__device__ void tail_exact(const T* __restrict__ b, T* __restrict__ x, int n, T a, const CoarseTable& ct)
+__device__ void lds_exact(const T* b, T* x, int n, T a, const CoarseTable& ct)
 {
     __shared__ double bh[27];
     int N = n * n * n;
@@ -443,72 +729,103 @@ __device__ void tail_exact(const T* __restrict__ b, T* __restrict__ x, int n, T 
     __syncthreads();
 }
 
-// One V(nu1,nu2) cycle over the tail grids of one lane.  Level 0 of the tail
-// starts from the iterate in u[0] (or from zero when zero_guess), the lower
-// levels from zero; the result is left in u[0].
+// One V(nu1,nu2) cycle over the tail grids of one lane, in LDS.  Level 0
+// starts from the iterate in global memory (or from zero when the tail top
+// is a correction grid), the lower levels from zero; the result is written
+// back to level 0's iterate.  LDS layout: level 0: x0, y0 (ping-pong);
+// levels l >= 1: x_l, y_l, b_l.
 template <typename T, int ORDER>
 __global__ void __launch_bounds__(HS_TAIL_THREADS) k_tail(const TailSeg* __restrict__ segs,
                                                           const LaneCtl* __restrict__ ctl,
                                                           hsk::MgArgs A, int nu1, int nu2)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
     const TailSeg& ts = segs[blockIdx.x];
-    const int zero_guess = ts.zero_guess;
     if (A.gate && ctl[ts.lane].mg_state != 0) return;
-    T a = T(lane_a(ctl, ts.lane, A.L, A.m));
-    T om = T(A.omega);
-    T* u[HS_MAXTAIL];
-    T* t[HS_MAXTAIL];
-    const T* b[HS_MAXTAIL];
-    for (int l = 0; l < ts.nlev; l++) {
-        u[l] = (T*)ts.u[l];
-        t[l] = (T*)ts.t[l];
-        b[l] = (const T*)ts.b[l];
+    const T a = T(lane_a(ctl, ts.lane, A.L, A.m));
+    const T om = T(A.omega);
+    const int nlev = ts.nlev;
+    const int last = nlev - 1;
+    T* gu0 = (T*)ts.u[0] + (long long)A.node * ts.node_stride;
+    const T* gb0 = (const T*)ts.b[0];
+    // LDS layout: level 0: X, Y; levels l >= 1: X, Y, B (n_l^3 each)
+    T* base = (T*)smem;
+    auto offs = [&](int l) {
+        int o = 0;
+        for (int q = 0; q < l; q++) o += (q == 0 ? 2 : 3) * ts.n[q] * ts.n[q] * ts.n[q];
+        return o;
+    };
+    auto X = [&](int l) { return base + offs(l); };
+    auto Y = [&](int l) { return base + offs(l) + ts.n[l] * ts.n[l] * ts.n[l]; };
+    auto Bv = [&](int l) { return base + offs(l) + 2 * ts.n[l] * ts.n[l] * ts.n[l]; };
+    const int n0 = ts.n[0];
+    const int N0 = n0 * n0 * n0;
+    __shared__ T s_rd[HS_MAXTAIL][8];
+    if ((int)threadIdx.x < nlev * 7) {
+        int l = threadIdx.x / 7, w = threadIdx.x % 7;
+        int nl = ts.n[l];
+        T ih2 = T((double)(nl + 1) * (double)(nl + 1));
+        T D = ORDER == 2 ? T(1) + a * ih2 * T(6) : T(1) + a * ih2 * (T(90 - w) / T(12));
+        s_rd[l][w] = om / D;
     }
-    u[0] += (long long)A.node * ts.node_stride;
-    const CoarseTable& ct = c_lc.ct[ts.coarse_table];
-    int last = ts.nlev - 1;
-    bool in_t[HS_MAXTAIL];   // iterate of level l currently sits in t[l]
-    // down
+    T b0[TAIL_Q];
+    {
+        const float inv_n = 1.0f / (float)n0;
+#pragma unroll
+        for (int q = 0; q < TAIL_Q; q++) {
+            int i, j, k, p;
+            b0[q] = tail_pt(n0, inv_n, q, i, j, k, p) ? gb0[p] : T(0);
+        }
+    }
+    if (!ts.zero_guess)
+        for (int p = threadIdx.x; p < N0; p += blockDim.x) X(0)[p] = gu0[p];
+    __syncthreads();
+    unsigned in_y = 0;   // bit l: level l's iterate sits in Y(l)
     for (int l = 0; l < last; l++) {
-        int n = ts.n[l];
-        bool zero = (l > 0) || zero_guess;
-        in_t[l] = false;
+        const int n = ts.n[l];
+        const bool zero = (l > 0) || ts.zero_guess;
         for (int s = 0; s < nu1; s++) {
-            T* src = in_t[l] ? t[l] : u[l];
-            T* dst = in_t[l] ? u[l] : t[l];
-            tail_jacobi<T, ORDER>(src, dst, b[l], n, a, om, zero && s == 0);
-            in_t[l] = !in_t[l];
+            bool iy = (in_y >> l) & 1;
+            T* src = iy ? Y(l) : X(l);
+            T* dst = iy ? X(l) : Y(l);
+            if (l == 0) lds_jacobi<T, ORDER, true>(src, dst, nullptr, b0, n, a, s_rd[0], zero && s == 0);
+            else lds_jacobi<T, ORDER, false>(src, dst, Bv(l), nullptr, n, a, s_rd[l], zero && s == 0);
+            in_y ^= 1u << l;
             __syncthreads();
         }
-        if (nu1 == 0 && zero) {
-            long long N = (long long)n * n * n;
-            for (long long p = threadIdx.x; p < N; p += blockDim.x) u[l][p] = T(0);
-            __syncthreads();
-        }
-        tail_restrict<T, ORDER>(in_t[l] ? t[l] : u[l], b[l], (T*)b[l + 1], n, a);
+        bool iy = (in_y >> l) & 1;
+        T* x = iy ? Y(l) : X(l);
+        T* r = iy ? X(l) : Y(l);
+        if (l == 0) lds_resid<T, ORDER, true>(x, nullptr, b0, r, n, a);
+        else lds_resid<T, ORDER, false>(x, Bv(l), nullptr, r, n, a);
+        __syncthreads();
+        lds_restrict<T>(r, Bv(l + 1), n);
         __syncthreads();
     }
-    // coarsest grid: exact (an initial guess there is irrelevant)
-    tail_exact<T>(b[last], u[last], ts.n[last], a, ct);
-    // up
+    if (last == 0) {
+        // single-grid tail: the exact solve reads the right-hand side from memory
+        lds_exact<T>(gb0, X(0), ts.n[0], a, c_lc.ct[ts.coarse_table]);
+    } else {
+        lds_exact<T>(Bv(last), X(last), ts.n[last], a, c_lc.ct[ts.coarse_table]);
+    }
     for (int l = last - 1; l >= 0; l--) {
-        int n = ts.n[l];
-        T* cur = in_t[l] ? t[l] : u[l];
-        tail_prolong<T>(cur, cur, u[l + 1], n);
+        const int n = ts.n[l];
+        bool iy = (in_y >> l) & 1;
+        const T* coarse = ((in_y >> (l + 1)) & 1) ? Y(l + 1) : X(l + 1);
+        lds_prolong_add<T>(iy ? Y(l) : X(l), coarse, n);
         __syncthreads();
         for (int s = 0; s < nu2; s++) {
-            T* src = in_t[l] ? t[l] : u[l];
-            T* dst = in_t[l] ? u[l] : t[l];
-            tail_jacobi<T, ORDER>(src, dst, b[l], n, a, om, false);
-            in_t[l] = !in_t[l];
-            __syncthreads();
-        }
-        if (in_t[l]) {
-            long long N = (long long)n * n * n;
-            for (long long p = threadIdx.x; p < N; p += blockDim.x) u[l][p] = t[l][p];
+            iy = (in_y >> l) & 1;
+            T* src = iy ? Y(l) : X(l);
+            T* dst = iy ? X(l) : Y(l);
+            if (l == 0) lds_jacobi<T, ORDER, true>(src, dst, nullptr, b0, n, a, s_rd[0], false);
+            else lds_jacobi<T, ORDER, false>(src, dst, Bv(l), nullptr, n, a, s_rd[l], false);
+            in_y ^= 1u << l;
             __syncthreads();
         }
     }
+    const T* res = ((in_y & 1u) ? Y(0) : X(0));
+    for (int p = threadIdx.x; p < N0; p += blockDim.x) gu0[p] = res[p];
 }
 
 // ---------------------------------------------------------------------------
@@ -525,41 +842,32 @@ __device__ __forceinline__ void finish_solve(LaneCtl& c, int cycle, int state)
     if (state == 2) c.failed_solves += 1;
 }
 
-// Before cycle `cycle`: rho = |b - A u|_inf / |b|_inf (|b| = 0 -> 1); stop when
-// rho <= tol, fail when cycle == max_cycles or rho is not finite.
-__global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict__ segs, int nseg,
-                                                      int nblk, LaneCtl* __restrict__ ctl,
-                                                      hsk::MgArgs A, int order, int src_is_t,
-                                                      int cycle, double tol, int max_cycles)
+// Stopping test before cycle `cycle`, one block per lane:
+// rho = |b - A u|_inf / |b|_inf (|b| = 0 -> 1); stop when rho <= tol, fail
+// when cycle == max_cycles or rho is not finite.
+__global__ void __launch_bounds__(HS_BLOCK) k_mg_decide(const GridSeg* __restrict__ segs, int nseg,
+                                                        int nblk, const double* __restrict__ partials,
+                                                        LaneCtl* __restrict__ ctl, int cycle,
+                                                        double tol, int max_cycles)
 {
-    int lb = xcd_remap(blockIdx.x, nblk);
-    int si = find_seg(segs, nseg, lb);
+    int si = blockIdx.x;
     const GridSeg sg = segs[si];
     LaneCtl& c = ctl[sg.lane];
     if (c.mg_state != 0) return;
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
-    const double* u = src_is_t ? (const double*)sg.t
-                               : (const double*)sg.u + (long long)A.node * sg.node_stride;
-    const double* b = (const double*)sg.b;
-    double a = lane_a(ctl, sg.lane, A.L, A.m);
+    int b0 = sg.blk_begin, nb = seg_nblk(segs, nseg, si, nblk);
     double r = 0.0, bb = 0.0;
-    if (q.in) {
-        double sc = order == 2 ? lap_scale<2, double>(n) : lap_scale<4, double>(n);
-        r = order == 2 ? resid_at<double, 2>(u, b, a, sc, q.i, q.j, q.k, n)
-                       : resid_at<double, 4>(u, b, a, sc, q.i, q.j, q.k, n);
-        r = fabs(r);
-        if (cycle == 0) bb = fabs(b[lin(q.i, q.j, q.k, n)]);
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        r = nmax(r, partials[2 * (b0 + q)]);
+        if (cycle == 0) bb = nmax(bb, partials[2 * (b0 + q) + 1]);
     }
-    bool last = seg_reduce_last(r, &c.res_bits, &c.red_cnt[0], seg_nblk(segs, nseg, si, nblk),
-                                cycle == 0 ? &c.bn_bits : nullptr, bb);
-    if (last && threadIdx.x == 0) {
-        double rmax = bitsd(atomicAdd(&c.res_bits, 0ull));
-        if (cycle == 0) c.bnorm = bitsd(atomicAdd(&c.bn_bits, 0ull));
+    r = block_max(r);
+    if (cycle == 0) bb = block_max(bb);
+    if (threadIdx.x == 0) {
+        if (cycle == 0) c.bnorm = bb;
         double scale = c.bnorm > 0.0 ? c.bnorm : 1.0;
-        double rho = rmax / scale;
+        double rho = r / scale;
         c.mg_rho = rho;
-        if (rho != rho || rmax > 1.7e308) {
+        if (rho != rho || r > 1.7e308) {
             finish_solve(c, cycle, 2);
             c.status = -4;
         } else if (rho <= tol) {
@@ -568,61 +876,86 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict_
             finish_solve(c, cycle, 2);
             if (c.status == 0) c.status = -3;
         }
-        c.res_bits = 0ull;
-        c.bn_bits = 0ull;
-        c.red_cnt[0] = 0u;
     }
 }
 
-// Mixed-precision refinement step on the finest grid: optionally u += e
-// (the FP32 correction), then r = b - A u in FP64, r32 = (float) r into the
-// FP32 right-hand side, and the same stopping test as k_mg_norm.
+// max-norm residual of the FP64 iterate of the finest grid, per block
+template <int ORDER>
+__global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict__ segs, int nseg,
+                                                      int nblk, const LaneCtl* __restrict__ ctl,
+                                                      hsk::MgArgs A, int cycle,
+                                                      double* __restrict__ partials)
+{
+    int lb = xcd_remap(blockIdx.x, nblk);
+    int si = find_seg(segs, nseg, lb);
+    const GridSeg sg = segs[si];
+    if (ctl[sg.lane].mg_state != 0) return;
+    const int n = sg.n;
+    PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
+    const double* u = (const double*)sg.u + (long long)A.node * sg.node_stride;
+    struct Op {
+        const double* b;
+        double a;
+        int cycle;
+        double rmax, bmax;
+        __device__ __forceinline__ void operator()(long long p, int, double c, double L)
+        {
+            double bp = b[p];
+            rmax = nmax(rmax, fabs(bp - (c - a * L)));
+            if (cycle == 0) bmax = nmax(bmax, fabs(bp));
+        }
+    } op{(const double*)sg.b, lane_a(ctl, sg.lane, A.L, A.m), cycle, 0.0, 0.0};
+    __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
+    lds_march<ORDER, double>(u, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX), q.z0,
+                             q.z1, pl, op);
+    double m = block_max(op.rmax);
+    double mb = block_max(op.bmax);
+    if (threadIdx.x == 0) {
+        partials[2 * lb] = m;
+        partials[2 * lb + 1] = mb;
+    }
+}
+
+// Mixed-precision refinement on the finest grid: r = b - A u in FP64,
+// r32 = (float) r into the FP32 right-hand side, per-block maxima of |r|
+// (and |b| at iteration 0).
 template <int ORDER>
 __global__ void __launch_bounds__(HS_BLOCK) k_ir_resid(const GridSeg* __restrict__ s64,
                                                        const GridSeg* __restrict__ s32, int nseg,
-                                                       int nblk, LaneCtl* __restrict__ ctl,
-                                                       hsk::MgArgs A, int iter, double tol,
-                                                       int max_iter)
+                                                       int nblk, const LaneCtl* __restrict__ ctl,
+                                                       hsk::MgArgs A, int iter,
+                                                       double* __restrict__ partials)
 {
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(s64, nseg, lb);
     const GridSeg sg = s64[si];
-    const GridSeg sf = s32[si];
-    LaneCtl& c = ctl[sg.lane];
-    if (c.mg_state != 0) return;
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
+    if (ctl[sg.lane].mg_state != 0) return;
+    const int n = sg.n;
+    PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     const double* u = (const double*)sg.u + (long long)A.node * sg.node_stride;
-    const double* b = (const double*)sg.b;
-    double a = lane_a(ctl, sg.lane, A.L, A.m);
-    double r = 0.0, bb = 0.0;
-    if (q.in) {
-        r = resid_at<double, ORDER>(u, b, a, lap_scale<ORDER, double>(n), q.i, q.j, q.k, n);
-        long long p = lin(q.i, q.j, q.k, n);
-        ((float*)sf.b)[p] = (float)r;
-        r = fabs(r);
-        if (iter == 0) bb = fabs(b[p]);
-    }
-    bool last = seg_reduce_last(r, &c.res_bits, &c.red_cnt[2], seg_nblk(s64, nseg, si, nblk),
-                                iter == 0 ? &c.bn_bits : nullptr, bb);
-    if (last && threadIdx.x == 0) {
-        double rmax = bitsd(atomicAdd(&c.res_bits, 0ull));
-        if (iter == 0) c.bnorm = bitsd(atomicAdd(&c.bn_bits, 0ull));
-        double scale = c.bnorm > 0.0 ? c.bnorm : 1.0;
-        double rho = rmax / scale;
-        c.mg_rho = rho;
-        if (rho != rho || rmax > 1.7e308) {
-            finish_solve(c, iter, 2);
-            c.status = -4;
-        } else if (rho <= tol) {
-            finish_solve(c, iter, 1);
-        } else if (iter >= max_iter) {
-            finish_solve(c, iter, 2);
-            if (c.status == 0) c.status = -3;
+    struct Op {
+        const double* b;
+        float* r32;
+        double a;
+        int iter;
+        double rmax, bmax;
+        __device__ __forceinline__ void operator()(long long p, int, double c, double L)
+        {
+            double bp = b[p];
+            double r = bp - (c - a * L);
+            r32[p] = (float)r;
+            rmax = nmax(rmax, fabs(r));
+            if (iter == 0) bmax = nmax(bmax, fabs(bp));
         }
-        c.res_bits = 0ull;
-        c.bn_bits = 0ull;
-        c.red_cnt[2] = 0u;
+    } op{(const double*)sg.b, (float*)s32[si].b, lane_a(ctl, sg.lane, A.L, A.m), iter, 0.0, 0.0};
+    __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
+    lds_march<ORDER, double>(u, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX), q.z0,
+                             q.z1, pl, op);
+    double m = block_max(op.rmax);
+    double mb = block_max(op.bmax);
+    if (threadIdx.x == 0) {
+        partials[2 * lb] = m;
+        partials[2 * lb + 1] = mb;
     }
 }
 
@@ -637,11 +970,14 @@ __global__ void __launch_bounds__(HS_BLOCK) k_ir_update(const GridSeg* __restric
     const GridSeg sg = s64[si];
     if (ctl[sg.lane].mg_state != 0) return;
     int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
+    PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     if (!q.in) return;
     double* u = (double*)sg.u + (long long)A.node * sg.node_stride;
-    long long p = lin(q.i, q.j, q.k, n);
-    u[p] += (double)((const float*)s32[si].u)[p];
+    const float* e = (const float*)s32[si].u;
+    for (int z = q.z0; z < q.z1; z++) {
+        long long p = lin(q.i, q.j, z, n);
+        u[p] += (double)e[p];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -681,18 +1017,18 @@ __global__ void __launch_bounds__(HS_BLOCK) k_spread(const SdcSeg* __restrict__ 
 // Sweep-constant right-hand side parts, from iterate k before any update:
 //   P_m = dt sum_j S_mj (FI_j + g_j s) - dt_m FI_{m+1} + (tau_{m+1} - tau_m)
 // so that substep m solves A_{nu dt_m} U_{m+1} = U_m + P_m (eqs. (7)-(8)).
-// With with_resid it also forms the collocation residual
+// With with_resid it also writes per-block maxima of the collocation residual
 //   R = max_m |U_0 + dt sum_j Q_mj (FI_j + g_j s) + tau_m - U_m|
-// and applies the SDC stopping test.
+// for the SDC stopping test (k_sdc_decide).
 __global__ void __launch_bounds__(HS_BLOCK) k_sweep_prep(const SdcSeg* __restrict__ segs, int nseg,
-                                                         int nblk, LaneCtl* __restrict__ ctl,
-                                                         int with_resid, double sdc_tol,
-                                                         int max_sweeps, int gate)
+                                                         int nblk, const LaneCtl* __restrict__ ctl,
+                                                         int with_resid, int gate,
+                                                         double* __restrict__ partials)
 {
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(segs, nseg, lb);
     const SdcSeg sg = segs[si];
-    LaneCtl& c = ctl[sg.lane];
+    const LaneCtl& c = ctl[sg.lane];
     if (gate && c.sdc_state != 0) return;
     int n = sg.n, M = sg.M;
     Pos q = grid_pos(lb - sg.blk_begin, n);
@@ -726,9 +1062,58 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep_prep(const SdcSeg* __restric
         }
     }
     if (!with_resid) return;
-    bool last = seg_reduce_last(R, &c.sdc_bits, &c.red_cnt[1], seg_nblk(segs, nseg, si, nblk));
-    if (last && threadIdx.x == 0) {
-        double r = bitsd(atomicAdd(&c.sdc_bits, 0ull));
+    double m = block_max(R);
+    if (threadIdx.x == 0) partials[2 * lb] = m;
+}
+
+// Collocation residual alone (per-block maxima), for a check after a sweep
+__global__ void __launch_bounds__(HS_BLOCK) k_sdc_resid(const SdcSeg* __restrict__ segs, int nseg,
+                                                        int nblk, const LaneCtl* __restrict__ ctl,
+                                                        double* __restrict__ partials)
+{
+    int lb = xcd_remap(blockIdx.x, nblk);
+    int si = find_seg(segs, nseg, lb);
+    const SdcSeg sg = segs[si];
+    const LaneCtl& c = ctl[sg.lane];
+    if (c.sdc_state != 0) return;
+    int n = sg.n, M = sg.M;
+    Pos q = grid_pos(lb - sg.blk_begin, n);
+    const SdcConst& K = c_lc.sdc[M];
+    double R = 0.0;
+    if (q.in) {
+        long long N = (long long)n * n * n;
+        long long p = lin(q.i, q.j, q.k, n);
+        double s = sval(sg.sig, q.i, q.j, q.k);
+        double F[HS_MAXM];
+        for (int j = 0; j < M; j++) F[j] = sg.FI[j * N + p] + c.g[sg.level][j] * s;
+        double u0 = sg.U[p];
+        for (int m = 1; m < M; m++) {
+            double acc = 0.0;
+            for (int j = 0; j < M; j++) acc += K.Q[m][j] * F[j];
+            double v = u0 + c.dt * acc - sg.U[m * N + p];
+            if (sg.tau) v += sg.tau[m * N + p];
+            R = nmax(R, fabs(v));
+        }
+    }
+    double m = block_max(R);
+    if (threadIdx.x == 0) partials[2 * lb] = m;
+}
+
+// SDC stopping test, one block per lane: R from the lane's block maxima.
+__global__ void __launch_bounds__(HS_BLOCK) k_sdc_decide(const SdcSeg* __restrict__ segs, int nseg,
+                                                         int nblk, const double* __restrict__ partials,
+                                                         LaneCtl* __restrict__ ctl, double sdc_tol,
+                                                         int max_sweeps)
+{
+    int si = blockIdx.x;
+    const SdcSeg sg = segs[si];
+    LaneCtl& c = ctl[sg.lane];
+    if (c.sdc_state != 0) return;
+    int b0 = sg.blk_begin, nb = seg_nblk(segs, nseg, si, nblk);
+    double r = 0.0;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) r = nmax(r, partials[2 * (b0 + q)]);
+    r = block_max(r);
+    if (threadIdx.x == 0) {
         c.sdc_res = r;
         if (r != r || r > 1.7e308) {
             c.sdc_state = 2;
@@ -739,8 +1124,6 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep_prep(const SdcSeg* __restric
             c.sdc_state = 2;
             if (c.status == 0) c.status = -3;
         }
-        c.sdc_bits = 0ull;
-        c.red_cnt[1] = 0u;
     }
 }
 
@@ -937,53 +1320,6 @@ __global__ void __launch_bounds__(HS_BLOCK) k_fas_interp(const FasSeg* __restric
     }
 }
 
-// SDC residual and stopping test (for the tolerance-driven sweep count)
-__global__ void __launch_bounds__(HS_BLOCK) k_sdc_resid(const SdcSeg* __restrict__ segs, int nseg,
-                                                        int nblk, LaneCtl* __restrict__ ctl,
-                                                        double sdc_tol, int max_sweeps)
-{
-    int lb = xcd_remap(blockIdx.x, nblk);
-    int si = find_seg(segs, nseg, lb);
-    const SdcSeg sg = segs[si];
-    LaneCtl& c = ctl[sg.lane];
-    if (c.sdc_state != 0) return;
-    int n = sg.n, M = sg.M;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
-    const SdcConst& K = c_lc.sdc[M];
-    double R = 0.0;
-    if (q.in) {
-        long long N = (long long)n * n * n;
-        long long p = lin(q.i, q.j, q.k, n);
-        double s = sval(sg.sig, q.i, q.j, q.k);
-        double F[HS_MAXM];
-        for (int j = 0; j < M; j++) F[j] = sg.FI[j * N + p] + c.g[sg.level][j] * s;
-        double u0 = sg.U[p];
-        for (int m = 1; m < M; m++) {
-            double acc = 0.0;
-            for (int j = 0; j < M; j++) acc += K.Q[m][j] * F[j];
-            double v = u0 + c.dt * acc - sg.U[m * N + p];
-            if (sg.tau) v += sg.tau[m * N + p];
-            R = nmax(R, fabs(v));
-        }
-    }
-    bool last = seg_reduce_last(R, &c.sdc_bits, &c.red_cnt[1], seg_nblk(segs, nseg, si, nblk));
-    if (last && threadIdx.x == 0) {
-        double r = bitsd(atomicAdd(&c.sdc_bits, 0ull));
-        c.sdc_res = r;
-        if (r != r || r > 1.7e308) {
-            c.sdc_state = 2;
-            c.status = -4;
-        } else if (r <= sdc_tol) {
-            c.sdc_state = 1;
-        } else if (c.sweeps_step >= max_sweeps) {
-            c.sdc_state = 2;
-            if (c.status == 0) c.status = -3;
-        }
-        c.sdc_bits = 0ull;
-        c.red_cnt[1] = 0u;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Lane bookkeeping
 // ---------------------------------------------------------------------------
@@ -1136,36 +1472,74 @@ namespace hsk {
 static inline dim3 g1(int nblk) { return dim3((unsigned)nblk); }
 static const dim3 BLK(HS_BLOCK);
 
-int grid_blocks(int n) { return tiles_x(n) * tiles_y(n) * n; }
+int grid_blocks(int n, int zb) { return tiles_x(n) * tiles_y(n) * ((n + zb - 1) / zb); }
+
+// z planes per block of the plane-marching kernels: as many as possible (up
+// to 8, fewer halo reloads and window warm-ups) while one grid still gives
+// 2048 blocks (8 per CU) to fill the chip.
+int choose_zb(int n)
+{
+    long long tiles = (long long)tiles_x(n) * tiles_y(n);
+    int zb = 8;
+    while (zb > 1 && tiles * ((n + zb - 1) / zb) < 2048) zb /= 2;
+    return zb;
+}
+
+size_t tail_lds_bytes(int n0, int elem)
+{
+    size_t words = 0;
+    int n = n0;
+    bool top = true;
+    while (true) {
+        size_t N = (size_t)n * n * n;
+        words += (top ? 2 : 3) * N;
+        top = false;
+        if (n <= 1) break;
+        n = (n - 1) / 2;
+    }
+    return words * (size_t)elem;
+}
 
 hipError_t set_constants(const LibConst& lc)
 {
     return hipMemcpyToSymbol(HIP_SYMBOL(c_lc), &lc, sizeof(LibConst), 0, hipMemcpyHostToDevice);
 }
 
-#define HS_ORDER_DISPATCH(order, KERNEL2, KERNEL4, GRID, BLOCK, ...)                   \
-    do {                                                                               \
-        if ((order) == 2) hipLaunchKernelGGL(KERNEL2, GRID, BLOCK, 0, s, __VA_ARGS__); \
-        else hipLaunchKernelGGL(KERNEL4, GRID, BLOCK, 0, s, __VA_ARGS__);              \
+#define HS_ORDER_DISPATCH(order, KERNEL2, KERNEL4, GRID, BLOCK, SHMEM, ...)                 \
+    do {                                                                                    \
+        if ((order) == 2) hipLaunchKernelGGL(KERNEL2, GRID, BLOCK, SHMEM, s, __VA_ARGS__);  \
+        else hipLaunchKernelGGL(KERNEL4, GRID, BLOCK, SHMEM, s, __VA_ARGS__);               \
     } while (0)
 
-template <typename T>
-hipError_t jacobi(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                  int first_sweep, int src_is_t, hipStream_t s)
+template <typename T, int MODE, int FINEST, int NORM>
+static hipError_t sweep_launch(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order,
+                               MgArgs a, int first_sweep, int src_is_t, int cycle, double* partials,
+                               hipStream_t s)
 {
-    if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_jacobi<T, 2>), (k_jacobi<T, 4>), g1(nblk), BLK, segs, nseg, nblk,
-                      ctl, a, first_sweep, src_is_t);
+    HS_ORDER_DISPATCH(order, (k_sweep<T, 2, MODE, FINEST, NORM>), (k_sweep<T, 4, MODE, FINEST, NORM>),
+                      g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a, first_sweep, src_is_t, partials,
+                      cycle);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t resid_restrict(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order,
-                          MgArgs a, int src_is_t, hipStream_t s)
+hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
+                 int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
+                 double* partials, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_resid_restrict<T, 2>), (k_resid_restrict<T, 4>), g1(nblk), BLK,
-                      segs, nseg, nblk, ctl, a, src_is_t);
+    if (mode == 1) return sweep_launch<T, 1, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
+    if (norm) return sweep_launch<T, 0, 1, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s);
+    if (finest_only) return sweep_launch<T, 0, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
+    return sweep_launch<T, 0, 0, 0>(ctl, segs, nseg, nblk, order, a, first_sweep, src_is_t, 0, partials, s);
+}
+
+template <typename T>
+hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,
+                       hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_restrict_fw<T>), g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, a, r_is_t);
     return hipGetLastError();
 }
 
@@ -1181,38 +1555,47 @@ hipError_t prolong(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs
 
 template <typename T>
 hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a, int nu1, int nu2,
-                hipStream_t s)
+                size_t lds_bytes, hipStream_t s)
 {
     if (nseg <= 0) return hipSuccess;
     HS_ORDER_DISPATCH(order, (k_tail<T, 2>), (k_tail<T, 4>), dim3((unsigned)nseg),
-                      dim3(HS_TAIL_THREADS), segs, ctl, a, nu1, nu2);
+                      dim3(HS_TAIL_THREADS), (unsigned)lds_bytes, segs, ctl, a, nu1, nu2);
     return hipGetLastError();
 }
 
-template hipError_t jacobi<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, hipStream_t);
-template hipError_t jacobi<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, hipStream_t);
-template hipError_t resid_restrict<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
-template hipError_t resid_restrict<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
+template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t);
+template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t);
+template hipError_t restrict_fw<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
+template hipError_t restrict_fw<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
 template hipError_t prolong<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);
 template hipError_t prolong<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);
-template hipError_t tail<double>(LaneCtl*, const TailSeg*, int, int, MgArgs, int, int, hipStream_t);
-template hipError_t tail<float>(LaneCtl*, const TailSeg*, int, int, MgArgs, int, int, hipStream_t);
+template hipError_t tail<double>(LaneCtl*, const TailSeg*, int, int, MgArgs, int, int, size_t, hipStream_t);
+template hipError_t tail<float>(LaneCtl*, const TailSeg*, int, int, MgArgs, int, int, size_t, hipStream_t);
 
-hipError_t mg_norm(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                   int src_is_t, int cycle, double tol, int max_cycles, hipStream_t s)
+hipError_t mg_decide(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, const double* partials,
+                     int cycle, double tol, int max_cycles, hipStream_t s)
 {
-    if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mg_norm, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, a, order, src_is_t,
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mg_decide, dim3((unsigned)nseg), BLK, 0, s, segs, nseg, nblk, partials, ctl,
                        cycle, tol, max_cycles);
     return hipGetLastError();
 }
 
-hipError_t ir_resid(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32, int nseg, int nblk,
-                    int order, MgArgs a, int iter, double tol, int max_iter, hipStream_t s)
+hipError_t mg_norm(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
+                   int cycle, double* partials, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_ir_resid<2>), (k_ir_resid<4>), g1(nblk), BLK, segs64, segs32,
-                      nseg, nblk, ctl, a, iter, tol, max_iter);
+    HS_ORDER_DISPATCH(order, (k_mg_norm<2>), (k_mg_norm<4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
+                      a, cycle, partials);
+    return hipGetLastError();
+}
+
+hipError_t ir_resid(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32, int nseg, int nblk,
+                    int order, MgArgs a, int iter, double* partials, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    HS_ORDER_DISPATCH(order, (k_ir_resid<2>), (k_ir_resid<4>), g1(nblk), BLK, 0, segs64, segs32,
+                      nseg, nblk, ctl, a, iter, partials);
     return hipGetLastError();
 }
 
@@ -1228,17 +1611,26 @@ hipError_t spread(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int orde
                   hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_spread<2>), (k_spread<4>), g1(nblk), BLK, segs, nseg, nblk, ctl,
+    HS_ORDER_DISPATCH(order, (k_spread<2>), (k_spread<4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
                       src_node);
     return hipGetLastError();
 }
 
 hipError_t sweep_prep(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int with_resid,
-                      double sdc_tol, int max_sweeps, int gate, hipStream_t s)
+                      int gate, double* partials, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sweep_prep, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, with_resid,
-                       sdc_tol, max_sweeps, gate);
+    hipLaunchKernelGGL(k_sweep_prep, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, with_resid, gate,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t sdc_decide(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, const double* partials,
+                      double sdc_tol, int max_sweeps, hipStream_t s)
+{
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sdc_decide, dim3((unsigned)nseg), BLK, 0, s, segs, nseg, nblk, partials, ctl,
+                       sdc_tol, max_sweeps);
     return hipGetLastError();
 }
 
@@ -1254,7 +1646,7 @@ hipError_t f_update(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int or
                     int next_rhs, int gate, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_f_update<2>), (k_f_update<4>), g1(nblk), BLK, segs, nseg, nblk,
+    HS_ORDER_DISPATCH(order, (k_f_update<2>), (k_f_update<4>), g1(nblk), BLK, 0, segs, nseg, nblk,
                       ctl, node, next_rhs, gate);
     return hipGetLastError();
 }
@@ -1263,17 +1655,16 @@ hipError_t eval_fi_all(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int
                        hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_eval_fi_all<2>), (k_eval_fi_all<4>), g1(nblk), BLK, segs, nseg,
+    HS_ORDER_DISPATCH(order, (k_eval_fi_all<2>), (k_eval_fi_all<4>), g1(nblk), BLK, 0, segs, nseg,
                       nblk, ctl, gate);
     return hipGetLastError();
 }
 
-hipError_t sdc_resid(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, double sdc_tol,
-                     int max_sweeps, hipStream_t s)
+hipError_t sdc_resid(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, double* partials,
+                     hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sdc_resid, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, sdc_tol,
-                       max_sweeps);
+    hipLaunchKernelGGL(k_sdc_resid, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, partials);
     return hipGetLastError();
 }
 
@@ -1281,7 +1672,7 @@ hipError_t handoff(LaneCtl* ctl, const SdcSeg* dst, const SdcSeg* src, int nseg,
                    int order, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_handoff<2>), (k_handoff<4>), g1(nblk), BLK, dst, src, nseg, nblk,
+    HS_ORDER_DISPATCH(order, (k_handoff<2>), (k_handoff<4>), g1(nblk), BLK, 0, dst, src, nseg, nblk,
                       ctl);
     return hipGetLastError();
 }
@@ -1290,7 +1681,7 @@ hipError_t fas_restrict(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, in
                         hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(corder, (k_fas_restrict<2>), (k_fas_restrict<4>), g1(nblk), BLK, segs, nseg,
+    HS_ORDER_DISPATCH(corder, (k_fas_restrict<2>), (k_fas_restrict<4>), g1(nblk), BLK, 0, segs, nseg,
                       nblk, ctl, gate);
     return hipGetLastError();
 }
@@ -1362,7 +1753,7 @@ hipError_t lap_apply(const SdcSeg* segs, int nseg, int nblk, int order, double a
                      const double* u, double* y, const long long* offs, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_lap_apply<2>), (k_lap_apply<4>), g1(nblk), BLK, segs, nseg, nblk,
+    HS_ORDER_DISPATCH(order, (k_lap_apply<2>), (k_lap_apply<4>), g1(nblk), BLK, 0, segs, nseg, nblk,
                       alpha, beta, u, y, offs);
     return hipGetLastError();
 }
@@ -1372,7 +1763,7 @@ hipError_t heat_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int or
                     const long long* offs, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_heat_rhs<2>), (k_heat_rhs<4>), g1(nblk), BLK, segs, nseg, nblk,
+    HS_ORDER_DISPATCH(order, (k_heat_rhs<2>), (k_heat_rhs<4>), g1(nblk), BLK, 0, segs, nseg, nblk,
                       ctl, u, t, fi, fe, offs);
     return hipGetLastError();
 }

@@ -168,15 +168,18 @@ struct Table {
     std::vector<S> h;
     S* d = nullptr;
     int nblk = 0;
+    int finest = 0;     // grid tables: every segment is a finest grid
     int nseg() const { return (int)h.size(); }
 };
 
 // multigrid tables of one SDC level, one precision, one set of lanes
 struct MgSet {
     int D = 0;                            // down steps above the tail
-    std::vector<Table<GridSeg>> jac, rr, pro;
+    std::vector<Table<GridSeg>> jac, rr, pro;  // z-marching sweeps, restriction, prolongation
     Table<TailSeg> tail;
-    Table<GridSeg> fine;                  // finest grids (norms, refinement)
+    size_t tail_lds = 0;                  // LDS bytes of the tail kernel
+    Table<GridSeg> fine;                  // finest grids (norms, refinement), z-marching
+    int fused_norm = 0;                   // jac[0] holds every lane's finest grid
 };
 
 struct LaneSet {
@@ -217,6 +220,10 @@ struct hs_plan {
     Table<SdcSeg> hf_dst, hf_src;              // PFASST fine hand-off p-1 -> p
     std::vector<Table<SdcSeg>> hc_dst, hc_src; // PFASST coarse hand-off, per slice
     Table<long long> offs[2];                  // lane-major packing offsets per SDC level
+    Table<GridSeg> user;                       // hs_smooth on caller arrays
+    double* partials = nullptr;                // per-block maxima of the reductions
+    const void* user_key[3] = {nullptr, nullptr, nullptr};
+    int user_level = -1;
     double* d_times = nullptr;                 // per-lane times for hs_heat_rhs
     int cpred[2][HS_MAXM];                     // predicted cycles per (level, substep)
     int cpred_user = 0;
@@ -301,11 +308,16 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             grid_ptrs(lb, l + 1, &cu, &ct, &cb);
             g.cu = cu;
             g.cb = cb;
-            g.blk_begin = bj; bj += hsk::grid_blocks(g.n); S.jac[s].h.push_back(g);
+            g.zb = hsk::choose_zb(g.n);
+            g.blk_begin = bj; bj += hsk::grid_blocks(g.n, g.zb); S.jac[s].h.push_back(g);
+            g.zb = 1;
             g.blk_begin = br; br += hsk::grid_blocks(g.nc); S.rr[s].h.push_back(g);
             g.blk_begin = bp; bp += hsk::grid_blocks(g.n); S.pro[s].h.push_back(g);
         }
         S.jac[s].nblk = bj;
+        S.jac[s].finest = 1;
+        for (const GridSeg& g : S.jac[s].h)
+            if (g.coarse) S.jac[s].finest = 0;
         S.rr[s].nblk = br;
         S.pro[s].nblk = bp;
     }
@@ -325,6 +337,7 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             ts.u[q] = u; ts.t[q] = t; ts.b[q] = bb;
         }
         ts.coarse_table = ct_index(P->order[L], g.back());
+        S.tail_lds = std::max(S.tail_lds, hsk::tail_lds_bytes(g[Db], fp32 ? 4 : 8));
         ts.zero_guess = (Db > 0 || fp32) ? 1 : 0;
         ts.node_stride = (Db == 0 && !fp32) ? lb.N[L] : 0;
         S.tail.h.push_back(ts);
@@ -335,12 +348,14 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         f.nc = g.size() > 1 ? g[1] : 0;
         f.coarse = fp32 ? 1 : 0;
         f.node_stride = fp32 ? 0 : lb.N[L];
+        f.zb = hsk::choose_zb(f.n);
         grid_ptrs(lb, 0, &f.u, &f.t, &f.b);
         f.blk_begin = bf;
-        bf += hsk::grid_blocks(f.n);
+        bf += hsk::grid_blocks(f.n, f.zb);
         S.fine.h.push_back(f);
     }
     S.fine.nblk = bf;
+    S.fused_norm = (Dmax > 0 && S.jac[0].finest && S.jac[0].nseg() == (int)ls.lanes.size()) ? 1 : 0;
 }
 
 SdcSeg sdc_seg(hs_plan* P, int b, int L)
@@ -474,6 +489,9 @@ void layout(hs_plan* P, char* base)
         finish_table(P->offs[L], bump);
     }
     P->d_times = bump.arr<double>(P->B);
+    P->user.h.assign(P->B, GridSeg());
+    finish_table(P->user, bump);
+    P->user.h.clear();
     // lane sets
     P->all = LaneSet();
     for (int b = 0; b < P->B; b++) P->all.lanes.push_back(b);
@@ -512,6 +530,21 @@ void layout(hs_plan* P, char* base)
             finish_table(P->hc_src[p], bump);
         }
     }
+    // per-block maxima of the reductions: two doubles per block of the largest launch
+    int maxblk = 1;
+    auto upd = [&](int nb) { maxblk = std::max(maxblk, nb); };
+    auto scan = [&](const LaneSet& ls) {
+        for (int L = 0; L < P->nlev; L++) {
+            upd(ls.sdc[L].nblk);
+            for (const MgSet* S : {&ls.mg64[L], &ls.mg32[L]}) {
+                upd(S->fine.nblk);
+                for (auto& t : S->jac) upd(t.nblk);
+            }
+        }
+    };
+    scan(P->all);
+    for (auto& ls : P->single) scan(ls);
+    P->partials = bump.arr<double>(2 * (size_t)maxblk);
     P->bytes = (bump.off + 255) & ~(size_t)255;
 }
 
@@ -615,19 +648,24 @@ bool all_sdc_done(hs_plan* P, const LaneSet& ls)
     return true;
 }
 
-// One V(nu1,nu2) cycle over the tables of S.
+// One V(nu1,nu2) cycle over the tables of S.  first_done: the first
+// pre-smoothing sweep of step 0 has already run (fused with the norm).
 template <typename T>
 hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
-                 hipStream_t s)
+                 bool first_done, hipStream_t s)
 {
     for (int st = 0; st < S.D; st++) {
         const Table<GridSeg>& J = S.jac[st];
-        for (int k = 0; k < nu1; k++)
-            HS_TRY(hsk::jacobi<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, k == 0, k & 1, s));
+        for (int k = (st == 0 && first_done) ? 1 : 0; k < nu1; k++)
+            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, k == 0, k & 1, J.finest, 0, 0,
+                                 P->partials, s));
+        // residual into the free buffer, then full weighting
+        int in_t = nu1 & 1;
+        HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 1, 0, in_t, 1, 0, 0, P->partials, s));
         const Table<GridSeg>& R = S.rr[st];
-        HS_TRY(hsk::resid_restrict<T>(P->ctl, R.d, R.nseg(), R.nblk, order, A, nu1 & 1, s));
+        HS_TRY(hsk::restrict_fw<T>(P->ctl, R.d, R.nseg(), R.nblk, A, !in_t, s));
     }
-    HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, s));
+    HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, S.tail_lds, s));
     for (int st = S.D - 1; st >= 0; st--) {
         int in_t = nu1 & 1;
         int dst_t = ((nu1 + nu2) & 1) ? !in_t : in_t;
@@ -636,7 +674,8 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
         int cur = dst_t;
         const Table<GridSeg>& J = S.jac[st];
         for (int k = 0; k < nu2; k++) {
-            HS_TRY(hsk::jacobi<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, cur, s));
+            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
+                                 P->partials, s));
             cur = !cur;
         }
     }
@@ -655,13 +694,25 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     if (!P->mixed) {
         const MgSet& S = ls.mg64[L];
         if (mg.fixed_cycles > 0) {
-            for (int c = 0; c < mg.fixed_cycles; c++) HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, s));
+            for (int c = 0; c < mg.fixed_cycles; c++)
+                HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, false, s));
             HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
             return HS_OK;
         }
         for (int c = 0;; c++) {
-            HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, 0, c, mg.tol,
-                                mg.max_cycles, s));
+            // residual norm before cycle c; fused with cycle c's first sweep when possible
+            if (S.fused_norm) {
+                const Table<GridSeg>& J = S.jac[0];
+                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, 0, 1, 1, c,
+                                          P->partials, s));
+                HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, P->partials, c, mg.tol,
+                                      mg.max_cycles, s));
+            } else {
+                HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, c,
+                                    P->partials, s));
+                HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, P->partials, c,
+                                      mg.tol, mg.max_cycles, s));
+            }
             if (c >= pred || c >= mg.max_cycles) {
                 HS_CHECK(read_ctl(P, s));
                 if (synced) *synced = true;
@@ -672,7 +723,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                 }
             }
             if (c >= mg.max_cycles) break;
-            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, s));
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, S.fused_norm != 0, s));
         }
         return HS_OK;
     }
@@ -684,18 +735,22 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     for (int it = 0;; it++) {
         if (fixed && it >= limit) break;
         HS_TRY(hsk::ir_resid(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, order, A,
-                             it, fixed ? -1.0 : mg.tol, fixed ? (1 << 30) : limit, s));
-        if (!fixed && (it >= pred || it >= limit)) {
-            HS_CHECK(read_ctl(P, s));
-            if (synced) *synced = true;
-            int mc = 0;
-            if (all_mg_done(P, ls, &mc)) {
-                pred = mc;
-                break;
+                             it, P->partials, s));
+        if (!fixed) {
+            HS_TRY(hsk::mg_decide(P->ctl, S64.fine.d, S64.fine.nseg(), S64.fine.nblk, P->partials, it,
+                                  mg.tol, limit, s));
+            if (it >= pred || it >= limit) {
+                HS_CHECK(read_ctl(P, s));
+                if (synced) *synced = true;
+                int mc = 0;
+                if (all_mg_done(P, ls, &mc)) {
+                    pred = mc;
+                    break;
+                }
             }
+            if (it >= limit) break;
         }
-        if (!fixed && it >= limit) break;
-        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, s));
+        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, false, s));
         HS_TRY(hsk::ir_update(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, A, s));
     }
     if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, s));
@@ -712,9 +767,10 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
     const Table<SdcSeg>& T = ls.sdc[L];
     int M = P->M[L];
     *outcome = SWEEP_RAN;
-    HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, P->pb.sdc_tol,
-                           P->pb.max_sweeps, 1, s));
+    HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, 1, P->partials, s));
     if (with_resid) {
+        HS_TRY(hsk::sdc_decide(P->ctl, T.d, T.nseg(), T.nblk, P->partials, P->pb.sdc_tol,
+                               P->pb.max_sweeps, s));
         HS_CHECK(read_ctl(P, s));
         if (all_sdc_done(P, ls)) {
             *outcome = SWEEP_DONE;
@@ -1000,6 +1056,54 @@ hs_status hs_mg_vcycle(hs_plan* P, int32_t level, const double* h_a, double* d_u
     return (hs_status)worst;
 }
 
+hs_status hs_smooth(hs_plan* P, int32_t level, const double* h_a, double* d_u, const double* d_b,
+                    double* d_tmp, int32_t nsweeps, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (level < 0 || level >= P->nlev || !h_a || !d_u || !d_b || !d_tmp || nsweeps < 0)
+        return HS_EINVAL;
+    for (int b = 0; b < P->B; b++)
+        if (!(h_a[b] >= 0.0) || !std::isfinite(h_a[b])) return HS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (P->user_key[0] != d_u || P->user_key[1] != d_b || P->user_key[2] != d_tmp ||
+        P->user_level != level) {
+        P->user.h.clear();
+        int bk = 0;
+        for (int b = 0; b < P->B; b++) {
+            const LaneBufs& lb = P->lanes[b];
+            long long o = P->offs[level].h[b];
+            GridSeg g;
+            std::memset(&g, 0, sizeof(g));
+            g.lane = b;
+            g.n = lb.n[level];
+            g.u = d_u + o;
+            g.t = d_tmp + o;
+            g.b = (void*)(d_b + o);
+            g.zb = hsk::choose_zb(g.n);
+            g.blk_begin = bk;
+            bk += hsk::grid_blocks(g.n, g.zb);
+            P->user.h.push_back(g);
+        }
+        P->user.nblk = bk;
+        HS_TRY(upload(P->user, s));
+        P->user_key[0] = d_u; P->user_key[1] = d_b; P->user_key[2] = d_tmp;
+        P->user_level = level;
+    }
+    for (int b = 0; b < P->B; b++) HS_TRY(hsk::set_a_user(P->ctl, b, h_a[b], s));
+    hsk::MgArgs A{level, -1, P->pb.mg.omega, 0, 0};
+    const Table<GridSeg>& T = P->user;
+    for (int k = 0; k < nsweeps; k++)
+        HS_TRY(hsk::sweep<double>(P->ctl, T.d, T.nseg(), T.nblk, P->order[level], A, 0, 0, k & 1, 1, 0, 0,
+                                  P->partials, s));
+    if (nsweeps & 1)
+        for (int b = 0; b < P->B; b++) {
+            long long o = P->offs[level].h[b];
+            HS_TRY(hipMemcpyAsync(d_u + o, d_tmp + o, P->lanes[b].N[level] * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+        }
+    return HS_OK;
+}
+
 hs_status hs_set_state(hs_plan* P, const double* d_u0, void* stream)
 {
     HS_CHECK(check_bound(P));
@@ -1019,6 +1123,28 @@ hs_status hs_set_state(hs_plan* P, const double* d_u0, void* stream)
         HS_TRY(hsk::set_lane(P->ctl, b, P->pb.nu, P->pb.dt, t0, P->pb.forcing_c, (int)nsteps, 1, s));
     }
     P->state_ready = 1;
+    return HS_OK;
+}
+
+hs_status hs_set_lane_state(hs_plan* P, int32_t lane, const double* d_u0, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (lane < 0 || lane >= P->B || !d_u0 || P->pb.nslices > 1) return HS_EINVAL;
+    const LaneBufs& lb = P->lanes[lane];
+    int M = P->M[0];
+    HS_TRY(hipMemcpyAsync(lb.U[0] + (M - 1) * lb.N[0], d_u0, lb.N[0] * sizeof(double),
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return HS_OK;
+}
+
+hs_status hs_get_lane_state(hs_plan* P, int32_t lane, double* d_u, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (lane < 0 || lane >= P->B || !d_u || P->pb.nslices > 1) return HS_EINVAL;
+    const LaneBufs& lb = P->lanes[lane];
+    int M = P->M[0];
+    HS_TRY(hipMemcpyAsync(d_u, lb.U[0] + (M - 1) * lb.N[0], lb.N[0] * sizeof(double),
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return HS_OK;
 }
 

@@ -53,6 +53,18 @@ class LaneStats(C.Structure):
                 ("last_rho", C.c_double), ("last_sdc_res", C.c_double)]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("order", C.c_int32), ("nnodes", C.c_int32), ("mg", MgDesc), ("sweeps", C.c_int32),
+                ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("forcing_c", C.c_double),
+                ("nclasses", C.c_int32), ("class_n", C.c_int32 * 8), ("class_slots", C.c_int32 * 8)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("cls", C.c_int32), ("lane", C.c_int32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("stats", LaneStats)]
+
+
 _lib = None
 _V = C.c_void_p
 _P = C.POINTER
@@ -81,6 +93,7 @@ def lib():
         "hs_lap_apply": [_V, C.c_int32, C.c_double, C.c_double, _V, _V, _V],
         "hs_heat_rhs": [_V, C.c_int32, _V, _V, _V, _V, _V],
         "hs_mg_vcycle": [_V, C.c_int32, _V, _V, _V, _V],
+        "hs_smooth": [_V, C.c_int32, _V, _V, _V, _V, C.c_int32, _V],
         "hs_set_state": [_V, _V, _V],
         "hs_get_state": [_V, _V, _V],
         "hs_get_nodes": [_V, C.c_int32, _V, _V, _V, _V, _V],
@@ -96,6 +109,15 @@ def lib():
         "hs_pfasst_run": [_V, _V],
         "hs_solve_graph": [_V, _V],
         "hs_stats_read": [_V, _V, _V],
+        "hs_set_lane_state": [_V, C.c_int32, _V, _V],
+        "hs_get_lane_state": [_V, C.c_int32, _V, _V],
+        "hs_server_pool_bytes": [_P(ServerDesc), _P(C.c_size_t)],
+        "hs_server_create": [_P(ServerDesc), _V, C.c_size_t, C.c_size_t, _P(_V)],
+        "hs_server_submit": [_V, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, _V, _V,
+                             _P(C.c_uint64)],
+        "hs_server_poll": [_V, C.c_uint64, _P(RequestInfo)],
+        "hs_server_drain": [_V],
+        "hs_server_destroy": [_V],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -259,10 +281,24 @@ class Plan:
         s = lib().hs_mg_vcycle(self._h, level, C.cast(aa, _V), _ptr(u), _ptr(b), self._s())
         return check(s, "hs_mg_vcycle", allow=(HS_ENOCONV,) if allow_noconv else ())
 
+    def smooth(self, u, b, tmp, a, nsweeps, level=0):
+        aa = (C.c_double * self.lanes)(*([a] * self.lanes if np.isscalar(a) else list(a)))
+        check(lib().hs_smooth(self._h, level, C.cast(aa, _V), _ptr(u), _ptr(b), _ptr(tmp), nsweeps,
+                              self._s()), "hs_smooth")
+
     # state and nodes ----------------------------------------------------
     def set_lane(self, lane, nu, dt, t0, nsteps, active=True):
         check(lib().hs_set_lane(self._h, lane, nu, dt, t0, nsteps, 1 if active else 0, self._s()),
               "hs_set_lane")
+
+    def set_lane_state(self, lane, u0):
+        check(lib().hs_set_lane_state(self._h, lane, _ptr(u0), self._s()), "hs_set_lane_state")
+
+    def get_lane_state(self, lane):
+        import torch
+        out = torch.empty(self.lane_n[lane] ** 3, dtype=torch.float64, device="cuda")
+        check(lib().hs_get_lane_state(self._h, lane, _ptr(out), self._s()), "hs_get_lane_state")
+        return out
 
     def set_state(self, u0):
         check(lib().hs_set_state(self._h, _ptr(u0), self._s()), "hs_set_state")

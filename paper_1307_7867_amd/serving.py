@@ -1,0 +1,163 @@
+"""Python driver of the serving core (hs_server_* in libheatst).
+
+The admission, slot management and continuous batching live in the C++
+core; this module owns the device pool (a torch allocation), keeps request
+tensors alive while the core uses them, sizes the slot classes from an HBM
+budget, and replays a Poisson arrival stream to measure latency and
+throughput.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import heatst as hs
+
+
+def lane_bytes(n, order=2, nnodes=5, precision=hs.HS_MIXED, **kw) -> int:
+    """Device bytes one lane (one resident request) of grid n needs."""
+    p = hs.Problem(n=n, order=order, nnodes=nnodes, precision=precision, **kw)
+    return p.workspace_bytes()
+
+
+def slots_for_budget(budget_bytes: int, sizes, weights, order=2, nnodes=5, precision=hs.HS_MIXED,
+                     max_slots=64, **kw) -> dict:
+    """Slots per grid-size class: every class gets one slot, then slots are
+    handed out in proportion to arrival weight x per-request work (n^3), as
+    long as the budget allows."""
+    per = {n: lane_bytes(n, order, nnodes, precision, **kw) for n in sizes}
+    slots = {n: 1 for n in sizes}
+    used = sum(per.values())
+    if used > budget_bytes:
+        raise ValueError("budget below one slot per class")
+    demand = {n: w * float(n) ** 3 for n, w in zip(sizes, weights)}
+    while True:
+        # class whose slots are most oversubscribed relative to its demand
+        cand = sorted(sizes, key=lambda n: slots[n] / demand[n])
+        grown = False
+        for n in cand:
+            if slots[n] < max_slots and used + per[n] <= budget_bytes:
+                slots[n] += 1
+                used += per[n]
+                grown = True
+                break
+        if not grown:
+            return slots
+
+
+class Server:
+    """Continuous-batching server for independent heat solves on one GPU."""
+
+    def __init__(self, slots: dict, order=2, nnodes=5, precision=hs.HS_MIXED, tol=1e-10,
+                 max_cycles=60, inner=(2, 2), nu1=2, nu2=1, sweeps=0, sdc_tol=1e-10, max_sweeps=40,
+                 forcing_c=3.0, budget_bytes=None):
+        import torch
+        L = hs.lib()
+        d = hs.ServerDesc()
+        d.order, d.nnodes = order, nnodes
+        d.mg = hs.MgDesc(nu1, nu2, 6.0 / 7.0, 3, tol, max_cycles, 0, precision, inner[0], inner[1])
+        d.sweeps, d.sdc_tol, d.max_sweeps, d.forcing_c = sweeps, sdc_tol, max_sweeps, forcing_c
+        items = sorted(slots.items())
+        d.nclasses = len(items)
+        for i, (n, s) in enumerate(items):
+            d.class_n[i] = n
+            d.class_slots[i] = s
+        need = C.c_size_t(0)
+        hs.check(L.hs_server_pool_bytes(C.byref(d), C.byref(need)), "hs_server_pool_bytes")
+        self.pool_bytes = need.value
+        self.pool = torch.empty(self.pool_bytes + 256, dtype=torch.uint8, device="cuda")
+        base = (self.pool.data_ptr() + 255) & ~255
+        self._h = C.c_void_p()
+        budget = budget_bytes if budget_bytes is not None else self.pool_bytes
+        hs.check(L.hs_server_create(C.byref(d), C.c_void_p(base), self.pool_bytes, budget,
+                                    C.byref(self._h)), "hs_server_create")
+        self.slots = dict(items)
+        self._keep = {}
+
+    def submit(self, n, nu, dt, nsteps, u0, t0=0.0):
+        import torch
+        u0 = u0.contiguous()
+        out = torch.empty_like(u0)
+        # the core reads u0 on its own streams: finish torch's pending work on it first
+        torch.cuda.current_stream().synchronize()
+        tk = C.c_uint64(0)
+        hs.check(hs.lib().hs_server_submit(self._h, n, nu, dt, t0, nsteps, C.c_void_p(u0.data_ptr()),
+                                           C.c_void_p(out.data_ptr()), C.byref(tk)), "hs_server_submit")
+        self._keep[tk.value] = (u0, out)
+        return tk.value
+
+    def poll(self, ticket):
+        info = hs.RequestInfo()
+        s = hs.lib().hs_server_poll(self._h, ticket, C.byref(info))
+        hs.check(s, "hs_server_poll")
+        return s == hs.HS_OK, info
+
+    def result(self, ticket):
+        return self._keep[ticket][1]
+
+    def release(self, ticket):
+        self._keep.pop(ticket, None)
+
+    def drain(self):
+        hs.check(hs.lib().hs_server_drain(self._h), "hs_server_drain")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            hs.lib().hs_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class StreamResult:
+    n_requests: int
+    wall_s: float
+    solves_per_s: float
+    p50_s: float
+    p99_s: float
+    mean_s: float
+    dof_updates: float
+
+
+def replay(server: Server, requests, u0_of, time_scale=1.0, keep_results=False):
+    """Submit `requests` (inputs.Request) at their arrival times (scaled) and
+    wait for all; latency = completion - arrival."""
+    t_start = time.perf_counter()
+    tickets = []
+    for r in requests:
+        due = t_start + r.arrival * time_scale
+        while True:
+            dtw = due - time.perf_counter()
+            if dtw <= 0:
+                break
+            time.sleep(min(dtw, 0.002))
+        t_arr = time.perf_counter()
+        tk = server.submit(r.n, r.nu, r.dt, r.nsteps, u0_of(r))
+        tickets.append((tk, r, t_arr))
+    server.drain()
+    t_end = time.perf_counter()
+    lat, infos = [], []
+    dof = 0.0
+    for tk, r, t_arr in tickets:
+        done, info = server.poll(tk)
+        assert done
+        infos.append(info)
+        dof += float(r.n) ** 3 * r.nsteps
+    # completion times from the core's clock, arrival from ours: use the core's
+    # submit stamp (taken inside submit) as the arrival
+    lat = np.array([i.t_done - i.t_submit for i in infos])
+    if not keep_results:
+        for tk, _, _ in tickets:
+            server.release(tk)
+    wall = t_end - t_start
+    res = StreamResult(len(requests), wall, len(requests) / wall, float(np.percentile(lat, 50)),
+                       float(np.percentile(lat, 99)), float(lat.mean()), dof)
+    return res, tickets, infos

@@ -216,7 +216,7 @@ def test_sdc_tolerance_mode_parity(torch):
     hs = heatst_mod()
     n = 15
     pb = hs.Problem(n=n, order=4, nnodes=5, nu=0.1, dt=0.05, nsteps=2, sweeps=0, sdc_tol=1e-10,
-                    max_sweeps=20, tol=1e-12)
+                    max_sweeps=40, tol=1e-12)
     plan = hs.Plan(pb)
     u0 = inputs.random_smooth(n, 2)
     plan.set_state(dev(torch, u0))
@@ -224,7 +224,7 @@ def test_sdc_tolerance_mode_parity(torch):
     got = host(plan.get_state()).reshape(n, n, n)
     st, stats = plan.stats()
     ref, s, ost = oracle.run(oracle.problem([(n, 4, 5)], nu=0.1, dt=0.05, nsteps=2, sweeps=0,
-                                            sdc_tol=1e-10, max_sweeps=20,
+                                            sdc_tol=1e-10, max_sweeps=40,
                                             mg=oracle.mg_params(tol=1e-12)), u0)
     assert s == oracle.OK and st == 0
     assert stats[0]["total_sweeps"] == ost.total_sweeps

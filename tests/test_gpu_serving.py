@@ -1,0 +1,82 @@
+"""Serving core on the GPU: every request's result in the mix equals the
+same request solved alone (bitwise: each lane takes its own decisions), and
+agrees with the FP64 oracle within the mixed-precision tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_7867_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def make_requests(count, seed, sizes):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        reqs.append(dict(n=int(rng.choice(sizes)), nu=float(rng.uniform(0.05, 0.2)),
+                         dt=float(rng.uniform(0.005, 0.05)), nsteps=int(rng.integers(1, 4)),
+                         seed=int(rng.integers(0, 1 << 30))))
+    return reqs
+
+
+def alone(torch, hs, r, precision):
+    plan = hs.Plan(hs.Problem(n=r["n"], order=2, nnodes=5, nu=r["nu"], dt=r["dt"], nsteps=r["nsteps"],
+                              sweeps=0, sdc_tol=1e-10, max_sweeps=40, precision=precision, tol=1e-12,
+                              max_cycles=60))
+    plan.set_state(torch.from_numpy(inputs.random_smooth(r["n"], r["seed"]).ravel()).cuda())
+    plan.solve()
+    return plan.get_state().cpu().numpy()
+
+
+def test_serving_mix_equals_alone_and_oracle(torch):
+    from paper_1307_7867_amd import heatst as hs
+    from paper_1307_7867_amd import serving
+    # refinement to 1e-12 relative residual so that the SDC threshold 1e-10 is reachable
+    srv = serving.Server({15: 2, 31: 3, 63: 2}, precision=hs.HS_MIXED, tol=1e-12, sdc_tol=1e-10,
+                         max_sweeps=40)
+    reqs = make_requests(10, 5, (15, 31, 63))
+    tickets = []
+    for r in reqs:
+        u0 = torch.from_numpy(inputs.random_smooth(r["n"], r["seed"]).ravel()).cuda()
+        tickets.append(srv.submit(r["n"], r["nu"], r["dt"], r["nsteps"], u0))
+    srv.drain()
+    for tk, r in zip(tickets, reqs):
+        done, info = srv.poll(tk)
+        assert done and info.status == 0
+        got = srv.result(tk).cpu().numpy()
+        ref = alone(torch, hs, r, hs.HS_MIXED)
+        assert np.array_equal(got, ref), r
+        if r["n"] <= 31:
+            n = r["n"]
+            o, s, _ = oracle.run(oracle.problem([(n, 2, 5)], nu=r["nu"], dt=r["dt"], nsteps=r["nsteps"],
+                                                sweeps=0, sdc_tol=1e-10, max_sweeps=40,
+                                                mg=oracle.mg_params(tol=1e-13, max_cycles=200)),
+                                 inputs.random_smooth(n, r["seed"]))
+            assert s == oracle.OK
+            err = np.abs(got.reshape(n, n, n) - o).max() / np.abs(o).max()
+            assert err <= 1e-9, (r, err)
+    srv.close()
+
+
+def test_serving_queues_when_slots_are_full(torch):
+    from paper_1307_7867_amd import heatst as hs
+    from paper_1307_7867_amd import serving
+    srv = serving.Server({15: 1}, precision=hs.HS_FP64, tol=1e-12, sdc_tol=1e-10)
+    u0 = torch.from_numpy(inputs.sine_product(15).ravel()).cuda()
+    tks = [srv.submit(15, 0.1, 0.02, 2, u0) for _ in range(3)]
+    srv.drain()
+    infos = [srv.poll(t)[1] for t in tks]
+    for a, b in zip(infos, infos[1:]):
+        assert b.t_admit >= a.t_done - 1e-6
+    outs = [srv.result(t).cpu().numpy() for t in tks]
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    srv.close()
