@@ -17,7 +17,7 @@ value = space-time DOF-updates/s = 127^3 * (5 - 1) substeps * 3 iterations
         * K / elapsed.
 
 roofline: the dominant kernel, the finest-grid weighted-Jacobi sweep
-(k_jacobi<double, 4, 1> on 127^3), timed with HIP events on its own stream
+(k_sweep<double, 4, 0, 1, 0> on 127^3), timed with HIP events on its stream
 (one launch per sweep, the solver's launch configuration); algorithmic
 bytes 24 per grid point (read u, b; write u').
 
@@ -104,6 +104,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm511", action="store_true", help="skip the 511^3 Jacobi measurement")
+    ap.add_argument("--workload", default="mlsdc127",
+                    choices=["mlsdc127", "mixed255", "pfasst16", "uneven64", "serving"],
+                    help="mlsdc127 (default): the headline two-level MLSDC run; the others are the "
+                         "mixed-precision, PFASST-slice, uneven-batch and serving workloads")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sdc-tol", type=float, default=1e-9)
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rates", default="0.5,1.0,1.5")
+    ap.add_argument("--max-n", type=int, default=511)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run a plain 512 MiB device copy (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -117,6 +129,18 @@ def main():
     from paper_1307_7867_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.calibration_copy:
+        src = torch.ones(64 * 2**20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload != "mlsdc127":
+        from paper_1307_7867_amd import workloads
+        out = getattr(workloads, args.workload)(args)
+        print(json.dumps(out), flush=True)
+        return
     pb = problem(hs)
     plan = hs.Plan(pb)
     u0 = torch.from_numpy(inputs.sine_product(NF).ravel()).cuda()
@@ -182,7 +206,7 @@ def main():
                                "V(2,1) Jacobi 6/7 to 3^3, rel. residual 1e-12",
                    "fine_n": NF, "coarse_n": NC, "dt": pb.dt, "iterations_per_step": ITERS,
                    "mg_tol": pb.tol},
-        "roofline": {"bound": "hbm", "kernel": "k_jacobi<double,4,1> on 127^3",
+        "roofline": {"bound": "hbm", "kernel": "k_sweep<double, 4, 0, 1, 0> (finest-grid weighted Jacobi) on 127^3",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "us_per_launch": jac_s * 1e6, "algorithmic_bytes_per_launch": jac_bytes},

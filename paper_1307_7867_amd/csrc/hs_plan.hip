@@ -216,6 +216,16 @@ struct hs_plan {
     LaneCtl* h_ctl = nullptr;                  // pinned copy for read-backs
     std::vector<LaneBufs> lanes;
     LaneSet all;
+    LaneSet run;                               // the active lanes (what a step launches over)
+    std::vector<int> active;                   // host view of every lane's active flag
+    bool run_dirty = true;
+    // device storage for the run set's tables, room for every lane in each
+    struct RunStore {
+        std::vector<GridSeg*> grid[2][2];      // [level][fp32]: jac/rr/pro per step, then fine
+        TailSeg* tail[2][2];
+        SdcSeg* sdc[2];
+        FasSeg *fasc, *fasf;
+    } store;
     std::vector<LaneSet> single;               // PFASST coarse pipeline, one lane each
     Table<SdcSeg> hf_dst, hf_src;              // PFASST fine hand-off p-1 -> p
     std::vector<Table<SdcSeg>> hc_dst, hc_src; // PFASST coarse hand-off, per slice
@@ -374,7 +384,8 @@ SdcSeg sdc_seg(hs_plan* P, int b, int L)
     return s;
 }
 
-void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
+// Host contents of every table of the lanes in ls.lanes.
+void build_set_host(hs_plan* P, LaneSet& ls)
 {
     for (int L = 0; L < P->nlev; L++) {
         int bk = 0;
@@ -411,6 +422,11 @@ void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
         ls.fasc.nblk = bc;
         ls.fasf.nblk = bf;
     }
+}
+
+void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
+{
+    build_set_host(P, ls);
     // device storage of every table
     for (int L = 0; L < P->nlev; L++) {
         finish_table(ls.sdc[L], bump);
@@ -496,6 +512,20 @@ void layout(hs_plan* P, char* base)
     P->all = LaneSet();
     for (int b = 0; b < P->B; b++) P->all.lanes.push_back(b);
     build_set(P, P->all, bump);
+    // run set storage: every table can hold all lanes
+    for (int L = 0; L < P->nlev; L++) {
+        for (int f = 0; f < 2; f++) {
+            const MgSet& S = f ? P->all.mg32[L] : P->all.mg64[L];
+            P->store.grid[L][f].clear();
+            for (int t = 0; t < 3 * S.D + 1; t++) P->store.grid[L][f].push_back(bump.arr<GridSeg>(P->B));
+            P->store.tail[L][f] = bump.arr<TailSeg>(P->B);
+        }
+        P->store.sdc[L] = bump.arr<SdcSeg>(P->B);
+    }
+    P->store.fasc = bump.arr<FasSeg>(P->B);
+    P->store.fasf = bump.arr<FasSeg>(P->B);
+    P->active.assign(P->B, 1);
+    P->run_dirty = true;
     P->single.clear();
     P->hf_dst = Table<SdcSeg>();
     P->hf_src = Table<SdcSeg>();
@@ -798,10 +828,49 @@ hs_status mlsdc_iter(hs_plan* P, LaneSet& ls, bool with_resid, hipStream_t s, in
     return HS_OK;
 }
 
+// Rebuild the run set's tables for the lanes currently active and upload
+// them (synchronous with respect to the host; ordered on stream s).
+hs_status refresh_run(hs_plan* P, hipStream_t s)
+{
+    if (!P->run_dirty) return HS_OK;
+    LaneSet& ls = P->run;
+    ls = LaneSet();
+    for (int b = 0; b < P->B; b++)
+        if (P->active[b]) ls.lanes.push_back(b);
+    build_set_host(P, ls);
+    for (int L = 0; L < P->nlev; L++) {
+        for (int f = 0; f < 2; f++) {
+            MgSet& S = f ? ls.mg32[L] : ls.mg64[L];
+            const MgSet& A = f ? P->all.mg32[L] : P->all.mg64[L];
+            // the run set never holds deeper lanes than the full set
+            if (S.D > A.D) return HS_ESTATE;
+            for (int st = 0; st < S.D; st++) {
+                S.jac[st].d = P->store.grid[L][f][3 * st];
+                S.rr[st].d = P->store.grid[L][f][3 * st + 1];
+                S.pro[st].d = P->store.grid[L][f][3 * st + 2];
+            }
+            S.fine.d = P->store.grid[L][f][3 * A.D];
+            S.tail.d = P->store.tail[L][f];
+            if (S.fine.h.empty()) S.fine.d = nullptr;
+            if (S.tail.h.empty()) S.tail.d = nullptr;
+        }
+        ls.sdc[L].d = ls.sdc[L].h.empty() ? nullptr : P->store.sdc[L];
+    }
+    if (P->nlev == 2) {
+        ls.fasc.d = ls.fasc.h.empty() ? nullptr : P->store.fasc;
+        ls.fasf.d = ls.fasf.h.empty() ? nullptr : P->store.fasf;
+    }
+    HS_TRY(upload_set(P, ls, s));
+    HS_TRY(hipStreamSynchronize(s));
+    P->run_dirty = false;
+    return HS_OK;
+}
+
 hs_status begin_step(hs_plan* P, hipStream_t s)
 {
+    HS_CHECK(refresh_run(P, s));
     HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M[0], P->nlev > 1 ? P->M[1] : P->M[0], s));
-    const Table<SdcSeg>& T = P->all.sdc[0];
+    const Table<SdcSeg>& T = P->run.sdc[0];
     HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[0], P->M[0] - 1, s));
     return HS_OK;
 }
@@ -811,15 +880,20 @@ hs_status step(hs_plan* P, hipStream_t s)
     HS_CHECK(begin_step(P, s));
     const hs_problem& pb = P->pb;
     int outcome;
+    LaneSet& ls = P->run;
+    if (ls.lanes.empty()) {
+        HS_TRY(hsk::end_step(P->ctl, P->B, s));
+        return HS_OK;
+    }
     if (pb.sweeps > 0) {
         for (int k = 0; k < pb.sweeps; k++) {
-            if (P->nlev == 1) HS_CHECK(sweep(P, P->all, 0, false, true, s, &outcome));
-            else HS_CHECK(mlsdc_iter(P, P->all, false, s, &outcome));
+            if (P->nlev == 1) HS_CHECK(sweep(P, ls, 0, false, true, s, &outcome));
+            else HS_CHECK(mlsdc_iter(P, ls, false, s, &outcome));
         }
     } else {
         for (int k = 0; k <= pb.max_sweeps + 1; k++) {
-            if (P->nlev == 1) HS_CHECK(sweep(P, P->all, 0, true, true, s, &outcome));
-            else HS_CHECK(mlsdc_iter(P, P->all, true, s, &outcome));
+            if (P->nlev == 1) HS_CHECK(sweep(P, ls, 0, true, true, s, &outcome));
+            else HS_CHECK(mlsdc_iter(P, ls, true, s, &outcome));
             if (outcome == SWEEP_DONE) break;
         }
     }
@@ -992,6 +1066,10 @@ hs_status hs_set_lane(hs_plan* P, int32_t lane, double nu, double dt, double t0,
         return HS_EINVAL;
     HS_TRY(hsk::set_lane(P->ctl, lane, nu, dt, t0, P->pb.forcing_c, nsteps, active ? 1 : 0,
                          (hipStream_t)stream));
+    if (P->active[lane] != (active ? 1 : 0)) {
+        P->active[lane] = active ? 1 : 0;
+        P->run_dirty = true;
+    }
     return HS_OK;
 }
 
@@ -1213,14 +1291,16 @@ hs_status hs_sdc_sweep(hs_plan* P, int32_t level, void* stream)
     HS_CHECK(check_bound(P));
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
     int outcome;
-    return sweep(P, P->all, level, false, level == 0, (hipStream_t)stream, &outcome);
+    HS_CHECK(refresh_run(P, (hipStream_t)stream));
+    return sweep(P, P->run, level, false, level == 0, (hipStream_t)stream, &outcome);
 }
 
 hs_status hs_fas_restrict(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
     if (P->nlev != 2) return HS_EINVAL;
-    LaneSet& ls = P->all;
+    HS_CHECK(refresh_run(P, (hipStream_t)stream));
+    LaneSet& ls = P->run;
     HS_TRY(hsk::fas_restrict(P->ctl, ls.fasc.d, ls.fasc.nseg(), ls.fasc.nblk, P->order[1], 1,
                              (hipStream_t)stream));
     return HS_OK;
@@ -1230,8 +1310,9 @@ hs_status hs_fas_interp(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
     if (P->nlev != 2) return HS_EINVAL;
-    LaneSet& ls = P->all;
     hipStream_t s = (hipStream_t)stream;
+    HS_CHECK(refresh_run(P, s));
+    LaneSet& ls = P->run;
     HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
     HS_TRY(hsk::eval_fi_all(P->ctl, ls.sdc[0].d, ls.sdc[0].nseg(), ls.sdc[0].nblk, P->order[0], 1, s));
     return HS_OK;
@@ -1242,7 +1323,8 @@ hs_status hs_mlsdc_iter(hs_plan* P, void* stream)
     HS_CHECK(check_bound(P));
     if (P->nlev != 2) return HS_EINVAL;
     int outcome;
-    return mlsdc_iter(P, P->all, false, (hipStream_t)stream, &outcome);
+    HS_CHECK(refresh_run(P, (hipStream_t)stream));
+    return mlsdc_iter(P, P->run, false, (hipStream_t)stream, &outcome);
 }
 
 hs_status hs_end_step(hs_plan* P, void* stream)
@@ -1273,19 +1355,23 @@ hs_status hs_solve_graph(hs_plan* P, void* stream)
     HS_CHECK(check_bound(P));
     if (P->pb.nslices > 1 || P->pb.sweeps <= 0 || P->pb.mg.fixed_cycles <= 0) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    // table uploads are not allowed inside a capture: bring them up to date first
+    HS_CHECK(refresh_run(P, s));
     if (!P->gexec) {
         HS_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hs_status st = step(P, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
-        if (st != HS_OK) {
+        if (st != HS_OK || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
-            return st;
+            (void)hipGetLastError();
+            return st != HS_OK ? st : HS_EDEVICE;
         }
         HS_TRY(e);
         P->graph = g;
         HS_TRY(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
     }
+    if (P->run_dirty) return HS_ESTATE;   // lanes changed since the graph was captured
     for (int k = 0; k < P->pb.nsteps; k++) HS_TRY(hipGraphLaunch(P->gexec, s));
     return HS_OK;
 }

@@ -23,23 +23,36 @@ def lane_bytes(n, order=2, nnodes=5, precision=hs.HS_MIXED, **kw) -> int:
     return p.workspace_bytes()
 
 
+def slot_cap(n: int) -> int:
+    """Most lanes worth batching for grid n.  Small grids are bound by launch
+    latency and gain from batching; from 255^3 on one lane saturates HBM and
+    more resident lanes only push its coarse grids out of the Infinity Cache,
+    so those classes get one lane and queue."""
+    if n <= 31:
+        return 64
+    if n <= 63:
+        return 32
+    if n <= 127:
+        return 8
+    return 1
+
+
 def slots_for_budget(budget_bytes: int, sizes, weights, order=2, nnodes=5, precision=hs.HS_MIXED,
-                     max_slots=64, **kw) -> dict:
+                     cap=slot_cap, **kw) -> dict:
     """Slots per grid-size class: every class gets one slot, then slots are
-    handed out in proportion to arrival weight x per-request work (n^3), as
-    long as the budget allows."""
+    handed out in proportion to the arrival weights (the share of requests of
+    each size) up to each class's cap, while the budget allows."""
     per = {n: lane_bytes(n, order, nnodes, precision, **kw) for n in sizes}
+    wt = dict(zip(sizes, weights))
     slots = {n: 1 for n in sizes}
     used = sum(per.values())
     if used > budget_bytes:
         raise ValueError("budget below one slot per class")
-    demand = {n: w * float(n) ** 3 for n, w in zip(sizes, weights)}
     while True:
-        # class whose slots are most oversubscribed relative to its demand
-        cand = sorted(sizes, key=lambda n: slots[n] / demand[n])
+        cand = sorted(sizes, key=lambda n: slots[n] / wt[n])
         grown = False
         for n in cand:
-            if slots[n] < max_slots and used + per[n] <= budget_bytes:
+            if slots[n] < cap(n) and used + per[n] <= budget_bytes:
                 slots[n] += 1
                 used += per[n]
                 grown = True

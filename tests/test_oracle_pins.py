@@ -534,3 +534,16 @@ def test_pfasst_few_iterations_differs_from_serial():
     pb2 = two_level(nf=7, nsteps=P, sweeps=30, dt=0.05)
     v, _, _ = oracle.pfasst_run(pb2, P, u0)
     assert np.abs(u - v).max() > 1e-9
+
+
+def test_collocation_reference_matches_converged_oracle_sdc():
+    """The per-mode collocation reference (oracle/collocation.py) equals many
+    SDC sweeps of the 3-D oracle on sine-mode data (two steps)."""
+    from oracle import collocation as col
+    n, order, M, nu, dt = 7, 4, 5, 0.1, 0.05
+    modes = [(1, 2, 3, 0.8), (2, 2, 1, -0.4), (1, 1, 1, 0.3)]
+    u0 = inputs.modes_field(n, modes)
+    pb = oracle.problem([(n, order, M)], nu=nu, dt=dt, nsteps=2, sweeps=60, mg=TIGHT)
+    u, st, _ = oracle.run(pb, u0)
+    ref = col.field(n, col.coefficients(n, order, M, nu, 0.0, dt, 2, modes))
+    assert np.abs(u - ref).max() < 1e-12

@@ -58,5 +58,6 @@ def test_slots_for_budget_respects_budget_and_weights():
     used = sum(slots[n] * serving.lane_bytes(n) for n in sizes)
     assert used <= budget
     assert all(slots[n] >= 1 for n in sizes)
-    # the largest class cannot grow by one more slot
-    assert used + serving.lane_bytes(127) > budget or slots[127] == 64
+    # every class is at its cap or the budget is exhausted for it
+    for n in sizes:
+        assert slots[n] == serving.slot_cap(n) or used + serving.lane_bytes(n) > budget
