@@ -547,3 +547,13 @@ def test_collocation_reference_matches_converged_oracle_sdc():
     u, st, _ = oracle.run(pb, u0)
     ref = col.field(n, col.coefficients(n, order, M, nu, 0.0, dt, 2, modes))
     assert np.abs(u - ref).max() < 1e-12
+
+
+def test_collocation_inverse_bound():
+    """max over z <= 0 of ||(I - z Q)^{-1}|| on the 4 unknown nodes (5 nodes)."""
+    Q = oracle.collocation_matrix(5)
+    worst = 0.0
+    for z in -np.logspace(-4, 6, 400):
+        Ai = np.linalg.inv((np.eye(5) - z * Q)[1:, 1:])
+        worst = max(worst, np.abs(Ai).sum(1).max())
+    assert worst <= 1.7
