@@ -609,76 +609,92 @@ __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict_
 // global memory).
 // ---------------------------------------------------------------------------
 
-// Point `q` of this thread on an n^3 tail grid (n <= 15): 16 lanes per x row,
-// 64 rows j + n k per pass, passes q = 0..TAIL_Q-1.  k = row / n is taken in
-// float, exact for rows < 256 (the fraction j / n stays below 1 - 1/16).
-constexpr int TAIL_Q = (HS_TAIL_N * HS_TAIL_N + 63) / 64;
-
-__device__ __forceinline__ bool tail_pt(int n, float inv_n, int q, int& i, int& j, int& k, int& p)
+// Sizes of the tail grids: level l of a tail whose top grid has n0 points
+// per axis, and the LDS offset (in elements) of level l.  Level 0 holds the
+// ping-pong pair X, Y (its right-hand side lives in registers); every lower
+// level holds X, Y and its right-hand side B.
+constexpr int tail_n(int n0, int l) { return ((n0 + 1) >> l) - 1; }
+constexpr int tail_cube(int n) { return n * n * n; }
+constexpr int tail_off(int n0, int l)
 {
-    int r = 64 * q + (int)(threadIdx.x >> 4);
+    int o = 0;
+    for (int q = 0; q < l; q++) o += (q == 0 ? 2 : 3) * tail_cube(tail_n(n0, q));
+    return o;
+}
+
+// The 1024 threads cover an N^3 tail grid in passes of 64 x rows, 16 threads
+// per row (N <= 15); tail_pt gives the point of this thread in pass q.
+template <int N>
+constexpr int tail_q() { return (N * N + 63) / 64; }
+
+template <int N>
+__device__ __forceinline__ bool tail_pt(int q, int& i, int& j, int& k, int& p)
+{
+    const int r = 64 * q + (int)(threadIdx.x >> 4);
     i = (int)(threadIdx.x & 15);
-    if (i >= n || r >= n * n) return false;
-    k = (int)((float)r * inv_n + 1e-3f);
-    j = r - k * n;
-    p = r * n + i;
+    if (i >= N || r >= N * N) return false;
+    k = r / N;
+    j = r - k * N;
+    p = r * N + i;
     return true;
 }
 
-// one weighted-Jacobi sweep (zero: from a zero guess) on a tail grid in LDS;
-// the right-hand side comes from registers (bv, top grid) or LDS (b);
+// one weighted-Jacobi sweep (zero: from a zero guess) on an N^3 tail grid in
+// LDS; the right-hand side comes from registers (bv, top grid) or LDS (b);
 // rd[w] = omega / D for a point next to w walls (D = diagonal of A_a)
-template <typename T, int ORDER, bool REG>
-__device__ __forceinline__ void lds_jacobi(const T* src, T* dst, const T* b, const T* bv, int n, T a,
+template <typename T, int ORDER, int N, bool REG>
+__device__ __forceinline__ void lds_jacobi(const T* src, T* dst, const T* b, const T* bv, T a,
                                            const T* rd, bool zero)
 {
-    const T sc = lap_scale<ORDER, T>(n);
-    const float inv_n = 1.0f / (float)n;
+    const T sc = lap_scale<ORDER, T>(N);
 #pragma unroll
-    for (int q = 0; q < TAIL_Q; q++) {
+    for (int q = 0; q < tail_q<N>(); q++) {
         int i, j, k, p;
-        if (!tail_pt(n, inv_n, q, i, j, k, p)) continue;
-        T bp = REG ? bv[q] : b[p];
-        int walls = ORDER == 2 ? 0 : (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
-        T r = rd[walls];
+        if (!tail_pt<N>(q, i, j, k, p)) continue;
+        const T bp = REG ? bv[q] : b[p];
+        const int walls =
+            ORDER == 2 ? 0 : (i == 0) + (i == N - 1) + (j == 0) + (j == N - 1) + (k == 0) + (k == N - 1);
+        const T r = rd[walls];
         if (zero) {
             dst[p] = r * bp;
         } else {
-            T c = src[p];
-            T Au = c - a * (sc * lap_at<ORDER, T>(src, p, i, j, k, n, c));
+            const T c = src[p];
+            const T Au = c - a * (sc * lap_at<ORDER, T>(src, p, i, j, k, N, c));
             dst[p] = c + r * (bp - Au);
         }
     }
 }
 
-template <typename T, int ORDER, bool REG>
-__device__ __forceinline__ void lds_resid(const T* u, const T* b, const T* bv, T* r, int n, T a)
+template <typename T, int ORDER, int N, bool REG>
+__device__ __forceinline__ void lds_resid(const T* u, const T* b, const T* bv, T* r, T a)
 {
-    const T sc = lap_scale<ORDER, T>(n);
-    const float inv_n = 1.0f / (float)n;
+    const T sc = lap_scale<ORDER, T>(N);
 #pragma unroll
-    for (int q = 0; q < TAIL_Q; q++) {
+    for (int q = 0; q < tail_q<N>(); q++) {
         int i, j, k, p;
-        if (!tail_pt(n, inv_n, q, i, j, k, p)) continue;
-        T c = u[p];
-        r[p] = (REG ? bv[q] : b[p]) - (c - a * (sc * lap_at<ORDER, T>(u, p, i, j, k, n, c)));
+        if (!tail_pt<N>(q, i, j, k, p)) continue;
+        const T c = u[p];
+        r[p] = (REG ? bv[q] : b[p]) - (c - a * (sc * lap_at<ORDER, T>(u, p, i, j, k, N, c)));
     }
 }
 
-template <typename T>
-__device__ void lds_restrict(const T* r, T* cb, int n)
+// full weighting of the N^3 residual r onto the coarse right-hand side cb
+template <typename T, int N>
+__device__ __forceinline__ void lds_restrict(const T* r, T* cb)
 {
-    int nc = (n - 1) / 2;
-    int Nc = nc * nc * nc;
+    constexpr int nc = (N - 1) / 2;
+    constexpr int Nc = nc * nc * nc;
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    for (int p = threadIdx.x; p < Nc; p += blockDim.x) {
-        int I = p % nc, J = (p / nc) % nc, K = p / (nc * nc);
-        const T* c = r + lin(2 * I + 1, 2 * J + 1, 2 * K + 1, n);
+    for (int p = threadIdx.x; p < Nc; p += HS_TAIL_THREADS) {
+        const int I = p % nc, J = (p / nc) % nc, K = p / (nc * nc);
+        const T* c = r + lin(2 * I + 1, 2 * J + 1, 2 * K + 1, N);
         T acc = T(0);
+#pragma unroll
         for (int dz = -1; dz <= 1; dz++) {
             T az = T(0);
+#pragma unroll
             for (int dy = -1; dy <= 1; dy++) {
-                const T* row = c + dz * n * n + dy * n;
+                const T* row = c + dz * N * N + dy * N;
                 T ay = (w[0] * row[-1] + w[1] * row[0]) + w[2] * row[1];
                 az += w[dy + 1] * ay;
             }
@@ -688,144 +704,221 @@ __device__ void lds_restrict(const T* r, T* cb, int n)
     }
 }
 
-template <typename T>
-__device__ void lds_prolong_add(T* u, const T* c, int n)
+// u += P c on an N^3 tail grid
+template <typename T, int N>
+__device__ __forceinline__ void lds_prolong_add(T* u, const T* c)
 {
-    int nc = (n - 1) / 2;
-    int N = n * n * n;
-    for (int p = threadIdx.x; p < N; p += blockDim.x) {
-        int i = p % n, j = (p / n) % n, k = p / (n * n);
-        u[p] += prolong_at<T>(c, nc, i, j, k);
+#pragma unroll
+    for (int q = 0; q < tail_q<N>(); q++) {
+        int i, j, k, p;
+        if (!tail_pt<N>(q, i, j, k, p)) continue;
+        u[p] += prolong_at<T>(c, (N - 1) / 2, i, j, k);
     }
 }
 
-// exact solve on a grid of n = 1 or 3 points per axis by the sine transform
-template <typename T>
-__device__ void lds_exact(const T* b, T* x, int n, T a, const CoarseTable& ct)
+// Exact solve on the coarsest grid (N = 1 or 3 points per axis) by the sine
+// transform: x = S diag(1 / (1 - a (lam_i + lam_j + lam_k))) S b with the
+// orthonormal, symmetric 1-D transform S and the 1-D eigenvalues lam (both
+// staged in LDS); bh is LDS scratch of N^3 values.
+template <typename T, int N>
+__device__ __forceinline__ void lds_exact(const T* b, T* x, T a, const double* S, const double* lam,
+                                          double* bh)
 {
-    __shared__ double bh[27];
-    int N = n * n * n;
-    int p = threadIdx.x;
-    if (p < N) {
-        int pi = p % n, pj = (p / n) % n, pk = p / (n * n);
+    constexpr int NN = N * N * N;
+    const int p = threadIdx.x;
+    if (p < NN) {
+        const int pi = p % N, pj = (p / N) % N, pk = p / (N * N);
+        double si[N], sj[N], sk[N];
+#pragma unroll
+        for (int q = 0; q < N; q++) {
+            si[q] = S[pi * 3 + q];
+            sj[q] = S[pj * 3 + q];
+            sk[q] = S[pk * 3 + q];
+        }
         double s = 0.0;
-        for (int k = 0; k < n; k++)
-            for (int j = 0; j < n; j++)
-                for (int i = 0; i < n; i++)
-                    s += ct.S[pk][k] * ct.S[pj][j] * ct.S[pi][i] * (double)b[(k * n + j) * n + i];
-        double mu = 1.0 - (double)a * (ct.lam[pi] + ct.lam[pj] + ct.lam[pk]);
+#pragma unroll
+        for (int k = 0; k < N; k++)
+#pragma unroll
+            for (int j = 0; j < N; j++)
+#pragma unroll
+                for (int i = 0; i < N; i++)
+                    s += sk[k] * sj[j] * si[i] * (double)b[(k * N + j) * N + i];
+        const double mu = 1.0 - (double)a * (lam[pi] + lam[pj] + lam[pk]);
         bh[p] = s / mu;
     }
     __syncthreads();
-    if (p < N) {
-        int i = p % n, j = (p / n) % n, k = p / (n * n);
+    if (p < NN) {
+        const int i = p % N, j = (p / N) % N, k = p / (N * N);
+        double ci[N], cj[N], ck[N];
+#pragma unroll
+        for (int q = 0; q < N; q++) {
+            ci[q] = S[q * 3 + i];
+            cj[q] = S[q * 3 + j];
+            ck[q] = S[q * 3 + k];
+        }
         double s = 0.0;
-        for (int pk = 0; pk < n; pk++)
-            for (int pj = 0; pj < n; pj++)
-                for (int pi = 0; pi < n; pi++)
-                    s += ct.S[pk][k] * ct.S[pj][j] * ct.S[pi][i] * bh[(pk * n + pj) * n + pi];
+#pragma unroll
+        for (int pk = 0; pk < N; pk++)
+#pragma unroll
+            for (int pj = 0; pj < N; pj++)
+#pragma unroll
+                for (int pi = 0; pi < N; pi++)
+                    s += ck[pk] * cj[pj] * ci[pi] * bh[(pk * N + pj) * N + pi];
         x[p] = T(s);
     }
     __syncthreads();
 }
 
-// One V(nu1,nu2) cycle over the tail grids of one lane, in LDS.  Level 0
-// starts from the iterate in global memory (or from zero when the tail top
-// is a correction grid), the lower levels from zero; the result is written
-// back to level 0's iterate.  LDS layout: level 0: x0, y0 (ping-pong);
-// levels l >= 1: x_l, y_l, b_l.
+// Shared state of one tail V-cycle.
+template <typename T>
+struct TailCtx {
+    T* base;               // LDS grids
+    const T* b0;           // right-hand side of the top grid, in registers (pass q -> b0[q])
+    T a;
+    const T (*rd)[8];      // omega / D per level and wall count
+    int nu1, nu2;
+    bool zero_top;         // the top grid starts from zero
+    const double* S;       // exact-solve transform and eigenvalues
+    const double* lam;
+    double* bh;
+    unsigned in_y;         // bit l: level l's iterate sits in Y(l)
+};
+
+// V(nu1, nu2) from level L down to the coarsest level LAST of a tail whose top
+// grid has N0 points per axis; every grid size is a compile-time constant.
+template <typename T, int ORDER, int N0, int L, int LAST>
+struct TailV {
+    static constexpr int n = tail_n(N0, L);
+    static constexpr int nc = tail_n(N0, L + 1);
+    __device__ static __forceinline__ void run(TailCtx<T>& c)
+    {
+        T* X = c.base + tail_off(N0, L);
+        T* Y = X + tail_cube(n);
+        const T* B = L == 0 ? nullptr : Y + tail_cube(n);
+        T* Xc = c.base + tail_off(N0, L + 1);
+        T* Yc = Xc + tail_cube(nc);
+        T* Bc = Yc + tail_cube(nc);
+        const bool zero = L > 0 || c.zero_top;
+        for (int s = 0; s < c.nu1; s++) {
+            const bool iy = (c.in_y >> L) & 1u;
+            lds_jacobi<T, ORDER, n, L == 0>(iy ? Y : X, iy ? X : Y, B, c.b0, c.a, c.rd[L], zero && s == 0);
+            c.in_y ^= 1u << L;
+            __syncthreads();
+        }
+        {
+            const bool iy = (c.in_y >> L) & 1u;
+            T* r = iy ? X : Y;
+            lds_resid<T, ORDER, n, L == 0>(iy ? Y : X, B, c.b0, r, c.a);
+            __syncthreads();
+            lds_restrict<T, n>(r, Bc);
+            __syncthreads();
+        }
+        TailV<T, ORDER, N0, L + 1, LAST>::run(c);
+        {
+            const bool iy = (c.in_y >> L) & 1u;
+            lds_prolong_add<T, n>(iy ? Y : X, ((c.in_y >> (L + 1)) & 1u) ? Yc : Xc);
+            __syncthreads();
+        }
+        for (int s = 0; s < c.nu2; s++) {
+            const bool iy = (c.in_y >> L) & 1u;
+            lds_jacobi<T, ORDER, n, L == 0>(iy ? Y : X, iy ? X : Y, B, c.b0, c.a, c.rd[L], false);
+            c.in_y ^= 1u << L;
+            __syncthreads();
+        }
+    }
+};
+
+template <typename T, int ORDER, int N0, int LAST>
+struct TailV<T, ORDER, N0, LAST, LAST> {
+    static constexpr int n = tail_n(N0, LAST);
+    __device__ static __forceinline__ void run(TailCtx<T>& c)
+    {
+        T* X = c.base + tail_off(N0, LAST);
+        lds_exact<T, n>(X + 2 * tail_cube(n), X, c.a, c.S, c.lam, c.bh);
+        c.in_y &= ~(1u << LAST);
+    }
+};
+
+// One V-cycle over the NLEV tail grids of one lane, top grid N0^3: level 0
+// starts from the iterate in global memory (or from zero when the top is a
+// correction grid), the lower levels from zero; the result is written back
+// to level 0's iterate.  A single-grid tail is just the exact solve.
+template <typename T, int ORDER, int N0, int NLEV>
+__device__ __forceinline__ void tail_run(TailCtx<T>& c, T* gu0, const T* gb0)
+{
+    constexpr int N0c = tail_cube(N0);
+    if constexpr (NLEV == 1) {
+        __syncthreads();
+        lds_exact<T, N0>(gb0, c.base, c.a, c.S, c.lam, c.bh);
+        for (int p = threadIdx.x; p < N0c; p += HS_TAIL_THREADS) gu0[p] = c.base[p];
+    } else {
+        T b0[tail_q<N0>()];
+#pragma unroll
+        for (int q = 0; q < tail_q<N0>(); q++) {
+            int i, j, k, p;
+            b0[q] = tail_pt<N0>(q, i, j, k, p) ? gb0[p] : T(0);
+        }
+        if (!c.zero_top)
+            for (int p = threadIdx.x; p < N0c; p += HS_TAIL_THREADS) c.base[p] = gu0[p];
+        __syncthreads();
+        c.b0 = b0;
+        c.in_y = 0;
+        TailV<T, ORDER, N0, 0, NLEV - 1>::run(c);
+        const T* res = (c.in_y & 1u) ? c.base + N0c : c.base;
+        for (int p = threadIdx.x; p < N0c; p += HS_TAIL_THREADS) gu0[p] = res[p];
+    }
+}
+
 template <typename T, int ORDER>
 __global__ void __launch_bounds__(HS_TAIL_THREADS) k_tail(const TailSeg* __restrict__ segs,
                                                           const LaneCtl* __restrict__ ctl,
                                                           hsk::MgArgs A, int nu1, int nu2)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ T s_rd[HS_MAXTAIL][8];
+    __shared__ double s_S[9], s_lam[3], s_bh[27];
     const TailSeg& ts = segs[blockIdx.x];
     if (A.gate && ctl[ts.lane].mg_state != 0) return;
-    const T a = T(lane_a(ctl, ts.lane, A.L, A.m));
-    const T om = T(A.omega);
+    const int n0 = ts.n[0];
     const int nlev = ts.nlev;
-    const int last = nlev - 1;
+    const T a = T(lane_a(ctl, ts.lane, A.L, A.m));
+    const int t = (int)threadIdx.x;
+    if (t < nlev * 7) {
+        const int l = t / 7, w = t % 7;
+        const int nl = ts.n[l];
+        const T ih2 = T((double)(nl + 1) * (double)(nl + 1));
+        const T D = ORDER == 2 ? T(1) + a * ih2 * T(6) : T(1) + a * ih2 * (T(90 - w) / T(12));
+        s_rd[l][w] = T(A.omega) / D;
+    } else if (t >= 64 && t < 64 + 12) {
+        const CoarseTable& ct = c_lc.ct[ts.coarse_table];
+        if (t < 64 + 9) s_S[t - 64] = ct.S[(t - 64) / 3][(t - 64) % 3];
+        else s_lam[t - 73] = ct.lam[t - 73];
+    }
+    TailCtx<T> c;
+    c.base = (T*)smem;
+    c.b0 = nullptr;
+    c.a = a;
+    c.rd = s_rd;
+    c.nu1 = nu1;
+    c.nu2 = nu2;
+    c.zero_top = ts.zero_guess != 0;
+    c.S = s_S;
+    c.lam = s_lam;
+    c.bh = s_bh;
+    c.in_y = 0;
     T* gu0 = (T*)ts.u[0] + (long long)A.node * ts.node_stride;
     const T* gb0 = (const T*)ts.b[0];
-    // LDS layout: level 0: X, Y; levels l >= 1: X, Y, B (n_l^3 each)
-    T* base = (T*)smem;
-    auto offs = [&](int l) {
-        int o = 0;
-        for (int q = 0; q < l; q++) o += (q == 0 ? 2 : 3) * ts.n[q] * ts.n[q] * ts.n[q];
-        return o;
-    };
-    auto X = [&](int l) { return base + offs(l); };
-    auto Y = [&](int l) { return base + offs(l) + ts.n[l] * ts.n[l] * ts.n[l]; };
-    auto Bv = [&](int l) { return base + offs(l) + 2 * ts.n[l] * ts.n[l] * ts.n[l]; };
-    const int n0 = ts.n[0];
-    const int N0 = n0 * n0 * n0;
-    __shared__ T s_rd[HS_MAXTAIL][8];
-    if ((int)threadIdx.x < nlev * 7) {
-        int l = threadIdx.x / 7, w = threadIdx.x % 7;
-        int nl = ts.n[l];
-        T ih2 = T((double)(nl + 1) * (double)(nl + 1));
-        T D = ORDER == 2 ? T(1) + a * ih2 * T(6) : T(1) + a * ih2 * (T(90 - w) / T(12));
-        s_rd[l][w] = om / D;
+    // the plan only builds tails of these shapes (top 2^k - 1 <= 15 down to 3 or 1)
+    switch (n0 * 8 + nlev) {
+    case 15 * 8 + 3: tail_run<T, ORDER, 15, 3>(c, gu0, gb0); break;
+    case 15 * 8 + 4: tail_run<T, ORDER, 15, 4>(c, gu0, gb0); break;
+    case 7 * 8 + 2: tail_run<T, ORDER, 7, 2>(c, gu0, gb0); break;
+    case 7 * 8 + 3: tail_run<T, ORDER, 7, 3>(c, gu0, gb0); break;
+    case 3 * 8 + 1: tail_run<T, ORDER, 3, 1>(c, gu0, gb0); break;
+    case 3 * 8 + 2: tail_run<T, ORDER, 3, 2>(c, gu0, gb0); break;
+    case 1 * 8 + 1: tail_run<T, ORDER, 1, 1>(c, gu0, gb0); break;
+    default: break;
     }
-    T b0[TAIL_Q];
-    {
-        const float inv_n = 1.0f / (float)n0;
-#pragma unroll
-        for (int q = 0; q < TAIL_Q; q++) {
-            int i, j, k, p;
-            b0[q] = tail_pt(n0, inv_n, q, i, j, k, p) ? gb0[p] : T(0);
-        }
-    }
-    if (!ts.zero_guess)
-        for (int p = threadIdx.x; p < N0; p += blockDim.x) X(0)[p] = gu0[p];
-    __syncthreads();
-    unsigned in_y = 0;   // bit l: level l's iterate sits in Y(l)
-    for (int l = 0; l < last; l++) {
-        const int n = ts.n[l];
-        const bool zero = (l > 0) || ts.zero_guess;
-        for (int s = 0; s < nu1; s++) {
-            bool iy = (in_y >> l) & 1;
-            T* src = iy ? Y(l) : X(l);
-            T* dst = iy ? X(l) : Y(l);
-            if (l == 0) lds_jacobi<T, ORDER, true>(src, dst, nullptr, b0, n, a, s_rd[0], zero && s == 0);
-            else lds_jacobi<T, ORDER, false>(src, dst, Bv(l), nullptr, n, a, s_rd[l], zero && s == 0);
-            in_y ^= 1u << l;
-            __syncthreads();
-        }
-        bool iy = (in_y >> l) & 1;
-        T* x = iy ? Y(l) : X(l);
-        T* r = iy ? X(l) : Y(l);
-        if (l == 0) lds_resid<T, ORDER, true>(x, nullptr, b0, r, n, a);
-        else lds_resid<T, ORDER, false>(x, Bv(l), nullptr, r, n, a);
-        __syncthreads();
-        lds_restrict<T>(r, Bv(l + 1), n);
-        __syncthreads();
-    }
-    if (last == 0) {
-        // single-grid tail: the exact solve reads the right-hand side from memory
-        lds_exact<T>(gb0, X(0), ts.n[0], a, c_lc.ct[ts.coarse_table]);
-    } else {
-        lds_exact<T>(Bv(last), X(last), ts.n[last], a, c_lc.ct[ts.coarse_table]);
-    }
-    for (int l = last - 1; l >= 0; l--) {
-        const int n = ts.n[l];
-        bool iy = (in_y >> l) & 1;
-        const T* coarse = ((in_y >> (l + 1)) & 1) ? Y(l + 1) : X(l + 1);
-        lds_prolong_add<T>(iy ? Y(l) : X(l), coarse, n);
-        __syncthreads();
-        for (int s = 0; s < nu2; s++) {
-            iy = (in_y >> l) & 1;
-            T* src = iy ? Y(l) : X(l);
-            T* dst = iy ? X(l) : Y(l);
-            if (l == 0) lds_jacobi<T, ORDER, true>(src, dst, nullptr, b0, n, a, s_rd[0], false);
-            else lds_jacobi<T, ORDER, false>(src, dst, Bv(l), nullptr, n, a, s_rd[l], false);
-            in_y ^= 1u << l;
-            __syncthreads();
-        }
-    }
-    const T* res = ((in_y & 1u) ? Y(0) : X(0));
-    for (int p = threadIdx.x; p < N0; p += blockDim.x) gu0[p] = res[p];
 }
 
 // ---------------------------------------------------------------------------
