@@ -163,10 +163,13 @@ hipError_t set_constants(const LibConst& lc);
 // Weighted-Jacobi sweep (mode 0) or residual r = b - A x written to the free
 // buffer (mode 1) over a z-marching table.  norm: also write per-block
 // maxima of |b - A x| (and |b| when cycle == 0) to partials (FP64 only).
+// src (mode 0 only): 0 = x is the buffer picked by src_is_t; 1 = x is the
+// zero-guess first sweep omega D^{-1} b formed on the fly.
 template <typename T>
 hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                  int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
-                 double* partials, hipStream_t s);
+                 double* partials, hipStream_t s, int src = 0);
+
 // full weighting of the residual held in the buffer selected by r_is_t
 template <typename T>
 hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,

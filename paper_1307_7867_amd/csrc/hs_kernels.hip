@@ -323,6 +323,78 @@ __device__ __forceinline__ void zmarch(const T* __restrict__ src, int n, int i, 
     }
 }
 
+// trilinear interpolation of a coarse field at fine point (i,j,k); walls 0.
+// Per axis a fine index either coincides with coarse (i-1)/2 (weight 1) or
+// lies between coarse i/2-1 and i/2 (weights 1/2, missing ones are walls).
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ c, int nc, int i, int j, int k)
+{
+    int ix0, ix1, iy0, iy1, iz0, iz1;
+    T wx, wy, wz;
+    if (i & 1) { ix0 = ix1 = (i - 1) >> 1; wx = T(1); } else { ix0 = (i >> 1) - 1; ix1 = i >> 1; wx = T(0.5); }
+    if (j & 1) { iy0 = iy1 = (j - 1) >> 1; wy = T(1); } else { iy0 = (j >> 1) - 1; iy1 = j >> 1; wy = T(0.5); }
+    if (k & 1) { iz0 = iz1 = (k - 1) >> 1; wz = T(1); } else { iz0 = (k >> 1) - 1; iz1 = k >> 1; wz = T(0.5); }
+    const bool two_x = !(i & 1), two_y = !(j & 1), two_z = !(k & 1);
+    const bool vx0 = ix0 >= 0, vx1 = two_x && ix1 < nc;
+    const bool vy0 = iy0 >= 0, vy1 = two_y && iy1 < nc;
+    const bool vz0 = iz0 >= 0, vz1 = two_z && iz1 < nc;
+    const int sy = nc, sz = nc * nc;
+    T s = T(0);
+#pragma unroll
+    for (int cz = 0; cz < 2; cz++) {
+        const bool vz = cz ? vz1 : vz0;
+        if (!vz) continue;
+        const int oz = (cz ? iz1 : iz0) * sz;
+        T sy_ = T(0);
+#pragma unroll
+        for (int cy = 0; cy < 2; cy++) {
+            const bool vy = cy ? vy1 : vy0;
+            if (!vy) continue;
+            const int o = oz + (cy ? iy1 : iy0) * sy;
+            T sx = T(0);
+            if (vx0) sx += c[o + ix0];
+            if (vx1) sx += c[o + ix1];
+            sy_ += wx * sx;
+        }
+        s += wy * sy_;
+    }
+    return wz * s;
+}
+
+// Sources of the plane march: the value of the field the stencil is applied
+// to at grid point (i, j, z), linear index p.
+template <typename T>
+struct SrcPlain {
+    const T* __restrict__ u;
+    __device__ __forceinline__ T at(long long p, int, int, int) const { return u[p]; }
+};
+
+// The first weighted-Jacobi sweep from a zero guess, omega D^{-1} b,
+// evaluated where it is read instead of being stored.
+template <typename T, int ORDER>
+struct SrcZeroJacobi {
+    const T* __restrict__ b;
+    T a, om;
+    int n;
+    __device__ __forceinline__ T at(long long p, int i, int j, int z) const
+    {
+        return om * b[p] / diag_A<ORDER, T>(a, i, j, z, n);
+    }
+};
+
+// value of the source at column (i, j), plane z' with the wall rules of the
+// stencil along z (pij = j n + i)
+template <int ORDER, typename T, class Src>
+__device__ __forceinline__ T zval_src(const Src& S, int i, int j, int z, int n, long long nn, long long pij)
+{
+    if (z >= 0 && z < n) return S.at(pij + (long long)z * nn, i, j, z);
+    if (ORDER == 4) {
+        if (z == -2) return -S.at(pij, i, j, 0);
+        if (z == n + 1) return -S.at(pij + (long long)(n - 1) * nn, i, j, n - 1);
+    }
+    return T(0);
+}
+
 // Plane march through LDS.  The block (64 x 4 threads) owns a 64 x 4 column
 // tile and planes z0..z1-1.  The current plane, with a halo of R = ORDER/2
 // points in x and y, sits in one of two LDS buffers; the z neighbours of each
@@ -340,9 +412,9 @@ struct Halo {
     static constexpr int HPT = (NH + HS_BLOCK - 1) / HS_BLOCK;  // halo cells per thread
 };
 
-template <int ORDER, typename T, typename Op>
-__device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int i0, int j0, int z0,
-                                          int z1, T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op)
+template <int ORDER, typename T, class Src, typename Op>
+__device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j0, int z0, int z1,
+                                              T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op)
 {
     using H = Halo<ORDER>;
     constexpr int R = H::R;
@@ -352,7 +424,7 @@ __device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int 
     const bool in = i < n && j < n;
     const T sc = lap_scale<ORDER, T>(n);
     // this thread's halo cells
-    int hrow[H::HPT], hcol[H::HPT];
+    int hrow[H::HPT], hcol[H::HPT], hgi[H::HPT], hgj[H::HPT];
     long long hoff[H::HPT];
     bool hin[H::HPT];
 #pragma unroll
@@ -374,18 +446,20 @@ __device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int 
         int gi = i0 + lcol - R, gj = j0 + lrow - R;
         hrow[h] = lrow;
         hcol[h] = lcol;
+        hgi[h] = gi;
+        hgj[h] = gj;
         hin[h] = lrow >= 0 && gi >= 0 && gi < n && gj >= 0 && gj < n;
         hoff[h] = hin[h] ? (long long)gj * n + gi : 0;
     }
-    const T* col = src + (long long)j * n + i;
+    const long long pij = (long long)j * n + i;
     T w[2 * R + 1];
 #pragma unroll
-    for (int d = -R; d <= R; d++) w[d + R] = in ? zval<ORDER, T>(col, z0 + d, n, nn) : T(0);
+    for (int d = -R; d <= R; d++) w[d + R] = in ? zval_src<ORDER, T>(S, i, j, z0 + d, n, nn, pij) : T(0);
     {
-        const T* plane = src + (long long)z0 * nn;
+        const long long pz = (long long)z0 * nn;
 #pragma unroll
         for (int h = 0; h < H::HPT; h++)
-            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? plane[hoff[h]] : T(0);
+            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? S.at(pz + hoff[h], hgi[h], hgj[h], z0) : T(0);
         pl[0][ly + R][lx + R] = w[R];
     }
     __syncthreads();
@@ -393,10 +467,11 @@ __device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int 
     for (int z = z0; z < z1; z++) {
         const bool more = z + 1 < z1;
         T hv[H::HPT];
-        const T* plane1 = src + (long long)(z + 1) * nn;
+        const long long pz1 = (long long)(z + 1) * nn;
 #pragma unroll
-        for (int h = 0; h < H::HPT; h++) hv[h] = (more && hin[h]) ? plane1[hoff[h]] : T(0);
-        T wn = (more && in) ? zval<ORDER, T>(col, z + R + 1, n, nn) : T(0);
+        for (int h = 0; h < H::HPT; h++)
+            hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hgi[h], hgj[h], z + 1) : T(0);
+        T wn = (more && in) ? zval_src<ORDER, T>(S, i, j, z + R + 1, n, nn, pij) : T(0);
         if (in) {
             const int yy = ly + R, xx = lx + R;
             const T c = w[R];
@@ -432,6 +507,14 @@ __device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int 
     }
 }
 
+template <int ORDER, typename T, typename Op>
+__device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int i0, int j0, int z0,
+                                          int z1, T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op)
+{
+    SrcPlain<T> S{src};
+    lds_march_src<ORDER, T>(S, n, i0, j0, z0, z1, pl, op);
+}
+
 // ---------------------------------------------------------------------------
 // Multigrid kernels
 // ---------------------------------------------------------------------------
@@ -461,7 +544,9 @@ struct SweepOp {
 // guess on correction grids: dst = omega D^{-1} b); MODE 1: residual
 // dst = b - A_a x.  x is the buffer picked by src_is_t, dst the other one.
 // NORM: per-block maxima of |b - A_a x| (and |b| at cycle 0) to partials.
-template <typename T, int ORDER, int MODE, int FINEST, int NORM>
+// SRC 1: x is the zero-guess first sweep omega D^{-1} b, formed on the fly
+// (this launch is the second sweep of a correction grid).
+template <typename T, int ORDER, int MODE, int FINEST, int NORM, int SRC>
 __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ segs, int nseg,
                                                     int nblk, const LaneCtl* __restrict__ ctl,
                                                     hsk::MgArgs A, int first_sweep, int src_is_t,
@@ -489,7 +574,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     op.cycle = cycle;
     op.rmax = 0.0;
     op.bmax = 0.0;
-    if (MODE == 0 && !FINEST && first_sweep && sg.coarse) {
+    if (SRC == 0 && MODE == 0 && !FINEST && first_sweep && sg.coarse) {
         if (q.in)
             for (int z = q.z0; z < q.z1; z++) {
                 long long p = lin(q.i, q.j, z, n);
@@ -497,8 +582,13 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
             }
     } else {
         __shared__ T pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
-        lds_march<ORDER, T>(src, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX),
-                            q.z0, q.z1, pl, op);
+        const int i0 = q.i - (int)(threadIdx.x % HS_TX), j0 = q.j - (int)(threadIdx.x / HS_TX);
+        if constexpr (SRC == 1) {
+            SrcZeroJacobi<T, ORDER> S{B, op.a, op.om, n};
+            lds_march_src<ORDER, T>(S, n, i0, j0, q.z0, q.z1, pl, op);
+        } else {
+            lds_march<ORDER, T>(src, n, i0, j0, q.z0, q.z1, pl, op);
+        }
     }
     if (NORM) {
         double m = block_max(op.rmax);
@@ -544,43 +634,6 @@ __global__ void __launch_bounds__(HS_BLOCK) k_restrict_fw(const GridSeg* __restr
     ((T*)sg.cb)[lin(q.i, q.j, q.k, nc)] = acc;
 }
 
-// trilinear interpolation of a coarse field at fine point (i,j,k); walls 0.
-// Per axis a fine index either coincides with coarse (i-1)/2 (weight 1) or
-// lies between coarse i/2-1 and i/2 (weights 1/2, missing ones are walls).
-template <typename T>
-__device__ __forceinline__ T prolong_at(const T* __restrict__ c, int nc, int i, int j, int k)
-{
-    int ix0, ix1, iy0, iy1, iz0, iz1;
-    T wx, wy, wz;
-    if (i & 1) { ix0 = ix1 = (i - 1) >> 1; wx = T(1); } else { ix0 = (i >> 1) - 1; ix1 = i >> 1; wx = T(0.5); }
-    if (j & 1) { iy0 = iy1 = (j - 1) >> 1; wy = T(1); } else { iy0 = (j >> 1) - 1; iy1 = j >> 1; wy = T(0.5); }
-    if (k & 1) { iz0 = iz1 = (k - 1) >> 1; wz = T(1); } else { iz0 = (k >> 1) - 1; iz1 = k >> 1; wz = T(0.5); }
-    const bool two_x = !(i & 1), two_y = !(j & 1), two_z = !(k & 1);
-    const bool vx0 = ix0 >= 0, vx1 = two_x && ix1 < nc;
-    const bool vy0 = iy0 >= 0, vy1 = two_y && iy1 < nc;
-    const bool vz0 = iz0 >= 0, vz1 = two_z && iz1 < nc;
-    const int sy = nc, sz = nc * nc;
-    T s = T(0);
-#pragma unroll
-    for (int cz = 0; cz < 2; cz++) {
-        const bool vz = cz ? vz1 : vz0;
-        if (!vz) continue;
-        const int oz = (cz ? iz1 : iz0) * sz;
-        T sy_ = T(0);
-#pragma unroll
-        for (int cy = 0; cy < 2; cy++) {
-            const bool vy = cy ? vy1 : vy0;
-            if (!vy) continue;
-            const int o = oz + (cy ? iy1 : iy0) * sy;
-            T sx = T(0);
-            if (vx0) sx += c[o + ix0];
-            if (vx1) sx += c[o + ix1];
-            sy_ += wx * sx;
-        }
-        s += wy * sy_;
-    }
-    return wz * s;
-}
 
 // dst = src + P cu (in place when src and dst are the same buffer)
 template <typename T>
@@ -1604,12 +1657,12 @@ hipError_t set_constants(const LibConst& lc)
         else hipLaunchKernelGGL(KERNEL4, GRID, BLOCK, SHMEM, s, __VA_ARGS__);               \
     } while (0)
 
-template <typename T, int MODE, int FINEST, int NORM>
+template <typename T, int MODE, int FINEST, int NORM, int SRC = 0>
 static hipError_t sweep_launch(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order,
                                MgArgs a, int first_sweep, int src_is_t, int cycle, double* partials,
                                hipStream_t s)
 {
-    HS_ORDER_DISPATCH(order, (k_sweep<T, 2, MODE, FINEST, NORM>), (k_sweep<T, 4, MODE, FINEST, NORM>),
+    HS_ORDER_DISPATCH(order, (k_sweep<T, 2, MODE, FINEST, NORM, SRC>), (k_sweep<T, 4, MODE, FINEST, NORM, SRC>),
                       g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a, first_sweep, src_is_t, partials,
                       cycle);
     return hipGetLastError();
@@ -1618,10 +1671,11 @@ static hipError_t sweep_launch(LaneCtl* ctl, const GridSeg* segs, int nseg, int 
 template <typename T>
 hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                  int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
-                 double* partials, hipStream_t s)
+                 double* partials, hipStream_t s, int src)
 {
     if (nblk <= 0) return hipSuccess;
     if (mode == 1) return sweep_launch<T, 1, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
+    if (src == 1) return sweep_launch<T, 0, 0, 0, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
     if (norm) return sweep_launch<T, 0, 1, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s);
     if (finest_only) return sweep_launch<T, 0, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
     return sweep_launch<T, 0, 0, 0>(ctl, segs, nseg, nblk, order, a, first_sweep, src_is_t, 0, partials, s);
@@ -1656,8 +1710,8 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
     return hipGetLastError();
 }
 
-template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t);
-template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t);
+template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
+template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
 template hipError_t restrict_fw<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
 template hipError_t restrict_fw<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
 template hipError_t prolong<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);

@@ -169,6 +169,7 @@ struct Table {
     S* d = nullptr;
     int nblk = 0;
     int finest = 0;     // grid tables: every segment is a finest grid
+    int coarse_all = 0; // grid tables: every segment is a correction grid (zero first guess)
     int nseg() const { return (int)h.size(); }
 };
 
@@ -180,6 +181,7 @@ struct MgSet {
     size_t tail_lds = 0;                  // LDS bytes of the tail kernel
     Table<GridSeg> fine;                  // finest grids (norms, refinement), z-marching
     int fused_norm = 0;                   // jac[0] holds every lane's finest grid
+    int uniform = 0;                      // every stage holds only finest or only correction grids
 };
 
 struct LaneSet {
@@ -326,8 +328,11 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         }
         S.jac[s].nblk = bj;
         S.jac[s].finest = 1;
-        for (const GridSeg& g : S.jac[s].h)
+        S.jac[s].coarse_all = 1;
+        for (const GridSeg& g : S.jac[s].h) {
             if (g.coarse) S.jac[s].finest = 0;
+            else S.jac[s].coarse_all = 0;
+        }
         S.rr[s].nblk = br;
         S.pro[s].nblk = bp;
     }
@@ -366,6 +371,10 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
     }
     S.fine.nblk = bf;
     S.fused_norm = (Dmax > 0 && S.jac[0].finest && S.jac[0].nseg() == (int)ls.lanes.size()) ? 1 : 0;
+    S.uniform = 1;
+    for (int s = 0; s < Dmax; s++)
+        if (!S.jac[s].finest && !S.jac[s].coarse_all) S.uniform = 0;
+    if (Dmax > 0 && !S.jac[0].coarse_all && !S.fused_norm) S.uniform = 0;
 }
 
 SdcSeg sdc_seg(hs_plan* P, int b, int L)
@@ -680,9 +689,11 @@ bool all_sdc_done(hs_plan* P, const LaneSet& ls)
 
 // One V(nu1,nu2) cycle over the tables of S.  first_done: the first
 // pre-smoothing sweep of step 0 has already run (fused with the norm).
+// One V(nu1, nu2) cycle over the grids above the tail (section 1.2), tables
+// whose stages mix finest and correction grids: every sweep is its own launch.
 template <typename T>
-hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
-                 bool first_done, hipStream_t s)
+hs_status vcycle_unfused(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
+                         bool first_done, hipStream_t s)
 {
     for (int st = 0; st < S.D; st++) {
         const Table<GridSeg>& J = S.jac[st];
@@ -708,6 +719,70 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
                                  P->partials, s));
             cur = !cur;
         }
+    }
+    return HS_OK;
+}
+
+// One V(nu1, nu2) cycle over the grids above the tail (section 1.2).  Each
+// grid keeps its iterate in one of two buffers (0 = u, 1 = t) and every sweep
+// moves it to the other one.  Correction grids start from zero: their first
+// sweep, omega D^{-1} b, is formed where the second sweep reads it instead of
+// being stored.  The prolongation writes the corrected iterate into the
+// buffer from which the post-smoothing sweeps end in u, where the next finer
+// grid's prolongation (or the caller) reads it; the finest grids start and
+// end in u.  first_done: the finest grids' first sweep already ran (fused
+// with the residual norm).
+template <typename T>
+hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
+                 bool first_done, hipStream_t s)
+{
+    if (!S.uniform) return vcycle_unfused<T>(P, S, order, A, nu1, nu2, first_done, s);
+    std::vector<int> loc(S.D);
+    for (int st = 0; st < S.D; st++) {
+        const Table<GridSeg>& J = S.jac[st];
+        int cur;
+        if (!J.coarse_all) {
+            cur = 0;
+            int k0 = 0;
+            if (st == 0 && first_done) {
+                cur ^= 1;
+                k0 = 1;
+            }
+            for (int k = k0; k < nu1; k++, cur ^= 1)
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
+                                     P->partials, s));
+        } else {
+            cur = 1;   // the first write goes to u; the prolongation picks the post-smoothing buffers
+            if (nu1 >= 2) {
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, 0, 0, 0,
+                                     P->partials, s, 1));
+                cur ^= 1;
+                for (int k = 2; k < nu1; k++, cur ^= 1)
+                    HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, 0, 0, 0,
+                                         P->partials, s));
+            } else {
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, cur, 0, 0, 0,
+                                     P->partials, s));
+                cur ^= 1;
+            }
+        }
+        loc[st] = cur;
+        // residual into the free buffer, then full weighting
+        HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 1, 0, cur, 1, 0, 0, P->partials, s));
+        const Table<GridSeg>& R = S.rr[st];
+        HS_TRY(hsk::restrict_fw<T>(P->ctl, R.d, R.nseg(), R.nblk, A, !cur, s));
+    }
+    HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, S.tail_lds, s));
+    for (int st = S.D - 1; st >= 0; st--) {
+        // the prolongation writes the corrected iterate to the buffer from which
+        // the nu2 post-smoothing sweeps end in u
+        const Table<GridSeg>& J = S.jac[st];
+        const Table<GridSeg>& Pr = S.pro[st];
+        int cur = nu2 & 1;
+        HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, loc[st], cur, s));
+        for (int k = 0; k < nu2; k++, cur ^= 1)
+            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
+                                 P->partials, s));
     }
     return HS_OK;
 }
