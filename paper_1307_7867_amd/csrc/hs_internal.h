@@ -8,9 +8,9 @@
 #define HS_MAXM 5          // collocation nodes per SDC level (3 and 5 are used)
 #define HS_MAXTAIL 5       // grids inside the single-workgroup coarse tail (15, 7, 3, 1)
 #define HS_TAIL_N 15       // grids with n <= HS_TAIL_N are handled by the tail kernel
-#define HS_BLOCK 256       // threads per block of the grid kernels
+#define HS_BLOCK 512       // threads per block of the grid kernels (HS_TX x HS_TY)
 #define HS_TX 64           // block tile along x (one wavefront per row)
-#define HS_TY 4            // block tile along y
+#define HS_TY 8            // block tile along y
 #define HS_TAIL_THREADS 1024
 #define HS_ZB 8            // z planes per block of the z-marching stencil kernels
 

@@ -2,7 +2,7 @@
 //
 // Every kernel of the multigrid and SDC hot path works on a table of
 // segments: one segment is one grid of one lane (an independent problem or
-// a PFASST time slice).  Blocks of 256 threads tile a grid as 64 x 4 points
+// a PFASST time slice).  Blocks of 512 threads tile a grid as 64 x 8 points
 // in x-y (one wavefront per x row, coalesced along x).  The stencil kernels
 // march along z through a chunk of planes per block and keep the z
 // neighbours of each column in registers; other kernels take one plane per
@@ -395,7 +395,7 @@ __device__ __forceinline__ T zval_src(const Src& S, int i, int j, int z, int n, 
     return T(0);
 }
 
-// Plane march through LDS.  The block (64 x 4 threads) owns a 64 x 4 column
+// Plane march through LDS.  The block (64 x 8 threads) owns a 64 x 8 column
 // tile and planes z0..z1-1.  The current plane, with a halo of R = ORDER/2
 // points in x and y, sits in one of two LDS buffers; the z neighbours of each
 // column sit in registers.  While plane z is computed, the halo of plane z+1
@@ -635,7 +635,44 @@ __global__ void __launch_bounds__(HS_BLOCK) k_restrict_fw(const GridSeg* __restr
 }
 
 
-// dst = src + P cu (in place when src and dst are the same buffer)
+// xy part of the trilinear interpolation of one coarse plane at fine column
+// (i, j): wy * (sum over the coarse rows of wx * (sum over the coarse
+// columns)), the per-plane term of prolong_at.
+template <typename T>
+struct ProlongXY {
+    int ix0, ix1, iy0, iy1;
+    bool vx0, vx1, vy0, vy1;
+    T wx, wy;
+    __device__ __forceinline__ ProlongXY(int i, int j, int nc)
+    {
+        if (i & 1) { ix0 = ix1 = (i - 1) >> 1; wx = T(1); } else { ix0 = (i >> 1) - 1; ix1 = i >> 1; wx = T(0.5); }
+        if (j & 1) { iy0 = iy1 = (j - 1) >> 1; wy = T(1); } else { iy0 = (j >> 1) - 1; iy1 = j >> 1; wy = T(0.5); }
+        vx0 = ix0 >= 0;
+        vx1 = !(i & 1) && ix1 < nc;
+        vy0 = iy0 >= 0;
+        vy1 = !(j & 1) && iy1 < nc;
+    }
+    __device__ __forceinline__ T at(const T* __restrict__ cplane, int nc) const
+    {
+        T sy = T(0);
+#pragma unroll
+        for (int cy = 0; cy < 2; cy++) {
+            const bool vy = cy ? vy1 : vy0;
+            if (!vy) continue;
+            const T* row = cplane + (cy ? iy1 : iy0) * nc;
+            T sx = T(0);
+            if (vx0) sx += row[ix0];
+            if (vx1) sx += row[ix1];
+            sy += wx * sx;
+        }
+        return wy * sy;
+    }
+};
+
+// dst = src + P cu (in place when src and dst are the same buffer).  Each
+// thread marches its fine column through the block's planes; the xy
+// interpolation of a coarse plane K serves the fine planes 2K, 2K+1, 2K+2
+// and is computed once.  Same operations, in the same order, as prolong_at.
 template <typename T>
 __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict__ segs, int nseg,
                                                       int nblk, const LaneCtl* __restrict__ ctl,
@@ -645,15 +682,43 @@ __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict_
     int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
     if (A.gate && ctl[sg.lane].mg_state != 0) return;
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
+    const int n = sg.n, nc = sg.nc;
+    PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     if (!q.in) return;
     T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
     T* Tt = (T*)sg.t;
     const T* src = src_is_t ? Tt : U;
     T* dst = dst_is_t ? Tt : U;
-    long long p = lin(q.i, q.j, q.k, n);
-    dst[p] = src[p] + prolong_at<T>((const T*)sg.cu, sg.nc, q.i, q.j, q.k);
+    const T* cu = (const T*)sg.cu;
+    const int ncc = nc * nc;
+    const ProlongXY<T> xy(q.i, q.j, nc);
+    // xy terms of the two most recent coarse planes
+    int ka = -2, kb = -2;
+    T ea = T(0), eb = T(0);
+    auto term = [&](int K) -> T {
+        if (K == kb) return eb;
+        if (K == ka) return ea;
+        T e = xy.at(cu + K * ncc, nc);
+        ka = kb;
+        ea = eb;
+        kb = K;
+        eb = e;
+        return e;
+    };
+    for (int z = q.z0; z < q.z1; z++) {
+        T corr;
+        if (z & 1) {
+            corr = T(1) * (T(0) + term((z - 1) >> 1));
+        } else {
+            const int K0 = (z >> 1) - 1, K1 = z >> 1;
+            T s = T(0);
+            if (K0 >= 0) s += term(K0);
+            if (K1 < nc) s += term(K1);
+            corr = T(0.5) * s;
+        }
+        const int p = lin(q.i, q.j, z, n);
+        dst[p] = src[p] + corr;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1622,12 +1687,12 @@ int grid_blocks(int n, int zb) { return tiles_x(n) * tiles_y(n) * ((n + zb - 1) 
 
 // z planes per block of the plane-marching kernels: as many as possible (up
 // to 8, fewer halo reloads and window warm-ups) while one grid still gives
-// 2048 blocks (8 per CU) to fill the chip.
+// 1024 blocks of 512 threads (16 waves per CU) to fill the chip.
 int choose_zb(int n)
 {
     long long tiles = (long long)tiles_x(n) * tiles_y(n);
     int zb = 8;
-    while (zb > 1 && tiles * ((n + zb - 1) / zb) < 2048) zb /= 2;
+    while (zb > 1 && tiles * ((n + zb - 1) / zb) < 1024) zb /= 2;
     return zb;
 }
 

@@ -324,7 +324,8 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             g.blk_begin = bj; bj += hsk::grid_blocks(g.n, g.zb); S.jac[s].h.push_back(g);
             g.zb = 1;
             g.blk_begin = br; br += hsk::grid_blocks(g.nc); S.rr[s].h.push_back(g);
-            g.blk_begin = bp; bp += hsk::grid_blocks(g.n); S.pro[s].h.push_back(g);
+            g.zb = hsk::choose_zb(g.n);
+            g.blk_begin = bp; bp += hsk::grid_blocks(g.n, g.zb); S.pro[s].h.push_back(g);
         }
         S.jac[s].nblk = bj;
         S.jac[s].finest = 1;
