@@ -155,7 +155,8 @@ struct MgArgs {
 };
 
 int grid_blocks(int n, int zb = 1);   // blocks covering an n^3 grid, zb planes per block
-int choose_zb(int n);                 // z planes per block of the plane-marching kernels
+int choose_zb(int n);
+int choose_zb_even(int n);   // even chunk length for resid_fw                 // z planes per block of the plane-marching kernels
 size_t tail_lds_bytes(int n0, int elem);  // LDS of the tail kernel whose top grid is n0
 
 hipError_t set_constants(const LibConst& lc);
@@ -174,6 +175,12 @@ hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int orde
 template <typename T>
 hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,
                        hipStream_t s);
+
+// Residual b - A x (x picked by src_is_t) restricted by full weighting into
+// GridSeg::cb in one pass; the table's chunks (zb) are even.
+template <typename T>
+hipError_t resid_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
+                    int src_is_t, hipStream_t s);
 template <typename T>
 hipError_t prolong(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int src_is_t,
                    int dst_is_t, hipStream_t s);

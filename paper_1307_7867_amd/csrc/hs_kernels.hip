@@ -395,6 +395,30 @@ __device__ __forceinline__ T zval_src(const Src& S, int i, int j, int z, int n, 
     return T(0);
 }
 
+// L_h sum (before the 1/h^2 scale) at a point whose plane sits in LDS with
+// row length LW (cell = its own cell) and whose z neighbours are the column
+// window w (w[R] = centre).  Cells outside the grid hold 0; the reflected
+// 4th-order taps one beyond a wall are -centre.
+template <int ORDER, typename T, int LW>
+__device__ __forceinline__ T plane_lap(const T* cell, const T* w, int i, int j, int n)
+{
+    if (ORDER == 2) {
+        const T c = w[1];
+        T c2 = T(2) * c;
+        return ((cell[-1] - c2) + cell[1]) + ((cell[-LW] - c2) + cell[LW]) + ((w[0] - c2) + w[2]);
+    } else {
+        const T c = w[2];
+        T m2 = i == 0 ? -c : cell[-2];
+        T p2 = i == n - 1 ? -c : cell[2];
+        T ax = (T(16) * (cell[-1] + cell[1]) - (m2 + p2)) - T(30) * c;
+        m2 = j == 0 ? -c : cell[-2 * LW];
+        p2 = j == n - 1 ? -c : cell[2 * LW];
+        T ay = (T(16) * (cell[-LW] + cell[LW]) - (m2 + p2)) - T(30) * c;
+        T az = (T(16) * (w[1] + w[3]) - (w[0] + w[4])) - T(30) * c;
+        return (ax + ay) + az;
+    }
+}
+
 // Plane march through LDS.  The block (64 x 8 threads) owns a 64 x 8 column
 // tile and planes z0..z1-1.  The current plane, with a halo of R = ORDER/2
 // points in x and y, sits in one of two LDS buffers; the z neighbours of each
@@ -473,25 +497,8 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
             hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hgi[h], hgj[h], z + 1) : T(0);
         T wn = (more && in) ? zval_src<ORDER, T>(S, i, j, z + R + 1, n, nn, pij) : T(0);
         if (in) {
-            const int yy = ly + R, xx = lx + R;
-            const T c = w[R];
-            T L;
-            if (ORDER == 2) {
-                T c2 = T(2) * c;
-                L = ((pl[buf][yy][xx - 1] - c2) + pl[buf][yy][xx + 1]) +
-                    ((pl[buf][yy - 1][xx] - c2) + pl[buf][yy + 1][xx]) + ((w[0] - c2) + w[2]);
-            } else {
-                // cells outside the grid hold 0; the reflected taps one beyond a wall are -c
-                T m2 = i == 0 ? -c : pl[buf][yy][xx - 2];
-                T p2 = i == n - 1 ? -c : pl[buf][yy][xx + 2];
-                T ax = (T(16) * (pl[buf][yy][xx - 1] + pl[buf][yy][xx + 1]) - (m2 + p2)) - T(30) * c;
-                m2 = j == 0 ? -c : pl[buf][yy - 2][xx];
-                p2 = j == n - 1 ? -c : pl[buf][yy + 2][xx];
-                T ay = (T(16) * (pl[buf][yy - 1][xx] + pl[buf][yy + 1][xx]) - (m2 + p2)) - T(30) * c;
-                T az = (T(16) * (w[1] + w[3]) - (w[0] + w[4])) - T(30) * c;
-                L = (ax + ay) + az;
-            }
-            op((long long)z * nn + (long long)j * n + i, z, c, sc * L);
+            const T L = plane_lap<ORDER, T, H::LW>(&pl[buf][ly + R][lx + R], w, i, j, n);
+            op((long long)z * nn + (long long)j * n + i, z, w[R], sc * L);
         }
         if (more) {
 #pragma unroll
@@ -634,6 +641,198 @@ __global__ void __launch_bounds__(HS_BLOCK) k_restrict_fw(const GridSeg* __restr
     ((T*)sg.cb)[lin(q.i, q.j, q.k, nc)] = acc;
 }
 
+
+// Residual and full weighting in one pass: cb(I) = sum over the 27 fine
+// neighbours of 2I+1 of (1/4,1/2,1/4)^3 (b - A_a x), x the buffer picked by
+// src_is_t; the fine residual is never stored.  The block owns the fine tile
+// x0..x0+63, y0..y0+7, planes z0..z1-1 (x0, y0, z0 and the chunk length
+// even) and the coarse points whose centre 2I+1 lies in it.  Their weights
+// reach one fine column, row and plane beyond the tile on the high side, so
+// the residual is formed on (64+1) x (8+1) points per plane and on planes
+// z0..z1 (threads 0..72, waves 0-1, take the extra column and row with their
+// own z window).  Per plane the residual goes to one of two LDS buffers; the
+// 128 coarse-point owners (waves 2-3) add the xy-weighted sum of the previous
+// plane's residual to their running z sum while the next one is formed, so a
+// plane costs one barrier.  Same operations, in the same order, as the
+// residual sweep followed by k_restrict_fw.
+template <int ORDER>
+struct RfwTile {
+    static constexpr int R = ORDER == 2 ? 1 : 2;
+    static constexpr int RX = HS_TX + 1, RY = HS_TY + 1;        // residual points per plane
+    static constexpr int LW = RX + 2 * R, LH = RY + 2 * R;      // x plane in LDS
+    static constexpr int NH = LW * LH - HS_TX * HS_TY;         // cells not owned by a main thread
+    static constexpr int HPT = (NH + HS_BLOCK - 1) / HS_BLOCK;
+    static constexpr int NX = HS_TY + RX;                       // extra residual points
+    static constexpr int NC = (HS_TX / 2) * (HS_TY / 2);        // coarse points per tile
+};
+
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(HS_BLOCK, 8) k_resid_fw(const GridSeg* __restrict__ segs, int nseg,
+                                                       int nblk, const LaneCtl* __restrict__ ctl,
+                                                       hsk::MgArgs A, int src_is_t)
+{
+    using G = RfwTile<ORDER>;
+    constexpr int R = G::R;
+    static_assert(G::HPT <= 2 && G::NX <= HS_BLOCK && G::NC <= HS_BLOCK, "tile");
+    __shared__ T pl[2][G::LH][G::LW];
+    __shared__ T rp[2][G::RY][G::RX];
+    const int lb = xcd_remap(blockIdx.x, nblk);
+    const int si = find_seg(segs, nseg, lb);
+    const GridSeg sg = segs[si];
+    if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    const int n = sg.n, nc = sg.nc;
+    const PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
+    const int t = (int)threadIdx.x;
+    const int lx = t % HS_TX, ly = t / HS_TX;
+    const int x0 = q.i - lx, y0 = q.j - ly;
+    const int z0 = q.z0, zl = min(q.z1, n - 1);   // residual planes z0..zl
+    const int nn = n * n;   // offsets stay below 2^31 for n <= 511
+    const T* U = (const T*)sg.u + (long long)A.node * sg.node_stride;
+    const T* x = src_is_t ? (const T*)sg.t : U;
+    const T* B = (const T*)sg.b;
+    T* cb = (T*)sg.cb;
+    const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
+    const T sc = lap_scale<ORDER, T>(n);
+    SrcPlain<T> S{x};
+    // main point
+    const int i = q.i, j = q.j;
+    const bool in = i < n && j < n;
+    const int pij = j * n + i;
+    // extra point: column x0+64 (rows y0..y0+7), then row y0+8 (x0..x0+64)
+    const bool has_x = t < G::NX;
+    const int exl = t < HS_TY ? HS_TX : t - HS_TY, eyl = t < HS_TY ? t : HS_TY;
+    const int ei = x0 + exl, ej = y0 + eyl;
+    const bool ein = has_x && ei < n && ej < n;
+    const int epij = ej * n + ei;
+    // cells of the LDS plane loaded by this thread besides its main point
+    int hrow[G::HPT], hcol[G::HPT], hgi[G::HPT], hgj[G::HPT];
+    bool hin[G::HPT];
+    int hoff[G::HPT];
+#pragma unroll
+    for (int h = 0; h < G::HPT; h++) {
+        // enumerate the plane's cells, skipping the main 64 x 8 block
+        int c = t + HS_BLOCK * h;
+        int lrow = -1, lcol = 0;
+        if (c < G::NH) {
+            // rows above the main block, then rows beside it, then rows below
+            const int top = R * G::LW;                        // rows 0..R-1
+            const int side = HS_TY * (G::LW - HS_TX);         // rows R..R+7, cells outside the main columns
+            if (c < top) {
+                lrow = c / G::LW;
+                lcol = c % G::LW;
+            } else if (c < top + side) {
+                const int s = c - top, per = G::LW - HS_TX;
+                lrow = R + s / per;
+                const int k = s % per;
+                lcol = k < R ? k : HS_TX + k;
+            } else {
+                const int s = c - top - side;
+                lrow = R + HS_TY + s / G::LW;
+                lcol = s % G::LW;
+            }
+        }
+        const int gi = x0 + lcol - R, gj = y0 + lrow - R;
+        hrow[h] = lrow;
+        hcol[h] = lcol;
+        hgi[h] = gi;
+        hgj[h] = gj;
+        hin[h] = lrow >= 0 && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        hoff[h] = hin[h] ? gj * n + gi : 0;
+    }
+    // coarse point owned by this thread (waves 2-3)
+    const int to = t - 2 * 64;
+    const bool own = to >= 0 && to < G::NC;
+    const int I = (x0 >> 1) + (to % (HS_TX / 2)), J = (y0 >> 1) + (to / (HS_TX / 2));
+    const bool cin = own && I < nc && J < nc;
+    const int cx = 2 * I + 1 - x0, cyy = 2 * J + 1 - y0;   // centre in rp
+    T acc = T(0);
+    int kopen = -1;   // coarse plane being summed
+    const T wfw[3] = {T(0.25), T(0.5), T(0.25)};
+    // column windows
+    T w[2 * R + 1], we[2 * R + 1];
+#pragma unroll
+    for (int d = -R; d <= R; d++) {
+        w[d + R] = in ? zval_src<ORDER, T>(S, i, j, z0 + d, n, nn, pij) : T(0);
+        we[d + R] = ein ? zval_src<ORDER, T>(S, ei, ej, z0 + d, n, nn, epij) : T(0);
+    }
+    {
+        const int pz = z0 * nn;
+#pragma unroll
+        for (int h = 0; h < G::HPT; h++)
+            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? S.at(pz + hoff[h], hgi[h], hgj[h], z0) : T(0);
+        pl[0][ly + R][lx + R] = w[R];
+    }
+    __syncthreads();
+    // full weighting of residual plane zp (in rp[zp & 1]) into the running sums
+    auto fw_plane = [&](int zp) {
+        T az = T(0);
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++) {
+            const T* row = &rp[zp & 1][cyy + dy][cx];
+            T ay = (wfw[0] * row[-1] + wfw[1] * row[0]) + wfw[2] * row[1];
+            az += wfw[dy + 1] * ay;
+        }
+        // coarse plane K takes fine planes 2K, 2K+1, 2K+2
+        if (zp & 1) {
+            if (kopen >= 0) acc += wfw[1] * az;
+        } else {
+            if (kopen >= 0) {
+                acc += wfw[2] * az;
+                cb[lin(I, J, kopen, nc)] = acc;
+                kopen = -1;
+            }
+            const int K = zp >> 1;
+            if (zp < q.z1 && K < nc) {
+                acc = T(0);
+                acc += wfw[0] * az;
+                kopen = K;
+            }
+        }
+    };
+    int buf = 0;
+    for (int z = z0; z <= zl; z++) {
+        const bool more = z + 1 <= zl;
+        T hv[G::HPT];
+        const int pz1 = (z + 1) * nn;
+#pragma unroll
+        for (int h = 0; h < G::HPT; h++)
+            hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hgi[h], hgj[h], z + 1) : T(0);
+        const T wn = (more && in) ? zval_src<ORDER, T>(S, i, j, z + R + 1, n, nn, pij) : T(0);
+        const T wen = (more && ein) ? zval_src<ORDER, T>(S, ei, ej, z + R + 1, n, nn, epij) : T(0);
+        // residual on the main and the extra points of plane z
+        T r = T(0);
+        if (in) {
+            const T L = plane_lap<ORDER, T, G::LW>(&pl[buf][ly + R][lx + R], w, i, j, n);
+            r = B[z * nn + pij] - (w[R] - a * (sc * L));
+        }
+        rp[z & 1][ly][lx] = r;
+        if (has_x) {
+            T re = T(0);
+            if (ein) {
+                const T L = plane_lap<ORDER, T, G::LW>(&pl[buf][eyl + R][exl + R], we, ei, ej, n);
+                re = B[z * nn + epij] - (we[R] - a * (sc * L));
+            }
+            rp[z & 1][eyl][exl] = re;
+        }
+        if (cin && z > z0) fw_plane(z - 1);
+        if (more) {
+#pragma unroll
+            for (int h = 0; h < G::HPT; h++)
+                if (hrow[h] >= 0) pl[buf ^ 1][hrow[h]][hcol[h]] = hv[h];
+            pl[buf ^ 1][ly + R][lx + R] = w[R + 1];
+        }
+#pragma unroll
+        for (int d = 0; d < 2 * R; d++) {
+            w[d] = w[d + 1];
+            we[d] = we[d + 1];
+        }
+        w[2 * R] = wn;
+        we[2 * R] = wen;
+        __syncthreads();
+        buf ^= 1;
+    }
+    if (cin) fw_plane(zl);
+}
 
 // xy part of the trilinear interpolation of one coarse plane at fine column
 // (i, j): wy * (sum over the coarse rows of wx * (sum over the coarse
@@ -1696,6 +1895,14 @@ int choose_zb(int n)
     return zb;
 }
 
+// z planes per block of the fused residual and restriction: even (a coarse
+// plane's centre and both its fine neighbours below lie in one chunk)
+int choose_zb_even(int n)
+{
+    int zb = choose_zb(n);
+    return zb < 2 ? 2 : zb;
+}
+
 size_t tail_lds_bytes(int n0, int elem)
 {
     size_t words = 0;
@@ -1756,6 +1963,16 @@ hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, Mg
 }
 
 template <typename T>
+hipError_t resid_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
+                    int src_is_t, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    HS_ORDER_DISPATCH(order, (k_resid_fw<T, 2>), (k_resid_fw<T, 4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
+                      a, src_is_t);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t prolong(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int src_is_t,
                    int dst_is_t, hipStream_t s)
 {
@@ -1779,6 +1996,8 @@ template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArg
 template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
 template hipError_t restrict_fw<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
 template hipError_t restrict_fw<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
+template hipError_t resid_fw<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
+template hipError_t resid_fw<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
 template hipError_t prolong<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);
 template hipError_t prolong<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);
 template hipError_t tail<double>(LaneCtl*, const TailSeg*, int, int, MgArgs, int, int, size_t, hipStream_t);

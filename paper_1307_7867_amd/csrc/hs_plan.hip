@@ -177,6 +177,7 @@ struct Table {
 struct MgSet {
     int D = 0;                            // down steps above the tail
     std::vector<Table<GridSeg>> jac, rr, pro;  // z-marching sweeps, restriction, prolongation
+    std::vector<Table<GridSeg>> rfw;           // fused residual + restriction (even z chunks)
     Table<TailSeg> tail;
     size_t tail_lds = 0;                  // LDS bytes of the tail kernel
     Table<GridSeg> fine;                  // finest grids (norms, refinement), z-marching
@@ -292,6 +293,7 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
     S.jac.assign(Dmax, {});
     S.rr.assign(Dmax, {});
     S.pro.assign(Dmax, {});
+    S.rfw.assign(Dmax, {});
     auto grid_ptrs = [&](const LaneBufs& lb, int l, void** u, void** t, void** b) {
         if (fp32) {
             *u = lb.fu[L][l]; *t = lb.ft[L][l]; *b = lb.fb[L][l];
@@ -302,7 +304,7 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         }
     };
     for (int s = 0; s < Dmax; s++) {
-        int bj = 0, br = 0, bp = 0;
+        int bj = 0, br = 0, bp = 0, bf2 = 0;
         for (int b : ls.lanes) {
             const LaneBufs& lb = P->lanes[b];
             int Db = tail_start(lb.grids[L]);
@@ -326,6 +328,8 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             g.blk_begin = br; br += hsk::grid_blocks(g.nc); S.rr[s].h.push_back(g);
             g.zb = hsk::choose_zb(g.n);
             g.blk_begin = bp; bp += hsk::grid_blocks(g.n, g.zb); S.pro[s].h.push_back(g);
+            g.zb = hsk::choose_zb_even(g.n);
+            g.blk_begin = bf2; bf2 += hsk::grid_blocks(g.n, g.zb); S.rfw[s].h.push_back(g);
         }
         S.jac[s].nblk = bj;
         S.jac[s].finest = 1;
@@ -336,6 +340,7 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         }
         S.rr[s].nblk = br;
         S.pro[s].nblk = bp;
+        S.rfw[s].nblk = bf2;
     }
     int bf = 0;
     for (int b : ls.lanes) {
@@ -444,6 +449,7 @@ void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
             for (auto& t : S->jac) finish_table(t, bump);
             for (auto& t : S->rr) finish_table(t, bump);
             for (auto& t : S->pro) finish_table(t, bump);
+            for (auto& t : S->rfw) finish_table(t, bump);
             finish_table(S->tail, bump);
             finish_table(S->fine, bump);
         }
@@ -527,7 +533,7 @@ void layout(hs_plan* P, char* base)
         for (int f = 0; f < 2; f++) {
             const MgSet& S = f ? P->all.mg32[L] : P->all.mg64[L];
             P->store.grid[L][f].clear();
-            for (int t = 0; t < 3 * S.D + 1; t++) P->store.grid[L][f].push_back(bump.arr<GridSeg>(P->B));
+            for (int t = 0; t < 4 * S.D + 1; t++) P->store.grid[L][f].push_back(bump.arr<GridSeg>(P->B));
             P->store.tail[L][f] = bump.arr<TailSeg>(P->B);
         }
         P->store.sdc[L] = bump.arr<SdcSeg>(P->B);
@@ -604,6 +610,7 @@ hipError_t upload_set(hs_plan* P, const LaneSet& ls, hipStream_t s)
             for (auto& t : S->jac) if ((e = upload(t, s)) != hipSuccess) return e;
             for (auto& t : S->rr) if ((e = upload(t, s)) != hipSuccess) return e;
             for (auto& t : S->pro) if ((e = upload(t, s)) != hipSuccess) return e;
+            for (auto& t : S->rfw) if ((e = upload(t, s)) != hipSuccess) return e;
             if ((e = upload(S->tail, s)) != hipSuccess) return e;
             if ((e = upload(S->fine, s)) != hipSuccess) return e;
         }
@@ -768,10 +775,9 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
             }
         }
         loc[st] = cur;
-        // residual into the free buffer, then full weighting
-        HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 1, 0, cur, 1, 0, 0, P->partials, s));
-        const Table<GridSeg>& R = S.rr[st];
-        HS_TRY(hsk::restrict_fw<T>(P->ctl, R.d, R.nseg(), R.nblk, A, !cur, s));
+        // residual restricted by full weighting in one pass
+        const Table<GridSeg>& RF = S.rfw[st];
+        HS_TRY(hsk::resid_fw<T>(P->ctl, RF.d, RF.nseg(), RF.nblk, order, A, cur, s));
     }
     HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, S.tail_lds, s));
     for (int st = S.D - 1; st >= 0; st--) {
@@ -921,11 +927,12 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
             // the run set never holds deeper lanes than the full set
             if (S.D > A.D) return HS_ESTATE;
             for (int st = 0; st < S.D; st++) {
-                S.jac[st].d = P->store.grid[L][f][3 * st];
-                S.rr[st].d = P->store.grid[L][f][3 * st + 1];
-                S.pro[st].d = P->store.grid[L][f][3 * st + 2];
+                S.jac[st].d = P->store.grid[L][f][4 * st];
+                S.rr[st].d = P->store.grid[L][f][4 * st + 1];
+                S.pro[st].d = P->store.grid[L][f][4 * st + 2];
+                S.rfw[st].d = P->store.grid[L][f][4 * st + 3];
             }
-            S.fine.d = P->store.grid[L][f][3 * A.D];
+            S.fine.d = P->store.grid[L][f][4 * A.D];
             S.tail.d = P->store.tail[L][f];
             if (S.fine.h.empty()) S.fine.d = nullptr;
             if (S.tail.h.empty()) S.tail.d = nullptr;
