@@ -176,6 +176,16 @@ template <typename T>
 hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,
                        hipStream_t s);
 
+// First post-smoothing sweep on x = u + P e: u picked by src_is_t, e the
+// coarser grid's iterate (GridSeg::cu); the result goes to the other buffer.
+template <typename T>
+hipError_t pjac(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
+                hipStream_t s);
+
+// Copy the finest iterate from t back to u for the lanes whose solve ran an
+// odd number of V-cycles (when every cycle moves the iterate).
+hipError_t mg_fixup(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, hipStream_t s);
+
 // Residual b - A x (x picked by src_is_t) restricted by full weighting into
 // GridSeg::cb in one pass; the table's chunks (zb) are even.
 template <typename T>

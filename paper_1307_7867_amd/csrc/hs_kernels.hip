@@ -839,32 +839,41 @@ __global__ void __launch_bounds__(HS_BLOCK, 8) k_resid_fw(const GridSeg* __restr
 // columns)), the per-plane term of prolong_at.
 template <typename T>
 struct ProlongXY {
-    int ix0, ix1, iy0, iy1;
-    bool vx0, vx1, vy0, vy1;
-    T wx, wy;
+    // coarse indices ix0 (ix1 = ix0 + 1 for even i, = ix0 for odd i), likewise
+    // y; bit 0/1: odd i / odd j, bits 2-5: the four index pairs are inside the
+    // grid (vx0, vx1, vy0, vy1)
+    int ix0, iy0, f;
+    ProlongXY() = default;
     __device__ __forceinline__ ProlongXY(int i, int j, int nc)
     {
-        if (i & 1) { ix0 = ix1 = (i - 1) >> 1; wx = T(1); } else { ix0 = (i >> 1) - 1; ix1 = i >> 1; wx = T(0.5); }
-        if (j & 1) { iy0 = iy1 = (j - 1) >> 1; wy = T(1); } else { iy0 = (j >> 1) - 1; iy1 = j >> 1; wy = T(0.5); }
-        vx0 = ix0 >= 0;
-        vx1 = !(i & 1) && ix1 < nc;
-        vy0 = iy0 >= 0;
-        vy1 = !(j & 1) && iy1 < nc;
+        const int ox = i & 1, oy = j & 1;
+        ix0 = ox ? (i - 1) >> 1 : (i >> 1) - 1;
+        iy0 = oy ? (j - 1) >> 1 : (j >> 1) - 1;
+        const int ix1 = ox ? ix0 : ix0 + 1, iy1 = oy ? iy0 : iy0 + 1;
+        f = ox | (oy << 1) | ((ix0 >= 0) << 2) | ((!ox && ix1 < nc) << 3) | ((iy0 >= 0) << 4) |
+            ((!oy && iy1 < nc) << 5);
     }
-    __device__ __forceinline__ T at(const T* __restrict__ cplane, int nc) const
+    __device__ __forceinline__ int ix1() const { return (f & 1) ? ix0 : ix0 + 1; }
+    __device__ __forceinline__ int iy1() const { return (f & 2) ? iy0 : iy0 + 1; }
+    __device__ __forceinline__ T wx() const { return (f & 1) ? T(1) : T(0.5); }
+    __device__ __forceinline__ T wy() const { return (f & 2) ? T(1) : T(0.5); }
+    // row base pointers: `plane` points at coarse (0, 0) of the plane (any
+    // origin shift folded in), `pitch` is the row length
+    __device__ __forceinline__ T at(const T* __restrict__ plane, int pitch) const
     {
+        const T wxv = wx();
         T sy = T(0);
 #pragma unroll
         for (int cy = 0; cy < 2; cy++) {
-            const bool vy = cy ? vy1 : vy0;
+            const bool vy = cy ? (f & 32) : (f & 16);
             if (!vy) continue;
-            const T* row = cplane + (cy ? iy1 : iy0) * nc;
+            const T* row = plane + (cy ? iy1() : iy0) * pitch;
             T sx = T(0);
-            if (vx0) sx += row[ix0];
-            if (vx1) sx += row[ix1];
-            sy += wx * sx;
+            if (f & 4) sx += row[ix0];
+            if (f & 8) sx += row[ix1()];
+            sy += wxv * sx;
         }
-        return wy * sy;
+        return wy() * sy;
     }
 };
 
@@ -917,6 +926,192 @@ __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict_
         }
         const int p = lin(q.i, q.j, z, n);
         dst[p] = src[p] + corr;
+    }
+}
+
+// First post-smoothing sweep with the coarse-grid correction applied as the
+// input is read: x = u + P e (u the buffer picked by src_is_t, e = GridSeg::cu
+// on the nc^3 grid), dst = x + omega D^{-1} (b - A_a x) into the other buffer;
+// the corrected x is never stored.  The coarse planes that the block's fine
+// planes interpolate from are staged in an LDS ring of 4 planes, each over
+// the 35 x 7 coarse points below the block's 68 x 12 (order 4) fine region,
+// one iteration ahead of their first use (a ring slot is reused only once
+// no fine plane still to be read interpolates from it).  The correction of every value
+// read (plane halo and column window) is the same sum, in the same order, as
+// k_prolong's, so the result equals k_prolong followed by a Jacobi sweep.
+struct PjCoarse {
+    static constexpr int CW = HS_TX / 2 + 3, CH = HS_TY / 2 + 3;   // coarse cells per ring plane
+    static constexpr int NCELL = CW * CH;
+    static constexpr int NR = 4;                                   // ring planes
+};
+
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict__ segs, int nseg, int nblk,
+                                                  const LaneCtl* __restrict__ ctl, hsk::MgArgs A,
+                                                  int src_is_t)
+{
+    using H = Halo<ORDER>;
+    using C = PjCoarse;
+    constexpr int R = H::R;
+    static_assert(C::NCELL <= HS_BLOCK, "one coarse cell per thread");
+    __shared__ T pl[2][H::LH][H::LW];
+    __shared__ T cr[C::NR][C::CH][C::CW];
+    const int lb = xcd_remap(blockIdx.x, nblk);
+    const int si = find_seg(segs, nseg, lb);
+    const GridSeg sg = segs[si];
+    if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    const int n = sg.n, nc = sg.nc;
+    const PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
+    const int t = (int)threadIdx.x;
+    const int lx = t % HS_TX, ly = t / HS_TX;
+    const int i = q.i, j = q.j, x0 = i - lx, y0 = j - ly;
+    const int z0 = q.z0, z1 = q.z1;
+    const bool in = i < n && j < n;
+    const int nn = n * n, ncc = nc * nc;   // offsets stay below 2^31 for n <= 511
+    T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
+    T* Tt = (T*)sg.t;
+    const T* x = src_is_t ? Tt : U;
+    T* dst = src_is_t ? U : Tt;
+    const T* B = (const T*)sg.b;
+    const T* cu = (const T*)sg.cu;
+    const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
+    const T om = T(A.omega);
+    const T sc = lap_scale<ORDER, T>(n);
+    const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;
+    // coarse cell of this thread in a ring plane
+    const bool has_c = t < C::NCELL;
+    const int ccx = cx0 + t % C::CW, ccy = cy0 + t / C::CW;
+    const bool cin = has_c && ccx >= 0 && ccx < nc && ccy >= 0 && ccy < nc;
+    const int coff = cin ? ccy * nc + ccx : 0;
+    int kl = -1;   // highest coarse plane staged
+    // coarse planes fine plane zf interpolates from: klo(zf) .. kneed(zf)
+    auto kneed = [&](int zf) { return min(nc - 1, max(0, zf >> 1)); };
+    auto klo = [&](int zf) { return max(0, ((zf + 1) >> 1) - 1); };
+    // xy term of coarse plane K at fine column (fi, fj), from the ring
+    auto term = [&](const ProlongXY<T>& w, int K) -> T {
+        // the ring plane holds coarse (cx0.., cy0..): shift the origin
+        return w.at(&cr[K & 3][0][0] - cy0 * C::CW - cx0, C::CW);
+    };
+    // correction P e at fine plane zf (0 <= zf < n) of the column described by w
+    auto corr = [&](const ProlongXY<T>& w, int zf) -> T {
+        if (zf & 1) return T(1) * (T(0) + term(w, (zf - 1) >> 1));
+        const int K0 = (zf >> 1) - 1, K1 = zf >> 1;
+        T s = T(0);
+        if (K0 >= 0) s += term(w, K0);
+        if (K1 < nc) s += term(w, K1);
+        return T(0.5) * s;
+    };
+    // corrected value of column (fi, fj) at plane zf with the z wall rules of the stencil
+    auto zv = [&](const ProlongXY<T>& w, int pij, int zf) -> T {
+        if (zf >= 0 && zf < n) return x[zf * nn + pij] + corr(w, zf);
+        if (ORDER == 4) {
+            if (zf == -2) return -(x[pij] + corr(w, 0));
+            if (zf == n + 1) return -(x[(n - 1) * nn + pij] + corr(w, n - 1));
+        }
+        return T(0);
+    };
+    // halo cells of this thread
+    int hrow[H::HPT], hcol[H::HPT], hoff[H::HPT];
+    bool hin[H::HPT];
+    ProlongXY<T> hw[H::HPT] = {};
+#pragma unroll
+    for (int h = 0; h < H::HPT; h++) {
+        int qq = t + HS_BLOCK * h;
+        int lrow = -1, lcol = 0;
+        if (qq < H::NH) {
+            if (qq < 2 * R * HS_TY) {
+                lrow = qq / (2 * R) + R;
+                int c = qq % (2 * R);
+                lcol = c < R ? c : HS_TX + c;
+            } else {
+                int tt = qq - 2 * R * HS_TY;
+                int rr = tt / H::LW;
+                lrow = rr < R ? rr : HS_TY + rr;
+                lcol = tt % H::LW;
+            }
+        }
+        const int gi = x0 + lcol - R, gj = y0 + lrow - R;
+        hrow[h] = lrow;
+        hcol[h] = lcol;
+        hin[h] = lrow >= 0 && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        hoff[h] = hin[h] ? gj * n + gi : 0;
+        hw[h] = ProlongXY<T>(hin[h] ? gi : 1, hin[h] ? gj : 1, nc);
+    }
+    const ProlongXY<T> mw(in ? i : 1, in ? j : 1, nc);
+    const int pij = in ? j * n + i : 0;
+    // stage the coarse planes the prologue and the first iteration read
+    {
+        const int kt = kneed(z0 + R + 1);
+        kl = klo(z0 - R) - 1;
+        for (int K = kl + 1; K <= kt; K++)
+            if (has_c) cr[K & 3][t / C::CW][t % C::CW] = cin ? cu[K * ncc + coff] : T(0);
+        kl = kt;
+    }
+    __syncthreads();
+    T w[2 * R + 1];
+#pragma unroll
+    for (int d = -R; d <= R; d++) w[d + R] = in ? zv(mw, pij, z0 + d) : T(0);
+#pragma unroll
+    for (int h = 0; h < H::HPT; h++)
+        if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? x[z0 * nn + hoff[h]] + corr(hw[h], z0) : T(0);
+    pl[0][ly + R][lx + R] = w[R];
+    __syncthreads();
+    int buf = 0;
+    for (int z = z0; z < z1; z++) {
+        const bool more = z + 1 < z1;
+        // raw values of the next plane's halo, the next column value, and the
+        // coarse plane(s) the next iteration needs
+        T hv[H::HPT];
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++) hv[h] = (more && hin[h]) ? x[(z + 1) * nn + hoff[h]] : T(0);
+        const int kt = more ? kneed(z + R + 2) : kl;
+        T cv = (has_c && cin && kt > kl) ? cu[kt * ncc + coff] : T(0);
+        if (in) {
+            const T L = plane_lap<ORDER, T, H::LW>(&pl[buf][ly + R][lx + R], w, i, j, n);
+            const int p = z * nn + pij;
+            const T c = w[R];
+            const T r = B[p] - (c - a * (sc * L));
+            dst[p] = c + om * r / diag_A<ORDER, T>(a, i, j, z, n);
+        }
+        const T wn = (more && in) ? zv(mw, pij, z + R + 1) : T(0);
+        if (more) {
+#pragma unroll
+            for (int h = 0; h < H::HPT; h++)
+                if (hrow[h] >= 0) pl[buf ^ 1][hrow[h]][hcol[h]] = hin[h] ? hv[h] + corr(hw[h], z + 1) : T(0);
+            pl[buf ^ 1][ly + R][lx + R] = w[R + 1];
+        }
+        if (kt > kl) {
+            if (has_c) cr[kt & 3][t / C::CW][t % C::CW] = cv;
+            kl = kt;
+        }
+#pragma unroll
+        for (int d = 0; d < 2 * R; d++) w[d] = w[d + 1];
+        w[2 * R] = wn;
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
+// After a solve whose V-cycles each leave the finest iterate in the other
+// buffer, lanes that ran an odd number of cycles hold it in t: copy it back
+// to the node field u.
+__global__ void __launch_bounds__(HS_BLOCK) k_mg_fixup(const GridSeg* __restrict__ segs, int nseg,
+                                                       int nblk, const LaneCtl* __restrict__ ctl,
+                                                       hsk::MgArgs A)
+{
+    int lb = xcd_remap(blockIdx.x, nblk);
+    int si = find_seg(segs, nseg, lb);
+    const GridSeg sg = segs[si];
+    const LaneCtl& c = ctl[sg.lane];
+    if (c.mg_state == 3 || (c.mg_cycle & 1) == 0) return;
+    const int n = sg.n;
+    PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
+    if (!q.in) return;
+    double* U = (double*)sg.u + (long long)A.node * sg.node_stride;
+    const double* Tt = (const double*)sg.t;
+    for (int z = q.z0; z < q.z1; z++) {
+        int p = lin(q.i, q.j, z, n);
+        U[p] = Tt[p];
     }
 }
 
@@ -1973,6 +2168,23 @@ hipError_t resid_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int o
 }
 
 template <typename T>
+hipError_t pjac(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
+                hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    HS_ORDER_DISPATCH(order, (k_pjac<T, 2>), (k_pjac<T, 4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a,
+                      src_is_t);
+    return hipGetLastError();
+}
+
+hipError_t mg_fixup(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mg_fixup, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, a);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t prolong(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int src_is_t,
                    int dst_is_t, hipStream_t s)
 {
@@ -1996,6 +2208,8 @@ template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArg
 template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
 template hipError_t restrict_fw<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
 template hipError_t restrict_fw<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
+template hipError_t pjac<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
+template hipError_t pjac<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
 template hipError_t resid_fw<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
 template hipError_t resid_fw<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
 template hipError_t prolong<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);

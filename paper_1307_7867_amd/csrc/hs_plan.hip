@@ -735,22 +735,25 @@ hs_status vcycle_unfused(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, i
 // grid keeps its iterate in one of two buffers (0 = u, 1 = t) and every sweep
 // moves it to the other one.  Correction grids start from zero: their first
 // sweep, omega D^{-1} b, is formed where the second sweep reads it instead of
-// being stored.  The prolongation writes the corrected iterate into the
-// buffer from which the post-smoothing sweeps end in u, where the next finer
-// grid's prolongation (or the caller) reads it; the finest grids start and
-// end in u.  first_done: the finest grids' first sweep already ran (fused
-// with the residual norm).
+// being stored, and their first write goes to the buffer that makes the cycle
+// end in u, where the next finer grid's prolongation reads the correction.
+// The residual is restricted in the same pass that forms it, and the
+// prolongated correction is applied as the first post-smoothing sweep reads
+// its input (nu2 >= 1).  The finest grids start in buffer *par and end in
+// *par ^ ((nu1 + nu2) & 1), written back to *par.  first_done: the finest
+// grids' first sweep already ran (fused with the residual norm).
 template <typename T>
 hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
-                 bool first_done, hipStream_t s)
+                 bool first_done, int* par, hipStream_t s)
 {
     if (!S.uniform) return vcycle_unfused<T>(P, S, order, A, nu1, nu2, first_done, s);
+    const bool pj = nu2 >= 1;
     std::vector<int> loc(S.D);
     for (int st = 0; st < S.D; st++) {
         const Table<GridSeg>& J = S.jac[st];
         int cur;
         if (!J.coarse_all) {
-            cur = 0;
+            cur = *par;
             int k0 = 0;
             if (st == 0 && first_done) {
                 cur ^= 1;
@@ -760,7 +763,8 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
                                      P->partials, s));
         } else {
-            cur = 1;   // the first write goes to u; the prolongation picks the post-smoothing buffers
+            const int writes = nu1 - (nu1 >= 2 ? 1 : 0) + (pj ? nu2 : 0);
+            cur = pj ? !((writes - 1) & 1) : 1;
             if (nu1 >= 2) {
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, 0, 0, 0,
                                      P->partials, s, 1));
@@ -781,16 +785,29 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
     }
     HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, S.tail_lds, s));
     for (int st = S.D - 1; st >= 0; st--) {
-        // the prolongation writes the corrected iterate to the buffer from which
-        // the nu2 post-smoothing sweeps end in u
         const Table<GridSeg>& J = S.jac[st];
-        const Table<GridSeg>& Pr = S.pro[st];
-        int cur = nu2 & 1;
-        HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, loc[st], cur, s));
-        for (int k = 0; k < nu2; k++, cur ^= 1)
-            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
-                                 P->partials, s));
+        int cur = loc[st];
+        if (pj) {
+            HS_TRY(hsk::pjac<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, cur, s));
+            cur ^= 1;
+            for (int k = 1; k < nu2; k++, cur ^= 1)
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
+                                     P->partials, s));
+        } else {
+            const Table<GridSeg>& Pr = S.pro[st];
+            HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, cur, cur, s));
+        }
+        if (!J.coarse_all) *par = cur;
     }
+    return HS_OK;
+}
+
+// Finest iterates left in t by an odd number of buffer-moving cycles go back
+// to the node fields.
+hs_status mg_finish(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int nu2, hipStream_t s)
+{
+    if (!S.uniform || S.D == 0 || S.jac[0].coarse_all || nu2 < 1 || !((nu1 + nu2) & 1)) return HS_OK;
+    HS_TRY(hsk::mg_fixup(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, A, s));
     return HS_OK;
 }
 
@@ -805,17 +822,18 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     int& pred = m >= 0 ? P->cpred[L][m] : P->cpred_user;
     if (!P->mixed) {
         const MgSet& S = ls.mg64[L];
+        int par = 0;
         if (mg.fixed_cycles > 0) {
             for (int c = 0; c < mg.fixed_cycles; c++)
-                HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, false, s));
+                HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, false, &par, s));
             HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
-            return HS_OK;
+            return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
         }
         for (int c = 0;; c++) {
             // residual norm before cycle c; fused with cycle c's first sweep when possible
             if (S.fused_norm) {
                 const Table<GridSeg>& J = S.jac[0];
-                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, 0, 1, 1, c,
+                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, par, 1, 1, c,
                                           P->partials, s));
                 HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, P->partials, c, mg.tol,
                                       mg.max_cycles, s));
@@ -835,9 +853,9 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                 }
             }
             if (c >= mg.max_cycles) break;
-            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, S.fused_norm != 0, s));
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, S.fused_norm != 0, &par, s));
         }
-        return HS_OK;
+        return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
     }
     // mixed precision: FP64 refinement around one FP32 cycle per iteration
     const MgSet& S64 = ls.mg64[L];
@@ -862,7 +880,8 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             }
             if (it >= limit) break;
         }
-        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, false, s));
+        int par32 = 0;
+        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, false, &par32, s));
         HS_TRY(hsk::ir_update(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, A, s));
     }
     if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, s));
