@@ -1354,50 +1354,45 @@ struct TailV<T, ORDER, N0, LAST, LAST> {
 // One V-cycle over the NLEV tail grids of one lane, top grid N0^3: level 0
 // starts from the iterate in global memory (or from zero when the top is a
 // correction grid), the lower levels from zero; the result is written back
-// to level 0's iterate.  A single-grid tail is just the exact solve.
+// to level 0's iterate.  A single-grid tail is just the exact solve.  The
+// top grid's loads are issued first, so their latency overlaps the lane's
+// state check and the set-up of the smoother weights.
+template <typename T>
+struct TailShared {
+    T rd[HS_MAXTAIL][8];
+    double S[9], lam[3], bh[27];
+};
+
 template <typename T, int ORDER, int N0, int NLEV>
-__device__ __forceinline__ void tail_run(TailCtx<T>& c, T* gu0, const T* gb0)
+__device__ __forceinline__ void tail_run(const TailSeg& ts, const LaneCtl* __restrict__ ctl,
+                                         const hsk::MgArgs& A, int nu1, int nu2, T* base,
+                                         TailShared<T>& sh)
 {
     constexpr int N0c = tail_cube(N0);
-    if constexpr (NLEV == 1) {
-        __syncthreads();
-        lds_exact<T, N0>(gb0, c.base, c.a, c.S, c.lam, c.bh);
-        for (int p = threadIdx.x; p < N0c; p += HS_TAIL_THREADS) gu0[p] = c.base[p];
-    } else {
-        T b0[tail_q<N0>()];
+    T (*s_rd)[8] = sh.rd;
+    double* s_S = sh.S;
+    double* s_lam = sh.lam;
+    double* s_bh = sh.bh;
+    const int t = (int)threadIdx.x;
+    T* gu0 = (T*)ts.u[0] + (long long)A.node * ts.node_stride;
+    const T* gb0 = (const T*)ts.b[0];
+    const bool zero_top = ts.zero_guess != 0;
+    T b0[tail_q<N0>()];
+    T u0[tail_q<N0>()];
+    if constexpr (NLEV > 1) {
 #pragma unroll
         for (int q = 0; q < tail_q<N0>(); q++) {
             int i, j, k, p;
-            b0[q] = tail_pt<N0>(q, i, j, k, p) ? gb0[p] : T(0);
+            const bool ok = tail_pt<N0>(q, i, j, k, p);
+            b0[q] = ok ? gb0[p] : T(0);
+            u0[q] = (ok && !zero_top) ? gu0[p] : T(0);
         }
-        if (!c.zero_top)
-            for (int p = threadIdx.x; p < N0c; p += HS_TAIL_THREADS) c.base[p] = gu0[p];
-        __syncthreads();
-        c.b0 = b0;
-        c.in_y = 0;
-        TailV<T, ORDER, N0, 0, NLEV - 1>::run(c);
-        const T* res = (c.in_y & 1u) ? c.base + N0c : c.base;
-        for (int p = threadIdx.x; p < N0c; p += HS_TAIL_THREADS) gu0[p] = res[p];
     }
-}
-
-template <typename T, int ORDER>
-__global__ void __launch_bounds__(HS_TAIL_THREADS) k_tail(const TailSeg* __restrict__ segs,
-                                                          const LaneCtl* __restrict__ ctl,
-                                                          hsk::MgArgs A, int nu1, int nu2)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ T s_rd[HS_MAXTAIL][8];
-    __shared__ double s_S[9], s_lam[3], s_bh[27];
-    const TailSeg& ts = segs[blockIdx.x];
     if (A.gate && ctl[ts.lane].mg_state != 0) return;
-    const int n0 = ts.n[0];
-    const int nlev = ts.nlev;
     const T a = T(lane_a(ctl, ts.lane, A.L, A.m));
-    const int t = (int)threadIdx.x;
-    if (t < nlev * 7) {
+    if (t < NLEV * 7) {
         const int l = t / 7, w = t % 7;
-        const int nl = ts.n[l];
+        const int nl = tail_n(N0, l);
         const T ih2 = T((double)(nl + 1) * (double)(nl + 1));
         const T D = ORDER == 2 ? T(1) + a * ih2 * T(6) : T(1) + a * ih2 * (T(90 - w) / T(12));
         s_rd[l][w] = T(A.omega) / D;
@@ -1407,28 +1402,54 @@ __global__ void __launch_bounds__(HS_TAIL_THREADS) k_tail(const TailSeg* __restr
         else s_lam[t - 73] = ct.lam[t - 73];
     }
     TailCtx<T> c;
-    c.base = (T*)smem;
-    c.b0 = nullptr;
+    c.base = base;
+    c.b0 = b0;
     c.a = a;
     c.rd = s_rd;
     c.nu1 = nu1;
     c.nu2 = nu2;
-    c.zero_top = ts.zero_guess != 0;
+    c.zero_top = zero_top;
     c.S = s_S;
     c.lam = s_lam;
     c.bh = s_bh;
     c.in_y = 0;
-    T* gu0 = (T*)ts.u[0] + (long long)A.node * ts.node_stride;
-    const T* gb0 = (const T*)ts.b[0];
+    if constexpr (NLEV == 1) {
+        __syncthreads();
+        lds_exact<T, N0>(gb0, c.base, c.a, c.S, c.lam, c.bh);
+        for (int p = t; p < N0c; p += HS_TAIL_THREADS) gu0[p] = c.base[p];
+    } else {
+        if (!zero_top) {
+#pragma unroll
+            for (int q = 0; q < tail_q<N0>(); q++) {
+                int i, j, k, p;
+                if (tail_pt<N0>(q, i, j, k, p)) base[p] = u0[q];
+            }
+        }
+        __syncthreads();
+        TailV<T, ORDER, N0, 0, NLEV - 1>::run(c);
+        const T* res = (c.in_y & 1u) ? c.base + N0c : c.base;
+        for (int p = t; p < N0c; p += HS_TAIL_THREADS) gu0[p] = res[p];
+    }
+}
+
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(HS_TAIL_THREADS) k_tail(const TailSeg* __restrict__ segs,
+                                                          const LaneCtl* __restrict__ ctl,
+                                                          hsk::MgArgs A, int nu1, int nu2)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ TailShared<T> sh;
+    T* base = (T*)smem;
+    const TailSeg& ts = segs[blockIdx.x];
     // the plan only builds tails of these shapes (top 2^k - 1 <= 15 down to 3 or 1)
-    switch (n0 * 8 + nlev) {
-    case 15 * 8 + 3: tail_run<T, ORDER, 15, 3>(c, gu0, gb0); break;
-    case 15 * 8 + 4: tail_run<T, ORDER, 15, 4>(c, gu0, gb0); break;
-    case 7 * 8 + 2: tail_run<T, ORDER, 7, 2>(c, gu0, gb0); break;
-    case 7 * 8 + 3: tail_run<T, ORDER, 7, 3>(c, gu0, gb0); break;
-    case 3 * 8 + 1: tail_run<T, ORDER, 3, 1>(c, gu0, gb0); break;
-    case 3 * 8 + 2: tail_run<T, ORDER, 3, 2>(c, gu0, gb0); break;
-    case 1 * 8 + 1: tail_run<T, ORDER, 1, 1>(c, gu0, gb0); break;
+    switch (ts.n[0] * 8 + ts.nlev) {
+    case 15 * 8 + 3: tail_run<T, ORDER, 15, 3>(ts, ctl, A, nu1, nu2, base, sh); break;
+    case 15 * 8 + 4: tail_run<T, ORDER, 15, 4>(ts, ctl, A, nu1, nu2, base, sh); break;
+    case 7 * 8 + 2: tail_run<T, ORDER, 7, 2>(ts, ctl, A, nu1, nu2, base, sh); break;
+    case 7 * 8 + 3: tail_run<T, ORDER, 7, 3>(ts, ctl, A, nu1, nu2, base, sh); break;
+    case 3 * 8 + 1: tail_run<T, ORDER, 3, 1>(ts, ctl, A, nu1, nu2, base, sh); break;
+    case 3 * 8 + 2: tail_run<T, ORDER, 3, 2>(ts, ctl, A, nu1, nu2, base, sh); break;
+    case 1 * 8 + 1: tail_run<T, ORDER, 1, 1>(ts, ctl, A, nu1, nu2, base, sh); break;
     default: break;
     }
 }
