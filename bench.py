@@ -17,7 +17,7 @@ value = space-time DOF-updates/s = 127^3 * (5 - 1) substeps * 3 iterations
         * K / elapsed.
 
 roofline: the dominant kernel, the finest-grid weighted-Jacobi sweep
-(k_sweep<double, 4, 0, 1, 0> on 127^3), timed with HIP events on its stream
+(k_sweep<double, 4, 0, 1, 0, 0> on 127^3), timed with HIP events on its stream
 (one launch per sweep, the solver's launch configuration); algorithmic
 bytes 24 per grid point (read u, b; write u').
 
@@ -206,7 +206,7 @@ def main():
                                "V(2,1) Jacobi 6/7 to 3^3, rel. residual 1e-12",
                    "fine_n": NF, "coarse_n": NC, "dt": pb.dt, "iterations_per_step": ITERS,
                    "mg_tol": pb.tol},
-        "roofline": {"bound": "hbm", "kernel": "k_sweep<double, 4, 0, 1, 0> (finest-grid weighted Jacobi) on 127^3",
+        "roofline": {"bound": "hbm", "kernel": "k_sweep<double, 4, 0, 1, 0, 0> (finest-grid weighted Jacobi) on 127^3",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "us_per_launch": jac_s * 1e6, "algorithmic_bytes_per_launch": jac_bytes},

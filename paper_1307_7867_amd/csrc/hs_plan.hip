@@ -794,8 +794,10 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
                                      P->partials, s));
         } else {
+            // no post-smoothing: the corrected iterate goes to u
             const Table<GridSeg>& Pr = S.pro[st];
-            HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, cur, cur, s));
+            HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, cur, 0, s));
+            cur = 0;
         }
         if (!J.coarse_all) *par = cur;
     }

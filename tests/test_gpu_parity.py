@@ -111,6 +111,25 @@ def test_mg_fixed_cycles_parity(torch, order, n):
         assert rel(got, ref) <= TOL, (n, b)
 
 
+@pytest.mark.parametrize("nu1,nu2,cycles", [(2, 1, 1), (2, 1, 2), (1, 1, 3), (2, 2, 2), (3, 0, 2), (1, 2, 1),
+                                             (1, 0, 3)])
+def test_mg_cycle_shapes_parity(torch, nu1, nu2, cycles):
+    """V(nu1, nu2) cycle shapes: odd and even sweep counts (the finest iterate
+    changes buffer on odd ones), a single pre-sweep, and no post-sweep."""
+    hs = heatst_mod()
+    n, order = 63, 4
+    a = [0.004, 0.0007]
+    plan = hs.Plan(hs.Problem(n=n, order=order, nnodes=3, batch=2, nu1=nu1, nu2=nu2, fixed_cycles=cycles))
+    bs = [inputs.random_field(n, 80 + b) for b in range(2)]
+    us = [inputs.random_smooth(n, 90 + b) for b in range(2)]
+    u = dev(torch, np.concatenate([x.ravel() for x in us]))
+    plan.mg_vcycle(u, dev(torch, np.concatenate([x.ravel() for x in bs])), a)
+    for b, got in enumerate(split(host(u), [n, n])):
+        ref, st, cyc, rho = oracle.mg_solve(bs[b], order, a[b], u0=us[b],
+                                            mg=oracle.mg_params(nu1=nu1, nu2=nu2, fixed_cycles=cycles))
+        assert rel(got, ref) <= TOL, (b, nu1, nu2, cycles)
+
+
 @pytest.mark.parametrize("order", [2, 4])
 def test_mg_tolerance_parity(torch, order):
     hs = heatst_mod()
