@@ -877,6 +877,35 @@ struct ProlongXY {
     }
 };
 
+// The xy term of ProlongXY read from a zero-padded LDS plane: every tap
+// exists (outside the grid it reads 0), so the validity tests become 0/1
+// weights and the four reads need no branches.  Adding the exact zeros
+// leaves every sum as ProlongXY::at forms it.
+template <typename T>
+struct RingTap {
+    int o;    // offset of coarse (ix0, iy0) in the padded plane
+    int f;    // bit 0: odd i, bit 1: odd j
+    RingTap() = default;
+    __device__ __forceinline__ RingTap(int i, int j, int ox0, int oy0, int pitch)
+    {
+        const int odx = i & 1, ody = j & 1;
+        const int ix0 = odx ? (i - 1) >> 1 : (i >> 1) - 1;
+        const int iy0 = ody ? (j - 1) >> 1 : (j >> 1) - 1;
+        o = (iy0 - oy0) * pitch + (ix0 - ox0);
+        f = odx | (ody << 1);
+    }
+    __device__ __forceinline__ T at(const T* __restrict__ plane, int pitch) const
+    {
+        const T ex = (f & 1) ? T(0) : T(1), ey = (f & 2) ? T(0) : T(1);
+        const T wx = (f & 1) ? T(1) : T(0.5), wy = (f & 2) ? T(1) : T(0.5);
+        const T* r0 = plane + o;
+        const T* r1 = r0 + pitch;
+        const T sx0 = r0[0] + ex * r0[1];
+        const T sx1 = r1[0] + ex * r1[1];
+        return wy * (wx * sx0 + ey * (wx * sx1));
+    }
+};
+
 // dst = src + P cu (in place when src and dst are the same buffer).  Each
 // thread marches its fine column through the block's planes; the xy
 // interpolation of a coarse plane K serves the fine planes 2K, 2K+1, 2K+2
@@ -934,13 +963,17 @@ __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict_
 // on the nc^3 grid), dst = x + omega D^{-1} (b - A_a x) into the other buffer;
 // the corrected x is never stored.  The coarse planes that the block's fine
 // planes interpolate from are staged in an LDS ring of 4 planes, each over
-// the 35 x 7 coarse points below the block's 68 x 12 (order 4) fine region,
-// one iteration ahead of their first use (a ring slot is reused only once
-// no fine plane still to be read interpolates from it).  The correction of every value
-// read (plane halo and column window) is the same sum, in the same order, as
-// k_prolong's, so the result equals k_prolong followed by a Jacobi sweep.
+// the 35 x 7 coarse points below the block's 68 x 12 (order 4) fine region
+// plus one column and row, one iteration ahead of their first use (a ring
+// slot is reused only once no fine plane still to be read interpolates from
+// it); coarse points outside the grid are stored as zeros, so the taps read
+// without branches.  Each correction adds the same nonzero terms, in the
+// same order, as k_prolong, so the result equals k_prolong followed by a
+// Jacobi sweep.
 struct PjCoarse {
-    static constexpr int CW = HS_TX / 2 + 3, CH = HS_TY / 2 + 3;   // coarse cells per ring plane
+    // coarse cells per ring plane: the 35 x 7 that the fine region interpolates
+    // from, plus one column and one row that the branch-free taps read with weight 0
+    static constexpr int CW = HS_TX / 2 + 4, CH = HS_TY / 2 + 4;
     static constexpr int NCELL = CW * CH;
     static constexpr int NR = 4;                                   // ring planes
 };
@@ -988,12 +1021,9 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
     auto kneed = [&](int zf) { return min(nc - 1, max(0, zf >> 1)); };
     auto klo = [&](int zf) { return max(0, ((zf + 1) >> 1) - 1); };
     // xy term of coarse plane K at fine column (fi, fj), from the ring
-    auto term = [&](const ProlongXY<T>& w, int K) -> T {
-        // the ring plane holds coarse (cx0.., cy0..): shift the origin
-        return w.at(&cr[K & 3][0][0] - cy0 * C::CW - cx0, C::CW);
-    };
+    auto term = [&](const RingTap<T>& w, int K) -> T { return w.at(&cr[K & 3][0][0], C::CW); };
     // correction P e at fine plane zf (0 <= zf < n) of the column described by w
-    auto corr = [&](const ProlongXY<T>& w, int zf) -> T {
+    auto corr = [&](const RingTap<T>& w, int zf) -> T {
         if (zf & 1) return T(1) * (T(0) + term(w, (zf - 1) >> 1));
         const int K0 = (zf >> 1) - 1, K1 = zf >> 1;
         T s = T(0);
@@ -1002,7 +1032,7 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
         return T(0.5) * s;
     };
     // corrected value of column (fi, fj) at plane zf with the z wall rules of the stencil
-    auto zv = [&](const ProlongXY<T>& w, int pij, int zf) -> T {
+    auto zv = [&](const RingTap<T>& w, int pij, int zf) -> T {
         if (zf >= 0 && zf < n) return x[zf * nn + pij] + corr(w, zf);
         if (ORDER == 4) {
             if (zf == -2) return -(x[pij] + corr(w, 0));
@@ -1013,7 +1043,7 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
     // halo cells of this thread
     int hrow[H::HPT], hcol[H::HPT], hoff[H::HPT];
     bool hin[H::HPT];
-    ProlongXY<T> hw[H::HPT] = {};
+    RingTap<T> hw[H::HPT] = {};
 #pragma unroll
     for (int h = 0; h < H::HPT; h++) {
         int qq = t + HS_BLOCK * h;
@@ -1035,9 +1065,9 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
         hcol[h] = lcol;
         hin[h] = lrow >= 0 && gi >= 0 && gi < n && gj >= 0 && gj < n;
         hoff[h] = hin[h] ? gj * n + gi : 0;
-        hw[h] = ProlongXY<T>(hin[h] ? gi : 1, hin[h] ? gj : 1, nc);
+        hw[h] = RingTap<T>(hin[h] ? gi : x0 + 1, hin[h] ? gj : y0 + 1, cx0, cy0, C::CW);
     }
-    const ProlongXY<T> mw(in ? i : 1, in ? j : 1, nc);
+    const RingTap<T> mw(in ? i : x0 + 1, in ? j : y0 + 1, cx0, cy0, C::CW);
     const int pij = in ? j * n + i : 0;
     // stage the coarse planes the prologue and the first iteration read
     {
