@@ -599,7 +599,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     }
     if (NORM) {
         double m = block_max(op.rmax);
-        double mb = block_max(op.bmax);
+        double mb = cycle == 0 ? block_max(op.bmax) : 0.0;   // |b| is taken once per solve
         if (threadIdx.x == 0) {
             partials[2 * lb] = m;
             partials[2 * lb + 1] = mb;
