@@ -96,6 +96,10 @@ typedef struct {
     int32_t fixed_cycles;    /* > 0: exactly this many cycles */
     int32_t precision;       /* hs_precision */
     int32_t inner_nu1, inner_nu2;
+    int32_t fused_sweeps;    /* 0 or 1: one smoothing sweep per pass over the grid; 2: the finest
+                                grids' first two pre-smoothing sweeps in one pass (temporal
+                                blocking; FP64, grids of 127^3 and up, nu1 >= 2; same results,
+                                measured slower than two passes on MI355X at 127^3 and 255^3) */
 } hs_mg_desc;
 
 typedef struct {

@@ -156,7 +156,8 @@ struct MgArgs {
 
 int grid_blocks(int n, int zb = 1);   // blocks covering an n^3 grid, zb planes per block
 int choose_zb(int n);
-int choose_zb_even(int n);   // even chunk length for resid_fw                 // z planes per block of the plane-marching kernels
+int choose_zb_even(int n);   // even chunk length for resid_fw
+int choose_zb_two(int n);    // chunk length for jac2                 // z planes per block of the plane-marching kernels
 size_t tail_lds_bytes(int n0, int elem);  // LDS of the tail kernel whose top grid is n0
 
 hipError_t set_constants(const LibConst& lc);
@@ -175,6 +176,13 @@ hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int orde
 template <typename T>
 hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,
                        hipStream_t s);
+
+// Two weighted-Jacobi sweeps in one pass: dst = J(J(x)), x picked by
+// src_is_t, dst the other buffer.  norm: per-block maxima of the first
+// sweep's residual (and |b| when cycle == 0) to partials, as sweep does.
+template <typename T>
+hipError_t jac2(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
+                int norm, int cycle, double* partials, hipStream_t s);
 
 // First post-smoothing sweep on x = u + P e: u picked by src_is_t, e the
 // coarser grid's iterate (GridSeg::cu); the result goes to the other buffer.

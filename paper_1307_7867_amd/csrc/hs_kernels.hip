@@ -642,6 +642,190 @@ __global__ void __launch_bounds__(HS_BLOCK) k_restrict_fw(const GridSeg* __restr
 }
 
 
+// Two weighted-Jacobi sweeps in one pass (temporal blocking, the
+// several-sweeps-per-pass remedy for the smoother's memory traffic):
+// v = J(x), dst = J(v), x the buffer picked by src_is_t, dst the other one;
+// v is never stored.  The block marches zj = z0-R .. z1-1+R.  On each plane
+// zj it forms v over its tile plus a halo of R: the x/y neighbours come from
+// plane zj of x over the tile plus 2R in LDS, the z neighbours from a
+// register window per v point (each thread owns up to two v points).  v goes
+// to an LDS ring of 2R+1 planes, from which dst is formed on plane zj-R over
+// the tile.  v outside the grid is 0; its wall planes follow the stencil's z
+// rules (v(-1) = v(n) = 0, v(-2) = -v(0), v(n+1) = -v(n-1)).  NORM: per-block
+// maxima of the first sweep's residual over the tile's planes z0..z1-1 (and of
+// |b| at cycle 0), as the sweep with the norm.  Same operations, in the same
+// order, as two separate sweeps.
+template <int ORDER>
+struct J2Tile {
+    static constexpr int R = ORDER == 2 ? 1 : 2;
+    static constexpr int NZ = 2 * R + 1;                    // v ring planes
+    static constexpr int UW = HS_TX + 4 * R, UH = HS_TY + 4 * R;
+    static constexpr int VW = HS_TX + 2 * R, VH = HS_TY + 2 * R;
+    static constexpr int NV = VW * VH;
+    static constexpr int VPT = (NV + HS_BLOCK - 1) / HS_BLOCK;
+    static constexpr int NO = UW * UH - NV;                  // x cells outside the v region
+    static constexpr int OPT = (NO + HS_BLOCK - 1) / HS_BLOCK;
+};
+
+template <typename T, int ORDER, int NORM>
+__global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ segs, int nseg, int nblk,
+                                                  const LaneCtl* __restrict__ ctl, hsk::MgArgs A,
+                                                  int src_is_t, double* __restrict__ partials, int cycle)
+{
+    using G = J2Tile<ORDER>;
+    constexpr int R = G::R, NZ = G::NZ;
+    static_assert(G::VPT <= 2 && G::OPT <= 1, "tile");
+    __shared__ T ub[2][G::UH][G::UW];
+    __shared__ T vr[NZ][G::VH][G::VW];
+    const int lb = xcd_remap(blockIdx.x, nblk);
+    const int si = find_seg(segs, nseg, lb);
+    const GridSeg sg = segs[si];
+    if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    const int n = sg.n;
+    const PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
+    const int t = (int)threadIdx.x;
+    const int lx = t % HS_TX, ly = t / HS_TX;
+    const int i = q.i, j = q.j, x0 = i - lx, y0 = j - ly;
+    const int z0 = q.z0, z1 = q.z1;
+    const bool in = i < n && j < n;
+    const int nn = n * n;   // offsets stay below 2^31 for n <= 511
+    T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
+    T* Tt = (T*)sg.t;
+    const T* x = src_is_t ? Tt : U;
+    T* dst = src_is_t ? U : Tt;
+    const T* B = (const T*)sg.b;
+    const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
+    const T om = T(A.omega);
+    const T sc = lap_scale<ORDER, T>(n);
+    SrcPlain<T> S{x};
+    double rmax = 0.0, bmax = 0.0;
+    // v points of this thread
+    int vx[G::VPT], vy[G::VPT], vgi[G::VPT], vgj[G::VPT];
+    bool vok[G::VPT], vin[G::VPT], vmain[G::VPT];
+#pragma unroll
+    for (int k = 0; k < G::VPT; k++) {
+        const int c = t + HS_BLOCK * k;
+        vok[k] = c < G::NV;
+        vx[k] = vok[k] ? c % G::VW : 0;
+        vy[k] = vok[k] ? c / G::VW : 0;
+        vgi[k] = x0 - R + vx[k];
+        vgj[k] = y0 - R + vy[k];
+        vin[k] = vok[k] && vgi[k] >= 0 && vgi[k] < n && vgj[k] >= 0 && vgj[k] < n;
+        vmain[k] = vin[k] && vx[k] >= R && vx[k] < R + HS_TX && vy[k] >= R && vy[k] < R + HS_TY;
+    }
+    // x cell outside the v region loaded by this thread
+    int orow = -1, ocol = 0, ooff = 0, ogi = 0, ogj = 0;
+    bool oin = false;
+    if (t < G::NO) {
+        const int top = R * G::UW, side = G::VH * 2 * R;
+        if (t < top) {
+            orow = t / G::UW;
+            ocol = t % G::UW;
+        } else if (t < top + side) {
+            const int s = t - top;
+            orow = R + s / (2 * R);
+            const int kk = s % (2 * R);
+            ocol = kk < R ? kk : G::VW + kk;
+        } else {
+            const int s = t - top - side;
+            orow = R + G::VH + s / G::UW;
+            ocol = s % G::UW;
+        }
+        ogi = x0 - 2 * R + ocol;
+        ogj = y0 - 2 * R + orow;
+        oin = ogi >= 0 && ogi < n && ogj >= 0 && ogj < n;
+        ooff = oin ? ogj * n + ogi : 0;
+    }
+    auto xz = [&](int gi, int gj, int zz) -> T {   // x at (gi, gj, zz) with the z wall rules
+        return zval_src<ORDER, T>(S, gi, gj, zz, n, nn, (long long)gj * n + gi);
+    };
+    const int zs = z0 - R, ze = z1 - 1 + R;   // v planes formed by the block
+    // z windows of the v points: x planes zs-R .. zs+R
+    T wv[G::VPT][2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < G::VPT; k++)
+#pragma unroll
+        for (int d = 0; d <= 2 * R; d++) wv[k][d] = vin[k] ? xz(vgi[k], vgj[k], zs - R + d) : T(0);
+    // x plane zs
+    if (orow >= 0) ub[zs & 1][orow][ocol] = oin ? xz(ogi, ogj, zs) : T(0);
+#pragma unroll
+    for (int k = 0; k < G::VPT; k++)
+        if (vok[k]) ub[zs & 1][vy[k] + R][vx[k] + R] = wv[k][R];
+    __syncthreads();
+    auto slot = [](int zz) { return ((zz % NZ) + NZ) % NZ; };
+    for (int zj = zs; zj <= ze; zj++) {
+        const bool more = zj + 1 <= ze;
+        // loads for the next plane and this plane's right-hand sides
+        T on = (more && oin) ? xz(ogi, ogj, zj + 1) : T(0);
+        T wn[G::VPT], bv[G::VPT];
+#pragma unroll
+        for (int k = 0; k < G::VPT; k++) {
+            wn[k] = (more && vin[k]) ? xz(vgi[k], vgj[k], zj + 1 + R) : T(0);
+            bv[k] = (vin[k] && zj >= 0 && zj < n) ? B[zj * nn + vgj[k] * n + vgi[k]] : T(0);
+        }
+        const int zo = zj - R;   // plane of dst formed in this step
+        const bool out = zo >= z0 && zo < z1 && in;
+        const T bo = out ? B[zo * nn + j * n + i] : T(0);
+        // first sweep on plane zj over the tile plus R
+#pragma unroll
+        for (int k = 0; k < G::VPT; k++) {
+            if (!vok[k]) continue;
+            T v = T(0);
+            if (zj >= 0 && zj < n) {
+                if (vin[k]) {
+                    const T c = wv[k][R];
+                    const T L = plane_lap<ORDER, T, G::UW>(&ub[zj & 1][vy[k] + R][vx[k] + R], wv[k], vgi[k],
+                                                           vgj[k], n);
+                    const T r = bv[k] - (c - a * (sc * L));
+                    v = c + om * r / diag_A<ORDER, T>(a, vgi[k], vgj[k], zj, n);
+                    if (NORM && vmain[k] && zj >= z0 && zj < z1) {
+                        rmax = nmax(rmax, (double)tabs(r));
+                        if (cycle == 0) bmax = nmax(bmax, (double)tabs(bv[k]));
+                    }
+                }
+                if (ORDER == 4 && zj == 0) vr[slot(-2)][vy[k]][vx[k]] = -v;
+            } else if (ORDER == 4 && zj == n + 1) {
+                v = -vr[slot(n - 1)][vy[k]][vx[k]];
+            }
+            if (!(ORDER == 4 && zj == -2)) vr[slot(zj)][vy[k]][vx[k]] = v;
+        }
+        __syncthreads();
+        // second sweep on plane zo over the tile
+        if (out) {
+            const int yy = ly + R, xx = lx + R;
+            T w2[2 * R + 1];
+#pragma unroll
+            for (int d = 0; d <= 2 * R; d++) w2[d] = vr[slot(zo - R + d)][yy][xx];
+            const T c = w2[R];
+            const T L = plane_lap<ORDER, T, G::VW>(&vr[slot(zo)][yy][xx], w2, i, j, n);
+            const T r = bo - (c - a * (sc * L));
+            dst[zo * nn + j * n + i] = c + om * r / diag_A<ORDER, T>(a, i, j, zo, n);
+        }
+        // x plane zj+1
+        if (more) {
+            if (orow >= 0) ub[(zj + 1) & 1][orow][ocol] = on;
+#pragma unroll
+            for (int k = 0; k < G::VPT; k++)
+                if (vok[k]) ub[(zj + 1) & 1][vy[k] + R][vx[k] + R] = wv[k][R + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < G::VPT; k++) {
+#pragma unroll
+            for (int d = 0; d < 2 * R; d++) wv[k][d] = wv[k][d + 1];
+            wv[k][2 * R] = wn[k];
+        }
+        __syncthreads();
+    }
+    if (NORM) {
+        double m = block_max(rmax);
+        double mb = cycle == 0 ? block_max(bmax) : 0.0;
+        if (t == 0) {
+            partials[2 * lb] = m;
+            partials[2 * lb + 1] = mb;
+        }
+    }
+}
+
 // Residual and full weighting in one pass: cb(I) = sum over the 27 fine
 // neighbours of 2I+1 of (1/4,1/2,1/4)^3 (b - A_a x), x the buffer picked by
 // src_is_t; the fine residual is never stored.  The block owns the fine tile
@@ -2141,6 +2325,14 @@ int choose_zb(int n)
     return zb;
 }
 
+// z planes per block of the two-sweep kernel: twice the sweeps' (the first
+// sweep is formed on R extra planes at each end of the block's chunk)
+int choose_zb_two(int n)
+{
+    const int zb = 2 * choose_zb(n);
+    return zb < 16 ? zb : 16;
+}
+
 // z planes per block of the fused residual and restriction: even (a coarse
 // plane's centre and both its fine neighbours below lie in one chunk)
 int choose_zb_even(int n)
@@ -2209,6 +2401,20 @@ hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, Mg
 }
 
 template <typename T>
+hipError_t jac2(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
+                int norm, int cycle, double* partials, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (norm)
+        HS_ORDER_DISPATCH(order, (k_jac2<T, 2, 1>), (k_jac2<T, 4, 1>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
+                          a, src_is_t, partials, cycle);
+    else
+        HS_ORDER_DISPATCH(order, (k_jac2<T, 2, 0>), (k_jac2<T, 4, 0>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
+                          a, src_is_t, partials, cycle);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t resid_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                     int src_is_t, hipStream_t s)
 {
@@ -2259,6 +2465,8 @@ template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArg
 template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
 template hipError_t restrict_fw<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
 template hipError_t restrict_fw<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
+template hipError_t jac2<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
+template hipError_t jac2<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
 template hipError_t pjac<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
 template hipError_t pjac<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
 template hipError_t resid_fw<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);

@@ -176,13 +176,15 @@ struct Table {
 // multigrid tables of one SDC level, one precision, one set of lanes
 struct MgSet {
     int D = 0;                            // down steps above the tail
-    std::vector<Table<GridSeg>> jac, rr, pro;  // z-marching sweeps, restriction, prolongation
+    std::vector<Table<GridSeg>> jac, rr, pro;  // z-marching sweeps, restriction, prolongation (and
+                                               // the two-sweep kernel on the finest grids)
     std::vector<Table<GridSeg>> rfw;           // fused residual + restriction (even z chunks)
     Table<TailSeg> tail;
     size_t tail_lds = 0;                  // LDS bytes of the tail kernel
     Table<GridSeg> fine;                  // finest grids (norms, refinement), z-marching
     int fused_norm = 0;                   // jac[0] holds every lane's finest grid
     int uniform = 0;                      // every stage holds only finest or only correction grids
+    int two = 0;                          // the finest grids' first two sweeps run as one pass
 };
 
 struct LaneSet {
@@ -326,7 +328,7 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             g.blk_begin = bj; bj += hsk::grid_blocks(g.n, g.zb); S.jac[s].h.push_back(g);
             g.zb = 1;
             g.blk_begin = br; br += hsk::grid_blocks(g.nc); S.rr[s].h.push_back(g);
-            g.zb = hsk::choose_zb(g.n);
+            g.zb = hsk::choose_zb_two(g.n);   // also the two-sweep kernel's table
             g.blk_begin = bp; bp += hsk::grid_blocks(g.n, g.zb); S.pro[s].h.push_back(g);
             g.zb = hsk::choose_zb_even(g.n);
             g.blk_begin = bf2; bf2 += hsk::grid_blocks(g.n, g.zb); S.rfw[s].h.push_back(g);
@@ -381,6 +383,10 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
     for (int s = 0; s < Dmax; s++)
         if (!S.jac[s].finest && !S.jac[s].coarse_all) S.uniform = 0;
     if (Dmax > 0 && !S.jac[0].coarse_all && !S.fused_norm) S.uniform = 0;
+    // the finest grids' first two sweeps in one pass, when asked for (chunks
+    // of 127^3 and larger grids are long enough for the extra planes it forms)
+    S.two = (P->pb.mg.fused_sweeps == 2 && S.uniform && Dmax > 0 && !S.jac[0].coarse_all &&
+             S.jac[0].h[0].n >= 127) ? 1 : 0;
 }
 
 SdcSeg sdc_seg(hs_plan* P, int b, int L)
@@ -585,6 +591,7 @@ void layout(hs_plan* P, char* base)
             for (const MgSet* S : {&ls.mg64[L], &ls.mg32[L]}) {
                 upd(S->fine.nblk);
                 for (auto& t : S->jac) upd(t.nblk);
+                for (auto& t : S->pro) upd(t.nblk);
             }
         }
     };
@@ -653,6 +660,7 @@ hs_status validate(const hs_problem* pb)
     if (mg.fixed_cycles < 0 || mg.max_cycles < 0 || mg.max_cycles > 100000) return HS_EINVAL;
     if (mg.fixed_cycles == 0 && !(mg.tol > 0.0)) return HS_EINVAL;
     if (mg.precision == HS_MIXED && (mg.inner_nu1 < 1 || mg.inner_nu2 < 0)) return HS_EINVAL;
+    if (mg.fused_sweeps < 0 || mg.fused_sweeps > 2) return HS_EINVAL;
     if (pb->sweeps < 0 || pb->max_sweeps < 0) return HS_EINVAL;
     if (pb->sweeps == 0 && !(pb->sdc_tol > 0.0)) return HS_EINVAL;
     if (pb->nslices < 1) return HS_EINVAL;
@@ -740,13 +748,15 @@ hs_status vcycle_unfused(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, i
 // The residual is restricted in the same pass that forms it, and the
 // prolongated correction is applied as the first post-smoothing sweep reads
 // its input (nu2 >= 1).  The finest grids start in buffer *par and end in
-// *par ^ ((nu1 + nu2) & 1), written back to *par.  first_done: the finest
-// grids' first sweep already ran (fused with the residual norm).
+// *par ^ (number of passes that wrote it), written back to *par.
+// first_done: number of the finest grids' sweeps that already ran in one
+// pass with the residual norm (1, or 2 for the two-sweep pass).  On grids
+// with S.two the first two sweeps run as one pass.
 template <typename T>
 hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
-                 bool first_done, int* par, hipStream_t s)
+                 int first_done, int* par, hipStream_t s)
 {
-    if (!S.uniform) return vcycle_unfused<T>(P, S, order, A, nu1, nu2, first_done, s);
+    if (!S.uniform) return vcycle_unfused<T>(P, S, order, A, nu1, nu2, first_done != 0, s);
     const bool pj = nu2 >= 1;
     std::vector<int> loc(S.D);
     for (int st = 0; st < S.D; st++) {
@@ -755,9 +765,15 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
         if (!J.coarse_all) {
             cur = *par;
             int k0 = 0;
-            if (st == 0 && first_done) {
+            if (first_done) {
+                // one pass (the sweep with the norm, or the two-sweep pass) already ran
                 cur ^= 1;
-                k0 = 1;
+                k0 = first_done;
+            } else if (S.two && nu1 >= 2) {
+                const Table<GridSeg>& J2 = S.pro[st];
+                HS_TRY(hsk::jac2<T>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, cur, 0, 0, P->partials, s));
+                cur ^= 1;
+                k0 = 2;
             }
             for (int k = k0; k < nu1; k++, cur ^= 1)
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
@@ -808,7 +824,9 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
 // to the node fields.
 hs_status mg_finish(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int nu2, hipStream_t s)
 {
-    if (!S.uniform || S.D == 0 || S.jac[0].coarse_all || nu2 < 1 || !((nu1 + nu2) & 1)) return HS_OK;
+    if (!S.uniform || S.D == 0 || S.jac[0].coarse_all || nu2 < 1) return HS_OK;
+    const int writes = nu1 - (S.two && nu1 >= 2 ? 1 : 0) + nu2;   // passes that move the finest iterate
+    if (!(writes & 1)) return HS_OK;
     HS_TRY(hsk::mg_fixup(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, A, s));
     return HS_OK;
 }
@@ -827,13 +845,19 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         int par = 0;
         if (mg.fixed_cycles > 0) {
             for (int c = 0; c < mg.fixed_cycles; c++)
-                HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, false, &par, s));
+                HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, 0, &par, s));
             HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
             return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
         }
         for (int c = 0;; c++) {
             // residual norm before cycle c; fused with cycle c's first sweep when possible
-            if (S.fused_norm) {
+            const bool two = S.two && mg.nu1 >= 2;
+            if (S.fused_norm && two) {
+                const Table<GridSeg>& J2 = S.pro[0];
+                HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, par, 1, c, P->partials, s));
+                HS_TRY(hsk::mg_decide(P->ctl, J2.d, J2.nseg(), J2.nblk, P->partials, c, mg.tol,
+                                      mg.max_cycles, s));
+            } else if (S.fused_norm) {
                 const Table<GridSeg>& J = S.jac[0];
                 HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, par, 1, 1, c,
                                           P->partials, s));
@@ -855,7 +879,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                 }
             }
             if (c >= mg.max_cycles) break;
-            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, S.fused_norm != 0, &par, s));
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, S.fused_norm ? (two ? 2 : 1) : 0, &par, s));
         }
         return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
     }
@@ -883,7 +907,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             if (it >= limit) break;
         }
         int par32 = 0;
-        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, false, &par32, s));
+        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, 0, &par32, s));
         HS_TRY(hsk::ir_update(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, A, s));
     }
     if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, s));

@@ -35,7 +35,7 @@ class MgDesc(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("omega", C.c_double),
                 ("n_coarsest", C.c_int32), ("tol", C.c_double), ("max_cycles", C.c_int32),
                 ("fixed_cycles", C.c_int32), ("precision", C.c_int32), ("inner_nu1", C.c_int32),
-                ("inner_nu2", C.c_int32)]
+                ("inner_nu2", C.c_int32), ("fused_sweeps", C.c_int32)]
 
 
 class ProblemDesc(C.Structure):
@@ -170,6 +170,7 @@ class Problem:
     precision: int = HS_FP64
     inner_nu1: int = 2
     inner_nu2: int = 2
+    fused_sweeps: int = 1
     sweeps: int = 4
     sdc_tol: float = 1e-10
     max_sweeps: int = 20
@@ -186,7 +187,8 @@ class Problem:
         if self.coarse:
             d.lev[1] = LevelDesc(*self.coarse)
         d.mg = MgDesc(self.nu1, self.nu2, self.omega, self.n_coarsest, self.tol, self.max_cycles,
-                      self.fixed_cycles, self.precision, self.inner_nu1, self.inner_nu2)
+                      self.fixed_cycles, self.precision, self.inner_nu1, self.inner_nu2,
+                      self.fused_sweeps)
         d.sweeps, d.sdc_tol, d.max_sweeps = self.sweeps, self.sdc_tol, self.max_sweeps
         d.batch, d.nslices = self.batch, self.nslices
         keep = None

@@ -111,6 +111,42 @@ def test_mg_fixed_cycles_parity(torch, order, n):
         assert rel(got, ref) <= TOL, (n, b)
 
 
+@pytest.mark.parametrize("fused", [1, 2])
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("nu1,cycles", [(2, 2), (3, 1), (1, 2)])
+def test_mg_127_parity(torch, order, nu1, cycles, fused):
+    """127^3, with one sweep per pass and with the first two pre-smoothing
+    sweeps in one pass (fused_sweeps = 2)."""
+    hs = heatst_mod()
+    n = 127
+    a = 0.0012
+    plan = hs.Plan(hs.Problem(n=n, order=order, nnodes=3, nu1=nu1, nu2=1, fixed_cycles=cycles,
+                              fused_sweeps=fused))
+    b = inputs.random_field(n, 131)
+    u0 = inputs.random_smooth(n, 132)
+    u = dev(torch, u0)
+    plan.mg_vcycle(u, dev(torch, b), a)
+    ref, st, cyc, rho = oracle.mg_solve(b, order, a, u0=u0, mg=oracle.mg_params(nu1=nu1, nu2=1, fixed_cycles=cycles))
+    assert rel(host(u).reshape(n, n, n), ref) <= TOL
+
+
+@pytest.mark.parametrize("fused", [1, 2])
+@pytest.mark.parametrize("order", [2, 4])
+def test_mg_127_tolerance_parity(torch, order, fused):
+    hs = heatst_mod()
+    n = 127
+    a = 0.0009
+    plan = hs.Plan(hs.Problem(n=n, order=order, nnodes=3, tol=1e-12, max_cycles=60, fused_sweeps=fused))
+    b = inputs.random_smooth(n, 141)
+    u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    plan.mg_vcycle(u, dev(torch, b), a)
+    st, stats = plan.stats()
+    ref, s, cyc, rho = oracle.mg_solve(b, order, a, mg=oracle.mg_params(tol=1e-12, max_cycles=60))
+    assert s == oracle.OK
+    assert stats[0]["max_cycles"] == cyc
+    assert rel(host(u).reshape(n, n, n), ref) <= TOL
+
+
 @pytest.mark.parametrize("nu1,nu2,cycles", [(2, 1, 1), (2, 1, 2), (1, 1, 3), (2, 2, 2), (3, 0, 2), (1, 2, 1),
                                              (1, 0, 3)])
 def test_mg_cycle_shapes_parity(torch, nu1, nu2, cycles):
