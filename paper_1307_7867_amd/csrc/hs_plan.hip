@@ -849,6 +849,9 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
             return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
         }
+        // the host checks the lanes at the predicted cycle count, then every
+        // second cycle: a gated surplus cycle costs less than a stream round trip
+        int next_check = pred;
         for (int c = 0;; c++) {
             // residual norm before cycle c; fused with cycle c's first sweep when possible
             const bool two = S.two && mg.nu1 >= 2;
@@ -869,7 +872,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                 HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, P->partials, c,
                                       mg.tol, mg.max_cycles, s));
             }
-            if (c >= pred || c >= mg.max_cycles) {
+            if (c >= next_check || c >= mg.max_cycles) {
                 HS_CHECK(read_ctl(P, s));
                 if (synced) *synced = true;
                 int mc = 0;
@@ -877,6 +880,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                     pred = mc;
                     break;
                 }
+                next_check = c + 2;
             }
             if (c >= mg.max_cycles) break;
             HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, S.fused_norm ? (two ? 2 : 1) : 0, &par, s));
@@ -888,6 +892,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     const MgSet& S32 = ls.mg32[L];
     bool fixed = mg.fixed_cycles > 0;
     int limit = fixed ? mg.fixed_cycles : mg.max_cycles;
+    int next_check = pred;
     for (int it = 0;; it++) {
         if (fixed && it >= limit) break;
         HS_TRY(hsk::ir_resid(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, order, A,
@@ -895,7 +900,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         if (!fixed) {
             HS_TRY(hsk::mg_decide(P->ctl, S64.fine.d, S64.fine.nseg(), S64.fine.nblk, P->partials, it,
                                   mg.tol, limit, s));
-            if (it >= pred || it >= limit) {
+            if (it >= next_check || it >= limit) {
                 HS_CHECK(read_ctl(P, s));
                 if (synced) *synced = true;
                 int mc = 0;
@@ -903,6 +908,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                     pred = mc;
                     break;
                 }
+                next_check = it + 2;
             }
             if (it >= limit) break;
         }
