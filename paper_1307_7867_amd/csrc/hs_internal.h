@@ -53,6 +53,9 @@ struct GridSeg {
     int32_t nc;             // next coarser grid (0 if none)
     int32_t coarse;         // 1: correction grid whose first sweep starts from zero
     int32_t zb;             // z planes per block of the launch using this table
+    int32_t moves;          // finest-grid tables: 1 if the grid lies above the coarse tail (its
+                            // iterate changes buffer during a solve), else 0
+    int32_t pad;
     long long node_stride;  // elements per node for the finest grid, else 0
     void* u;                // iterate
     void* t;                // ping-pong partner of u
@@ -162,20 +165,25 @@ size_t tail_lds_bytes(int n0, int elem);  // LDS of the tail kernel whose top gr
 
 hipError_t set_constants(const LibConst& lc);
 
+// Source-buffer codes of the grid kernels: bit 0 picks t (else u) on the
+// finest grids, bit 1 on the correction grids (GridSeg::coarse); bit 2
+// (sweep only) leaves the correction grids untouched.  A table holds both
+// kinds when its lanes have hierarchies of different depth.
+inline int src_code(int finest_t, int coarse_t, int skip_coarse = 0)
+{
+    return (finest_t & 1) | ((coarse_t & 1) << 1) | (skip_coarse ? 4 : 0);
+}
+
 // Weighted-Jacobi sweep (mode 0) or residual r = b - A x written to the free
 // buffer (mode 1) over a z-marching table.  norm: also write per-block
 // maxima of |b - A x| (and |b| when cycle == 0) to partials (FP64 only).
-// src (mode 0 only): 0 = x is the buffer picked by src_is_t; 1 = x is the
-// zero-guess first sweep omega D^{-1} b formed on the fly.
+// src_is_t is a source-buffer code (src_code).  src (mode 0 only): 0 = x is
+// the buffer the code picks; 1 = on correction grids x is the zero-guess
+// first sweep omega D^{-1} b formed on the fly (finest grids as with 0).
 template <typename T>
 hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                  int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
                  double* partials, hipStream_t s, int src = 0);
-
-// full weighting of the residual held in the buffer selected by r_is_t
-template <typename T>
-hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,
-                       hipStream_t s);
 
 // Two weighted-Jacobi sweeps in one pass: dst = J(J(x)), x picked by
 // src_is_t, dst the other buffer.  norm: per-block maxima of the first
@@ -190,8 +198,9 @@ template <typename T>
 hipError_t pjac(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
                 hipStream_t s);
 
-// Copy the finest iterate from t back to u for the lanes whose solve ran an
-// odd number of V-cycles (when every cycle moves the iterate).
+// Copy the finest iterate from t back to u for the lanes whose grid moves
+// (GridSeg::moves) and whose solve ran an odd number of V-cycles (when every
+// cycle moves the iterate an odd number of times).
 hipError_t mg_fixup(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, hipStream_t s);
 
 // Residual b - A x (x picked by src_is_t) restricted by full weighting into
@@ -211,9 +220,10 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
 // when cycle == max_cycles or rho is not finite
 hipError_t mg_decide(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, const double* partials,
                      int cycle, double tol, int max_cycles, hipStream_t s);
-// max-norm residual of an FP64 solve into partials (tables without a fused sweep)
+// max-norm residual of an FP64 solve into partials (tables without a fused
+// sweep); bit 0 of src_is_t: the iterate of grids with GridSeg::moves is in t
 hipError_t mg_norm(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                   int cycle, double* partials, hipStream_t s);
+                   int cycle, double* partials, int src_is_t, hipStream_t s);
 // iterative refinement: r = b - A u in FP64, r32 = (float) r into the FP32
 // hierarchy, per-block maxima into partials
 hipError_t ir_resid(LaneCtl* ctl, const GridSeg* segs64, const GridSeg* segs32, int nseg, int nblk,

@@ -50,6 +50,12 @@ __device__ __forceinline__ int find_seg(const S* segs, int nseg, int lb)
     return lo;
 }
 
+// buffer picked by a source-buffer code for this segment (1 = t)
+__device__ __forceinline__ int seg_src(int code, const GridSeg& sg)
+{
+    return sg.coarse ? (code >> 1) & 1 : code & 1;
+}
+
 __host__ __device__ __forceinline__ int tiles_x(int n) { return (n + HS_TX - 1) / HS_TX; }
 __host__ __device__ __forceinline__ int tiles_y(int n) { return (n + HS_TY - 1) / HS_TY; }
 
@@ -563,13 +569,15 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
     if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    if ((src_is_t & 4) && sg.coarse) return;
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
     T* Tt = (T*)sg.t;
     const T* B = (const T*)sg.b;
-    const T* src = src_is_t ? Tt : U;
-    T* dst = src_is_t ? U : Tt;
+    const int st = seg_src(src_is_t, sg);
+    const T* src = st ? Tt : U;
+    T* dst = st ? U : Tt;
     SweepOp<T, ORDER, MODE, NORM> op;
     op.dst = dst;
     op.b = B;
@@ -590,7 +598,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     } else {
         __shared__ T pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
         const int i0 = q.i - (int)(threadIdx.x % HS_TX), j0 = q.j - (int)(threadIdx.x / HS_TX);
-        if constexpr (SRC == 1) {
+        if (SRC == 1 && sg.coarse) {
             SrcZeroJacobi<T, ORDER> S{B, op.a, op.om, n};
             lds_march_src<ORDER, T>(S, n, i0, j0, q.z0, q.z1, pl, op);
         } else {
@@ -606,41 +614,6 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
         }
     }
 }
-
-// Full weighting of the residual r held in the free buffer: one thread per
-// coarse point, cb(I) = sum over the 27 fine neighbours of 2I+1 of
-// (1/4,1/2,1/4)^3 r.
-template <typename T>
-__global__ void __launch_bounds__(HS_BLOCK) k_restrict_fw(const GridSeg* __restrict__ segs, int nseg,
-                                                          int nblk, const LaneCtl* __restrict__ ctl,
-                                                          hsk::MgArgs A, int r_is_t)
-{
-    int lb = xcd_remap(blockIdx.x, nblk);
-    int si = find_seg(segs, nseg, lb);
-    const GridSeg sg = segs[si];
-    if (A.gate && ctl[sg.lane].mg_state != 0) return;
-    int n = sg.n, nc = sg.nc;
-    Pos q = grid_pos(lb - sg.blk_begin, nc);
-    if (!q.in) return;
-    const T* r = r_is_t ? (const T*)sg.t : (const T*)sg.u + (long long)A.node * sg.node_stride;
-    const long long nn = (long long)n * n;
-    const T* c = r + lin(2 * q.i + 1, 2 * q.j + 1, 2 * q.k + 1, n);
-    const T w[3] = {T(0.25), T(0.5), T(0.25)};
-    T acc = T(0);
-#pragma unroll
-    for (int dz = -1; dz <= 1; dz++) {
-        T az = T(0);
-#pragma unroll
-        for (int dy = -1; dy <= 1; dy++) {
-            const T* row = c + dz * nn + (long long)dy * n;
-            T ay = (w[0] * row[-1] + w[1] * row[0]) + w[2] * row[1];
-            az += w[dy + 1] * ay;
-        }
-        acc += w[dz + 1] * az;
-    }
-    ((T*)sg.cb)[lin(q.i, q.j, q.k, nc)] = acc;
-}
-
 
 // Two weighted-Jacobi sweeps in one pass (temporal blocking, the
 // several-sweeps-per-pass remedy for the smoother's memory traffic):
@@ -691,8 +664,9 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
     const int nn = n * n;   // offsets stay below 2^31 for n <= 511
     T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
     T* Tt = (T*)sg.t;
-    const T* x = src_is_t ? Tt : U;
-    T* dst = src_is_t ? U : Tt;
+    const int st = seg_src(src_is_t, sg);
+    const T* x = st ? Tt : U;
+    T* dst = st ? U : Tt;
     const T* B = (const T*)sg.b;
     const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
     const T om = T(A.omega);
@@ -837,8 +811,8 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
 // own z window).  Per plane the residual goes to one of two LDS buffers; the
 // 128 coarse-point owners (waves 2-3) add the xy-weighted sum of the previous
 // plane's residual to their running z sum while the next one is formed, so a
-// plane costs one barrier.  Same operations, in the same order, as the
-// residual sweep followed by k_restrict_fw.
+// plane costs one barrier.  Per coarse point the weights are summed in the
+// order: x within a row, rows within a plane, planes.
 template <int ORDER>
 struct RfwTile {
     static constexpr int R = ORDER == 2 ? 1 : 2;
@@ -872,7 +846,7 @@ __global__ void __launch_bounds__(HS_BLOCK, 8) k_resid_fw(const GridSeg* __restr
     const int z0 = q.z0, zl = min(q.z1, n - 1);   // residual planes z0..zl
     const int nn = n * n;   // offsets stay below 2^31 for n <= 511
     const T* U = (const T*)sg.u + (long long)A.node * sg.node_stride;
-    const T* x = src_is_t ? (const T*)sg.t : U;
+    const T* x = seg_src(src_is_t, sg) ? (const T*)sg.t : U;
     const T* B = (const T*)sg.b;
     T* cb = (T*)sg.cb;
     const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
@@ -1108,7 +1082,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict_
     if (!q.in) return;
     T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
     T* Tt = (T*)sg.t;
-    const T* src = src_is_t ? Tt : U;
+    const T* src = seg_src(src_is_t, sg) ? Tt : U;
     T* dst = dst_is_t ? Tt : U;
     const T* cu = (const T*)sg.cu;
     const int ncc = nc * nc;
@@ -1187,8 +1161,9 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
     const int nn = n * n, ncc = nc * nc;   // offsets stay below 2^31 for n <= 511
     T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
     T* Tt = (T*)sg.t;
-    const T* x = src_is_t ? Tt : U;
-    T* dst = src_is_t ? U : Tt;
+    const int st = seg_src(src_is_t, sg);
+    const T* x = st ? Tt : U;
+    T* dst = st ? U : Tt;
     const T* B = (const T*)sg.b;
     const T* cu = (const T*)sg.cu;
     const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
@@ -1317,7 +1292,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_fixup(const GridSeg* __restrict
     int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
     const LaneCtl& c = ctl[sg.lane];
-    if (c.mg_state == 3 || (c.mg_cycle & 1) == 0) return;
+    if (!sg.moves || c.mg_state == 3 || (c.mg_cycle & 1) == 0) return;
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     if (!q.in) return;
@@ -1724,7 +1699,7 @@ template <int ORDER>
 __global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict__ segs, int nseg,
                                                       int nblk, const LaneCtl* __restrict__ ctl,
                                                       hsk::MgArgs A, int cycle,
-                                                      double* __restrict__ partials)
+                                                      double* __restrict__ partials, int src_is_t)
 {
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(segs, nseg, lb);
@@ -1732,7 +1707,8 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict_
     if (ctl[sg.lane].mg_state != 0) return;
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
-    const double* u = (const double*)sg.u + (long long)A.node * sg.node_stride;
+    const double* u = (sg.moves && (src_is_t & 1)) ? (const double*)sg.t
+                                                  : (const double*)sg.u + (long long)A.node * sg.node_stride;
     struct Op {
         const double* b;
         double a;
@@ -2392,15 +2368,6 @@ hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int orde
 }
 
 template <typename T>
-hipError_t restrict_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int r_is_t,
-                       hipStream_t s)
-{
-    if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_restrict_fw<T>), g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, a, r_is_t);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t jac2(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
                 int norm, int cycle, double* partials, hipStream_t s)
 {
@@ -2463,8 +2430,6 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
 
 template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
 template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
-template hipError_t restrict_fw<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
-template hipError_t restrict_fw<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, hipStream_t);
 template hipError_t jac2<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
 template hipError_t jac2<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
 template hipError_t pjac<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
@@ -2486,11 +2451,11 @@ hipError_t mg_decide(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, cons
 }
 
 hipError_t mg_norm(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                   int cycle, double* partials, hipStream_t s)
+                   int cycle, double* partials, int src_is_t, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
     HS_ORDER_DISPATCH(order, (k_mg_norm<2>), (k_mg_norm<4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
-                      a, cycle, partials);
+                      a, cycle, partials, src_is_t);
     return hipGetLastError();
 }
 

@@ -176,14 +176,15 @@ struct Table {
 // multigrid tables of one SDC level, one precision, one set of lanes
 struct MgSet {
     int D = 0;                            // down steps above the tail
-    std::vector<Table<GridSeg>> jac, rr, pro;  // z-marching sweeps, restriction, prolongation (and
-                                               // the two-sweep kernel on the finest grids)
+    std::vector<Table<GridSeg>> jac, pro;      // z-marching sweeps, prolongation (and the
+                                               // two-sweep kernel on the finest grids)
     std::vector<Table<GridSeg>> rfw;           // fused residual + restriction (even z chunks)
     Table<TailSeg> tail;
     size_t tail_lds = 0;                  // LDS bytes of the tail kernel
     Table<GridSeg> fine;                  // finest grids (norms, refinement), z-marching
     int fused_norm = 0;                   // jac[0] holds every lane's finest grid
     int uniform = 0;                      // every stage holds only finest or only correction grids
+    int moves = 0;                        // some finest grid lies above the tail
     int two = 0;                          // the finest grids' first two sweeps run as one pass
 };
 
@@ -226,7 +227,7 @@ struct hs_plan {
     bool run_dirty = true;
     // device storage for the run set's tables, room for every lane in each
     struct RunStore {
-        std::vector<GridSeg*> grid[2][2];      // [level][fp32]: jac/rr/pro per step, then fine
+        std::vector<GridSeg*> grid[2][2];      // [level][fp32]: jac/pro/rfw per stage, then fine
         TailSeg* tail[2][2];
         SdcSeg* sdc[2];
         FasSeg *fasc, *fasf;
@@ -293,7 +294,6 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
     for (int b : ls.lanes) Dmax = std::max(Dmax, tail_start(P->lanes[b].grids[L]));
     S.D = Dmax;
     S.jac.assign(Dmax, {});
-    S.rr.assign(Dmax, {});
     S.pro.assign(Dmax, {});
     S.rfw.assign(Dmax, {});
     auto grid_ptrs = [&](const LaneBufs& lb, int l, void** u, void** t, void** b) {
@@ -306,7 +306,7 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         }
     };
     for (int s = 0; s < Dmax; s++) {
-        int bj = 0, br = 0, bp = 0, bf2 = 0;
+        int bj = 0, bp = 0, bf2 = 0;
         for (int b : ls.lanes) {
             const LaneBufs& lb = P->lanes[b];
             int Db = tail_start(lb.grids[L]);
@@ -326,8 +326,6 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             g.cb = cb;
             g.zb = hsk::choose_zb(g.n);
             g.blk_begin = bj; bj += hsk::grid_blocks(g.n, g.zb); S.jac[s].h.push_back(g);
-            g.zb = 1;
-            g.blk_begin = br; br += hsk::grid_blocks(g.nc); S.rr[s].h.push_back(g);
             g.zb = hsk::choose_zb_two(g.n);   // also the two-sweep kernel's table
             g.blk_begin = bp; bp += hsk::grid_blocks(g.n, g.zb); S.pro[s].h.push_back(g);
             g.zb = hsk::choose_zb_even(g.n);
@@ -340,7 +338,6 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             if (g.coarse) S.jac[s].finest = 0;
             else S.jac[s].coarse_all = 0;
         }
-        S.rr[s].nblk = br;
         S.pro[s].nblk = bp;
         S.rfw[s].nblk = bf2;
     }
@@ -372,6 +369,8 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         f.coarse = fp32 ? 1 : 0;
         f.node_stride = fp32 ? 0 : lb.N[L];
         f.zb = hsk::choose_zb(f.n);
+        f.moves = (Db > 0 && !fp32) ? 1 : 0;
+        S.moves |= f.moves;
         grid_ptrs(lb, 0, &f.u, &f.t, &f.b);
         f.blk_begin = bf;
         bf += hsk::grid_blocks(f.n, f.zb);
@@ -453,7 +452,6 @@ void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
         finish_table(ls.sdc[L], bump);
         for (MgSet* S : {&ls.mg64[L], &ls.mg32[L]}) {
             for (auto& t : S->jac) finish_table(t, bump);
-            for (auto& t : S->rr) finish_table(t, bump);
             for (auto& t : S->pro) finish_table(t, bump);
             for (auto& t : S->rfw) finish_table(t, bump);
             finish_table(S->tail, bump);
@@ -539,7 +537,7 @@ void layout(hs_plan* P, char* base)
         for (int f = 0; f < 2; f++) {
             const MgSet& S = f ? P->all.mg32[L] : P->all.mg64[L];
             P->store.grid[L][f].clear();
-            for (int t = 0; t < 4 * S.D + 1; t++) P->store.grid[L][f].push_back(bump.arr<GridSeg>(P->B));
+            for (int t = 0; t < 3 * S.D + 1; t++) P->store.grid[L][f].push_back(bump.arr<GridSeg>(P->B));
             P->store.tail[L][f] = bump.arr<TailSeg>(P->B);
         }
         P->store.sdc[L] = bump.arr<SdcSeg>(P->B);
@@ -615,7 +613,6 @@ hipError_t upload_set(hs_plan* P, const LaneSet& ls, hipStream_t s)
         if ((e = upload(ls.sdc[L], s)) != hipSuccess) return e;
         for (const MgSet* S : {&ls.mg64[L], &ls.mg32[L]}) {
             for (auto& t : S->jac) if ((e = upload(t, s)) != hipSuccess) return e;
-            for (auto& t : S->rr) if ((e = upload(t, s)) != hipSuccess) return e;
             for (auto& t : S->pro) if ((e = upload(t, s)) != hipSuccess) return e;
             for (auto& t : S->rfw) if ((e = upload(t, s)) != hipSuccess) return e;
             if ((e = upload(S->tail, s)) != hipSuccess) return e;
@@ -703,42 +700,6 @@ bool all_sdc_done(hs_plan* P, const LaneSet& ls)
     return true;
 }
 
-// One V(nu1,nu2) cycle over the tables of S.  first_done: the first
-// pre-smoothing sweep of step 0 has already run (fused with the norm).
-// One V(nu1, nu2) cycle over the grids above the tail (section 1.2), tables
-// whose stages mix finest and correction grids: every sweep is its own launch.
-template <typename T>
-hs_status vcycle_unfused(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
-                         bool first_done, hipStream_t s)
-{
-    for (int st = 0; st < S.D; st++) {
-        const Table<GridSeg>& J = S.jac[st];
-        for (int k = (st == 0 && first_done) ? 1 : 0; k < nu1; k++)
-            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, k == 0, k & 1, J.finest, 0, 0,
-                                 P->partials, s));
-        // residual into the free buffer, then full weighting
-        int in_t = nu1 & 1;
-        HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 1, 0, in_t, 1, 0, 0, P->partials, s));
-        const Table<GridSeg>& R = S.rr[st];
-        HS_TRY(hsk::restrict_fw<T>(P->ctl, R.d, R.nseg(), R.nblk, A, !in_t, s));
-    }
-    HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, S.tail_lds, s));
-    for (int st = S.D - 1; st >= 0; st--) {
-        int in_t = nu1 & 1;
-        int dst_t = ((nu1 + nu2) & 1) ? !in_t : in_t;
-        const Table<GridSeg>& Pr = S.pro[st];
-        HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, in_t, dst_t, s));
-        int cur = dst_t;
-        const Table<GridSeg>& J = S.jac[st];
-        for (int k = 0; k < nu2; k++) {
-            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
-                                 P->partials, s));
-            cur = !cur;
-        }
-    }
-    return HS_OK;
-}
-
 // One V(nu1, nu2) cycle over the grids above the tail (section 1.2).  Each
 // grid keeps its iterate in one of two buffers (0 = u, 1 = t) and every sweep
 // moves it to the other one.  Correction grids start from zero: their first
@@ -748,7 +709,11 @@ hs_status vcycle_unfused(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, i
 // The residual is restricted in the same pass that forms it, and the
 // prolongated correction is applied as the first post-smoothing sweep reads
 // its input (nu2 >= 1).  The finest grids start in buffer *par and end in
-// *par ^ (number of passes that wrote it), written back to *par.
+// *par ^ (number of passes that wrote it), written back to *par.  When the
+// lanes' hierarchies differ in depth a stage holds finest grids of some lanes
+// and correction grids of others: each launch then picks the buffer per grid
+// role, and the finest grids' first sweep runs alone so that both kinds
+// reach their second sweep in the same launch.
 // first_done: number of the finest grids' sweeps that already ran in one
 // pass with the residual norm (1, or 2 for the two-sweep pass).  On grids
 // with S.two the first two sweeps run as one pass.
@@ -756,66 +721,75 @@ template <typename T>
 hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
                  int first_done, int* par, hipStream_t s)
 {
-    if (!S.uniform) return vcycle_unfused<T>(P, S, order, A, nu1, nu2, first_done != 0, s);
     const bool pj = nu2 >= 1;
-    std::vector<int> loc(S.D);
+    // correction grids: passes that write them, and the buffer of their first
+    // (virtual) iterate that makes the last write land in u
+    const int writes_c = (nu1 >= 2 ? nu1 - 1 : 1) + (pj ? nu2 : 0);
+    const int cc0 = pj ? !((writes_c - 1) & 1) : 1;
+    std::vector<int> locf(S.D), locc(S.D);
     for (int st = 0; st < S.D; st++) {
         const Table<GridSeg>& J = S.jac[st];
-        int cur;
-        if (!J.coarse_all) {
-            cur = *par;
+        const bool hasF = !J.coarse_all, hasC = !J.finest;
+        int cf = *par, cc = cc0;
+        auto code = [&](int skip = 0) { return hsk::src_code(cf, cc, skip); };
+        if (!hasC) {
             int k0 = 0;
             if (first_done) {
                 // one pass (the sweep with the norm, or the two-sweep pass) already ran
-                cur ^= 1;
+                cf ^= 1;
                 k0 = first_done;
             } else if (S.two && nu1 >= 2) {
                 const Table<GridSeg>& J2 = S.pro[st];
-                HS_TRY(hsk::jac2<T>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, cur, 0, 0, P->partials, s));
-                cur ^= 1;
+                HS_TRY(hsk::jac2<T>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, code(), 0, 0, P->partials, s));
+                cf ^= 1;
                 k0 = 2;
             }
-            for (int k = k0; k < nu1; k++, cur ^= 1)
-                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
+            for (int k = k0; k < nu1; k++, cf ^= 1)
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 1, 0, 0,
+                                     P->partials, s));
+        } else if (nu1 >= 2) {
+            // finest grids' first sweep alone, then the correction grids' second
+            // sweep from their zero-guess first one, next to the finest grids' second
+            if (hasF) {
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(1), 0, 0, 0,
+                                     P->partials, s));
+                cf ^= 1;
+            }
+            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 0, 0, 0,
+                                 P->partials, s, 1));
+            cf ^= 1; cc ^= 1;
+            for (int k = 2; k < nu1; k++, cf ^= 1, cc ^= 1)
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 0, 0, 0,
                                      P->partials, s));
         } else {
-            const int writes = nu1 - (nu1 >= 2 ? 1 : 0) + (pj ? nu2 : 0);
-            cur = pj ? !((writes - 1) & 1) : 1;
-            if (nu1 >= 2) {
-                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, 0, 0, 0,
-                                     P->partials, s, 1));
-                cur ^= 1;
-                for (int k = 2; k < nu1; k++, cur ^= 1)
-                    HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, 0, 0, 0,
-                                         P->partials, s));
-            } else {
-                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, cur, 0, 0, 0,
-                                     P->partials, s));
-                cur ^= 1;
-            }
+            HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, code(), 0, 0, 0,
+                                 P->partials, s));
+            cf ^= 1; cc ^= 1;
         }
-        loc[st] = cur;
+        locf[st] = cf;
+        locc[st] = cc;
         // residual restricted by full weighting in one pass
         const Table<GridSeg>& RF = S.rfw[st];
-        HS_TRY(hsk::resid_fw<T>(P->ctl, RF.d, RF.nseg(), RF.nblk, order, A, cur, s));
+        HS_TRY(hsk::resid_fw<T>(P->ctl, RF.d, RF.nseg(), RF.nblk, order, A, code(), s));
     }
     HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, S.tail_lds, s));
     for (int st = S.D - 1; st >= 0; st--) {
         const Table<GridSeg>& J = S.jac[st];
-        int cur = loc[st];
+        int cf = locf[st], cc = locc[st];
+        auto code = [&]() { return hsk::src_code(cf, cc); };
         if (pj) {
-            HS_TRY(hsk::pjac<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, cur, s));
-            cur ^= 1;
-            for (int k = 1; k < nu2; k++, cur ^= 1)
-                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, cur, J.finest, 0, 0,
+            HS_TRY(hsk::pjac<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, code(), s));
+            cf ^= 1; cc ^= 1;
+            for (int k = 1; k < nu2; k++, cf ^= 1, cc ^= 1)
+                HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), J.finest, 0, 0,
                                      P->partials, s));
         } else {
             // no post-smoothing: the corrected iterate goes to u
             const Table<GridSeg>& Pr = S.pro[st];
-            HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, cur, 0, s));
-            cur = 0;
+            HS_TRY(hsk::prolong<T>(P->ctl, Pr.d, Pr.nseg(), Pr.nblk, A, code(), 0, s));
+            cf = cc = 0;
         }
-        if (!J.coarse_all) *par = cur;
+        if (!J.coarse_all) *par = cf;
     }
     return HS_OK;
 }
@@ -824,7 +798,7 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
 // to the node fields.
 hs_status mg_finish(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int nu2, hipStream_t s)
 {
-    if (!S.uniform || S.D == 0 || S.jac[0].coarse_all || nu2 < 1) return HS_OK;
+    if (!S.moves || nu2 < 1) return HS_OK;
     const int writes = nu1 - (S.two && nu1 >= 2 ? 1 : 0) + nu2;   // passes that move the finest iterate
     if (!(writes & 1)) return HS_OK;
     HS_TRY(hsk::mg_fixup(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, A, s));
@@ -857,18 +831,19 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             const bool two = S.two && mg.nu1 >= 2;
             if (S.fused_norm && two) {
                 const Table<GridSeg>& J2 = S.pro[0];
-                HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, par, 1, c, P->partials, s));
+                HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, hsk::src_code(par, 0), 1, c,
+                                         P->partials, s));
                 HS_TRY(hsk::mg_decide(P->ctl, J2.d, J2.nseg(), J2.nblk, P->partials, c, mg.tol,
                                       mg.max_cycles, s));
             } else if (S.fused_norm) {
                 const Table<GridSeg>& J = S.jac[0];
-                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, par, 1, 1, c,
-                                          P->partials, s));
+                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(par, 0), 1,
+                                          1, c, P->partials, s));
                 HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, P->partials, c, mg.tol,
                                       mg.max_cycles, s));
             } else {
                 HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, c,
-                                    P->partials, s));
+                                    P->partials, par, s));
                 HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, P->partials, c,
                                       mg.tol, mg.max_cycles, s));
             }
@@ -978,12 +953,11 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
             // the run set never holds deeper lanes than the full set
             if (S.D > A.D) return HS_ESTATE;
             for (int st = 0; st < S.D; st++) {
-                S.jac[st].d = P->store.grid[L][f][4 * st];
-                S.rr[st].d = P->store.grid[L][f][4 * st + 1];
-                S.pro[st].d = P->store.grid[L][f][4 * st + 2];
-                S.rfw[st].d = P->store.grid[L][f][4 * st + 3];
+                S.jac[st].d = P->store.grid[L][f][3 * st];
+                S.pro[st].d = P->store.grid[L][f][3 * st + 1];
+                S.rfw[st].d = P->store.grid[L][f][3 * st + 2];
             }
-            S.fine.d = P->store.grid[L][f][4 * A.D];
+            S.fine.d = P->store.grid[L][f][3 * A.D];
             S.tail.d = P->store.tail[L][f];
             if (S.fine.h.empty()) S.fine.d = nullptr;
             if (S.tail.h.empty()) S.tail.d = nullptr;

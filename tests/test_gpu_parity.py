@@ -166,6 +166,46 @@ def test_mg_cycle_shapes_parity(torch, nu1, nu2, cycles):
         assert rel(got, ref) <= TOL, (b, nu1, nu2, cycles)
 
 
+@pytest.mark.parametrize("nu1,nu2,cycles", [(2, 1, 2), (2, 1, 3), (1, 1, 3), (3, 2, 2), (3, 0, 2), (1, 0, 1)])
+def test_mg_uneven_depth_shapes_parity(torch, nu1, nu2, cycles):
+    """Lanes whose hierarchies differ in depth (63, 31, 15 and 127): a stage
+    holds the finest grid of one lane next to correction grids of deeper
+    lanes, and lanes whose finest grid is already in the coarse tail."""
+    hs = heatst_mod()
+    ns, order = [63, 31, 15, 127], 4
+    a = [0.004, 0.0007, 0.01, 0.0012]
+    plan = hs.Plan(hs.Problem(n=31, order=order, nnodes=3, batch=len(ns), lane_n=ns, nu1=nu1, nu2=nu2,
+                              fixed_cycles=cycles))
+    bs = [inputs.random_field(n, 180 + b) for b, n in enumerate(ns)]
+    us = [inputs.random_smooth(n, 190 + b) for b, n in enumerate(ns)]
+    u = dev(torch, np.concatenate([x.ravel() for x in us]))
+    plan.mg_vcycle(u, dev(torch, np.concatenate([x.ravel() for x in bs])), a)
+    for b, got in enumerate(split(host(u), ns)):
+        ref, st, cyc, rho = oracle.mg_solve(bs[b], order, a[b], u0=us[b],
+                                            mg=oracle.mg_params(nu1=nu1, nu2=nu2, fixed_cycles=cycles))
+        assert rel(got, ref) <= TOL, (ns[b], nu1, nu2, cycles)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_mg_uneven_depth_tolerance_parity(torch, order):
+    """Tolerance-driven solves over lanes of different depth: each lane stops
+    at its own cycle count and its iterate ends in the caller's buffer."""
+    hs = heatst_mod()
+    ns = [63, 15, 31]
+    a = [0.003, 0.02, 0.0005]
+    plan = hs.Plan(hs.Problem(n=31, order=order, nnodes=3, batch=len(ns), lane_n=ns, tol=1e-12,
+                              max_cycles=80))
+    bs = [inputs.random_smooth(n, 150 + b) for b, n in enumerate(ns)]
+    u = torch.zeros(sum(n ** 3 for n in ns), dtype=torch.float64, device="cuda")
+    plan.mg_vcycle(u, dev(torch, np.concatenate([x.ravel() for x in bs])), a)
+    st, stats = plan.stats()
+    for b, got in enumerate(split(host(u), ns)):
+        ref, s, cyc, rho = oracle.mg_solve(bs[b], order, a[b], mg=oracle.mg_params(tol=1e-12, max_cycles=80))
+        assert s == oracle.OK
+        assert stats[b]["max_cycles"] == cyc, ns[b]
+        assert rel(got, ref) <= TOL, ns[b]
+
+
 @pytest.mark.parametrize("order", [2, 4])
 def test_mg_tolerance_parity(torch, order):
     hs = heatst_mod()
