@@ -161,15 +161,53 @@ __device__ __forceinline__ T lap_scale(int n)
     return ORDER == 2 ? ih2 : ih2 / T(12);
 }
 
-// diagonal of A_a = I - a L_h at (i,j,k)
-template <int ORDER, typename T>
-__device__ __forceinline__ T diag_A(T a, int i, int j, int k, int n)
+// Global-memory pointer.  The grid pointers come from the segment tables, so
+// the compiler cannot tell they are global and would emit flat loads; those
+// count against the LDS wait counter as well, and every wait for an LDS read
+// would then also wait for the global loads in flight.  Kernels that mix LDS
+// traffic with global loads cast their grid pointers to this type.
+#define HS_G __attribute__((address_space(1)))
+
+// (90 - w) / 12, the 4th-order centre weight (in units of 1/h^2) of a point
+// next to w walls, as the division evaluates it
+template <typename T>
+__device__ __forceinline__ T centre4(int w)
 {
-    T ih2 = T((double)(n + 1) * (double)(n + 1));
-    if (ORDER == 2) return T(1) + a * ih2 * T(6);
-    int walls = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1) + (k == 0) + (k == n - 1);
-    return T(1) + a * ih2 * (T(90 - walls) / T(12));
+    return w == 0 ? T(90) / T(12) : w == 1 ? T(89) / T(12) : w == 2 ? T(88) / T(12) :
+           w == 3 ? T(87) / T(12) : w == 4 ? T(86) / T(12) : w == 5 ? T(85) / T(12) : T(84) / T(12);
 }
+
+// omega / D along the column (i, j) of an n^3 grid, D the diagonal of A_a.
+// D depends on the number of walls next to a point, which along a column
+// changes only on the planes z = 0 and z = n-1, so a column needs at most
+// three values; sweeps multiply by them instead of dividing per point.
+template <int ORDER, typename T>
+struct ColRd {
+    T r0 = T(0), r1 = T(0), r2 = T(0);   // 0, 1 and 2 walls along z
+    ColRd() = default;
+    __device__ __forceinline__ ColRd(T a, T om, int i, int j, int n)
+    {
+        const T ih2 = T((double)(n + 1) * (double)(n + 1));
+        if (ORDER == 2) {
+            r0 = r1 = r2 = om / (T(1) + a * ih2 * T(6));
+        } else {
+            const int w = (i == 0) + (i == n - 1) + (j == 0) + (j == n - 1);
+            r0 = om / (T(1) + a * ih2 * centre4<T>(w));
+            r1 = om / (T(1) + a * ih2 * centre4<T>(w + 1));
+            r2 = n == 1 ? om / (T(1) + a * ih2 * centre4<T>(w + 2)) : r1;
+        }
+    }
+    // Weighted sum with one weight 1 and the others 0 (exact: the values are
+    // finite).  A select between the members would be turned into a load at
+    // a computed member address, which keeps the enclosing object out of
+    // registers.
+    __device__ __forceinline__ T at(int z, int n) const
+    {
+        if (ORDER == 2) return r0;
+        const int wz = (z == 0) + (z == n - 1);
+        return (T(wz == 0) * r0 + T(wz == 1) * r1) + T(wz == 2) * r2;
+    }
+};
 
 template <typename T>
 struct Ld3 {
@@ -368,35 +406,38 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ c, int nc, int i, 
 }
 
 // Sources of the plane march: the value of the field the stencil is applied
-// to at grid point (i, j, z), linear index p.
+// to at grid point p (linear index) on plane z of a column whose handle
+// S.col(i, j) is taken once.
 template <typename T>
 struct SrcPlain {
-    const T* __restrict__ u;
-    __device__ __forceinline__ T at(long long p, int, int, int) const { return u[p]; }
+    const HS_G T* __restrict__ u;
+    struct Col {};
+    __device__ __forceinline__ Col col(int, int) const { return Col{}; }
+    __device__ __forceinline__ T at(long long p, const Col&, int) const { return u[p]; }
 };
 
 // The first weighted-Jacobi sweep from a zero guess, omega D^{-1} b,
 // evaluated where it is read instead of being stored.
 template <typename T, int ORDER>
 struct SrcZeroJacobi {
-    const T* __restrict__ b;
+    const HS_G T* __restrict__ b;
     T a, om;
     int n;
-    __device__ __forceinline__ T at(long long p, int i, int j, int z) const
-    {
-        return om * b[p] / diag_A<ORDER, T>(a, i, j, z, n);
-    }
+    using Col = ColRd<ORDER, T>;
+    __device__ __forceinline__ Col col(int i, int j) const { return Col(a, om, i, j, n); }
+    __device__ __forceinline__ T at(long long p, const Col& c, int z) const { return c.at(z, n) * b[p]; }
 };
 
-// value of the source at column (i, j), plane z' with the wall rules of the
-// stencil along z (pij = j n + i)
+// value of the source on the column with handle c (pij = j n + i) at plane
+// z' with the wall rules of the stencil along z
 template <int ORDER, typename T, class Src>
-__device__ __forceinline__ T zval_src(const Src& S, int i, int j, int z, int n, long long nn, long long pij)
+__device__ __forceinline__ T zval_src(const Src& S, const typename Src::Col& c, int z, int n, long long nn,
+                                      long long pij)
 {
-    if (z >= 0 && z < n) return S.at(pij + (long long)z * nn, i, j, z);
+    if (z >= 0 && z < n) return S.at(pij + (long long)z * nn, c, z);
     if (ORDER == 4) {
-        if (z == -2) return -S.at(pij, i, j, 0);
-        if (z == n + 1) return -S.at(pij + (long long)(n - 1) * nn, i, j, n - 1);
+        if (z == -2) return -S.at(pij, c, 0);
+        if (z == n + 1) return -S.at(pij + (long long)(n - 1) * nn, c, n - 1);
     }
     return T(0);
 }
@@ -482,14 +523,18 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
         hoff[h] = hin[h] ? (long long)gj * n + gi : 0;
     }
     const long long pij = (long long)j * n + i;
+    const typename Src::Col cc = S.col(i, j);
+    typename Src::Col hc[H::HPT];
+#pragma unroll
+    for (int h = 0; h < H::HPT; h++) hc[h] = S.col(hgi[h], hgj[h]);
     T w[2 * R + 1];
 #pragma unroll
-    for (int d = -R; d <= R; d++) w[d + R] = in ? zval_src<ORDER, T>(S, i, j, z0 + d, n, nn, pij) : T(0);
+    for (int d = -R; d <= R; d++) w[d + R] = in ? zval_src<ORDER, T>(S, cc, z0 + d, n, nn, pij) : T(0);
     {
         const long long pz = (long long)z0 * nn;
 #pragma unroll
         for (int h = 0; h < H::HPT; h++)
-            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? S.at(pz + hoff[h], hgi[h], hgj[h], z0) : T(0);
+            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? S.at(pz + hoff[h], hc[h], z0) : T(0);
         pl[0][ly + R][lx + R] = w[R];
     }
     __syncthreads();
@@ -500,8 +545,8 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
         const long long pz1 = (long long)(z + 1) * nn;
 #pragma unroll
         for (int h = 0; h < H::HPT; h++)
-            hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hgi[h], hgj[h], z + 1) : T(0);
-        T wn = (more && in) ? zval_src<ORDER, T>(S, i, j, z + R + 1, n, nn, pij) : T(0);
+            hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hc[h], z + 1) : T(0);
+        T wn = (more && in) ? zval_src<ORDER, T>(S, cc, z + R + 1, n, nn, pij) : T(0);
         if (in) {
             const T L = plane_lap<ORDER, T, H::LW>(&pl[buf][ly + R][lx + R], w, i, j, n);
             op((long long)z * nn + (long long)j * n + i, z, w[R], sc * L);
@@ -521,7 +566,7 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
 }
 
 template <int ORDER, typename T, typename Op>
-__device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int i0, int j0, int z0,
+__device__ __forceinline__ void lds_march(const HS_G T* __restrict__ src, int n, int i0, int j0, int z0,
                                           int z1, T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op)
 {
     SrcPlain<T> S{src};
@@ -534,17 +579,19 @@ __device__ __forceinline__ void lds_march(const T* __restrict__ src, int n, int 
 
 template <typename T, int ORDER, int MODE, int NORM>
 struct SweepOp {
-    T* __restrict__ dst;
-    const T* __restrict__ b;
-    T a, om;
-    int i, j, n;
+    HS_G T* __restrict__ dst;
+    const HS_G T* __restrict__ b;
+    T a;
+    ColRd<ORDER, T> rd;   // omega / D on this thread's column
+    int n;
     int cycle;
     double rmax, bmax;
+    __device__ __forceinline__ SweepOp(T a_, T om, int i, int j, int n_) : a(a_), rd(a_, om, i, j, n_), n(n_) {}
     __device__ __forceinline__ void operator()(long long p, int z, T c, T L)
     {
         T bp = b[p];
         T r = bp - (c - a * L);
-        if (MODE == 0) dst[p] = c + om * r / diag_A<ORDER, T>(a, i, j, z, n);
+        if (MODE == 0) dst[p] = c + rd.at(z, n) * r;
         else dst[p] = r;
         if (NORM) {
             rmax = nmax(rmax, (double)tabs(r));
@@ -572,20 +619,16 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     if ((src_is_t & 4) && sg.coarse) return;
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
-    T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
-    T* Tt = (T*)sg.t;
-    const T* B = (const T*)sg.b;
+    HS_G T* U = (HS_G T*)sg.u + (long long)A.node * sg.node_stride;
+    HS_G T* Tt = (HS_G T*)sg.t;
+    const HS_G T* B = (const HS_G T*)sg.b;
     const int st = seg_src(src_is_t, sg);
-    const T* src = st ? Tt : U;
-    T* dst = st ? U : Tt;
-    SweepOp<T, ORDER, MODE, NORM> op;
+    const HS_G T* src = st ? Tt : U;
+    HS_G T* dst = st ? U : Tt;
+    const T om = T(A.omega);
+    SweepOp<T, ORDER, MODE, NORM> op(T(lane_a(ctl, sg.lane, A.L, A.m)), om, q.i, q.j, n);
     op.dst = dst;
     op.b = B;
-    op.a = T(lane_a(ctl, sg.lane, A.L, A.m));
-    op.om = T(A.omega);
-    op.i = q.i;
-    op.j = q.j;
-    op.n = n;
     op.cycle = cycle;
     op.rmax = 0.0;
     op.bmax = 0.0;
@@ -593,13 +636,13 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
         if (q.in)
             for (int z = q.z0; z < q.z1; z++) {
                 long long p = lin(q.i, q.j, z, n);
-                dst[p] = op.om * B[p] / diag_A<ORDER, T>(op.a, q.i, q.j, z, n);
+                dst[p] = op.rd.at(z, n) * B[p];
             }
     } else {
         __shared__ T pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
         const int i0 = q.i - (int)(threadIdx.x % HS_TX), j0 = q.j - (int)(threadIdx.x / HS_TX);
         if (SRC == 1 && sg.coarse) {
-            SrcZeroJacobi<T, ORDER> S{B, op.a, op.om, n};
+            SrcZeroJacobi<T, ORDER> S{B, op.a, om, n};
             lds_march_src<ORDER, T>(S, n, i0, j0, q.z0, q.z1, pl, op);
         } else {
             lds_march<ORDER, T>(src, n, i0, j0, q.z0, q.z1, pl, op);
@@ -662,12 +705,12 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
     const int z0 = q.z0, z1 = q.z1;
     const bool in = i < n && j < n;
     const int nn = n * n;   // offsets stay below 2^31 for n <= 511
-    T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
-    T* Tt = (T*)sg.t;
+    HS_G T* U = (HS_G T*)sg.u + (long long)A.node * sg.node_stride;
+    HS_G T* Tt = (HS_G T*)sg.t;
     const int st = seg_src(src_is_t, sg);
-    const T* x = st ? Tt : U;
-    T* dst = st ? U : Tt;
-    const T* B = (const T*)sg.b;
+    const HS_G T* x = st ? Tt : U;
+    HS_G T* dst = st ? U : Tt;
+    const HS_G T* B = (const HS_G T*)sg.b;
     const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
     const T om = T(A.omega);
     const T sc = lap_scale<ORDER, T>(n);
@@ -687,6 +730,10 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
         vin[k] = vok[k] && vgi[k] >= 0 && vgi[k] < n && vgj[k] >= 0 && vgj[k] < n;
         vmain[k] = vin[k] && vx[k] >= R && vx[k] < R + HS_TX && vy[k] >= R && vy[k] < R + HS_TY;
     }
+    ColRd<ORDER, T> vrd[G::VPT] = {};
+#pragma unroll
+    for (int k = 0; k < G::VPT; k++) vrd[k] = ColRd<ORDER, T>(a, om, vgi[k], vgj[k], n);
+    const ColRd<ORDER, T> rd(a, om, i, j, n);
     // x cell outside the v region loaded by this thread
     int orow = -1, ocol = 0, ooff = 0, ogi = 0, ogj = 0;
     bool oin = false;
@@ -711,7 +758,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
         ooff = oin ? ogj * n + ogi : 0;
     }
     auto xz = [&](int gi, int gj, int zz) -> T {   // x at (gi, gj, zz) with the z wall rules
-        return zval_src<ORDER, T>(S, gi, gj, zz, n, nn, (long long)gj * n + gi);
+        return zval_src<ORDER, T>(S, S.col(gi, gj), zz, n, nn, (long long)gj * n + gi);
     };
     const int zs = z0 - R, ze = z1 - 1 + R;   // v planes formed by the block
     // z windows of the v points: x planes zs-R .. zs+R
@@ -751,7 +798,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
                     const T L = plane_lap<ORDER, T, G::UW>(&ub[zj & 1][vy[k] + R][vx[k] + R], wv[k], vgi[k],
                                                            vgj[k], n);
                     const T r = bv[k] - (c - a * (sc * L));
-                    v = c + om * r / diag_A<ORDER, T>(a, vgi[k], vgj[k], zj, n);
+                    v = c + vrd[k].at(zj, n) * r;
                     if (NORM && vmain[k] && zj >= z0 && zj < z1) {
                         rmax = nmax(rmax, (double)tabs(r));
                         if (cycle == 0) bmax = nmax(bmax, (double)tabs(bv[k]));
@@ -773,7 +820,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
             const T c = w2[R];
             const T L = plane_lap<ORDER, T, G::VW>(&vr[slot(zo)][yy][xx], w2, i, j, n);
             const T r = bo - (c - a * (sc * L));
-            dst[zo * nn + j * n + i] = c + om * r / diag_A<ORDER, T>(a, i, j, zo, n);
+            dst[zo * nn + j * n + i] = c + rd.at(zo, n) * r;
         }
         // x plane zj+1
         if (more) {
@@ -845,10 +892,10 @@ __global__ void __launch_bounds__(HS_BLOCK, 8) k_resid_fw(const GridSeg* __restr
     const int x0 = q.i - lx, y0 = q.j - ly;
     const int z0 = q.z0, zl = min(q.z1, n - 1);   // residual planes z0..zl
     const int nn = n * n;   // offsets stay below 2^31 for n <= 511
-    const T* U = (const T*)sg.u + (long long)A.node * sg.node_stride;
-    const T* x = seg_src(src_is_t, sg) ? (const T*)sg.t : U;
-    const T* B = (const T*)sg.b;
-    T* cb = (T*)sg.cb;
+    const HS_G T* U = (const HS_G T*)sg.u + (long long)A.node * sg.node_stride;
+    const HS_G T* x = seg_src(src_is_t, sg) ? (const HS_G T*)sg.t : U;
+    const HS_G T* B = (const HS_G T*)sg.b;
+    HS_G T* cb = (HS_G T*)sg.cb;
     const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
     const T sc = lap_scale<ORDER, T>(n);
     SrcPlain<T> S{x};
@@ -910,14 +957,14 @@ __global__ void __launch_bounds__(HS_BLOCK, 8) k_resid_fw(const GridSeg* __restr
     T w[2 * R + 1], we[2 * R + 1];
 #pragma unroll
     for (int d = -R; d <= R; d++) {
-        w[d + R] = in ? zval_src<ORDER, T>(S, i, j, z0 + d, n, nn, pij) : T(0);
-        we[d + R] = ein ? zval_src<ORDER, T>(S, ei, ej, z0 + d, n, nn, epij) : T(0);
+        w[d + R] = in ? zval_src<ORDER, T>(S, S.col(i, j), z0 + d, n, nn, pij) : T(0);
+        we[d + R] = ein ? zval_src<ORDER, T>(S, S.col(ei, ej), z0 + d, n, nn, epij) : T(0);
     }
     {
         const int pz = z0 * nn;
 #pragma unroll
         for (int h = 0; h < G::HPT; h++)
-            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? S.at(pz + hoff[h], hgi[h], hgj[h], z0) : T(0);
+            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? S.at(pz + hoff[h], S.col(0, 0), z0) : T(0);
         pl[0][ly + R][lx + R] = w[R];
     }
     __syncthreads();
@@ -954,9 +1001,9 @@ __global__ void __launch_bounds__(HS_BLOCK, 8) k_resid_fw(const GridSeg* __restr
         const int pz1 = (z + 1) * nn;
 #pragma unroll
         for (int h = 0; h < G::HPT; h++)
-            hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hgi[h], hgj[h], z + 1) : T(0);
-        const T wn = (more && in) ? zval_src<ORDER, T>(S, i, j, z + R + 1, n, nn, pij) : T(0);
-        const T wen = (more && ein) ? zval_src<ORDER, T>(S, ei, ej, z + R + 1, n, nn, epij) : T(0);
+            hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], S.col(0, 0), z + 1) : T(0);
+        const T wn = (more && in) ? zval_src<ORDER, T>(S, S.col(i, j), z + R + 1, n, nn, pij) : T(0);
+        const T wen = (more && ein) ? zval_src<ORDER, T>(S, S.col(ei, ej), z + R + 1, n, nn, epij) : T(0);
         // residual on the main and the extra points of plane z
         T r = T(0);
         if (in) {
@@ -1017,7 +1064,8 @@ struct ProlongXY {
     __device__ __forceinline__ T wy() const { return (f & 2) ? T(1) : T(0.5); }
     // row base pointers: `plane` points at coarse (0, 0) of the plane (any
     // origin shift folded in), `pitch` is the row length
-    __device__ __forceinline__ T at(const T* __restrict__ plane, int pitch) const
+    template <class P>
+    __device__ __forceinline__ T at(P plane, int pitch) const
     {
         const T wxv = wx();
         T sy = T(0);
@@ -1025,7 +1073,7 @@ struct ProlongXY {
         for (int cy = 0; cy < 2; cy++) {
             const bool vy = cy ? (f & 32) : (f & 16);
             if (!vy) continue;
-            const T* row = plane + (cy ? iy1() : iy0) * pitch;
+            const auto row = plane + (cy ? iy1() : iy0) * pitch;
             T sx = T(0);
             if (f & 4) sx += row[ix0];
             if (f & 8) sx += row[ix1()];
@@ -1052,7 +1100,8 @@ struct RingTap {
         o = (iy0 - oy0) * pitch + (ix0 - ox0);
         f = odx | (ody << 1);
     }
-    __device__ __forceinline__ T at(const T* __restrict__ plane, int pitch) const
+    template <class P>
+    __device__ __forceinline__ T at(P plane, int pitch) const
     {
         const T ex = (f & 1) ? T(0) : T(1), ey = (f & 2) ? T(0) : T(1);
         const T wx = (f & 1) ? T(1) : T(0.5), wy = (f & 2) ? T(1) : T(0.5);
@@ -1080,11 +1129,11 @@ __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict_
     const int n = sg.n, nc = sg.nc;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     if (!q.in) return;
-    T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
-    T* Tt = (T*)sg.t;
-    const T* src = seg_src(src_is_t, sg) ? Tt : U;
-    T* dst = dst_is_t ? Tt : U;
-    const T* cu = (const T*)sg.cu;
+    HS_G T* U = (HS_G T*)sg.u + (long long)A.node * sg.node_stride;
+    HS_G T* Tt = (HS_G T*)sg.t;
+    const HS_G T* src = seg_src(src_is_t, sg) ? Tt : U;
+    HS_G T* dst = dst_is_t ? Tt : U;
+    const HS_G T* cu = (const HS_G T*)sg.cu;
     const int ncc = nc * nc;
     const ProlongXY<T> xy(q.i, q.j, nc);
     // xy terms of the two most recent coarse planes
@@ -1159,13 +1208,13 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
     const int z0 = q.z0, z1 = q.z1;
     const bool in = i < n && j < n;
     const int nn = n * n, ncc = nc * nc;   // offsets stay below 2^31 for n <= 511
-    T* U = (T*)sg.u + (long long)A.node * sg.node_stride;
-    T* Tt = (T*)sg.t;
+    HS_G T* U = (HS_G T*)sg.u + (long long)A.node * sg.node_stride;
+    HS_G T* Tt = (HS_G T*)sg.t;
     const int st = seg_src(src_is_t, sg);
-    const T* x = st ? Tt : U;
-    T* dst = st ? U : Tt;
-    const T* B = (const T*)sg.b;
-    const T* cu = (const T*)sg.cu;
+    const HS_G T* x = st ? Tt : U;
+    HS_G T* dst = st ? U : Tt;
+    const HS_G T* B = (const HS_G T*)sg.b;
+    const HS_G T* cu = (const HS_G T*)sg.cu;
     const T a = T(lane_a(ctl, sg.lane, A.L, A.m));
     const T om = T(A.omega);
     const T sc = lap_scale<ORDER, T>(n);
@@ -1237,6 +1286,7 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
         kl = kt;
     }
     __syncthreads();
+    const ColRd<ORDER, T> rd(a, om, i, j, n);
     T w[2 * R + 1];
 #pragma unroll
     for (int d = -R; d <= R; d++) w[d + R] = in ? zv(mw, pij, z0 + d) : T(0);
@@ -1260,7 +1310,7 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
             const int p = z * nn + pij;
             const T c = w[R];
             const T r = B[p] - (c - a * (sc * L));
-            dst[p] = c + om * r / diag_A<ORDER, T>(a, i, j, z, n);
+            dst[p] = c + rd.at(z, n) * r;
         }
         const T wn = (more && in) ? zv(mw, pij, z + R + 1) : T(0);
         if (more) {
@@ -1296,8 +1346,8 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_fixup(const GridSeg* __restrict
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     if (!q.in) return;
-    double* U = (double*)sg.u + (long long)A.node * sg.node_stride;
-    const double* Tt = (const double*)sg.t;
+    HS_G double* U = (HS_G double*)sg.u + (long long)A.node * sg.node_stride;
+    const HS_G double* Tt = (const HS_G double*)sg.t;
     for (int z = q.z0; z < q.z1; z++) {
         int p = lin(q.i, q.j, z, n);
         U[p] = Tt[p];
@@ -1421,8 +1471,8 @@ __device__ __forceinline__ void lds_prolong_add(T* u, const T* c)
 // transform: x = S diag(1 / (1 - a (lam_i + lam_j + lam_k))) S b with the
 // orthonormal, symmetric 1-D transform S and the 1-D eigenvalues lam (both
 // staged in LDS); bh is LDS scratch of N^3 values.
-template <typename T, int N>
-__device__ __forceinline__ void lds_exact(const T* b, T* x, T a, const double* S, const double* lam,
+template <typename T, int N, class PB>
+__device__ __forceinline__ void lds_exact(PB b, T* x, T a, const double* S, const double* lam,
                                           double* bh)
 {
     constexpr int NN = N * N * N;
@@ -1563,8 +1613,8 @@ __device__ __forceinline__ void tail_run(const TailSeg& ts, const LaneCtl* __res
     double* s_lam = sh.lam;
     double* s_bh = sh.bh;
     const int t = (int)threadIdx.x;
-    T* gu0 = (T*)ts.u[0] + (long long)A.node * ts.node_stride;
-    const T* gb0 = (const T*)ts.b[0];
+    HS_G T* gu0 = (HS_G T*)ts.u[0] + (long long)A.node * ts.node_stride;
+    const HS_G T* gb0 = (const HS_G T*)ts.b[0];
     const bool zero_top = ts.zero_guess != 0;
     T b0[tail_q<N0>()];
     T u0[tail_q<N0>()];
@@ -1707,10 +1757,11 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict_
     if (ctl[sg.lane].mg_state != 0) return;
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
-    const double* u = (sg.moves && (src_is_t & 1)) ? (const double*)sg.t
-                                                  : (const double*)sg.u + (long long)A.node * sg.node_stride;
+    const HS_G double* u = (sg.moves && (src_is_t & 1))
+                               ? (const HS_G double*)sg.t
+                               : (const HS_G double*)sg.u + (long long)A.node * sg.node_stride;
     struct Op {
-        const double* b;
+        const HS_G double* b;
         double a;
         int cycle;
         double rmax, bmax;
@@ -1720,7 +1771,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict_
             rmax = nmax(rmax, fabs(bp - (c - a * L)));
             if (cycle == 0) bmax = nmax(bmax, fabs(bp));
         }
-    } op{(const double*)sg.b, lane_a(ctl, sg.lane, A.L, A.m), cycle, 0.0, 0.0};
+    } op{(const HS_G double*)sg.b, lane_a(ctl, sg.lane, A.L, A.m), cycle, 0.0, 0.0};
     __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
     lds_march<ORDER, double>(u, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX), q.z0,
                              q.z1, pl, op);
@@ -1748,10 +1799,10 @@ __global__ void __launch_bounds__(HS_BLOCK) k_ir_resid(const GridSeg* __restrict
     if (ctl[sg.lane].mg_state != 0) return;
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
-    const double* u = (const double*)sg.u + (long long)A.node * sg.node_stride;
+    const HS_G double* u = (const HS_G double*)sg.u + (long long)A.node * sg.node_stride;
     struct Op {
-        const double* b;
-        float* r32;
+        const HS_G double* b;
+        HS_G float* r32;
         double a;
         int iter;
         double rmax, bmax;
@@ -1763,7 +1814,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_ir_resid(const GridSeg* __restrict
             rmax = nmax(rmax, fabs(r));
             if (iter == 0) bmax = nmax(bmax, fabs(bp));
         }
-    } op{(const double*)sg.b, (float*)s32[si].b, lane_a(ctl, sg.lane, A.L, A.m), iter, 0.0, 0.0};
+    } op{(const HS_G double*)sg.b, (HS_G float*)s32[si].b, lane_a(ctl, sg.lane, A.L, A.m), iter, 0.0, 0.0};
     __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
     lds_march<ORDER, double>(u, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX), q.z0,
                              q.z1, pl, op);
@@ -1788,8 +1839,8 @@ __global__ void __launch_bounds__(HS_BLOCK) k_ir_update(const GridSeg* __restric
     int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     if (!q.in) return;
-    double* u = (double*)sg.u + (long long)A.node * sg.node_stride;
-    const float* e = (const float*)s32[si].u;
+    HS_G double* u = (HS_G double*)sg.u + (long long)A.node * sg.node_stride;
+    const HS_G float* e = (const HS_G float*)s32[si].u;
     for (int z = q.z0; z < q.z1; z++) {
         long long p = lin(q.i, q.j, z, n);
         u[p] += (double)e[p];
@@ -2292,12 +2343,14 @@ int grid_blocks(int n, int zb) { return tiles_x(n) * tiles_y(n) * ((n + zb - 1) 
 
 // z planes per block of the plane-marching kernels: as many as possible (up
 // to 8, fewer halo reloads and window warm-ups) while one grid still gives
-// 1024 blocks of 512 threads (16 waves per CU) to fill the chip.
+// 512 blocks of 512 threads (two per CU).  At 127^3 eight planes per block
+// (512 blocks) measured faster than four (1024 blocks): the chip is then
+// half occupied, but each block warms up its z window half as often.
 int choose_zb(int n)
 {
     long long tiles = (long long)tiles_x(n) * tiles_y(n);
     int zb = 8;
-    while (zb > 1 && tiles * ((n + zb - 1) / zb) < 1024) zb /= 2;
+    while (zb > 1 && tiles * ((n + zb - 1) / zb) < 512) zb /= 2;
     return zb;
 }
 
