@@ -871,8 +871,10 @@ struct RfwTile {
     static constexpr int NC = (HS_TX / 2) * (HS_TY / 2);        // coarse points per tile
 };
 
+// At most 6 waves per SIMD (up to 80 VGPRs): with a 64-register cap the
+// 4th-order kernel spilled.
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(HS_BLOCK, 8) k_resid_fw(const GridSeg* __restrict__ segs, int nseg,
+__global__ void __launch_bounds__(HS_BLOCK, 6) k_resid_fw(const GridSeg* __restrict__ segs, int nseg,
                                                        int nblk, const LaneCtl* __restrict__ ctl,
                                                        hsk::MgArgs A, int src_is_t)
 {
