@@ -41,10 +41,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1307_7867_amd", "csrc", "hs_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_fp64_order4_127.traffic.json")
 
 
-def problem(hs, fused_sweeps=1):
+def problem(hs, fused_sweeps=1, cycle_graphs=0):
     return hs.Problem(n=NF, order=4, nnodes=MF, coarse=(NC, 2, MC), nu=0.1, dt=0.05, t0=0.0,
                       forcing_c=3.0, nsteps=20, sweeps=ITERS, nu1=2, nu2=1, omega=6.0 / 7.0,
-                      n_coarsest=3, tol=1e-12, max_cycles=60, fused_sweeps=fused_sweeps)
+                      n_coarsest=3, tol=1e-12, max_cycles=60, fused_sweeps=fused_sweeps,
+                      cycle_graphs=cycle_graphs)
 
 
 def kernel_hash():
@@ -116,6 +117,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--fused-sweeps", type=int, default=1, choices=[1, 2],
                     help="2: run the finest grid's first two pre-smoothing sweeps as one pass")
+    ap.add_argument("--cycle-graphs", type=int, default=0, choices=[0, 1],
+                    help="1: replay the predicted cycles of each solve from HIP graphs (measured "
+                         "slower than launching every kernel from the host)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 512 MiB device copy (reference for byte counters)")
     args = ap.parse_args()
@@ -143,7 +147,7 @@ def main():
         out = getattr(workloads, args.workload)(args)
         print(json.dumps(out), flush=True)
         return
-    pb = problem(hs, args.fused_sweeps)
+    pb = problem(hs, args.fused_sweeps, args.cycle_graphs)
     plan = hs.Plan(pb)
     u0 = torch.from_numpy(inputs.sine_product(NF).ravel()).cuda()
 
@@ -207,7 +211,7 @@ def main():
                                "coarse 63^3 2nd-order 3 nodes, nu=0.1, dt=0.05, 3 iterations/step, "
                                "V(2,1) Jacobi 6/7 to 3^3, rel. residual 1e-12",
                    "fine_n": NF, "coarse_n": NC, "dt": pb.dt, "iterations_per_step": ITERS,
-                   "mg_tol": pb.tol, "fused_sweeps": pb.fused_sweeps},
+                   "mg_tol": pb.tol, "fused_sweeps": pb.fused_sweeps, "cycle_graphs": pb.cycle_graphs},
         "roofline": {"bound": "hbm", "kernel": "k_sweep<double, 4, 0, 1, 0, 0> (finest-grid weighted Jacobi) on 127^3",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,

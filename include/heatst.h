@@ -100,6 +100,13 @@ typedef struct {
                                 grids' first two pre-smoothing sweeps in one pass (temporal
                                 blocking; FP64, grids of 127^3 and up, nu1 >= 2; same results,
                                 measured slower than two passes on MI355X at 127^3 and 255^3) */
+    int32_t cycle_graphs;    /* 1: a tolerance-driven FP64 solve launches its first cycle from the
+                                host and replays cycles 1..pred-1 and the stopping test at pred
+                                (pred = the previous solve's cycle count at this node) as one HIP
+                                graph, captured on first use per (lane set, level, node, pred);
+                                later cycles are launched one by one.  0: every kernel is launched
+                                from the host.  Same results; with ROCm 7 on MI355X the graph
+                                replay measured slower (29.0 vs 27.8 ms per 127^3 MLSDC step). */
 } hs_mg_desc;
 
 typedef struct {

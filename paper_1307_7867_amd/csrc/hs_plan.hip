@@ -246,6 +246,18 @@ struct hs_plan {
     int state_ready = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // Graphs of the predicted part of tolerance-driven solves: cycles 1..K-1
+    // and the stopping test at K of one (lane set, level, substep, node).
+    struct CycleGraph {
+        const LaneSet* set;
+        unsigned epoch;
+        int L, m, node, K;
+        int par;                               // finest grids' buffer after the K cycles
+        hipGraphExec_t exec;
+    };
+    std::vector<CycleGraph> cgraphs;
+    unsigned set_epoch = 0;                    // bumped when a lane set's tables change
+    hipStream_t cap = nullptr;                 // capture stream (nothing runs on it)
 };
 
 namespace {
@@ -658,6 +670,7 @@ hs_status validate(const hs_problem* pb)
     if (mg.fixed_cycles == 0 && !(mg.tol > 0.0)) return HS_EINVAL;
     if (mg.precision == HS_MIXED && (mg.inner_nu1 < 1 || mg.inner_nu2 < 0)) return HS_EINVAL;
     if (mg.fused_sweeps < 0 || mg.fused_sweeps > 2) return HS_EINVAL;
+    if (mg.cycle_graphs < 0 || mg.cycle_graphs > 1) return HS_EINVAL;
     if (pb->sweeps < 0 || pb->max_sweeps < 0) return HS_EINVAL;
     if (pb->sweeps == 0 && !(pb->sdc_tol > 0.0)) return HS_EINVAL;
     if (pb->nslices < 1) return HS_EINVAL;
@@ -805,6 +818,58 @@ hs_status mg_finish(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int nu2,
     return HS_OK;
 }
 
+// Destroy the cycle graphs (all, or only those recorded over tables that
+// have since changed).  A graph may still be in flight: wait for the device.
+void drop_cycle_graphs(hs_plan* P, bool stale_only = false)
+{
+    bool any = false;
+    for (const auto& g : P->cgraphs) any |= !stale_only || g.epoch != P->set_epoch;
+    if (!any) return;
+    (void)hipDeviceSynchronize();
+    std::vector<hs_plan::CycleGraph> keep;
+    for (auto& g : P->cgraphs) {
+        if (!stale_only || g.epoch != P->set_epoch) (void)hipGraphExecDestroy(g.exec);
+        else keep.push_back(g);
+    }
+    P->cgraphs.swap(keep);
+}
+
+// The graph of cycles 1..K-1 and the stopping test at K of a solve over ls
+// (level L, substep m, node), captured by `record` on the plan's capture
+// stream on first use.  *par enters as the finest grids' buffer at cycle 1
+// and leaves as the buffer after the K cycles.
+template <class F>
+hs_status cycle_graph(hs_plan* P, const LaneSet& ls, int L, int m, int node, int K, hipGraphExec_t* exec,
+                      int* par, F record)
+{
+    for (const auto& g : P->cgraphs)
+        if (g.set == &ls && g.epoch == P->set_epoch && g.L == L && g.m == m && g.node == node && g.K == K) {
+            *exec = g.exec;
+            *par = g.par;
+            return HS_OK;
+        }
+    if (P->cgraphs.size() >= 64) drop_cycle_graphs(P);
+    if (!P->cap) HS_TRY(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+    HS_TRY(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+    int pg = *par;
+    hs_status st = record(P->cap, &pg);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P->cap, &g);
+    if (st != HS_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return st != HS_OK ? st : HS_EDEVICE;
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HS_TRY(e);
+    P->cgraphs.push_back({&ls, P->set_epoch, L, m, node, K, pg, ge});
+    *exec = ge;
+    *par = pg;
+    return HS_OK;
+}
+
 // Solve (I - a L) U_node = rhs for the lanes of ls at SDC level L; a from
 // the lane's a[L][m] (m >= 0) or a_user (m = -1).
 hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t s, bool* synced)
@@ -823,30 +888,56 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
             return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
         }
+        const bool two = S.two && mg.nu1 >= 2;
+        // residual norm and stopping test before cycle c; the norm is fused
+        // with cycle c's first sweep when possible
+        auto head = [&](int c, int pc, hipStream_t st) -> hs_status {
+            if (S.fused_norm && two) {
+                const Table<GridSeg>& J2 = S.pro[0];
+                HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, hsk::src_code(pc, 0), 1, c,
+                                         P->partials, st));
+                HS_TRY(hsk::mg_decide(P->ctl, J2.d, J2.nseg(), J2.nblk, P->partials, c, mg.tol,
+                                      mg.max_cycles, st));
+            } else if (S.fused_norm) {
+                const Table<GridSeg>& J = S.jac[0];
+                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(pc, 0), 1,
+                                          1, c, P->partials, st));
+                HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, P->partials, c, mg.tol,
+                                      mg.max_cycles, st));
+            } else {
+                HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, c,
+                                    P->partials, pc, st));
+                HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, P->partials, c,
+                                      mg.tol, mg.max_cycles, st));
+            }
+            return HS_OK;
+        };
+        const int first_done = S.fused_norm ? (two ? 2 : 1) : 0;
         // the host checks the lanes at the predicted cycle count, then every
         // second cycle: a gated surplus cycle costs less than a stream round trip
         int next_check = pred;
-        for (int c = 0;; c++) {
-            // residual norm before cycle c; fused with cycle c's first sweep when possible
-            const bool two = S.two && mg.nu1 >= 2;
-            if (S.fused_norm && two) {
-                const Table<GridSeg>& J2 = S.pro[0];
-                HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, hsk::src_code(par, 0), 1, c,
-                                         P->partials, s));
-                HS_TRY(hsk::mg_decide(P->ctl, J2.d, J2.nseg(), J2.nblk, P->partials, c, mg.tol,
-                                      mg.max_cycles, s));
-            } else if (S.fused_norm) {
-                const Table<GridSeg>& J = S.jac[0];
-                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(par, 0), 1,
-                                          1, c, P->partials, s));
-                HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, P->partials, c, mg.tol,
-                                      mg.max_cycles, s));
-            } else {
-                HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, c,
-                                    P->partials, par, s));
-                HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, P->partials, c,
-                                      mg.tol, mg.max_cycles, s));
-            }
+        int c = 0;
+        bool head_done = false;
+        if (mg.cycle_graphs && pred >= 2 && pred < mg.max_cycles) {
+            // cycle 0 from the host, then cycles 1..pred-1 and the test at
+            // pred from one graph, whose launch overlaps cycle 0
+            HS_CHECK(head(0, par, s));
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, first_done, &par, s));
+            hipGraphExec_t ge = nullptr;
+            HS_CHECK(cycle_graph(P, ls, L, m, node, pred, &ge, &par, [&](hipStream_t st, int* pp) -> hs_status {
+                for (int k = 1; k < pred; k++) {
+                    HS_CHECK(head(k, *pp, st));
+                    HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, first_done, pp, st));
+                }
+                return head(pred, *pp, st);
+            }));
+            HS_TRY(hipGraphLaunch(ge, s));
+            c = pred;
+            head_done = true;
+        }
+        for (;; c++) {
+            if (!head_done) HS_CHECK(head(c, par, s));
+            head_done = false;
             if (c >= next_check || c >= mg.max_cycles) {
                 HS_CHECK(read_ctl(P, s));
                 if (synced) *synced = true;
@@ -858,7 +949,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                 next_check = c + 2;
             }
             if (c >= mg.max_cycles) break;
-            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, S.fused_norm ? (two ? 2 : 1) : 0, &par, s));
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, first_done, &par, s));
         }
         return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
     }
@@ -946,6 +1037,7 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
     for (int b = 0; b < P->B; b++)
         if (P->active[b]) ls.lanes.push_back(b);
     build_set_host(P, ls);
+    P->set_epoch++;   // graphs recorded over the old tables are stale
     for (int L = 0; L < P->nlev; L++) {
         for (int f = 0; f < 2; f++) {
             MgSet& S = f ? ls.mg32[L] : ls.mg64[L];
@@ -970,6 +1062,7 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
     }
     HS_TRY(upload_set(P, ls, s));
     HS_TRY(hipStreamSynchronize(s));
+    drop_cycle_graphs(P, true);
     P->run_dirty = false;
     return HS_OK;
 }
@@ -1112,6 +1205,7 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
     HS_TRY(ensure_constants());
     HS_TRY(hipGetDevice(&P->device));
     P->ws = (char*)d_ws;
+    drop_cycle_graphs(P);
     layout(P, P->ws);
     if (!P->h_ctl) HS_TRY(hipHostMalloc((void**)&P->h_ctl, sizeof(LaneCtl) * P->B, hipHostMallocDefault));
     // sine tables sin(pi (i+1) h)
@@ -1152,6 +1246,8 @@ hs_status hs_plan_destroy(hs_plan* P)
     if (!P) return HS_EINVAL;
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
+    drop_cycle_graphs(P);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
     if (P->h_ctl) (void)hipHostFree(P->h_ctl);
     delete P;
     return HS_OK;

@@ -35,7 +35,7 @@ class MgDesc(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("omega", C.c_double),
                 ("n_coarsest", C.c_int32), ("tol", C.c_double), ("max_cycles", C.c_int32),
                 ("fixed_cycles", C.c_int32), ("precision", C.c_int32), ("inner_nu1", C.c_int32),
-                ("inner_nu2", C.c_int32), ("fused_sweeps", C.c_int32)]
+                ("inner_nu2", C.c_int32), ("fused_sweeps", C.c_int32), ("cycle_graphs", C.c_int32)]
 
 
 class ProblemDesc(C.Structure):
@@ -171,6 +171,7 @@ class Problem:
     inner_nu1: int = 2
     inner_nu2: int = 2
     fused_sweeps: int = 1
+    cycle_graphs: int = 0
     sweeps: int = 4
     sdc_tol: float = 1e-10
     max_sweeps: int = 20
@@ -188,7 +189,7 @@ class Problem:
             d.lev[1] = LevelDesc(*self.coarse)
         d.mg = MgDesc(self.nu1, self.nu2, self.omega, self.n_coarsest, self.tol, self.max_cycles,
                       self.fixed_cycles, self.precision, self.inner_nu1, self.inner_nu2,
-                      self.fused_sweeps)
+                      self.fused_sweeps, self.cycle_graphs)
         d.sweeps, d.sdc_tol, d.max_sweeps = self.sweeps, self.sdc_tol, self.max_sweeps
         d.batch, d.nslices = self.batch, self.nslices
         keep = None

@@ -71,7 +71,7 @@ class Server:
         L = hs.lib()
         d = hs.ServerDesc()
         d.order, d.nnodes = order, nnodes
-        d.mg = hs.MgDesc(nu1, nu2, 6.0 / 7.0, 3, tol, max_cycles, 0, precision, inner[0], inner[1], 1)
+        d.mg = hs.MgDesc(nu1, nu2, 6.0 / 7.0, 3, tol, max_cycles, 0, precision, inner[0], inner[1], 1, 0)
         d.sweeps, d.sdc_tol, d.max_sweeps, d.forcing_c = sweeps, sdc_tol, max_sweeps, forcing_c
         items = sorted(slots.items())
         d.nclasses = len(items)

@@ -88,7 +88,7 @@ def base_problem(**kw):
                                 dict(fixed_cycles=0, tol=0.0),
                                 dict(coarse=(8, 2, 3)), dict(coarse=(7, 2, 4), nnodes=5, n=15),
                                 dict(nslices=4, batch=4), dict(lane_n=[15, 17], batch=2),
-                                dict(fused_sweeps=3), dict(fused_sweeps=-1)])
+                                dict(fused_sweeps=3), dict(fused_sweeps=-1), dict(cycle_graphs=2)])
 def test_invalid_problems_rejected(kw):
     p = base_problem(**kw)
     with pytest.raises(heatst.HeatstError) as e:

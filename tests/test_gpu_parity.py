@@ -345,6 +345,52 @@ def test_solve_graph_matches_eager(torch):
     assert np.array_equal(ea, eg)
 
 
+def _run_mlsdc(hs, torch, cycle_graphs, u0, nsteps=3):
+    pb = hs.Problem(n=31, order=4, nnodes=5, coarse=(15, 2, 3), nu=0.1, dt=0.05, nsteps=nsteps, sweeps=3,
+                    tol=1e-12, max_cycles=60, cycle_graphs=cycle_graphs)
+    plan = hs.Plan(pb)
+    plan.set_state(u0)
+    plan.solve()
+    st, stats = plan.stats()
+    return host(plan.get_state()), stats
+
+
+def test_cycle_graphs_match_eager(torch):
+    """Tolerance-driven MLSDC with the predicted cycles replayed from HIP
+    graphs gives the launches' results bit for bit, with the same cycle
+    counts (the predictions change between solves, so several graphs are
+    recorded and reused)."""
+    hs = heatst_mod()
+    u0 = dev(torch, inputs.random_smooth(31, 21))
+    e_state, e_stats = _run_mlsdc(hs, torch, 0, u0)
+    g_state, g_stats = _run_mlsdc(hs, torch, 1, u0)
+    assert np.array_equal(e_state, g_state)
+    for k in ("total_cycles", "total_solves", "max_cycles"):
+        assert e_stats[0][k] == g_stats[0][k], k
+
+
+def test_cycle_graphs_follow_lane_changes(torch):
+    """Lanes switched off and on between steps: graphs recorded over the old
+    run set are not replayed over the new one."""
+    hs = heatst_mod()
+    ns = [31, 15, 31]
+    u0s = [inputs.random_smooth(n, 30 + i) for i, n in enumerate(ns)]
+    out = []
+    for cg in (0, 1):
+        plan = hs.Plan(hs.Problem(n=31, order=2, nnodes=3, nu=0.1, dt=0.02, nsteps=4, sweeps=3, tol=1e-12,
+                                  batch=3, lane_n=ns, cycle_graphs=cg))
+        plan.set_state(dev(torch, np.concatenate([u.ravel() for u in u0s])))
+        plan.step()
+        plan.set_lane(1, 0.1, 0.02, 0.02, 3, active=False)
+        plan.step()
+        plan.step()
+        plan.set_lane(1, 0.1, 0.02, 0.02, 3, active=True)
+        plan.step()
+        torch.cuda.synchronize()
+        out.append(host(plan.get_state()))
+    assert np.array_equal(out[0], out[1])
+
+
 # ----------------------------------------------------------------------------
 # MLSDC / FAS / PFASST
 # ----------------------------------------------------------------------------

@@ -11,7 +11,7 @@ from paper_1307_7867_amd import serving
 def desc(classes, precision=hs.HS_MIXED):
     d = hs.ServerDesc()
     d.order, d.nnodes = 2, 5
-    d.mg = hs.MgDesc(2, 1, 6.0 / 7.0, 3, 1e-10, 60, 0, precision, 2, 2, 1)
+    d.mg = hs.MgDesc(2, 1, 6.0 / 7.0, 3, 1e-10, 60, 0, precision, 2, 2, 1, 0)
     d.sweeps, d.sdc_tol, d.max_sweeps, d.forcing_c = 0, 1e-10, 40, 3.0
     d.nclasses = len(classes)
     for i, (n, s) in enumerate(classes):
