@@ -161,7 +161,7 @@ int grid_blocks(int n, int zb = 1);   // blocks covering an n^3 grid, zb planes 
 int choose_zb(int n);
 int choose_zb_even(int n);   // even chunk length for resid_fw
 int choose_zb_two(int n);    // chunk length for jac2                 // z planes per block of the plane-marching kernels
-size_t tail_lds_bytes(int n0, int elem);  // LDS of the tail kernel whose top grid is n0
+size_t tail_lds_bytes(int n0, int elem, int order);  // LDS of the tail kernel whose top grid is n0
 
 hipError_t set_constants(const LibConst& lc);
 

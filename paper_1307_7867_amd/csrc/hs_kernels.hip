@@ -216,48 +216,6 @@ struct Ld3 {
     __device__ __forceinline__ T operator()(int i, int j, int k) const { return u[lin(i, j, k, n)]; }
 };
 
-// L_h sum at p of an n^3 grid with neighbour offsets taken from p (32-bit)
-template <int ORDER, typename T>
-__device__ __forceinline__ T lap_at(const T* __restrict__ u, int p, int i, int j, int k, int n, T c)
-{
-    const int sy = n, sz = n * n;
-    const T zero = T(0);
-    if (ORDER == 2) {
-        T xm = i > 0 ? u[p - 1] : zero;
-        T xp = i < n - 1 ? u[p + 1] : zero;
-        T ym = j > 0 ? u[p - sy] : zero;
-        T yp = j < n - 1 ? u[p + sy] : zero;
-        T zm = k > 0 ? u[p - sz] : zero;
-        T zp = k < n - 1 ? u[p + sz] : zero;
-        T c2 = T(2) * c;
-        return ((xm - c2) + xp) + ((ym - c2) + yp) + ((zm - c2) + zp);
-    } else {
-        T ax, ay, az;
-        {
-            T m1 = i >= 1 ? u[p - 1] : zero;
-            T m2 = i >= 2 ? u[p - 2] : (i == 1 ? zero : -c);
-            T p1 = i <= n - 2 ? u[p + 1] : zero;
-            T p2 = i <= n - 3 ? u[p + 2] : (i == n - 2 ? zero : -c);
-            ax = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
-        }
-        {
-            T m1 = j >= 1 ? u[p - sy] : zero;
-            T m2 = j >= 2 ? u[p - 2 * sy] : (j == 1 ? zero : -c);
-            T p1 = j <= n - 2 ? u[p + sy] : zero;
-            T p2 = j <= n - 3 ? u[p + 2 * sy] : (j == n - 2 ? zero : -c);
-            ay = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
-        }
-        {
-            T m1 = k >= 1 ? u[p - sz] : zero;
-            T m2 = k >= 2 ? u[p - 2 * sz] : (k == 1 ? zero : -c);
-            T p1 = k <= n - 2 ? u[p + sz] : zero;
-            T p2 = k <= n - 3 ? u[p + 2 * sz] : (k == n - 2 ? zero : -c);
-            az = (T(16) * (m1 + p1) - (m2 + p2)) - T(30) * c;
-        }
-        return (ax + ay) + az;
-    }
-}
-
 // coarse-grid view of a fine field by injection: coarse (I,J,K) is fine (2I+1, 2J+1, 2K+1)
 struct LdInj {
     const double* __restrict__ uf;
@@ -365,44 +323,6 @@ __device__ __forceinline__ void zmarch(const T* __restrict__ src, int n, int i, 
 #pragma unroll
         for (int d = 0; d < 2 * R; d++) w[d] = w[d + 1];
     }
-}
-
-// trilinear interpolation of a coarse field at fine point (i,j,k); walls 0.
-// Per axis a fine index either coincides with coarse (i-1)/2 (weight 1) or
-// lies between coarse i/2-1 and i/2 (weights 1/2, missing ones are walls).
-template <typename T>
-__device__ __forceinline__ T prolong_at(const T* __restrict__ c, int nc, int i, int j, int k)
-{
-    int ix0, ix1, iy0, iy1, iz0, iz1;
-    T wx, wy, wz;
-    if (i & 1) { ix0 = ix1 = (i - 1) >> 1; wx = T(1); } else { ix0 = (i >> 1) - 1; ix1 = i >> 1; wx = T(0.5); }
-    if (j & 1) { iy0 = iy1 = (j - 1) >> 1; wy = T(1); } else { iy0 = (j >> 1) - 1; iy1 = j >> 1; wy = T(0.5); }
-    if (k & 1) { iz0 = iz1 = (k - 1) >> 1; wz = T(1); } else { iz0 = (k >> 1) - 1; iz1 = k >> 1; wz = T(0.5); }
-    const bool two_x = !(i & 1), two_y = !(j & 1), two_z = !(k & 1);
-    const bool vx0 = ix0 >= 0, vx1 = two_x && ix1 < nc;
-    const bool vy0 = iy0 >= 0, vy1 = two_y && iy1 < nc;
-    const bool vz0 = iz0 >= 0, vz1 = two_z && iz1 < nc;
-    const int sy = nc, sz = nc * nc;
-    T s = T(0);
-#pragma unroll
-    for (int cz = 0; cz < 2; cz++) {
-        const bool vz = cz ? vz1 : vz0;
-        if (!vz) continue;
-        const int oz = (cz ? iz1 : iz0) * sz;
-        T sy_ = T(0);
-#pragma unroll
-        for (int cy = 0; cy < 2; cy++) {
-            const bool vy = cy ? vy1 : vy0;
-            if (!vy) continue;
-            const int o = oz + (cy ? iy1 : iy0) * sy;
-            T sx = T(0);
-            if (vx0) sx += c[o + ix0];
-            if (vx1) sx += c[o + ix1];
-            sy_ += wx * sx;
-        }
-        s += wy * sy_;
-    }
-    return wz * s;
 }
 
 // Sources of the plane march: the value of the field the stencil is applied
@@ -1043,7 +963,10 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_resid_fw(const GridSeg* __restr
 
 // xy part of the trilinear interpolation of one coarse plane at fine column
 // (i, j): wy * (sum over the coarse rows of wx * (sum over the coarse
-// columns)), the per-plane term of prolong_at.
+// columns)).  Per axis a fine index either coincides with coarse (i-1)/2
+// (weight 1) or lies between coarse i/2-1 and i/2 (weights 1/2); taps beyond
+// a wall are 0.  The full interpolation is wz * (sum over the coarse planes
+// of this term).
 template <typename T>
 struct ProlongXY {
     // coarse indices ix0 (ix1 = ix0 + 1 for even i, = ix0 for odd i), likewise
@@ -1118,7 +1041,8 @@ struct RingTap {
 // dst = src + P cu (in place when src and dst are the same buffer).  Each
 // thread marches its fine column through the block's planes; the xy
 // interpolation of a coarse plane K serves the fine planes 2K, 2K+1, 2K+2
-// and is computed once.  Same operations, in the same order, as prolong_at.
+// and is computed once; the planes' terms are summed and scaled by wz as in
+// ProlongXY's definition.
 template <typename T>
 __global__ void __launch_bounds__(HS_BLOCK) k_prolong(const GridSeg* __restrict__ segs, int nseg,
                                                       int nblk, const LaneCtl* __restrict__ ctl,
@@ -1365,14 +1289,76 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_fixup(const GridSeg* __restrict
 // Sizes of the tail grids: level l of a tail whose top grid has n0 points
 // per axis, and the LDS offset (in elements) of level l.  Level 0 holds the
 // ping-pong pair X, Y (its right-hand side lives in registers); every lower
-// level holds X, Y and its right-hand side B.
+// level holds X, Y and its right-hand side B.  X and Y carry R = ORDER/2
+// layers of zero cells on every face, so the stencil and the prolongation
+// read their taps at fixed offsets without tests; B is unpadded.
 constexpr int tail_n(int n0, int l) { return ((n0 + 1) >> l) - 1; }
 constexpr int tail_cube(int n) { return n * n * n; }
-constexpr int tail_off(int n0, int l)
+constexpr int tail_r(int order) { return order == 4 ? 2 : 1; }
+constexpr int tail_p(int n, int order) { return n + 2 * tail_r(order); }
+constexpr int tail_pcube(int n, int order) { return tail_cube(tail_p(n, order)); }
+constexpr int tail_words(int n, int order, bool top) { return 2 * tail_pcube(n, order) + (top ? 0 : tail_cube(n)); }
+constexpr int tail_off(int n0, int order, int l)
 {
     int o = 0;
-    for (int q = 0; q < l; q++) o += (q == 0 ? 2 : 3) * tail_cube(tail_n(n0, q));
+    for (int q = 0; q < l; q++) o += tail_words(tail_n(n0, q), order, q == 0);
     return o;
+}
+
+// index of interior point (i, j, k) of an N^3 tail grid in its padded array
+template <int N, int ORDER>
+__device__ __forceinline__ int tpad(int i, int j, int k)
+{
+    constexpr int R = tail_r(ORDER), P = tail_p(N, ORDER);
+    return ((k + R) * P + (j + R)) * P + (i + R);
+}
+
+// L_h sum at padded index q of a tail grid (row length P, zero cells beyond
+// the walls).  The 4th-order tap two cells beyond a wall is the odd
+// reflection -c: the zero cell leaves it out, and it is added back as +c per
+// wall.
+template <int ORDER, typename T, int P>
+__device__ __forceinline__ T lap_pad(const T* u, int q, T c, int walls)
+{
+    constexpr int sy = P, sz = P * P;
+    if (ORDER == 2) {
+        const T c2 = T(2) * c;
+        return ((u[q - 1] - c2) + u[q + 1]) + ((u[q - sy] - c2) + u[q + sy]) + ((u[q - sz] - c2) + u[q + sz]);
+    } else {
+        const T ax = (T(16) * (u[q - 1] + u[q + 1]) - (u[q - 2] + u[q + 2])) - T(30) * c;
+        const T ay = (T(16) * (u[q - sy] + u[q + sy]) - (u[q - 2 * sy] + u[q + 2 * sy])) - T(30) * c;
+        const T az = (T(16) * (u[q - sz] + u[q + sz]) - (u[q - 2 * sz] + u[q + 2 * sz])) - T(30) * c;
+        return ((ax + ay) + az) + T(walls) * c;
+    }
+}
+
+// trilinear interpolation at fine point (i, j, k) from a padded coarse tail
+// grid of NC points per axis.  Per axis an odd fine index reads coarse
+// (i-1)/2 with weight 1 (its second tap is the zero cell at -1), an even one
+// coarse i/2-1 and i/2 with weight 1/2 (the zero cells stand for the walls).
+template <typename T, int ORDER, int NC>
+__device__ __forceinline__ T prolong_pad(const T* c, int i, int j, int k)
+{
+    constexpr int R = tail_r(ORDER), P = tail_p(NC, ORDER);
+    int x0, x1, y0, y1, z0, z1;
+    T wx, wy, wz;
+    if (i & 1) { x0 = (i - 1) >> 1; x1 = -1; wx = T(1); } else { x0 = (i >> 1) - 1; x1 = i >> 1; wx = T(0.5); }
+    if (j & 1) { y0 = (j - 1) >> 1; y1 = -1; wy = T(1); } else { y0 = (j >> 1) - 1; y1 = j >> 1; wy = T(0.5); }
+    if (k & 1) { z0 = (k - 1) >> 1; z1 = -1; wz = T(1); } else { z0 = (k >> 1) - 1; z1 = k >> 1; wz = T(0.5); }
+    T s = T(0);
+#pragma unroll
+    for (int cz = 0; cz < 2; cz++) {
+        const int oz = ((cz ? z1 : z0) + R) * P * P;
+        T sy_ = T(0);
+#pragma unroll
+        for (int cy = 0; cy < 2; cy++) {
+            const int o = oz + ((cy ? y1 : y0) + R) * P + R;
+            const T sx = c[o + x0] + c[o + x1];
+            sy_ += wx * sx;
+        }
+        s += wy * sy_;
+    }
+    return wz * s;
 }
 
 // The 1024 threads cover an N^3 tail grid in passes of 64 x rows, 16 threads
@@ -1399,21 +1385,23 @@ template <typename T, int ORDER, int N, bool REG>
 __device__ __forceinline__ void lds_jacobi(const T* src, T* dst, const T* b, const T* bv, T a,
                                            const T* rd, bool zero)
 {
+    constexpr int P = tail_p(N, ORDER);
     const T sc = lap_scale<ORDER, T>(N);
 #pragma unroll
     for (int q = 0; q < tail_q<N>(); q++) {
         int i, j, k, p;
         if (!tail_pt<N>(q, i, j, k, p)) continue;
+        const int pp = tpad<N, ORDER>(i, j, k);
         const T bp = REG ? bv[q] : b[p];
         const int walls =
             ORDER == 2 ? 0 : (i == 0) + (i == N - 1) + (j == 0) + (j == N - 1) + (k == 0) + (k == N - 1);
         const T r = rd[walls];
         if (zero) {
-            dst[p] = r * bp;
+            dst[pp] = r * bp;
         } else {
-            const T c = src[p];
-            const T Au = c - a * (sc * lap_at<ORDER, T>(src, p, i, j, k, N, c));
-            dst[p] = c + r * (bp - Au);
+            const T c = src[pp];
+            const T Au = c - a * (sc * lap_pad<ORDER, T, P>(src, pp, c, walls));
+            dst[pp] = c + r * (bp - Au);
         }
     }
 }
@@ -1421,33 +1409,39 @@ __device__ __forceinline__ void lds_jacobi(const T* src, T* dst, const T* b, con
 template <typename T, int ORDER, int N, bool REG>
 __device__ __forceinline__ void lds_resid(const T* u, const T* b, const T* bv, T* r, T a)
 {
+    constexpr int P = tail_p(N, ORDER);
     const T sc = lap_scale<ORDER, T>(N);
 #pragma unroll
     for (int q = 0; q < tail_q<N>(); q++) {
         int i, j, k, p;
         if (!tail_pt<N>(q, i, j, k, p)) continue;
-        const T c = u[p];
-        r[p] = (REG ? bv[q] : b[p]) - (c - a * (sc * lap_at<ORDER, T>(u, p, i, j, k, N, c)));
+        const int pp = tpad<N, ORDER>(i, j, k);
+        const int walls =
+            ORDER == 2 ? 0 : (i == 0) + (i == N - 1) + (j == 0) + (j == N - 1) + (k == 0) + (k == N - 1);
+        const T c = u[pp];
+        r[pp] = (REG ? bv[q] : b[p]) - (c - a * (sc * lap_pad<ORDER, T, P>(u, pp, c, walls)));
     }
 }
 
-// full weighting of the N^3 residual r onto the coarse right-hand side cb
-template <typename T, int N>
+// full weighting of the N^3 residual r (padded) onto the coarse right-hand
+// side cb (unpadded)
+template <typename T, int ORDER, int N>
 __device__ __forceinline__ void lds_restrict(const T* r, T* cb)
 {
     constexpr int nc = (N - 1) / 2;
     constexpr int Nc = nc * nc * nc;
+    constexpr int P = tail_p(N, ORDER);
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
     for (int p = threadIdx.x; p < Nc; p += HS_TAIL_THREADS) {
         const int I = p % nc, J = (p / nc) % nc, K = p / (nc * nc);
-        const T* c = r + lin(2 * I + 1, 2 * J + 1, 2 * K + 1, N);
+        const T* c = r + tpad<N, ORDER>(2 * I + 1, 2 * J + 1, 2 * K + 1);
         T acc = T(0);
 #pragma unroll
         for (int dz = -1; dz <= 1; dz++) {
             T az = T(0);
 #pragma unroll
             for (int dy = -1; dy <= 1; dy++) {
-                const T* row = c + dz * N * N + dy * N;
+                const T* row = c + dz * P * P + dy * P;
                 T ay = (w[0] * row[-1] + w[1] * row[0]) + w[2] * row[1];
                 az += w[dy + 1] * ay;
             }
@@ -1457,23 +1451,23 @@ __device__ __forceinline__ void lds_restrict(const T* r, T* cb)
     }
 }
 
-// u += P c on an N^3 tail grid
-template <typename T, int N>
+// u += P c on an N^3 tail grid (both padded)
+template <typename T, int ORDER, int N>
 __device__ __forceinline__ void lds_prolong_add(T* u, const T* c)
 {
 #pragma unroll
     for (int q = 0; q < tail_q<N>(); q++) {
         int i, j, k, p;
         if (!tail_pt<N>(q, i, j, k, p)) continue;
-        u[p] += prolong_at<T>(c, (N - 1) / 2, i, j, k);
+        u[tpad<N, ORDER>(i, j, k)] += prolong_pad<T, ORDER, (N - 1) / 2>(c, i, j, k);
     }
 }
 
 // Exact solve on the coarsest grid (N = 1 or 3 points per axis) by the sine
 // transform: x = S diag(1 / (1 - a (lam_i + lam_j + lam_k))) S b with the
 // orthonormal, symmetric 1-D transform S and the 1-D eigenvalues lam (both
-// staged in LDS); bh is LDS scratch of N^3 values.
-template <typename T, int N, class PB>
+// staged in LDS); bh is LDS scratch of N^3 values.  b is unpadded, x padded.
+template <typename T, int ORDER, int N, class PB>
 __device__ __forceinline__ void lds_exact(PB b, T* x, T a, const double* S, const double* lam,
                                           double* bh)
 {
@@ -1517,7 +1511,7 @@ __device__ __forceinline__ void lds_exact(PB b, T* x, T a, const double* S, cons
 #pragma unroll
                 for (int pi = 0; pi < N; pi++)
                     s += ck[pk] * cj[pj] * ci[pi] * bh[(pk * N + pj) * N + pi];
-        x[p] = T(s);
+        x[tpad<N, ORDER>(i, j, k)] = T(s);
     }
     __syncthreads();
 }
@@ -1545,12 +1539,12 @@ struct TailV {
     static constexpr int nc = tail_n(N0, L + 1);
     __device__ static __forceinline__ void run(TailCtx<T>& c)
     {
-        T* X = c.base + tail_off(N0, L);
-        T* Y = X + tail_cube(n);
-        const T* B = L == 0 ? nullptr : Y + tail_cube(n);
-        T* Xc = c.base + tail_off(N0, L + 1);
-        T* Yc = Xc + tail_cube(nc);
-        T* Bc = Yc + tail_cube(nc);
+        T* X = c.base + tail_off(N0, ORDER, L);
+        T* Y = X + tail_pcube(n, ORDER);
+        const T* B = L == 0 ? nullptr : Y + tail_pcube(n, ORDER);
+        T* Xc = c.base + tail_off(N0, ORDER, L + 1);
+        T* Yc = Xc + tail_pcube(nc, ORDER);
+        T* Bc = Yc + tail_pcube(nc, ORDER);
         const bool zero = L > 0 || c.zero_top;
         for (int s = 0; s < c.nu1; s++) {
             const bool iy = (c.in_y >> L) & 1u;
@@ -1563,13 +1557,13 @@ struct TailV {
             T* r = iy ? X : Y;
             lds_resid<T, ORDER, n, L == 0>(iy ? Y : X, B, c.b0, r, c.a);
             __syncthreads();
-            lds_restrict<T, n>(r, Bc);
+            lds_restrict<T, ORDER, n>(r, Bc);
             __syncthreads();
         }
         TailV<T, ORDER, N0, L + 1, LAST>::run(c);
         {
             const bool iy = (c.in_y >> L) & 1u;
-            lds_prolong_add<T, n>(iy ? Y : X, ((c.in_y >> (L + 1)) & 1u) ? Yc : Xc);
+            lds_prolong_add<T, ORDER, n>(iy ? Y : X, ((c.in_y >> (L + 1)) & 1u) ? Yc : Xc);
             __syncthreads();
         }
         for (int s = 0; s < c.nu2; s++) {
@@ -1586,8 +1580,8 @@ struct TailV<T, ORDER, N0, LAST, LAST> {
     static constexpr int n = tail_n(N0, LAST);
     __device__ static __forceinline__ void run(TailCtx<T>& c)
     {
-        T* X = c.base + tail_off(N0, LAST);
-        lds_exact<T, n>(X + 2 * tail_cube(n), X, c.a, c.S, c.lam, c.bh);
+        T* X = c.base + tail_off(N0, ORDER, LAST);
+        lds_exact<T, ORDER, n>(X + 2 * tail_pcube(n, ORDER), X, c.a, c.S, c.lam, c.bh);
         c.in_y &= ~(1u << LAST);
     }
 };
@@ -1654,22 +1648,31 @@ __device__ __forceinline__ void tail_run(const TailSeg& ts, const LaneCtl* __res
     c.lam = s_lam;
     c.bh = s_bh;
     c.in_y = 0;
+    // zero every grid, so the cells beyond the walls read 0
+    constexpr int words = tail_off(N0, ORDER, NLEV);
+    for (int w = t; w < words; w += HS_TAIL_THREADS) base[w] = T(0);
+    __syncthreads();
+    // the top grid's result (padded) back to its global iterate
+    auto store_top = [&](const T* res) {
+        for (int p = t; p < N0c; p += HS_TAIL_THREADS) {
+            const int i = p % N0, j = (p / N0) % N0, k = p / (N0 * N0);
+            gu0[p] = res[tpad<N0, ORDER>(i, j, k)];
+        }
+    };
     if constexpr (NLEV == 1) {
-        __syncthreads();
-        lds_exact<T, N0>(gb0, c.base, c.a, c.S, c.lam, c.bh);
-        for (int p = t; p < N0c; p += HS_TAIL_THREADS) gu0[p] = c.base[p];
+        lds_exact<T, ORDER, N0>(gb0, c.base, c.a, c.S, c.lam, c.bh);
+        store_top(c.base);
     } else {
         if (!zero_top) {
 #pragma unroll
             for (int q = 0; q < tail_q<N0>(); q++) {
                 int i, j, k, p;
-                if (tail_pt<N0>(q, i, j, k, p)) base[p] = u0[q];
+                if (tail_pt<N0>(q, i, j, k, p)) base[tpad<N0, ORDER>(i, j, k)] = u0[q];
             }
         }
         __syncthreads();
         TailV<T, ORDER, N0, 0, NLEV - 1>::run(c);
-        const T* res = (c.in_y & 1u) ? c.base + N0c : c.base;
-        for (int p = t; p < N0c; p += HS_TAIL_THREADS) gu0[p] = res[p];
+        store_top((c.in_y & 1u) ? c.base + tail_pcube(N0, ORDER) : c.base);
     }
 }
 
@@ -2372,14 +2375,13 @@ int choose_zb_even(int n)
     return zb < 2 ? 2 : zb;
 }
 
-size_t tail_lds_bytes(int n0, int elem)
+size_t tail_lds_bytes(int n0, int elem, int order)
 {
     size_t words = 0;
     int n = n0;
     bool top = true;
     while (true) {
-        size_t N = (size_t)n * n * n;
-        words += (top ? 2 : 3) * N;
+        words += (size_t)tail_words(n, order, top);
         top = false;
         if (n <= 1) break;
         n = (n - 1) / 2;
@@ -2478,6 +2480,17 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
                 size_t lds_bytes, hipStream_t s)
 {
     if (nseg <= 0) return hipSuccess;
+    // padded 4th-order tails of a 15^3 top grid need more than 64 KB of LDS
+    static size_t allowed[2] = {0, 0};
+    size_t& al = allowed[order == 4 ? 1 : 0];
+    if (lds_bytes > al) {
+        hipError_t e = order == 4 ? hipFuncSetAttribute((const void*)k_tail<T, 4>,
+                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes)
+                                  : hipFuncSetAttribute((const void*)k_tail<T, 2>,
+                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        al = lds_bytes;
+    }
     HS_ORDER_DISPATCH(order, (k_tail<T, 2>), (k_tail<T, 4>), dim3((unsigned)nseg),
                       dim3(HS_TAIL_THREADS), (unsigned)lds_bytes, segs, ctl, a, nu1, nu2);
     return hipGetLastError();

@@ -369,7 +369,7 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             ts.u[q] = u; ts.t[q] = t; ts.b[q] = bb;
         }
         ts.coarse_table = ct_index(P->order[L], g.back());
-        S.tail_lds = std::max(S.tail_lds, hsk::tail_lds_bytes(g[Db], fp32 ? 4 : 8));
+        S.tail_lds = std::max(S.tail_lds, hsk::tail_lds_bytes(g[Db], fp32 ? 4 : 8, P->order[L]));
         ts.zero_guess = (Db > 0 || fp32) ? 1 : 0;
         ts.node_stride = (Db == 0 && !fp32) ? lb.N[L] : 0;
         S.tail.h.push_back(ts);
