@@ -254,6 +254,31 @@ __device__ __forceinline__ double block_max(double v)
     return v;
 }
 
+// block-wide maxima of two values at once (one pair of barriers); results
+// valid in thread 0.  All threads must call it.
+__device__ __forceinline__ void block_max2(double& v, double& u)
+{
+    __shared__ double sm[2][16];
+    for (int off = 32; off > 0; off >>= 1) {
+        v = nmax(v, __shfl_xor(v, off, 64));
+        u = nmax(u, __shfl_xor(u, off, 64));
+    }
+    int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    __syncthreads();
+    if (l == 0) {
+        sm[0][w] = v;
+        sm[1][w] = u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nw = (blockDim.x + 63) / 64;
+        for (int q = 1; q < nw; q++) {
+            v = nmax(v, sm[0][q]);
+            u = nmax(u, sm[1][q]);
+        }
+    }
+}
+
 template <typename S>
 __device__ __forceinline__ int seg_nblk(const S* segs, int nseg, int si, int nblk)
 {
@@ -569,8 +594,14 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
         }
     }
     if (NORM) {
-        double m = block_max(op.rmax);
-        double mb = cycle == 0 ? block_max(op.bmax) : 0.0;   // |b| is taken once per solve
+        // |b| is taken once per solve
+        double m = op.rmax, mb = op.bmax;
+        if (cycle == 0) {
+            block_max2(m, mb);
+        } else {
+            m = block_max(m);
+            mb = 0.0;
+        }
         if (threadIdx.x == 0) {
             partials[2 * lb] = m;
             partials[2 * lb + 1] = mb;
@@ -758,8 +789,13 @@ __global__ void __launch_bounds__(HS_BLOCK) k_jac2(const GridSeg* __restrict__ s
         __syncthreads();
     }
     if (NORM) {
-        double m = block_max(rmax);
-        double mb = cycle == 0 ? block_max(bmax) : 0.0;
+        double m = rmax, mb = bmax;
+        if (cycle == 0) {
+            block_max2(m, mb);
+        } else {
+            m = block_max(m);
+            mb = 0.0;
+        }
         if (t == 0) {
             partials[2 * lb] = m;
             partials[2 * lb + 1] = mb;
@@ -1780,8 +1816,8 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_norm(const GridSeg* __restrict_
     __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
     lds_march<ORDER, double>(u, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX), q.z0,
                              q.z1, pl, op);
-    double m = block_max(op.rmax);
-    double mb = block_max(op.bmax);
+    double m = op.rmax, mb = op.bmax;
+    block_max2(m, mb);
     if (threadIdx.x == 0) {
         partials[2 * lb] = m;
         partials[2 * lb + 1] = mb;
@@ -1823,8 +1859,8 @@ __global__ void __launch_bounds__(HS_BLOCK) k_ir_resid(const GridSeg* __restrict
     __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
     lds_march<ORDER, double>(u, n, q.i - (int)(threadIdx.x % HS_TX), q.j - (int)(threadIdx.x / HS_TX), q.z0,
                              q.z1, pl, op);
-    double m = block_max(op.rmax);
-    double mb = block_max(op.bmax);
+    double m = op.rmax, mb = op.bmax;
+    block_max2(m, mb);
     if (threadIdx.x == 0) {
         partials[2 * lb] = m;
         partials[2 * lb + 1] = mb;
@@ -2348,14 +2384,14 @@ int grid_blocks(int n, int zb) { return tiles_x(n) * tiles_y(n) * ((n + zb - 1) 
 
 // z planes per block of the plane-marching kernels: as many as possible (up
 // to 8, fewer halo reloads and window warm-ups) while one grid still gives
-// 512 blocks of 512 threads (two per CU).  At 127^3 eight planes per block
-// (512 blocks) measured faster than four (1024 blocks): the chip is then
-// half occupied, but each block warms up its z window half as often.
+// 256 blocks of 512 threads (one per CU).  Measured: at 127^3 eight planes
+// per block (512 blocks) beat four (1024 blocks) and sixteen (256 blocks);
+// at 63^3 two planes (256 blocks) beat one (504 blocks).
 int choose_zb(int n)
 {
     long long tiles = (long long)tiles_x(n) * tiles_y(n);
     int zb = 8;
-    while (zb > 1 && tiles * ((n + zb - 1) / zb) < 512) zb /= 2;
+    while (zb > 1 && tiles * ((n + zb - 1) / zb) < 256) zb /= 2;
     return zb;
 }
 
