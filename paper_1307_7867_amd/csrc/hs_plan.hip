@@ -241,7 +241,12 @@ struct hs_plan {
     const void* user_key[3] = {nullptr, nullptr, nullptr};
     int user_level = -1;
     double* d_times = nullptr;                 // per-lane times for hs_heat_rhs
-    int cpred[2][HS_MAXM];                     // predicted cycles per (level, substep)
+    // predicted cycles per (level, substep, iteration within the step): the
+    // warm start improves from one iteration to the next, so the first
+    // iteration of a step needs more cycles than the last one of the step before
+    static constexpr int PRED_K = 4;
+    int cpred[2][HS_MAXM][PRED_K];
+    int sweep_k = 0;                           // iterations (fine sweeps) done in this step
     int cpred_user = 0;
     int state_ready = 0;
     hipGraph_t graph = nullptr;
@@ -878,7 +883,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     int order = P->order[L];
     hsk::MgArgs A{L, m, mg.omega, node, 1};
     HS_TRY(hsk::begin_solve(P->ctl, P->B, s));
-    int& pred = m >= 0 ? P->cpred[L][m] : P->cpred_user;
+    int& pred = m >= 0 ? P->cpred[L][m][std::min(P->sweep_k, hs_plan::PRED_K - 1)] : P->cpred_user;
     if (!P->mixed) {
         const MgSet& S = ls.mg64[L];
         int par = 0;
@@ -1012,6 +1017,7 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
         HS_CHECK(mg_solve(P, ls, L, m, m + 1, s, nullptr));
         HS_TRY(hsk::f_update(P->ctl, T.d, T.nseg(), T.nblk, P->order[L], m + 1, m + 2 < M ? 1 : 0, 1, s));
     }
+    if (P->nlev == 1) P->sweep_k++;
     return HS_OK;
 }
 
@@ -1024,6 +1030,7 @@ hs_status mlsdc_iter(hs_plan* P, LaneSet& ls, bool with_resid, hipStream_t s, in
     HS_CHECK(sweep(P, ls, 1, false, false, s, &o2));
     HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
     HS_TRY(hsk::eval_fi_all(P->ctl, ls.sdc[0].d, ls.sdc[0].nseg(), ls.sdc[0].nblk, P->order[0], 1, s));
+    P->sweep_k++;
     return HS_OK;
 }
 
@@ -1070,6 +1077,7 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
 hs_status begin_step(hs_plan* P, hipStream_t s)
 {
     HS_CHECK(refresh_run(P, s));
+    P->sweep_k = 0;
     HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M[0], P->nlev > 1 ? P->M[1] : P->M[0], s));
     const Table<SdcSeg>& T = P->run.sdc[0];
     HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[0], P->M[0] - 1, s));
@@ -1169,7 +1177,8 @@ static void init_plan(hs_plan* P, const hs_problem* pb)
         for (int b = 0; b < P->B; b++) P->lane_n[b] = pb->h_lane_n[b];
     P->pb.h_lane_n = nullptr;
     for (int L = 0; L < 2; L++)
-        for (int m = 0; m < HS_MAXM; m++) P->cpred[L][m] = 1;
+        for (int m = 0; m < HS_MAXM; m++)
+            for (int k = 0; k < hs_plan::PRED_K; k++) P->cpred[L][m][k] = 1;
     P->cpred_user = 1;
 }
 
@@ -1634,6 +1643,7 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
             HS_TRY(hsk::fas_interp(P->ctl, all.fasf.d, all.fasf.nseg(), all.fasf.nblk, 1, s));
             HS_TRY(hsk::eval_fi_all(P->ctl, all.sdc[0].d, all.sdc[0].nseg(), all.sdc[0].nblk,
                                     P->order[0], 1, s));
+            P->sweep_k++;
         }
         HS_TRY(hsk::end_step(P->ctl, P->B, s));
     }
