@@ -175,15 +175,18 @@ inline int src_code(int finest_t, int coarse_t, int skip_coarse = 0)
 }
 
 // Weighted-Jacobi sweep (mode 0) or residual r = b - A x written to the free
-// buffer (mode 1) over a z-marching table.  norm: also write per-block
-// maxima of |b - A x| (and |b| when cycle == 0) to partials (FP64 only).
+// buffer (mode 1) over a z-marching table.  norm 1 (finest grids, FP64): also
+// write per-block maxima of |b - A x| (and |b| when cycle == 0) to partials;
+// norm 2: first take the stopping test before cycle `cycle` (tol, max_cycles
+// as mg_decide) from the maxima a norm-1 launch over the same table left, and
+// sweep only the lanes that go on.
 // src_is_t is a source-buffer code (src_code).  src (mode 0 only): 0 = x is
 // the buffer the code picks; 1 = on correction grids x is the zero-guess
 // first sweep omega D^{-1} b formed on the fly (finest grids as with 0).
 template <typename T>
 hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                  int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
-                 double* partials, hipStream_t s, int src = 0);
+                 double* partials, hipStream_t s, int src = 0, double tol = 0.0, int max_cycles = 0);
 
 // Two weighted-Jacobi sweeps in one pass: dst = J(J(x)), x picked by
 // src_is_t, dst the other buffer.  norm: per-block maxima of the first

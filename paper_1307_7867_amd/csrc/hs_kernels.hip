@@ -226,6 +226,17 @@ struct LdInj {
     }
 };
 
+// record the end of a multigrid solve (state 1 converged, 2 failed)
+__device__ __forceinline__ void finish_solve(LaneCtl& c, int cycle, int state)
+{
+    c.mg_state = state;
+    c.mg_cycle = cycle;
+    c.total_cycles += cycle;
+    c.total_solves += 1;
+    if (cycle > c.max_cycles) c.max_cycles = cycle;
+    if (state == 2) c.failed_solves += 1;
+}
+
 __device__ __forceinline__ double lane_a(const LaneCtl* ctl, int lane, int L, int m)
 {
     return m >= 0 ? ctl[lane].a[L][m] : ctl[lane].a_user;
@@ -548,19 +559,54 @@ struct SweepOp {
 // MODE 0: weighted Jacobi  dst = x + omega D^{-1} (b - A_a x)  (from a zero
 // guess on correction grids: dst = omega D^{-1} b); MODE 1: residual
 // dst = b - A_a x.  x is the buffer picked by src_is_t, dst the other one.
-// NORM: per-block maxima of |b - A_a x| (and |b| at cycle 0) to partials.
+// NORM 1: per-block maxima of |b - A_a x| (and |b| at cycle 0) to partials.
+// NORM 2: first the stopping test before cycle `cycle` (as mg_decide takes
+// it) from the maxima a NORM 1 launch over the same table left in partials;
+// every block reduces its lane's maxima and decides alike, the lane's first
+// block records the outcome, and lanes that stop return before sweeping.
 // SRC 1: x is the zero-guess first sweep omega D^{-1} b, formed on the fly
 // (this launch is the second sweep of a correction grid).
-template <typename T, int ORDER, int MODE, int FINEST, int NORM, int SRC>
+template <typename T, int ORDER, int MODE, int FINEST, int NORM_, int SRC>
 __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ segs, int nseg,
-                                                    int nblk, const LaneCtl* __restrict__ ctl,
+                                                    int nblk, LaneCtl* __restrict__ ctl,
                                                     hsk::MgArgs A, int first_sweep, int src_is_t,
-                                                    double* __restrict__ partials, int cycle)
+                                                    double* __restrict__ partials, int cycle, double tol,
+                                                    int max_cycles)
 {
+    constexpr int NORM = NORM_ == 1;
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
     if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    if (NORM_ == 2) {
+        const int b0 = sg.blk_begin, nb = seg_nblk(segs, nseg, si, nblk);
+        double r = 0.0, bb = 0.0;
+        for (int q = threadIdx.x; q < nb; q += HS_BLOCK) {
+            r = nmax(r, partials[2 * (b0 + q)]);
+            if (cycle == 0) bb = nmax(bb, partials[2 * (b0 + q) + 1]);
+        }
+        block_max2(r, bb);
+        __shared__ int s_state;
+        if (threadIdx.x == 0) {
+            LaneCtl& c = ctl[sg.lane];
+            const double bn = cycle == 0 ? bb : c.bnorm;
+            const double rho = r / (bn > 0.0 ? bn : 1.0);
+            const bool bad = rho != rho || r > 1.7e308;
+            const int state = bad ? 2 : (rho <= tol ? 1 : (cycle >= max_cycles ? 2 : 0));
+            if (lb == b0) {
+                if (cycle == 0) c.bnorm = bn;
+                c.mg_rho = rho;
+                if (state != 0) {
+                    finish_solve(c, cycle, state);
+                    if (bad) c.status = -4;
+                    else if (state == 2 && c.status == 0) c.status = -3;
+                }
+            }
+            s_state = state;
+        }
+        __syncthreads();
+        if (s_state != 0) return;
+    }
     if ((src_is_t & 4) && sg.coarse) return;
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
@@ -1738,15 +1784,6 @@ __global__ void __launch_bounds__(HS_TAIL_THREADS) k_tail(const TailSeg* __restr
 // Solve control
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void finish_solve(LaneCtl& c, int cycle, int state)
-{
-    c.mg_state = state;
-    c.mg_cycle = cycle;
-    c.total_cycles += cycle;
-    c.total_solves += 1;
-    if (cycle > c.max_cycles) c.max_cycles = cycle;
-    if (state == 2) c.failed_solves += 1;
-}
 
 // Stopping test before cycle `cycle`, one block per lane:
 // rho = |b - A u|_inf / |b|_inf (|b| = 0 -> 1); stop when rho <= tol, fail
@@ -2439,23 +2476,26 @@ hipError_t set_constants(const LibConst& lc)
 template <typename T, int MODE, int FINEST, int NORM, int SRC = 0>
 static hipError_t sweep_launch(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order,
                                MgArgs a, int first_sweep, int src_is_t, int cycle, double* partials,
-                               hipStream_t s)
+                               hipStream_t s, double tol = 0.0, int max_cycles = 0)
 {
     HS_ORDER_DISPATCH(order, (k_sweep<T, 2, MODE, FINEST, NORM, SRC>), (k_sweep<T, 4, MODE, FINEST, NORM, SRC>),
                       g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a, first_sweep, src_is_t, partials,
-                      cycle);
+                      cycle, tol, max_cycles);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                  int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
-                 double* partials, hipStream_t s, int src)
+                 double* partials, hipStream_t s, int src, double tol, int max_cycles)
 {
     if (nblk <= 0) return hipSuccess;
     if (mode == 1) return sweep_launch<T, 1, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
     if (src == 1) return sweep_launch<T, 0, 0, 0, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
-    if (norm) return sweep_launch<T, 0, 1, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s);
+    if (norm == 1) return sweep_launch<T, 0, 1, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s);
+    if (norm == 2)
+        return sweep_launch<T, 0, 1, 2>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s, tol,
+                                        max_cycles);
     if (finest_only) return sweep_launch<T, 0, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
     return sweep_launch<T, 0, 0, 0>(ctl, segs, nseg, nblk, order, a, first_sweep, src_is_t, 0, partials, s);
 }
@@ -2532,8 +2572,8 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
     return hipGetLastError();
 }
 
-template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
-template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int);
+template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int, double, int);
+template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int, double, int);
 template hipError_t jac2<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
 template hipError_t jac2<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
 template hipError_t pjac<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);

@@ -170,6 +170,7 @@ struct Table {
     int nblk = 0;
     int finest = 0;     // grid tables: every segment is a finest grid
     int coarse_all = 0; // grid tables: every segment is a correction grid (zero first guess)
+    int max_seg_blocks = 0;  // grid tables: most blocks of one segment
     int nseg() const { return (int)h.size(); }
 };
 
@@ -351,6 +352,8 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         S.jac[s].nblk = bj;
         S.jac[s].finest = 1;
         S.jac[s].coarse_all = 1;
+        for (const GridSeg& g : S.jac[s].h)
+            S.jac[s].max_seg_blocks = std::max(S.jac[s].max_seg_blocks, hsk::grid_blocks(g.n, g.zb));
         for (const GridSeg& g : S.jac[s].h) {
             if (g.coarse) S.jac[s].finest = 0;
             else S.jac[s].coarse_all = 0;
@@ -732,12 +735,12 @@ bool all_sdc_done(hs_plan* P, const LaneSet& ls)
 // and correction grids of others: each launch then picks the buffer per grid
 // role, and the finest grids' first sweep runs alone so that both kinds
 // reach their second sweep in the same launch.
-// first_done: number of the finest grids' sweeps that already ran in one
-// pass with the residual norm (1, or 2 for the two-sweep pass).  On grids
-// with S.two the first two sweeps run as one pass.
+// sweeps_done / passes_done: the finest grids' first sweeps that already ran
+// with the residual norm (and the stopping test), and the passes they took.
+// On grids with S.two the first two sweeps run as one pass.
 template <typename T>
 hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, int nu2,
-                 int first_done, int* par, hipStream_t s)
+                 int sweeps_done, int passes_done, int* par, hipStream_t s)
 {
     const bool pj = nu2 >= 1;
     // correction grids: passes that write them, and the buffer of their first
@@ -752,10 +755,9 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
         auto code = [&](int skip = 0) { return hsk::src_code(cf, cc, skip); };
         if (!hasC) {
             int k0 = 0;
-            if (first_done) {
-                // one pass (the sweep with the norm, or the two-sweep pass) already ran
-                cf ^= 1;
-                k0 = first_done;
+            if (sweeps_done) {
+                cf ^= passes_done & 1;
+                k0 = sweeps_done;
             } else if (S.two && nu1 >= 2) {
                 const Table<GridSeg>& J2 = S.pro[st];
                 HS_TRY(hsk::jac2<T>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, code(), 0, 0, P->partials, s));
@@ -889,15 +891,25 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         int par = 0;
         if (mg.fixed_cycles > 0) {
             for (int c = 0; c < mg.fixed_cycles; c++)
-                HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, 0, &par, s));
+                HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, 0, 0, &par, s));
             HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
             return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
         }
         const bool two = S.two && mg.nu1 >= 2;
+        // the second sweep takes the stopping test from the norm sweep's
+        // maxima (no decision launch) while a lane's maxima are few enough
+        // for every block to reduce them
+        const bool fold = S.fused_norm && !two && mg.nu1 >= 2 && S.jac[0].max_seg_blocks <= 1024;
         // residual norm and stopping test before cycle c; the norm is fused
         // with cycle c's first sweep when possible
         auto head = [&](int c, int pc, hipStream_t st) -> hs_status {
-            if (S.fused_norm && two) {
+            if (fold) {
+                const Table<GridSeg>& J = S.jac[0];
+                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(pc, 0), 1,
+                                          1, c, P->partials, st));
+                HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, hsk::src_code(pc ^ 1, 0),
+                                          1, 2, c, P->partials, st, 0, mg.tol, mg.max_cycles));
+            } else if (S.fused_norm && two) {
                 const Table<GridSeg>& J2 = S.pro[0];
                 HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, hsk::src_code(pc, 0), 1, c,
                                          P->partials, st));
@@ -917,7 +929,8 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             }
             return HS_OK;
         };
-        const int first_done = S.fused_norm ? (two ? 2 : 1) : 0;
+        const int sd = fold ? 2 : (S.fused_norm ? (two ? 2 : 1) : 0);   // sweeps and passes of head()
+        const int pd = fold ? 2 : (S.fused_norm ? 1 : 0);
         // the host checks the lanes at the predicted cycle count, then every
         // second cycle: a gated surplus cycle costs less than a stream round trip
         int next_check = pred;
@@ -927,12 +940,12 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             // cycle 0 from the host, then cycles 1..pred-1 and the test at
             // pred from one graph, whose launch overlaps cycle 0
             HS_CHECK(head(0, par, s));
-            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, first_done, &par, s));
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, sd, pd, &par, s));
             hipGraphExec_t ge = nullptr;
             HS_CHECK(cycle_graph(P, ls, L, m, node, pred, &ge, &par, [&](hipStream_t st, int* pp) -> hs_status {
                 for (int k = 1; k < pred; k++) {
                     HS_CHECK(head(k, *pp, st));
-                    HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, first_done, pp, st));
+                    HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, sd, pd, pp, st));
                 }
                 return head(pred, *pp, st);
             }));
@@ -954,7 +967,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                 next_check = c + 2;
             }
             if (c >= mg.max_cycles) break;
-            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, first_done, &par, s));
+            HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, sd, pd, &par, s));
         }
         return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
     }
@@ -984,7 +997,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             if (it >= limit) break;
         }
         int par32 = 0;
-        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, 0, &par32, s));
+        HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, 0, 0, &par32, s));
         HS_TRY(hsk::ir_update(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, A, s));
     }
     if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, s));
