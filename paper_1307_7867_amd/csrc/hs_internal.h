@@ -244,10 +244,11 @@ hipError_t sdc_decide(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, cons
                       double sdc_tol, int max_sweeps, hipStream_t s);
 hipError_t make_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int m, int gate,
                     hipStream_t s);
-hipError_t f_update(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int node,
-                    int next_rhs, int gate, hipStream_t s);
-hipError_t eval_fi_all(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int gate,
-                       hipStream_t s);
+// FI_m = nu L U_m at nodes m0..m1-1 (and rhs = U + P at node rhs_node, -1 for
+// none) over the blocks of the lanes' finest-grid z-marching table gsegs; the
+// SDC table ssegs holds the same lanes in the same order.
+hipError_t fi_march(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int nseg, int nblk, int order,
+                    int m0, int m1, int rhs_node, int gate, hipStream_t s);
 hipError_t sdc_resid(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, double* partials,
                      hipStream_t s);
 hipError_t handoff(LaneCtl* ctl, const SdcSeg* dst, const SdcSeg* src, int nseg, int nblk,

@@ -2089,50 +2089,41 @@ __global__ void __launch_bounds__(HS_BLOCK) k_make_rhs(const SdcSeg* __restrict_
     sg.rhs[p] = sg.U[m * N + p] + sg.P[m * N + p];
 }
 
-// FI_node = nu L U_node; with next_rhs also rhs = U_node + P_node (the
-// right-hand side of the next substep, which starts from this node).
+// FI_m = nu L U_m at nodes m0..m1-1, and at node rhs_node also rhs = U + P
+// (the right-hand side of the next substep, which starts from that node).
+// The blocks follow a z-marching table of the same lanes' finest grids
+// (gsegs); the node arrays come from the SDC table (ssegs, same order).
 template <int ORDER>
-__global__ void __launch_bounds__(HS_BLOCK) k_f_update(const SdcSeg* __restrict__ segs, int nseg,
-                                                       int nblk, const LaneCtl* __restrict__ ctl,
-                                                       int node, int next_rhs, int gate)
+__global__ void __launch_bounds__(HS_BLOCK) k_fi_march(const GridSeg* __restrict__ gsegs,
+                                                       const SdcSeg* __restrict__ ssegs, int nseg, int nblk,
+                                                       const LaneCtl* __restrict__ ctl, int m0, int m1,
+                                                       int rhs_node, int gate)
 {
     int lb = xcd_remap(blockIdx.x, nblk);
-    int si = find_seg(segs, nseg, lb);
-    const SdcSeg sg = segs[si];
+    int si = find_seg(gsegs, nseg, lb);
+    const GridSeg sg = gsegs[si];
+    const SdcSeg ss = ssegs[si];
     if (gate && ctl[sg.lane].sdc_state != 0) return;
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
-    if (!q.in) return;
-    long long N = (long long)n * n * n;
-    long long p = lin(q.i, q.j, q.k, n);
-    const double* un = sg.U + node * N;
-    Ld3<double> ld{un, n};
-    double c = un[p];
-    sg.FI[node * N + p] = ctl[sg.lane].nu * (lap_scale<ORDER, double>(n) * lap_sum<ORDER, double>(ld, q.i, q.j, q.k, n, c));
-    if (next_rhs) sg.rhs[p] = c + sg.P[node * N + p];
-}
-
-// FI_m = nu L U_m at every node
-template <int ORDER>
-__global__ void __launch_bounds__(HS_BLOCK) k_eval_fi_all(const SdcSeg* __restrict__ segs, int nseg,
-                                                          int nblk, const LaneCtl* __restrict__ ctl,
-                                                          int gate)
-{
-    int lb = xcd_remap(blockIdx.x, nblk);
-    int si = find_seg(segs, nseg, lb);
-    const SdcSeg sg = segs[si];
-    if (gate && ctl[sg.lane].sdc_state != 0) return;
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
-    if (!q.in) return;
-    long long N = (long long)n * n * n;
-    long long p = lin(q.i, q.j, q.k, n);
-    double nu = ctl[sg.lane].nu;
-    double sc = lap_scale<ORDER, double>(n);
-    for (int m = 0; m < sg.M; m++) {
-        const double* um = sg.U + m * N;
-        Ld3<double> ld{um, n};
-        sg.FI[m * N + p] = nu * (sc * lap_sum<ORDER, double>(ld, q.i, q.j, q.k, n, um[p]));
+    const int n = sg.n;
+    PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
+    const long long N = (long long)n * n * n;
+    struct Op {
+        HS_G double* fi;
+        HS_G double* rhs;
+        const HS_G double* P;
+        double nu;
+        __device__ __forceinline__ void operator()(long long p, int, double c, double L)
+        {
+            fi[p] = nu * L;
+            if (rhs) rhs[p] = c + P[p];
+        }
+    };
+    __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
+    const int i0 = q.i - (int)(threadIdx.x % HS_TX), j0 = q.j - (int)(threadIdx.x / HS_TX);
+    for (int m = m0; m < m1; m++) {
+        Op op{(HS_G double*)ss.FI + m * N, m == rhs_node ? (HS_G double*)ss.rhs : nullptr,
+              (const HS_G double*)ss.P + m * N, ctl[sg.lane].nu};
+        lds_march<ORDER, double>((const HS_G double*)ss.U + m * N, n, i0, j0, q.z0, q.z1, pl, op);
     }
 }
 
@@ -2655,21 +2646,12 @@ hipError_t make_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int m,
     return hipGetLastError();
 }
 
-hipError_t f_update(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int node,
-                    int next_rhs, int gate, hipStream_t s)
+hipError_t fi_march(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int nseg, int nblk, int order,
+                    int m0, int m1, int rhs_node, int gate, hipStream_t s)
 {
-    if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_f_update<2>), (k_f_update<4>), g1(nblk), BLK, 0, segs, nseg, nblk,
-                      ctl, node, next_rhs, gate);
-    return hipGetLastError();
-}
-
-hipError_t eval_fi_all(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order, int gate,
-                       hipStream_t s)
-{
-    if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_eval_fi_all<2>), (k_eval_fi_all<4>), g1(nblk), BLK, 0, segs, nseg,
-                      nblk, ctl, gate);
+    if (nblk <= 0 || m1 <= m0) return hipSuccess;
+    HS_ORDER_DISPATCH(order, (k_fi_march<2>), (k_fi_march<4>), g1(nblk), BLK, 0, gsegs, ssegs, nseg, nblk, ctl,
+                      m0, m1, rhs_node, gate);
     return hipGetLastError();
 }
 

@@ -1012,6 +1012,7 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
                 int* outcome)
 {
     const Table<SdcSeg>& T = ls.sdc[L];
+    const Table<GridSeg>& F = ls.mg64[L].fine;   // z-marching blocks over the same lanes
     int M = P->M[L];
     *outcome = SWEEP_RAN;
     HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, 1, P->partials, s));
@@ -1028,7 +1029,8 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
     HS_TRY(hsk::make_rhs(P->ctl, T.d, T.nseg(), T.nblk, 0, 1, s));
     for (int m = 0; m + 1 < M; m++) {
         HS_CHECK(mg_solve(P, ls, L, m, m + 1, s, nullptr));
-        HS_TRY(hsk::f_update(P->ctl, T.d, T.nseg(), T.nblk, P->order[L], m + 1, m + 2 < M ? 1 : 0, 1, s));
+        HS_TRY(hsk::fi_march(P->ctl, F.d, T.d, T.nseg(), F.nblk, P->order[L], m + 1, m + 2, m + 2 < M ? m + 1 : -1,
+                             1, s));
     }
     if (P->nlev == 1) P->sweep_k++;
     return HS_OK;
@@ -1042,7 +1044,8 @@ hs_status mlsdc_iter(hs_plan* P, LaneSet& ls, bool with_resid, hipStream_t s, in
     int o2;
     HS_CHECK(sweep(P, ls, 1, false, false, s, &o2));
     HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
-    HS_TRY(hsk::eval_fi_all(P->ctl, ls.sdc[0].d, ls.sdc[0].nseg(), ls.sdc[0].nblk, P->order[0], 1, s));
+    HS_TRY(hsk::fi_march(P->ctl, ls.mg64[0].fine.d, ls.sdc[0].d, ls.sdc[0].nseg(), ls.mg64[0].fine.nblk,
+                         P->order[0], 0, P->M[0], -1, 1, s));
     P->sweep_k++;
     return HS_OK;
 }
@@ -1540,7 +1543,8 @@ hs_status hs_fas_interp(hs_plan* P, void* stream)
     HS_CHECK(refresh_run(P, s));
     LaneSet& ls = P->run;
     HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
-    HS_TRY(hsk::eval_fi_all(P->ctl, ls.sdc[0].d, ls.sdc[0].nseg(), ls.sdc[0].nblk, P->order[0], 1, s));
+    HS_TRY(hsk::fi_march(P->ctl, ls.mg64[0].fine.d, ls.sdc[0].d, ls.sdc[0].nseg(), ls.mg64[0].fine.nblk,
+                         P->order[0], 0, P->M[0], -1, 1, s));
     return HS_OK;
 }
 
@@ -1654,8 +1658,8 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
             }
             // (iv) interpolation on every slice, node 0 included
             HS_TRY(hsk::fas_interp(P->ctl, all.fasf.d, all.fasf.nseg(), all.fasf.nblk, 1, s));
-            HS_TRY(hsk::eval_fi_all(P->ctl, all.sdc[0].d, all.sdc[0].nseg(), all.sdc[0].nblk,
-                                    P->order[0], 1, s));
+            HS_TRY(hsk::fi_march(P->ctl, all.mg64[0].fine.d, all.sdc[0].d, all.sdc[0].nseg(), all.mg64[0].fine.nblk,
+                                 P->order[0], 0, P->M[0], -1, 1, s));
             P->sweep_k++;
         }
         HS_TRY(hsk::end_step(P->ctl, P->B, s));
