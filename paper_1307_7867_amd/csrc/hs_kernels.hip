@@ -23,6 +23,9 @@
 // the coarsest grid) are this library's choice, the paper names none.
 #include "hs_internal.h"
 
+#include <map>
+#include <mutex>
+
 #include <math.h>
 
 namespace {
@@ -2547,16 +2550,24 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
                 size_t lds_bytes, hipStream_t s)
 {
     if (nseg <= 0) return hipSuccess;
-    // padded 4th-order tails of a 15^3 top grid need more than 64 KB of LDS
-    static size_t allowed[2] = {0, 0};
-    size_t& al = allowed[order == 4 ? 1 : 0];
-    if (lds_bytes > al) {
-        hipError_t e = order == 4 ? hipFuncSetAttribute((const void*)k_tail<T, 4>,
-                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes)
-                                  : hipFuncSetAttribute((const void*)k_tail<T, 2>,
-                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    // padded 4th-order tails of a 15^3 top grid need more than 64 KB of LDS;
+    // the limit is raised once per device and kernel instance
+    if (lds_bytes > 65536) {
+        static std::mutex mu;
+        static std::map<std::pair<int, int>, size_t> allowed;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
-        al = lds_bytes;
+        std::lock_guard<std::mutex> lock(mu);
+        size_t& al = allowed[{dev, order}];
+        if (lds_bytes > al) {
+            e = order == 4 ? hipFuncSetAttribute((const void*)k_tail<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds_bytes)
+                           : hipFuncSetAttribute((const void*)k_tail<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds_bytes);
+            if (e != hipSuccess) return e;
+            al = lds_bytes;
+        }
     }
     HS_ORDER_DISPATCH(order, (k_tail<T, 2>), (k_tail<T, 4>), dim3((unsigned)nseg),
                       dim3(HS_TAIL_THREADS), (unsigned)lds_bytes, segs, ctl, a, nu1, nu2);
