@@ -24,6 +24,7 @@
 #include "hs_internal.h"
 
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include <math.h>
@@ -432,7 +433,18 @@ __device__ __forceinline__ T plane_lap(const T* cell, const T* w, int i, int j, 
 // and the column value of plane z+R+1 are already in flight, so one memory
 // latency is hidden behind every plane.  Every thread of the block must call
 // this (it synchronises); op(p, z, c, L) is called for the points inside the
-// grid with p the linear index, c = src[p] and L = L_h src at p.
+// grid with p the linear index, c = src[p] and L = L_h src at p.  An op with a
+// member pre(p) (a load of its own, such as the right-hand side) has it issued
+// one plane ahead, with the plane loads, and gets the value as op(p, z, c, L, v).
+template <class Op, class = void>
+struct OpPre {
+    static constexpr bool value = false;
+};
+template <class Op>
+struct OpPre<Op, std::void_t<decltype(&Op::pre)>> {
+    static constexpr bool value = true;
+};
+
 template <int ORDER>
 struct Halo {
     static constexpr int R = ORDER == 2 ? 1 : 2;
@@ -486,9 +498,12 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
     typename Src::Col hc[H::HPT];
 #pragma unroll
     for (int h = 0; h < H::HPT; h++) hc[h] = S.col(hgi[h], hgj[h]);
+    constexpr bool PRE = OpPre<Op>::value;
     T w[2 * R + 1];
 #pragma unroll
     for (int d = -R; d <= R; d++) w[d + R] = in ? zval_src<ORDER, T>(S, cc, z0 + d, n, nn, pij) : T(0);
+    T pv = T(0);
+    if constexpr (PRE) pv = in ? op.pre(pij + (long long)z0 * nn) : T(0);
     {
         const long long pz = (long long)z0 * nn;
 #pragma unroll
@@ -506,10 +521,14 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
         for (int h = 0; h < H::HPT; h++)
             hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hc[h], z + 1) : T(0);
         T wn = (more && in) ? zval_src<ORDER, T>(S, cc, z + R + 1, n, nn, pij) : T(0);
+        T pn = T(0);
+        if constexpr (PRE) pn = (more && in) ? op.pre(pz1 + pij) : T(0);
         if (in) {
             const T L = plane_lap<ORDER, T, H::LW>(&pl[buf][ly + R][lx + R], w, i, j, n);
-            op((long long)z * nn + (long long)j * n + i, z, w[R], sc * L);
+            if constexpr (PRE) op((long long)z * nn + pij, z, w[R], sc * L, pv);
+            else op((long long)z * nn + pij, z, w[R], sc * L);
         }
+        pv = pn;
         if (more) {
 #pragma unroll
             for (int h = 0; h < H::HPT; h++)
@@ -546,9 +565,9 @@ struct SweepOp {
     int cycle;
     double rmax, bmax;
     __device__ __forceinline__ SweepOp(T a_, T om, int i, int j, int n_) : a(a_), rd(a_, om, i, j, n_), n(n_) {}
-    __device__ __forceinline__ void operator()(long long p, int z, T c, T L)
+    __device__ __forceinline__ T pre(long long p) const { return b[p]; }
+    __device__ __forceinline__ void operator()(long long p, int z, T c, T L, T bp)
     {
-        T bp = b[p];
         T r = bp - (c - a * L);
         if (MODE == 0) dst[p] = c + rd.at(z, n) * r;
         else dst[p] = r;
@@ -967,6 +986,9 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_resid_fw(const GridSeg* __restr
         w[d + R] = in ? zval_src<ORDER, T>(S, S.col(i, j), z0 + d, n, nn, pij) : T(0);
         we[d + R] = ein ? zval_src<ORDER, T>(S, S.col(ei, ej), z0 + d, n, nn, epij) : T(0);
     }
+    // right-hand side of the plane being formed, loaded one plane ahead
+    T bv = in ? B[z0 * nn + pij] : T(0);
+    T bev = ein ? B[z0 * nn + epij] : T(0);
     {
         const int pz = z0 * nn;
 #pragma unroll
@@ -1011,21 +1033,25 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_resid_fw(const GridSeg* __restr
             hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], S.col(0, 0), z + 1) : T(0);
         const T wn = (more && in) ? zval_src<ORDER, T>(S, S.col(i, j), z + R + 1, n, nn, pij) : T(0);
         const T wen = (more && ein) ? zval_src<ORDER, T>(S, S.col(ei, ej), z + R + 1, n, nn, epij) : T(0);
+        const T bn = (more && in) ? B[pz1 + pij] : T(0);
+        const T ben = (more && ein) ? B[pz1 + epij] : T(0);
         // residual on the main and the extra points of plane z
         T r = T(0);
         if (in) {
             const T L = plane_lap<ORDER, T, G::LW>(&pl[buf][ly + R][lx + R], w, i, j, n);
-            r = B[z * nn + pij] - (w[R] - a * (sc * L));
+            r = bv - (w[R] - a * (sc * L));
         }
         rp[z & 1][ly][lx] = r;
         if (has_x) {
             T re = T(0);
             if (ein) {
                 const T L = plane_lap<ORDER, T, G::LW>(&pl[buf][eyl + R][exl + R], we, ei, ej, n);
-                re = B[z * nn + epij] - (we[R] - a * (sc * L));
+                re = bev - (we[R] - a * (sc * L));
             }
             rp[z & 1][eyl][exl] = re;
         }
+        bv = bn;
+        bev = ben;
         if (cin && z > z0) fw_plane(z - 1);
         if (more) {
 #pragma unroll
@@ -1250,12 +1276,21 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
         if (K1 < nc) s += term(w, K1);
         return T(0.5) * s;
     };
-    // corrected value of column (fi, fj) at plane zf with the z wall rules of the stencil
-    auto zv = [&](const RingTap<T>& w, int pij, int zf) -> T {
-        if (zf >= 0 && zf < n) return x[zf * nn + pij] + corr(w, zf);
+    // value of x that the z wall rules of the stencil read for plane zf of a
+    // column (0 beyond the reach of the rules), and the corrected value from it
+    auto zraw = [&](int pij, int zf) -> T {
+        if (zf >= 0 && zf < n) return x[zf * nn + pij];
         if (ORDER == 4) {
-            if (zf == -2) return -(x[pij] + corr(w, 0));
-            if (zf == n + 1) return -(x[(n - 1) * nn + pij] + corr(w, n - 1));
+            if (zf == -2) return x[pij];
+            if (zf == n + 1) return x[(n - 1) * nn + pij];
+        }
+        return T(0);
+    };
+    auto zfix = [&](const RingTap<T>& w, T raw, int zf) -> T {
+        if (zf >= 0 && zf < n) return raw + corr(w, zf);
+        if (ORDER == 4) {
+            if (zf == -2) return -(raw + corr(w, 0));
+            if (zf == n + 1) return -(raw + corr(w, n - 1));
         }
         return T(0);
     };
@@ -1288,22 +1323,33 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
     }
     const RingTap<T> mw(in ? i : x0 + 1, in ? j : y0 + 1, cx0, cy0, C::CW);
     const int pij = in ? j * n + i : 0;
-    // stage the coarse planes the prologue and the first iteration read
+    // The prologue's loads go out together: the raw column window and halo of
+    // plane z0, the right-hand side of z0, and the coarse planes that the
+    // prologue and the first iteration read (at most NR of them).
+    T w[2 * R + 1];
+#pragma unroll
+    for (int d = -R; d <= R; d++) w[d + R] = in ? zraw(pij, z0 + d) : T(0);
+    T hr[H::HPT];
+#pragma unroll
+    for (int h = 0; h < H::HPT; h++) hr[h] = hin[h] ? x[z0 * nn + hoff[h]] : T(0);
+    T bv = in ? B[z0 * nn + pij] : T(0);
     {
-        const int kt = kneed(z0 + R + 1);
-        kl = klo(z0 - R) - 1;
-        for (int K = kl + 1; K <= kt; K++)
-            if (has_c) cr[K & 3][t / C::CW][t % C::CW] = cin ? cu[K * ncc + coff] : T(0);
+        const int k0 = klo(z0 - R), kt = kneed(z0 + R + 1);
+        T cs[C::NR];
+#pragma unroll
+        for (int s = 0; s < C::NR; s++) cs[s] = (cin && k0 + s <= kt) ? cu[(k0 + s) * ncc + coff] : T(0);
+#pragma unroll
+        for (int s = 0; s < C::NR; s++)
+            if (has_c && k0 + s <= kt) cr[(k0 + s) & 3][t / C::CW][t % C::CW] = cs[s];
         kl = kt;
     }
     __syncthreads();
     const ColRd<ORDER, T> rd(a, om, i, j, n);
-    T w[2 * R + 1];
 #pragma unroll
-    for (int d = -R; d <= R; d++) w[d + R] = in ? zv(mw, pij, z0 + d) : T(0);
+    for (int d = -R; d <= R; d++) w[d + R] = in ? zfix(mw, w[d + R], z0 + d) : T(0);
 #pragma unroll
     for (int h = 0; h < H::HPT; h++)
-        if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? x[z0 * nn + hoff[h]] + corr(hw[h], z0) : T(0);
+        if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? hr[h] + corr(hw[h], z0) : T(0);
     pl[0][ly + R][lx + R] = w[R];
     __syncthreads();
     int buf = 0;
@@ -1316,14 +1362,17 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
         for (int h = 0; h < H::HPT; h++) hv[h] = (more && hin[h]) ? x[(z + 1) * nn + hoff[h]] : T(0);
         const int kt = more ? kneed(z + R + 2) : kl;
         T cv = (has_c && cin && kt > kl) ? cu[kt * ncc + coff] : T(0);
+        const T wr = (more && in) ? zraw(pij, z + R + 1) : T(0);
+        const T bn = (more && in) ? B[(z + 1) * nn + pij] : T(0);
         if (in) {
             const T L = plane_lap<ORDER, T, H::LW>(&pl[buf][ly + R][lx + R], w, i, j, n);
             const int p = z * nn + pij;
             const T c = w[R];
-            const T r = B[p] - (c - a * (sc * L));
+            const T r = bv - (c - a * (sc * L));
             dst[p] = c + rd.at(z, n) * r;
         }
-        const T wn = (more && in) ? zv(mw, pij, z + R + 1) : T(0);
+        bv = bn;
+        const T wn = (more && in) ? zfix(mw, wr, z + R + 1) : T(0);
         if (more) {
 #pragma unroll
             for (int h = 0; h < H::HPT; h++)
