@@ -241,6 +241,10 @@ __device__ __forceinline__ void finish_solve(LaneCtl& c, int cycle, int state)
     if (state == 2) c.failed_solves += 1;
 }
 
+// A lane's multigrid state, read unconditionally (every lane of a table has
+// an entry) so that the load is not tied to the gate flag's branch.
+__device__ __forceinline__ int ld_state(const LaneCtl* ctl, int lane) { return ctl[lane].mg_state; }
+
 __device__ __forceinline__ double lane_a(const LaneCtl* ctl, int lane, int L, int m)
 {
     return m >= 0 ? ctl[lane].a[L][m] : ctl[lane].a_user;
@@ -371,9 +375,12 @@ __device__ __forceinline__ void zmarch(const T* __restrict__ src, int n, int i, 
 template <typename T>
 struct SrcPlain {
     const HS_G T* __restrict__ u;
+    static constexpr bool kSplit = false;
     struct Col {};
     __device__ __forceinline__ Col col(int, int) const { return Col{}; }
-    __device__ __forceinline__ T at(long long p, const Col&, int) const { return u[p]; }
+    __device__ __forceinline__ T raw(long long p) const { return u[p]; }
+    __device__ __forceinline__ T fix(T v, const Col&, int) const { return v; }
+    __device__ __forceinline__ T at(long long p, const Col& c, int z) const { return fix(raw(p), c, z); }
 };
 
 // The first weighted-Jacobi sweep from a zero guess, omega D^{-1} b,
@@ -383,10 +390,39 @@ struct SrcZeroJacobi {
     const HS_G T* __restrict__ b;
     T a, om;
     int n;
+    static constexpr bool kSplit = true;   // the weights take divisions: form them while the loads fly
     using Col = ColRd<ORDER, T>;
     __device__ __forceinline__ Col col(int i, int j) const { return Col(a, om, i, j, n); }
-    __device__ __forceinline__ T at(long long p, const Col& c, int z) const { return c.at(z, n) * b[p]; }
+    __device__ __forceinline__ T raw(long long p) const { return b[p]; }
+    __device__ __forceinline__ T fix(T v, const Col& c, int z) const { return c.at(z, n) * v; }
+    __device__ __forceinline__ T at(long long p, const Col& c, int z) const { return fix(raw(p), c, z); }
 };
+
+// Plane whose value the wall rules of the stencil along z read for plane z
+// (itself inside the grid, the mirrored plane with a sign change for the
+// 4th-order ghost planes -2 and n+1), or -1 where the value is 0.
+template <int ORDER>
+__device__ __forceinline__ int zmirror(int z, int n)
+{
+    if (z >= 0 && z < n) return z;
+    if (ORDER == 4) {
+        if (z == -2) return 0;
+        if (z == n + 1) return n - 1;
+    }
+    return -1;
+}
+
+// Plane z of a column from the raw value loaded at plane zmirror(z): the
+// source's own finishing step, then the wall sign.  Splitting the load from
+// this step lets every load of a plane go out before any of them is used.
+template <int ORDER, typename T, class Src>
+__device__ __forceinline__ T zfix_src(const Src& S, const typename Src::Col& c, T raw, int z, int n)
+{
+    const int zm = zmirror<ORDER>(z, n);
+    if (zm < 0) return T(0);
+    const T v = S.fix(raw, c, zm);
+    return zm == z ? v : -v;
+}
 
 // value of the source on the column with handle c (pij = j n + i) at plane
 // z' with the wall rules of the stencil along z
@@ -436,12 +472,24 @@ __device__ __forceinline__ T plane_lap(const T* cell, const T* w, int i, int j, 
 // grid with p the linear index, c = src[p] and L = L_h src at p.  An op with a
 // member pre(p) (a load of its own, such as the right-hand side) has it issued
 // one plane ahead, with the plane loads, and gets the value as op(p, z, c, L, v).
+// A block whose lane is gated (its solve has stopped) leaves after the
+// prologue and the march returns false: the gate's load then goes out beside
+// the prologue's loads instead of in front of them.
 template <class Op, class = void>
 struct OpPre {
     static constexpr bool value = false;
 };
 template <class Op>
 struct OpPre<Op, std::void_t<decltype(&Op::pre)>> {
+    static constexpr bool value = true;
+};
+
+template <class Op, class = void>
+struct OpBegin {
+    static constexpr bool value = false;
+};
+template <class Op>
+struct OpBegin<Op, std::void_t<decltype(&Op::begin)>> {
     static constexpr bool value = true;
 };
 
@@ -455,8 +503,9 @@ struct Halo {
 };
 
 template <int ORDER, typename T, class Src, typename Op>
-__device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j0, int z0, int z1,
-                                              T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op)
+__device__ __forceinline__ bool lds_march_src(const Src& S, int n, int i0, int j0, int z0, int z1,
+                                              T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op,
+                                              bool gated = false)
 {
     using H = Halo<ORDER>;
     constexpr int R = H::R;
@@ -494,24 +543,46 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
         hoff[h] = hin[h] ? (long long)gj * n + gi : 0;
     }
     const long long pij = (long long)j * n + i;
-    const typename Src::Col cc = S.col(i, j);
-    typename Src::Col hc[H::HPT];
-#pragma unroll
-    for (int h = 0; h < H::HPT; h++) hc[h] = S.col(hgi[h], hgj[h]);
-    constexpr bool PRE = OpPre<Op>::value;
-    T w[2 * R + 1];
-#pragma unroll
-    for (int d = -R; d <= R; d++) w[d + R] = in ? zval_src<ORDER, T>(S, cc, z0 + d, n, nn, pij) : T(0);
+    constexpr bool PRE = OpPre<Op>::value, SPLIT = Src::kSplit;
+    T w[2 * R + 1], hr[H::HPT];
     T pv = T(0);
-    if constexpr (PRE) pv = in ? op.pre(pij + (long long)z0 * nn) : T(0);
-    {
-        const long long pz = (long long)z0 * nn;
+    typename Src::Col cc, hc[H::HPT];
+    if constexpr (SPLIT) {
+        // the prologue's loads first (column window, halo of plane z0, the
+        // op's own value), then the column weights and the op's set-up while
+        // they are in flight, then the finishing steps
 #pragma unroll
-        for (int h = 0; h < H::HPT; h++)
-            if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hin[h] ? S.at(pz + hoff[h], hc[h], z0) : T(0);
-        pl[0][ly + R][lx + R] = w[R];
+        for (int d = -R; d <= R; d++) {
+            const int zm = zmirror<ORDER>(z0 + d, n);
+            w[d + R] = (in && zm >= 0) ? S.raw(pij + (long long)zm * nn) : T(0);
+        }
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++) hr[h] = hin[h] ? S.raw((long long)z0 * nn + hoff[h]) : T(0);
+        if constexpr (PRE) pv = in ? op.pre(pij + (long long)z0 * nn) : T(0);
+        if constexpr (OpBegin<Op>::value) op.begin();
+        cc = S.col(i, j);
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++) hc[h] = S.col(hgi[h], hgj[h]);
+#pragma unroll
+        for (int d = -R; d <= R; d++) w[d + R] = in ? zfix_src<ORDER, T>(S, cc, w[d + R], z0 + d, n) : T(0);
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++) hr[h] = hin[h] ? S.fix(hr[h], hc[h], z0) : T(0);
+    } else {
+        // a plain source: the set-up first, then the loads with the wall rules
+        // applied in place (measured faster for this form)
+        if constexpr (OpBegin<Op>::value) op.begin();
+#pragma unroll
+        for (int d = -R; d <= R; d++) w[d + R] = in ? zval_src<ORDER, T>(S, cc, z0 + d, n, nn, pij) : T(0);
+        if constexpr (PRE) pv = in ? op.pre(pij + (long long)z0 * nn) : T(0);
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++) hr[h] = hin[h] ? S.at((long long)z0 * nn + hoff[h], hc[h], z0) : T(0);
     }
+#pragma unroll
+    for (int h = 0; h < H::HPT; h++)
+        if (hrow[h] >= 0) pl[0][hrow[h]][hcol[h]] = hr[h];
+    pl[0][ly + R][lx + R] = w[R];
     __syncthreads();
+    if (gated) return false;
     int buf = 0;
     for (int z = z0; z < z1; z++) {
         const bool more = z + 1 < z1;
@@ -519,8 +590,14 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
         const long long pz1 = (long long)(z + 1) * nn;
 #pragma unroll
         for (int h = 0; h < H::HPT; h++)
-            hv[h] = (more && hin[h]) ? S.at(pz1 + hoff[h], hc[h], z + 1) : T(0);
-        T wn = (more && in) ? zval_src<ORDER, T>(S, cc, z + R + 1, n, nn, pij) : T(0);
+            hv[h] = (more && hin[h]) ? (SPLIT ? S.raw(pz1 + hoff[h]) : S.at(pz1 + hoff[h], hc[h], z + 1)) : T(0);
+        T wn = T(0);
+        if constexpr (SPLIT) {
+            const int zmn = zmirror<ORDER>(z + R + 1, n);
+            wn = (more && in && zmn >= 0) ? S.raw(pij + (long long)zmn * nn) : T(0);
+        } else {
+            wn = (more && in) ? zval_src<ORDER, T>(S, cc, z + R + 1, n, nn, pij) : T(0);
+        }
         T pn = T(0);
         if constexpr (PRE) pn = (more && in) ? op.pre(pz1 + pij) : T(0);
         if (in) {
@@ -532,23 +609,27 @@ __device__ __forceinline__ void lds_march_src(const Src& S, int n, int i0, int j
         if (more) {
 #pragma unroll
             for (int h = 0; h < H::HPT; h++)
-                if (hrow[h] >= 0) pl[buf ^ 1][hrow[h]][hcol[h]] = hv[h];
+                if (hrow[h] >= 0)
+                    pl[buf ^ 1][hrow[h]][hcol[h]] = SPLIT ? (hin[h] ? S.fix(hv[h], hc[h], z + 1) : T(0)) : hv[h];
             pl[buf ^ 1][ly + R][lx + R] = w[R + 1];
         }
 #pragma unroll
         for (int d = 0; d < 2 * R; d++) w[d] = w[d + 1];
-        w[2 * R] = wn;
+        if constexpr (SPLIT) w[2 * R] = (more && in) ? zfix_src<ORDER, T>(S, cc, wn, z + R + 1, n) : T(0);
+        else w[2 * R] = wn;
         __syncthreads();
         buf ^= 1;
     }
+    return true;
 }
 
 template <int ORDER, typename T, typename Op>
-__device__ __forceinline__ void lds_march(const HS_G T* __restrict__ src, int n, int i0, int j0, int z0,
-                                          int z1, T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op)
+__device__ __forceinline__ bool lds_march(const HS_G T* __restrict__ src, int n, int i0, int j0, int z0,
+                                          int z1, T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op,
+                                          bool gated = false)
 {
     SrcPlain<T> S{src};
-    lds_march_src<ORDER, T>(S, n, i0, j0, z0, z1, pl, op);
+    return lds_march_src<ORDER, T>(S, n, i0, j0, z0, z1, pl, op, gated);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,11 +641,13 @@ struct SweepOp {
     HS_G T* __restrict__ dst;
     const HS_G T* __restrict__ b;
     T a;
-    ColRd<ORDER, T> rd;   // omega / D on this thread's column
-    int n;
+    ColRd<ORDER, T> rd;   // omega / D on this thread's column, formed by begin()
+    T om;
+    int i, j, n;
     int cycle;
     double rmax, bmax;
-    __device__ __forceinline__ SweepOp(T a_, T om, int i, int j, int n_) : a(a_), rd(a_, om, i, j, n_), n(n_) {}
+    __device__ __forceinline__ SweepOp(T a_, T om_, int i_, int j_, int n_) : a(a_), om(om_), i(i_), j(j_), n(n_) {}
+    __device__ __forceinline__ void begin() { rd = ColRd<ORDER, T>(a, om, i, j, n); }
     __device__ __forceinline__ T pre(long long p) const { return b[p]; }
     __device__ __forceinline__ void operator()(long long p, int z, T c, T L, T bp)
     {
@@ -599,7 +682,9 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
-    if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    // the gate is read beside the first loads and tested after them
+    const int lane_state = ld_state(ctl, sg.lane);
+    const bool gated = A.gate && lane_state != 0;
     if (NORM_ == 2) {
         const int b0 = sg.blk_begin, nb = seg_nblk(segs, nseg, si, nblk);
         double r = 0.0, bb = 0.0;
@@ -608,6 +693,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
             if (cycle == 0) bb = nmax(bb, partials[2 * (b0 + q) + 1]);
         }
         block_max2(r, bb);
+        if (gated) return;
         __shared__ int s_state;
         if (threadIdx.x == 0) {
             LaneCtl& c = ctl[sg.lane];
@@ -646,6 +732,8 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     op.rmax = 0.0;
     op.bmax = 0.0;
     if (SRC == 0 && MODE == 0 && !FINEST && first_sweep && sg.coarse) {
+        if (gated) return;
+        op.begin();
         if (q.in)
             for (int z = q.z0; z < q.z1; z++) {
                 long long p = lin(q.i, q.j, z, n);
@@ -654,12 +742,16 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     } else {
         __shared__ T pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
         const int i0 = q.i - (int)(threadIdx.x % HS_TX), j0 = q.j - (int)(threadIdx.x / HS_TX);
+        // NORM 2 has taken the gate with the stopping test
+        const bool g = NORM_ != 2 && gated;
+        bool ran;
         if (SRC == 1 && sg.coarse) {
             SrcZeroJacobi<T, ORDER> S{B, op.a, om, n};
-            lds_march_src<ORDER, T>(S, n, i0, j0, q.z0, q.z1, pl, op);
+            ran = lds_march_src<ORDER, T>(S, n, i0, j0, q.z0, q.z1, pl, op, g);
         } else {
-            lds_march<ORDER, T>(src, n, i0, j0, q.z0, q.z1, pl, op);
+            ran = lds_march<ORDER, T>(src, n, i0, j0, q.z0, q.z1, pl, op, g);
         }
+        if (!ran) return;
     }
     if (NORM) {
         // |b| is taken once per solve
@@ -910,7 +1002,9 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_resid_fw(const GridSeg* __restr
     const int lb = xcd_remap(blockIdx.x, nblk);
     const int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
-    if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    // the gate is read beside the prologue loads and tested after them
+    const int lane_state = ld_state(ctl, sg.lane);
+    const bool gated = A.gate && lane_state != 0;
     const int n = sg.n, nc = sg.nc;
     const PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     const int t = (int)threadIdx.x;
@@ -997,6 +1091,7 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_resid_fw(const GridSeg* __restr
         pl[0][ly + R][lx + R] = w[R];
     }
     __syncthreads();
+    if (gated) return;
     // full weighting of residual plane zp (in rp[zp & 1]) into the running sums
     auto fw_plane = [&](int zp) {
         T az = T(0);
@@ -1236,7 +1331,9 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
     const int lb = xcd_remap(blockIdx.x, nblk);
     const int si = find_seg(segs, nseg, lb);
     const GridSeg sg = segs[si];
-    if (A.gate && ctl[sg.lane].mg_state != 0) return;
+    // the gate is read beside the prologue loads and tested after them
+    const int lane_state = ld_state(ctl, sg.lane);
+    const bool gated = A.gate && lane_state != 0;
     const int n = sg.n, nc = sg.nc;
     const PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     const int t = (int)threadIdx.x;
@@ -1344,6 +1441,7 @@ __global__ void __launch_bounds__(HS_BLOCK, 6) k_pjac(const GridSeg* __restrict_
         kl = kt;
     }
     __syncthreads();
+    if (gated) return;
     const ColRd<ORDER, T> rd(a, om, i, j, n);
 #pragma unroll
     for (int d = -R; d <= R; d++) w[d + R] = in ? zfix(mw, w[d + R], z0 + d) : T(0);
