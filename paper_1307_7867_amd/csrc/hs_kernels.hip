@@ -1656,9 +1656,13 @@ __device__ __forceinline__ void lds_resid(const T* u, const T* b, const T* bv, T
 }
 
 // full weighting of the N^3 residual r (padded) onto the coarse right-hand
-// side cb (unpadded)
-template <typename T, int ORDER, int N>
-__device__ __forceinline__ void lds_restrict(const T* r, T* cb)
+// side cb (unpadded).  With NEXT the coarse grid's starting iterate is
+// written too (padded, to nx): its first pre-smoothing sweep from the zero
+// guess, omega D^{-1} cb with rdc[w] = omega / D next to w walls, the same
+// product that sweep forms, or zero when the grid is not pre-smoothed
+// (rdc null).  That saves the sweep a pass of its own.
+template <typename T, int ORDER, int N, bool NEXT = false>
+__device__ __forceinline__ void lds_restrict(const T* r, T* cb, T* nx = nullptr, const T* rdc = nullptr)
 {
     constexpr int nc = (N - 1) / 2;
     constexpr int Nc = nc * nc * nc;
@@ -1680,6 +1684,11 @@ __device__ __forceinline__ void lds_restrict(const T* r, T* cb)
             acc += w[dz + 1] * az;
         }
         cb[p] = acc;
+        if constexpr (NEXT) {
+            const int walls = ORDER == 2 ? 0
+                                         : (I == 0) + (I == nc - 1) + (J == 0) + (J == nc - 1) + (K == 0) + (K == nc - 1);
+            nx[tpad<nc, ORDER>(I, J, K)] = rdc ? rdc[walls] * acc : T(0);
+        }
     }
 }
 
@@ -1761,6 +1770,7 @@ struct TailCtx {
     const double* lam;
     double* bh;
     unsigned in_y;         // bit l: level l's iterate sits in Y(l)
+    unsigned pre_done;     // bit l: level l's first pre-smoothing sweep was formed by the previous pass
 };
 
 // V(nu1, nu2) from level L down to the coarsest level LAST of a tail whose top
@@ -1778,7 +1788,7 @@ struct TailV {
         T* Yc = Xc + tail_pcube(nc, ORDER);
         T* Bc = Yc + tail_pcube(nc, ORDER);
         const bool zero = L > 0 || c.zero_top;
-        for (int s = 0; s < c.nu1; s++) {
+        for (int s = (int)((c.pre_done >> L) & 1u); s < c.nu1; s++) {
             const bool iy = (c.in_y >> L) & 1u;
             lds_jacobi<T, ORDER, n, L == 0>(iy ? Y : X, iy ? X : Y, B, c.b0, c.a, c.rd[L], zero && s == 0);
             c.in_y ^= 1u << L;
@@ -1789,7 +1799,18 @@ struct TailV {
             T* r = iy ? X : Y;
             lds_resid<T, ORDER, n, L == 0>(iy ? Y : X, B, c.b0, r, c.a);
             __syncthreads();
-            lds_restrict<T, ORDER, n>(r, Bc);
+            if constexpr (L + 1 < LAST) {
+                // the coarse grid starts from zero: its first sweep (into Yc)
+                // or its zero iterate (Xc) comes with its right-hand side
+                const bool pre = c.nu1 > 0;
+                lds_restrict<T, ORDER, n, true>(r, Bc, pre ? Yc : Xc, pre ? c.rd[L + 1] : nullptr);
+                if (pre) {
+                    c.in_y |= 1u << (L + 1);
+                    c.pre_done |= 1u << (L + 1);
+                }
+            } else {
+                lds_restrict<T, ORDER, n>(r, Bc);
+            }
             __syncthreads();
         }
         TailV<T, ORDER, N0, L + 1, LAST>::run(c);
@@ -1880,9 +1901,16 @@ __device__ __forceinline__ void tail_run(const TailSeg& ts, const LaneCtl* __res
     c.lam = s_lam;
     c.bh = s_bh;
     c.in_y = 0;
-    // zero every grid, so the cells beyond the walls read 0
-    constexpr int words = tail_off(N0, ORDER, NLEV);
-    for (int w = t; w < words; w += HS_TAIL_THREADS) base[w] = T(0);
+    c.pre_done = 0;
+    // zero every grid, so the cells beyond the walls read 0 (16-byte stores)
+    {
+        constexpr int bytes = tail_off(N0, ORDER, NLEV) * (int)sizeof(T);
+        uint4* b16 = reinterpret_cast<uint4*>(base);
+        for (int w = t; w < bytes / 16; w += HS_TAIL_THREADS) b16[w] = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (bytes % 16 != 0) {
+            if (t < (bytes % 16) / (int)sizeof(T)) base[(bytes / 16) * (16 / (int)sizeof(T)) + t] = T(0);
+        }
+    }
     __syncthreads();
     // the top grid's result (padded) back to its global iterate
     auto store_top = [&](const T* res) {
@@ -1895,12 +1923,30 @@ __device__ __forceinline__ void tail_run(const TailSeg& ts, const LaneCtl* __res
         lds_exact<T, ORDER, N0>(gb0, c.base, c.a, c.S, c.lam, c.bh);
         store_top(c.base);
     } else {
-        if (!zero_top) {
+        // the top grid's starting iterate: u0, or from a zero start its first
+        // pre-smoothing sweep omega D^{-1} b (into Y, the product that sweep
+        // forms) or zero when it is not pre-smoothed
+        T* X0 = base;
+        T* Y0 = base + tail_pcube(N0, ORDER);
+        const bool pre = zero_top && nu1 > 0;
 #pragma unroll
-            for (int q = 0; q < tail_q<N0>(); q++) {
-                int i, j, k, p;
-                if (tail_pt<N0>(q, i, j, k, p)) base[tpad<N0, ORDER>(i, j, k)] = u0[q];
+        for (int q = 0; q < tail_q<N0>(); q++) {
+            int i, j, k, p;
+            if (!tail_pt<N0>(q, i, j, k, p)) continue;
+            const int pp = tpad<N0, ORDER>(i, j, k);
+            if (!zero_top) {
+                X0[pp] = u0[q];
+            } else if (pre) {
+                const int walls =
+                    ORDER == 2 ? 0 : (i == 0) + (i == N0 - 1) + (j == 0) + (j == N0 - 1) + (k == 0) + (k == N0 - 1);
+                Y0[pp] = s_rd[0][walls] * b0[q];
+            } else {
+                X0[pp] = T(0);
             }
+        }
+        if (pre) {
+            c.in_y |= 1u;
+            c.pre_done |= 1u;
         }
         __syncthreads();
         TailV<T, ORDER, N0, 0, NLEV - 1>::run(c);
