@@ -931,8 +931,11 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         };
         const int sd = fold ? 2 : (S.fused_norm ? (two ? 2 : 1) : 0);   // sweeps and passes of head()
         const int pd = fold ? 2 : (S.fused_norm ? 1 : 0);
-        // the host checks the lanes at the predicted cycle count, then every
-        // second cycle: a gated surplus cycle costs less than a stream round trip
+        // the host checks the lanes at the predicted cycle count, then after
+        // every cycle: a miss is nearly always a count one above the last
+        // solve's, and a round trip (a 4 us copy and about 20 us of host turn-
+        // around) costs less than the gated surplus cycle (11 launches of
+        // about 3 us) that a check every second cycle would let through
         int next_check = pred;
         int c = 0;
         bool head_done = false;
@@ -964,7 +967,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                     pred = mc;
                     break;
                 }
-                next_check = c + 2;
+                next_check = c + 1;
             }
             if (c >= mg.max_cycles) break;
             HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, sd, pd, &par, s));
@@ -992,7 +995,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                     pred = mc;
                     break;
                 }
-                next_check = it + 2;
+                next_check = it + 1;
             }
             if (it >= limit) break;
         }
