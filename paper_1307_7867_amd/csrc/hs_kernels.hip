@@ -474,7 +474,10 @@ __device__ __forceinline__ T plane_lap(const T* cell, const T* w, int i, int j, 
 // one plane ahead, with the plane loads, and gets the value as op(p, z, c, L, v).
 // A block whose lane is gated (its solve has stopped) leaves after the
 // prologue and the march returns false: the gate's load then goes out beside
-// the prologue's loads instead of in front of them.
+// the prologue's loads instead of in front of them.  mid() is called by every
+// thread once the prologue's loads are issued and before their values are
+// used; when it returns false the march returns false (a decision that needs
+// loads of its own overlaps them with the prologue's).
 template <class Op, class = void>
 struct OpPre {
     static constexpr bool value = false;
@@ -502,10 +505,14 @@ struct Halo {
     static constexpr int HPT = (NH + HS_BLOCK - 1) / HS_BLOCK;  // halo cells per thread
 };
 
-template <int ORDER, typename T, class Src, typename Op>
+struct MidNone {
+    __device__ __forceinline__ bool operator()() const { return true; }
+};
+
+template <int ORDER, typename T, class Src, typename Op, class Mid = MidNone>
 __device__ __forceinline__ bool lds_march_src(const Src& S, int n, int i0, int j0, int z0, int z1,
                                               T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op,
-                                              bool gated = false)
+                                              bool gated = false, Mid mid = Mid())
 {
     using H = Halo<ORDER>;
     constexpr int R = H::R;
@@ -559,6 +566,7 @@ __device__ __forceinline__ bool lds_march_src(const Src& S, int n, int i0, int j
 #pragma unroll
         for (int h = 0; h < H::HPT; h++) hr[h] = hin[h] ? S.raw((long long)z0 * nn + hoff[h]) : T(0);
         if constexpr (PRE) pv = in ? op.pre(pij + (long long)z0 * nn) : T(0);
+        if (!mid()) return false;
         if constexpr (OpBegin<Op>::value) op.begin();
         cc = S.col(i, j);
 #pragma unroll
@@ -576,6 +584,7 @@ __device__ __forceinline__ bool lds_march_src(const Src& S, int n, int i0, int j
         if constexpr (PRE) pv = in ? op.pre(pij + (long long)z0 * nn) : T(0);
 #pragma unroll
         for (int h = 0; h < H::HPT; h++) hr[h] = hin[h] ? S.at((long long)z0 * nn + hoff[h], hc[h], z0) : T(0);
+        if (!mid()) return false;
     }
 #pragma unroll
     for (int h = 0; h < H::HPT; h++)
@@ -623,13 +632,13 @@ __device__ __forceinline__ bool lds_march_src(const Src& S, int n, int i0, int j
     return true;
 }
 
-template <int ORDER, typename T, typename Op>
+template <int ORDER, typename T, typename Op, class Mid = MidNone>
 __device__ __forceinline__ bool lds_march(const HS_G T* __restrict__ src, int n, int i0, int j0, int z0,
                                           int z1, T (*pl)[Halo<ORDER>::LH][Halo<ORDER>::LW], Op& op,
-                                          bool gated = false)
+                                          bool gated = false, Mid mid = Mid())
 {
     SrcPlain<T> S{src};
-    return lds_march_src<ORDER, T>(S, n, i0, j0, z0, z1, pl, op, gated);
+    return lds_march_src<ORDER, T>(S, n, i0, j0, z0, z1, pl, op, gated, mid);
 }
 
 // ---------------------------------------------------------------------------
@@ -685,16 +694,31 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     // the gate is read beside the first loads and tested after them
     const int lane_state = ld_state(ctl, sg.lane);
     const bool gated = A.gate && lane_state != 0;
+    // NORM 2: the lane's partial maxima are loaded here (two per thread cover
+    // a norm sweep of up to 2 HS_BLOCK blocks, a loop takes any more) and
+    // reduced once the march's first loads are out
+    const int b0 = sg.blk_begin, nb = NORM_ == 2 ? seg_nblk(segs, nseg, si, nblk) : 0;
+    double pr[2] = {0.0, 0.0}, pb[2] = {0.0, 0.0};
     if (NORM_ == 2) {
-        const int b0 = sg.blk_begin, nb = seg_nblk(segs, nseg, si, nblk);
-        double r = 0.0, bb = 0.0;
-        for (int q = threadIdx.x; q < nb; q += HS_BLOCK) {
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int q = (int)threadIdx.x + k * HS_BLOCK;
+            if (q < nb) {
+                pr[k] = partials[2 * (b0 + q)];
+                if (cycle == 0) pb[k] = partials[2 * (b0 + q) + 1];
+            }
+        }
+    }
+    __shared__ int s_state;
+    // the stopping test (NORM 2); false: the lane stops (or is gated) and the block returns
+    auto decide = [&]() -> bool {
+        double r = nmax(pr[0], pr[1]), bb = nmax(pb[0], pb[1]);
+        for (int q = (int)threadIdx.x + 2 * HS_BLOCK; q < nb; q += HS_BLOCK) {
             r = nmax(r, partials[2 * (b0 + q)]);
             if (cycle == 0) bb = nmax(bb, partials[2 * (b0 + q) + 1]);
         }
         block_max2(r, bb);
-        if (gated) return;
-        __shared__ int s_state;
+        if (gated) return false;
         if (threadIdx.x == 0) {
             LaneCtl& c = ctl[sg.lane];
             const double bn = cycle == 0 ? bb : c.bnorm;
@@ -713,7 +737,11 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
             s_state = state;
         }
         __syncthreads();
-        if (s_state != 0) return;
+        return s_state == 0;
+    };
+    if (NORM_ == 2 && (src_is_t & 4) && sg.coarse) {
+        decide();
+        return;
     }
     if ((src_is_t & 4) && sg.coarse) return;
     const int n = sg.n;
@@ -742,14 +770,15 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
     } else {
         __shared__ T pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
         const int i0 = q.i - (int)(threadIdx.x % HS_TX), j0 = q.j - (int)(threadIdx.x / HS_TX);
-        // NORM 2 has taken the gate with the stopping test
-        const bool g = NORM_ != 2 && gated;
+        // NORM 2 takes the gate with the stopping test, inside the march
         bool ran;
-        if (SRC == 1 && sg.coarse) {
+        if constexpr (NORM_ == 2) {
+            ran = lds_march<ORDER, T>(src, n, i0, j0, q.z0, q.z1, pl, op, false, decide);
+        } else if (SRC == 1 && sg.coarse) {
             SrcZeroJacobi<T, ORDER> S{B, op.a, om, n};
-            ran = lds_march_src<ORDER, T>(S, n, i0, j0, q.z0, q.z1, pl, op, g);
+            ran = lds_march_src<ORDER, T>(S, n, i0, j0, q.z0, q.z1, pl, op, gated);
         } else {
-            ran = lds_march<ORDER, T>(src, n, i0, j0, q.z0, q.z1, pl, op, g);
+            ran = lds_march<ORDER, T>(src, n, i0, j0, q.z0, q.z1, pl, op, gated);
         }
         if (!ran) return;
     }
