@@ -56,12 +56,16 @@ def kernel_hash():
 def measure_jacobi(torch, hs, plan, n, sweeps_a=10, sweeps_b=60):
     """Average duration of one finest-grid Jacobi launch, from HIP events on
     the stream the launches go to (difference of two launch counts removes
-    the fixed cost of the call)."""
+    the fixed cost of the call).  About 2 ms of device work (fills of a
+    1 GiB buffer) is queued ahead of the first event, so the host has queued
+    every timed launch before the device reaches them: the figure is the
+    device's back-to-back time, not the host's launch rate."""
     N = n ** 3
     g = torch.Generator(device="cuda").manual_seed(0)
     u = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
     b = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
     tmp = torch.empty_like(u)
+    pad = torch.empty(2 ** 27, dtype=torch.float64, device="cuda")
     a = 0.1 * 0.05 * 0.17267316464601146
     s = torch.cuda.current_stream()
     plan.smooth(u, b, tmp, a, 2)   # table upload and warm-up
@@ -69,6 +73,8 @@ def measure_jacobi(torch, hs, plan, n, sweeps_a=10, sweeps_b=60):
     for k in (sweeps_a, sweeps_b):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         s.synchronize()
+        for _ in range(10):
+            pad.fill_(1.0)
         e0.record(s)
         plan.smooth(u, b, tmp, a, k)
         e1.record(s)
