@@ -579,6 +579,9 @@ __device__ __forceinline__ bool lds_march_src(const Src& S, int n, int i0, int j
         // a plain source: the set-up first, then the loads with the wall rules
         // applied in place (measured faster for this form)
         if constexpr (OpBegin<Op>::value) op.begin();
+        cc = S.col(i, j);
+#pragma unroll
+        for (int h = 0; h < H::HPT; h++) hc[h] = S.col(hgi[h], hgj[h]);
 #pragma unroll
         for (int d = -R; d <= R; d++) w[d + R] = in ? zval_src<ORDER, T>(S, cc, z0 + d, n, nn, pij) : T(0);
         if constexpr (PRE) pv = in ? op.pre(pij + (long long)z0 * nn) : T(0);
