@@ -154,7 +154,7 @@ struct MgArgs {
     int32_t m;         // substep (index into a[L][]); -1 = a_user
     double omega;
     int32_t node;      // node of the finest grid
-    int32_t gate;      // 1 = skip lanes whose mg_state != 0
+    int32_t gate;      // 1 = skip lanes whose mg_state != 0; 2 (copy-back only) = skip lanes still solving
 };
 
 int grid_blocks(int n, int zb = 1);   // blocks covering an n^3 grid, zb planes per block
@@ -203,7 +203,8 @@ hipError_t pjac(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order
 
 // Copy the finest iterate from t back to u for the lanes whose grid moves
 // (GridSeg::moves) and whose solve ran an odd number of V-cycles (when every
-// cycle moves the iterate an odd number of times).
+// cycle moves the iterate an odd number of times).  a.gate == 2: only lanes
+// whose solve has stopped (issued before the host knows which have).
 hipError_t mg_fixup(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, hipStream_t s);
 
 // Residual b - A x (x picked by src_is_t) restricted by full weighting into
@@ -246,7 +247,9 @@ hipError_t make_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int m,
                     hipStream_t s);
 // FI_m = nu L U_m at nodes m0..m1-1 (and rhs = U + P at node rhs_node, -1 for
 // none) over the blocks of the lanes' finest-grid z-marching table gsegs; the
-// SDC table ssegs holds the same lanes in the same order.
+// SDC table ssegs holds the same lanes in the same order.  gate 1: lanes whose
+// SDC iteration has stopped skip; gate 2: also lanes whose current solve is
+// still running.
 hipError_t fi_march(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int nseg, int nblk, int order,
                     int m0, int m1, int rhs_node, int gate, hipStream_t s);
 hipError_t sdc_resid(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, double* partials,

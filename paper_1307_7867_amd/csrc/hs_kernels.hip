@@ -1533,6 +1533,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_fixup(const GridSeg* __restrict
     const GridSeg sg = segs[si];
     const LaneCtl& c = ctl[sg.lane];
     if (!sg.moves || c.mg_state == 3 || (c.mg_cycle & 1) == 0) return;
+    if (A.gate == 2 && c.mg_state == 0) return;   // issued ahead of the host's check: stopped solves only
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     if (!q.in) return;
@@ -2332,6 +2333,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_fi_march(const GridSeg* __restrict
     const GridSeg sg = gsegs[si];
     const SdcSeg ss = ssegs[si];
     if (gate && ctl[sg.lane].sdc_state != 0) return;
+    if (gate == 2 && ctl[sg.lane].mg_state == 0) return;   // issued ahead of the host's check: stopped solves only
     const int n = sg.n;
     PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     const long long N = (long long)n * n * n;

@@ -264,6 +264,7 @@ struct hs_plan {
     std::vector<CycleGraph> cgraphs;
     unsigned set_epoch = 0;                    // bumped when a lane set's tables change
     hipStream_t cap = nullptr;                 // capture stream (nothing runs on it)
+    hipEvent_t ev_ctl = nullptr;               // marks the lane states' copy to h_ctl
 };
 
 namespace {
@@ -877,9 +878,41 @@ hs_status cycle_graph(hs_plan* P, const LaneSet& ls, int L, int m, int node, int
     return HS_OK;
 }
 
+// The work that follows a substep's solve in an SDC sweep: F_I at the solved
+// node (and the next substep's right-hand side), over the lanes' finest grids.
+struct PostSolve {
+    const Table<GridSeg>* F;
+    const Table<SdcSeg>* T;
+    int order, m0, m1, rhs_node;
+    bool done = false;   // the launches issued at the final check were the real ones
+};
+
+// Read the lane states back at a check.  With post, the solve's closing
+// launches (the iterate's copy-back and the post-solve work) are issued
+// behind the states' copy, gated to the lanes whose solve has stopped: they
+// run while the host waits for the copy and decides.  If every lane has
+// stopped they were the real launches; otherwise they did the stopped lanes'
+// share, and the launches after the solve repeat it with the same result.
+hs_status read_ctl_ahead(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int nu2, const PostSolve* post,
+                         hipStream_t s)
+{
+    if (!post) return read_ctl(P, s);
+    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->B, hipMemcpyDeviceToHost, s));
+    HS_TRY(hipEventRecord(P->ev_ctl, s));
+    hsk::MgArgs G = A;
+    G.gate = 2;
+    HS_CHECK(mg_finish(P, S, G, nu1, nu2, s));
+    HS_TRY(hsk::fi_march(P->ctl, post->F->d, post->T->d, post->T->nseg(), post->F->nblk, post->order, post->m0,
+                         post->m1, post->rhs_node, 2, s));
+    HS_TRY(hipEventSynchronize(P->ev_ctl));
+    return HS_OK;
+}
+
 // Solve (I - a L) U_node = rhs for the lanes of ls at SDC level L; a from
-// the lane's a[L][m] (m >= 0) or a_user (m = -1).
-hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t s, bool* synced)
+// the lane's a[L][m] (m >= 0) or a_user (m = -1).  post: see read_ctl_ahead;
+// when post->done is set on return the post-solve work has been issued.
+hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t s, bool* synced,
+                   PostSolve* post = nullptr)
 {
     const hs_mg_desc& mg = P->pb.mg;
     int order = P->order[L];
@@ -960,11 +993,15 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             if (!head_done) HS_CHECK(head(c, par, s));
             head_done = false;
             if (c >= next_check || c >= mg.max_cycles) {
-                HS_CHECK(read_ctl(P, s));
+                HS_CHECK(read_ctl_ahead(P, S, A, mg.nu1, mg.nu2, post, s));
                 if (synced) *synced = true;
                 int mc = 0;
                 if (all_mg_done(P, ls, &mc)) {
                     pred = mc;
+                    if (post) {
+                        post->done = true;
+                        return HS_OK;
+                    }
                     break;
                 }
                 next_check = c + 1;
@@ -1031,9 +1068,11 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
     if (count) HS_TRY(hsk::begin_sweep(P->ctl, P->B, s));
     HS_TRY(hsk::make_rhs(P->ctl, T.d, T.nseg(), T.nblk, 0, 1, s));
     for (int m = 0; m + 1 < M; m++) {
-        HS_CHECK(mg_solve(P, ls, L, m, m + 1, s, nullptr));
-        HS_TRY(hsk::fi_march(P->ctl, F.d, T.d, T.nseg(), F.nblk, P->order[L], m + 1, m + 2, m + 2 < M ? m + 1 : -1,
-                             1, s));
+        PostSolve post{&F, &T, P->order[L], m + 1, m + 2, m + 2 < M ? m + 1 : -1};
+        HS_CHECK(mg_solve(P, ls, L, m, m + 1, s, nullptr, &post));
+        if (!post.done)
+            HS_TRY(hsk::fi_march(P->ctl, F.d, T.d, T.nseg(), F.nblk, P->order[L], post.m0, post.m1, post.rhs_node,
+                                 1, s));
     }
     if (P->nlev == 1) P->sweep_k++;
     return HS_OK;
@@ -1236,6 +1275,7 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
     drop_cycle_graphs(P);
     layout(P, P->ws);
     if (!P->h_ctl) HS_TRY(hipHostMalloc((void**)&P->h_ctl, sizeof(LaneCtl) * P->B, hipHostMallocDefault));
+    if (!P->ev_ctl) HS_TRY(hipEventCreateWithFlags(&P->ev_ctl, hipEventDisableTiming));
     // sine tables sin(pi (i+1) h)
     std::map<const double*, int> sig;
     for (auto& lb : P->lanes)
@@ -1277,6 +1317,7 @@ hs_status hs_plan_destroy(hs_plan* P)
     drop_cycle_graphs(P);
     if (P->cap) (void)hipStreamDestroy(P->cap);
     if (P->h_ctl) (void)hipHostFree(P->h_ctl);
+    if (P->ev_ctl) (void)hipEventDestroy(P->ev_ctl);
     delete P;
     return HS_OK;
 }
