@@ -116,7 +116,7 @@ def main():
                     help="mlsdc127 (default): the headline two-level MLSDC run; the others are the "
                          "mixed-precision, PFASST-slice, uneven-batch and serving workloads")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--sdc-tol", type=float, default=1e-9)
+    ap.add_argument("--sdc-tol", type=float, default=1e-10)
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--rates", default="0.5,1.0,1.5")
     ap.add_argument("--max-n", type=int, default=511)

@@ -170,10 +170,15 @@ void worker(hs_server* S, Class* Cp)
                 out = S->reqs[tk].d_out;
             }
             if (st[l].steps_done < nsteps && st[l].status == HS_OK) continue;
-            hs_get_lane_state(C.plan, l, out, C.stream);
-            hs_set_lane(C.plan, l, 0.1, 0.01, 0.0, 0, 0, C.stream);
-            (void)hipStreamSynchronize(C.stream);
-            retire(S, C, l, st[l]);
+            // the result copy and the lane's release must both succeed, else the
+            // request finishes with the failure instead of an unwritten output
+            hs_lane_stats fin = st[l];
+            hs_status ce = hs_get_lane_state(C.plan, l, out, C.stream);
+            hs_status re = hs_set_lane(C.plan, l, 0.1, 0.01, 0.0, 0, 0, C.stream);
+            if (hipStreamSynchronize(C.stream) != hipSuccess && ce == HS_OK) ce = HS_EDEVICE;
+            if (ce != HS_OK) fin.status = ce;
+            else if (re != HS_OK) fin.status = re;
+            retire(S, C, l, fin);
         }
     }
 }

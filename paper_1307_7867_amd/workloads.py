@@ -5,9 +5,9 @@ record.  Inputs are synthetic (paper_1307_7867_amd.inputs), generated on the
 host and copied to HBM before any timed region.
 
   mixed255  255^3, 4th order, 5 nodes, dt 0.02, 10 steps, 8 random sine
-            modes: FP32 V(2,2) inside FP64 refinement to 1e-10 relative
+            modes: FP32 V(2,2) inside FP64 refinement to 1e-12 relative
             residual, against FP64 V(2,1) to 1e-12; SDC sweeps until the
-            collocation residual is below --sdc-tol.
+            collocation residual is below --sdc-tol (1e-10).
   pfasst16  16 PFASST time slices x 5 nodes, 127^3 (4th order) / 63^3 (2nd
             order), dt 0.01, 4 iterations, every phase one batched launch
             sequence over the slices; against 16 serial MLSDC steps; plus the
@@ -48,7 +48,9 @@ def mixed255(args):
     u0 = _dev(inputs.random_smooth(n, args.seed))
     res = {}
     outs = {}
-    for name, prec, tol, inner in (("mixed", hs.HS_MIXED, 1e-10, (2, 2)), ("fp64", hs.HS_FP64, 1e-12, (2, 2))):
+    # refinement to 1e-12 relative: the SDC threshold 1e-10 is then reachable and the
+    # mixed result stays within 1e-10 of the FP64 one
+    for name, prec, tol, inner in (("mixed", hs.HS_MIXED, 1e-12, (2, 2)), ("fp64", hs.HS_FP64, 1e-12, (2, 2))):
         pb = hs.Problem(n=n, order=4, nnodes=M, nu=0.1, dt=dt, nsteps=nsteps, sweeps=0,
                         sdc_tol=args.sdc_tol, max_sweeps=40, precision=prec, tol=tol, max_cycles=80,
                         inner_nu1=inner[0], inner_nu2=inner[1])

@@ -8,11 +8,12 @@ benchmark times.
   oracle.  The multigrid runs a fixed 2 V(2,1) cycles per solve so the CPU
   oracle finishes in seconds; the kernels, tables and launch shapes are the
   ones of the tolerance-driven benchmark run.
-* 255^3, 4th order, 5 nodes, FP32 multigrid inside FP64 iterative
-  refinement, SDC swept to a residual of 1e-9, 8 random sine modes: the CPU
-  oracle is too slow at this size, so the end state is compared with the
-  exact collocation solution (per-mode solve of eq. (6), which converged SDC
-  reaches).  Bound: the SDC residual R <= sdc_tol per step maps to an error
+* 255^3, 4th order, 5 nodes, FP64 multigrid, SDC swept to a residual of
+  1e-10, 8 random sine modes (the mixed-precision runs of this configuration
+  are in test_gpu_configs.py): the CPU oracle is too slow at this size, so
+  the end state is compared with the exact collocation solution (per-mode
+  solve of eq. (6), which converged SDC reaches).  Bound: the SDC residual
+  R <= sdc_tol per step maps to an error
   of at most ||(I - z Q)^{-1}|| * R <= 1.7 R per step over all stiffness
   z = dt nu lambda <= 0 (5 Lobatto nodes; checked by the
   oracle pin test_collocation_inverse_bound), the step map is a contraction, so after
@@ -95,14 +96,13 @@ def test_mlsdc_127_first_iteration_parity(torch):
     assert np.abs(host(gtau).reshape(tau.shape) - tau).max() <= 1e-11 * dt * np.abs(FIf).max()
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_mixed_255_vs_collocation(torch, precision):
+def test_fp64_255_vs_collocation(torch):
     from paper_1307_7867_amd import heatst as hs
-    n, M, nu, dt, nsteps, sdc_tol = 255, 5, 0.1, 0.02, 2, 1e-9
+    n, M, nu, dt, nsteps, sdc_tol = 255, 5, 0.1, 0.02, 2, 1e-10
+    precision = "fp64"
     modes = inputs.random_modes(0)
-    prec, tol = (hs.HS_MIXED, 1e-10) if precision == "mixed" else (hs.HS_FP64, 1e-12)
     pb = hs.Problem(n=n, order=4, nnodes=M, nu=nu, dt=dt, nsteps=nsteps, sweeps=0, sdc_tol=sdc_tol,
-                    max_sweeps=40, precision=prec, tol=tol, max_cycles=80, inner_nu1=2, inner_nu2=2)
+                    max_sweeps=40, precision=hs.HS_FP64, tol=1e-12, max_cycles=80)
     plan = hs.Plan(pb)
     plan.set_state(dev(torch, inputs.modes_field(n, modes)))
     plan.solve()

@@ -245,24 +245,6 @@ def test_mg_nonfinite_reported(torch):
     assert e.value.status == hs.HS_ENONFINITE
 
 
-@pytest.mark.parametrize("order", [2, 4])
-def test_mg_mixed_precision_refinement(torch, order):
-    hs = heatst_mod()
-    n = 63
-    a = 0.002
-    plan = hs.Plan(hs.Problem(n=n, order=order, nnodes=3, precision=hs.HS_MIXED, tol=1e-10,
-                              max_cycles=60))
-    b = inputs.random_smooth(n, 3)
-    u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
-    plan.mg_vcycle(u, dev(torch, b), a)
-    got = host(u).reshape(n, n, n)
-    ref, s, cyc, rho = oracle.mg_solve(b, order, a, mg=oracle.mg_params(tol=1e-14, max_cycles=200))
-    # relative residual of the GPU result, in FP64 on the CPU
-    r = oracle.residual(got, b, order, a)
-    assert np.abs(r).max() / np.abs(b).max() <= 1e-10
-    assert rel(got, ref) <= 1e-9
-
-
 # ----------------------------------------------------------------------------
 # SDC
 # ----------------------------------------------------------------------------
