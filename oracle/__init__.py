@@ -97,6 +97,7 @@ def lib():
                                     C.POINTER(Stats)]
         L.or_run.argtypes = [C.POINTER(Problem), _D, C.POINTER(Stats)]
         L.or_pfasst_run.argtypes = [C.POINTER(Problem), C.c_int, _D, C.POINTER(Stats)]
+        L.or_pfasst.argtypes = [C.POINTER(Problem), C.c_int, C.c_int, _D, C.POINTER(Stats)]
     return _lib
 
 
@@ -282,4 +283,15 @@ def pfasst_run(pb, P, u0):
     u = _f(u0).copy()
     st = Stats()
     s = lib().or_pfasst_run(C.byref(pb), P, _p(u), C.byref(st))
+    return u, s, st
+
+
+def pfasst(pb, P, u0, pred_sweeps=0):
+    """PFASST with an optional serial coarse predictor (pred_sweeps coarse
+    sweeps per slice) and, with pb.sweeps == 0, iterations until every
+    slice's collocation residual is <= pb.sdc_tol.  Returns (u, status, Stats);
+    Stats.sweeps is the number of iterations of the last block."""
+    u = _f(u0).copy()
+    st = Stats()
+    s = lib().or_pfasst(C.byref(pb), P, pred_sweeps, _p(u), C.byref(st))
     return u, s, st

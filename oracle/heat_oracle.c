@@ -20,6 +20,10 @@
  *
  * Compile with -ffp-contract=off: no fused multiply-adds, so every
  * expression is rounded exactly as written.
+ *
+ * Parity unpinned: the timing of PFASST's fine hand-off in or_pfasst (the
+ * previous iteration's end value) is a reading that no test fixes; every
+ * other function is pinned by tests/test_oracle_pins.py.
  */
 #include <math.h>
 #include <stdint.h>
@@ -875,22 +879,43 @@ int or_run(const or_problem *pb, double *u, or_stats *st)
  * concurrently on P time slices; new values are passed forward after each
  * level's sweep; the coarse level hands over in a blocking pipeline).  This
  * is the reading used, one block of P consecutive steps starting at t0 from
- * u; iterations fixed at pb->sweeps:
+ * u:
  *  - every slice starts with u spread over all of its fine nodes;
+ *  - optional coarse predictor (pred_sweeps > 0; also a reading: the paper
+ *    leaves PFASST's start to its references and notes that early
+ *    iterations on later slices start from inaccurate values): the coarse
+ *    level is run serially through the slices without the FAS correction.
+ *    Slice p restricts its fine values; for p >= 1 its coarse nodes all take
+ *    the coarse end value of slice p-1 (spread, as a time step starts);
+ *    then pred_sweeps coarse sweeps.  Every slice then interpolates its
+ *    coarse correction (node 0 included) to the fine level.  The coarse
+ *    values this leaves are those of a serial coarse SDC run over the P
+ *    steps with pred_sweeps sweeps each;
  *  - iteration: (i) for p >= 1, fine node 0 of slice p takes the fine end
- *    value of slice p-1 as it stood at the end of the previous iteration;
- *    fine sweep on every slice; (ii) restriction + tau on every slice;
- *    (iii) slices in order p = 0..P-1: for p >= 1 coarse node 0 takes the
- *    coarse end value slice p-1 has just computed, then the coarse sweep;
- *    (iv) interpolation on every slice, node 0 included.
+ *    value of slice p-1 as it stood at the end of the previous iteration
+ *    (the predictor's result before the first) -- parity unpinned: no pin
+ *    distinguishes this timing from taking the end value of the current
+ *    iteration; fine sweep on every slice;
+ *    (ii) restriction + tau on every slice; (iii) slices in order
+ *    p = 0..P-1: for p >= 1 coarse node 0 takes the coarse end value slice
+ *    p-1 has just computed, then the coarse sweep; (iv) interpolation on
+ *    every slice, node 0 included;
+ *  - pb->sweeps > 0: exactly that many iterations.  pb->sweeps == 0: after
+ *    the fine hand-off of every iteration the collocation residual of every
+ *    slice is taken (eq. (6) moved to one side, max norm, absolute, as in
+ *    or_sdc_residual); the iteration stops when the largest is at most
+ *    pb->sdc_tol (section 2 thresholds the residual of the PFASST
+ *    iterations) and fails with OR_ENOCONV after pb->max_sweeps iterations;
  *  - the result is the fine end value of slice P-1.
  * nsteps must be a multiple of P; blocks run one after the other.
+ * st->sweeps: iterations of the last block.
  */
-int or_pfasst_run(const or_problem *pb, int P, double *u, or_stats *st)
+int or_pfasst(const or_problem *pb, int P, int pred_sweeps, double *u, or_stats *st)
 {
     int s = check_problem(pb);
     if (s != OR_OK) return s;
-    if (pb->nlevels != 2 || P < 1 || pb->nsteps % P != 0 || pb->sweeps <= 0) return OR_EINVAL;
+    if (pb->nlevels != 2 || P < 1 || pb->nsteps % P != 0 || pb->sweeps < 0 || pred_sweeps < 0)
+        return OR_EINVAL;
     const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
     int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
     size_t Nf = cube(nf), Nc = cube(nc);
@@ -899,17 +924,49 @@ int or_pfasst_run(const or_problem *pb, int P, double *u, or_stats *st)
     double *Uc = alloc0(P * SC), *FIc = alloc0(P * SC), *Ut = alloc0(P * SC), *tau = alloc0(P * SC);
     double *ends = alloc0((size_t)P * Nf);
     if (st) memset(st, 0, sizeof(*st));
-    int status = OR_OK;
+    int status = OR_OK, k = 0;
     for (int blk = 0; blk < pb->nsteps / P; blk++) {
         double tb = pb->t0 + (double)(blk * P) * pb->dt;
         for (int p = 0; p < P; p++) or_spread(Lf, pb->nu, u, Uf + p * SF, FIf + p * SF);
-        for (int k = 0; k < pb->sweeps; k++) {
+        if (pred_sweeps > 0) {
+            for (int p = 0; p < P; p++) {
+                double tn = tb + p * pb->dt;
+                or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf + p * SF, FIf + p * SF,
+                                Uc + p * SC, FIc + p * SC, Ut + p * SC, tau + p * SC);
+                if (p >= 1) {
+                    /* the coarse step starts from slice p-1's end value, spread */
+                    memcpy(ends, Uc + (p - 1) * SC + (size_t)(Mc - 1) * Nc, Nc * sizeof(double));
+                    or_spread(Lc, pb->nu, ends, Uc + p * SC, FIc + p * SC);
+                }
+                for (int j = 0; j < pred_sweeps; j++) {
+                    s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc + p * SC, FIc + p * SC,
+                                     NULL, NULL);
+                    if (s != OR_OK && status == OR_OK) status = s;
+                }
+            }
+            for (int p = 0; p < P; p++)
+                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC);
+        }
+        for (k = 0;; k++) {
+            if (pb->sweeps > 0 && k >= pb->sweeps) break;
             /* (i) fine hand-off from the previous iteration's end values */
             for (int p = 0; p < P; p++)
                 memcpy(ends + (size_t)p * Nf, Uf + p * SF + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
             for (int p = 1; p < P; p++) {
                 memcpy(Uf + p * SF, ends + (size_t)(p - 1) * Nf, Nf * sizeof(double));
                 or_lap_apply(nf, Lf->order, 0.0, pb->nu, Uf + p * SF, FIf + p * SF);
+            }
+            if (pb->sweeps == 0) {
+                double R = 0.0;
+                for (int p = 0; p < P; p++) {
+                    double r = or_sdc_residual(Lf, pb->nu, tb + p * pb->dt, pb->dt, pb->forcing_c, Uf + p * SF,
+                                               FIf + p * SF, NULL);
+                    if (r > R || r != r) R = r;
+                }
+                if (st) st->last_residual = R;
+                if (R != R) { if (status == OR_OK) status = OR_ENONFINITE; break; }
+                if (R <= pb->sdc_tol) break;
+                if (k >= pb->max_sweeps) { if (status == OR_OK) status = OR_ENOCONV; break; }
             }
             for (int p = 0; p < P; p++) {
                 double tn = tb + p * pb->dt;
@@ -939,7 +996,14 @@ int or_pfasst_run(const or_problem *pb, int P, double *u, or_stats *st)
         }
         memcpy(u, Uf + (size_t)(P - 1) * SF + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
     }
-    if (st) { st->status = status; st->sweeps = pb->sweeps; }
+    if (st) { st->status = status; st->sweeps = k; }
     free(Uf); free(FIf); free(Uc); free(FIc); free(Ut); free(tau); free(ends);
     return status;
+}
+
+/* PFASST with fixed iterations and no predictor (see or_pfasst). */
+int or_pfasst_run(const or_problem *pb, int P, double *u, or_stats *st)
+{
+    if (pb->sweeps <= 0) return OR_EINVAL;
+    return or_pfasst(pb, P, 0, u, st);
 }

@@ -536,6 +536,82 @@ def test_pfasst_few_iterations_differs_from_serial():
     assert np.abs(u - v).max() > 1e-9
 
 
+def test_pfasst_tolerance_one_slice_is_mlsdc_tolerance():
+    """PFASST iterating until the collocation residual is <= sdc_tol, on one
+    slice, is MLSDC with the same stopping rule: same result bit for bit and
+    the same number of iterations (two different code paths of the oracle)."""
+    pb = two_level(nf=15, nsteps=2, sweeps=0)
+    pb.sdc_tol, pb.max_sweeps = 1e-10, 30
+    u0 = inputs.random_smooth(15, 12)
+    a, s1, st1 = oracle.run(pb, u0)
+    b, s2, st2 = oracle.pfasst(pb, 1, u0)
+    assert s1 == s2 == oracle.OK
+    assert st2.sweeps == st1.sweeps >= 2
+    assert np.array_equal(a, b)
+
+
+def test_pfasst_tolerance_converges_to_serial_composite_collocation():
+    """Residual-based termination at 1e-12 on 4 slices lands within a few
+    1e-12 of the serial composite collocation solution, with and without
+    the coarse predictor."""
+    P = 4
+    pb = two_level(nf=7, nsteps=P, sweeps=0, dt=0.05)
+    pb.sdc_tol, pb.max_sweeps = 1e-12, 80
+    u0 = inputs.random_smooth(7, 8)
+    ref = u0.copy()
+    for p in range(P):
+        Uf, _ = fine_collocation(pb, ref, p * pb.dt)
+        ref = Uf[-1].copy()
+    iters = []
+    for pred in (0, 2):
+        u, s, st = oracle.pfasst(pb, P, u0, pred_sweeps=pred)
+        assert s == oracle.OK
+        assert np.abs(u - ref).max() < 2e-11, pred
+        iters.append(st.sweeps)
+    assert all(2 <= k < 80 for k in iters)
+
+
+def test_pfasst_tolerance_reports_nonconvergence():
+    pb = two_level(nf=7, nsteps=4, sweeps=0, dt=0.05)
+    pb.sdc_tol, pb.max_sweeps = 1e-14, 2
+    u, s, st = oracle.pfasst(pb, 4, inputs.random_smooth(7, 8))
+    assert s == oracle.ENOCONV and st.sweeps == 2
+
+
+@pytest.mark.parametrize("pred", [1, 3])
+def test_pfasst_predictor_is_serial_coarse_sdc(pred):
+    """The coarse predictor runs the coarse level serially through the slices
+    (no FAS correction): after it, the last slice's coarse end value is that
+    of a single-level coarse SDC run over the P steps with `pred` sweeps per
+    step from the injected initial value, and the fine end value is u0 plus
+    the trilinear prolongation of the coarse change.  A tolerance so loose
+    that the first residual test stops the run returns exactly that."""
+    P, nf = 4, 15
+    nc = (nf - 1) // 2
+    pb = two_level(nf=nf, nsteps=P, sweeps=0, dt=0.05)
+    pb.sdc_tol, pb.max_sweeps = 1e300, 10
+    u0 = inputs.random_smooth(nf, 13)
+    got, s, st = oracle.pfasst(pb, P, u0, pred_sweeps=pred)
+    assert s == oracle.OK and st.sweeps == 0
+    uc0 = oracle.inject(u0)
+    cpb = oracle.problem([(nc, 2, 3)], nu=pb.nu, dt=pb.dt, nsteps=P, sweeps=pred, forcing_c=pb.forcing_c,
+                         mg=pb.mg)
+    uc, s2, _ = oracle.run(cpb, uc0)
+    assert s2 == oracle.OK
+    expect = oracle.prolong_add(uc - uc0, u0)
+    assert np.array_equal(got, expect)
+
+
+def test_pfasst_predictor_changes_the_start():
+    """Control for the pin above: without the predictor the same run returns
+    the spread initial value."""
+    pb = two_level(nf=15, nsteps=4, sweeps=0, dt=0.05)
+    pb.sdc_tol, pb.max_sweeps = 1e300, 10
+    u0 = inputs.random_smooth(15, 13)
+    got, s, st = oracle.pfasst(pb, 4, u0, pred_sweeps=0)
+    assert np.array_equal(got, u0)
+
+
 def test_collocation_reference_matches_converged_oracle_sdc():
     """The per-mode collocation reference (oracle/collocation.py) equals many
     SDC sweeps of the 3-D oracle on sine-mode data (two steps)."""
