@@ -32,8 +32,9 @@
  *     at the sum of n_{b'}^3 over b' < b.
  *   - All device memory is owned by the caller: hs_workspace_bytes gives
  *     the exact size, hs_plan_bind hands it over.  The library never
- *     allocates device memory.  The plan object itself is host memory owned
- *     by the library (hs_plan_create / hs_plan_destroy).
+ *     allocates device memory; its one static device array (8 MiB per GPU)
+ *     serves hs_mg_solve_static only.  The plan object itself is host
+ *     memory owned by the library (hs_plan_create / hs_plan_destroy).
  *   - Pointers named d_* are device pointers, h_* host pointers.
  *   - stream is a hipStream_t (NULL = default stream).  Every call is
  *     asynchronous on it unless documented otherwise.
@@ -191,6 +192,28 @@ hs_status hs_mg_vcycle(hs_plan* plan, int32_t level, const double* h_a, double* 
  * launch of the same kernel the solver uses on its finest grids. */
 hs_status hs_smooth(hs_plan* plan, int32_t level, const double* h_a, double* d_u,
                     const double* d_b, double* d_tmp, int32_t nsweeps, void* stream);
+
+/* Allocation-free variant of hs_mg_vcycle for one grid, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  It solves
+ * (I - a L_h) u = b on one n^3 grid of the given Laplacian order with the
+ * multigrid of *mg, from the initial guess in d_u (overwritten with the
+ * solution; d_b is only read), exactly as hs_mg_vcycle does on a one-lane
+ * plan (same kernels, same stopping rule, same results).  No plan or
+ * workspace: the coarse grids, the lane state, the segment tables and the
+ * reduction partials live in a static device array of 8 MiB per GPU, which
+ * the GPU holds from the first call until the process ends.  n must be at
+ * most HS_STATIC_MAX_N (63), else HS_ENOMEM and nothing is launched;
+ * mg->cycle_graphs must be 0 (HS_EINVAL).  The call allocates nothing on
+ * the device or in pinned host memory and creates no stream or event; it
+ * synchronises `stream` and returns the solve's status (HS_ENOCONV,
+ * HS_ENONFINITE as hs_mg_vcycle).  Every call on one GPU uses that GPU's
+ * array and re-initialises all of it that it reads: calls that overlap on
+ * one GPU (other host threads, other streams) race and must be serialised
+ * by the caller. */
+#define HS_STATIC_MAX_N 63
+hs_status hs_mg_solve_static(int32_t n, int32_t order, double a, const hs_mg_desc* mg, double* d_u,
+                             const double* d_b, void* stream);
 
 /* State (the value at the start of the next step) of every lane, lane-major
  * fine-level fields.  hs_set_state also resets the lanes' step counters.

@@ -265,6 +265,11 @@ struct hs_plan {
     unsigned set_epoch = 0;                    // bumped when a lane set's tables change
     hipStream_t cap = nullptr;                 // capture stream (nothing runs on it)
     hipEvent_t ev_ctl = nullptr;               // marks the lane states' copy to h_ctl
+    // stand-alone solve in caller arrays (hs_mg_solve_static): the finest grid's
+    // iterate is ext_u (node 0) and its right-hand side ext_b; no node data
+    bool solve_only = false;
+    double* ext_u = nullptr;
+    const double* ext_b = nullptr;
 };
 
 namespace {
@@ -508,10 +513,16 @@ void layout(hs_plan* P, char* base)
             lb.n[L] = n;
             lb.N[L] = N;
             lb.sig[L] = sig[n];
-            lb.U[L] = bump.arr<double>(M * N);
-            lb.FI[L] = bump.arr<double>(M * N);
-            lb.P[L] = bump.arr<double>((M - 1) * N);
-            lb.rhs[L] = bump.arr<double>(N);
+            if (P->solve_only) {
+                lb.U[L] = P->ext_u;
+                lb.FI[L] = lb.P[L] = nullptr;
+                lb.rhs[L] = const_cast<double*>(P->ext_b);   // read only: no kernel writes a finest rhs
+            } else {
+                lb.U[L] = bump.arr<double>(M * N);
+                lb.FI[L] = bump.arr<double>(M * N);
+                lb.P[L] = bump.arr<double>((M - 1) * N);
+                lb.rhs[L] = bump.arr<double>(N);
+            }
             lb.tmp[L] = bump.arr<double>(N);
             if (L == 1) {
                 lb.Ut = bump.arr<double>(M * N);
@@ -1188,6 +1199,40 @@ hs_status lanes_status(hs_plan* P)
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Device scratch of the allocation-free stand-alone solve (hs_mg_solve_static):
+// one array per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: its device address is taken once per
+// device with hipGetSymbolAddress and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+#define HS_STATIC_SCRATCH_BYTES (8u << 20)
+
+static __device__ __align__(256) unsigned char scratch[HS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+// Device address of this device's scratch (taken on the first call per device).
+hs_status scratch_address(void** out)
+{
+    int dev = 0;
+    HS_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return HS_EDEVICE;
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return HS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1405,6 +1450,56 @@ hs_status hs_mg_vcycle(hs_plan* P, int32_t level, const double* h_a, double* d_u
     }
     for (int b = 0; b < P->B; b++) P->h_ctl[b].status = 0;
     return (hs_status)worst;
+}
+
+hs_status hs_mg_solve_static(int32_t n, int32_t order, double a, const hs_mg_desc* mg, double* d_u,
+                             const double* d_b, void* stream)
+{
+    if (!mg || !d_u || !d_b || !(a >= 0.0) || !std::isfinite(a)) return HS_EINVAL;
+    if (mg->cycle_graphs != 0) return HS_EINVAL;   // graph capture would allocate
+    hs_problem pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.nu = 1.0;
+    pb.dt = 1.0;
+    pb.nlevels = 1;
+    pb.lev[0].n = n;
+    pb.lev[0].order = order;
+    pb.lev[0].nnodes = 2;
+    pb.mg = *mg;
+    pb.sweeps = 1;
+    pb.sdc_tol = 1.0;
+    pb.max_sweeps = 1;
+    pb.batch = 1;
+    pb.nslices = 1;
+    HS_CHECK(validate(&pb));
+    if (n > HS_STATIC_MAX_N) return HS_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    hs_plan P;
+    init_plan(&P, &pb);
+    P.solve_only = true;
+    P.ext_u = d_u;
+    P.ext_b = d_b;
+    layout(&P, nullptr);
+    if (P.bytes > HS_STATIC_SCRATCH_BYTES) return HS_ENOMEM;
+    void* base = nullptr;
+    HS_CHECK(scratch_address(&base));
+    HS_TRY(ensure_constants());
+    P.ws = (char*)base;
+    layout(&P, P.ws);
+    LaneCtl h_ctl;                                 // pageable host copy for the stopping checks
+    P.h_ctl = &h_ctl;
+    P.bound = true;
+    // every call re-initialises what it reads: tables, the lane state (all of
+    // its fields that a solve reads), the per-lane coefficient
+    HS_TRY(upload_set(&P, P.all, s));
+    HS_TRY(hsk::set_lane(P.ctl, 0, 1.0, 1.0, 0.0, 0.0, 0, 1, s));
+    HS_TRY(hsk::set_a_user(P.ctl, 0, a, s));
+    hs_status st = mg_solve(&P, P.all, 0, -1, 0, s, nullptr);
+    if (st == HS_OK) st = read_ctl(&P, s);
+    P.h_ctl = nullptr;
+    if (st != HS_OK) return st;
+    if (h_ctl.mg_state == 2) return h_ctl.status < 0 ? (hs_status)h_ctl.status : HS_ENOCONV;
+    return HS_OK;
 }
 
 hs_status hs_smooth(hs_plan* P, int32_t level, const double* h_a, double* d_u, const double* d_b,

@@ -94,6 +94,7 @@ def lib():
         "hs_heat_rhs": [_V, C.c_int32, _V, _V, _V, _V, _V],
         "hs_mg_vcycle": [_V, C.c_int32, _V, _V, _V, _V],
         "hs_smooth": [_V, C.c_int32, _V, _V, _V, _V, C.c_int32, _V],
+        "hs_mg_solve_static": [C.c_int32, C.c_int32, C.c_double, _V, _V, _V, _V],
         "hs_set_state": [_V, _V, _V],
         "hs_get_state": [_V, _V, _V],
         "hs_get_nodes": [_V, C.c_int32, _V, _V, _V, _V, _V],
@@ -146,6 +147,20 @@ def collocation(M: int):
     Q = np.zeros((M, M))
     check(lib().hs_collocation(M, tau.ctypes.data_as(_V), Q.ctypes.data_as(_V)), "hs_collocation")
     return tau, Q
+
+
+HS_STATIC_MAX_N = 63
+
+
+def mg_solve_static(u, b, a, n, order, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest=3, tol=1e-12,
+                    max_cycles=60, fixed_cycles=0, precision=HS_FP64, inner=(2, 2), stream=None,
+                    allow=()):
+    """hs_mg_solve_static: solve (I - a L_h) u = b on one n^3 grid in place on
+    the device tensor u, with no plan and no device allocation (the library's
+    static scratch holds everything else).  Returns the status."""
+    d = MgDesc(nu1, nu2, omega, n_coarsest, tol, max_cycles, fixed_cycles, precision, inner[0], inner[1], 1, 0)
+    s = lib().hs_mg_solve_static(n, order, a, C.byref(d), _ptr(u), _ptr(b), _stream(stream))
+    return check(s, "hs_mg_solve_static", allow=allow)
 
 
 @dataclass

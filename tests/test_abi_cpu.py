@@ -139,3 +139,20 @@ def test_product_path_has_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(heatst, "_lib", None)
     with pytest.raises(RuntimeError):
         heatst.Problem().workspace_bytes()
+
+
+def test_static_solve_rejects_before_launching():
+    """hs_mg_solve_static validates on the host: grids above HS_STATIC_MAX_N
+    get HS_ENOMEM and graph capture HS_EINVAL before any device call (the
+    pointers are never touched)."""
+    import ctypes as C
+    L = heatst.lib()
+    d = heatst.MgDesc(2, 1, 6.0 / 7.0, 3, 1e-12, 60, 0, heatst.HS_FP64, 2, 2, 1, 0)
+    fake = C.c_void_p(0x1000)
+    assert L.hs_mg_solve_static(127, 2, 0.01, C.byref(d), fake, fake, None) == heatst.HS_ENOMEM
+    assert L.hs_mg_solve_static(heatst.HS_STATIC_MAX_N + 2, 2, 0.01, C.byref(d), fake, fake,
+                                None) == heatst.HS_EINVAL   # 65 is not 2^k - 1
+    g = heatst.MgDesc(2, 1, 6.0 / 7.0, 3, 1e-12, 60, 0, heatst.HS_FP64, 2, 2, 1, 1)
+    assert L.hs_mg_solve_static(31, 2, 0.01, C.byref(g), fake, fake, None) == heatst.HS_EINVAL
+    assert L.hs_mg_solve_static(31, 2, -1.0, C.byref(d), fake, fake, None) == heatst.HS_EINVAL
+    assert L.hs_mg_solve_static(31, 2, 0.01, C.byref(d), None, fake, None) == heatst.HS_EINVAL
