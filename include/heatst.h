@@ -124,6 +124,12 @@ typedef struct {
     int32_t batch;           /* lanes */
     int32_t nslices;         /* 1, or = batch for PFASST time slices */
     const int32_t* h_lane_n; /* NULL, or per-lane fine n (uneven batches, nlevels = 1) */
+    int32_t pfasst_pred_sweeps; /* PFASST: coarse sweeps per slice of the serial coarse predictor
+                                   run before the first iteration (0 = none); see hs_pfasst_run */
+    int32_t lane_memory;     /* 0: every lane's fields live in the plan workspace; 1: each lane's
+                                fields live in device memory of its own, bound to the lane with
+                                hs_plan_bind_lane while it holds a problem (the serving core's
+                                plans); nslices must be 1 */
 } hs_problem;
 
 /* Per-lane statistics (hs_stats_read). */
@@ -137,6 +143,7 @@ typedef struct {
     int32_t failed_solves;
     double last_rho;         /* relative residual of the last solve */
     double last_sdc_res;     /* last collocation residual taken */
+    int64_t level_cycles[2]; /* total_cycles split by SDC level (fine, coarse) */
 } hs_lane_stats;
 
 typedef struct hs_plan hs_plan;
@@ -159,6 +166,20 @@ hs_status hs_plan_create(const hs_problem* pb, hs_plan** plan);
 hs_status hs_plan_bind(hs_plan* plan, void* d_ws, size_t bytes, void* stream);
 
 hs_status hs_plan_destroy(hs_plan* plan);
+
+/* Plans with lane_memory = 1.  hs_lane_bytes: the device bytes lane `lane`
+ * of a plan for *pb needs (fields, multigrid hierarchy).
+ * hs_plan_bind_lane lays the (inactive) lane out in caller-owned d_mem
+ * (256-byte aligned, at least hs_lane_bytes) -- synchronous;
+ * hs_plan_unbind_lane releases an inactive lane's memory back to the caller.
+ * A lane must be bound before hs_set_lane activates it.  Calls that work on
+ * every lane at once (hs_lap_apply, hs_heat_rhs, hs_mg_vcycle, hs_smooth,
+ * hs_set_state, hs_get_state, hs_get_nodes, hs_set_nodes, hs_solve_graph,
+ * hs_pfasst_run) return HS_EINVAL on such plans; the step-level calls run
+ * over the active lanes. */
+hs_status hs_lane_bytes(const hs_problem* pb, int32_t lane, size_t* bytes);
+hs_status hs_plan_bind_lane(hs_plan* plan, int32_t lane, void* d_mem, size_t bytes, void* stream);
+hs_status hs_plan_unbind_lane(hs_plan* plan, int32_t lane);
 
 /* Number of lanes and lane l's fine n (for sizing user arrays). */
 hs_status hs_plan_lanes(const hs_plan* plan, int32_t* lanes, int32_t* h_lane_n);
@@ -253,9 +274,63 @@ hs_status hs_end_step(hs_plan* plan, void* stream);
 hs_status hs_step(hs_plan* plan, void* stream);
 hs_status hs_solve(hs_plan* plan, void* stream);
 
-/* PFASST (nslices = batch = P, nlevels = 2): nsteps / P blocks of P slices,
- * `sweeps` iterations each. */
+/* PFASST (section 1.1; nslices = batch = P, nlevels = 2): nsteps / P blocks
+ * of P time slices.  Every slice starts from the block's initial value
+ * spread over its nodes.  With pfasst_pred_sweeps > 0 a coarse predictor
+ * runs first: the coarse level goes serially through the slices without
+ * the FAS correction (slice p starts from slice p-1's coarse end value,
+ * spread, and does pfasst_pred_sweeps coarse sweeps), then every slice
+ * interpolates its coarse correction to the fine level.  Each iteration:
+ * fine hand-off (slice p takes slice p-1's fine end value of the previous
+ * iteration), fine sweeps of all slices as one batch, FAS restriction,
+ * the coarse sweeps as a blocking pipeline p = 0..P-1, interpolation.
+ * sweeps > 0: that many iterations.  sweeps = 0: iterate until every
+ * slice's collocation residual, taken after the hand-off, is <= sdc_tol
+ * (the paper's PFASST threshold, section 2), at most max_sweeps
+ * iterations (then the lanes report HS_ENOCONV).  The lanes' total_sweeps
+ * count the iterations.  Synchronises once per iteration in the
+ * tolerance mode. */
 hs_status hs_pfasst_run(hs_plan* plan, void* stream);
+
+/* Launch timer, a measurement aid: with kind > 0 every launch of one kernel
+ * of the multigrid cycles on the finest grids of SDC level 0 is bracketed by
+ * HIP events that record the kernel's own start and end on the call's
+ * stream (hipExtLaunchKernelGGL), up to max_launches launches; kind 0 turns
+ * it off.  The events are created here (not inside timed work).
+ * hs_plan_timer_read synchronises on the last event and returns the number
+ * of timed launches and their summed duration in milliseconds, then starts
+ * a new count.  Kinds (add HS_TIMER_FP32 for the FP32 inner cycles of mixed
+ * precision solves): */
+#define HS_TIMER_PJAC 1       /* prolongation + first post-smoothing sweep */
+#define HS_TIMER_RESID_FW 2   /* residual + full-weighting restriction */
+#define HS_TIMER_SWEEP1 3     /* first pre-smoothing sweep (with the residual norm in FP64 solves) */
+#define HS_TIMER_SWEEP2 4     /* second pre-smoothing sweep (with the stopping test when folded in) */
+#define HS_TIMER_FP32 16
+hs_status hs_plan_timer(hs_plan* plan, int32_t kind, int32_t max_launches);
+hs_status hs_plan_timer_read(hs_plan* plan, int32_t* launches, double* total_ms);
+
+/* Launch-shape tuning.  The plane-marching kernels (sweeps, residual +
+ * restriction, prolongation + sweep) give each block `zb` consecutive z
+ * planes of a 64 x 8 tile; a grid's launch shape is chosen per grid size n,
+ * Laplacian order, precision (0 FP64, 1 FP32) and batch (how many grids of
+ * that size one launch covers).  Without an entry the built-in rule applies
+ * (the largest zb of 8, 4, 2, 1 that still gives 256 blocks per grid).  An
+ * entry matches the largest batch <= the launch's count, else the smallest
+ * batch.  Entries apply to plans created afterwards; a process-wide table
+ * guarded by a lock.
+ *   hs_tune_set:    add or replace one entry (zb 1..64, zb_rfw even 2..64);
+ *   hs_tune_clear:  remove every entry;
+ *   hs_tune_load:   read entries from a JSON file written by the autotuner
+ *                   (paper_1307_7867_amd/tune.py): an object whose "entries"
+ *                   array holds objects with integer fields n, order,
+ *                   precision, batch, zb, zb_rfw (other fields ignored);
+ *                   returns the number of entries read;
+ *   hs_tune_lookup: the zb / zb_rfw a plan created now would use. */
+hs_status hs_tune_set(int32_t n, int32_t order, int32_t precision, int32_t batch, int32_t zb, int32_t zb_rfw);
+hs_status hs_tune_clear(void);
+hs_status hs_tune_load(const char* json_path, int32_t* entries);
+hs_status hs_tune_lookup(int32_t n, int32_t order, int32_t precision, int32_t batch, int32_t* zb,
+                         int32_t* zb_rfw);
 
 /* Capture hs_step into a HIP graph and replay it for the remaining steps
  * (fixed sweep and cycle counts only). */
@@ -268,15 +343,22 @@ hs_status hs_stats_read(hs_plan* plan, hs_lane_stats* h_out, void* stream);
  * Serving: a request loop for many independent heat solves.
  *
  * Requests (grid n, nu, dt, t0, steps, initial field) are grouped by grid
- * size into classes.  Every class is one batched plan with `slots` lanes,
- * laid out in the caller's device pool when the server is created (the
- * classes together must fit both the pool and hbm_budget, else
- * HS_ENOMEM); a lane holds one request's hierarchy from admission to
- * completion.  Each class is driven by its own host thread on its own HIP
- * stream (default priority): before every time step it admits queued
- * requests into free lanes, then advances all of its active lanes by one
- * step in one batched launch sequence, then retires the lanes that are
- * done (copying their final field to the request's output).  New requests
+ * size into classes.  Every class is one batched plan with `slots` lanes
+ * whose shared workspace (lane states, tables, partials) sits at the front
+ * of the caller's device pool.  The rest of the pool is a heap: a request
+ * is admitted -- given a free lane of its class and its own fields and
+ * multigrid hierarchy carved from the heap -- while the bytes of all
+ * admitted requests stay within hbm_budget minus the shared workspace.
+ * Admission follows arrival order; the oldest request that a lane is free
+ * for but whose bytes do not fit reserves them, so the requests behind it
+ * may only use what is left (a large request is not starved by small ones,
+ * which still fill the room it cannot use).
+ * Each class is driven by its own host thread on its own HIP stream
+ * (default priority): at every time-step boundary it binds the memory of
+ * newly admitted requests to their lanes, advances all of its active lanes
+ * by one step in one batched launch sequence, then retires the lanes that
+ * are done (copying their final field to the request's output) and
+ * returns their memory, which admits waiting requests.  New requests
  * therefore join at the next step boundary and different classes overlap
  * on the device.  Every lane takes its own stopping decisions, so a
  * request's result does not depend on what else is in the batch.
@@ -292,11 +374,11 @@ typedef struct {
     double forcing_c;
     int32_t nclasses;
     int32_t class_n[HS_MAX_CLASSES];
-    int32_t class_slots[HS_MAX_CLASSES];
+    int32_t class_slots[HS_MAX_CLASSES];   /* lanes of the class's plan (most of its requests at once) */
 } hs_server_desc;
 
 typedef struct {
-    int32_t state;                /* 0 queued, 1 running, 2 done */
+    int32_t state;                /* 0 queued, 1 admitted / running, 2 done */
     int32_t status;               /* hs_status of the finished request */
     int32_t cls, lane;
     double t_submit, t_admit, t_done;   /* seconds since the server was created */
@@ -305,8 +387,14 @@ typedef struct {
 
 typedef struct hs_server hs_server;
 
-/* Device bytes the classes of *d need (pool size to pass to hs_server_create). */
-hs_status hs_server_pool_bytes(const hs_server_desc* d, size_t* bytes);
+/* Device bytes of the classes' shared workspaces, and that plus every lane
+ * of every class holding a request (the most the pool can usefully hold). */
+hs_status hs_server_pool_bytes(const hs_server_desc* d, size_t* shared_bytes, size_t* full_bytes);
+/* Heap bytes one request of grid n holds while admitted. */
+hs_status hs_server_request_bytes(const hs_server_desc* d, int32_t n, size_t* bytes);
+/* d_pool: caller-owned device memory (256-byte aligned).  HS_ENOMEM unless
+ * both pool_bytes and hbm_budget hold the shared workspaces plus one
+ * request of the largest class. */
 hs_status hs_server_create(const hs_server_desc* d, void* d_pool, size_t pool_bytes,
                            size_t hbm_budget, hs_server** server);
 /* Queue a request.  d_u0 (n^3 values) must stay valid until the request is
@@ -316,8 +404,11 @@ hs_status hs_server_submit(hs_server* s, int32_t n, double nu, double dt, double
                            const double* d_u0, double* d_out, uint64_t* ticket);
 /* HS_OK when the request is done (info filled), HS_PENDING otherwise. */
 hs_status hs_server_poll(hs_server* s, uint64_t ticket, hs_request_info* info);
+/* Heap bytes the admitted requests hold now, and the most they may hold. */
+hs_status hs_server_resident(hs_server* s, size_t* resident_bytes, size_t* budget_bytes);
 /* Block until every submitted request is done. */
 hs_status hs_server_drain(hs_server* s);
+/* Stop: running requests finish, queued ones are dropped. */
 hs_status hs_server_destroy(hs_server* s);
 
 #ifdef __cplusplus

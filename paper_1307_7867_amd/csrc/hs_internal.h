@@ -42,6 +42,7 @@ struct LaneCtl {
     long long total_cycles;
     int32_t total_solves, max_cycles, total_sweeps, sweeps_step;
     int32_t failed_solves, pad1;
+    long long level_cycles[2];   // cycles of the solves on SDC level 0 / 1
 };
 
 // One grid of one lane at one multigrid level.  The finest grid of an SDC
@@ -149,6 +150,12 @@ struct LibConst {
 // ---------------------------------------------------------------------------
 namespace hsk {
 
+// Start / stop events of one timed launch (hipExtLaunchKernelGGL records the
+// kernel's own start and end); both null = untimed.
+struct EvPair {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 struct MgArgs {
     int32_t L;         // SDC level whose coefficients apply
     int32_t m;         // substep (index into a[L][]); -1 = a_user
@@ -186,7 +193,8 @@ inline int src_code(int finest_t, int coarse_t, int skip_coarse = 0)
 template <typename T>
 hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                  int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
-                 double* partials, hipStream_t s, int src = 0, double tol = 0.0, int max_cycles = 0);
+                 double* partials, hipStream_t s, int src = 0, double tol = 0.0, int max_cycles = 0,
+                 EvPair ev = {});
 
 // Two weighted-Jacobi sweeps in one pass: dst = J(J(x)), x picked by
 // src_is_t, dst the other buffer.  norm: per-block maxima of the first
@@ -199,7 +207,7 @@ hipError_t jac2(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order
 // coarser grid's iterate (GridSeg::cu); the result goes to the other buffer.
 template <typename T>
 hipError_t pjac(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
-                hipStream_t s);
+                hipStream_t s, EvPair ev = {});
 
 // Copy the finest iterate from t back to u for the lanes whose grid moves
 // (GridSeg::moves) and whose solve ran an odd number of V-cycles (when every
@@ -211,7 +219,7 @@ hipError_t mg_fixup(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArg
 // GridSeg::cb in one pass; the table's chunks (zb) are even.
 template <typename T>
 hipError_t resid_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                    int src_is_t, hipStream_t s);
+                    int src_is_t, hipStream_t s, EvPair ev = {});
 template <typename T>
 hipError_t prolong(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, MgArgs a, int src_is_t,
                    int dst_is_t, hipStream_t s);
@@ -223,7 +231,7 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
 // rho = max|r| / max|b| (|b| taken at cycle 0); stop when rho <= tol, fail
 // when cycle == max_cycles or rho is not finite
 hipError_t mg_decide(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, const double* partials,
-                     int cycle, double tol, int max_cycles, hipStream_t s);
+                     int cycle, double tol, int max_cycles, int level, hipStream_t s);
 // max-norm residual of an FP64 solve into partials (tables without a fused
 // sweep); bit 0 of src_is_t: the iterate of grids with GridSeg::moves is in t
 hipError_t mg_norm(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
@@ -265,12 +273,16 @@ hipError_t fas_interp(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int 
 hipError_t begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int M1, hipStream_t s);
 hipError_t end_step(LaneCtl* ctl, int nlanes, hipStream_t s);
 hipError_t begin_solve(LaneCtl* ctl, int nlanes, hipStream_t s);
-hipError_t end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, hipStream_t s);
+hipError_t end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, int level, hipStream_t s);
 hipError_t begin_sweep(LaneCtl* ctl, int nlanes, hipStream_t s);
 hipError_t set_lane(LaneCtl* ctl, int lane, double nu, double dt, double t0, double forcing_c,
                     int nsteps, int active, hipStream_t s);
 hipError_t set_a_user(LaneCtl* ctl, int lane, double a, hipStream_t s);
 hipError_t copy(const double* src, double* dst, long long count, hipStream_t s);
+hipError_t fill(double* dst, long long count, double v, hipStream_t s);
+// lanes whose SDC state is "converged" go back to "iterate" (PFASST keeps
+// every slice iterating until all of them meet the tolerance)
+hipError_t sdc_reopen(LaneCtl* ctl, int nlanes, hipStream_t s);
 
 // kernel-level calls of the public ABI on lane-major packed user arrays
 hipError_t lap_apply(const SdcSeg* segs, int nseg, int nblk, int order, double alpha, double beta,

@@ -23,6 +23,8 @@
 // the coarsest grid) are this library's choice, the paper names none.
 #include "hs_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <map>
 #include <type_traits>
 #include <mutex>
@@ -231,11 +233,12 @@ struct LdInj {
 };
 
 // record the end of a multigrid solve (state 1 converged, 2 failed)
-__device__ __forceinline__ void finish_solve(LaneCtl& c, int cycle, int state)
+__device__ __forceinline__ void finish_solve(LaneCtl& c, int cycle, int state, int level)
 {
     c.mg_state = state;
     c.mg_cycle = cycle;
     c.total_cycles += cycle;
+    c.level_cycles[level & 1] += cycle;
     c.total_solves += 1;
     if (cycle > c.max_cycles) c.max_cycles = cycle;
     if (state == 2) c.failed_solves += 1;
@@ -732,7 +735,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_sweep(const GridSeg* __restrict__ 
                 if (cycle == 0) c.bnorm = bn;
                 c.mg_rho = rho;
                 if (state != 0) {
-                    finish_solve(c, cycle, state);
+                    finish_solve(c, cycle, state, A.L);
                     if (bad) c.status = -4;
                     else if (state == 2 && c.status == 0) c.status = -3;
                 }
@@ -2020,7 +2023,7 @@ __global__ void __launch_bounds__(HS_TAIL_THREADS) k_tail(const TailSeg* __restr
 __global__ void __launch_bounds__(HS_BLOCK) k_mg_decide(const GridSeg* __restrict__ segs, int nseg,
                                                         int nblk, const double* __restrict__ partials,
                                                         LaneCtl* __restrict__ ctl, int cycle,
-                                                        double tol, int max_cycles)
+                                                        double tol, int max_cycles, int level)
 {
     int si = blockIdx.x;
     const GridSeg sg = segs[si];
@@ -2040,12 +2043,12 @@ __global__ void __launch_bounds__(HS_BLOCK) k_mg_decide(const GridSeg* __restric
         double rho = r / scale;
         c.mg_rho = rho;
         if (rho != rho || r > 1.7e308) {
-            finish_solve(c, cycle, 2);
+            finish_solve(c, cycle, 2, level);
             c.status = -4;
         } else if (rho <= tol) {
-            finish_solve(c, cycle, 1);
+            finish_solve(c, cycle, 1, level);
         } else if (cycle >= max_cycles) {
-            finish_solve(c, cycle, 2);
+            finish_solve(c, cycle, 2, level);
             if (c.status == 0) c.status = -3;
         }
     }
@@ -2532,12 +2535,12 @@ __global__ void k_begin_solve(LaneCtl* ctl, int nlanes)
     c.mg_cycle = 0;
 }
 
-__global__ void k_end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles)
+__global__ void k_end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, int level)
 {
     int lane = blockIdx.x * blockDim.x + threadIdx.x;
     if (lane >= nlanes) return;
     LaneCtl& c = ctl[lane];
-    if (c.mg_state == 0) finish_solve(c, cycles, 1);
+    if (c.mg_state == 0) finish_solve(c, cycles, 1, level);
 }
 
 __global__ void k_begin_sweep(LaneCtl* ctl, int nlanes)
@@ -2560,6 +2563,7 @@ __global__ void k_set_lane(LaneCtl* ctl, int lane, double nu, double dt, double 
     c.bnorm = c.mg_rho = c.sdc_res = 0.0;
     c.total_cycles = 0; c.total_solves = 0; c.max_cycles = 0; c.total_sweeps = 0;
     c.sweeps_step = 0; c.failed_solves = 0; c.a_user = 0.0;
+    c.level_cycles[0] = c.level_cycles[1] = 0;
 }
 
 __global__ void k_set_a_user(LaneCtl* ctl, int lane, double a)
@@ -2567,6 +2571,22 @@ __global__ void k_set_a_user(LaneCtl* ctl, int lane, double a)
     ctl[lane].a_user = a;
     ctl[lane].mg_state = 0;
     ctl[lane].sdc_state = 0;
+}
+
+__global__ void k_fill(double* __restrict__ dst, long long count, double v)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) dst[i] = v;
+}
+
+// PFASST residual test: lanes that met the tolerance keep iterating while
+// another slice has not (state 1 -> 0); failed lanes stay failed.
+__global__ void k_sdc_reopen(LaneCtl* ctl, int nlanes)
+{
+    int lane = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= nlanes) return;
+    if (ctl[lane].sdc_state == 1) ctl[lane].sdc_state = 0;
 }
 
 __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long count)
@@ -2694,31 +2714,44 @@ hipError_t set_constants(const LibConst& lc)
         else hipLaunchKernelGGL(KERNEL4, GRID, BLOCK, SHMEM, s, __VA_ARGS__);               \
     } while (0)
 
+// As HS_ORDER_DISPATCH; with events in ev the launch records the kernel's
+// own start and end in them (for the launch timer).
+#define HS_ORDER_DISPATCH_EV(ev, order, KERNEL2, KERNEL4, GRID, BLOCK, SHMEM, ...)                          \
+    do {                                                                                                    \
+        if (!(ev).start) HS_ORDER_DISPATCH(order, KERNEL2, KERNEL4, GRID, BLOCK, SHMEM, __VA_ARGS__);       \
+        else if ((order) == 2)                                                                              \
+            hipExtLaunchKernelGGL(KERNEL2, GRID, BLOCK, SHMEM, s, (ev).start, (ev).stop, 0, __VA_ARGS__);   \
+        else hipExtLaunchKernelGGL(KERNEL4, GRID, BLOCK, SHMEM, s, (ev).start, (ev).stop, 0, __VA_ARGS__);  \
+    } while (0)
+
 template <typename T, int MODE, int FINEST, int NORM, int SRC = 0>
 static hipError_t sweep_launch(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order,
                                MgArgs a, int first_sweep, int src_is_t, int cycle, double* partials,
-                               hipStream_t s, double tol = 0.0, int max_cycles = 0)
+                               hipStream_t s, double tol = 0.0, int max_cycles = 0, EvPair ev = {})
 {
-    HS_ORDER_DISPATCH(order, (k_sweep<T, 2, MODE, FINEST, NORM, SRC>), (k_sweep<T, 4, MODE, FINEST, NORM, SRC>),
-                      g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a, first_sweep, src_is_t, partials,
-                      cycle, tol, max_cycles);
+    HS_ORDER_DISPATCH_EV(ev, order, (k_sweep<T, 2, MODE, FINEST, NORM, SRC>), (k_sweep<T, 4, MODE, FINEST, NORM, SRC>),
+                         g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a, first_sweep, src_is_t, partials,
+                         cycle, tol, max_cycles);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
                  int mode, int first_sweep, int src_is_t, int finest_only, int norm, int cycle,
-                 double* partials, hipStream_t s, int src, double tol, int max_cycles)
+                 double* partials, hipStream_t s, int src, double tol, int max_cycles, EvPair ev)
 {
     if (nblk <= 0) return hipSuccess;
     if (mode == 1) return sweep_launch<T, 1, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
     if (src == 1) return sweep_launch<T, 0, 0, 0, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
-    if (norm == 1) return sweep_launch<T, 0, 1, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s);
+    if (norm == 1)
+        return sweep_launch<T, 0, 1, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s, 0.0, 0, ev);
     if (norm == 2)
         return sweep_launch<T, 0, 1, 2>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s, tol,
-                                        max_cycles);
-    if (finest_only) return sweep_launch<T, 0, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
-    return sweep_launch<T, 0, 0, 0>(ctl, segs, nseg, nblk, order, a, first_sweep, src_is_t, 0, partials, s);
+                                        max_cycles, ev);
+    if (finest_only)
+        return sweep_launch<T, 0, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s, 0.0, 0, ev);
+    return sweep_launch<T, 0, 0, 0>(ctl, segs, nseg, nblk, order, a, first_sweep, src_is_t, 0, partials, s, 0.0, 0,
+                                    ev);
 }
 
 template <typename T>
@@ -2737,21 +2770,21 @@ hipError_t jac2(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order
 
 template <typename T>
 hipError_t resid_fw(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a,
-                    int src_is_t, hipStream_t s)
+                    int src_is_t, hipStream_t s, EvPair ev)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_resid_fw<T, 2>), (k_resid_fw<T, 4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
-                      a, src_is_t);
+    HS_ORDER_DISPATCH_EV(ev, order, (k_resid_fw<T, 2>), (k_resid_fw<T, 4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl,
+                         a, src_is_t);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t pjac(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int order, MgArgs a, int src_is_t,
-                hipStream_t s)
+                hipStream_t s, EvPair ev)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_pjac<T, 2>), (k_pjac<T, 4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a,
-                      src_is_t);
+    HS_ORDER_DISPATCH_EV(ev, order, (k_pjac<T, 2>), (k_pjac<T, 4>), g1(nblk), BLK, 0, segs, nseg, nblk, ctl, a,
+                         src_is_t);
     return hipGetLastError();
 }
 
@@ -2801,25 +2834,25 @@ hipError_t tail(LaneCtl* ctl, const TailSeg* segs, int nseg, int order, MgArgs a
     return hipGetLastError();
 }
 
-template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int, double, int);
-template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int, double, int);
+template hipError_t sweep<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int, double, int, EvPair);
+template hipError_t sweep<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, int, int, int, double*, hipStream_t, int, double, int, EvPair);
 template hipError_t jac2<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
 template hipError_t jac2<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, int, int, double*, hipStream_t);
-template hipError_t pjac<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
-template hipError_t pjac<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
-template hipError_t resid_fw<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
-template hipError_t resid_fw<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t);
+template hipError_t pjac<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t, EvPair);
+template hipError_t pjac<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t, EvPair);
+template hipError_t resid_fw<double>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t, EvPair);
+template hipError_t resid_fw<float>(LaneCtl*, const GridSeg*, int, int, int, MgArgs, int, hipStream_t, EvPair);
 template hipError_t prolong<double>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);
 template hipError_t prolong<float>(LaneCtl*, const GridSeg*, int, int, MgArgs, int, int, hipStream_t);
 template hipError_t tail<double>(LaneCtl*, const TailSeg*, int, int, MgArgs, int, int, size_t, hipStream_t);
 template hipError_t tail<float>(LaneCtl*, const TailSeg*, int, int, MgArgs, int, int, size_t, hipStream_t);
 
 hipError_t mg_decide(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, const double* partials,
-                     int cycle, double tol, int max_cycles, hipStream_t s)
+                     int cycle, double tol, int max_cycles, int level, hipStream_t s)
 {
     if (nseg <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mg_decide, dim3((unsigned)nseg), BLK, 0, s, segs, nseg, nblk, partials, ctl,
-                       cycle, tol, max_cycles);
+                       cycle, tol, max_cycles, level);
     return hipGetLastError();
 }
 
@@ -2947,9 +2980,9 @@ hipError_t begin_solve(LaneCtl* ctl, int nlanes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, hipStream_t s)
+hipError_t end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, int level, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_end_solve_fixed, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes, cycles);
+    hipLaunchKernelGGL(k_end_solve_fixed, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes, cycles, level);
     return hipGetLastError();
 }
 
@@ -2979,6 +3012,21 @@ hipError_t copy(const double* src, double* dst, long long count, hipStream_t s)
     long long blocks = (count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count);
+    return hipGetLastError();
+}
+
+hipError_t fill(double* dst, long long count, double v, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    long long blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, dst, count, v);
+    return hipGetLastError();
+}
+
+hipError_t sdc_reopen(LaneCtl* ctl, int nlanes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sdc_reopen, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes);
     return hipGetLastError();
 }
 

@@ -6,11 +6,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <type_traits>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
 #include <set>
+#include <string>
 #include <vector>
 
 namespace {
@@ -270,6 +273,13 @@ struct hs_plan {
     bool solve_only = false;
     double* ext_u = nullptr;
     const double* ext_b = nullptr;
+    // sine tables per grid size; lanes' own memory (pb.lane_memory)
+    std::map<int, double*> sig;
+    std::vector<void*> lane_base;
+    // launch timer (hs_plan_timer): start / stop event pairs of the timed kind
+    int timer_kind = 0;
+    std::vector<hipEvent_t> timer_ev;
+    int timer_used = 0;
 };
 
 namespace {
@@ -310,6 +320,43 @@ void finish_table(Table<S>& t, Bump& bump)
     t.d = t.h.empty() ? nullptr : bump.arr<S>(t.h.size());
 }
 
+// ---------------------------------------------------------------------------
+// Launch-shape table (hs_tune_*): z planes per block of the plane-marching
+// kernels for the grids of size n, Laplacian order and precision when one
+// launch covers `batch` grids of that size.  Filled by the autotuner;
+// without an entry the built-in rule (hsk::choose_zb) applies.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    int n, order, prec, batch, zb, zb_rfw;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+// The entry of the largest batch <= count, else the one of the smallest batch.
+void tuned_zb(int n, int order, int prec, int count, int* zb, int* zb_rfw)
+{
+    *zb = hsk::choose_zb(n);
+    *zb_rfw = hsk::choose_zb_even(n);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneEntry* best = nullptr;
+    for (const TuneEntry& e : g_tune) {
+        if (e.n != n || e.order != order || e.prec != prec) continue;
+        if (!best) best = &e;
+        else if (e.batch <= count && (best->batch > count || e.batch > best->batch)) best = &e;
+        else if (e.batch > count && best->batch > count && e.batch < best->batch) best = &e;
+    }
+    if (best) {
+        *zb = best->zb;
+        *zb_rfw = best->zb_rfw;
+    }
+}
+
+bool valid_tune(int n, int order, int prec, int batch, int zb, int zb_rfw)
+{
+    return n >= 1 && n <= 511 && ((n + 1) & n) == 0 && (order == 2 || order == 4) && (prec == 0 || prec == 1) &&
+           batch >= 1 && zb >= 1 && zb <= 64 && zb_rfw >= 2 && zb_rfw <= 64 && (zb_rfw & 1) == 0;
+}
+
 // Build the multigrid tables of SDC level L for the lanes of `ls`.
 template <typename T>
 void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
@@ -329,8 +376,15 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             *u = lb.gu[L][l]; *t = lb.gt[L][l]; *b = lb.gb[L][l];
         }
     };
+    const int prec = fp32 ? 1 : 0;
     for (int s = 0; s < Dmax; s++) {
         int bj = 0, bp = 0, bf2 = 0;
+        std::map<int, int> count;   // grids of each size in this stage
+        for (int b : ls.lanes) {
+            const LaneBufs& lb = P->lanes[b];
+            int l = s - (Dmax - tail_start(lb.grids[L]));
+            if (l >= 0) count[lb.grids[L][l]]++;
+        }
         for (int b : ls.lanes) {
             const LaneBufs& lb = P->lanes[b];
             int Db = tail_start(lb.grids[L]);
@@ -348,11 +402,13 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
             grid_ptrs(lb, l + 1, &cu, &ct, &cb);
             g.cu = cu;
             g.cb = cb;
-            g.zb = hsk::choose_zb(g.n);
+            int zb, zb_rfw;
+            tuned_zb(g.n, P->order[L], prec, count[g.n], &zb, &zb_rfw);
+            g.zb = zb;
             g.blk_begin = bj; bj += hsk::grid_blocks(g.n, g.zb); S.jac[s].h.push_back(g);
             g.zb = hsk::choose_zb_two(g.n);   // also the two-sweep kernel's table
             g.blk_begin = bp; bp += hsk::grid_blocks(g.n, g.zb); S.pro[s].h.push_back(g);
-            g.zb = hsk::choose_zb_even(g.n);
+            g.zb = zb_rfw;
             g.blk_begin = bf2; bf2 += hsk::grid_blocks(g.n, g.zb); S.rfw[s].h.push_back(g);
         }
         S.jac[s].nblk = bj;
@@ -368,6 +424,8 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         S.rfw[s].nblk = bf2;
     }
     int bf = 0;
+    std::map<int, int> fcount;   // finest grids of each size
+    for (int b : ls.lanes) fcount[P->lanes[b].grids[L][0]]++;
     for (int b : ls.lanes) {
         const LaneBufs& lb = P->lanes[b];
         const std::vector<int>& g = lb.grids[L];
@@ -394,7 +452,8 @@ void build_mg(hs_plan* P, LaneSet& ls, int L, bool fp32, MgSet& S)
         f.nc = g.size() > 1 ? g[1] : 0;
         f.coarse = fp32 ? 1 : 0;
         f.node_stride = fp32 ? 0 : lb.N[L];
-        f.zb = hsk::choose_zb(f.n);
+        int zb_rfw_unused;
+        tuned_zb(f.n, P->order[L], prec, fcount[f.n], &f.zb, &zb_rfw_unused);
         f.moves = (Db > 0 && !fp32) ? 1 : 0;
         S.moves |= f.moves;
         grid_ptrs(lb, 0, &f.u, &f.t, &f.b);
@@ -491,60 +550,89 @@ void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
 }
 
 // Lay out the whole workspace.  With base == nullptr only sizes are taken.
+// One lane's fields (node data, right-hand side, ping-pong buffer, the
+// multigrid hierarchy in FP64 and, for mixed precision, FP32) from `bump`.
+void lay_lane(hs_plan* P, int b, Bump& bump)
+{
+    LaneBufs& lb = P->lanes[b];
+    lb = LaneBufs();
+    const hs_mg_desc& mg = P->pb.mg;
+    for (int L = 0; L < P->nlev; L++) {
+        int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
+        long long N = cube(n);
+        int M = P->M[L];
+        lb.n[L] = n;
+        lb.N[L] = N;
+        lb.sig[L] = P->sig[n];
+        if (P->solve_only) {
+            lb.U[L] = P->ext_u;
+            lb.FI[L] = lb.P[L] = nullptr;
+            lb.rhs[L] = const_cast<double*>(P->ext_b);   // read only: no kernel writes a finest rhs
+        } else {
+            lb.U[L] = bump.arr<double>(M * N);
+            lb.FI[L] = bump.arr<double>(M * N);
+            lb.P[L] = bump.arr<double>((M - 1) * N);
+            lb.rhs[L] = bump.arr<double>(N);
+        }
+        lb.tmp[L] = bump.arr<double>(N);
+        if (L == 1) {
+            lb.Ut = bump.arr<double>(M * N);
+            lb.tau = bump.arr<double>(M * N);
+        }
+        lb.grids[L] = mg_grids(n, mg.n_coarsest);
+        size_t G = lb.grids[L].size();
+        lb.gu[L].assign(G, nullptr); lb.gt[L].assign(G, nullptr); lb.gb[L].assign(G, nullptr);
+        lb.fu[L].assign(G, nullptr); lb.ft[L].assign(G, nullptr); lb.fb[L].assign(G, nullptr);
+        for (size_t l = 0; l < G; l++) {
+            long long Ng = cube(lb.grids[L][l]);
+            if (l > 0) {
+                lb.gu[L][l] = bump.arr<double>(Ng);
+                lb.gt[L][l] = bump.arr<double>(Ng);
+                lb.gb[L][l] = bump.arr<double>(Ng);
+            }
+            if (P->mixed) {
+                lb.fu[L][l] = bump.arr<float>(Ng);
+                lb.ft[L][l] = bump.arr<float>(Ng);
+                lb.fb[L][l] = bump.arr<float>(Ng);
+            }
+        }
+    }
+}
+
+// Bytes of lane b's fields when each lane lives in memory of its own.
+size_t lane_bytes_of(hs_plan* P, int b)
+{
+    LaneBufs keep = P->lanes[b];
+    Bump sizing(nullptr);
+    lay_lane(P, b, sizing);
+    P->lanes[b] = keep;
+    return (sizing.off + 255) & ~(size_t)255;
+}
+
+// Lay out the whole workspace.  With base == nullptr only sizes are taken.
+// Plans with lane memory of their own (pb.lane_memory) keep every lane's
+// fields out of the workspace: a bound lane's come from its memory
+// (hs_plan_bind_lane), an unbound lane's pointers are placeholders that no
+// launch reads (only active lanes, which must be bound, are launched over).
 void layout(hs_plan* P, char* base)
 {
     Bump bump(base);
     P->ctl = bump.arr<LaneCtl>(P->B);
     // sine tables, one per distinct n
-    std::map<int, double*> sig;
+    P->sig.clear();
     for (int b = 0; b < P->B; b++)
         for (int L = 0; L < P->nlev; L++) {
             int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
-            if (!sig.count(n)) sig[n] = bump.arr<double>(n);
+            if (!P->sig.count(n)) P->sig[n] = bump.arr<double>(n);
         }
     P->lanes.assign(P->B, LaneBufs());
-    const hs_mg_desc& mg = P->pb.mg;
+    if (P->lane_base.size() != (size_t)P->B) P->lane_base.assign(P->B, nullptr);
     for (int b = 0; b < P->B; b++) {
-        LaneBufs& lb = P->lanes[b];
-        for (int L = 0; L < P->nlev; L++) {
-            int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
-            long long N = cube(n);
-            int M = P->M[L];
-            lb.n[L] = n;
-            lb.N[L] = N;
-            lb.sig[L] = sig[n];
-            if (P->solve_only) {
-                lb.U[L] = P->ext_u;
-                lb.FI[L] = lb.P[L] = nullptr;
-                lb.rhs[L] = const_cast<double*>(P->ext_b);   // read only: no kernel writes a finest rhs
-            } else {
-                lb.U[L] = bump.arr<double>(M * N);
-                lb.FI[L] = bump.arr<double>(M * N);
-                lb.P[L] = bump.arr<double>((M - 1) * N);
-                lb.rhs[L] = bump.arr<double>(N);
-            }
-            lb.tmp[L] = bump.arr<double>(N);
-            if (L == 1) {
-                lb.Ut = bump.arr<double>(M * N);
-                lb.tau = bump.arr<double>(M * N);
-            }
-            lb.grids[L] = mg_grids(n, mg.n_coarsest);
-            size_t G = lb.grids[L].size();
-            lb.gu[L].assign(G, nullptr); lb.gt[L].assign(G, nullptr); lb.gb[L].assign(G, nullptr);
-            lb.fu[L].assign(G, nullptr); lb.ft[L].assign(G, nullptr); lb.fb[L].assign(G, nullptr);
-            for (size_t l = 0; l < G; l++) {
-                long long Ng = cube(lb.grids[L][l]);
-                if (l > 0) {
-                    lb.gu[L][l] = bump.arr<double>(Ng);
-                    lb.gt[L][l] = bump.arr<double>(Ng);
-                    lb.gb[L][l] = bump.arr<double>(Ng);
-                }
-                if (P->mixed) {
-                    lb.fu[L][l] = bump.arr<float>(Ng);
-                    lb.ft[L][l] = bump.arr<float>(Ng);
-                    lb.fb[L][l] = bump.arr<float>(Ng);
-                }
-            }
+        if (!P->pb.lane_memory) {
+            lay_lane(P, b, bump);
+        } else {
+            Bump own((char*)P->lane_base[b]);
+            lay_lane(P, b, own);
         }
     }
     for (int L = 0; L < P->nlev; L++) {
@@ -694,9 +782,14 @@ hs_status validate(const hs_problem* pb)
     if (pb->sweeps < 0 || pb->max_sweeps < 0) return HS_EINVAL;
     if (pb->sweeps == 0 && !(pb->sdc_tol > 0.0)) return HS_EINVAL;
     if (pb->nslices < 1) return HS_EINVAL;
+    if (pb->pfasst_pred_sweeps < 0 || pb->pfasst_pred_sweeps > 64) return HS_EINVAL;
+    if (pb->lane_memory != 0 && pb->lane_memory != 1) return HS_EINVAL;
+    if (pb->lane_memory && pb->nslices != 1) return HS_EINVAL;
     if (pb->nslices > 1) {
-        if (pb->nslices != pb->batch || pb->nlevels != 2 || pb->sweeps <= 0) return HS_EINVAL;
+        if (pb->nslices != pb->batch || pb->nlevels != 2) return HS_EINVAL;
         if (pb->nsteps % pb->nslices != 0) return HS_EINVAL;
+    } else if (pb->pfasst_pred_sweeps != 0) {
+        return HS_EINVAL;
     }
     return HS_OK;
 }
@@ -731,6 +824,21 @@ bool all_sdc_done(hs_plan* P, const LaneSet& ls)
     for (int b : ls.lanes)
         if (P->h_ctl[b].sdc_state == 0) return false;
     return true;
+}
+
+// Events for a launch of timer kind `kind` (HS_TIMER_*) on the finest grids of
+// SDC level L in precision T; empty unless the plan times that kind on level
+// 0 and has events left.
+template <typename T>
+hsk::EvPair timer_events(hs_plan* P, int kind, int L)
+{
+    hsk::EvPair e;
+    const int want = kind | (std::is_same<T, float>::value ? HS_TIMER_FP32 : 0);
+    if (P->timer_kind != want || L != 0 || 2 * (P->timer_used + 1) > (int)P->timer_ev.size()) return e;
+    e.start = P->timer_ev[2 * P->timer_used];
+    e.stop = P->timer_ev[2 * P->timer_used + 1];
+    P->timer_used++;
+    return e;
 }
 
 // One V(nu1, nu2) cycle over the grids above the tail (section 1.2).  Each
@@ -776,9 +884,12 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
                 cf ^= 1;
                 k0 = 2;
             }
-            for (int k = k0; k < nu1; k++, cf ^= 1)
+            for (int k = k0; k < nu1; k++, cf ^= 1) {
+                hsk::EvPair ev;
+                if (st == 0 && k < 2) ev = timer_events<T>(P, k == 0 ? HS_TIMER_SWEEP1 : HS_TIMER_SWEEP2, A.L);
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 1, 0, 0,
-                                     P->partials, s));
+                                     P->partials, s, 0, 0.0, 0, ev));
+            }
         } else if (nu1 >= 2) {
             // finest grids' first sweep alone, then the correction grids' second
             // sweep from their zero-guess first one, next to the finest grids' second
@@ -787,8 +898,10 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
                                      P->partials, s));
                 cf ^= 1;
             }
+            hsk::EvPair ev;
+            if (st == 0 && !hasF && S.uniform) ev = timer_events<T>(P, HS_TIMER_SWEEP2, A.L);
             HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 0, 0, 0,
-                                 P->partials, s, 1));
+                                 P->partials, s, 1, 0.0, 0, ev));
             cf ^= 1; cc ^= 1;
             for (int k = 2; k < nu1; k++, cf ^= 1, cc ^= 1)
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 0, 0, 0,
@@ -802,7 +915,9 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
         locc[st] = cc;
         // residual restricted by full weighting in one pass
         const Table<GridSeg>& RF = S.rfw[st];
-        HS_TRY(hsk::resid_fw<T>(P->ctl, RF.d, RF.nseg(), RF.nblk, order, A, code(), s));
+        hsk::EvPair ev;
+        if (st == 0 && S.uniform) ev = timer_events<T>(P, HS_TIMER_RESID_FW, A.L);
+        HS_TRY(hsk::resid_fw<T>(P->ctl, RF.d, RF.nseg(), RF.nblk, order, A, code(), s, ev));
     }
     HS_TRY(hsk::tail<T>(P->ctl, S.tail.d, S.tail.nseg(), order, A, nu1, nu2, S.tail_lds, s));
     for (int st = S.D - 1; st >= 0; st--) {
@@ -810,7 +925,9 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
         int cf = locf[st], cc = locc[st];
         auto code = [&]() { return hsk::src_code(cf, cc); };
         if (pj) {
-            HS_TRY(hsk::pjac<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, code(), s));
+            hsk::EvPair ev;
+            if (st == 0 && S.uniform) ev = timer_events<T>(P, HS_TIMER_PJAC, A.L);
+            HS_TRY(hsk::pjac<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, code(), s, ev));
             cf ^= 1; cc ^= 1;
             for (int k = 1; k < nu2; k++, cf ^= 1, cc ^= 1)
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), J.finest, 0, 0,
@@ -936,40 +1053,48 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         if (mg.fixed_cycles > 0) {
             for (int c = 0; c < mg.fixed_cycles; c++)
                 HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, 0, 0, &par, s));
-            HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, s));
+            HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, L, s));
             return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
         }
         const bool two = S.two && mg.nu1 >= 2;
         // the second sweep takes the stopping test from the norm sweep's
         // maxima (no decision launch) while a lane's maxima are few enough
         // for every block to reduce them
-        const bool fold = S.fused_norm && !two && mg.nu1 >= 2 && S.jac[0].max_seg_blocks <= 1024;
+        // (and while the launch is one wave of blocks: in a larger one every
+        // block's extra reduction adds to each wave, measured 213 against
+        // 162 us for the plain sweep on 16 lanes of 127^3, more than a
+        // separate decision launch costs)
+        const bool fold = S.fused_norm && !two && mg.nu1 >= 2 && S.jac[0].max_seg_blocks <= 1024 &&
+                          S.jac[0].nblk <= 1024;
         // residual norm and stopping test before cycle c; the norm is fused
         // with cycle c's first sweep when possible
         auto head = [&](int c, int pc, hipStream_t st) -> hs_status {
             if (fold) {
                 const Table<GridSeg>& J = S.jac[0];
                 HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(pc, 0), 1,
-                                          1, c, P->partials, st));
+                                          1, c, P->partials, st, 0, 0.0, 0,
+                                          timer_events<double>(P, HS_TIMER_SWEEP1, L)));
                 HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, hsk::src_code(pc ^ 1, 0),
-                                          1, 2, c, P->partials, st, 0, mg.tol, mg.max_cycles));
+                                          1, 2, c, P->partials, st, 0, mg.tol, mg.max_cycles,
+                                          timer_events<double>(P, HS_TIMER_SWEEP2, L)));
             } else if (S.fused_norm && two) {
                 const Table<GridSeg>& J2 = S.pro[0];
                 HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, hsk::src_code(pc, 0), 1, c,
                                          P->partials, st));
                 HS_TRY(hsk::mg_decide(P->ctl, J2.d, J2.nseg(), J2.nblk, P->partials, c, mg.tol,
-                                      mg.max_cycles, st));
+                                      mg.max_cycles, L, st));
             } else if (S.fused_norm) {
                 const Table<GridSeg>& J = S.jac[0];
                 HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(pc, 0), 1,
-                                          1, c, P->partials, st));
+                                          1, c, P->partials, st, 0, 0.0, 0,
+                                          timer_events<double>(P, HS_TIMER_SWEEP1, L)));
                 HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, P->partials, c, mg.tol,
-                                      mg.max_cycles, st));
+                                      mg.max_cycles, L, st));
             } else {
                 HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, c,
                                     P->partials, pc, st));
                 HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, P->partials, c,
-                                      mg.tol, mg.max_cycles, st));
+                                      mg.tol, mg.max_cycles, L, st));
             }
             return HS_OK;
         };
@@ -1034,7 +1159,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                              it, P->partials, s));
         if (!fixed) {
             HS_TRY(hsk::mg_decide(P->ctl, S64.fine.d, S64.fine.nseg(), S64.fine.nblk, P->partials, it,
-                                  mg.tol, limit, s));
+                                  mg.tol, limit, L, s));
             if (it >= next_check || it >= limit) {
                 HS_CHECK(read_ctl(P, s));
                 if (synced) *synced = true;
@@ -1051,7 +1176,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, 0, 0, &par32, s));
         HS_TRY(hsk::ir_update(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, A, s));
     }
-    if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, s));
+    if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, L, s));
     return HS_OK;
 }
 
@@ -1059,14 +1184,17 @@ enum { SWEEP_RAN = 0, SWEEP_DONE = 1 };
 
 // One SDC sweep of level L over ls (eq. (7)).  With_resid: take the
 // collocation residual first and stop the lanes that meet sdc_tol.
+// prep_done: the sweep-constant parts were formed by the caller's residual
+// pass (and with_resid is false).
 hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hipStream_t s,
-                int* outcome)
+                int* outcome, bool prep_done = false)
 {
     const Table<SdcSeg>& T = ls.sdc[L];
     const Table<GridSeg>& F = ls.mg64[L].fine;   // z-marching blocks over the same lanes
     int M = P->M[L];
     *outcome = SWEEP_RAN;
-    HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, 1, P->partials, s));
+    if (!prep_done)
+        HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, 1, P->partials, s));
     if (with_resid) {
         HS_TRY(hsk::sdc_decide(P->ctl, T.d, T.nseg(), T.nblk, P->partials, P->pb.sdc_tol,
                                P->pb.max_sweeps, s));
@@ -1334,7 +1462,7 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
         HS_TRY(hipMemcpyAsync((void*)kv.first, keep.back().data(), n * sizeof(double),
                               hipMemcpyHostToDevice, s));
     }
-    HS_TRY(upload_set(P, P->all, s));
+    if (!P->pb.lane_memory) HS_TRY(upload_set(P, P->all, s));   // else the lanes' pointers come later
     for (auto& ls : P->single) HS_TRY(upload_set(P, ls, s));
     HS_TRY(upload(P->hf_dst, s));
     HS_TRY(upload(P->hf_src, s));
@@ -1347,10 +1475,56 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
             t0 = P->pb.t0 + b * P->pb.dt;
             nsteps = 1;
         }
-        HS_TRY(hsk::set_lane(P->ctl, b, P->pb.nu, P->pb.dt, t0, P->pb.forcing_c, (int)nsteps, 1, s));
+        const int active = P->pb.lane_memory ? 0 : 1;   // lanes of their own memory wait for it
+        HS_TRY(hsk::set_lane(P->ctl, b, P->pb.nu, P->pb.dt, t0, P->pb.forcing_c, (int)nsteps, active, s));
+        P->active[b] = active;
     }
+    P->run_dirty = true;
     HS_TRY(hipStreamSynchronize(s));
     P->bound = true;
+    return HS_OK;
+}
+
+hs_status hs_lane_bytes(const hs_problem* pb, int32_t lane, size_t* bytes)
+{
+    HS_CHECK(validate(pb));
+    if (!bytes || lane < 0 || lane >= pb->batch) return HS_EINVAL;
+    hs_plan P;
+    init_plan(&P, pb);
+    P.sig.clear();
+    for (int L = 0; L < P.nlev; L++) {
+        int n = L == 0 ? P.lane_n[lane] : (P.lane_n[lane] - 1) / 2;
+        P.sig[n] = nullptr;
+    }
+    P.lanes.assign(P.B, LaneBufs());
+    *bytes = lane_bytes_of(&P, lane);
+    return HS_OK;
+}
+
+hs_status hs_plan_bind_lane(hs_plan* P, int32_t lane, void* d_mem, size_t bytes, void* stream)
+{
+    HS_CHECK(check_bound(P));
+    if (!P->pb.lane_memory || lane < 0 || lane >= P->B || !d_mem || ((uintptr_t)d_mem & 255)) return HS_EINVAL;
+    if (P->active[lane]) return HS_ESTATE;
+    if (bytes < lane_bytes_of(P, lane)) return HS_ENOMEM;
+    // the lane's sine tables stay where the workspace put them
+    P->lane_base[lane] = d_mem;
+    Bump own((char*)d_mem);
+    lay_lane(P, lane, own);
+    P->run_dirty = true;
+    (void)stream;
+    return HS_OK;
+}
+
+hs_status hs_plan_unbind_lane(hs_plan* P, int32_t lane)
+{
+    HS_CHECK(check_bound(P));
+    if (!P->pb.lane_memory || lane < 0 || lane >= P->B) return HS_EINVAL;
+    if (P->active[lane]) return HS_ESTATE;
+    P->lane_base[lane] = nullptr;
+    Bump none(nullptr);
+    lay_lane(P, lane, none);
+    P->run_dirty = true;
     return HS_OK;
 }
 
@@ -1363,6 +1537,7 @@ hs_status hs_plan_destroy(hs_plan* P)
     if (P->cap) (void)hipStreamDestroy(P->cap);
     if (P->h_ctl) (void)hipHostFree(P->h_ctl);
     if (P->ev_ctl) (void)hipEventDestroy(P->ev_ctl);
+    for (hipEvent_t e : P->timer_ev) (void)hipEventDestroy(e);
     delete P;
     return HS_OK;
 }
@@ -1382,6 +1557,7 @@ hs_status hs_set_lane(hs_plan* P, int32_t lane, double nu, double dt, double t0,
     HS_CHECK(check_bound(P));
     if (lane < 0 || lane >= P->B || !(nu > 0) || !(dt > 0) || nsteps < 0 || !std::isfinite(t0))
         return HS_EINVAL;
+    if (active && P->pb.lane_memory && !P->lane_base[lane]) return HS_ESTATE;   // no memory bound yet
     HS_TRY(hsk::set_lane(P->ctl, lane, nu, dt, t0, P->pb.forcing_c, nsteps, active ? 1 : 0,
                          (hipStream_t)stream));
     if (P->active[lane] != (active ? 1 : 0)) {
@@ -1395,6 +1571,7 @@ hs_status hs_lap_apply(hs_plan* P, int32_t level, double alpha, double beta, con
                        double* d_y, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || !d_u || !d_y) return HS_EINVAL;
     const Table<SdcSeg>& T = P->all.sdc[level];
     HS_TRY(hsk::lap_apply(T.d, T.nseg(), T.nblk, P->order[level], alpha, beta, d_u, d_y,
@@ -1406,6 +1583,7 @@ hs_status hs_heat_rhs(hs_plan* P, int32_t level, const double* d_u, const double
                       double* d_fe, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || (d_fi && !d_u) || (d_fe && !h_t)) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     std::vector<double> t(P->B, 0.0);
@@ -1423,6 +1601,7 @@ hs_status hs_mg_vcycle(hs_plan* P, int32_t level, const double* h_a, double* d_u
                        void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || !h_a || !d_u || !d_b) return HS_EINVAL;
     for (int b = 0; b < P->B; b++)
         if (!(h_a[b] >= 0.0) || !std::isfinite(h_a[b])) return HS_EINVAL;
@@ -1506,6 +1685,7 @@ hs_status hs_smooth(hs_plan* P, int32_t level, const double* h_a, double* d_u, c
                     double* d_tmp, int32_t nsweeps, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || !h_a || !d_u || !d_b || !d_tmp || nsweeps < 0)
         return HS_EINVAL;
     for (int b = 0; b < P->B; b++)
@@ -1553,6 +1733,7 @@ hs_status hs_smooth(hs_plan* P, int32_t level, const double* h_a, double* d_u, c
 hs_status hs_set_state(hs_plan* P, const double* d_u0, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (!d_u0) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     int M = P->M[0];
@@ -1576,6 +1757,7 @@ hs_status hs_set_lane_state(hs_plan* P, int32_t lane, const double* d_u0, void* 
 {
     HS_CHECK(check_bound(P));
     if (lane < 0 || lane >= P->B || !d_u0 || P->pb.nslices > 1) return HS_EINVAL;
+    if (P->pb.lane_memory && !P->lane_base[lane]) return HS_ESTATE;
     const LaneBufs& lb = P->lanes[lane];
     int M = P->M[0];
     HS_TRY(hipMemcpyAsync(lb.U[0] + (M - 1) * lb.N[0], d_u0, lb.N[0] * sizeof(double),
@@ -1587,6 +1769,7 @@ hs_status hs_get_lane_state(hs_plan* P, int32_t lane, double* d_u, void* stream)
 {
     HS_CHECK(check_bound(P));
     if (lane < 0 || lane >= P->B || !d_u || P->pb.nslices > 1) return HS_EINVAL;
+    if (P->pb.lane_memory && !P->lane_base[lane]) return HS_ESTATE;
     const LaneBufs& lb = P->lanes[lane];
     int M = P->M[0];
     HS_TRY(hipMemcpyAsync(d_u, lb.U[0] + (M - 1) * lb.N[0], lb.N[0] * sizeof(double),
@@ -1597,6 +1780,7 @@ hs_status hs_get_lane_state(hs_plan* P, int32_t lane, double* d_u, void* stream)
 hs_status hs_get_state(hs_plan* P, double* d_u, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (!d_u) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     int M = P->M[0];
@@ -1618,6 +1802,7 @@ hs_status hs_get_nodes(hs_plan* P, int32_t level, double* d_U, double* d_FI, dou
                        double* d_tau, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
     if ((d_Ut || d_tau) && level != 1) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -1636,6 +1821,7 @@ hs_status hs_get_nodes(hs_plan* P, int32_t level, double* d_U, double* d_FI, dou
 hs_status hs_set_nodes(hs_plan* P, int32_t level, const double* d_U, const double* d_FI, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     int M = P->M[level];
@@ -1722,6 +1908,7 @@ hs_status hs_solve(hs_plan* P, void* stream)
 hs_status hs_solve_graph(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (P->pb.nslices > 1 || P->pb.sweeps <= 0 || P->pb.mg.fixed_cycles <= 0) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     // table uploads are not allowed inside a capture: bring them up to date first
@@ -1758,13 +1945,43 @@ __global__ void k_pfasst_block(LaneCtl* ctl, int P, double t0, double dt, int bl
 }
 }  // namespace
 
+namespace {
+
+// Coarse predictor of PFASST (see hs_pfasst_run): restriction of the spread
+// fine values, the coarse level run serially through the slices without the
+// FAS correction, interpolation of the coarse correction.
+hs_status pfasst_predictor(hs_plan* P, hipStream_t s)
+{
+    LaneSet& all = P->all;
+    HS_TRY(hsk::fas_restrict(P->ctl, all.fasc.d, all.fasc.nseg(), all.fasc.nblk, P->order[1], 1, s));
+    for (int b = 0; b < P->B; b++) HS_TRY(hsk::fill(P->lanes[b].tau, (long long)P->M[1] * P->lanes[b].N[1], 0.0, s));
+    int outcome;
+    for (int p = 0; p < P->B; p++) {
+        if (p > 0) {
+            // slice p's coarse step starts from slice p-1's coarse end value, spread over its nodes
+            HS_TRY(hsk::handoff(P->ctl, P->hc_dst[p].d, P->hc_src[p].d, 1, P->hc_dst[p].nblk, P->order[1], s));
+            const Table<SdcSeg>& T = P->single[p].sdc[1];
+            HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[1], 0, s));
+        }
+        for (int j = 0; j < P->pb.pfasst_pred_sweeps; j++) HS_CHECK(sweep(P, P->single[p], 1, false, false, s, &outcome));
+    }
+    HS_TRY(hsk::fas_interp(P->ctl, all.fasf.d, all.fasf.nseg(), all.fasf.nblk, 1, s));
+    HS_TRY(hsk::fi_march(P->ctl, all.mg64[0].fine.d, all.sdc[0].d, all.sdc[0].nseg(), all.mg64[0].fine.nblk,
+                         P->order[0], 0, P->M[0], -1, 1, s));
+    return HS_OK;
+}
+
+}  // namespace
+
 extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->pb.lane_memory) return HS_EINVAL;
     if (P->pb.nslices <= 1) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int Pn = P->B, Mf = P->M[0], Mc = P->M[1];
+    int Pn = P->B, Mf = P->M[0];
     int nblocks = P->pb.nsteps / Pn;
+    const bool fixed = P->pb.sweeps > 0;
     LaneSet& all = P->all;
     for (int blk = 0; blk < nblocks; blk++) {
         if (blk > 0) {
@@ -1780,12 +1997,33 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
                            P->pb.t0, P->pb.dt, blk);
         HS_TRY(hipGetLastError());
         HS_CHECK(begin_step(P, s));
-        for (int k = 0; k < P->pb.sweeps; k++) {
-            // (i) fine hand-off from the previous iteration, then fine sweeps on every slice
+        if (P->pb.pfasst_pred_sweeps > 0) HS_CHECK(pfasst_predictor(P, s));
+        for (int k = 0;; k++) {
+            if (fixed && k >= P->pb.sweeps) break;
+            // (i) fine hand-off from the previous iteration
             HS_TRY(hsk::handoff(P->ctl, P->hf_dst.d, P->hf_src.d, P->hf_dst.nseg(), P->hf_dst.nblk,
                                 P->order[0], s));
+            bool prep_done = false;
+            if (!fixed) {
+                // every slice's collocation residual after the hand-off (formed with the
+                // sweep's constant parts); stop when all meet sdc_tol
+                const Table<SdcSeg>& T = all.sdc[0];
+                HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, 1, 1, P->partials, s));
+                HS_TRY(hsk::sdc_decide(P->ctl, T.d, T.nseg(), T.nblk, P->partials, P->pb.sdc_tol,
+                                       P->pb.max_sweeps, s));
+                HS_CHECK(read_ctl(P, s));
+                bool done = true, failed = false;
+                for (int b = 0; b < Pn; b++) {
+                    int st = P->h_ctl[b].sdc_state;
+                    if (st == 0) done = false;
+                    if (st == 2) failed = true;
+                }
+                if (done || failed) break;   // a failure is recorded in the lanes' status
+                HS_TRY(hsk::sdc_reopen(P->ctl, P->B, s));
+                prep_done = true;
+            }
             int outcome;
-            HS_CHECK(sweep(P, all, 0, false, true, s, &outcome));
+            HS_CHECK(sweep(P, all, 0, false, true, s, &outcome, prep_done));
             // (ii) restriction and FAS correction on every slice
             HS_TRY(hsk::fas_restrict(P->ctl, all.fasc.d, all.fasc.nseg(), all.fasc.nblk, P->order[1], 1, s));
             // (iii) coarse pipeline: slice p starts from slice p-1's new coarse end value
@@ -1803,7 +2041,156 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
         }
         HS_TRY(hsk::end_step(P->ctl, P->B, s));
     }
-    (void)Mc;
+    return HS_OK;
+}
+
+extern "C" hs_status hs_plan_timer(hs_plan* P, int32_t kind, int32_t max_launches)
+{
+    HS_CHECK(check_bound(P));
+    const int base = kind & ~HS_TIMER_FP32;
+    if (kind < 0 || (kind != 0 && (base < HS_TIMER_PJAC || base > HS_TIMER_SWEEP2)) || max_launches < 0 ||
+        max_launches > 65536)
+        return HS_EINVAL;
+    HS_TRY(hipDeviceSynchronize());   // no timed launch may still use the old events
+    for (hipEvent_t e : P->timer_ev) (void)hipEventDestroy(e);
+    P->timer_ev.clear();
+    P->timer_used = 0;
+    P->timer_kind = 0;
+    if (kind == 0 || max_launches == 0) return HS_OK;
+    for (int i = 0; i < 2 * max_launches; i++) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (hipEvent_t x : P->timer_ev) (void)hipEventDestroy(x);
+            P->timer_ev.clear();
+            return HS_EDEVICE;
+        }
+        P->timer_ev.push_back(e);
+    }
+    P->timer_kind = kind;
+    return HS_OK;
+}
+
+extern "C" hs_status hs_plan_timer_read(hs_plan* P, int32_t* launches, double* total_ms)
+{
+    HS_CHECK(check_bound(P));
+    if (!launches || !total_ms) return HS_EINVAL;
+    double ms = 0.0;
+    if (P->timer_used > 0) HS_TRY(hipEventSynchronize(P->timer_ev[2 * P->timer_used - 1]));
+    for (int i = 0; i < P->timer_used; i++) {
+        float t = 0.0f;
+        HS_TRY(hipEventElapsedTime(&t, P->timer_ev[2 * i], P->timer_ev[2 * i + 1]));
+        ms += t;
+    }
+    *launches = P->timer_used;
+    *total_ms = ms;
+    P->timer_used = 0;
+    return HS_OK;
+}
+
+namespace {
+
+// Integer fields of the flat objects of a tuning file: every {...} that has no
+// nested object gives one map of "key": number pairs.
+std::vector<std::map<std::string, long long>> parse_flat_objects(const std::string& t)
+{
+    std::vector<std::map<std::string, long long>> out;
+    size_t i = 0;
+    while ((i = t.find('{', i)) != std::string::npos) {
+        size_t j = t.find_first_of("{}", i + 1);
+        if (j == std::string::npos) break;
+        if (t[j] == '{') {   // nested: the inner object is scanned next
+            i = j;
+            continue;
+        }
+        std::map<std::string, long long> obj;
+        size_t k = i + 1;
+        while (true) {
+            size_t q0 = t.find('"', k);
+            if (q0 == std::string::npos || q0 > j) break;
+            size_t q1 = t.find('"', q0 + 1);
+            if (q1 == std::string::npos || q1 > j) break;
+            std::string key = t.substr(q0 + 1, q1 - q0 - 1);
+            size_t c = t.find_first_not_of(" \t\r\n", q1 + 1);
+            if (c == std::string::npos || c > j || t[c] != ':') { k = q1 + 1; continue; }
+            size_t v = t.find_first_not_of(" \t\r\n", c + 1);
+            if (v == std::string::npos || v > j) break;
+            char* end = nullptr;
+            long long val = std::strtoll(t.c_str() + v, &end, 10);
+            size_t e = end ? (size_t)(end - t.c_str()) : v;
+            if (e > v && e <= j && (t[e] == ',' || t[e] == '}' || t[e] == ' ' || t[e] == '\n' || t[e] == '\r' ||
+                                   t[e] == '\t'))
+                obj[key] = val;
+            // skip the value (a string may hold commas)
+            if (t[v] == '"') {
+                size_t s1 = t.find('"', v + 1);
+                k = s1 == std::string::npos ? j : s1 + 1;
+            } else {
+                k = e > v ? e : v + 1;
+            }
+        }
+        out.push_back(obj);
+        i = j + 1;
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" hs_status hs_tune_set(int32_t n, int32_t order, int32_t precision, int32_t batch, int32_t zb,
+                                 int32_t zb_rfw)
+{
+    if (!valid_tune(n, order, precision, batch, zb, zb_rfw)) return HS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (TuneEntry& e : g_tune)
+        if (e.n == n && e.order == order && e.prec == precision && e.batch == batch) {
+            e.zb = zb;
+            e.zb_rfw = zb_rfw;
+            return HS_OK;
+        }
+    g_tune.push_back({n, order, precision, batch, zb, zb_rfw});
+    return HS_OK;
+}
+
+extern "C" hs_status hs_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return HS_OK;
+}
+
+extern "C" hs_status hs_tune_load(const char* json_path, int32_t* entries)
+{
+    if (!json_path) return HS_EINVAL;
+    FILE* f = std::fopen(json_path, "rb");
+    if (!f) return HS_EINVAL;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    int count = 0;
+    static const char* keys[] = {"n", "order", "precision", "batch", "zb", "zb_rfw"};
+    for (const auto& obj : parse_flat_objects(text)) {
+        bool all = true;
+        for (const char* k : keys) all = all && obj.count(k);
+        if (!all) continue;
+        hs_status st = hs_tune_set((int)obj.at("n"), (int)obj.at("order"), (int)obj.at("precision"),
+                                   (int)obj.at("batch"), (int)obj.at("zb"), (int)obj.at("zb_rfw"));
+        if (st != HS_OK) return st;
+        count++;
+    }
+    if (entries) *entries = count;
+    return HS_OK;
+}
+
+extern "C" hs_status hs_tune_lookup(int32_t n, int32_t order, int32_t precision, int32_t batch, int32_t* zb,
+                                    int32_t* zb_rfw)
+{
+    if (!zb || !zb_rfw || !valid_tune(n, order, precision, batch < 1 ? 1 : batch, 1, 2)) return HS_EINVAL;
+    int a = 0, b = 0;
+    tuned_zb(n, order, precision, batch, &a, &b);
+    *zb = a;
+    *zb_rfw = b;
     return HS_OK;
 }
 
@@ -1824,6 +2211,8 @@ extern "C" hs_status hs_stats_read(hs_plan* P, hs_lane_stats* out, void* stream)
         o.failed_solves = c.failed_solves;
         o.last_rho = c.mg_rho;
         o.last_sdc_res = c.sdc_res;
+        o.level_cycles[0] = c.level_cycles[0];
+        o.level_cycles[1] = c.level_cycles[1];
     }
     return lanes_status(P);
 }

@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libheatst.so")
+TUNE_CACHE = os.path.join(HERE, "tune_cache.json")
 
 HS_OK, HS_EINVAL, HS_ENOMEM, HS_ENOCONV, HS_ENONFINITE, HS_EDEVICE, HS_ESTATE, HS_PENDING = \
     0, -1, -2, -3, -4, -5, -6, 1
@@ -43,14 +44,16 @@ class ProblemDesc(C.Structure):
                 ("forcing_c", C.c_double), ("nsteps", C.c_int32), ("nlevels", C.c_int32),
                 ("lev", LevelDesc * 2), ("mg", MgDesc), ("sweeps", C.c_int32),
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("batch", C.c_int32),
-                ("nslices", C.c_int32), ("h_lane_n", C.POINTER(C.c_int32))]
+                ("nslices", C.c_int32), ("h_lane_n", C.POINTER(C.c_int32)),
+                ("pfasst_pred_sweeps", C.c_int32), ("lane_memory", C.c_int32)]
 
 
 class LaneStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("steps_done", C.c_int32), ("total_sweeps", C.c_int32),
                 ("total_solves", C.c_int32), ("total_cycles", C.c_int64),
                 ("max_cycles", C.c_int32), ("failed_solves", C.c_int32),
-                ("last_rho", C.c_double), ("last_sdc_res", C.c_double)]
+                ("last_rho", C.c_double), ("last_sdc_res", C.c_double),
+                ("level_cycles", C.c_int64 * 2)]
 
 
 class ServerDesc(C.Structure):
@@ -95,6 +98,12 @@ def lib():
         "hs_mg_vcycle": [_V, C.c_int32, _V, _V, _V, _V],
         "hs_smooth": [_V, C.c_int32, _V, _V, _V, _V, C.c_int32, _V],
         "hs_mg_solve_static": [C.c_int32, C.c_int32, C.c_double, _V, _V, _V, _V],
+        "hs_plan_timer": [_V, C.c_int32, C.c_int32],
+        "hs_plan_timer_read": [_V, _P(C.c_int32), _P(C.c_double)],
+        "hs_tune_set": [C.c_int32] * 6,
+        "hs_tune_clear": [],
+        "hs_tune_load": [C.c_char_p, _P(C.c_int32)],
+        "hs_tune_lookup": [C.c_int32] * 4 + [_P(C.c_int32), _P(C.c_int32)],
         "hs_set_state": [_V, _V, _V],
         "hs_get_state": [_V, _V, _V],
         "hs_get_nodes": [_V, C.c_int32, _V, _V, _V, _V, _V],
@@ -112,7 +121,12 @@ def lib():
         "hs_stats_read": [_V, _V, _V],
         "hs_set_lane_state": [_V, C.c_int32, _V, _V],
         "hs_get_lane_state": [_V, C.c_int32, _V, _V],
-        "hs_server_pool_bytes": [_P(ServerDesc), _P(C.c_size_t)],
+        "hs_server_pool_bytes": [_P(ServerDesc), _P(C.c_size_t), _P(C.c_size_t)],
+        "hs_server_request_bytes": [_P(ServerDesc), C.c_int32, _P(C.c_size_t)],
+        "hs_server_resident": [_V, _P(C.c_size_t), _P(C.c_size_t)],
+        "hs_lane_bytes": [_P(ProblemDesc), C.c_int32, _P(C.c_size_t)],
+        "hs_plan_bind_lane": [_V, C.c_int32, _V, C.c_size_t, _V],
+        "hs_plan_unbind_lane": [_V, C.c_int32],
         "hs_server_create": [_P(ServerDesc), _V, C.c_size_t, C.c_size_t, _P(_V)],
         "hs_server_submit": [_V, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, _V, _V,
                              _P(C.c_uint64)],
@@ -125,6 +139,12 @@ def lib():
         f.restype = S
         f.argtypes = args
     _lib = L
+    # launch shapes tuned on this GPU model (paper_1307_7867_amd/tune.py), unless
+    # HEATST_TUNE_CACHE names another file or is empty (built-in shapes)
+    path = os.environ.get("HEATST_TUNE_CACHE", TUNE_CACHE)
+    if path and os.path.exists(path):
+        cnt = C.c_int32(0)
+        check(L.hs_tune_load(os.fsencode(path), C.byref(cnt)), "hs_tune_load")
     return L
 
 
@@ -150,6 +170,29 @@ def collocation(M: int):
 
 
 HS_STATIC_MAX_N = 63
+
+
+HS_TIMER_PJAC, HS_TIMER_RESID_FW, HS_TIMER_SWEEP1, HS_TIMER_SWEEP2, HS_TIMER_FP32 = 1, 2, 3, 4, 16
+
+
+def tune_set(n, order, precision, batch, zb, zb_rfw):
+    check(lib().hs_tune_set(n, order, precision, batch, zb, zb_rfw), "hs_tune_set")
+
+
+def tune_clear():
+    check(lib().hs_tune_clear(), "hs_tune_clear")
+
+
+def tune_load(path) -> int:
+    cnt = C.c_int32(0)
+    check(lib().hs_tune_load(os.fsencode(path), C.byref(cnt)), "hs_tune_load")
+    return cnt.value
+
+
+def tune_lookup(n, order, precision, batch):
+    zb, zr = C.c_int32(0), C.c_int32(0)
+    check(lib().hs_tune_lookup(n, order, precision, batch, C.byref(zb), C.byref(zr)), "hs_tune_lookup")
+    return zb.value, zr.value
 
 
 def mg_solve_static(u, b, a, n, order, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest=3, tol=1e-12,
@@ -193,6 +236,7 @@ class Problem:
     batch: int = 1
     nslices: int = 1
     lane_n: list | None = None
+    pfasst_pred_sweeps: int = 0
 
     def desc(self):
         d = ProblemDesc()
@@ -207,6 +251,7 @@ class Problem:
                       self.fused_sweeps, self.cycle_graphs)
         d.sweeps, d.sdc_tol, d.max_sweeps = self.sweeps, self.sdc_tol, self.max_sweeps
         d.batch, d.nslices = self.batch, self.nslices
+        d.pfasst_pred_sweeps = self.pfasst_pred_sweeps
         keep = None
         if self.lane_n is not None:
             keep = (C.c_int32 * len(self.lane_n))(*self.lane_n)
@@ -378,4 +423,18 @@ class Plan:
     def stats(self):
         arr = (LaneStats * self.lanes)()
         st = lib().hs_stats_read(self._h, C.cast(arr, _V), self._s())
-        return st, [dict((f, getattr(a, f)) for f, _ in LaneStats._fields_) for a in arr]
+        out = []
+        for a in arr:
+            d = dict((f, getattr(a, f)) for f, _ in LaneStats._fields_)
+            d["level_cycles"] = list(a.level_cycles)
+            out.append(d)
+        return st, out
+
+    # measurement aid ----------------------------------------------------
+    def timer(self, kind, max_launches=4096):
+        check(lib().hs_plan_timer(self._h, kind, max_launches), "hs_plan_timer")
+
+    def timer_read(self):
+        n, ms = C.c_int32(0), C.c_double(0.0)
+        check(lib().hs_plan_timer_read(self._h, C.byref(n), C.byref(ms)), "hs_plan_timer_read")
+        return n.value, ms.value

@@ -1,10 +1,10 @@
 """Python driver of the serving core (hs_server_* in libheatst).
 
-The admission, slot management and continuous batching live in the C++
-core; this module owns the device pool (a torch allocation), keeps request
-tensors alive while the core uses them, sizes the slot classes from an HBM
-budget, and replays a Poisson arrival stream to measure latency and
-throughput.
+The admission by resident bytes, lane management and continuous batching
+live in the C++ core; this module owns the device pool (a torch
+allocation), keeps request tensors alive while the core uses them, sizes
+the classes' lane counts, and replays a Poisson arrival stream to measure
+latency and throughput.
 """
 from __future__ import annotations
 
@@ -18,77 +18,102 @@ from . import heatst as hs
 
 
 def lane_bytes(n, order=2, nnodes=5, precision=hs.HS_MIXED, **kw) -> int:
-    """Device bytes one lane (one resident request) of grid n needs."""
+    """Device bytes one request of grid n holds while admitted (its fields and
+    multigrid hierarchy)."""
     p = hs.Problem(n=n, order=order, nnodes=nnodes, precision=precision, **kw)
-    return p.workspace_bytes()
+    d, keep = p.desc()
+    d.lane_memory = 1
+    out = C.c_size_t(0)
+    hs.check(hs.lib().hs_lane_bytes(C.byref(d), 0, C.byref(out)), "hs_lane_bytes")
+    return out.value
 
 
-def slot_cap(n: int) -> int:
-    """Most lanes worth batching for grid n.  Small grids are bound by launch
-    latency and gain from batching; from 255^3 on one lane saturates HBM and
-    more resident lanes only push its coarse grids out of the Infinity Cache,
-    so those classes get one lane and queue."""
+def lane_cap(n: int) -> int:
+    """Lanes of a size class's batched plan (the most of its requests served
+    at once; the budget decides how many are resident).  Small grids are
+    bound by launch latency and gain from wide batches; from 255^3 on a few
+    lanes already saturate HBM."""
     if n <= 31:
         return 64
     if n <= 63:
         return 32
     if n <= 127:
-        return 8
-    return 1
+        return 16
+    return 8
 
 
-def slots_for_budget(budget_bytes: int, sizes, weights, order=2, nnodes=5, precision=hs.HS_MIXED,
-                     cap=slot_cap, **kw) -> dict:
-    """Slots per grid-size class: every class gets one slot, then slots are
-    handed out in proportion to the arrival weights (the share of requests of
-    each size) up to each class's cap, while the budget allows."""
-    per = {n: lane_bytes(n, order, nnodes, precision, **kw) for n in sizes}
-    wt = dict(zip(sizes, weights))
-    slots = {n: 1 for n in sizes}
-    used = sum(per.values())
-    if used > budget_bytes:
-        raise ValueError("budget below one slot per class")
-    while True:
-        cand = sorted(sizes, key=lambda n: slots[n] / wt[n])
-        grown = False
-        for n in cand:
-            if slots[n] < cap(n) and used + per[n] <= budget_bytes:
-                slots[n] += 1
-                used += per[n]
-                grown = True
-                break
-        if not grown:
-            return slots
+def capacities_for_budget(budget_bytes: int, sizes, order=2, nnodes=5, precision=hs.HS_MIXED,
+                          cap=lane_cap, **kw) -> dict:
+    """Lanes per class: the class cap, or fewer when the budget could never
+    hold that many requests of the class at once."""
+    out = {}
+    for n in sizes:
+        per = lane_bytes(n, order, nnodes, precision, **kw)
+        out[n] = max(1, min(cap(n), budget_bytes // per))
+    return out
+
+
+def _desc(slots, order, nnodes, precision, tol, max_cycles, inner, nu1, nu2, sweeps, sdc_tol, max_sweeps,
+          forcing_c):
+    d = hs.ServerDesc()
+    d.order, d.nnodes = order, nnodes
+    d.mg = hs.MgDesc(nu1, nu2, 6.0 / 7.0, 3, tol, max_cycles, 0, precision, inner[0], inner[1], 1, 0)
+    d.sweeps, d.sdc_tol, d.max_sweeps, d.forcing_c = sweeps, sdc_tol, max_sweeps, forcing_c
+    items = sorted(slots.items())
+    d.nclasses = len(items)
+    for i, (n, s) in enumerate(items):
+        d.class_n[i] = n
+        d.class_slots[i] = s
+    return d, items
+
+
+def pool_bytes(desc):
+    """(shared workspace bytes, bytes with every lane of every class in use)."""
+    sh, full = C.c_size_t(0), C.c_size_t(0)
+    hs.check(hs.lib().hs_server_pool_bytes(C.byref(desc), C.byref(sh), C.byref(full)), "hs_server_pool_bytes")
+    return sh.value, full.value
 
 
 class Server:
-    """Continuous-batching server for independent heat solves on one GPU."""
+    """Continuous-batching server for independent heat solves on one GPU.
+
+    slots: {grid n: lanes of that class's plan}.  budget_bytes: the most
+    device memory the server holds (shared workspaces plus the admitted
+    requests); the pool is sized to it (or to every lane in use, if less)."""
 
     def __init__(self, slots: dict, order=2, nnodes=5, precision=hs.HS_MIXED, tol=1e-10,
                  max_cycles=60, inner=(2, 2), nu1=2, nu2=1, sweeps=0, sdc_tol=1e-10, max_sweeps=40,
                  forcing_c=3.0, budget_bytes=None):
         import torch
         L = hs.lib()
-        d = hs.ServerDesc()
-        d.order, d.nnodes = order, nnodes
-        d.mg = hs.MgDesc(nu1, nu2, 6.0 / 7.0, 3, tol, max_cycles, 0, precision, inner[0], inner[1], 1, 0)
-        d.sweeps, d.sdc_tol, d.max_sweeps, d.forcing_c = sweeps, sdc_tol, max_sweeps, forcing_c
-        items = sorted(slots.items())
-        d.nclasses = len(items)
-        for i, (n, s) in enumerate(items):
-            d.class_n[i] = n
-            d.class_slots[i] = s
-        need = C.c_size_t(0)
-        hs.check(L.hs_server_pool_bytes(C.byref(d), C.byref(need)), "hs_server_pool_bytes")
-        self.pool_bytes = need.value
+        d, items = _desc(slots, order, nnodes, precision, tol, max_cycles, inner, nu1, nu2, sweeps, sdc_tol,
+                         max_sweeps, forcing_c)
+        shared, full = pool_bytes(d)
+        budget = full if budget_bytes is None else int(budget_bytes)
+        self.pool_bytes = min(full, budget)
+        self.budget_bytes = budget
+        self.shared_bytes = shared
         self.pool = torch.empty(self.pool_bytes + 256, dtype=torch.uint8, device="cuda")
         base = (self.pool.data_ptr() + 255) & ~255
         self._h = C.c_void_p()
-        budget = budget_bytes if budget_bytes is not None else self.pool_bytes
         hs.check(L.hs_server_create(C.byref(d), C.c_void_p(base), self.pool_bytes, budget,
                                     C.byref(self._h)), "hs_server_create")
         self.slots = dict(items)
         self._keep = {}
+
+    @classmethod
+    def for_budget(cls, budget_bytes, sizes, weights=None, order=2, nnodes=5, precision=hs.HS_MIXED, **kw):
+        """A server for the grid sizes `sizes` whose resident requests share
+        budget_bytes (weights are accepted for symmetry with the request
+        stream; admission does not need them)."""
+        caps = capacities_for_budget(budget_bytes, sizes, order, nnodes, precision,
+                                     tol=kw.get("tol", 1e-10))
+        return cls(caps, order=order, nnodes=nnodes, precision=precision, budget_bytes=budget_bytes, **kw)
+
+    def resident(self):
+        r, b = C.c_size_t(0), C.c_size_t(0)
+        hs.check(hs.lib().hs_server_resident(self._h, C.byref(r), C.byref(b)), "hs_server_resident")
+        return r.value, b.value
 
     def submit(self, n, nu, dt, nsteps, u0, t0=0.0):
         import torch

@@ -2,6 +2,7 @@
 and exports every entry point of include/heatst.h, the problem validation
 and workspace sizing behave, and the collocation data the GPU path uses
 (computed independently of the oracle) matches the exact values."""
+import json
 import math
 import os
 import re
@@ -156,3 +157,52 @@ def test_static_solve_rejects_before_launching():
     assert L.hs_mg_solve_static(31, 2, 0.01, C.byref(g), fake, fake, None) == heatst.HS_EINVAL
     assert L.hs_mg_solve_static(31, 2, -1.0, C.byref(d), fake, fake, None) == heatst.HS_EINVAL
     assert L.hs_mg_solve_static(31, 2, 0.01, C.byref(d), None, fake, None) == heatst.HS_EINVAL
+
+
+def test_tune_table_parse_lookup_and_fallback(tmp_path):
+    """The launch-shape table: built-in rule without entries, the entry of the
+    largest batch <= the launch's count (else the smallest), JSON loading
+    (extra fields and nested objects ignored), invalid entries rejected."""
+    heatst.tune_clear()
+    try:
+        assert heatst.tune_lookup(127, 4, 0, 16) == (8, 8)     # built-in: 8 planes at 127^3
+        assert heatst.tune_lookup(63, 2, 0, 1) == (2, 2)       # 2 planes at 63^3
+        path = tmp_path / "tune.json"
+        path.write_text(json.dumps({
+            "device": "gfx950", "meta": {"note": "x, y", "n": 5},
+            "entries": [
+                {"n": 127, "order": 4, "precision": 0, "batch": 1, "zb": 8, "zb_rfw": 8, "us": 1.5},
+                {"n": 127, "order": 4, "precision": 0, "batch": 16, "zb": 16, "zb_rfw": 32},
+                {"n": 63, "order": 2, "precision": 1, "batch": 4, "zb": 4, "zb_rfw": 4, "note": "a,b"},
+            ]}))
+        assert heatst.tune_load(str(path)) == 3
+        assert heatst.tune_lookup(127, 4, 0, 16) == (16, 32)
+        assert heatst.tune_lookup(127, 4, 0, 40) == (16, 32)   # largest batch <= 40
+        assert heatst.tune_lookup(127, 4, 0, 8) == (8, 8)      # largest batch <= 8 is 1
+        assert heatst.tune_lookup(63, 2, 1, 1) == (4, 4)       # none <= 1: the smallest batch
+        assert heatst.tune_lookup(63, 2, 0, 4) == (2, 2)       # other precision: built-in rule
+        assert heatst.tune_lookup(127, 2, 0, 16) == (8, 8)     # other order: built-in rule
+        heatst.tune_set(127, 4, 0, 16, 4, 4)                    # replaces the entry
+        assert heatst.tune_lookup(127, 4, 0, 16) == (4, 4)
+        for bad in [(127, 4, 0, 16, 0, 8), (127, 4, 0, 16, 8, 3), (100, 4, 0, 1, 8, 8), (127, 3, 0, 1, 8, 8),
+                    (127, 4, 2, 1, 8, 8), (127, 4, 0, 0, 8, 8), (127, 4, 0, 1, 65, 8)]:
+            with pytest.raises(heatst.HeatstError):
+                heatst.tune_set(*bad)
+        with pytest.raises(heatst.HeatstError):
+            heatst.tune_load(str(tmp_path / "missing.json"))
+        # a plan takes the shape at creation: its workspace holds the same bytes either way
+        p = base_problem(n=31, nnodes=3)
+        b0 = p.workspace_bytes()
+        heatst.tune_set(31, 2, 0, 1, 1, 2)
+        assert p.workspace_bytes() >= b0
+    finally:
+        heatst.tune_clear()
+
+
+def test_pfasst_predictor_needs_slices():
+    with pytest.raises(heatst.HeatstError) as e:
+        base_problem(n=31, nnodes=3, pfasst_pred_sweeps=1).workspace_bytes()
+    assert e.value.status == heatst.HS_EINVAL
+    p = base_problem(n=31, order=4, nnodes=5, coarse=(15, 2, 3), batch=4, nslices=4, nsteps=4, sweeps=0,
+                     pfasst_pred_sweeps=2)
+    assert p.workspace_bytes() > 0

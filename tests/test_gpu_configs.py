@@ -248,3 +248,51 @@ def test_uneven64_tolerance_mode(torch):
         worst = max(worst, e)
         assert e <= TOL, (i, n, e)
     print(f"uneven64 tolerance mode: worst error of the n <= 63 lanes {worst:.2e}")
+
+
+# ----------------------------------------------------------------------------
+# PFASST with the coarse predictor and residual-based termination
+# ----------------------------------------------------------------------------
+
+PF_TOL_CASES = {
+    # name: (nf, slices, predictor sweeps, sdc_tol)
+    "pfasst_tol_15_p4": (15, 4, 1, 1e-10),
+    "pfasst_tol_31_p16": (31, 16, 1, 1e-10),
+    "pfasst_tol_31_p16_nopred": (31, 16, 0, 1e-10),
+}
+
+
+def _pfasst_tol_ref(name):
+    nf, P, pred, tol = PF_TOL_CASES[name]
+    pb = oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, dt=0.01, nsteps=P, sweeps=0, sdc_tol=tol,
+                        max_sweeps=30, mg=oracle.mg_params(tol=1e-12, max_cycles=60))
+    return oracle.pfasst(pb, P, inputs.random_smooth(nf, 31), pred_sweeps=pred)
+
+
+for _name in PF_TOL_CASES:
+    BACKGROUND_REFS[_name] = (lambda name=_name: _pfasst_tol_ref(name))
+
+
+@pytest.mark.parametrize("name", sorted(PF_TOL_CASES))
+def test_pfasst_predictor_tolerance_parity(torch, name):
+    """PFASST with the serial coarse predictor and iterations until every
+    slice's collocation residual is <= 1e-10: same result and the same number
+    of iterations as the oracle."""
+    from paper_1307_7867_amd import heatst as hs
+    nf, P, pred, tol = PF_TOL_CASES[name]
+    pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=((nf - 1) // 2, 2, 3), nu=0.1, dt=0.01, nsteps=P, sweeps=0,
+                    sdc_tol=tol, max_sweeps=30, tol=1e-12, max_cycles=60, batch=P, nslices=P,
+                    pfasst_pred_sweeps=pred)
+    plan = hs.Plan(pb)
+    plan.set_state(dev(torch, inputs.random_smooth(nf, 31)))
+    plan.pfasst_run()
+    got = host(plan.get_state()).reshape(nf, nf, nf)
+    st, stats = plan.stats()
+    assert st == 0, hs.status_string(st)
+    ref, s, ost = background_ref(name, lambda: _pfasst_tol_ref(name))
+    assert s == oracle.OK
+    iters = {x["total_sweeps"] for x in stats}
+    err = rel(got, ref)
+    print(f"{name}: iterations gpu {sorted(iters)} oracle {ost.sweeps}, |gpu - oracle| / |oracle| = {err:.2e}")
+    assert iters == {ost.sweeps}
+    assert err <= TOL

@@ -157,3 +157,38 @@ def test_serving_queues_when_slots_are_full(torch):
     outs = [srv.result(t).cpu().numpy() for t in tks]
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
     srv.close()
+
+
+def test_admission_by_resident_bytes(torch):
+    """Requests are admitted while their bytes fit the budget, not by fixed
+    slots.  With room for one 63^3 request and two 31^3 ones beside the
+    shared tables: the second 63^3 request waits for the first although its
+    class has four lanes; the 31^3 requests submitted before it run beside
+    the first; the 31^3 requests submitted after it do not overtake it (it
+    reserves its bytes); every result equals the request solved alone."""
+    from paper_1307_7867_amd import heatst as hs
+    from paper_1307_7867_amd import serving
+    b31, b63 = serving.lane_bytes(31), serving.lane_bytes(63)
+    probe = serving.Server({31: 4, 63: 4}, precision=hs.HS_MIXED, tol=1e-12, sdc_tol=1e-10, max_sweeps=40)
+    shared = probe.shared_bytes
+    probe.close()
+    budget = shared + b63 + 2 * b31
+    srv = serving.Server({31: 4, 63: 4}, precision=hs.HS_MIXED, tol=1e-12, sdc_tol=1e-10, max_sweeps=40,
+                         budget_bytes=budget)
+    assert srv.resident() == (0, budget - shared)
+    reqs = [dict(n=63, nu=0.1, dt=0.01, nsteps=3, seed=81), dict(n=31, nu=0.07, dt=0.02, nsteps=2, seed=91),
+            dict(n=31, nu=0.12, dt=0.01, nsteps=2, seed=92), dict(n=63, nu=0.05, dt=0.02, nsteps=2, seed=82),
+            dict(n=31, nu=0.09, dt=0.03, nsteps=2, seed=93), dict(n=31, nu=0.15, dt=0.01, nsteps=1, seed=94)]
+    u0s = [torch.from_numpy(inputs.random_smooth(r["n"], r["seed"]).ravel()).cuda() for r in reqs]
+    torch.cuda.synchronize()
+    tks = [srv.submit(r["n"], r["nu"], r["dt"], r["nsteps"], u0) for r, u0 in zip(reqs, u0s)]
+    srv.drain()
+    inf = [srv.poll(t)[1] for t in tks]
+    assert all(i.state == 2 and i.status == 0 for i in inf)
+    assert inf[3].t_admit >= inf[0].t_done - 1e-6          # one 63^3 request resident at a time
+    assert inf[1].t_admit < inf[0].t_done and inf[2].t_admit < inf[0].t_done   # 31^3 beside it
+    assert inf[4].t_admit >= inf[3].t_admit and inf[5].t_admit >= inf[3].t_admit   # no overtaking
+    for tk, r in zip(tks, reqs):
+        assert np.array_equal(srv.result(tk).cpu().numpy(), alone(torch, hs, r, hs.HS_MIXED)), r
+    assert srv.resident()[0] == 0
+    srv.close()

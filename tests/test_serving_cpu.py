@@ -1,5 +1,5 @@
 """Host-side checks of the serving core (no GPU): class validation, pool
-sizing and admission by budget."""
+sizing and the budget check at creation."""
 import ctypes as C
 
 import pytest
@@ -19,45 +19,69 @@ def desc(classes, precision=hs.HS_MIXED):
     return d
 
 
-def pool_bytes(d):
+def sizes(d):
+    sh, full = C.c_size_t(0), C.c_size_t(0)
+    s = hs.lib().hs_server_pool_bytes(C.byref(d), C.byref(sh), C.byref(full))
+    return s, sh.value, full.value
+
+
+def request_bytes(d, n):
     out = C.c_size_t(0)
-    s = hs.lib().hs_server_pool_bytes(C.byref(d), C.byref(out))
+    s = hs.lib().hs_server_request_bytes(C.byref(d), n, C.byref(out))
     return s, out.value
 
 
 @pytest.mark.parametrize("classes", [[], [(16, 2)], [(31, 0)], [(31, 2), (31, 1)], [(1023, 1)]])
 def test_invalid_classes_rejected(classes):
-    s, _ = pool_bytes(desc(classes))
+    s, _, _ = sizes(desc(classes))
     assert s == hs.HS_EINVAL
 
 
-def test_pool_bytes_is_sum_of_class_plans():
-    s, total = pool_bytes(desc([(31, 3), (63, 2)]))
+def test_request_bytes_are_the_lane_fields_and_hierarchy():
+    """A request of grid n holds its node data (U, F_I: 5 nodes; 4 quadrature
+    fields; rhs, tmp) and the FP64 correction grids and FP32 grids of its
+    hierarchy, nothing of the class's shared tables."""
+    d = desc([(31, 3), (63, 2)])
+    for n in (31, 63):
+        s, b = request_bytes(d, n)
+        assert s == hs.HS_OK
+        N = n ** 3
+        fields = (5 + 5 + 4 + 2) * N * 8
+        grids, g = [], n
+        while g >= 3:
+            grids.append(g)
+            g = (g - 1) // 2
+        fp64 = sum(3 * k ** 3 * 8 for k in grids[1:])
+        fp32 = sum(3 * k ** 3 * 4 for k in grids)
+        assert fields + fp64 + fp32 <= b <= fields + fp64 + fp32 + 64 * 256
+        assert b == serving.lane_bytes(n)
+    assert request_bytes(d, 127)[0] == hs.HS_EINVAL
+
+
+def test_pool_bytes_is_shared_plus_every_lane():
+    d = desc([(31, 3), (63, 2)])
+    s, sh, full = sizes(d)
     assert s == hs.HS_OK
-    per31 = serving.lane_bytes(31)
-    per63 = serving.lane_bytes(63)
-    assert total >= 2 * per63 + 3 * per31 * 0.9
-    assert total <= 3 * per31 + 2 * per63 + (1 << 20)
+    assert 0 < sh < 1 << 20            # lane states, tables and partials only
+    assert full == sh + 3 * request_bytes(d, 31)[1] + 2 * request_bytes(d, 63)[1]
 
 
-def test_create_rejects_budget_below_need():
-    d = desc([(31, 2)])
-    s, need = pool_bytes(d)
+def test_create_rejects_pool_or_budget_below_one_request():
+    d = desc([(31, 2), (63, 1)])
+    _, sh, full = sizes(d)
+    need = sh + request_bytes(d, 63)[1]
     h = C.c_void_p()
-    # the budget check happens before any device call; the pool pointer is never used
-    st = hs.lib().hs_server_create(C.byref(d), C.c_void_p(256), need, need - 1, C.byref(h))
+    # the checks happen before any device call; the pool pointer is never used
+    st = hs.lib().hs_server_create(C.byref(d), C.c_void_p(256), full, need - 1, C.byref(h))
     assert st == hs.HS_ENOMEM
-    st = hs.lib().hs_server_create(C.byref(d), C.c_void_p(256), need - 1, need, C.byref(h))
+    st = hs.lib().hs_server_create(C.byref(d), C.c_void_p(256), need - 1, full, C.byref(h))
     assert st == hs.HS_ENOMEM
 
 
-def test_slots_for_budget_respects_budget_and_weights():
-    sizes, weights = (31, 63, 127), (8, 4, 2)
-    budget = 2 * 10**9
-    slots = serving.slots_for_budget(budget, sizes, weights)
-    used = sum(slots[n] * serving.lane_bytes(n) for n in sizes)
-    assert used <= budget
-    assert all(slots[n] >= 1 for n in sizes)
-    # every class is at its cap or the budget is exhausted for it
-    for n in sizes:
-        assert slots[n] == serving.slot_cap(n) or used + serving.lane_bytes(n) > budget
+def test_capacities_follow_caps_and_budget():
+    big = 10 ** 12
+    caps = serving.capacities_for_budget(big, (31, 63, 127, 255, 511))
+    assert caps == {n: serving.lane_cap(n) for n in (31, 63, 127, 255, 511)}
+    small = 3 * serving.lane_bytes(255) + 1
+    caps = serving.capacities_for_budget(small, (31, 255))
+    assert caps[255] == 3 and caps[31] == serving.lane_cap(31)
