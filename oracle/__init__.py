@@ -49,7 +49,7 @@ class Problem(C.Structure):
     _fields_ = [("nu", C.c_double), ("t0", C.c_double), ("dt", C.c_double),
                 ("forcing_c", C.c_double), ("nsteps", C.c_int32), ("sweeps", C.c_int32),
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("nlevels", C.c_int32),
-                ("lev", Level * 2), ("mg", MG)]
+                ("lev", Level * 2), ("mg", MG), ("node_parallel", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -90,6 +90,8 @@ def lib():
                                       C.c_double, _D, _D, _D]
         L.or_sdc_sweep.argtypes = [C.POINTER(Level), C.POINTER(MG), C.c_double, C.c_double,
                                    C.c_double, C.c_double, _D, _D, _D, C.POINTER(Stats)]
+        L.or_sdc_sweep_nodes.argtypes = [C.POINTER(Level), C.POINTER(MG), C.c_double, C.c_double,
+                                         C.c_double, C.c_double, _D, _D, C.POINTER(Stats)]
         L.or_fas_restrict.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, C.c_double,
                                       C.c_double, C.c_double, _D, _D, _D, _D, _D, _D]
         L.or_fas_interp.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, _D, _D, _D, _D]
@@ -122,8 +124,9 @@ def level(n, order, M) -> Level:
 
 
 def problem(levels, nu=0.1, t0=0.0, dt=0.1, nsteps=1, forcing_c=3.0, sweeps=4, sdc_tol=1e-10,
-            max_sweeps=20, mg=None) -> Problem:
+            max_sweeps=20, mg=None, node_parallel=0) -> Problem:
     pb = Problem()
+    pb.node_parallel = node_parallel
     pb.nu, pb.t0, pb.dt, pb.forcing_c = nu, t0, dt, forcing_c
     pb.nsteps, pb.sweeps, pb.sdc_tol, pb.max_sweeps = nsteps, sweeps, sdc_tol, max_sweeps
     pb.nlevels = len(levels)
@@ -247,6 +250,13 @@ def sdc_sweep(lv, mg, nu, tn, dt, c, U, FI, tau=None):
     st = Stats()
     s = lib().or_sdc_sweep(C.byref(lv), C.byref(mg), nu, tn, dt, c, _p(U), _p(FI),
                            _p(tau) if tau is not None else None, C.byref(st))
+    return s, st
+
+
+def sdc_sweep_nodes(lv, mg, nu, tn, dt, c, U, FI):
+    """In-place node-parallel sweep on U, FI.  Returns (status, Stats)."""
+    st = Stats()
+    s = lib().or_sdc_sweep_nodes(C.byref(lv), C.byref(mg), nu, tn, dt, c, _p(U), _p(FI), C.byref(st))
     return s, st
 
 

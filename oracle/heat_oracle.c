@@ -61,6 +61,7 @@ typedef struct {
     int32_t nlevels;     /* 1 = SDC, 2 = MLSDC */
     or_level lev[2];     /* lev[0] fine, lev[1] coarse */
     or_mg mg;
+    int32_t node_parallel; /* single-level SDC: 1 = node-parallel sweeps (or_sdc_sweep_nodes) */
 } or_problem;
 
 typedef struct {
@@ -658,6 +659,59 @@ int or_sdc_sweep(const or_level *L, const or_mg *mg, double nu, double tn, doubl
 }
 
 /*
+ * One node-parallel SDC sweep -- an addition, not in the paper.  The IMEX
+ * sweep of eq. (7) treats the implicit part with the lower-triangular
+ * matrix of the implicit-Euler substeps, so its M-1 solves run one after the
+ * other.  Replacing that matrix by the diagonal d_m = tau_m (each node an
+ * implicit Euler step over [t_0, t_m]) makes the solves independent:
+ *   (I - dt tau_m nu L_h) U^{k+1}_m
+ *       = U_0 + dt sum_j q_{m,j} f(U^k_j, t_j) - dt tau_m nu L_h U^k_m,
+ * m = 1..M-1, every right-hand side built from iterate k, each solved by
+ * or_mg_solve from the guess U^k_m; then f^I is recomputed at those nodes.
+ * The collocation solution of eq. (6) is still the fixed point: there
+ * U_m = U_0 + dt sum_j q_{m,j} f_j, so the right-hand side is
+ * (I - dt tau_m nu L_h) U_m.
+ */
+int or_sdc_sweep_nodes(const or_level *L, const or_mg *mg, double nu, double tn, double dt, double c,
+                       double *U, double *FI, or_stats *st)
+{
+    int M = L->M, n = L->n;
+    size_t N = cube(n);
+    double Q[OR_MAXM * OR_MAXM], nodes[OR_MAXM];
+    or_collocation_matrix(M, Q);
+    or_lobatto_nodes(M, nodes);
+    double *FE = alloc0((size_t)M * N);
+    for (int j = 0; j < M; j++) or_forcing(n, nu, c, tn + dt * nodes[j], FE + (size_t)j * N);
+    /* every right-hand side from iterate k, before any node changes */
+    double *rhs = alloc0((size_t)(M - 1) * N);
+    for (int m = 1; m < M; m++) {
+        double dm = dt * nodes[m];
+        for (size_t p = 0; p < N; p++) {
+            double s = 0.0;
+            for (int j = 0; j < M; j++) s += Q[m * M + j] * (FI[(size_t)j * N + p] + FE[(size_t)j * N + p]);
+            rhs[(size_t)(m - 1) * N + p] = U[p] + dt * s - dm * FI[(size_t)m * N + p];
+        }
+    }
+    int status = OR_OK;
+    for (int m = 1; m < M; m++) {
+        int cyc = 0;
+        double rho = 0.0;
+        int s = or_mg_solve(n, L->order, nu * (dt * nodes[m]), mg, U + (size_t)m * N, rhs + (size_t)(m - 1) * N,
+                            &cyc, &rho);
+        if (s != OR_OK && status == OR_OK) status = s;
+        if (st) {
+            st->total_solves++;
+            st->total_cycles += cyc;
+            if (cyc > st->max_cycles_seen) st->max_cycles_seen = cyc;
+        }
+    }
+    for (int m = 1; m < M; m++) or_lap_apply(n, L->order, 0.0, nu, U + (size_t)m * N, FI + (size_t)m * N);
+    if (st) st->total_sweeps++;
+    free(FE); free(rhs);
+    return status;
+}
+
+/*
  * One single-level SDC time step [t_n, t_n + dt] from u (overwritten with
  * the end value U_{M-1}, i.e. the last collocation node, eq. (9)).
  */
@@ -678,7 +732,9 @@ static int sdc_step(const or_problem *pb, double tn, double *u, or_stats *st)
             if (R <= pb->sdc_tol) break;
             if (k >= pb->max_sweeps) { status = OR_ENOCONV; break; }
         }
-        int s = or_sdc_sweep(L, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, U, FI, NULL, st);
+        int s = pb->node_parallel
+                    ? or_sdc_sweep_nodes(L, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, U, FI, st)
+                    : or_sdc_sweep(L, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, U, FI, NULL, st);
         if (s != OR_OK && status == OR_OK) status = s;
     }
     if (pb->sweeps > 0 && st)
@@ -848,6 +904,7 @@ static int check_problem(const or_problem *pb)
         if ((pb->lev[0].M - 1) % (pb->lev[1].M - 1) != 0) return OR_EINVAL;
     }
     if (!(pb->dt > 0.0) || !(pb->nu > 0.0) || pb->nsteps < 0) return OR_EINVAL;
+    if (pb->node_parallel != 0 && (pb->node_parallel != 1 || pb->nlevels != 1)) return OR_EINVAL;
     return OR_OK;
 }
 

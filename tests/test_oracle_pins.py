@@ -612,6 +612,77 @@ def test_pfasst_predictor_changes_the_start():
     assert np.array_equal(got, u0)
 
 
+# ----------------------------------------------------------------------------
+# Node-parallel SDC sweep (an addition: diagonal implicit part d_m = tau_m)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order,M", [(2, 3), (4, 5), (2, 5)])
+def test_node_parallel_sweep_scalar_twin(order, M):
+    """On a sum of sine modes every mode follows its own scalar recurrence
+    a_m <- (a_0 + dt sum_j q_mj (mu a_j + g_j) - dt tau_m mu a_m) / (1 - dt tau_m mu),
+    all m from the old iterate (mu = nu lambda_k, g the forcing of mode
+    (1,1,1)); three 3-D sweeps with tight multigrid match it mode by mode."""
+    n, nu, dt, t0, c = 15, 0.1, 0.1, 0.2, 3.0
+    modes = {(1, 1, 1): 0.7, (2, 1, 3): -0.4, (3, 3, 1): 0.25}
+    u0 = sum(a * inputs.sine_mode(n, k) for k, a in modes.items())
+    lv = oracle.level(n, order, M)
+    U, FI = oracle.spread(lv, nu, u0)
+    for _ in range(3):
+        s, _ = oracle.sdc_sweep_nodes(lv, TIGHT, nu, t0, dt, c, U, FI)
+        assert s == oracle.OK
+    t, Qex = exact_q(M)
+    Q = np.array(Qex.evalf(30).tolist(), dtype=float)
+    tau = np.array([float(x) for x in t])
+    for k, a0 in modes.items():
+        mu = nu * lam(order, n, k)
+        g = (-(np.sin(t0 + dt * tau) - c * nu * math.pi ** 2 * np.cos(t0 + dt * tau)) if k == (1, 1, 1)
+             else np.zeros(M))
+        a = np.full(M, a0)
+        for _ in range(3):
+            new = a.copy()
+            for m in range(1, M):
+                new[m] = (a0 + dt * Q[m] @ (mu * a + g) - dt * tau[m] * mu * a[m]) / (1 - dt * tau[m] * mu)
+            a = new
+        for m in range(M):
+            assert abs(project(U[m], k) - a[m]) < 1e-12 * max(1.0, abs(a0)), (k, m)
+
+
+def test_node_parallel_sweeps_reach_collocation():
+    """The collocation solution of eq. (6) is the fixed point of the
+    node-parallel sweep too: many sweeps land on the per-mode collocation
+    reference, and its step count differs from the sequential sweep's."""
+    from oracle import collocation as col
+    n, order, M, nu, dt = 7, 4, 5, 0.1, 0.05
+    modes = [(1, 2, 3, 0.8), (2, 2, 1, -0.4), (1, 1, 1, 0.3)]
+    u0 = inputs.modes_field(n, modes)
+    pb = oracle.problem([(n, order, M)], nu=nu, dt=dt, nsteps=2, sweeps=0, sdc_tol=1e-13, max_sweeps=200,
+                        mg=TIGHT, node_parallel=1)
+    u, st, stats = oracle.run(pb, u0)
+    assert st == oracle.OK
+    ref = col.field(n, col.coefficients(n, order, M, nu, 0.0, dt, 2, modes))
+    assert np.abs(u - ref).max() < 1e-12
+    pb.node_parallel = 0
+    v, st2, stats2 = oracle.run(pb, u0)
+    assert st2 == oracle.OK and stats2.total_sweeps < stats.total_sweeps
+
+
+def test_node_parallel_one_sweep_differs_from_sequential():
+    n, M, nu, dt = 7, 5, 0.1, 0.1
+    lv = oracle.level(n, 2, M)
+    u0 = inputs.random_smooth(n, 4)
+    U1, F1 = oracle.spread(lv, nu, u0)
+    U2, F2 = oracle.spread(lv, nu, u0)
+    oracle.sdc_sweep_nodes(lv, TIGHT, nu, 0.0, dt, 3.0, U1, F1)
+    oracle.sdc_sweep(lv, TIGHT, nu, 0.0, dt, 3.0, U2, F2)
+    assert np.abs(U1 - U2).max() > 1e-6
+
+
+def test_node_parallel_needs_one_level():
+    pb = oracle.problem([(15, 4, 5), (7, 2, 3)], node_parallel=1)
+    u, s, _ = oracle.run(pb, inputs.sine_product(15))
+    assert s == oracle.EINVAL
+
+
 def test_collocation_reference_matches_converged_oracle_sdc():
     """The per-mode collocation reference (oracle/collocation.py) equals many
     SDC sweeps of the 3-D oracle on sine-mode data (two steps)."""
