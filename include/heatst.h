@@ -130,6 +130,12 @@ typedef struct {
                                 fields live in device memory of its own, bound to the lane with
                                 hs_plan_bind_lane while it holds a problem (the serving core's
                                 plans); nslices must be 1 */
+    int32_t sdc_node_parallel; /* 1: node-parallel SDC sweeps (single level, not in the paper): the
+                                implicit part of the sweep is the diagonal tau_m instead of the
+                                implicit-Euler substeps, so every node's right-hand side comes from
+                                the previous iterate, (I - nu dt tau_m L_h) U_m = U_0 + dt (QF)_m
+                                - nu dt tau_m L_h U_m^old, and the M-1 solves of all lanes run as one
+                                batched multigrid solve; same collocation fixed point (eq. (6)) */
 } hs_problem;
 
 /* Per-lane statistics (hs_stats_read). */

@@ -41,7 +41,8 @@ struct LaneCtl {
     // statistics
     long long total_cycles;
     int32_t total_solves, max_cycles, total_sweeps, sweeps_step;
-    int32_t failed_solves, pad1;
+    int32_t failed_solves;
+    int32_t parent;              // node-parallel solver lane: its SDC lane, else -1
     long long level_cycles[2];   // cycles of the solves on SDC level 0 / 1
 };
 
@@ -272,8 +273,9 @@ hipError_t fas_interp(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int 
 // lane bookkeeping
 hipError_t begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int M1, hipStream_t s);
 hipError_t end_step(LaneCtl* ctl, int nlanes, hipStream_t s);
-hipError_t begin_solve(LaneCtl* ctl, int nlanes, hipStream_t s);
-hipError_t end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, int level, hipStream_t s);
+// lane states first .. first + nlanes - 1
+hipError_t begin_solve(LaneCtl* ctl, int first, int nlanes, hipStream_t s);
+hipError_t end_solve_fixed(LaneCtl* ctl, int first, int nlanes, int cycles, int level, hipStream_t s);
 hipError_t begin_sweep(LaneCtl* ctl, int nlanes, hipStream_t s);
 hipError_t set_lane(LaneCtl* ctl, int lane, double nu, double dt, double t0, double forcing_c,
                     int nsteps, int active, hipStream_t s);
@@ -283,6 +285,13 @@ hipError_t fill(double* dst, long long count, double v, hipStream_t s);
 // lanes whose SDC state is "converged" go back to "iterate" (PFASST keeps
 // every slice iterating until all of them meet the tolerance)
 hipError_t sdc_reopen(LaneCtl* ctl, int nlanes, hipStream_t s);
+// node-parallel SDC: solver lane (b, m) = nlanes + b (M - 1) + m - 1 solves
+// node m of SDC lane b.  np_lanes: mode 0 makes them idle children of their
+// lanes, mode 1 sets their a = nu (dt tau_m) for the current step.
+hipError_t np_lanes(LaneCtl* ctl, int nlanes, int M, int mode, hipStream_t s);
+// right-hand sides of the node-parallel sweep into SdcSeg::P (node m at
+// P + (m-1) N): U_0 + dt sum_j Q_mj (FI_j + g_j s) - dt tau_m FI_m
+hipError_t np_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, hipStream_t s);
 
 // kernel-level calls of the public ABI on lane-major packed user arrays
 hipError_t lap_apply(const SdcSeg* segs, int nseg, int nblk, int order, double alpha, double beta,

@@ -2526,19 +2526,73 @@ __global__ void k_end_step(LaneCtl* ctl, int nlanes)
     }
 }
 
-__global__ void k_begin_solve(LaneCtl* ctl, int nlanes)
+__global__ void k_begin_solve(LaneCtl* ctl, int first, int nlanes)
 {
-    int lane = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane >= nlanes) return;
+    int lane = first + blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= first + nlanes) return;
     LaneCtl& c = ctl[lane];
-    c.mg_state = c.sdc_state != 0 ? 3 : 0;
+    // a node-parallel solver lane solves while its SDC lane iterates
+    const int sdc = c.parent >= 0 ? ctl[c.parent].sdc_state : c.sdc_state;
+    c.mg_state = sdc != 0 ? 3 : 0;
     c.mg_cycle = 0;
 }
 
-__global__ void k_end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, int level)
+__global__ void k_np_lanes(LaneCtl* ctl, int nlanes, int M, int mode)
 {
-    int lane = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane >= nlanes) return;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nlanes * (M - 1)) return;
+    const int b = s / (M - 1), m = s % (M - 1) + 1;
+    LaneCtl& c = ctl[nlanes + s];
+    if (mode == 0) {
+        c.parent = b;
+        c.active = 1;
+        c.sdc_state = 0;
+        c.mg_state = 3;
+        c.status = 0;
+        c.bnorm = c.mg_rho = c.sdc_res = 0.0;
+        c.total_cycles = 0; c.total_solves = 0; c.max_cycles = 0; c.total_sweeps = 0;
+        c.sweeps_step = 0; c.failed_solves = 0;
+        c.level_cycles[0] = c.level_cycles[1] = 0;
+        c.a_user = 0.0;
+    } else {
+        const LaneCtl& p = ctl[b];
+        c.a_user = p.nu * (p.dt * c_lc.sdc[M].tau[m]);
+    }
+}
+
+// Right-hand sides of the node-parallel sweep (all from iterate k):
+//   rhs_m = U_0 + dt sum_j Q_mj (FI_j + g_j s) - dt tau_m FI_m,  m = 1..M-1,
+// written to P + (m-1) N, where solver lane (b, m) takes its right-hand side.
+__global__ void __launch_bounds__(HS_BLOCK) k_np_rhs(const SdcSeg* __restrict__ segs, int nseg, int nblk,
+                                                     const LaneCtl* __restrict__ ctl)
+{
+    int lb = xcd_remap(blockIdx.x, nblk);
+    int si = find_seg(segs, nseg, lb);
+    const SdcSeg sg = segs[si];
+    const LaneCtl& c = ctl[sg.lane];
+    if (c.sdc_state != 0) return;
+    int n = sg.n, M = sg.M;
+    Pos q = grid_pos(lb - sg.blk_begin, n);
+    if (!q.in) return;
+    const SdcConst& K = c_lc.sdc[M];
+    long long N = (long long)n * n * n;
+    long long p = lin(q.i, q.j, q.k, n);
+    double s = sval(sg.sig, q.i, q.j, q.k);
+    double dt = c.dt;
+    double F[HS_MAXM];
+    for (int j = 0; j < M; j++) F[j] = sg.FI[j * N + p] + c.g[sg.level][j] * s;
+    const double u0 = sg.U[p];
+    for (int m = 1; m < M; m++) {
+        double acc = 0.0;
+        for (int j = 0; j < M; j++) acc += K.Q[m][j] * F[j];
+        sg.P[(m - 1) * N + p] = (u0 + dt * acc) - (dt * K.tau[m]) * sg.FI[m * N + p];
+    }
+}
+
+__global__ void k_end_solve_fixed(LaneCtl* ctl, int first, int nlanes, int cycles, int level)
+{
+    int lane = first + blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= first + nlanes) return;
     LaneCtl& c = ctl[lane];
     if (c.mg_state == 0) finish_solve(c, cycles, 1, level);
 }
@@ -2564,6 +2618,7 @@ __global__ void k_set_lane(LaneCtl* ctl, int lane, double nu, double dt, double 
     c.total_cycles = 0; c.total_solves = 0; c.max_cycles = 0; c.total_sweeps = 0;
     c.sweeps_step = 0; c.failed_solves = 0; c.a_user = 0.0;
     c.level_cycles[0] = c.level_cycles[1] = 0;
+    c.parent = -1;
 }
 
 __global__ void k_set_a_user(LaneCtl* ctl, int lane, double a)
@@ -2741,8 +2796,10 @@ hipError_t sweep(LaneCtl* ctl, const GridSeg* segs, int nseg, int nblk, int orde
                  double* partials, hipStream_t s, int src, double tol, int max_cycles, EvPair ev)
 {
     if (nblk <= 0) return hipSuccess;
-    if (mode == 1) return sweep_launch<T, 1, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
-    if (src == 1) return sweep_launch<T, 0, 0, 0, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s);
+    if (mode == 1)
+        return sweep_launch<T, 1, 1, 0>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s, 0.0, 0, ev);
+    if (src == 1)
+        return sweep_launch<T, 0, 0, 0, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, 0, partials, s, 0.0, 0, ev);
     if (norm == 1)
         return sweep_launch<T, 0, 1, 1>(ctl, segs, nseg, nblk, order, a, 0, src_is_t, cycle, partials, s, 0.0, 0, ev);
     if (norm == 2)
@@ -2974,15 +3031,15 @@ hipError_t end_step(LaneCtl* ctl, int nlanes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t begin_solve(LaneCtl* ctl, int nlanes, hipStream_t s)
+hipError_t begin_solve(LaneCtl* ctl, int first, int nlanes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin_solve, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes);
+    hipLaunchKernelGGL(k_begin_solve, lanes_grid(nlanes), dim3(64), 0, s, ctl, first, nlanes);
     return hipGetLastError();
 }
 
-hipError_t end_solve_fixed(LaneCtl* ctl, int nlanes, int cycles, int level, hipStream_t s)
+hipError_t end_solve_fixed(LaneCtl* ctl, int first, int nlanes, int cycles, int level, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_end_solve_fixed, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes, cycles, level);
+    hipLaunchKernelGGL(k_end_solve_fixed, lanes_grid(nlanes), dim3(64), 0, s, ctl, first, nlanes, cycles, level);
     return hipGetLastError();
 }
 
@@ -3021,6 +3078,21 @@ hipError_t fill(double* dst, long long count, double v, hipStream_t s)
     long long blocks = (count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, dst, count, v);
+    return hipGetLastError();
+}
+
+hipError_t np_lanes(LaneCtl* ctl, int nlanes, int M, int mode, hipStream_t s)
+{
+    const int total = nlanes * (M - 1);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_np_lanes, lanes_grid(total), dim3(64), 0, s, ctl, nlanes, M, mode);
+    return hipGetLastError();
+}
+
+hipError_t np_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_np_rhs, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl);
     return hipGetLastError();
 }
 

@@ -216,6 +216,8 @@ struct hs_plan {
     hs_problem pb;
     std::vector<int> lane_n;
     int B = 0, nlev = 1;
+    int nctl = 0;                              // lane states: B SDC lanes, then node-parallel solver lanes
+    bool np = false;                           // node-parallel SDC sweeps (pb.sdc_node_parallel)
     int order[2] = {2, 2}, M[2] = {3, 3};
     bool mixed = false;
     size_t bytes = 0;
@@ -227,6 +229,7 @@ struct hs_plan {
     std::vector<LaneBufs> lanes;
     LaneSet all;
     LaneSet run;                               // the active lanes (what a step launches over)
+    LaneSet np_set;                            // node-parallel solver lanes (multigrid tables only)
     std::vector<int> active;                   // host view of every lane's active flag
     bool run_dirty = true;
     // device storage for the run set's tables, room for every lane in each
@@ -599,6 +602,44 @@ void lay_lane(hs_plan* P, int b, Bump& bump)
     }
 }
 
+// Node-parallel solver lane sl = B + b (M-1) + m - 1: its finest grid is node m
+// of SDC lane b (iterate U_m, right-hand side in b's P array at m - 1), with
+// a ping-pong buffer and a multigrid hierarchy of its own.
+void lay_np_lane(hs_plan* P, int sl, Bump& bump)
+{
+    const int M = P->M[0];
+    const int b = (sl - P->B) / (M - 1), m = (sl - P->B) % (M - 1) + 1;
+    const LaneBufs& pb = P->lanes[b];
+    LaneBufs& lb = P->lanes[sl];
+    lb = LaneBufs();
+    const int n = pb.n[0];
+    const long long N = pb.N[0];
+    lb.n[0] = n;
+    lb.N[0] = N;
+    lb.sig[0] = pb.sig[0];
+    lb.U[0] = pb.U[0] + m * N;
+    lb.FI[0] = lb.P[0] = nullptr;
+    lb.rhs[0] = pb.P[0] + (m - 1) * N;
+    lb.tmp[0] = bump.arr<double>(N);
+    lb.grids[0] = mg_grids(n, P->pb.mg.n_coarsest);
+    size_t G = lb.grids[0].size();
+    lb.gu[0].assign(G, nullptr); lb.gt[0].assign(G, nullptr); lb.gb[0].assign(G, nullptr);
+    lb.fu[0].assign(G, nullptr); lb.ft[0].assign(G, nullptr); lb.fb[0].assign(G, nullptr);
+    for (size_t l = 0; l < G; l++) {
+        long long Ng = cube(lb.grids[0][l]);
+        if (l > 0) {
+            lb.gu[0][l] = bump.arr<double>(Ng);
+            lb.gt[0][l] = bump.arr<double>(Ng);
+            lb.gb[0][l] = bump.arr<double>(Ng);
+        }
+        if (P->mixed) {
+            lb.fu[0][l] = bump.arr<float>(Ng);
+            lb.ft[0][l] = bump.arr<float>(Ng);
+            lb.fb[0][l] = bump.arr<float>(Ng);
+        }
+    }
+}
+
 // Bytes of lane b's fields when each lane lives in memory of its own.
 size_t lane_bytes_of(hs_plan* P, int b)
 {
@@ -617,7 +658,7 @@ size_t lane_bytes_of(hs_plan* P, int b)
 void layout(hs_plan* P, char* base)
 {
     Bump bump(base);
-    P->ctl = bump.arr<LaneCtl>(P->B);
+    P->ctl = bump.arr<LaneCtl>(P->nctl);
     // sine tables, one per distinct n
     P->sig.clear();
     for (int b = 0; b < P->B; b++)
@@ -625,7 +666,7 @@ void layout(hs_plan* P, char* base)
             int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
             if (!P->sig.count(n)) P->sig[n] = bump.arr<double>(n);
         }
-    P->lanes.assign(P->B, LaneBufs());
+    P->lanes.assign(P->nctl, LaneBufs());
     if (P->lane_base.size() != (size_t)P->B) P->lane_base.assign(P->B, nullptr);
     for (int b = 0; b < P->B; b++) {
         if (!P->pb.lane_memory) {
@@ -635,6 +676,7 @@ void layout(hs_plan* P, char* base)
             lay_lane(P, b, own);
         }
     }
+    for (int sl = P->B; sl < P->nctl; sl++) lay_np_lane(P, sl, bump);
     for (int L = 0; L < P->nlev; L++) {
         P->offs[L].h.assign(P->B, 0);
         long long o = 0;
@@ -652,6 +694,20 @@ void layout(hs_plan* P, char* base)
     P->all = LaneSet();
     for (int b = 0; b < P->B; b++) P->all.lanes.push_back(b);
     build_set(P, P->all, bump);
+    P->np_set = LaneSet();
+    if (P->np) {
+        for (int sl = P->B; sl < P->nctl; sl++) P->np_set.lanes.push_back(sl);
+        for (MgSet* S : {&P->np_set.mg64[0], &P->np_set.mg32[0]}) *S = MgSet();
+        build_mg<double>(P, P->np_set, 0, false, P->np_set.mg64[0]);
+        if (P->mixed) build_mg<float>(P, P->np_set, 0, true, P->np_set.mg32[0]);
+        for (MgSet* S : {&P->np_set.mg64[0], &P->np_set.mg32[0]}) {
+            for (auto& t : S->jac) finish_table(t, bump);
+            for (auto& t : S->pro) finish_table(t, bump);
+            for (auto& t : S->rfw) finish_table(t, bump);
+            finish_table(S->tail, bump);
+            finish_table(S->fine, bump);
+        }
+    }
     // run set storage: every table can hold all lanes
     for (int L = 0; L < P->nlev; L++) {
         for (int f = 0; f < 2; f++) {
@@ -715,6 +771,11 @@ void layout(hs_plan* P, char* base)
     };
     scan(P->all);
     for (auto& ls : P->single) scan(ls);
+    for (const MgSet* S : {&P->np_set.mg64[0], &P->np_set.mg32[0]}) {
+        upd(S->fine.nblk);
+        for (auto& t : S->jac) upd(t.nblk);
+        for (auto& t : S->pro) upd(t.nblk);
+    }
     P->partials = bump.arr<double>(2 * (size_t)maxblk);
     P->bytes = (bump.off + 255) & ~(size_t)255;
 }
@@ -784,6 +845,9 @@ hs_status validate(const hs_problem* pb)
     if (pb->nslices < 1) return HS_EINVAL;
     if (pb->pfasst_pred_sweeps < 0 || pb->pfasst_pred_sweeps > 64) return HS_EINVAL;
     if (pb->lane_memory != 0 && pb->lane_memory != 1) return HS_EINVAL;
+    if (pb->sdc_node_parallel != 0 &&
+        (pb->sdc_node_parallel != 1 || pb->nlevels != 1 || pb->nslices != 1 || pb->lane_memory))
+        return HS_EINVAL;
     if (pb->lane_memory && pb->nslices != 1) return HS_EINVAL;
     if (pb->nslices > 1) {
         if (pb->nslices != pb->batch || pb->nlevels != 2) return HS_EINVAL;
@@ -801,7 +865,7 @@ hs_status validate(const hs_problem* pb)
 
 hs_status read_ctl(hs_plan* P, hipStream_t s)
 {
-    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->B, hipMemcpyDeviceToHost, s));
+    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
     HS_TRY(hipStreamSynchronize(s));
     return HS_OK;
 }
@@ -1025,7 +1089,7 @@ hs_status read_ctl_ahead(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int
                          hipStream_t s)
 {
     if (!post) return read_ctl(P, s);
-    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->B, hipMemcpyDeviceToHost, s));
+    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
     HS_TRY(hipEventRecord(P->ev_ctl, s));
     hsk::MgArgs G = A;
     G.gate = 2;
@@ -1045,7 +1109,10 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     const hs_mg_desc& mg = P->pb.mg;
     int order = P->order[L];
     hsk::MgArgs A{L, m, mg.omega, node, 1};
-    HS_TRY(hsk::begin_solve(P->ctl, P->B, s));
+    // the lane states this solve decides: the SDC lanes, or the node-parallel solver lanes
+    const int c0 = &ls == &P->np_set ? P->B : 0;
+    const int cn = &ls == &P->np_set ? P->nctl - P->B : P->B;
+    HS_TRY(hsk::begin_solve(P->ctl, c0, cn, s));
     int& pred = m >= 0 ? P->cpred[L][m][std::min(P->sweep_k, hs_plan::PRED_K - 1)] : P->cpred_user;
     if (!P->mixed) {
         const MgSet& S = ls.mg64[L];
@@ -1053,7 +1120,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         if (mg.fixed_cycles > 0) {
             for (int c = 0; c < mg.fixed_cycles; c++)
                 HS_CHECK(vcycle<double>(P, S, order, A, mg.nu1, mg.nu2, 0, 0, &par, s));
-            HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, mg.fixed_cycles, L, s));
+            HS_TRY(hsk::end_solve_fixed(P->ctl, c0, cn, mg.fixed_cycles, L, s));
             return mg_finish(P, S, A, mg.nu1, mg.nu2, s);
         }
         const bool two = S.two && mg.nu1 >= 2;
@@ -1176,7 +1243,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         HS_CHECK(vcycle<float>(P, S32, order, A, mg.inner_nu1, mg.inner_nu2, 0, 0, &par32, s));
         HS_TRY(hsk::ir_update(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, A, s));
     }
-    if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, P->B, limit, L, s));
+    if (fixed) HS_TRY(hsk::end_solve_fixed(P->ctl, c0, cn, limit, L, s));
     return HS_OK;
 }
 
@@ -1205,6 +1272,15 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
         }
     }
     if (count) HS_TRY(hsk::begin_sweep(P->ctl, P->B, s));
+    if (P->np && L == 0) {
+        // node-parallel sweep: every node's right-hand side from iterate k, the
+        // M-1 solves of every lane as one batched multigrid solve, then F_I
+        HS_TRY(hsk::np_rhs(P->ctl, T.d, T.nseg(), T.nblk, s));
+        HS_CHECK(mg_solve(P, P->np_set, L, -1, 0, s, nullptr));
+        HS_TRY(hsk::fi_march(P->ctl, F.d, T.d, T.nseg(), F.nblk, P->order[L], 1, M, -1, 1, s));
+        P->sweep_k++;
+        return HS_OK;
+    }
     HS_TRY(hsk::make_rhs(P->ctl, T.d, T.nseg(), T.nblk, 0, 1, s));
     for (int m = 0; m + 1 < M; m++) {
         PostSolve post{&F, &T, P->order[L], m + 1, m + 2, m + 2 < M ? m + 1 : -1};
@@ -1276,6 +1352,7 @@ hs_status begin_step(hs_plan* P, hipStream_t s)
     HS_CHECK(refresh_run(P, s));
     P->sweep_k = 0;
     HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M[0], P->nlev > 1 ? P->M[1] : P->M[0], s));
+    if (P->np) HS_TRY(hsk::np_lanes(P->ctl, P->B, P->M[0], 1, s));
     const Table<SdcSeg>& T = P->run.sdc[0];
     HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[0], P->M[0] - 1, s));
     return HS_OK;
@@ -1406,6 +1483,8 @@ static void init_plan(hs_plan* P, const hs_problem* pb)
     P->lane_n.assign(P->B, pb->lev[0].n);
     if (pb->h_lane_n)
         for (int b = 0; b < P->B; b++) P->lane_n[b] = pb->h_lane_n[b];
+    P->np = pb->sdc_node_parallel != 0;
+    P->nctl = P->B + (P->np ? P->B * (P->M[0] - 1) : 0);
     P->pb.h_lane_n = nullptr;
     for (int L = 0; L < 2; L++)
         for (int m = 0; m < HS_MAXM; m++)
@@ -1447,7 +1526,7 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
     P->ws = (char*)d_ws;
     drop_cycle_graphs(P);
     layout(P, P->ws);
-    if (!P->h_ctl) HS_TRY(hipHostMalloc((void**)&P->h_ctl, sizeof(LaneCtl) * P->B, hipHostMallocDefault));
+    if (!P->h_ctl) HS_TRY(hipHostMalloc((void**)&P->h_ctl, sizeof(LaneCtl) * P->nctl, hipHostMallocDefault));
     if (!P->ev_ctl) HS_TRY(hipEventCreateWithFlags(&P->ev_ctl, hipEventDisableTiming));
     // sine tables sin(pi (i+1) h)
     std::map<const double*, int> sig;
@@ -1463,6 +1542,13 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
                               hipMemcpyHostToDevice, s));
     }
     if (!P->pb.lane_memory) HS_TRY(upload_set(P, P->all, s));   // else the lanes' pointers come later
+    for (const MgSet* S : {&P->np_set.mg64[0], &P->np_set.mg32[0]}) {
+        for (auto& t : S->jac) HS_TRY(upload(t, s));
+        for (auto& t : S->pro) HS_TRY(upload(t, s));
+        for (auto& t : S->rfw) HS_TRY(upload(t, s));
+        HS_TRY(upload(S->tail, s));
+        HS_TRY(upload(S->fine, s));
+    }
     for (auto& ls : P->single) HS_TRY(upload_set(P, ls, s));
     HS_TRY(upload(P->hf_dst, s));
     HS_TRY(upload(P->hf_src, s));
@@ -1479,6 +1565,7 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
         HS_TRY(hsk::set_lane(P->ctl, b, P->pb.nu, P->pb.dt, t0, P->pb.forcing_c, (int)nsteps, active, s));
         P->active[b] = active;
     }
+    if (P->np) HS_TRY(hsk::np_lanes(P->ctl, P->B, P->M[0], 0, s));
     P->run_dirty = true;
     HS_TRY(hipStreamSynchronize(s));
     P->bound = true;
@@ -2199,6 +2286,18 @@ extern "C" hs_status hs_stats_read(hs_plan* P, hs_lane_stats* out, void* stream)
     HS_CHECK(check_bound(P));
     if (!out) return HS_EINVAL;
     HS_CHECK(read_ctl(P, (hipStream_t)stream));
+    // a node-parallel lane's solves are done by its solver lanes
+    for (int sl = P->B; sl < P->nctl; sl++) {
+        const LaneCtl& c = P->h_ctl[sl];
+        LaneCtl& p = P->h_ctl[c.parent];
+        p.total_cycles += c.total_cycles;
+        p.total_solves += c.total_solves;
+        p.failed_solves += c.failed_solves;
+        p.max_cycles = std::max(p.max_cycles, c.max_cycles);
+        p.level_cycles[0] += c.level_cycles[0];
+        p.mg_rho = std::max(p.mg_rho, c.mg_rho);
+        if (c.status < p.status) p.status = c.status;
+    }
     for (int b = 0; b < P->B; b++) {
         const LaneCtl& c = P->h_ctl[b];
         hs_lane_stats& o = out[b];

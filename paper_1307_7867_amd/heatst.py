@@ -45,7 +45,8 @@ class ProblemDesc(C.Structure):
                 ("lev", LevelDesc * 2), ("mg", MgDesc), ("sweeps", C.c_int32),
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("batch", C.c_int32),
                 ("nslices", C.c_int32), ("h_lane_n", C.POINTER(C.c_int32)),
-                ("pfasst_pred_sweeps", C.c_int32), ("lane_memory", C.c_int32)]
+                ("pfasst_pred_sweeps", C.c_int32), ("lane_memory", C.c_int32),
+                ("sdc_node_parallel", C.c_int32)]
 
 
 class LaneStats(C.Structure):
@@ -237,6 +238,7 @@ class Problem:
     nslices: int = 1
     lane_n: list | None = None
     pfasst_pred_sweeps: int = 0
+    sdc_node_parallel: int = 0
 
     def desc(self):
         d = ProblemDesc()
@@ -252,6 +254,7 @@ class Problem:
         d.sweeps, d.sdc_tol, d.max_sweeps = self.sweeps, self.sdc_tol, self.max_sweeps
         d.batch, d.nslices = self.batch, self.nslices
         d.pfasst_pred_sweeps = self.pfasst_pred_sweeps
+        d.sdc_node_parallel = self.sdc_node_parallel
         keep = None
         if self.lane_n is not None:
             keep = (C.c_int32 * len(self.lane_n))(*self.lane_n)

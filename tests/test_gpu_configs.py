@@ -6,8 +6,9 @@
   mixed-precision workload uses); and the 255^3 configuration (4th order, 5
   nodes, dt = 0.02, 10 steps, SDC swept to a collocation residual of 1e-10)
   for seeds 0, 1, 2 against the exact collocation solution.
-* PFASST (section 1.1): 16 time slices at 63^3 / 31^3 and 2 slices at the
-  benchmark's 127^3 / 63^3, against the oracle's serial PFASST.
+* PFASST (section 1.1): 16 time slices at 63^3 / 31^3 (without and with the
+  coarse predictor) and 2 slices at the benchmark's 127^3 / 63^3, against the
+  oracle's serial PFASST.
 * The uneven batch of 64 instances with n drawn from {31, 63, 127}: every
   lane against the oracle (fixed cycle counts), and the tolerance-driven
   benchmark setting with every lane bitwise equal to the same instance
@@ -80,23 +81,21 @@ def _uneven_tol_ref(i):
 
 
 PF_CASES = {
-    # name: (nf, slices, iterations, fixed cycles, dt)
-    "pfasst16_63": (63, 16, 2, 2, 0.01),
-    "pfasst2_127": (127, 2, 1, 2, 0.01),
+    # name: (nf, slices, iterations, fixed cycles, dt, coarse predictor sweeps)
+    "pfasst16_63": (63, 16, 2, 2, 0.01, 0),
+    "pfasst16_63_pred": (63, 16, 2, 2, 0.01, 1),
+    "pfasst2_127": (127, 2, 1, 2, 0.01, 1),
 }
 
 
 def _pfasst_ref(name):
-    nf, P, K, cyc, dt = PF_CASES[name]
+    nf, P, K, cyc, dt, pred = PF_CASES[name]
     pb = oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, dt=dt, nsteps=P, sweeps=K,
                         mg=oracle.mg_params(fixed_cycles=cyc))
-    return oracle.pfasst_run(pb, P, inputs.sine_product(nf))
+    return oracle.pfasst(pb, P, inputs.sine_product(nf), pred_sweeps=pred)
 
 
-BACKGROUND_REFS = {
-    "pfasst16_63": lambda: _pfasst_ref("pfasst16_63"),
-    "pfasst2_127": lambda: _pfasst_ref("pfasst2_127"),
-}
+BACKGROUND_REFS = {name: (lambda name=name: _pfasst_ref(name)) for name in PF_CASES}
 # one background job per lane and setting
 for _i, _n in enumerate(UNEVEN_NS):
     BACKGROUND_REFS[f"uneven_fixed_{_i}"] = (lambda i=_i, n=_n: oracle.run(
@@ -104,7 +103,7 @@ for _i, _n in enumerate(UNEVEN_NS):
                        mg=oracle.mg_params(fixed_cycles=2)), uneven_u0(i, n))[0])
     if _n <= 63:
         BACKGROUND_REFS[f"uneven_tol_{_i}"] = (lambda i=_i: _uneven_tol_ref(i))
-BACKGROUND_LONG = {"pfasst16_63", "pfasst2_127"} | {f"uneven_fixed_{i}" for i, n in enumerate(UNEVEN_NS) if n == 127}
+BACKGROUND_LONG = set(PF_CASES) | {f"uneven_fixed_{i}" for i, n in enumerate(UNEVEN_NS) if n == 127}
 
 
 # ----------------------------------------------------------------------------
@@ -174,9 +173,9 @@ def test_config3_mixed_255_ten_steps(torch, seed):
 @pytest.mark.parametrize("name", sorted(PF_CASES))
 def test_pfasst_config_sizes_parity(torch, name):
     from paper_1307_7867_amd import heatst as hs
-    nf, P, K, cyc, dt = PF_CASES[name]
+    nf, P, K, cyc, dt, pred = PF_CASES[name]
     pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=((nf - 1) // 2, 2, 3), nu=0.1, dt=dt, nsteps=P,
-                    sweeps=K, fixed_cycles=cyc, batch=P, nslices=P)
+                    sweeps=K, fixed_cycles=cyc, batch=P, nslices=P, pfasst_pred_sweeps=pred)
     plan = hs.Plan(pb)
     plan.set_state(dev(torch, inputs.sine_product(nf)))
     plan.pfasst_run()

@@ -478,3 +478,71 @@ def test_lane_alone_equals_lane_in_batch(torch):
     alone.set_state(dev(torch, u0s[1]))
     alone.solve()
     assert np.array_equal(host(alone.get_state()).reshape(63, 63, 63), got[1])
+
+
+# ----------------------------------------------------------------------------
+# node-parallel SDC sweep: the M-1 solves of a sweep as one batched solve
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,order", [(3, 2), (5, 4), (5, 2)])
+def test_node_parallel_sweep_parity(torch, M, order):
+    """Node values after each of two node-parallel sweeps (fixed cycles) against
+    the oracle's or_sdc_sweep_nodes."""
+    hs = heatst_mod()
+    n, nu, dt, t0 = 31, 0.1, 0.05, 0.2
+    plan = hs.Plan(hs.Problem(n=n, order=order, nnodes=M, nu=nu, dt=dt, t0=t0, fixed_cycles=4,
+                              sdc_node_parallel=1))
+    u0 = inputs.random_smooth(n, 17)
+    plan.set_state(dev(torch, u0))
+    plan.begin_step()
+    lv = oracle.level(n, order, M)
+    U, FI = oracle.spread(lv, nu, u0)
+    mg = oracle.mg_params(fixed_cycles=4)
+    for k in range(2):
+        plan.sdc_sweep(0)
+        oracle.sdc_sweep_nodes(lv, mg, nu, t0, dt, 3.0, U, FI)
+        gU, gF, _, _ = plan.get_nodes(0)
+        assert rel(host(gU).reshape(U.shape), U) <= TOL, k
+        assert rel(host(gF).reshape(FI.shape), FI) <= 1e-11, k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_node_parallel_tolerance_mode_parity(torch, precision):
+    """Uneven lanes, sweeps until the collocation residual is <= 1e-10, solves
+    to 1e-12 (mixed: FP32 V(2,2) in FP64 refinement): same sweep counts as the
+    oracle and within 1e-12 (FP64) / 1e-10 (mixed) of it."""
+    hs = heatst_mod()
+    ns = [31, 15, 63]
+    prec = hs.HS_FP64 if precision == "fp64" else hs.HS_MIXED
+    pb = hs.Problem(n=31, order=2, nnodes=5, nu=0.1, dt=0.02, nsteps=2, sweeps=0, sdc_tol=1e-10, max_sweeps=60,
+                    tol=1e-12, max_cycles=60, batch=len(ns), lane_n=ns, precision=prec, sdc_node_parallel=1)
+    plan = hs.Plan(pb)
+    u0s = [inputs.random_smooth(n, 140 + i) for i, n in enumerate(ns)]
+    plan.set_state(dev(torch, np.concatenate([u.ravel() for u in u0s])))
+    plan.solve()
+    st, stats = plan.stats()
+    assert st == 0
+    got = split(host(plan.get_state()), ns)
+    for i, n in enumerate(ns):
+        mg = oracle.mg_params(tol=1e-12 if precision == "fp64" else 1e-13, max_cycles=200)
+        ref, s, ost = oracle.run(oracle.problem([(n, 2, 5)], nu=0.1, dt=0.02, nsteps=2, sweeps=0, sdc_tol=1e-10,
+                                                max_sweeps=60, mg=mg, node_parallel=1), u0s[i])
+        assert s == oracle.OK
+        assert stats[i]["total_sweeps"] == ost.total_sweeps, n
+        assert rel(got[i], ref) <= (TOL if precision == "fp64" else 1e-10), n
+
+
+def test_node_parallel_lane_alone_equals_in_batch(torch):
+    hs = heatst_mod()
+    ns = [31, 63]
+    kw = dict(order=4, nnodes=5, nu=0.1, dt=0.01, nsteps=2, sweeps=3, tol=1e-12, max_cycles=60,
+              sdc_node_parallel=1)
+    u0s = [inputs.random_smooth(n, 150 + i) for i, n in enumerate(ns)]
+    plan = hs.Plan(hs.Problem(n=31, batch=2, lane_n=ns, **kw))
+    plan.set_state(dev(torch, np.concatenate([u.ravel() for u in u0s])))
+    plan.solve()
+    got = split(host(plan.get_state()), ns)
+    alone = hs.Plan(hs.Problem(n=63, **kw))
+    alone.set_state(dev(torch, u0s[1]))
+    alone.solve()
+    assert np.array_equal(host(alone.get_state()).reshape(63, 63, 63), got[1])
