@@ -1,28 +1,41 @@
 #!/usr/bin/env python3
 """Benchmark of the space-time heat solver's hot path on one MI355X.
 
-Workload (two-level MLSDC with FAS, FP64): fine level 127^3 with the wide
-4th-order stencil and 5 Gauss-Lobatto nodes, coarse level 63^3 with the
-7-point stencil and 3 nodes, nu = 0.1, dt = 0.05, 3 MLSDC iterations per
-step, every implicit substep solved by V(2,1) multigrid cycles (weighted
-Jacobi 6/7, full weighting, trilinear, exact 3^3 solve) to a relative
-residual of 1e-12; initial value u0 = sin(pi x) sin(pi y) sin(pi z) and
-the consistent manufactured forcing (c = 3).  Inputs are synthetic and
-generated on the host, then copied to HBM before timing.
+Headline workload (the largest FP64 configuration that runs on one GPU):
+PFASST with 16 concurrent time slices as one batch, two-level MLSDC per
+slice -- fine level 127^3 with the wide 4th-order stencil and 5
+Gauss-Lobatto nodes, coarse level 63^3 with the 7-point stencil and 3
+nodes -- nu = 0.1, dt = 0.01, a serial coarse predictor (one coarse sweep
+per slice) and then 4 PFASST iterations per block of 16 steps, every
+implicit substep solved by V(2,1) multigrid cycles (weighted Jacobi
+6/7, full weighting, trilinear, exact 3^3 solve) to a relative residual of
+1e-12; initial value u0 = sin(pi x) sin(pi y) sin(pi z) and the consistent
+manufactured forcing (c = 3).  Inputs are synthetic, generated on the host
+and copied to HBM before timing.
 
-A step is one MLSDC time step.  --steps K time steps are timed (K = 20 is
-the run to T = 1); --warmup W steps run first and the state is then reset.
+A step is one PFASST block (16 time slices, 4 iterations).  --steps K
+blocks are timed back to back (16 K time steps); --warmup W blocks run first
+and the state is then reset.
 
-value = space-time DOF-updates/s = 127^3 * (5 - 1) substeps * 3 iterations
-        * K / elapsed.
+value = space-time DOF-updates/s = 127^3 * (5 - 1) substeps * 4 iterations
+        * 16 slices * K / elapsed.
 
-roofline: the dominant kernel, the finest-grid weighted-Jacobi sweep
-(k_sweep<double, 4, 0, 1, 0, 0> on 127^3), timed with HIP events on its stream
-(one launch per sweep, the solver's launch configuration); algorithmic
-bytes 24 per grid point (read u, b; write u').
+roofline: the dominant kernel of the batched fine sweeps, k_pjac<double, 4>
+(prolongation + first post-smoothing sweep) on the 16 x 127^3 finest grids,
+timed live inside the timed run with HIP events that record each launch's
+own start and end on the stream it runs on (hs_plan_timer); algorithmic
+bytes 25 per grid point of every lane the launch updates (read u, b and the
+coarse correction at 1/8 density, write u'), summed from the lanes' own
+fine-level cycle counts.
 
-cpu_baseline: the CPU oracle (plain serial C) on one MLSDC iteration of the
-first step of the same workload.
+cpu_baseline: the CPU oracle (plain serial C, one core) on one MLSDC
+iteration of the first slice of the same workload.
+
+extra: the other configurations as records of their own -- 15^3 SDC
+latency, the 127^3/63^3 MLSDC run with the coarse/fine sweep-time ratio,
+the eq. (10) PFASST model, node-parallel against sequential SDC sweeps,
+the 255^3 mixed-precision run, the uneven batch of 64 instances, the 511^3
+kernel microbenchmark and a short serving stream -- unless --no-extras.
 """
 import argparse
 import hashlib
@@ -36,16 +49,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-NF, NC, MF, MC, ITERS = 127, 63, 5, 3, 3
+NF, NC, MF, MC, ITERS, SLICES, DT = 127, 63, 5, 3, 4, 16, 0.01
+PJAC_BYTES = 25          # per fine grid point: read u, b (16), coarse e at 1/8 density (1), write u' (8)
 KERNEL_SRC = os.path.join(ROOT, "paper_1307_7867_amd", "csrc", "hs_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_fp64_order4_127.traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pjac_fp64_order4_pfasst16.traffic.json")
 
 
-def problem(hs, fused_sweeps=1, cycle_graphs=0):
-    return hs.Problem(n=NF, order=4, nnodes=MF, coarse=(NC, 2, MC), nu=0.1, dt=0.05, t0=0.0,
-                      forcing_c=3.0, nsteps=20, sweeps=ITERS, nu1=2, nu2=1, omega=6.0 / 7.0,
-                      n_coarsest=3, tol=1e-12, max_cycles=60, fused_sweeps=fused_sweeps,
-                      cycle_graphs=cycle_graphs)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+PRED = 1                 # coarse sweeps per slice of the serial coarse predictor
+
+
+def problem(hs, nblocks, **kw):
+    return hs.Problem(n=NF, order=4, nnodes=MF, coarse=(NC, 2, MC), nu=0.1, dt=DT, t0=0.0, forcing_c=3.0,
+                      nsteps=SLICES * nblocks, sweeps=ITERS, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest=3,
+                      tol=1e-12, max_cycles=60, batch=SLICES, nslices=SLICES, pfasst_pred_sweeps=PRED, **kw)
 
 
 def kernel_hash():
@@ -53,154 +73,100 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measure_jacobi(torch, hs, plan, n, sweeps_a=10, sweeps_b=60):
-    """Average duration of one finest-grid Jacobi launch, from HIP events on
-    the stream the launches go to (difference of two launch counts removes
-    the fixed cost of the call).  About 2 ms of device work (fills of a
-    1 GiB buffer) is queued ahead of the first event, so the host has queued
-    every timed launch before the device reaches them: the figure is the
-    device's back-to-back time, not the host's launch rate."""
-    N = n ** 3
-    g = torch.Generator(device="cuda").manual_seed(0)
-    u = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
-    b = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
-    tmp = torch.empty_like(u)
-    pad = torch.empty(2 ** 27, dtype=torch.float64, device="cuda")
-    a = 0.1 * 0.05 * 0.17267316464601146
-    s = torch.cuda.current_stream()
-    plan.smooth(u, b, tmp, a, 2)   # table upload and warm-up
-    times = []
-    for k in (sweeps_a, sweeps_b):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.synchronize()
-        for _ in range(10):
-            pad.fill_(1.0)
-        e0.record(s)
-        plan.smooth(u, b, tmp, a, k)
-        e1.record(s)
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
-    return (times[1] - times[0]) / (sweeps_b - sweeps_a) * 1e-3   # seconds per launch
-
-
-def cpu_baseline(sample_iters=1):
+def cpu_baseline():
+    """One MLSDC iteration of slice 0 of the first block, as the GPU runs it
+    (fine sweep of 4 multigrid solves to 1e-12 from the spread initial value,
+    restriction + tau, coarse sweep, interpolation), by the serial C oracle."""
     import numpy as np
     import oracle
     from paper_1307_7867_amd import inputs
-    pb = oracle.problem([(NF, 4, MF), (NC, 2, MC)], nu=0.1, dt=0.05, nsteps=1, sweeps=1,
-                        forcing_c=3.0, mg=oracle.mg_params(tol=1e-12, max_cycles=60))
+    pb = oracle.problem([(NF, 4, MF), (NC, 2, MC)], nu=0.1, dt=DT, nsteps=1, sweeps=1, forcing_c=3.0,
+                        mg=oracle.mg_params(tol=1e-12, max_cycles=60))
     u0 = inputs.sine_product(NF)
     Uf, FIf = oracle.spread(pb.lev[0], pb.nu, u0)
     Uc = np.zeros((MC, NC, NC, NC))
     FIc, Ut, tau = np.zeros_like(Uc), np.zeros_like(Uc), np.zeros_like(Uc)
     t0 = time.perf_counter()
-    for _ in range(sample_iters):
-        oracle.mlsdc_iter(pb, 0.0, Uf, FIf, Uc, FIc, Ut, tau)
+    s, st = oracle.mlsdc_iter(pb, 0.0, Uf, FIf, Uc, FIc, Ut, tau)
     el = time.perf_counter() - t0
-    return {"value": NF ** 3 * (MF - 1) * sample_iters / el, "unit": "DOF-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{sample_iters} MLSDC iteration(s) of the first time step of the same workload "
-                      f"(fine sweep with 4 multigrid solves to 1e-12, FAS restriction, coarse sweep, "
-                      f"interpolation), serial C, {el:.1f} s"}
+    cps = st.total_cycles / max(1, st.total_solves)
+    return {"value": NF ** 3 * (MF - 1) / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 MLSDC iteration of slice 0 of the first block of the same workload (fine sweep of "
+                      f"{st.total_solves} multigrid solves to 1e-12 from the spread initial value, "
+                      f"{cps:.1f} V-cycles per solve; FAS restriction, coarse sweep, interpolation), "
+                      f"serial C, {el:.1f} s",
+            "vcycles_per_solve": cps, "seconds": el}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm511", action="store_true", help="skip the 511^3 Jacobi measurement")
-    ap.add_argument("--workload", default="mlsdc127",
-                    choices=["mlsdc127", "mixed255", "pfasst16", "uneven64", "serving"],
-                    help="mlsdc127 (default): the headline two-level MLSDC run; the others are the "
-                         "mixed-precision, PFASST-slice, uneven-batch and serving workloads")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--sdc-tol", type=float, default=1e-10)
-    ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--rates", default="0.5,1.0,1.5")
-    ap.add_argument("--max-n", type=int, default=511)
-    ap.add_argument("--budget-gb", type=float, default=200.0)
-    ap.add_argument("--fused-sweeps", type=int, default=1, choices=[1, 2],
-                    help="2: run the finest grid's first two pre-smoothing sweeps as one pass")
-    ap.add_argument("--cycle-graphs", type=int, default=0, choices=[0, 1],
-                    help="1: replay the predicted cycles of each solve from HIP graphs (measured "
-                         "slower than launching every kernel from the host)")
-    ap.add_argument("--calibration-copy", action="store_true",
-                    help="first run a plain 512 MiB device copy (reference for byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by lanes or PFASST slices across GPUs only in design).",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_1307_7867_amd import heatst as hs
-    from paper_1307_7867_amd import inputs
-
-    torch.cuda.set_device(0)
-    if args.calibration_copy:
-        src = torch.ones(64 * 2**20, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    if args.workload != "mlsdc127":
-        from paper_1307_7867_amd import workloads
-        out = getattr(workloads, args.workload)(args)
-        print(json.dumps(out), flush=True)
-        return
-    pb = problem(hs, args.fused_sweeps, args.cycle_graphs)
-    plan = hs.Plan(pb)
+def headline(args, torch, hs, inputs):
     u0 = torch.from_numpy(inputs.sine_product(NF).ravel()).cuda()
-
-    plan.set_state(u0)
+    warm = hs.Plan(problem(hs, 1))
     for _ in range(args.warmup):
-        plan.step()
+        warm.set_state(u0)
+        warm.pfasst_run()
     torch.cuda.synchronize()
-    plan.set_state(u0)            # timed run starts at t = 0
+    del warm
+    plan = hs.Plan(problem(hs, args.steps))
+    plan.set_state(u0)
+    plan.timer(hs.HS_TIMER_PJAC, 8192)
     torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} MLSDC steps of {NF}^3/{NC}^3", file=sys.stderr, flush=True)
+    log(f"timing {args.steps} PFASST block(s) of {SLICES} slices x {ITERS} iterations, {NF}^3/{NC}^3")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.step()
+    plan.pfasst_run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    launches, kms = plan.timer_read()
     st, stats = plan.stats()
-    hs.check(st, "bench solve")
+    hs.check(st, "bench PFASST run")
     u = plan.get_state().cpu().numpy().reshape(NF, NF, NF)
-    T = args.steps * pb.dt
+    T = args.steps * SLICES * DT
+    import numpy as np
     ex = inputs.sine_product(NF) * math.cos(T)
     err = float(np.abs(u - ex).max() / np.abs(ex).max())
-    dof_updates = NF ** 3 * (MF - 1) * ITERS * args.steps
+    fine_lane_cycles = sum(s["level_cycles"][0] for s in stats)
+    fine_solves = SLICES * args.steps * ITERS * (MF - 1)
+    dof_updates = NF ** 3 * (MF - 1) * ITERS * SLICES * args.steps
     value = dof_updates / elapsed
-    s0 = stats[0]
-    print(f"[bench] {elapsed:.3f} s, {value:.3e} DOF-updates/s, V-cycles {s0['total_cycles']} over "
-          f"{s0['total_solves']} solves", file=sys.stderr, flush=True)
-
-    # dominant kernel: finest-grid Jacobi sweep
-    jac_s = measure_jacobi(torch, hs, plan, NF)
-    jac_bytes = 24 * NF ** 3
-    achieved = jac_bytes / jac_s / 1e9
+    pjac_bytes = PJAC_BYTES * NF ** 3 * fine_lane_cycles
+    achieved = pjac_bytes / (kms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
         if rec.get("kernel_src_sha") == kernel_hash():
             traffic = rec.get("bytes_per_launch")
-    extra = {}
-    if not args.no_hbm511:
-        big = hs.Plan(hs.Problem(n=511, order=4, nnodes=2, nu=0.1, dt=0.05, sweeps=1, fixed_cycles=1))
-        js = measure_jacobi(torch, hs, big, 511, 4, 24)
-        extra["jacobi_511_fp64_order4"] = {"us_per_launch": js * 1e6,
-                                           "GBps_algorithmic": 24 * 511 ** 3 / js / 1e9,
-                                           "frac_of_8TBps": 24 * 511 ** 3 / js / 1e9 / PEAK_HBM_GBS}
-        del big
-        torch.cuda.empty_cache()
+    log(f"{elapsed:.3f} s, {value:.3e} DOF-updates/s, k_pjac {launches} launches {kms / launches * 1e3:.1f} us, "
+        f"{achieved:.0f} GB/s")
+    del plan
+    shapes = {f"{n}^3 order {o} x{b}": list(hs.tune_lookup(n, o, 0, b))
+              for n, o, b in ((127, 4, SLICES), (63, 4, SLICES), (31, 4, SLICES), (63, 2, 1), (31, 2, 1))}
+    builtin_s = None
+    if not args.no_builtin_compare:
+        builtin_s = builtin_shapes_run(args, torch, hs, u0)
+    out = _headline_record(args, elapsed, value, achieved, traffic, launches, kms, pjac_bytes, fine_lane_cycles,
+                           fine_solves, err, stats, shapes, builtin_s)
+    return out
 
-    out = {
+
+def builtin_shapes_run(args, torch, hs, u0):
+    """The same run with the built-in launch shapes: what the autotuner's table gains."""
+    hs.tune_clear()
+    base = hs.Plan(problem(hs, args.steps))
+    base.set_state(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    base.pfasst_run()
+    torch.cuda.synchronize()
+    builtin_s = time.perf_counter() - t0
+    del base
+    if os.path.exists(hs.TUNE_CACHE):
+        hs.tune_load(hs.TUNE_CACHE)
+    log(f"built-in launch shapes: {builtin_s:.3f} s")
+    return builtin_s
+
+
+def _headline_record(args, elapsed, value, achieved, traffic, launches, kms, pjac_bytes, fine_lane_cycles,
+                     fine_solves, err, stats, shapes, builtin_s):
+    return {
         "metric": "DOF-updates/s",
         "value": value,
         "unit": "DOF-updates/s",
@@ -213,22 +179,88 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "two-level MLSDC + FAS, FP64: fine 127^3 4th-order 5 Lobatto nodes, "
-                               "coarse 63^3 2nd-order 3 nodes, nu=0.1, dt=0.05, 3 iterations/step, "
-                               "V(2,1) Jacobi 6/7 to 3^3, rel. residual 1e-12",
-                   "fine_n": NF, "coarse_n": NC, "dt": pb.dt, "iterations_per_step": ITERS,
-                   "mg_tol": pb.tol, "fused_sweeps": pb.fused_sweeps, "cycle_graphs": pb.cycle_graphs},
-        "roofline": {"bound": "hbm", "kernel": "k_sweep<double, 4, 0, 1, 0, 0> (finest-grid weighted Jacobi) on 127^3",
-                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "us_per_launch": jac_s * 1e6, "algorithmic_bytes_per_launch": jac_bytes},
+        "config": {"workload": "PFASST, 16 time slices batched on one GPU x 5 Lobatto nodes, two-level MLSDC + "
+                               "FAS per slice, FP64: fine 127^3 4th-order, coarse 63^3 2nd-order 3 nodes, nu=0.1, "
+                               "dt=0.01, coarse predictor + 4 PFASST iterations per block of 16 steps, V(2,1) "
+                               "Jacobi 6/7 to 3^3, rel. residual 1e-12",
+                   "fine_n": NF, "coarse_n": NC, "slices": SLICES, "dt": DT, "iterations": ITERS,
+                   "blocks": args.steps, "mg_tol": 1e-12, "predictor_coarse_sweeps": PRED},
+        "roofline": {"bound": "hbm", "kernel": "k_pjac<double, 4> on the 16 x 127^3 finest grids (batched)",
+                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic, "launches": launches, "us_per_launch": kms / launches * 1e3,
+                     "algorithmic_bytes_per_launch": pjac_bytes / launches,
+                     "algorithmic_bytes_per_point": PJAC_BYTES, "lane_cycles": fine_lane_cycles},
         "error_vs_exact": err,
-        "vcycles": s0["total_cycles"],
-        "solves": s0["total_solves"],
-        "extra": extra,
+        "tuning": {"shapes_zb_zb_rfw": shapes, "seconds_builtin_shapes": builtin_s,
+                   "gain_over_builtin": builtin_s / elapsed if builtin_s else None},
+        "fine_vcycles_per_solve": fine_lane_cycles / fine_solves,
+        "coarse_vcycles": sum(s["level_cycles"][1] for s in stats),
     }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4, help="PFASST blocks (16 time steps each) timed")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline PFASST measurement")
+    ap.add_argument("--no-builtin-compare", action="store_true",
+                    help="skip the second headline run with the built-in launch shapes")
+    ap.add_argument("--plain-capacity", type=float, default=0.0,
+                    help="serving: the plain path's solves/s (skips measuring it)")
+    ap.add_argument("--workload", default="pfasst16",
+                    choices=["pfasst16", "sdc15", "mlsdc127", "mixed255", "uneven64", "serving", "micro511",
+                             "eq10", "sdcnp127"],
+                    help="pfasst16 (default): the headline line with every other workload as an extra; "
+                         "any other name runs that workload alone")
+    ap.add_argument("--seeds", default="0", help="mixed255: comma-separated seeds")
+    ap.add_argument("--sdc-tol", type=float, default=1e-10)
+    ap.add_argument("--pfasst-max-iters", type=int, default=40,
+                    help="eq10: cap on PFASST iterations to the 1e-10 residual")
+    ap.add_argument("--requests", type=int, default=16)
+    ap.add_argument("--rates", default="1.0")
+    ap.add_argument("--max-n", type=int, default=255)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run a plain 512 MiB device copy (reference for byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by lanes or PFASST slices across GPUs only in design).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1307_7867_amd import heatst as hs
+    from paper_1307_7867_amd import inputs
+    from paper_1307_7867_amd import workloads
+
+    torch.cuda.set_device(0)
+    if args.calibration_copy:
+        src = torch.ones(64 * 2**20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload != "pfasst16":
+        out = getattr(workloads, args.workload)(args)
+        print(json.dumps(out), flush=True)
+        return
+    out = headline(args, torch, hs, inputs)
+    if not args.no_extras:
+        extra = {}
+        for name in ("sdc15", "mlsdc127", "eq10", "sdcnp127", "mixed255", "uneven64", "micro511", "serving"):
+            log(f"extra: {name}")
+            t0 = time.perf_counter()
+            extra[name] = getattr(workloads, name)(args)
+            extra[name]["wall_s"] = time.perf_counter() - t0
+            log(f"extra {name}: {extra[name]['wall_s']:.1f} s")
+            torch.cuda.empty_cache()
+        out["extra"] = extra
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 

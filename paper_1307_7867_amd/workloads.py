@@ -1,26 +1,37 @@
-"""Benchmark workloads besides the headline MLSDC run (bench.py --workload).
+"""Benchmark workloads besides the headline PFASST run (bench.py).
 
 Each function takes the parsed bench.py arguments and returns one JSON-able
 record.  Inputs are synthetic (paper_1307_7867_amd.inputs), generated on the
 host and copied to HBM before any timed region.
 
+  sdc15     15^3, 2nd order, 3 nodes, dt 0.125, 8 steps to T = 1, 4 sweeps,
+            V(2,1) to 1e-12: per-step latency (launch-bound).
+  mlsdc127  two-level MLSDC, fine 127^3 4th order 5 nodes, coarse 63^3 2nd
+            order 3 nodes, dt 0.05, 20 steps, 3 iterations: DOF-updates/s and
+            the coarse/fine sweep-time ratio alpha of eq. (10).
+  eq10      the PFASST speedup model of eq. (10) with GPU-measured inputs:
+            alpha, beta, K_S (serial SDC sweeps per step to the 1e-10
+            residual) and K_P (PFASST iterations to it, 16 slices, with and
+            without the coarse predictor); beside it the measured time of the
+            16 batched slices against 16 serial SDC steps.
+  sdcnp127  127^3 SDC to the 1e-10 residual with sequential sweeps and with
+            node-parallel sweeps (the M-1 solves of a sweep as one batch).
   mixed255  255^3, 4th order, 5 nodes, dt 0.02, 10 steps, 8 random sine
             modes: FP32 V(2,2) inside FP64 refinement to 1e-12 relative
             residual, against FP64 V(2,1) to 1e-12; SDC sweeps until the
             collocation residual is below --sdc-tol (1e-10).
-  pfasst16  16 PFASST time slices x 5 nodes, 127^3 (4th order) / 63^3 (2nd
-            order), dt 0.01, 4 iterations, every phase one batched launch
-            sequence over the slices; against 16 serial MLSDC steps; plus the
-            coarse-to-fine sweep time ratio alpha of the paper's speedup model.
   uneven64  64 independent instances with n drawn from {31, 63, 127}: one
             batched plan against one plan per instance run in turn.
-  serving   Poisson stream of requests (n from {31..511} weighted 8:4:2:1:1,
-            nu, dt, steps random) through the serving core (mixed precision)
-            against the plain path (one request at a time, FP64 V-cycles).
+  micro511  single-kernel rates on the finest grid of the 511^3 hierarchy
+            (FP64 and the FP32 inner cycles of mixed precision) and of a
+            batch of two 255^3 grids, from HIP events on each launch.
+  serving   Poisson stream of requests (n from {31..255} by default,
+            weighted 8:4:2:1, nu, dt, steps random) through the serving core
+            (mixed precision) and, replayed with the same arrival times, the
+            plain path (one request at a time, FP64 V-cycles); both measured.
 """
 from __future__ import annotations
 
-import math
 import sys
 import time
 
@@ -41,112 +52,235 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
 
 
+def _timed(fn):
+    _sync()
+    t0 = time.perf_counter()
+    fn()
+    _sync()
+    return time.perf_counter() - t0
+
+
+# ----------------------------------------------------------------------------
+# configuration 1: 15^3 SDC latency
+# ----------------------------------------------------------------------------
+
+def sdc15(args):
+    from . import heatst as hs
+    from . import inputs
+    n = 15
+    pb = hs.Problem(n=n, order=2, nnodes=3, nu=0.1, dt=0.125, nsteps=8, sweeps=4, tol=1e-12)
+    plan = hs.Plan(pb)
+    u0 = _dev(inputs.sine_product(n))
+    plan.set_state(u0)
+    plan.solve()
+    per = []
+    for _ in range(5):
+        plan.set_state(u0)
+        per.append(_timed(plan.solve) / 8)
+    st, stats = plan.stats()
+    return {"workload": "sdc15", "metric": "ms per SDC step", "value": float(np.median(per)) * 1e3,
+            "unit": "ms", "steps": 8, "runs": len(per), "min_ms": min(per) * 1e3,
+            "vcycles_per_solve": stats[0]["total_cycles"] / stats[0]["total_solves"]}
+
+
+# ----------------------------------------------------------------------------
+# configuration 2: two-level MLSDC at 127^3 / 63^3, alpha
+# ----------------------------------------------------------------------------
+
+def _sweep_alpha(hs, nf, nc, dt, reps=3):
+    """alpha = time of one coarse sweep / time of one fine sweep (one lane);
+    beta = time of restriction + interpolation / time of one fine sweep."""
+    from . import inputs
+    pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=1, sweeps=1,
+                    tol=1e-12, max_cycles=60)
+    plan = hs.Plan(pb)
+    plan.set_state(_dev(inputs.sine_product(nf)))
+    tf, tc, tr = [], [], []
+    for _ in range(reps):
+        plan.begin_step()
+        plan.sdc_sweep(0)
+        tr.append(_timed(plan.fas_restrict))
+        tf.append(_timed(lambda: plan.sdc_sweep(0)))
+        tc.append(_timed(lambda: plan.sdc_sweep(1)))
+        tr[-1] += _timed(plan.fas_interp)
+    f, c, r = min(tf), min(tc), min(tr)
+    return c / f, r / f, {"fine_sweep_ms": f * 1e3, "coarse_sweep_ms": c * 1e3, "transfer_ms": r * 1e3}
+
+
+def mlsdc127(args):
+    from . import heatst as hs
+    from . import inputs
+    nf, nc, K, steps = 127, 63, 3, 20
+    pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=0.05, nsteps=steps, sweeps=K,
+                    tol=1e-12, max_cycles=60)
+    plan = hs.Plan(pb)
+    u0 = _dev(inputs.sine_product(nf))
+    plan.set_state(u0)
+    plan.step()
+    plan.set_state(u0)
+    el = _timed(plan.solve)
+    st, stats = plan.stats()
+    hs.check(st, "mlsdc127")
+    u = plan.get_state().cpu().numpy().reshape(nf, nf, nf)
+    ex = inputs.sine_product(nf) * np.cos(steps * 0.05)
+    del plan
+    alpha, beta, t = _sweep_alpha(hs, nf, nc, 0.05)
+    return {"workload": "mlsdc127", "metric": "DOF-updates/s", "value": nf ** 3 * 4 * K * steps / el,
+            "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
+            "vcycles": stats[0]["total_cycles"], "solves": stats[0]["total_solves"],
+            "error_vs_exact": float(np.abs(u - ex).max() / np.abs(ex).max()),
+            "alpha_coarse_over_fine_sweep": alpha, **t}
+
+
+# ----------------------------------------------------------------------------
+# eq. (10): the PFASST speedup model with GPU-measured inputs
+# ----------------------------------------------------------------------------
+
+def eq10(args):
+    """s(P) = K_S P / (P alpha + K_P (1 + alpha + beta)) (eq. (10)) for P = 16
+    slices of the 127^3/63^3 problem at dt = 0.01 to the residual 1e-10, with
+    alpha, beta, K_S and K_P measured here; and the one-GPU time ratio of 16
+    serial SDC steps to the 16 batched PFASST slices (each to 1e-10)."""
+    from . import heatst as hs
+    from . import inputs
+    nf, nc, P, dt, tol = 127, 63, 16, 0.01, 1e-10
+    u0 = _dev(inputs.sine_product(nf))
+    # serial single-level SDC on the fine problem: K_S
+    sdc = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, nu=0.1, dt=dt, nsteps=P, sweeps=0, sdc_tol=tol,
+                             max_sweeps=30, tol=1e-12, max_cycles=60))
+    sdc.set_state(u0)
+    sdc.step()
+    sdc.set_state(u0)
+    t_sdc = _timed(sdc.solve)
+    st, stats = sdc.stats()
+    hs.check(st, "eq10 serial SDC")
+    K_S = stats[0]["total_sweeps"] / P
+    u_sdc = sdc.get_state().cpu().numpy()
+    del sdc
+    # serial MLSDC to the same residual (the paper's P_T = 1 point)
+    ml = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P, sweeps=0,
+                            sdc_tol=tol, max_sweeps=30, tol=1e-12, max_cycles=60))
+    ml.set_state(u0)
+    ml.step()
+    ml.set_state(u0)
+    t_ml = _timed(ml.solve)
+    st, mstats = ml.stats()
+    hs.check(st, "eq10 serial MLSDC")
+    del ml
+    alpha, beta, t = _sweep_alpha(hs, nf, nc, dt)
+    rows = {}
+    for pred in (0, 1):
+        pf = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P, sweeps=0,
+                                sdc_tol=tol, max_sweeps=args.pfasst_max_iters, tol=1e-12, max_cycles=60, batch=P,
+                                nslices=P, pfasst_pred_sweeps=pred))
+        pf.set_state(u0)
+        pf.pfasst_run()
+        pf.set_state(u0)
+        t_pf = _timed(pf.pfasst_run)
+        st, pstats = pf.stats()
+        hs.check(st, "eq10 PFASST", allow=(hs.HS_ENOCONV,))
+        K_P = pstats[0]["total_sweeps"]
+        u_pf = pf.get_state().cpu().numpy()
+        del pf
+        model = K_S * P / (P * alpha + K_P * (1 + alpha + beta))
+        rows[f"predictor_{pred}"] = {
+            "K_P": K_P, "converged": st == hs.HS_OK, "last_residual": max(x["last_sdc_res"] for x in pstats),
+            "model_speedup_P16": model, "pfasst_seconds": t_pf,
+            "one_gpu_speedup_vs_serial_sdc": t_sdc / t_pf, "one_gpu_speedup_vs_serial_mlsdc": t_ml / t_pf,
+            "rel_diff_vs_serial_sdc": float(np.abs(u_pf - u_sdc).max() / np.abs(u_sdc).max())}
+    return {"workload": "eq10", "P": P, "K_S": K_S, "alpha": alpha, "beta": beta,
+            "serial_sdc_seconds": t_sdc, "serial_mlsdc_seconds": t_ml,
+            "serial_mlsdc_iterations_per_step": mstats[0]["total_sweeps"] / P, **t, **rows,
+            "note": "model: eq. (10) for P processors, one slice each; one-GPU ratios: the 16 slices run as "
+                    "one batch on a single GPU"}
+
+
+# ----------------------------------------------------------------------------
+# node-parallel against sequential SDC sweeps
+# ----------------------------------------------------------------------------
+
+def sdcnp127(args):
+    """127^3, 4th order, 5 nodes, nu 0.1, dt 0.01, 8 steps, sweeps until the
+    collocation residual is <= 1e-10, V(2,1) to 1e-12: the sequential IMEX
+    sweep (4 solves one after the other) against the node-parallel sweep
+    (the 4 solves as one batched solve); both reach the same collocation
+    solution."""
+    from . import heatst as hs
+    from . import inputs
+    n, steps = 127, 8
+    u0 = _dev(inputs.random_smooth(n, 5))
+    res, outs = {}, {}
+    for name, npar in (("sequential", 0), ("node_parallel", 1)):
+        plan = hs.Plan(hs.Problem(n=n, order=4, nnodes=5, nu=0.1, dt=0.01, nsteps=steps, sweeps=0, sdc_tol=1e-10,
+                                  max_sweeps=60, tol=1e-12, max_cycles=60, sdc_node_parallel=npar))
+        plan.set_state(u0)
+        plan.step()
+        plan.set_state(u0)
+        el = _timed(plan.solve)
+        st, stats = plan.stats()
+        hs.check(st, f"sdcnp127 {name}")
+        outs[name] = plan.get_state().cpu().numpy()
+        res[name] = {"seconds": el, "ms_per_step": el / steps * 1e3, "sweeps_per_step": stats[0]["total_sweeps"] / steps,
+                     "vcycles": stats[0]["total_cycles"], "solves": stats[0]["total_solves"]}
+        del plan
+    diff = float(np.abs(outs["node_parallel"] - outs["sequential"]).max() / np.abs(outs["sequential"]).max())
+    return {"workload": "sdcnp127", "metric": "ms per step", "value": res["node_parallel"]["ms_per_step"],
+            "unit": "ms", **res, "speedup_node_parallel": res["sequential"]["seconds"] / res["node_parallel"]["seconds"],
+            "rel_diff": diff}
+
+
+# ----------------------------------------------------------------------------
+# configuration 3: 255^3 mixed precision
+# ----------------------------------------------------------------------------
+
 def mixed255(args):
     from . import heatst as hs
     from . import inputs
     n, M, dt, nsteps = 255, 5, 0.02, 10
-    u0 = _dev(inputs.random_smooth(n, args.seed))
-    res = {}
-    outs = {}
-    # refinement to 1e-12 relative: the SDC threshold 1e-10 is then reachable and the
-    # mixed result stays within 1e-10 of the FP64 one
-    for name, prec, tol, inner in (("mixed", hs.HS_MIXED, 1e-12, (2, 2)), ("fp64", hs.HS_FP64, 1e-12, (2, 2))):
-        pb = hs.Problem(n=n, order=4, nnodes=M, nu=0.1, dt=dt, nsteps=nsteps, sweeps=0,
-                        sdc_tol=args.sdc_tol, max_sweeps=40, precision=prec, tol=tol, max_cycles=80,
-                        inner_nu1=inner[0], inner_nu2=inner[1])
-        plan = hs.Plan(pb)
-        plan.set_state(u0)
-        plan.step()                      # warm-up step (state reset below)
-        _sync()
-        plan.set_state(u0)
-        _sync()
-        t0 = time.perf_counter()
-        plan.solve()
-        _sync()
-        el = time.perf_counter() - t0
-        st, stats = plan.stats()
-        s0 = stats[0]
-        outs[name] = plan.get_state().cpu().numpy()
-        res[name] = {"seconds": el, "ms_per_step": el / nsteps * 1e3, "status": st,
-                     "sweeps": s0["total_sweeps"], "solves": s0["total_solves"],
-                     "cycles_or_refinements": s0["total_cycles"],
-                     "dof_updates_per_s": n ** 3 * (M - 1) * s0["total_sweeps"] / el,
-                     "steps_per_s": nsteps / el}
-        _log(f"{name}: {el:.3f} s, sweeps {s0['total_sweeps']}, inner iterations {s0['total_cycles']}")
-        del plan
-    diff = float(np.abs(outs["mixed"] - outs["fp64"]).max() / np.abs(outs["fp64"]).max())
-    return {"workload": "mixed255", "metric": "steps/s", "value": res["mixed"]["steps_per_s"],
-            "unit": "steps/s", "seed": args.seed, "sdc_tol": args.sdc_tol, "mixed": res["mixed"],
-            "fp64": res["fp64"], "speedup_mixed_vs_fp64": res["fp64"]["seconds"] / res["mixed"]["seconds"],
-            "rel_diff_mixed_vs_fp64": diff}
+    seeds = [int(x) for x in str(args.seeds).split(",")]
+    out = {"workload": "mixed255", "metric": "steps/s", "unit": "steps/s", "sdc_tol": args.sdc_tol,
+           "seeds": {}}
+    for seed in seeds:
+        u0 = _dev(inputs.random_smooth(n, seed))
+        res, outs = {}, {}
+        # refinement to 1e-12 relative: the SDC threshold 1e-10 is then reachable and the
+        # mixed result stays within 1e-10 of the FP64 one
+        for name, prec in (("mixed", hs.HS_MIXED), ("fp64", hs.HS_FP64)):
+            pb = hs.Problem(n=n, order=4, nnodes=M, nu=0.1, dt=dt, nsteps=nsteps, sweeps=0,
+                            sdc_tol=args.sdc_tol, max_sweeps=40, precision=prec, tol=1e-12, max_cycles=80,
+                            inner_nu1=2, inner_nu2=2)
+            plan = hs.Plan(pb)
+            plan.set_state(u0)
+            plan.step()                      # warm-up step (state reset below)
+            plan.set_state(u0)
+            el = _timed(plan.solve)
+            st, stats = plan.stats()
+            s0 = stats[0]
+            outs[name] = plan.get_state().cpu().numpy()
+            res[name] = {"seconds": el, "ms_per_step": el / nsteps * 1e3, "status": st,
+                         "sweeps": s0["total_sweeps"], "solves": s0["total_solves"],
+                         "cycles_or_refinements": s0["total_cycles"],
+                         "dof_updates_per_s": n ** 3 * (M - 1) * s0["total_sweeps"] / el}
+            _log(f"mixed255 seed {seed} {name}: {el:.3f} s, sweeps {s0['total_sweeps']}")
+            del plan
+        diff = float(np.abs(outs["mixed"] - outs["fp64"]).max() / np.abs(outs["fp64"]).max())
+        out["seeds"][str(seed)] = {"mixed": res["mixed"], "fp64": res["fp64"],
+                                   "speedup_mixed_vs_fp64": res["fp64"]["seconds"] / res["mixed"]["seconds"],
+                                   "rel_diff_mixed_vs_fp64": diff}
+    first = out["seeds"][str(seeds[0])]
+    out["value"] = nsteps / first["mixed"]["seconds"]
+    out["speedup_mixed_vs_fp64"] = first["speedup_mixed_vs_fp64"]
+    return out
 
 
-def _sweep_alpha(hs, nf, nc):
-    """alpha = time of one coarse sweep / time of one fine sweep (single lane)."""
-    pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=0.01, nsteps=1, sweeps=1,
-                    tol=1e-12, max_cycles=60)
-    plan = hs.Plan(pb)
-    from . import inputs
-    plan.set_state(_dev(inputs.sine_product(nf)))
-    times = {}
-    for level in (0, 1, 0, 1):
-        plan.begin_step()
-        plan.sdc_sweep(0)
-        plan.fas_restrict()
-        _sync()
-        t0 = time.perf_counter()
-        plan.sdc_sweep(level)
-        _sync()
-        times[level] = time.perf_counter() - t0
-    return times[1] / times[0], times
-
-
-def pfasst16(args):
-    from . import heatst as hs
-    from . import inputs
-    P, nf, nc, dt, K = 16, 127, 63, 0.01, 4
-    u0 = _dev(inputs.sine_product(nf))
-    pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P, sweeps=K,
-                    tol=1e-12, max_cycles=60, batch=P, nslices=P)
-    plan = hs.Plan(pb)
-    plan.set_state(u0)
-    plan.pfasst_run()
-    _sync()
-    plan.set_state(u0)
-    _sync()
-    t0 = time.perf_counter()
-    plan.pfasst_run()
-    _sync()
-    t_pf = time.perf_counter() - t0
-    upf = plan.get_state().cpu().numpy()
-    del plan
-    # serial MLSDC over the same 16 steps with the same iteration count
-    ser = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P,
-                             sweeps=K, tol=1e-12, max_cycles=60))
-    ser.set_state(u0)
-    ser.step()
-    _sync()
-    ser.set_state(u0)
-    _sync()
-    t0 = time.perf_counter()
-    ser.solve()
-    _sync()
-    t_ser = time.perf_counter() - t0
-    user = ser.get_state().cpu().numpy()
-    del ser
-    alpha, times = _sweep_alpha(hs, nf, nc)
-    dof = nf ** 3 * 4 * K * P
-    return {"workload": "pfasst16", "metric": "DOF-updates/s", "value": dof / t_pf, "unit": "DOF-updates/s",
-            "pfasst_seconds": t_pf, "serial_mlsdc_seconds": t_ser, "speedup_vs_serial": t_ser / t_pf,
-            "rel_diff_pfasst_vs_serial": float(np.abs(upf - user).max() / np.abs(user).max()),
-            "alpha_coarse_over_fine_sweep": alpha,
-            "fine_sweep_ms": times[0] * 1e3, "coarse_sweep_ms": times[1] * 1e3}
-
+# ----------------------------------------------------------------------------
+# configuration 4 (second part): uneven batch of 64 instances
+# ----------------------------------------------------------------------------
 
 def uneven64(args):
     from . import heatst as hs
     from . import inputs
-    ns = inputs.uneven_sizes(args.seed, 64)
+    ns = inputs.uneven_sizes(0, 64)
     dt, nsteps, sweeps = 0.01, 2, 4
     u0s = [inputs.random_smooth(n, 100 + i) for i, n in enumerate(ns)]
     flat = _dev(np.concatenate([u.ravel() for u in u0s]))
@@ -155,13 +289,8 @@ def uneven64(args):
     plan = hs.Plan(pb)
     plan.set_state(flat)
     plan.step()
-    _sync()
     plan.set_state(flat)
-    _sync()
-    t0 = time.perf_counter()
-    plan.solve()
-    _sync()
-    t_b = time.perf_counter() - t0
+    t_b = _timed(plan.solve)
     got = plan.get_state().cpu().numpy()
     del plan
     # one plan per instance, in turn
@@ -176,13 +305,8 @@ def uneven64(args):
             plans[n].set_state(_dev(u0s[i]))
             plans[n].step()            # warm-up
         p = plans[n]
-        u = _dev(u0s[i])
-        p.set_state(u)
-        _sync()
-        t0 = time.perf_counter()
-        p.solve()
-        _sync()
-        t_s += time.perf_counter() - t0
+        p.set_state(_dev(u0s[i]))
+        t_s += _timed(p.solve)
         alone = p.get_state().cpu().numpy()
         maxdiff = max(maxdiff, float(np.abs(alone - got[off:off + n ** 3]).max()))
         off += n ** 3
@@ -190,6 +314,120 @@ def uneven64(args):
     return {"workload": "uneven64", "metric": "DOF-updates/s", "value": dof / t_b, "unit": "DOF-updates/s",
             "batched_seconds": t_b, "sequential_seconds": t_s, "speedup_batched_vs_sequential": t_s / t_b,
             "max_abs_diff_batched_vs_alone": maxdiff, "sizes": {str(n): ns.count(n) for n in (31, 63, 127)}}
+
+
+# ----------------------------------------------------------------------------
+# kernel microbenchmark on the 511^3 hierarchy
+# ----------------------------------------------------------------------------
+
+# algorithmic bytes per grid point of each timed kernel (each input read once,
+# each output written once)
+_BYTES = {("pjac", 0): 25.0, ("resid_fw", 0): 17.0, ("sweep1", 0): 24.0, ("sweep2", 0): 24.0,
+          ("pjac", 1): 12.5, ("resid_fw", 1): 8.5, ("sweep2", 1): 8.0}
+
+
+def _kernel_rates(hs, plan, kinds, run, npts, prec, reps=3):
+    out = {}
+    for name, kind in kinds:
+        plan.timer(kind | (hs.HS_TIMER_FP32 if prec else 0), 256)
+        for _ in range(reps):
+            run()
+        launches, ms = plan.timer_read()
+        plan.timer(0, 0)
+        if launches == 0:
+            continue
+        us = ms / launches * 1e3
+        gbs = _BYTES[(name, prec)] * npts / (us * 1e-6) / 1e9
+        out[name] = {"us_per_launch": us, "launches": launches, "GBps_algorithmic": gbs,
+                     "frac_of_8TBps": gbs / 8000.0, "bytes_per_point": _BYTES[(name, prec)]}
+    return out
+
+
+def micro511(args):
+    """Finest-grid kernels in the solver's own launches: fixed-cycle V(2,1)
+    solves (FP64) and refinement iterations with FP32 V(2,2) cycles (mixed),
+    4th order, at 511^3 and on a batch of two 255^3 grids; the Jacobi sweep
+    and the operator application alone through hs_smooth / hs_lap_apply."""
+    import torch
+    from . import heatst as hs
+    from . import inputs
+    res = {}
+    kinds64 = [("sweep1", hs.HS_TIMER_SWEEP1), ("sweep2", hs.HS_TIMER_SWEEP2), ("resid_fw", hs.HS_TIMER_RESID_FW),
+               ("pjac", hs.HS_TIMER_PJAC)]
+    kinds32 = [("sweep2", hs.HS_TIMER_SWEEP2), ("resid_fw", hs.HS_TIMER_RESID_FW), ("pjac", hs.HS_TIMER_PJAC)]
+    a = 0.1 * 0.05 * 0.17267316464601146
+    for n, batch in ((511, 1), (255, 2)):
+        N = n ** 3 * batch
+        g = torch.Generator(device="cuda").manual_seed(0)
+        b = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+        u = torch.zeros_like(b)
+        for prec, kinds in ((0, kinds64), (1, kinds32)):
+            plan = hs.Plan(hs.Problem(n=n, order=4, nnodes=2, nu=0.1, dt=0.05, fixed_cycles=2, batch=batch,
+                                      precision=hs.HS_MIXED if prec else hs.HS_FP64, inner_nu1=2, inner_nu2=2))
+            plan.mg_vcycle(u, b, a)      # tables and warm-up
+            rates = _kernel_rates(hs, plan, kinds, lambda: plan.mg_vcycle(u, b, a), N, prec)
+            res[f"{n}^3 x{batch} {'fp32' if prec else 'fp64'}"] = rates
+            if prec == 0 and batch == 1:
+                # the operator alone and plain Jacobi sweeps (one launch each)
+                y = torch.empty_like(b)
+                tmp = torch.empty_like(b)
+                s = torch.cuda.current_stream()
+                for name, fn, bpp in (("lap_apply", lambda: plan.lap_apply(u, 1.0, -a, out=y), 16.0),
+                                      ("jacobi", lambda: plan.smooth(u, b, tmp, a, 2), 24.0)):
+                    fn()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    s.synchronize()
+                    e0.record(s)
+                    for _ in range(5):
+                        fn()
+                    e1.record(s)
+                    e1.synchronize()
+                    per = e0.elapsed_time(e1) / (5 * (2 if name == "jacobi" else 1)) * 1e-3
+                    gbs = bpp * N / per / 1e9
+                    rates[name] = {"us_per_launch": per * 1e6, "GBps_algorithmic": gbs, "frac_of_8TBps": gbs / 8000.0,
+                                   "bytes_per_point": bpp}
+                del y, tmp
+            del plan
+            torch.cuda.empty_cache()
+        del b, u
+        torch.cuda.empty_cache()
+    return {"workload": "micro511", "order": 4, "kernels": res,
+            "note": "per-launch times from HIP events that record each kernel's own start and end; "
+                    "algorithmic bytes: every input read once, every output written once"}
+
+
+# ----------------------------------------------------------------------------
+# configuration 5: serving
+# ----------------------------------------------------------------------------
+
+def _plain_replay(hs, reqs, u0_of, keep):
+    """The plain path under the same arrivals: one request at a time, in
+    arrival order, FP64 V(2,1) to 1e-12, SDC to 1e-10; latency = completion -
+    arrival on one clock."""
+    plans = {}
+    for r in reqs:
+        if r.n not in plans:
+            plans[r.n] = hs.Plan(hs.Problem(n=r.n, order=2, nnodes=5, nu=0.1, dt=0.01, nsteps=1, sweeps=0,
+                                            sdc_tol=1e-10, max_sweeps=40, tol=1e-12, max_cycles=80))
+    inputs_dev = [u0_of(r) for r in reqs]
+    _sync()
+    t_start = time.perf_counter()
+    lat, outs = [], {}
+    for r, u0 in zip(reqs, inputs_dev):
+        now = time.perf_counter() - t_start
+        if now < r.arrival:
+            time.sleep(r.arrival - now)
+        p = plans[r.n]
+        p.set_lane(0, r.nu, r.dt, 0.0, r.nsteps)
+        p.set_lane_state(0, u0)
+        for _ in range(r.nsteps):
+            p.step()
+        _sync()
+        lat.append(time.perf_counter() - t_start - r.arrival)
+        if keep:
+            outs[r.rid] = p.get_lane_state(0).cpu().numpy()
+    wall = time.perf_counter() - t_start
+    return np.array(lat), wall, outs
 
 
 def serving(args):
@@ -203,60 +441,43 @@ def serving(args):
     def u0_of(r):
         return _dev(inputs.random_smooth(r.n, r.seed))
 
-    # plain path: one request at a time, FP64 V(2,1) cycles to 1e-12, SDC to 1e-10
-    sample = inputs.serving_requests(args.seed + 1, R, 1.0, sizes=sizes, weights=weights)
-    plans = {}
-    service = []
-    for r in sample:
-        if r.n not in plans:
-            plans[r.n] = hs.Plan(hs.Problem(n=r.n, order=2, nnodes=5, nu=0.1, dt=0.01, nsteps=1, sweeps=0,
-                                            sdc_tol=1e-10, max_sweeps=40, tol=1e-12, max_cycles=80))
-        p = plans[r.n]
-        p.set_lane(0, r.nu, r.dt, 0.0, r.nsteps)
-        p.set_lane_state(0, u0_of(r))
-        _sync()
-        t0 = time.perf_counter()
-        for _ in range(r.nsteps):
-            p.step()
-        _sync()
-        service.append(time.perf_counter() - t0)
-        _log(f"plain request {len(service)}/{len(sample)}: n={r.n} steps={r.nsteps} {service[-1]:.3f} s")
-    plain_capacity = len(sample) / sum(service)
-    del plans
-    _log(f"plain path: {plain_capacity:.3f} solves/s over {len(sample)} requests")
-
-    def fifo_latencies(arrivals, svc):
-        t, lat = 0.0, []
-        for a, s in zip(arrivals, svc):
-            t = max(t, a) + s
-            lat.append(t - a)
-        return np.array(lat)
-
+    # capacity of the plain path: the stream with every request at t = 0
+    if getattr(args, "plain_capacity", 0.0) > 0:
+        plain_capacity, lat0, wall0 = args.plain_capacity, None, None
+    else:
+        burst = inputs.serving_requests(1, R, 1e9, sizes=sizes, weights=weights)
+        lat0, wall0, _ = _plain_replay(hs, burst, u0_of, False)
+        plain_capacity = R / wall0
+    _log(f"plain path: {plain_capacity:.3f} solves/s over {R} requests")
     budget = int(args.budget_gb * 1e9)
-    slots = sv.slots_for_budget(budget, sizes, weights, precision=hs.HS_MIXED, tol=1e-12)
-    _log(f"slots {slots}")
-    srv = sv.Server(slots, precision=hs.HS_MIXED, tol=1e-12, sdc_tol=1e-10, max_sweeps=40, budget_bytes=budget)
+    srv = sv.Server.for_budget(budget, sizes, weights, precision=hs.HS_MIXED, tol=1e-12, sdc_tol=1e-10,
+                               max_sweeps=40)
     rows = []
     for f in [float(x) for x in args.rates.split(",")]:
         rate = f * plain_capacity
-        reqs = inputs.serving_requests(args.seed + 1, R, rate, sizes=sizes, weights=weights)
-        res, tickets, infos = sv.replay(srv, reqs, u0_of)
+        reqs = inputs.serving_requests(1, R, rate, sizes=sizes, weights=weights)
+        res, tickets, infos = sv.replay(srv, reqs, u0_of, keep_results=True)
+        served = {r.rid: srv.result(tk).cpu().numpy() for tk, r, _ in tickets}
+        for tk, _, _ in tickets:
+            srv.release(tk)
         bad = sum(1 for i in infos if i.status != 0)
-        plain_lat = fifo_latencies([r.arrival for r in reqs], service)
+        plat, pwall, pouts = _plain_replay(hs, reqs, u0_of, True)
+        worst = max(float(np.abs(served[k] - pouts[k]).max() / np.abs(pouts[k]).max()) for k in pouts)
         rows.append({"rate_factor": f, "rate_per_s": rate, "solves_per_s": res.solves_per_s,
                      "p50_s": res.p50_s, "p99_s": res.p99_s, "failed": bad,
-                     "plain_p50_s": float(np.percentile(plain_lat, 50)),
-                     "plain_p99_s": float(np.percentile(plain_lat, 99)),
-                     "plain_solves_per_s": len(reqs) / float(max(r.arrival + l for r, l in zip(reqs, plain_lat)))})
-        _log(f"rate x{f}: {res.solves_per_s:.3f} solves/s p50 {res.p50_s:.3f} s p99 {res.p99_s:.3f} s")
-    # saturation: every request at t = 0
-    reqs = inputs.serving_requests(args.seed + 1, R, 1e9, sizes=sizes, weights=weights)
-    res, _, infos = sv.replay(srv, reqs, u0_of)
+                     "plain_solves_per_s": R / pwall, "plain_p50_s": float(np.percentile(plat, 50)),
+                     "plain_p99_s": float(np.percentile(plat, 99)),
+                     "max_rel_diff_served_vs_plain": worst})
+        _log(f"rate x{f}: served {res.solves_per_s:.3f} solves/s p50 {res.p50_s:.3f} p99 {res.p99_s:.3f}; "
+             f"plain {R / pwall:.3f} solves/s p50 {np.percentile(plat, 50):.3f} p99 {np.percentile(plat, 99):.3f}; "
+             f"max diff {worst:.2e}")
+    reqs = inputs.serving_requests(1, R, 1e9, sizes=sizes, weights=weights)
+    res, _, _ = sv.replay(srv, reqs, u0_of)
     srv.close()
     return {"workload": "serving", "metric": "solves/s", "value": res.solves_per_s, "unit": "solves/s",
-            "plain_fp64_solves_per_s": plain_capacity,
-            "speedup_vs_plain": res.solves_per_s / plain_capacity,
+            "plain_fp64_solves_per_s": plain_capacity, "speedup_vs_plain": res.solves_per_s / plain_capacity,
             "saturated": {"p50_s": res.p50_s, "p99_s": res.p99_s, "wall_s": res.wall_s},
-            "rates": rows, "slots": {str(k): v for k, v in slots.items()}, "requests_per_rate": R,
-            "sizes": list(sizes), "weights": list(weights),
-            "tolerances": {"sdc_residual": 1e-10, "inner_relative_residual": 1e-12}}
+            "plain_saturated": None if lat0 is None else
+            {"p50_s": float(np.percentile(lat0, 50)), "p99_s": float(np.percentile(lat0, 99)), "wall_s": wall0},
+            "rates": rows, "requests_per_rate": R, "sizes": list(sizes), "weights": list(weights),
+            "budget_bytes": budget, "tolerances": {"sdc_residual": 1e-10, "inner_relative_residual": 1e-12}}
