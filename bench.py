@@ -11,7 +11,11 @@ implicit substep solved by V(2,1) multigrid cycles (weighted Jacobi
 6/7, full weighting, trilinear, exact 3^3 solve) to a relative residual of
 1e-12; initial value u0 = sin(pi x) sin(pi y) sin(pi z) and the consistent
 manufactured forcing (c = 3).  Inputs are synthetic, generated on the host
-and copied to HBM before timing.
+and copied to HBM before timing.  The slices run in 4 groups of 4: the fine
+sweeps of one group (one batched launch per kernel over its 4 slices)
+overlap the coarse pipeline of the group before it, which a second host
+thread issues on a second stream (--groups; the results are bit for bit
+those of the one-batch order).
 
 A step is one PFASST block (16 time slices, 4 iterations).  --steps K
 blocks are timed back to back (16 K time steps); --warmup W blocks run first
@@ -21,7 +25,7 @@ value = space-time DOF-updates/s = 127^3 * (5 - 1) substeps * 4 iterations
         * 16 slices * K / elapsed.
 
 roofline: the dominant kernel of the batched fine sweeps, k_pjac<double, 4>
-(prolongation + first post-smoothing sweep) on the 16 x 127^3 finest grids,
+(prolongation + first post-smoothing sweep) on one group's 127^3 finest grids,
 timed live inside the timed run with HIP events that record each launch's
 own start and end on the stream it runs on (hs_plan_timer); algorithmic
 bytes 25 per grid point of every lane the launch updates (read u, b and the
@@ -30,6 +34,9 @@ fine-level cycle counts.
 
 cpu_baseline: the CPU oracle (plain serial C, one core) on one MLSDC
 iteration of the first slice of the same workload.
+
+serial_mlsdc_equal_work: the same 16 K steps by one-lane MLSDC with 4
+iterations per step, the speedup of the PFASST run over it.
 
 extra: the other configurations as records of their own -- 15^3 SDC
 latency, the 127^3/63^3 MLSDC run with the coarse/fine sweep-time ratio,
@@ -60,12 +67,14 @@ def log(msg):
 
 
 PRED = 1                 # coarse sweeps per slice of the serial coarse predictor
+GROUPS = 4               # slice groups: a group's fine sweeps overlap the previous group's coarse pipeline
 
 
-def problem(hs, nblocks, **kw):
+def problem(hs, nblocks, groups=0, **kw):
     return hs.Problem(n=NF, order=4, nnodes=MF, coarse=(NC, 2, MC), nu=0.1, dt=DT, t0=0.0, forcing_c=3.0,
                       nsteps=SLICES * nblocks, sweeps=ITERS, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest=3,
-                      tol=1e-12, max_cycles=60, batch=SLICES, nslices=SLICES, pfasst_pred_sweeps=PRED, **kw)
+                      tol=1e-12, max_cycles=60, batch=SLICES, nslices=SLICES, pfasst_pred_sweeps=PRED,
+                      pfasst_groups=groups, **kw)
 
 
 def kernel_hash():
@@ -100,13 +109,13 @@ def cpu_baseline():
 
 def headline(args, torch, hs, inputs):
     u0 = torch.from_numpy(inputs.sine_product(NF).ravel()).cuda()
-    warm = hs.Plan(problem(hs, 1))
+    warm = hs.Plan(problem(hs, 1, args.groups))
     for _ in range(args.warmup):
         warm.set_state(u0)
         warm.pfasst_run()
     torch.cuda.synchronize()
     del warm
-    plan = hs.Plan(problem(hs, args.steps))
+    plan = hs.Plan(problem(hs, args.steps, args.groups))
     plan.set_state(u0)
     plan.timer(hs.HS_TIMER_PJAC, 8192)
     torch.cuda.synchronize()
@@ -137,20 +146,47 @@ def headline(args, torch, hs, inputs):
     log(f"{elapsed:.3f} s, {value:.3e} DOF-updates/s, k_pjac {launches} launches {kms / launches * 1e3:.1f} us, "
         f"{achieved:.0f} GB/s")
     del plan
+    gb = SLICES // args.groups if args.groups >= 2 else SLICES   # lanes per fine launch
     shapes = {f"{n}^3 order {o} x{b}": list(hs.tune_lookup(n, o, 0, b))
-              for n, o, b in ((127, 4, SLICES), (63, 4, SLICES), (31, 4, SLICES), (63, 2, 1), (31, 2, 1))}
+              for n, o, b in ((127, 4, gb), (63, 4, gb), (31, 4, gb), (63, 2, 1), (31, 2, 1))}
     builtin_s = None
     if not args.no_builtin_compare:
         builtin_s = builtin_shapes_run(args, torch, hs, u0)
     out = _headline_record(args, elapsed, value, achieved, traffic, launches, kms, pjac_bytes, fine_lane_cycles,
                            fine_solves, err, stats, shapes, builtin_s)
+    if not args.no_serial_compare:
+        out["serial_mlsdc_equal_work"] = serial_mlsdc_run(args, torch, hs, inputs, u0, elapsed)
     return out
+
+
+def serial_mlsdc_run(args, torch, hs, inputs, u0, pfasst_s):
+    """The same 16 K time steps by one-lane MLSDC, step after step, with the
+    PFASST run's 4 iterations per step (equal fine work, no predictor)."""
+    import numpy as np
+    pb = hs.Problem(n=NF, order=4, nnodes=MF, coarse=(NC, 2, MC), nu=0.1, dt=DT, t0=0.0, forcing_c=3.0,
+                    nsteps=SLICES * args.steps, sweeps=ITERS, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest=3,
+                    tol=1e-12, max_cycles=60)
+    plan = hs.Plan(pb)
+    plan.set_state(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st, _ = plan.stats()
+    hs.check(st, "bench serial MLSDC")
+    u = plan.get_state().cpu().numpy().reshape(NF, NF, NF)
+    ex = inputs.sine_product(NF) * math.cos(args.steps * SLICES * DT)
+    del plan
+    log(f"serial MLSDC, same steps and iterations: {el:.3f} s (PFASST {pfasst_s / el:.3f} of it)")
+    return {"seconds": el, "steps": SLICES * args.steps, "iterations_per_step": ITERS,
+            "pfasst_speedup": el / pfasst_s, "error_vs_exact": float(np.abs(u - ex).max() / np.abs(ex).max())}
 
 
 def builtin_shapes_run(args, torch, hs, u0):
     """The same run with the built-in launch shapes: what the autotuner's table gains."""
     hs.tune_clear()
-    base = hs.Plan(problem(hs, args.steps))
+    base = hs.Plan(problem(hs, args.steps, args.groups))
     base.set_state(u0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -182,10 +218,14 @@ def _headline_record(args, elapsed, value, achieved, traffic, launches, kms, pja
         "config": {"workload": "PFASST, 16 time slices batched on one GPU x 5 Lobatto nodes, two-level MLSDC + "
                                "FAS per slice, FP64: fine 127^3 4th-order, coarse 63^3 2nd-order 3 nodes, nu=0.1, "
                                "dt=0.01, coarse predictor + 4 PFASST iterations per block of 16 steps, V(2,1) "
-                               "Jacobi 6/7 to 3^3, rel. residual 1e-12",
+                               "Jacobi 6/7 to 3^3, rel. residual 1e-12; slices in groups whose batched fine "
+                               "sweeps overlap the coarse pipeline",
                    "fine_n": NF, "coarse_n": NC, "slices": SLICES, "dt": DT, "iterations": ITERS,
-                   "blocks": args.steps, "mg_tol": 1e-12, "predictor_coarse_sweeps": PRED},
-        "roofline": {"bound": "hbm", "kernel": "k_pjac<double, 4> on the 16 x 127^3 finest grids (batched)",
+                   "blocks": args.steps, "mg_tol": 1e-12, "predictor_coarse_sweeps": PRED,
+                   "slice_groups": args.groups},
+        "roofline": {"bound": "hbm",
+                     "kernel": f"k_pjac<double, 4> on the finest 127^3 grids of one slice group "
+                               f"({SLICES // max(1, args.groups)} lanes per launch)",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "launches": launches, "us_per_launch": kms / launches * 1e3,
                      "algorithmic_bytes_per_launch": pjac_bytes / launches,
@@ -205,10 +245,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline PFASST measurement")
+    ap.add_argument("--groups", type=int, default=GROUPS,
+                    help="PFASST slice groups whose fine sweeps overlap the coarse pipeline (0: one batch)")
+    ap.add_argument("--no-serial-compare", action="store_true",
+                    help="skip the serial MLSDC run of the same steps")
     ap.add_argument("--no-builtin-compare", action="store_true",
                     help="skip the second headline run with the built-in launch shapes")
     ap.add_argument("--plain-capacity", type=float, default=0.0,
                     help="serving: the plain path's solves/s (skips measuring it)")
+    ap.add_argument("--no-saturated", action="store_true",
+                    help="serving: skip the closing all-at-once stream")
     ap.add_argument("--workload", default="pfasst16",
                     choices=["pfasst16", "sdc15", "mlsdc127", "mixed255", "uneven64", "serving", "micro511",
                              "eq10", "sdcnp127"],

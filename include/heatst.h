@@ -136,6 +136,11 @@ typedef struct {
                                 the previous iterate, (I - nu dt tau_m L_h) U_m = U_0 + dt (QF)_m
                                 - nu dt tau_m L_h U_m^old, and the M-1 solves of all lanes run as one
                                 batched multigrid solve; same collocation fixed point (eq. (6)) */
+    int32_t pfasst_groups;   /* PFASST with sweeps > 0: 0 or 1 runs every iteration's fine sweeps as
+                                one batch, then the coarse pipeline; G >= 2 (dividing nslices)
+                                splits the slices into G groups of consecutive slices whose fine
+                                sweeps and coarse pipeline overlap (see hs_pfasst_run); same
+                                results */
 } hs_problem;
 
 /* Per-lane statistics (hs_stats_read). */
@@ -295,7 +300,20 @@ hs_status hs_solve(hs_plan* plan, void* stream);
  * (the paper's PFASST threshold, section 2), at most max_sweeps
  * iterations (then the lanes report HS_ENOCONV).  The lanes' total_sweeps
  * count the iterations.  Synchronises once per iteration in the
- * tolerance mode. */
+ * tolerance mode.
+ *
+ * pfasst_groups = G >= 2 (fixed iterations): the same operations in a
+ * pipelined order.  The slices form G groups of P/G consecutive slices;
+ * the fine sweep of one group runs as one batch on `stream` while the
+ * coarse pipeline of the group before it runs on a second stream of the
+ * plan, issued by a second host thread, so the coarse sweeps of PFASST's
+ * pipeline overlap the fine work as the paper's processors do (section
+ * 1.1).  Every operation sees the data it sees in the order above: a
+ * group's first slice takes its fine and coarse hand-offs from copies of
+ * the previous group's end values made at the point the serial order reads
+ * them.  The call returns once all work is issued on `stream` (the second
+ * stream's work is ordered before the end of it); it is not reentrant for
+ * one plan. */
 hs_status hs_pfasst_run(hs_plan* plan, void* stream);
 
 /* Launch timer, a measurement aid: with kind > 0 every launch of one kernel

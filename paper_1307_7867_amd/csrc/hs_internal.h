@@ -276,7 +276,7 @@ hipError_t end_step(LaneCtl* ctl, int nlanes, hipStream_t s);
 // lane states first .. first + nlanes - 1
 hipError_t begin_solve(LaneCtl* ctl, int first, int nlanes, hipStream_t s);
 hipError_t end_solve_fixed(LaneCtl* ctl, int first, int nlanes, int cycles, int level, hipStream_t s);
-hipError_t begin_sweep(LaneCtl* ctl, int nlanes, hipStream_t s);
+hipError_t begin_sweep(LaneCtl* ctl, int first, int nlanes, hipStream_t s);
 hipError_t set_lane(LaneCtl* ctl, int lane, double nu, double dt, double t0, double forcing_c,
                     int nsteps, int active, hipStream_t s);
 hipError_t set_a_user(LaneCtl* ctl, int lane, double a, hipStream_t s);

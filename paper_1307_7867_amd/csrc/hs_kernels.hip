@@ -2597,10 +2597,10 @@ __global__ void k_end_solve_fixed(LaneCtl* ctl, int first, int nlanes, int cycle
     if (c.mg_state == 0) finish_solve(c, cycles, 1, level);
 }
 
-__global__ void k_begin_sweep(LaneCtl* ctl, int nlanes)
+__global__ void k_begin_sweep(LaneCtl* ctl, int first, int nlanes)
 {
-    int lane = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane >= nlanes) return;
+    int lane = first + blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= first + nlanes) return;
     LaneCtl& c = ctl[lane];
     if (c.sdc_state == 0) c.sweeps_step += 1;
 }
@@ -3033,19 +3033,22 @@ hipError_t end_step(LaneCtl* ctl, int nlanes, hipStream_t s)
 
 hipError_t begin_solve(LaneCtl* ctl, int first, int nlanes, hipStream_t s)
 {
+    if (nlanes <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_begin_solve, lanes_grid(nlanes), dim3(64), 0, s, ctl, first, nlanes);
     return hipGetLastError();
 }
 
 hipError_t end_solve_fixed(LaneCtl* ctl, int first, int nlanes, int cycles, int level, hipStream_t s)
 {
+    if (nlanes <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_end_solve_fixed, lanes_grid(nlanes), dim3(64), 0, s, ctl, first, nlanes, cycles, level);
     return hipGetLastError();
 }
 
-hipError_t begin_sweep(LaneCtl* ctl, int nlanes, hipStream_t s)
+hipError_t begin_sweep(LaneCtl* ctl, int first, int nlanes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin_sweep, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes);
+    if (nlanes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_begin_sweep, lanes_grid(nlanes), dim3(64), 0, s, ctl, first, nlanes);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <type_traits>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -194,6 +196,7 @@ struct MgSet {
 
 struct LaneSet {
     std::vector<int> lanes;
+    int first = 0, span = 0;                   // lanes[] lie in first .. first + span - 1
     MgSet mg64[2], mg32[2];
     Table<SdcSeg> sdc[2];
     Table<FasSeg> fasc, fasf;
@@ -283,6 +286,24 @@ struct hs_plan {
     int timer_kind = 0;
     std::vector<hipEvent_t> timer_ev;
     int timer_used = 0;
+    // PFASST slice-group pipeline (pb.pfasst_groups = G >= 2): the lane sets of
+    // the G groups of consecutive slices, the fine hand-off into each group's
+    // slices, the coarse hand-off into a group's first slice, and the end
+    // values of each group's last slice that those two read (fine after the
+    // group's interpolation, coarse after its coarse sweeps)
+    int G = 0;
+    std::vector<LaneSet> grp;
+    std::vector<Table<SdcSeg>> gh_dst, gh_src, gc_src;
+    std::vector<double*> snap_f, snap_c;
+    // the coarse sweeps run on a stream of their own, issued by a second host
+    // thread with host-side state of its own (see issuer())
+    hipStream_t pipe = nullptr;
+    double* partials2 = nullptr;
+    LaneCtl* h_ctl2 = nullptr;
+    hipEvent_t ev_ctl2 = nullptr;
+    int sweep_k2 = 0;
+    std::vector<hipEvent_t> ev_r, ev_c;        // group's restriction / coarse sweeps recorded
+    hipEvent_t ev_go = nullptr;                // block started
 };
 
 namespace {
@@ -495,6 +516,8 @@ SdcSeg sdc_seg(hs_plan* P, int b, int L)
 // Host contents of every table of the lanes in ls.lanes.
 void build_set_host(hs_plan* P, LaneSet& ls)
 {
+    ls.first = ls.lanes.empty() ? 0 : *std::min_element(ls.lanes.begin(), ls.lanes.end());
+    ls.span = ls.lanes.empty() ? 0 : *std::max_element(ls.lanes.begin(), ls.lanes.end()) - ls.first + 1;
     for (int L = 0; L < P->nlev; L++) {
         int bk = 0;
         ls.sdc[L].h.clear();
@@ -756,6 +779,56 @@ void layout(hs_plan* P, char* base)
             finish_table(P->hc_src[p], bump);
         }
     }
+    // PFASST slice groups: lane sets, snapshots of the last slices' end values,
+    // and the hand-off tables that read them at the group boundaries
+    P->grp.clear();
+    P->gh_dst.clear();
+    P->gh_src.clear();
+    P->gc_src.clear();
+    P->snap_f.clear();
+    P->snap_c.clear();
+    P->G = P->pb.nslices > 1 && P->pb.pfasst_groups >= 2 ? P->pb.pfasst_groups : 0;
+    if (P->G) {
+        const int G = P->G, Q = P->B / G;
+        P->grp.resize(G);
+        P->gh_dst.resize(G);
+        P->gh_src.resize(G);
+        P->gc_src.resize(G);
+        for (int g = 0; g < G; g++) {
+            for (int b = g * Q; b < (g + 1) * Q; b++) P->grp[g].lanes.push_back(b);
+            build_set(P, P->grp[g], bump);
+            if (g + 1 < G) {
+                P->snap_f.push_back(bump.arr<double>((size_t)P->lanes[0].N[0]));
+                P->snap_c.push_back(bump.arr<double>((size_t)P->lanes[0].N[1]));
+            }
+        }
+        for (int g = 0; g < G; g++) {
+            int bk = 0;
+            for (int p = std::max(1, g * Q); p < (g + 1) * Q; p++) {
+                SdcSeg d = sdc_seg(P, p, 0), src = sdc_seg(P, p - 1, 0);
+                if (p == g * Q) {   // across the boundary: the snapshot, a single node
+                    src.U = P->snap_f[g - 1];
+                    src.M = 1;
+                }
+                d.blk_begin = src.blk_begin = bk;
+                bk += hsk::grid_blocks(d.n);
+                P->gh_dst[g].h.push_back(d);
+                P->gh_src[g].h.push_back(src);
+            }
+            P->gh_dst[g].nblk = P->gh_src[g].nblk = bk;
+            finish_table(P->gh_dst[g], bump);
+            finish_table(P->gh_src[g], bump);
+            if (g > 0) {
+                SdcSeg src = sdc_seg(P, g * Q - 1, 1);
+                src.U = P->snap_c[g - 1];
+                src.M = 1;
+                src.blk_begin = 0;
+                P->gc_src[g].h.push_back(src);
+                P->gc_src[g].nblk = hsk::grid_blocks(src.n);
+                finish_table(P->gc_src[g], bump);
+            }
+        }
+    }
     // per-block maxima of the reductions: two doubles per block of the largest launch
     int maxblk = 1;
     auto upd = [&](int nb) { maxblk = std::max(maxblk, nb); };
@@ -776,7 +849,9 @@ void layout(hs_plan* P, char* base)
         for (auto& t : S->jac) upd(t.nblk);
         for (auto& t : S->pro) upd(t.nblk);
     }
+    for (auto& ls : P->grp) scan(ls);
     P->partials = bump.arr<double>(2 * (size_t)maxblk);
+    P->partials2 = P->G ? bump.arr<double>(2 * (size_t)maxblk) : nullptr;
     P->bytes = (bump.off + 255) & ~(size_t)255;
 }
 
@@ -849,6 +924,10 @@ hs_status validate(const hs_problem* pb)
         (pb->sdc_node_parallel != 1 || pb->nlevels != 1 || pb->nslices != 1 || pb->lane_memory))
         return HS_EINVAL;
     if (pb->lane_memory && pb->nslices != 1) return HS_EINVAL;
+    if (pb->pfasst_groups < 0 || pb->pfasst_groups > pb->nslices) return HS_EINVAL;
+    if (pb->pfasst_groups >= 2 &&
+        (pb->nslices % pb->pfasst_groups != 0 || pb->sweeps <= 0 || pb->mg.cycle_graphs))
+        return HS_EINVAL;
     if (pb->nslices > 1) {
         if (pb->nslices != pb->batch || pb->nlevels != 2) return HS_EINVAL;
         if (pb->nsteps % pb->nslices != 0) return HS_EINVAL;
@@ -863,19 +942,38 @@ hs_status validate(const hs_problem* pb)
 // issuing cycles / sweeps (tolerance mode only).
 // ---------------------------------------------------------------------------
 
+// Host-side state of the thread that issues work on stream s: the per-block
+// maxima of the reductions, the pinned copy of the lane states with the event
+// that marks it, and the iteration count that indexes the cycle predictions.
+// The coarse sweeps of the PFASST pipeline are issued on P->pipe by a thread
+// of their own; everything else runs on the caller's stream.
+struct Issuer {
+    double* partials;
+    LaneCtl* h_ctl;
+    hipEvent_t ev_ctl;
+    int* sweep_k;
+};
+
+Issuer issuer(hs_plan* P, hipStream_t s)
+{
+    if (P->pipe && s == P->pipe) return {P->partials2, P->h_ctl2, P->ev_ctl2, &P->sweep_k2};
+    return {P->partials, P->h_ctl, P->ev_ctl, &P->sweep_k};
+}
+
 hs_status read_ctl(hs_plan* P, hipStream_t s)
 {
-    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
+    HS_TRY(hipMemcpyAsync(issuer(P, s).h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
     HS_TRY(hipStreamSynchronize(s));
     return HS_OK;
 }
 
-bool all_mg_done(hs_plan* P, const LaneSet& ls, int* maxc)
+bool all_mg_done(hs_plan* P, const LaneSet& ls, int* maxc, hipStream_t s)
 {
+    const LaneCtl* h = issuer(P, s).h_ctl;
     bool done = true;
     int mc = 0;
     for (int b : ls.lanes) {
-        const LaneCtl& c = P->h_ctl[b];
+        const LaneCtl& c = h[b];
         if (c.mg_state == 0) done = false;
         else if (c.mg_state != 3) mc = std::max(mc, c.mg_cycle);
     }
@@ -883,10 +981,11 @@ bool all_mg_done(hs_plan* P, const LaneSet& ls, int* maxc)
     return done;
 }
 
-bool all_sdc_done(hs_plan* P, const LaneSet& ls)
+bool all_sdc_done(hs_plan* P, const LaneSet& ls, hipStream_t s)
 {
+    const LaneCtl* h = issuer(P, s).h_ctl;
     for (int b : ls.lanes)
-        if (P->h_ctl[b].sdc_state == 0) return false;
+        if (h[b].sdc_state == 0) return false;
     return true;
 }
 
@@ -944,7 +1043,7 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
                 k0 = sweeps_done;
             } else if (S.two && nu1 >= 2) {
                 const Table<GridSeg>& J2 = S.pro[st];
-                HS_TRY(hsk::jac2<T>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, code(), 0, 0, P->partials, s));
+                HS_TRY(hsk::jac2<T>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, code(), 0, 0, issuer(P, s).partials, s));
                 cf ^= 1;
                 k0 = 2;
             }
@@ -952,27 +1051,27 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
                 hsk::EvPair ev;
                 if (st == 0 && k < 2) ev = timer_events<T>(P, k == 0 ? HS_TIMER_SWEEP1 : HS_TIMER_SWEEP2, A.L);
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 1, 0, 0,
-                                     P->partials, s, 0, 0.0, 0, ev));
+                                     issuer(P, s).partials, s, 0, 0.0, 0, ev));
             }
         } else if (nu1 >= 2) {
             // finest grids' first sweep alone, then the correction grids' second
             // sweep from their zero-guess first one, next to the finest grids' second
             if (hasF) {
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(1), 0, 0, 0,
-                                     P->partials, s));
+                                     issuer(P, s).partials, s));
                 cf ^= 1;
             }
             hsk::EvPair ev;
             if (st == 0 && !hasF && S.uniform) ev = timer_events<T>(P, HS_TIMER_SWEEP2, A.L);
             HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 0, 0, 0,
-                                 P->partials, s, 1, 0.0, 0, ev));
+                                 issuer(P, s).partials, s, 1, 0.0, 0, ev));
             cf ^= 1; cc ^= 1;
             for (int k = 2; k < nu1; k++, cf ^= 1, cc ^= 1)
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), 0, 0, 0,
-                                     P->partials, s));
+                                     issuer(P, s).partials, s));
         } else {
             HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, code(), 0, 0, 0,
-                                 P->partials, s));
+                                 issuer(P, s).partials, s));
             cf ^= 1; cc ^= 1;
         }
         locf[st] = cf;
@@ -995,7 +1094,7 @@ hs_status vcycle(hs_plan* P, const MgSet& S, int order, hsk::MgArgs A, int nu1, 
             cf ^= 1; cc ^= 1;
             for (int k = 1; k < nu2; k++, cf ^= 1, cc ^= 1)
                 HS_TRY(hsk::sweep<T>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, code(), J.finest, 0, 0,
-                                     P->partials, s));
+                                     issuer(P, s).partials, s));
         } else {
             // no post-smoothing: the corrected iterate goes to u
             const Table<GridSeg>& Pr = S.pro[st];
@@ -1089,14 +1188,15 @@ hs_status read_ctl_ahead(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int
                          hipStream_t s)
 {
     if (!post) return read_ctl(P, s);
-    HS_TRY(hipMemcpyAsync(P->h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
-    HS_TRY(hipEventRecord(P->ev_ctl, s));
+    const Issuer I = issuer(P, s);
+    HS_TRY(hipMemcpyAsync(I.h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
+    HS_TRY(hipEventRecord(I.ev_ctl, s));
     hsk::MgArgs G = A;
     G.gate = 2;
     HS_CHECK(mg_finish(P, S, G, nu1, nu2, s));
     HS_TRY(hsk::fi_march(P->ctl, post->F->d, post->T->d, post->T->nseg(), post->F->nblk, post->order, post->m0,
                          post->m1, post->rhs_node, 2, s));
-    HS_TRY(hipEventSynchronize(P->ev_ctl));
+    HS_TRY(hipEventSynchronize(I.ev_ctl));
     return HS_OK;
 }
 
@@ -1109,11 +1209,11 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     const hs_mg_desc& mg = P->pb.mg;
     int order = P->order[L];
     hsk::MgArgs A{L, m, mg.omega, node, 1};
-    // the lane states this solve decides: the SDC lanes, or the node-parallel solver lanes
-    const int c0 = &ls == &P->np_set ? P->B : 0;
-    const int cn = &ls == &P->np_set ? P->nctl - P->B : P->B;
+    // the lane states this solve decides: the set's SDC lanes, or the node-parallel solver lanes
+    const int c0 = &ls == &P->np_set ? P->B : ls.first;
+    const int cn = &ls == &P->np_set ? P->nctl - P->B : ls.span;
     HS_TRY(hsk::begin_solve(P->ctl, c0, cn, s));
-    int& pred = m >= 0 ? P->cpred[L][m][std::min(P->sweep_k, hs_plan::PRED_K - 1)] : P->cpred_user;
+    int& pred = m >= 0 ? P->cpred[L][m][std::min(*issuer(P, s).sweep_k, hs_plan::PRED_K - 1)] : P->cpred_user;
     if (!P->mixed) {
         const MgSet& S = ls.mg64[L];
         int par = 0;
@@ -1136,31 +1236,32 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
         // residual norm and stopping test before cycle c; the norm is fused
         // with cycle c's first sweep when possible
         auto head = [&](int c, int pc, hipStream_t st) -> hs_status {
+            double* const part = issuer(P, st).partials;
             if (fold) {
                 const Table<GridSeg>& J = S.jac[0];
                 HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(pc, 0), 1,
-                                          1, c, P->partials, st, 0, 0.0, 0,
+                                          1, c, part, st, 0, 0.0, 0,
                                           timer_events<double>(P, HS_TIMER_SWEEP1, L)));
                 HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 0, hsk::src_code(pc ^ 1, 0),
-                                          1, 2, c, P->partials, st, 0, mg.tol, mg.max_cycles,
+                                          1, 2, c, part, st, 0, mg.tol, mg.max_cycles,
                                           timer_events<double>(P, HS_TIMER_SWEEP2, L)));
             } else if (S.fused_norm && two) {
                 const Table<GridSeg>& J2 = S.pro[0];
                 HS_TRY(hsk::jac2<double>(P->ctl, J2.d, J2.nseg(), J2.nblk, order, A, hsk::src_code(pc, 0), 1, c,
-                                         P->partials, st));
-                HS_TRY(hsk::mg_decide(P->ctl, J2.d, J2.nseg(), J2.nblk, P->partials, c, mg.tol,
+                                         part, st));
+                HS_TRY(hsk::mg_decide(P->ctl, J2.d, J2.nseg(), J2.nblk, part, c, mg.tol,
                                       mg.max_cycles, L, st));
             } else if (S.fused_norm) {
                 const Table<GridSeg>& J = S.jac[0];
                 HS_TRY(hsk::sweep<double>(P->ctl, J.d, J.nseg(), J.nblk, order, A, 0, 1, hsk::src_code(pc, 0), 1,
-                                          1, c, P->partials, st, 0, 0.0, 0,
+                                          1, c, part, st, 0, 0.0, 0,
                                           timer_events<double>(P, HS_TIMER_SWEEP1, L)));
-                HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, P->partials, c, mg.tol,
+                HS_TRY(hsk::mg_decide(P->ctl, J.d, J.nseg(), J.nblk, part, c, mg.tol,
                                       mg.max_cycles, L, st));
             } else {
                 HS_TRY(hsk::mg_norm(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, order, A, c,
-                                    P->partials, pc, st));
-                HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, P->partials, c,
+                                    part, pc, st));
+                HS_TRY(hsk::mg_decide(P->ctl, S.fine.d, S.fine.nseg(), S.fine.nblk, part, c,
                                       mg.tol, mg.max_cycles, L, st));
             }
             return HS_OK;
@@ -1199,7 +1300,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
                 HS_CHECK(read_ctl_ahead(P, S, A, mg.nu1, mg.nu2, post, s));
                 if (synced) *synced = true;
                 int mc = 0;
-                if (all_mg_done(P, ls, &mc)) {
+                if (all_mg_done(P, ls, &mc, s)) {
                     pred = mc;
                     if (post) {
                         post->done = true;
@@ -1223,15 +1324,15 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
     for (int it = 0;; it++) {
         if (fixed && it >= limit) break;
         HS_TRY(hsk::ir_resid(P->ctl, S64.fine.d, S32.fine.d, S64.fine.nseg(), S64.fine.nblk, order, A,
-                             it, P->partials, s));
+                             it, issuer(P, s).partials, s));
         if (!fixed) {
-            HS_TRY(hsk::mg_decide(P->ctl, S64.fine.d, S64.fine.nseg(), S64.fine.nblk, P->partials, it,
+            HS_TRY(hsk::mg_decide(P->ctl, S64.fine.d, S64.fine.nseg(), S64.fine.nblk, issuer(P, s).partials, it,
                                   mg.tol, limit, L, s));
             if (it >= next_check || it >= limit) {
                 HS_CHECK(read_ctl(P, s));
                 if (synced) *synced = true;
                 int mc = 0;
-                if (all_mg_done(P, ls, &mc)) {
+                if (all_mg_done(P, ls, &mc, s)) {
                     pred = mc;
                     break;
                 }
@@ -1261,24 +1362,24 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
     int M = P->M[L];
     *outcome = SWEEP_RAN;
     if (!prep_done)
-        HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, 1, P->partials, s));
+        HS_TRY(hsk::sweep_prep(P->ctl, T.d, T.nseg(), T.nblk, with_resid ? 1 : 0, 1, issuer(P, s).partials, s));
     if (with_resid) {
-        HS_TRY(hsk::sdc_decide(P->ctl, T.d, T.nseg(), T.nblk, P->partials, P->pb.sdc_tol,
+        HS_TRY(hsk::sdc_decide(P->ctl, T.d, T.nseg(), T.nblk, issuer(P, s).partials, P->pb.sdc_tol,
                                P->pb.max_sweeps, s));
         HS_CHECK(read_ctl(P, s));
-        if (all_sdc_done(P, ls)) {
+        if (all_sdc_done(P, ls, s)) {
             *outcome = SWEEP_DONE;
             return HS_OK;
         }
     }
-    if (count) HS_TRY(hsk::begin_sweep(P->ctl, P->B, s));
+    if (count) HS_TRY(hsk::begin_sweep(P->ctl, ls.first, ls.span, s));
     if (P->np && L == 0) {
         // node-parallel sweep: every node's right-hand side from iterate k, the
         // M-1 solves of every lane as one batched multigrid solve, then F_I
         HS_TRY(hsk::np_rhs(P->ctl, T.d, T.nseg(), T.nblk, s));
         HS_CHECK(mg_solve(P, P->np_set, L, -1, 0, s, nullptr));
         HS_TRY(hsk::fi_march(P->ctl, F.d, T.d, T.nseg(), F.nblk, P->order[L], 1, M, -1, 1, s));
-        P->sweep_k++;
+        (*issuer(P, s).sweep_k)++;
         return HS_OK;
     }
     HS_TRY(hsk::make_rhs(P->ctl, T.d, T.nseg(), T.nblk, 0, 1, s));
@@ -1289,7 +1390,7 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
             HS_TRY(hsk::fi_march(P->ctl, F.d, T.d, T.nseg(), F.nblk, P->order[L], post.m0, post.m1, post.rhs_node,
                                  1, s));
     }
-    if (P->nlev == 1) P->sweep_k++;
+    if (P->nlev == 1) (*issuer(P, s).sweep_k)++;
     return HS_OK;
 }
 
@@ -1554,6 +1655,22 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
     HS_TRY(upload(P->hf_src, s));
     for (auto& t : P->hc_dst) HS_TRY(upload(t, s));
     for (auto& t : P->hc_src) HS_TRY(upload(t, s));
+    for (auto& ls : P->grp) HS_TRY(upload_set(P, ls, s));
+    for (auto* v : {&P->gh_dst, &P->gh_src, &P->gc_src})
+        for (auto& t : *v) HS_TRY(upload(t, s));
+    if (P->G) {
+        // the coarse pipeline's stream (default priority) and its thread's read-back state
+        if (!P->pipe) HS_TRY(hipStreamCreateWithFlags(&P->pipe, hipStreamNonBlocking));
+        if (!P->h_ctl2) HS_TRY(hipHostMalloc((void**)&P->h_ctl2, sizeof(LaneCtl) * P->nctl, hipHostMallocDefault));
+        if (!P->ev_ctl2) HS_TRY(hipEventCreateWithFlags(&P->ev_ctl2, hipEventDisableTiming));
+        if (!P->ev_go) HS_TRY(hipEventCreateWithFlags(&P->ev_go, hipEventDisableTiming));
+        for (auto* v : {&P->ev_r, &P->ev_c})
+            while ((int)v->size() < P->G) {
+                hipEvent_t e = nullptr;
+                HS_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                v->push_back(e);
+            }
+    }
     for (int L = 0; L < P->nlev; L++) HS_TRY(upload(P->offs[L], s));
     for (int b = 0; b < P->B; b++) {
         double t0 = P->pb.t0, nsteps = P->pb.nsteps;
@@ -1625,6 +1742,12 @@ hs_status hs_plan_destroy(hs_plan* P)
     if (P->h_ctl) (void)hipHostFree(P->h_ctl);
     if (P->ev_ctl) (void)hipEventDestroy(P->ev_ctl);
     for (hipEvent_t e : P->timer_ev) (void)hipEventDestroy(e);
+    if (P->pipe) (void)hipStreamDestroy(P->pipe);
+    if (P->h_ctl2) (void)hipHostFree(P->h_ctl2);
+    if (P->ev_ctl2) (void)hipEventDestroy(P->ev_ctl2);
+    if (P->ev_go) (void)hipEventDestroy(P->ev_go);
+    for (hipEvent_t e : P->ev_r) (void)hipEventDestroy(e);
+    for (hipEvent_t e : P->ev_c) (void)hipEventDestroy(e);
     delete P;
     return HS_OK;
 }
@@ -2058,6 +2181,188 @@ hs_status pfasst_predictor(hs_plan* P, hipStream_t s)
     return HS_OK;
 }
 
+// Hand-shake of the two threads that issue a pipelined PFASST run: each
+// side counts what it has recorded (a group's restriction, a group's coarse
+// sweeps, a block's start); the other side waits on the host for the count it
+// needs before it makes its stream wait on the event.  An event is recorded
+// again only after the other side's stream wait on its previous record has
+// been issued: each side's next record depends on what the other posts after
+// that wait.
+struct PipeSync {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<int> r, c;
+    int go = 0;
+    bool abort = false;
+    hs_status first = HS_OK;   // the failure that stopped the run
+    void post(int& count)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            count++;
+        }
+        cv.notify_all();
+    }
+    // false when the other side has given up
+    bool wait(const int& count, int need)
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return abort || count >= need; });
+        return count >= need;
+    }
+    // a side that fails stops both; a wait that returns false reports HS_ESTATE
+    void stop(hs_status st)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (!abort) first = st;
+            abort = true;
+        }
+        cv.notify_all();
+    }
+};
+
+// The end values of a group's last slice that the next group's hand-offs read.
+hipError_t snapshot(hs_plan* P, int g, int L, hipStream_t s)
+{
+    const LaneBufs& lb = P->lanes[(g + 1) * (P->B / P->G) - 1];
+    double* dst = L == 0 ? P->snap_f[g] : P->snap_c[g];
+    return hipMemcpyAsync(dst, lb.U[L] + (long long)(P->M[L] - 1) * lb.N[L], lb.N[L] * sizeof(double),
+                          hipMemcpyDeviceToDevice, s);
+}
+
+// Coarse side of a pipelined PFASST run (its own thread, stream P->pipe):
+// per block the predictor's serial coarse sweeps, then per iteration and
+// group, once the group's restriction is done, the coarse pipeline through
+// the group's slices.
+hs_status pipe_coarse(hs_plan* P, PipeSync& ps, int nblocks)
+{
+    hipStream_t c = P->pipe;
+    HS_TRY(hipSetDevice(P->device));
+    const int G = P->G, Q = P->B / G, K = P->pb.sweeps, pred = P->pb.pfasst_pred_sweeps;
+    std::vector<int> got_r(G, 0);
+    auto chain = [&](int g, bool predictor) -> hs_status {
+        int outcome;
+        for (int p = g * Q; p < (g + 1) * Q; p++) {
+            if (p > 0) {
+                // slice p's coarse start: slice p-1's end value (across a group boundary, its copy)
+                const Table<SdcSeg>& src = p == g * Q ? P->gc_src[g] : P->hc_src[p];
+                HS_TRY(hsk::handoff(P->ctl, P->hc_dst[p].d, src.d, 1, P->hc_dst[p].nblk, P->order[1], c));
+                if (predictor) {
+                    const Table<SdcSeg>& T = P->single[p].sdc[1];
+                    HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[1], 0, c));
+                }
+            }
+            for (int j = 0; j < (predictor ? pred : 1); j++)
+                HS_CHECK(sweep(P, P->single[p], 1, false, false, c, &outcome));
+        }
+        if (g + 1 < G) HS_TRY(snapshot(P, g, 1, c));
+        HS_TRY(hipEventRecord(P->ev_c[g], c));
+        ps.post(ps.c[g]);
+        return HS_OK;
+    };
+    for (int blk = 0; blk < nblocks; blk++) {
+        if (!ps.wait(ps.go, blk + 1)) return HS_ESTATE;
+        HS_TRY(hipStreamWaitEvent(c, P->ev_go, 0));
+        P->sweep_k2 = 0;
+        if (pred > 0)
+            for (int g = 0; g < G; g++) HS_CHECK(chain(g, true));
+        for (int k = 0; k < K; k++) {
+            P->sweep_k2 = k;
+            for (int g = 0; g < G; g++) {
+                if (!ps.wait(ps.r[g], ++got_r[g])) return HS_ESTATE;
+                HS_TRY(hipStreamWaitEvent(c, P->ev_r[g], 0));
+                HS_CHECK(chain(g, false));
+            }
+        }
+    }
+    return HS_OK;
+}
+
+// Fine side of a pipelined PFASST run (the caller's thread and stream): per
+// iteration and group, once the group's coarse sweeps of the previous
+// iteration (or of the predictor) are done, their interpolation, the copy of
+// the group's last end value for the next group, the group's fine hand-off,
+// its fine sweeps as one batch and its restriction.
+hs_status pipe_fine(hs_plan* P, PipeSync& ps, int nblocks, hipStream_t s)
+{
+    const int G = P->G, K = P->pb.sweeps, Mf = P->M[0];
+    const bool pred = P->pb.pfasst_pred_sweeps > 0;
+    std::vector<int> got_c(G, 0);
+    auto interp = [&](int g) -> hs_status {
+        if (!ps.wait(ps.c[g], ++got_c[g])) return HS_ESTATE;
+        HS_TRY(hipStreamWaitEvent(s, P->ev_c[g], 0));
+        const LaneSet& gs = P->grp[g];
+        HS_TRY(hsk::fas_interp(P->ctl, gs.fasf.d, gs.fasf.nseg(), gs.fasf.nblk, 1, s));
+        HS_TRY(hsk::fi_march(P->ctl, gs.mg64[0].fine.d, gs.sdc[0].d, gs.sdc[0].nseg(), gs.mg64[0].fine.nblk,
+                             P->order[0], 0, Mf, -1, 1, s));
+        return HS_OK;
+    };
+    for (int blk = 0; blk < nblocks; blk++) {
+        if (blk > 0) {
+            // the next block starts from the last slice's end value
+            const LaneBufs& last = P->lanes[P->B - 1];
+            for (int p = 0; p + 1 < P->B; p++) {
+                const LaneBufs& lb = P->lanes[p];
+                HS_TRY(hipMemcpyAsync(lb.U[0] + (Mf - 1) * lb.N[0], last.U[0] + (Mf - 1) * last.N[0],
+                                      lb.N[0] * 8, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        hipLaunchKernelGGL(k_pfasst_block, dim3((P->B + 63) / 64), dim3(64), 0, s, P->ctl, P->B, P->pb.t0,
+                           P->pb.dt, blk);
+        HS_TRY(hipGetLastError());
+        HS_CHECK(begin_step(P, s));
+        if (pred) {
+            // the predictor's restriction of the spread values, without the FAS correction
+            const LaneSet& all = P->all;
+            HS_TRY(hsk::fas_restrict(P->ctl, all.fasc.d, all.fasc.nseg(), all.fasc.nblk, P->order[1], 1, s));
+            for (int b = 0; b < P->B; b++)
+                HS_TRY(hsk::fill(P->lanes[b].tau, (long long)P->M[1] * P->lanes[b].N[1], 0.0, s));
+        }
+        HS_TRY(hipEventRecord(P->ev_go, s));
+        ps.post(ps.go);
+        for (int k = 0; k < K; k++) {
+            for (int g = 0; g < G; g++) {
+                LaneSet& gs = P->grp[g];
+                if (pred || k > 0) HS_CHECK(interp(g));
+                if (g + 1 < G) HS_TRY(snapshot(P, g, 0, s));
+                if (P->gh_dst[g].nseg() > 0)
+                    HS_TRY(hsk::handoff(P->ctl, P->gh_dst[g].d, P->gh_src[g].d, P->gh_dst[g].nseg(),
+                                        P->gh_dst[g].nblk, P->order[0], s));
+                int outcome;
+                HS_CHECK(sweep(P, gs, 0, false, true, s, &outcome));
+                HS_TRY(hsk::fas_restrict(P->ctl, gs.fasc.d, gs.fasc.nseg(), gs.fasc.nblk, P->order[1], 1, s));
+                HS_TRY(hipEventRecord(P->ev_r[g], s));
+                ps.post(ps.r[g]);
+            }
+            P->sweep_k++;
+        }
+        for (int g = 0; g < G; g++) HS_CHECK(interp(g));
+        HS_TRY(hsk::end_step(P->ctl, P->B, s));
+    }
+    return HS_OK;
+}
+
+hs_status pfasst_pipelined(hs_plan* P, int nblocks, hipStream_t s)
+{
+    PipeSync ps;
+    ps.r.assign(P->G, 0);
+    ps.c.assign(P->G, 0);
+    std::thread worker;
+    try {
+        worker = std::thread([&] {
+            hs_status st = pipe_coarse(P, ps, nblocks);
+            if (st != HS_OK) ps.stop(st);
+        });
+    } catch (...) {
+        return HS_EDEVICE;
+    }
+    hs_status st = pipe_fine(P, ps, nblocks, s);
+    if (st != HS_OK) ps.stop(st);
+    worker.join();
+    return ps.abort ? ps.first : HS_OK;
+}
+
 }  // namespace
 
 extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
@@ -2066,6 +2371,7 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
     if (P->pb.lane_memory) return HS_EINVAL;
     if (P->pb.nslices <= 1) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (P->G >= 2) return pfasst_pipelined(P, P->pb.nsteps / P->B, s);
     int Pn = P->B, Mf = P->M[0];
     int nblocks = P->pb.nsteps / Pn;
     const bool fixed = P->pb.sweeps > 0;

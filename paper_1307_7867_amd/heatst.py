@@ -46,7 +46,7 @@ class ProblemDesc(C.Structure):
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("batch", C.c_int32),
                 ("nslices", C.c_int32), ("h_lane_n", C.POINTER(C.c_int32)),
                 ("pfasst_pred_sweeps", C.c_int32), ("lane_memory", C.c_int32),
-                ("sdc_node_parallel", C.c_int32)]
+                ("sdc_node_parallel", C.c_int32), ("pfasst_groups", C.c_int32)]
 
 
 class LaneStats(C.Structure):
@@ -239,6 +239,7 @@ class Problem:
     lane_n: list | None = None
     pfasst_pred_sweeps: int = 0
     sdc_node_parallel: int = 0
+    pfasst_groups: int = 0
 
     def desc(self):
         d = ProblemDesc()
@@ -255,6 +256,7 @@ class Problem:
         d.batch, d.nslices = self.batch, self.nslices
         d.pfasst_pred_sweeps = self.pfasst_pred_sweeps
         d.sdc_node_parallel = self.sdc_node_parallel
+        d.pfasst_groups = self.pfasst_groups
         keep = None
         if self.lane_n is not None:
             keep = (C.c_int32 * len(self.lane_n))(*self.lane_n)

@@ -165,11 +165,22 @@ class StreamResult:
     dof_updates: float
 
 
-def replay(server: Server, requests, u0_of, time_scale=1.0, keep_results=False):
+def replay(server: Server, requests, u0_of, time_scale=1.0, keep_results=False, progress=None,
+           progress_every=30.0):
     """Submit `requests` (inputs.Request) at their arrival times (scaled) and
-    wait for all; latency = completion - arrival."""
+    wait for all; latency = completion - arrival.  progress(msg), when given,
+    is called about every `progress_every` seconds with the counts so far."""
     t_start = time.perf_counter()
+    t_note = t_start
     tickets = []
+
+    def note(force=False):
+        nonlocal t_note
+        now = time.perf_counter()
+        if progress is not None and (force or now - t_note >= progress_every):
+            t_note = now
+            progress(f"replay: {len(tickets)}/{len(requests)} submitted after {now - t_start:.0f} s")
+
     for r in requests:
         due = t_start + r.arrival * time_scale
         while True:
@@ -177,10 +188,19 @@ def replay(server: Server, requests, u0_of, time_scale=1.0, keep_results=False):
             if dtw <= 0:
                 break
             time.sleep(min(dtw, 0.002))
+            note()
         t_arr = time.perf_counter()
         tk = server.submit(r.n, r.nu, r.dt, r.nsteps, u0_of(r))
         tickets.append((tk, r, t_arr))
-    server.drain()
+    if progress is None:
+        server.drain()
+    else:
+        pending = [tk for tk, _, _ in tickets]
+        while pending:
+            pending = [tk for tk in pending if not server.poll(tk)[0]]
+            if pending:
+                time.sleep(0.05)
+                note()
     t_end = time.perf_counter()
     lat, infos = [], []
     dof = 0.0

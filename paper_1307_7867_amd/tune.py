@@ -15,7 +15,7 @@ paper_1307_7867_amd/tune_cache.json when it exists):
 Shapes only move work between blocks; every shape gives bitwise the same
 results (tests/test_gpu_tuning.py).
 
-    python -m paper_1307_7867_amd.tune [--out FILE] [--quick]
+    python -m paper_1307_7867_amd.tune [--out FILE] [--quick] [--missing]
 """
 from __future__ import annotations
 
@@ -29,11 +29,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tune_cache.json")
 
 # (n, order, precision, batch): the launch shapes of the benchmark's workloads
-# (PFASST 16 x 127^3/63^3, the MLSDC and SDC runs, the mixed-precision 255^3
-# run, the uneven batch and the serving classes)
+# (PFASST 16 x 127^3/63^3 in one batch or in slice groups of 8, 4 or 2, the MLSDC
+# and SDC runs, the mixed-precision 255^3 run, the uneven batch and the
+# serving classes)
 SHAPES = [
     (31, 4, 0, 1), (63, 4, 0, 1), (127, 4, 0, 1),
     (31, 4, 0, 16), (63, 4, 0, 16), (127, 4, 0, 16),
+    (31, 4, 0, 8), (63, 4, 0, 8), (127, 4, 0, 8),
+    (31, 4, 0, 4), (63, 4, 0, 4), (127, 4, 0, 4),
+    (31, 4, 0, 2), (63, 4, 0, 2), (127, 4, 0, 2),
     (31, 2, 0, 1), (63, 2, 0, 1), (31, 2, 0, 16), (63, 2, 0, 16),
     (31, 2, 0, 19), (63, 2, 0, 22), (127, 2, 0, 23),
     (255, 4, 0, 1), (63, 4, 1, 1), (127, 4, 1, 1), (255, 4, 1, 1),
@@ -65,11 +69,17 @@ def _time_cycles(hs, torch, n, order, prec, batch, cycles=3, reps=3):
     return best
 
 
-def tune(shapes=SHAPES, quick=False, log=print):
+def tune(shapes=SHAPES, quick=False, log=print, keep=()):
+    """Tune `shapes`; entries in `keep` (earlier results) are loaded first and
+    not tuned again."""
     import torch
     from . import heatst as hs
     hs.tune_clear()
-    entries = []
+    for e in keep:
+        hs.tune_set(e["n"], e["order"], e["precision"], e["batch"], e["zb"], e["zb_rfw"])
+    done = {(e["n"], e["order"], e["precision"], e["batch"]) for e in keep}
+    shapes = [sh for sh in shapes if tuple(sh) not in done]
+    entries = list(keep)
     for n, order, prec, batch in sorted(shapes, key=lambda s: (s[0], s[3])):
         builtin = hs.tune_lookup(n, order, prec, batch)
         t_builtin = _time_cycles(hs, torch, n, order, prec, batch)
@@ -103,11 +113,16 @@ def main():
     ap = argparse.ArgumentParser(description="tune the plane-marching launch shapes on this GPU")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
+    ap.add_argument("--missing", action="store_true",
+                    help="keep the entries already in --out and tune only the shapes it lacks")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     name = torch.cuda.get_device_properties(0).name
-    entries = tune(quick=args.quick, log=lambda m: print(m, file=sys.stderr, flush=True))
+    keep = []
+    if args.missing and os.path.exists(args.out):
+        keep = json.load(open(args.out)).get("entries", [])
+    entries = tune(quick=args.quick, log=lambda m: print(m, file=sys.stderr, flush=True), keep=keep)
     with open(args.out, "w") as f:
         json.dump({"device": name, "arch": "gfx950", "entries": entries}, f, indent=1)
     print(json.dumps({"entries": len(entries), "out": args.out}))

@@ -206,3 +206,29 @@ def test_pfasst_predictor_needs_slices():
     p = base_problem(n=31, order=4, nnodes=5, coarse=(15, 2, 3), batch=4, nslices=4, nsteps=4, sweeps=0,
                      pfasst_pred_sweeps=2)
     assert p.workspace_bytes() > 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(pfasst_groups=3),                                   # does not divide 4 slices
+    dict(pfasst_groups=8),                                   # more groups than slices
+    dict(pfasst_groups=-1),
+    dict(pfasst_groups=2, sweeps=0),                         # groups need fixed iterations
+    dict(pfasst_groups=2, cycle_graphs=1),
+])
+def test_pfasst_groups_validated(kw):
+    args = dict(n=31, order=4, nnodes=5, coarse=(15, 2, 3), batch=4, nslices=4, nsteps=4, sweeps=2)
+    args.update(kw)
+    with pytest.raises(heatst.HeatstError) as e:
+        base_problem(**args).workspace_bytes()
+    assert e.value.status == heatst.HS_EINVAL
+
+
+def test_pfasst_groups_add_snapshots_only():
+    """Two groups of two slices: the group tables, one fine and one coarse
+    end-value copy and a second block of partial maxima, nothing per slice."""
+    args = dict(n=31, order=4, nnodes=5, coarse=(15, 2, 3), batch=4, nslices=4, nsteps=4, sweeps=2)
+    b0 = base_problem(**args).workspace_bytes()
+    b2 = base_problem(pfasst_groups=2, **args).workspace_bytes()
+    snaps = (31 ** 3 + 15 ** 3) * 8
+    assert b0 + snaps <= b2 <= b0 + snaps + (1 << 20)
+    assert base_problem(pfasst_groups=1, **args).workspace_bytes() == b0

@@ -191,6 +191,35 @@ def test_pfasst_config_sizes_parity(torch, name):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("groups", [2, 4])
+def test_pfasst_groups_config_size_parity(torch, groups):
+    """16 slices of 63^3/31^3 with the coarse predictor in 2 or 4 slice
+    groups (the benchmark's pipelined schedule): the oracle's result, and bit
+    for bit the result without groups."""
+    from paper_1307_7867_amd import heatst as hs
+    name = "pfasst16_63_pred"
+    nf, P, K, cyc, dt, pred = PF_CASES[name]
+    outs = []
+    for g in (0, groups):
+        pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=((nf - 1) // 2, 2, 3), nu=0.1, dt=dt, nsteps=P,
+                        sweeps=K, fixed_cycles=cyc, batch=P, nslices=P, pfasst_pred_sweeps=pred,
+                        pfasst_groups=g)
+        plan = hs.Plan(pb)
+        plan.set_state(dev(torch, inputs.sine_product(nf)))
+        plan.pfasst_run()
+        outs.append(host(plan.get_state()).reshape(nf, nf, nf))
+        st, _ = plan.stats()
+        assert st == 0
+        del plan
+        torch.cuda.empty_cache()
+    assert np.array_equal(outs[0], outs[1])
+    ref, s, _ = background_ref(name, lambda: _pfasst_ref(name))
+    assert s == oracle.OK
+    err = rel(outs[1], ref)
+    print(f"{name}, {groups} groups: |gpu - oracle| / |oracle| = {err:.2e}")
+    assert err <= TOL
+
+
 # ----------------------------------------------------------------------------
 # uneven batch of 64 instances
 # ----------------------------------------------------------------------------

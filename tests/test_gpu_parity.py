@@ -443,6 +443,36 @@ def test_pfasst_parity(torch):
     assert rel(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("groups,pred", [(2, 0), (2, 1), (4, 1)])
+def test_pfasst_groups_parity(torch, groups, pred):
+    """Slice groups only reorder PFASST's operations (the fine sweeps of one
+    group beside the coarse pipeline of the group before it, on a second
+    stream): over two blocks the result equals the oracle's and, bit for bit,
+    the same plan without groups."""
+    hs = heatst_mod()
+    nf, P = 15, 4
+    u0 = inputs.random_smooth(nf, 11)
+    outs, sweeps = [], []
+    for g in (0, groups):
+        pb = mlsdc_problem(hs, nf, nu=0.1, dt=0.02, nsteps=2 * P, sweeps=3, tol=1e-12, batch=P, nslices=P,
+                           pfasst_pred_sweeps=pred, pfasst_groups=g)
+        plan = hs.Plan(pb)
+        plan.set_state(dev(torch, u0))
+        plan.pfasst_run()
+        outs.append(host(plan.get_state()).reshape(nf, nf, nf))
+        st, stats = plan.stats()
+        assert st == 0
+        sweeps.append([(x["total_sweeps"], x["level_cycles"]) for x in stats])
+        del plan
+    ref, s, _ = oracle.pfasst(oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, dt=0.02,
+                                             nsteps=2 * P, sweeps=3, mg=oracle.mg_params(tol=1e-12)),
+                              P, u0, pred_sweeps=pred)
+    assert s == oracle.OK
+    assert rel(outs[1], ref) <= TOL
+    assert np.array_equal(outs[0], outs[1])
+    assert sweeps[0] == sweeps[1]
+
+
 # ----------------------------------------------------------------------------
 # batching
 # ----------------------------------------------------------------------------
