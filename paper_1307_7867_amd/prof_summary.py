@@ -1,13 +1,19 @@
 """Summaries of rocprofv3 output for the measurement records under profiles/.
 
-    python -m paper_1307_7867_amd.prof_summary stats <kernel_trace.csv> [--t0 NAME] [--top K]
+    python -m paper_1307_7867_amd.prof_summary stats <kernel_trace.csv> [--top K]
+            [--split REGEX:BLOCKS:PERIOD]
         per-kernel totals over the whole trace and, per launch size (blocks),
         the calls / mean / median duration of each kernel (markdown).
     python -m paper_1307_7867_amd.prof_summary traffic <fetch_counter.csv> <write_counter.csv>
-            --kernel REGEX --blocks N --bytes-per-launch B --src FILE --out JSON
+            --kernel REGEX --blocks N [--period P --phase Q] --bytes-per-launch B --src FILE --out JSON
         FETCH_SIZE / WRITE_SIZE per dispatch (KiB, mean over the kernel's
         launches of N blocks), scaled by what the same counters read for the device copies of
         bench.py --calibration-copy (512 MiB each), as bytes per launch.
+
+Launches of one kernel with the same block count on two grid levels (a
+V-cycle launches the kernel on each level in turn) are told apart by their
+order: --split / --period take them in dispatch order and number them
+0..PERIOD-1 cyclically; --phase keeps one of those phases.
 """
 from __future__ import annotations
 
@@ -39,16 +45,25 @@ def blocks(row) -> int:
     return g // max(1, w)
 
 
-def stats(trace, top=30):
-    rows = list(csv.DictReader(open(trace)))
+def stats(trace, top=30, split=None):
+    rows = sorted(csv.DictReader(open(trace)), key=lambda r: int(r["Dispatch_Id"]))
     tot = defaultdict(lambda: [0, 0.0])
     per = defaultdict(list)
+    sp_re, sp_blk, sp_per = None, 0, 1
+    if split:
+        sp_re, b, pr = split.rsplit(":", 2)
+        sp_blk, sp_per = int(b), int(pr)
+    seen = 0
     for r in rows:
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
         k = short(r["Kernel_Name"])
         tot[k][0] += 1
         tot[k][1] += d
-        per[(k, blocks(r))].append(d)
+        b = blocks(r)
+        if sp_re and b == sp_blk and re.search(sp_re, r["Kernel_Name"]):
+            k = f"{k} [phase {seen % sp_per}]"
+            seen += 1
+        per[(k, b)].append(d)
     all_us = sum(v[1] for v in tot.values())
     out = ["| kernel | calls | avg us | total ms | share |", "|---|---:|---:|---:|---:|"]
     for k, (c, t) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:top]:
@@ -69,15 +84,16 @@ def _counter_rows(path):
     return out
 
 
-def _per_dispatch(rows, regex, nblk=None):
+def _per_dispatch(rows, regex, nblk=None, period=1, phase=0):
     acc = defaultdict(float)
     for disp, name, b, cname, val in rows:
         if re.search(regex, name) and (nblk is None or b == nblk):
             acc[disp] += val
-    return [acc[k] for k in sorted(acc)]
+    vals = [acc[k] for k in sorted(acc)]
+    return vals[phase::period]
 
 
-def traffic(fetch_csv, write_csv, kernel, nblk, bytes_per_launch, src, out):
+def traffic(fetch_csv, write_csv, kernel, nblk, bytes_per_launch, src, out, period=1, phase=0):
     copy_bytes = 512 * 1024 * 1024
     f_rows, w_rows = _counter_rows(fetch_csv), _counter_rows(write_csv)
     f_cal = _per_dispatch(f_rows, "copyBuffer|copy")
@@ -87,10 +103,13 @@ def traffic(fetch_csv, write_csv, kernel, nblk, bytes_per_launch, src, out):
     f_fac = copy_bytes / 1024 / statistics.median(f_cal)
     w_fac = copy_bytes / 1024 / statistics.median(w_cal)
     # mean over every dispatch: launches differ in how many lanes are still active
-    fd, wd = _per_dispatch(f_rows, kernel, nblk), _per_dispatch(w_rows, kernel, nblk)
+    fd, wd = _per_dispatch(f_rows, kernel, nblk, period, phase), _per_dispatch(w_rows, kernel, nblk, period, phase)
     fk, wk = statistics.mean(fd), statistics.mean(wd)
+    # the other phases' means, to show the levels apart
+    others = {q: statistics.mean(_per_dispatch(f_rows, kernel, nblk, period, q)) for q in range(period) if q != phase}
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    rec = {"kernel": kernel, "blocks": nblk, "kernel_src_sha": sha, "dispatches": [len(fd), len(wd)],
+    rec = {"kernel": kernel, "blocks": nblk, "period": period, "phase": phase,
+           "fetch_kib_other_phases": others, "kernel_src_sha": sha, "dispatches": [len(fd), len(wd)],
            "fetch_kib": fk, "write_kib": wk,
            "fetch_factor": f_fac, "write_factor": w_fac, "calibration_fetch_kib": f_cal,
            "calibration_write_kib": w_cal,
@@ -108,19 +127,23 @@ def main():
     s = sub.add_parser("stats")
     s.add_argument("trace")
     s.add_argument("--top", type=int, default=30)
+    s.add_argument("--split", default=None)
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
     t.add_argument("--kernel", required=True)
     t.add_argument("--blocks", type=int, required=True)
     t.add_argument("--bytes-per-launch", type=float, required=True)
+    t.add_argument("--period", type=int, default=1)
+    t.add_argument("--phase", type=int, default=0)
     t.add_argument("--src", required=True)
     t.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
-        print(stats(a.trace, a.top))
+        print(stats(a.trace, a.top, a.split))
     else:
-        print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.blocks, a.bytes_per_launch, a.src, a.out), indent=1))
+        print(json.dumps(traffic(a.fetch, a.write, a.kernel, a.blocks, a.bytes_per_launch, a.src, a.out,
+                                 a.period, a.phase), indent=1))
 
 
 if __name__ == "__main__":
