@@ -44,7 +44,12 @@ struct LaneCtl {
     int32_t failed_solves;
     int32_t parent;              // node-parallel solver lane: its SDC lane, else -1
     long long level_cycles[2];   // cycles of the solves on SDC level 0 / 1
+    // Every lane's state fills whole 256-byte blocks: lanes that kernels on
+    // different streams update at the same time (PFASST slice groups) never
+    // share a cache line.
+    char pad_[160];
 };
+static_assert(sizeof(LaneCtl) % 256 == 0, "lane states must not share cache lines");
 
 // One grid of one lane at one multigrid level.  The finest grid of an SDC
 // solve lives inside the node array: its iterate is u + node * node_stride.

@@ -960,9 +960,32 @@ Issuer issuer(hs_plan* P, hipStream_t s)
     return {P->partials, P->h_ctl, P->ev_ctl, &P->sweep_k};
 }
 
-hs_status read_ctl(hs_plan* P, hipStream_t s)
+// The range of lane states that holds the lanes of ls (all of them for a
+// null set).  A read-back copies only that range, so a stream never reads the
+// lane states that kernels on another stream are writing.
+void ctl_range(const hs_plan* P, const LaneSet* ls, int* first, int* count)
 {
-    HS_TRY(hipMemcpyAsync(issuer(P, s).h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
+    if (!ls || ls->lanes.empty()) {
+        *first = 0;
+        *count = P->nctl;
+        return;
+    }
+    const auto mm = std::minmax_element(ls->lanes.begin(), ls->lanes.end());
+    *first = *mm.first;
+    *count = *mm.second - *mm.first + 1;
+}
+
+hipError_t copy_ctl(hs_plan* P, const LaneSet* ls, hipStream_t s)
+{
+    int first, count;
+    ctl_range(P, ls, &first, &count);
+    return hipMemcpyAsync(issuer(P, s).h_ctl + first, P->ctl + first, sizeof(LaneCtl) * count,
+                          hipMemcpyDeviceToHost, s);
+}
+
+hs_status read_ctl(hs_plan* P, hipStream_t s, const LaneSet* ls = nullptr)
+{
+    HS_TRY(copy_ctl(P, ls, s));
     HS_TRY(hipStreamSynchronize(s));
     return HS_OK;
 }
@@ -1184,12 +1207,12 @@ struct PostSolve {
 // run while the host waits for the copy and decides.  If every lane has
 // stopped they were the real launches; otherwise they did the stopped lanes'
 // share, and the launches after the solve repeat it with the same result.
-hs_status read_ctl_ahead(hs_plan* P, const MgSet& S, hsk::MgArgs A, int nu1, int nu2, const PostSolve* post,
-                         hipStream_t s)
+hs_status read_ctl_ahead(hs_plan* P, const LaneSet& ls, const MgSet& S, hsk::MgArgs A, int nu1, int nu2,
+                         const PostSolve* post, hipStream_t s)
 {
-    if (!post) return read_ctl(P, s);
+    if (!post) return read_ctl(P, s, &ls);
     const Issuer I = issuer(P, s);
-    HS_TRY(hipMemcpyAsync(I.h_ctl, P->ctl, sizeof(LaneCtl) * P->nctl, hipMemcpyDeviceToHost, s));
+    HS_TRY(copy_ctl(P, &ls, s));
     HS_TRY(hipEventRecord(I.ev_ctl, s));
     hsk::MgArgs G = A;
     G.gate = 2;
@@ -1297,7 +1320,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             if (!head_done) HS_CHECK(head(c, par, s));
             head_done = false;
             if (c >= next_check || c >= mg.max_cycles) {
-                HS_CHECK(read_ctl_ahead(P, S, A, mg.nu1, mg.nu2, post, s));
+                HS_CHECK(read_ctl_ahead(P, ls, S, A, mg.nu1, mg.nu2, post, s));
                 if (synced) *synced = true;
                 int mc = 0;
                 if (all_mg_done(P, ls, &mc, s)) {
@@ -1329,7 +1352,7 @@ hs_status mg_solve(hs_plan* P, LaneSet& ls, int L, int m, int node, hipStream_t 
             HS_TRY(hsk::mg_decide(P->ctl, S64.fine.d, S64.fine.nseg(), S64.fine.nblk, issuer(P, s).partials, it,
                                   mg.tol, limit, L, s));
             if (it >= next_check || it >= limit) {
-                HS_CHECK(read_ctl(P, s));
+                HS_CHECK(read_ctl(P, s, &ls));
                 if (synced) *synced = true;
                 int mc = 0;
                 if (all_mg_done(P, ls, &mc, s)) {
@@ -1366,7 +1389,7 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
     if (with_resid) {
         HS_TRY(hsk::sdc_decide(P->ctl, T.d, T.nseg(), T.nblk, issuer(P, s).partials, P->pb.sdc_tol,
                                P->pb.max_sweeps, s));
-        HS_CHECK(read_ctl(P, s));
+        HS_CHECK(read_ctl(P, s, &ls));
         if (all_sdc_done(P, ls, s)) {
             *outcome = SWEEP_DONE;
             return HS_OK;
@@ -2468,8 +2491,8 @@ extern "C" hs_status hs_plan_timer_read(hs_plan* P, int32_t* launches, double* t
     HS_CHECK(check_bound(P));
     if (!launches || !total_ms) return HS_EINVAL;
     double ms = 0.0;
-    if (P->timer_used > 0) HS_TRY(hipEventSynchronize(P->timer_ev[2 * P->timer_used - 1]));
     for (int i = 0; i < P->timer_used; i++) {
+        HS_TRY(hipEventSynchronize(P->timer_ev[2 * i + 1]));
         float t = 0.0f;
         HS_TRY(hipEventElapsedTime(&t, P->timer_ev[2 * i], P->timer_ev[2 * i + 1]));
         ms += t;

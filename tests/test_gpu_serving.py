@@ -5,8 +5,8 @@ agrees with the FP64 oracle within the mixed-precision tolerance of 1e-10
 refinement to a relative residual of 1e-12 and sweeps SDC to a collocation
 residual of 1e-10.  A 127^3 request is compared with the oracle (its
 reference takes minutes on one core and runs in a background thread from
-the start of the session); a 255^3 request, too large for the oracle, with
-the plain FP64 GPU path."""
+the start of the session); a 255^3 and a 511^3 request, too large for the
+oracle, with the plain FP64 GPU path."""
 import numpy as np
 import pytest
 
@@ -113,15 +113,15 @@ def test_serving_127_request_vs_oracle(torch):
     assert err <= 1e-10
 
 
-def test_serving_255_request_vs_fp64_gpu(torch):
-    """A 255^3 request (mixed precision) against the plain per-request FP64
-    path (V(2,1) cycles to 1e-12) on the GPU: same SDC sweep count, within
-    1e-10."""
+@pytest.mark.parametrize("n,nu,dt,nsteps,seed", [(255, 0.12, 0.02, 2, 23), (511, 0.1, 0.01, 1, 29)])
+def test_serving_large_request_vs_fp64_gpu(torch, n, nu, dt, nsteps, seed):
+    """A 255^3 or 511^3 request (mixed precision) against the plain
+    per-request FP64 path (V(2,1) cycles to 1e-12) on the GPU: same SDC sweep
+    count, within 1e-10."""
     from paper_1307_7867_amd import heatst as hs
     from paper_1307_7867_amd import serving
-    n, nu, dt, nsteps, seed = 255, 0.12, 0.02, 2, 23
     u0 = torch.from_numpy(inputs.random_smooth(n, seed).ravel()).cuda()
-    srv = serving.Server({255: 1}, precision=hs.HS_MIXED, tol=1e-12, sdc_tol=1e-10, max_sweeps=40)
+    srv = serving.Server({n: 1}, precision=hs.HS_MIXED, tol=1e-12, sdc_tol=1e-10, max_sweeps=40)
     tk = srv.submit(n, nu, dt, nsteps, u0)
     srv.drain()
     done, info = srv.poll(tk)
@@ -138,10 +138,12 @@ def test_serving_255_request_vs_fp64_gpu(torch):
     assert pst == 0
     ref = plain.get_state().cpu().numpy()
     err = np.abs(got - ref).max() / np.abs(ref).max()
-    print(f"255^3 request: sweeps served {info.stats.total_sweeps} plain {pstats[0]['total_sweeps']}, "
+    print(f"{n}^3 request: sweeps served {info.stats.total_sweeps} plain {pstats[0]['total_sweeps']}, "
           f"|served - plain| / |plain| = {err:.2e}")
     assert info.stats.total_sweeps == pstats[0]["total_sweeps"]
     assert err <= 1e-10
+    del plain, u0
+    torch.cuda.empty_cache()
 
 
 def test_serving_queues_when_slots_are_full(torch):
