@@ -58,7 +58,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 NF, NC, MF, MC, ITERS, SLICES, DT = 127, 63, 5, 3, 4, 16, 0.01
 PJAC_BYTES = 25          # per fine grid point: read u, b (16), coarse e at 1/8 density (1), write u' (8)
-KERNEL_SRC = os.path.join(ROOT, "paper_1307_7867_amd", "csrc", "hs_kernels.hip")
+# the kernels and the structures they read (the traffic record is void once either changes)
+KERNEL_SRC = [os.path.join(ROOT, "paper_1307_7867_amd", "csrc", f) for f in ("hs_kernels.hip", "hs_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pjac_fp64_order4_pfasst16.traffic.json")
 
 
@@ -78,8 +79,11 @@ def problem(hs, nblocks, groups=0, **kw):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline():

@@ -5,7 +5,7 @@
         per-kernel totals over the whole trace and, per launch size (blocks),
         the calls / mean / median duration of each kernel (markdown).
     python -m paper_1307_7867_amd.prof_summary traffic <fetch_counter.csv> <write_counter.csv>
-            --kernel REGEX --blocks N [--period P --phase Q] --bytes-per-launch B --src FILE --out JSON
+            --kernel REGEX --blocks N [--period P --phase Q] --bytes-per-launch B --src FILE [FILE ...] --out JSON
         FETCH_SIZE / WRITE_SIZE per dispatch (KiB, mean over the kernel's
         launches of N blocks), scaled by what the same counters read for the device copies of
         bench.py --calibration-copy (512 MiB each), as bytes per launch.
@@ -107,7 +107,10 @@ def traffic(fetch_csv, write_csv, kernel, nblk, bytes_per_launch, src, out, peri
     fk, wk = statistics.mean(fd), statistics.mean(wd)
     # the other phases' means, to show the levels apart
     others = {q: statistics.mean(_per_dispatch(f_rows, kernel, nblk, period, q)) for q in range(period) if q != phase}
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in src:            # the hash bench.py compares: the sources in this order
+        h.update(open(path, "rb").read())
+    sha = h.hexdigest()[:16]
     rec = {"kernel": kernel, "blocks": nblk, "period": period, "phase": phase,
            "fetch_kib_other_phases": others, "kernel_src_sha": sha, "dispatches": [len(fd), len(wd)],
            "fetch_kib": fk, "write_kib": wk,
@@ -136,7 +139,7 @@ def main():
     t.add_argument("--bytes-per-launch", type=float, required=True)
     t.add_argument("--period", type=int, default=1)
     t.add_argument("--phase", type=int, default=0)
-    t.add_argument("--src", required=True)
+    t.add_argument("--src", required=True, nargs="+")
     t.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
