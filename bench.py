@@ -38,6 +38,10 @@ iteration of the first slice of the same workload.
 serial_mlsdc_equal_work: the same 16 K steps by one-lane MLSDC with 4
 iterations per step, the speedup of the PFASST run over it.
 
+one_batch: the same run without slice groups (all 16 slices' fine sweeps in
+one batch, then the coarse pipeline), with k_pjac timed on 16 x 127^3 finest
+grids, a working set far beyond the Infinity Cache.
+
 extra: the other configurations as records of their own -- 15^3 SDC
 latency, the 127^3/63^3 MLSDC run with the coarse/fine sweep-time ratio,
 the eq. (10) PFASST model, node-parallel against sequential SDC sweeps,
@@ -160,7 +164,32 @@ def headline(args, torch, hs, inputs):
                            fine_solves, err, stats, shapes, builtin_s)
     if not args.no_serial_compare:
         out["serial_mlsdc_equal_work"] = serial_mlsdc_run(args, torch, hs, inputs, u0, elapsed)
+    if args.groups >= 2 and not args.no_one_batch:
+        out["one_batch"] = one_batch_run(args, torch, hs, u0, elapsed)
     return out
+
+
+def one_batch_run(args, torch, hs, u0, grouped_s):
+    """The same blocks with all 16 slices' fine sweeps in one batch (no slice
+    groups): its k_pjac launches cover 16 x 127^3 finest grids, a working set
+    (16 lanes x u, t, b = 786 MB) far beyond the Infinity Cache."""
+    plan = hs.Plan(problem(hs, args.steps, 0))
+    plan.set_state(u0)
+    plan.timer(hs.HS_TIMER_PJAC, 8192)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.pfasst_run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    launches, kms = plan.timer_read()
+    st, stats = plan.stats()
+    hs.check(st, "bench one-batch PFASST run")
+    del plan
+    byts = PJAC_BYTES * NF ** 3 * sum(x["level_cycles"][0] for x in stats)
+    gbs = byts / (kms * 1e-3) / 1e9
+    log(f"one batch: {el:.3f} s; k_pjac {launches} launches {kms / launches * 1e3:.1f} us, {gbs:.0f} GB/s")
+    return {"seconds": el, "groups_speedup": el / grouped_s, "pjac_launches": launches,
+            "pjac_us_per_launch": kms / launches * 1e3, "pjac_achieved_GBps": gbs, "pjac_frac": gbs / PEAK_HBM_GBS}
 
 
 def serial_mlsdc_run(args, torch, hs, inputs, u0, pfasst_s):
@@ -253,6 +282,8 @@ def main():
                     help="PFASST slice groups whose fine sweeps overlap the coarse pipeline (0: one batch)")
     ap.add_argument("--no-serial-compare", action="store_true",
                     help="skip the serial MLSDC run of the same steps")
+    ap.add_argument("--no-one-batch", action="store_true",
+                    help="skip the run without slice groups (k_pjac on 16 x 127^3)")
     ap.add_argument("--no-builtin-compare", action="store_true",
                     help="skip the second headline run with the built-in launch shapes")
     ap.add_argument("--plain-capacity", type=float, default=0.0,
