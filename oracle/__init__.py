@@ -49,7 +49,7 @@ class Problem(C.Structure):
     _fields_ = [("nu", C.c_double), ("t0", C.c_double), ("dt", C.c_double),
                 ("forcing_c", C.c_double), ("nsteps", C.c_int32), ("sweeps", C.c_int32),
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("nlevels", C.c_int32),
-                ("lev", Level * 2), ("mg", MG), ("node_parallel", C.c_int32)]
+                ("lev", Level * 2), ("mg", MG), ("node_parallel", C.c_int32), ("fas_interp", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -76,6 +76,7 @@ def lib():
         L.or_jacobi.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _D, _D, _D]
         L.or_restrict_fw.argtypes = [C.c_int, _D, _D]
         L.or_prolong_add.argtypes = [C.c_int, _D, _D]
+        L.or_prolong_add_cubic.argtypes = [C.c_int, _D, _D]
         L.or_inject.argtypes = [C.c_int, _D, _D]
         L.or_dense_solve.argtypes = [C.c_int, C.c_int, C.c_double, _D, _D]
         L.or_mg_solve.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(MG), _D, _D,
@@ -94,7 +95,7 @@ def lib():
                                          C.c_double, C.c_double, _D, _D, C.POINTER(Stats)]
         L.or_fas_restrict.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, C.c_double,
                                       C.c_double, C.c_double, _D, _D, _D, _D, _D, _D]
-        L.or_fas_interp.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, _D, _D, _D, _D]
+        L.or_fas_interp.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, _D, _D, _D, _D, C.c_int]
         L.or_mlsdc_iter.argtypes = [C.POINTER(Problem), C.c_double, _D, _D, _D, _D, _D, _D,
                                     C.POINTER(Stats)]
         L.or_run.argtypes = [C.POINTER(Problem), _D, C.POINTER(Stats)]
@@ -124,9 +125,10 @@ def level(n, order, M) -> Level:
 
 
 def problem(levels, nu=0.1, t0=0.0, dt=0.1, nsteps=1, forcing_c=3.0, sweeps=4, sdc_tol=1e-10,
-            max_sweeps=20, mg=None, node_parallel=0) -> Problem:
+            max_sweeps=20, mg=None, node_parallel=0, fas_interp=1) -> Problem:
     pb = Problem()
     pb.node_parallel = node_parallel
+    pb.fas_interp = fas_interp
     pb.nu, pb.t0, pb.dt, pb.forcing_c = nu, t0, dt, forcing_c
     pb.nsteps, pb.sweeps, pb.sdc_tol, pb.max_sweeps = nsteps, sweeps, sdc_tol, max_sweeps
     pb.nlevels = len(levels)
@@ -180,6 +182,13 @@ def restrict_fw(rf):
 def prolong_add(ec, uf):
     ec = _f(ec); out = _f(uf).copy()
     lib().or_prolong_add(ec.shape[0], _p(ec), _p(out))
+    return out
+
+
+def prolong_add_cubic(ec, uf):
+    """uf + tricubic interpolation of ec (the FAS correction transfer with fas_interp = 3)."""
+    ec = _f(ec); out = _f(uf).copy()
+    lib().or_prolong_add_cubic(ec.shape[0], _p(ec), _p(out))
     return out
 
 
@@ -269,9 +278,9 @@ def fas_restrict(lf, lc, nu, tn, dt, c, Uf, FIf):
     return Uc, FIc, Ut, tau
 
 
-def fas_interp(lf, lc, nu, Uf, FIf, Uc, Ut):
-    """In-place on Uf, FIf."""
-    lib().or_fas_interp(C.byref(lf), C.byref(lc), nu, _p(Uf), _p(FIf), _p(_f(Uc)), _p(_f(Ut)))
+def fas_interp(lf, lc, nu, Uf, FIf, Uc, Ut, interp=1):
+    """In-place on Uf, FIf; interp 1 trilinear, 3 tricubic in space."""
+    lib().or_fas_interp(C.byref(lf), C.byref(lc), nu, _p(Uf), _p(FIf), _p(_f(Uc)), _p(_f(Ut)), interp)
 
 
 def mlsdc_iter(pb, tn, Uf, FIf, Uc, FIc, Ut, tau):

@@ -62,6 +62,8 @@ typedef struct {
     or_level lev[2];     /* lev[0] fine, lev[1] coarse */
     or_mg mg;
     int32_t node_parallel; /* single-level SDC: 1 = node-parallel sweeps (or_sdc_sweep_nodes) */
+    int32_t fas_interp;    /* MLSDC / PFASST: spatial interpolation of the coarse correction,
+                              1 (or 0) trilinear, 3 tricubic (or_prolong_add_cubic) */
 } or_problem;
 
 typedef struct {
@@ -283,6 +285,62 @@ void or_prolong_add(int nc, const double *ec, double *uf)
                             if (I < 0 || I >= nc || J < 0 || J >= nc || K < 0 || K >= nc) continue;
                             s += wx[a] * wy[b] * wz[c] * ec[((size_t)K * nc + J) * nc + I];
                         }
+                uf[((size_t)k * nf + j) * nf + i] += s;
+            }
+}
+
+/*
+ * Tricubic interpolation added to a fine field: uf += P3 ec.  Per axis a
+ * fine point that coincides with a coarse point takes its value; a point
+ * halfway between coarse points takes the cubic Lagrange interpolant
+ * through the two coarse points on either side, weights (-1, 9, 9, -1)/16.
+ * A tap on a wall is 0; a tap one coarse cell beyond a wall takes the odd
+ * reflection of the value one cell inside it (u(-x) = -u(x) about the wall),
+ * which continues the zero Dirichlet data the way sine modes do.  The fine
+ * value is the sum over the taps of wx wy wz ec, taps in x, y, z order.
+ */
+static double cubic_tap(const double *ec, int nc, int I, int J, int K)
+{
+    int idx[3] = {I, J, K};
+    double sign = 1.0;
+    for (int d = 0; d < 3; d++) {
+        if (idx[d] == -1 || idx[d] == nc) return 0.0;
+        if (idx[d] == -2) { idx[d] = 0; sign = -sign; }
+        else if (idx[d] == nc + 1) { idx[d] = nc - 1; sign = -sign; }
+    }
+    return sign * ec[((size_t)idx[2] * nc + idx[1]) * nc + idx[0]];
+}
+
+static void cubic_weights(int i, int idx[4], double wt[4], int *cnt)
+{
+    if (i % 2 == 1) {            /* coincides with coarse (i-1)/2 */
+        idx[0] = (i - 1) / 2; wt[0] = 1.0; *cnt = 1;
+    } else {                     /* between coarse i/2-1 and i/2 */
+        int m = i / 2;
+        idx[0] = m - 2; wt[0] = -1.0 / 16.0;
+        idx[1] = m - 1; wt[1] = 9.0 / 16.0;
+        idx[2] = m;     wt[2] = 9.0 / 16.0;
+        idx[3] = m + 1; wt[3] = -1.0 / 16.0;
+        *cnt = 4;
+    }
+}
+
+void or_prolong_add_cubic(int nc, const double *ec, double *uf)
+{
+    int nf = 2 * nc + 1;
+    for (int k = 0; k < nf; k++)
+        for (int j = 0; j < nf; j++)
+            for (int i = 0; i < nf; i++) {
+                int ix[4], iy[4], iz[4], cx, cy, cz;
+                double wx[4], wy[4], wz[4];
+                cubic_weights(i, ix, wx, &cx);
+                cubic_weights(j, iy, wy, &cy);
+                cubic_weights(k, iz, wz, &cz);
+                double s = 0.0;
+                for (int c = 0; c < cz; c++)
+                    for (int b = 0; b < cy; b++)
+                        for (int a = 0; a < cx; a++)
+                            s += wx[a] * wy[b] * wz[c] * cubic_tap(ec, nc, ix[a], iy[b], iz[c]);
                 uf[((size_t)k * nf + j) * nf + i] += s;
             }
 }
@@ -810,14 +868,16 @@ void or_fas_restrict(const or_level *Lf, const or_level *Lc, double nu, double t
 }
 
 /*
- * Interpolation of the coarse correction back to the fine MLSDC level.
+ * Interpolation of the coarse correction back to the fine MLSDC level
+ * (section 1.1; the paper leaves the transfer operators to its references).
  * dU_m = Uc_m - Ut_m at every coarse node; a fine node coinciding with a
- * coarse node takes P dU (trilinear in space), the others take
- * P(sum_j l_j(tau_f) dU_j) (Lagrange in time on the coarse nodes).  Then
- * f^I is recomputed on the fine level at every node.
+ * coarse node takes P dU, the others take P(sum_j l_j(tau_f) dU_j)
+ * (Lagrange in time on the coarse nodes), with P trilinear (interp 1 or 0)
+ * or tricubic (interp 3) in space.  Then f^I is recomputed on the fine
+ * level at every node.
  */
 void or_fas_interp(const or_level *Lf, const or_level *Lc, double nu, double *Uf, double *FIf,
-                   const double *Uc, const double *Ut)
+                   const double *Uc, const double *Ut, int interp)
 {
     int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
     size_t Nf = cube(nf), Nc = cube(nc);
@@ -838,7 +898,8 @@ void or_fas_interp(const or_level *Lf, const or_level *Lc, double nu, double *Uf
                 ec[p] = s;
             }
         }
-        or_prolong_add(nc, ec, Uf + (size_t)mf * Nf);
+        if (interp == 3) or_prolong_add_cubic(nc, ec, Uf + (size_t)mf * Nf);
+        else or_prolong_add(nc, ec, Uf + (size_t)mf * Nf);
     }
     for (int mf = 0; mf < Mf; mf++)
         or_lap_apply(nf, Lf->order, 0.0, nu, Uf + (size_t)mf * Nf, FIf + (size_t)mf * Nf);
@@ -857,7 +918,7 @@ int or_mlsdc_iter(const or_problem *pb, double tn, double *Uf, double *FIf, doub
     or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, Uc, FIc, Ut, tau);
     int s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc, FIc, tau, NULL);
     if (s != OR_OK && status == OR_OK) status = s;
-    or_fas_interp(Lf, Lc, pb->nu, Uf, FIf, Uc, Ut);
+    or_fas_interp(Lf, Lc, pb->nu, Uf, FIf, Uc, Ut, pb->fas_interp);
     return status;
 }
 
@@ -905,6 +966,7 @@ static int check_problem(const or_problem *pb)
     }
     if (!(pb->dt > 0.0) || !(pb->nu > 0.0) || pb->nsteps < 0) return OR_EINVAL;
     if (pb->node_parallel != 0 && (pb->node_parallel != 1 || pb->nlevels != 1)) return OR_EINVAL;
+    if (pb->fas_interp != 0 && pb->fas_interp != 1 && pb->fas_interp != 3) return OR_EINVAL;
     return OR_OK;
 }
 
@@ -1002,7 +1064,7 @@ int or_pfasst(const or_problem *pb, int P, int pred_sweeps, double *u, or_stats 
                 }
             }
             for (int p = 0; p < P; p++)
-                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC);
+                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC, pb->fas_interp);
         }
         for (k = 0;; k++) {
             if (pb->sweeps > 0 && k >= pb->sweeps) break;
@@ -1049,7 +1111,7 @@ int or_pfasst(const or_problem *pb, int P, int pred_sweeps, double *u, or_stats 
             }
             /* (iv) interpolation */
             for (int p = 0; p < P; p++)
-                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC);
+                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC, pb->fas_interp);
         }
         memcpy(u, Uf + (size_t)(P - 1) * SF + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
     }

@@ -704,3 +704,98 @@ def test_collocation_inverse_bound():
         Ai = np.linalg.inv((np.eye(5) - z * Q)[1:, 1:])
         worst = max(worst, np.abs(Ai).sum(1).max())
     assert worst <= 1.7
+
+
+# ----------------------------------------------------------------------------
+# tricubic transfer of the FAS correction (fas_interp = 3)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [7, 15, 31])
+def test_cubic_interpolation_on_sine_modes(n):
+    """Per axis a coinciding fine point keeps the coarse value and a midpoint
+    gets (9 cos(t/2) - cos(3t/2))/8 times the mode, t = k pi h_c (sum of the
+    two tap pairs); the odd reflection beyond the walls keeps this exact up
+    to the wall."""
+    nc = (n - 1) // 2
+    hc = 1.0 / (nc + 1)
+    for k in [(1, 1, 1), (2, 3, 1), (nc, 1, nc)]:
+        got = oracle.prolong_add_cubic(inputs.sine_mode(nc, k), np.zeros((n, n, n)))
+        f = []
+        for kk in k:
+            t = kk * math.pi * hc
+            g = (9.0 * math.cos(t / 2) - math.cos(1.5 * t)) / 8.0
+            f.append(np.where(np.arange(n) % 2 == 1, 1.0, g))
+        ex = inputs.sine_mode(n, k) * f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :]
+        assert np.abs(got - ex).max() < 1e-14
+
+
+def test_cubic_interpolation_exact_for_cubics_away_from_walls():
+    nc = 15
+    n = 2 * nc + 1
+    xc = (np.arange(nc) + 1) / (nc + 1)
+    xf = (np.arange(n) + 1) / (n + 1)
+    px = lambda x: x ** 3 - 0.7 * x
+    py = lambda y: 2 * y ** 3 + y ** 2 - 1
+    pz = lambda z: z ** 3 + 0.5 * z
+    ec = pz(xc)[:, None, None] * py(xc)[None, :, None] * px(xc)[None, None, :]
+    ex = pz(xf)[:, None, None] * py(xf)[None, :, None] * px(xf)[None, None, :]
+    got = oracle.prolong_add_cubic(ec, np.zeros((n, n, n)))
+    inner = slice(4, n - 4)        # every tap of these points lies inside the grid
+    assert np.abs(got[inner, inner, inner] - ex[inner, inner, inner]).max() < 1e-13
+    # the trilinear transfer is not exact for them: the pin tells the two apart
+    lin = oracle.prolong_add(ec, np.zeros((n, n, n)))
+    assert np.abs(lin[inner, inner, inner] - ex[inner, inner, inner]).max() > 1e-5
+
+
+def test_fas_fixed_point_cubic():
+    pb = two_level(nf=15, dt=0.1)
+    pb.fas_interp = 3
+    u0 = inputs.random_smooth(15, 4)
+    Uf, FIf = fine_collocation(pb, u0, 0.2)
+    lf, lc = pb.lev[0], pb.lev[1]
+    Uc, FIc, Ut, tau = oracle.fas_restrict(lf, lc, pb.nu, 0.2, pb.dt, pb.forcing_c, Uf, FIf)
+    oracle.sdc_sweep(lc, pb.mg, pb.nu, 0.2, pb.dt, pb.forcing_c, Uc, FIc, tau)
+    U2, F2 = Uf.copy(), FIf.copy()
+    oracle.fas_interp(lf, lc, pb.nu, U2, F2, Uc, Ut, interp=3)
+    assert np.abs(U2 - Uf).max() < 1e-12
+
+
+def test_mlsdc_cubic_converges_to_fine_collocation():
+    pb = two_level(nf=7, sweeps=50, dt=0.1)
+    pb.fas_interp = 3
+    u0 = inputs.random_smooth(7, 6)
+    u, st, _ = oracle.run(pb, u0)
+    Uf, _ = fine_collocation(pb, u0, 0.0)
+    assert np.abs(u - Uf[-1]).max() < 1e-11
+
+
+def test_pfasst_cubic_one_slice_is_mlsdc():
+    pb = two_level(nf=15, nsteps=2, sweeps=3)
+    pb.fas_interp = 3
+    u0 = inputs.random_smooth(15, 7)
+    a, s1, _ = oracle.run(pb, u0)
+    b, s2, _ = oracle.pfasst_run(pb, 1, u0)
+    assert s1 == s2 == oracle.OK
+    assert np.array_equal(a, b)
+
+
+def test_cubic_transfer_cuts_mlsdc_iterations():
+    """Control that the option is wired through: to the 1e-10 residual the
+    tricubic transfer needs fewer MLSDC iterations than the trilinear one
+    (31^3/15^3, 4th-order fine level), and both reach the same solution."""
+    out = {}
+    for interp in (1, 3):
+        pb = two_level(nf=31, nsteps=2, sweeps=0, dt=0.01)
+        pb.sdc_tol, pb.max_sweeps, pb.fas_interp = 1e-10, 40, interp
+        u, s, st = oracle.run(pb, inputs.sine_product(31))
+        assert s == oracle.OK
+        out[interp] = (u, st.total_sweeps)
+    assert out[3][1] < out[1][1]
+    assert np.abs(out[3][0] - out[1][0]).max() < 1e-9
+
+
+def test_invalid_fas_interp_rejected():
+    pb = two_level(nf=7)
+    pb.fas_interp = 2
+    _, s, _ = oracle.run(pb, inputs.sine_product(7))
+    assert s == oracle.EINVAL
