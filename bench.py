@@ -11,7 +11,10 @@ implicit substep solved by V(2,1) multigrid cycles (weighted Jacobi
 6/7, full weighting, trilinear, exact 3^3 solve) to a relative residual of
 1e-12; initial value u0 = sin(pi x) sin(pi y) sin(pi z) and the consistent
 manufactured forcing (c = 3).  Inputs are synthetic, generated on the host
-and copied to HBM before timing.  The slices run in 4 groups of 4: the fine
+and copied to HBM before timing.  The coarse corrections go back to the
+fine level by tricubic interpolation (--fas-interp 1: trilinear; both are
+pinned readings of a transfer the paper leaves to its references).  The
+slices run in 4 groups of 4: the fine
 sweeps of one group (one batched launch per kernel over its 4 slices)
 overlap the coarse pipeline of the group before it, which a second host
 thread issues on a second stream (--groups; the results are bit for bit
@@ -73,13 +76,14 @@ def log(msg):
 
 PRED = 1                 # coarse sweeps per slice of the serial coarse predictor
 GROUPS = 4               # slice groups: a group's fine sweeps overlap the previous group's coarse pipeline
+FAS_INTERP = 3           # spatial transfer of the coarse correction (1 trilinear, 3 tricubic)
 
 
-def problem(hs, nblocks, groups=0, **kw):
+def problem(hs, nblocks, groups=GROUPS, fas_interp=FAS_INTERP, **kw):
     return hs.Problem(n=NF, order=4, nnodes=MF, coarse=(NC, 2, MC), nu=0.1, dt=DT, t0=0.0, forcing_c=3.0,
                       nsteps=SLICES * nblocks, sweeps=ITERS, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest=3,
                       tol=1e-12, max_cycles=60, batch=SLICES, nslices=SLICES, pfasst_pred_sweeps=PRED,
-                      pfasst_groups=groups, **kw)
+                      pfasst_groups=groups, fas_interp=fas_interp, **kw)
 
 
 def kernel_hash():
@@ -117,13 +121,13 @@ def cpu_baseline():
 
 def headline(args, torch, hs, inputs):
     u0 = torch.from_numpy(inputs.sine_product(NF).ravel()).cuda()
-    warm = hs.Plan(problem(hs, 1, args.groups))
+    warm = hs.Plan(problem(hs, 1, args.groups, args.fas_interp))
     for _ in range(args.warmup):
         warm.set_state(u0)
         warm.pfasst_run()
     torch.cuda.synchronize()
     del warm
-    plan = hs.Plan(problem(hs, args.steps, args.groups))
+    plan = hs.Plan(problem(hs, args.steps, args.groups, args.fas_interp))
     plan.set_state(u0)
     plan.timer(hs.HS_TIMER_PJAC, 8192)
     torch.cuda.synchronize()
@@ -173,7 +177,7 @@ def one_batch_run(args, torch, hs, u0, grouped_s):
     """The same blocks with all 16 slices' fine sweeps in one batch (no slice
     groups): its k_pjac launches cover 16 x 127^3 finest grids, a working set
     (16 lanes x u, t, b = 786 MB) far beyond the Infinity Cache."""
-    plan = hs.Plan(problem(hs, args.steps, 0))
+    plan = hs.Plan(problem(hs, args.steps, 0, args.fas_interp))
     plan.set_state(u0)
     plan.timer(hs.HS_TIMER_PJAC, 8192)
     torch.cuda.synchronize()
@@ -198,7 +202,7 @@ def serial_mlsdc_run(args, torch, hs, inputs, u0, pfasst_s):
     import numpy as np
     pb = hs.Problem(n=NF, order=4, nnodes=MF, coarse=(NC, 2, MC), nu=0.1, dt=DT, t0=0.0, forcing_c=3.0,
                     nsteps=SLICES * args.steps, sweeps=ITERS, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest=3,
-                    tol=1e-12, max_cycles=60)
+                    tol=1e-12, max_cycles=60, fas_interp=args.fas_interp)
     plan = hs.Plan(pb)
     plan.set_state(u0)
     torch.cuda.synchronize()
@@ -219,7 +223,7 @@ def serial_mlsdc_run(args, torch, hs, inputs, u0, pfasst_s):
 def builtin_shapes_run(args, torch, hs, u0):
     """The same run with the built-in launch shapes: what the autotuner's table gains."""
     hs.tune_clear()
-    base = hs.Plan(problem(hs, args.steps, args.groups))
+    base = hs.Plan(problem(hs, args.steps, args.groups, args.fas_interp))
     base.set_state(u0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -252,10 +256,11 @@ def _headline_record(args, elapsed, value, achieved, traffic, launches, kms, pja
                                "FAS per slice, FP64: fine 127^3 4th-order, coarse 63^3 2nd-order 3 nodes, nu=0.1, "
                                "dt=0.01, coarse predictor + 4 PFASST iterations per block of 16 steps, V(2,1) "
                                "Jacobi 6/7 to 3^3, rel. residual 1e-12; slices in groups whose batched fine "
-                               "sweeps overlap the coarse pipeline",
+                               "sweeps overlap the coarse pipeline; tricubic transfer of the coarse correction",
                    "fine_n": NF, "coarse_n": NC, "slices": SLICES, "dt": DT, "iterations": ITERS,
                    "blocks": args.steps, "mg_tol": 1e-12, "predictor_coarse_sweeps": PRED,
-                   "slice_groups": args.groups},
+                   "slice_groups": args.groups,
+                   "fas_transfer": "tricubic" if args.fas_interp == 3 else "trilinear"},
         "roofline": {"bound": "hbm",
                      "kernel": f"k_pjac<double, 4> on the finest 127^3 grids of one slice group "
                                f"({SLICES // max(1, args.groups)} lanes per launch)",
@@ -280,6 +285,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the headline PFASST measurement")
     ap.add_argument("--groups", type=int, default=GROUPS,
                     help="PFASST slice groups whose fine sweeps overlap the coarse pipeline (0: one batch)")
+    ap.add_argument("--fas-interp", type=int, default=FAS_INTERP, choices=(1, 3),
+                    help="spatial transfer of the coarse correction: 1 trilinear, 3 tricubic")
     ap.add_argument("--no-serial-compare", action="store_true",
                     help="skip the serial MLSDC run of the same steps")
     ap.add_argument("--no-one-batch", action="store_true",

@@ -114,6 +114,7 @@ struct FasSeg {
     double *Uc, *FIc, *Ut, *tau;  // coarse [Mc][Nc]
     const double* sigf;
     const double* sigc;
+    double* Exy;                  // tricubic transfer: [Mc][nc][nf][nf] xy-interpolated corrections
 };
 
 // Exact solve on the coarsest grid (n = 3 or 1) by the discrete sine
@@ -272,6 +273,7 @@ hipError_t handoff(LaneCtl* ctl, const SdcSeg* dst, const SdcSeg* src, int nseg,
                    int order, hipStream_t s);
 hipError_t fas_restrict(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int corder, int gate,
                         hipStream_t s);
+hipError_t fas_interp3(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int gate, hipStream_t s);
 hipError_t fas_interp(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int gate,
                       hipStream_t s);
 

@@ -2489,6 +2489,134 @@ __global__ void __launch_bounds__(HS_BLOCK) k_fas_interp(const FasSeg* __restric
     }
 }
 
+// Tricubic transfer of the coarse correction (fas_interp = 3), as k_fas_interp
+// but with 4-point Lagrange interpolation per axis: a fine index that
+// coincides with a coarse one takes its value, a midpoint the weights
+// (-1, 9, 9, -1)/16 on the two coarse points on either side; a tap on a wall
+// is 0 and a tap one cell beyond a wall the odd reflection of the point one
+// cell inside.  Separable, in two passes: the xy interpolation of every
+// coarse plane into Exy, then per fine point the z interpolation and the
+// Lagrange combination in time of k_fas_interp.
+struct Cubic1 {
+    int idx[4];
+    double w[4];
+    int cnt;
+};
+
+__device__ __forceinline__ Cubic1 cubic1(int i)
+{
+    Cubic1 c;
+    if (i & 1) {
+        c.idx[0] = (i - 1) >> 1;
+        c.w[0] = 1.0;
+        c.cnt = 1;
+    } else {
+        const int m = i >> 1;
+        c.idx[0] = m - 2; c.w[0] = -1.0 / 16.0;
+        c.idx[1] = m - 1; c.w[1] = 9.0 / 16.0;
+        c.idx[2] = m;     c.w[2] = 9.0 / 16.0;
+        c.idx[3] = m + 1; c.w[3] = -1.0 / 16.0;
+        c.cnt = 4;
+    }
+    return c;
+}
+
+// coarse index of a tap and its sign (0: the tap is on a wall)
+__device__ __forceinline__ int cubic_fold(int I, int nc, double& sign)
+{
+    if (I == -1 || I == nc) {
+        sign = 0.0;
+        return 0;
+    }
+    if (I == -2) {
+        sign = -sign;
+        return 0;
+    }
+    if (I == nc + 1) {
+        sign = -sign;
+        return nc - 1;
+    }
+    return I;
+}
+
+// Exy[j][K][fj][fi] = xy interpolation of dU_j = Uc_j - Ut_j on coarse plane K
+// (blocks of the fine table whose plane index is below nc; the rest return)
+__global__ void __launch_bounds__(HS_BLOCK) k_fas_interp3_xy(const FasSeg* __restrict__ segs, int nseg,
+                                                             int nblk, const LaneCtl* __restrict__ ctl,
+                                                             int gate)
+{
+    int lb = xcd_remap(blockIdx.x, nblk);
+    int si = find_seg(segs, nseg, lb);
+    const FasSeg sg = segs[si];
+    if (gate && ctl[sg.lane].sdc_state != 0) return;
+    const int nf = sg.nf, nc = sg.nc;
+    Pos q = grid_pos(lb - sg.blk_begin, nf);
+    if (!q.in || q.k >= nc) return;
+    const long long Nc = (long long)nc * nc * nc, Nxy = (long long)nc * nf * nf;
+    const Cubic1 cx = cubic1(q.i), cy = cubic1(q.j);
+    for (int jn = 0; jn < sg.Mc; jn++) {
+        const double* uc = sg.Uc + jn * Nc;
+        const double* ut = sg.Ut + jn * Nc;
+        double sy = 0.0;
+        for (int b = 0; b < cy.cnt; b++) {
+            double sgy = 1.0;
+            const int J = cubic_fold(cy.idx[b], nc, sgy);
+            if (sgy == 0.0) continue;
+            double sx = 0.0;
+            for (int a = 0; a < cx.cnt; a++) {
+                double sgn = sgy;
+                const int I = cubic_fold(cx.idx[a], nc, sgn);
+                if (sgn == 0.0) continue;
+                const long long pc = lin(I, J, q.k, nc);
+                sx += cx.w[a] * (sgn * (uc[pc] - ut[pc]));
+            }
+            sy += cy.w[b] * sx;
+        }
+        sg.Exy[jn * Nxy + ((long long)q.k * nf + q.j) * nf + q.i] = sy;
+    }
+}
+
+// z interpolation of Exy at every fine point, then U_f += the Lagrange
+// combination in time (as k_fas_interp)
+__global__ void __launch_bounds__(HS_BLOCK) k_fas_interp3_z(const FasSeg* __restrict__ segs, int nseg,
+                                                            int nblk, const LaneCtl* __restrict__ ctl,
+                                                            int gate)
+{
+    int lb = xcd_remap(blockIdx.x, nblk);
+    int si = find_seg(segs, nseg, lb);
+    const FasSeg sg = segs[si];
+    if (gate && ctl[sg.lane].sdc_state != 0) return;
+    const int nf = sg.nf, nc = sg.nc;
+    Pos q = grid_pos(lb - sg.blk_begin, nf);
+    if (!q.in) return;
+    const long long Nf = (long long)nf * nf * nf, Nxy = (long long)nc * nf * nf;
+    const long long pf = lin(q.i, q.j, q.k, nf);
+    const long long pxy = (long long)q.j * nf + q.i;
+    const Cubic1 cz = cubic1(q.k);
+    double e[HS_MAXM];
+    for (int jn = 0; jn < sg.Mc; jn++) {
+        const double* E = sg.Exy + jn * Nxy;
+        double s = 0.0;
+        for (int c = 0; c < cz.cnt; c++) {
+            double sgn = 1.0;
+            const int K = cubic_fold(cz.idx[c], nc, sgn);
+            if (sgn == 0.0) continue;
+            s += cz.w[c] * (sgn * E[(long long)K * nf * nf + pxy]);
+        }
+        e[jn] = s;
+    }
+    const InterpConst& ip = c_lc.ip[sg.Mf][sg.Mc];
+    for (int mf = 0; mf < sg.Mf; mf++) {
+        double corr = 0.0;
+        if (mf % ip.stride == 0) {
+            corr = e[mf / ip.stride];
+        } else {
+            for (int jn = 0; jn < sg.Mc; jn++) corr += ip.w[mf][jn] * e[jn];
+        }
+        sg.Uf[mf * Nf + pf] += corr;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Lane bookkeeping
 // ---------------------------------------------------------------------------
@@ -3006,6 +3134,16 @@ hipError_t fas_restrict(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, in
     if (nblk <= 0) return hipSuccess;
     HS_ORDER_DISPATCH(corder, (k_fas_restrict<2>), (k_fas_restrict<4>), g1(nblk), BLK, 0, segs, nseg,
                       nblk, ctl, gate);
+    return hipGetLastError();
+}
+
+hipError_t fas_interp3(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int gate, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fas_interp3_xy, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, gate);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fas_interp3_z, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, gate);
     return hipGetLastError();
 }
 

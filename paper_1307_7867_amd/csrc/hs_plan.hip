@@ -207,6 +207,7 @@ struct LaneBufs {
     long long N[2] = {0, 0};
     double *U[2], *FI[2], *P[2], *rhs[2], *tmp[2];
     double *Ut = nullptr, *tau = nullptr;
+    double* fxy = nullptr;                     // tricubic FAS transfer: xy-interpolated coarse corrections
     const double* sig[2];
     std::vector<int> grids[2];                 // n of every multigrid grid, finest first
     std::vector<double*> gu[2], gt[2], gb[2];  // FP64 grids (index 0 unused)
@@ -547,6 +548,7 @@ void build_set_host(hs_plan* P, LaneSet& ls)
             f.Uf = lb.U[0]; f.FIf = lb.FI[0];
             f.Uc = lb.U[1]; f.FIc = lb.FI[1]; f.Ut = lb.Ut; f.tau = lb.tau;
             f.sigf = lb.sig[0]; f.sigc = lb.sig[1];
+            f.Exy = lb.fxy;
             f.blk_begin = bc; bc += hsk::grid_blocks(f.nc); ls.fasc.h.push_back(f);
             f.blk_begin = bf; bf += hsk::grid_blocks(f.nf); ls.fasf.h.push_back(f);
         }
@@ -623,6 +625,8 @@ void lay_lane(hs_plan* P, int b, Bump& bump)
             }
         }
     }
+    if (P->nlev == 2 && P->pb.fas_interp == 3)
+        lb.fxy = bump.arr<double>((size_t)P->M[1] * lb.n[1] * lb.n[0] * lb.n[0]);
 }
 
 // Node-parallel solver lane sl = B + b (M-1) + m - 1: its finest grid is node m
@@ -925,6 +929,7 @@ hs_status validate(const hs_problem* pb)
         return HS_EINVAL;
     if (pb->lane_memory && pb->nslices != 1) return HS_EINVAL;
     if (pb->pfasst_groups < 0 || pb->pfasst_groups > pb->nslices) return HS_EINVAL;
+    if (pb->fas_interp != 0 && pb->fas_interp != 1 && pb->fas_interp != 3) return HS_EINVAL;
     if (pb->pfasst_groups >= 2 &&
         (pb->nslices % pb->pfasst_groups != 0 || pb->sweeps <= 0 || pb->mg.cycle_graphs))
         return HS_EINVAL;
@@ -1417,6 +1422,16 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
     return HS_OK;
 }
 
+// Interpolation of the coarse corrections of ls's lanes to their fine nodes:
+// trilinear, or tricubic with pb.fas_interp = 3 (section 1.1 leaves the
+// transfer to the references).
+hipError_t fas_interp(hs_plan* P, const LaneSet& ls, hipStream_t s)
+{
+    if (P->pb.fas_interp == 3)
+        return hsk::fas_interp3(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s);
+    return hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s);
+}
+
 hs_status mlsdc_iter(hs_plan* P, LaneSet& ls, bool with_resid, hipStream_t s, int* outcome)
 {
     HS_CHECK(sweep(P, ls, 0, with_resid, true, s, outcome));
@@ -1424,7 +1439,7 @@ hs_status mlsdc_iter(hs_plan* P, LaneSet& ls, bool with_resid, hipStream_t s, in
     HS_TRY(hsk::fas_restrict(P->ctl, ls.fasc.d, ls.fasc.nseg(), ls.fasc.nblk, P->order[1], 1, s));
     int o2;
     HS_CHECK(sweep(P, ls, 1, false, false, s, &o2));
-    HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
+    HS_TRY(fas_interp(P, ls, s));
     HS_TRY(hsk::fi_march(P->ctl, ls.mg64[0].fine.d, ls.sdc[0].d, ls.sdc[0].nseg(), ls.mg64[0].fine.nblk,
                          P->order[0], 0, P->M[0], -1, 1, s));
     P->sweep_k++;
@@ -2100,7 +2115,7 @@ hs_status hs_fas_interp(hs_plan* P, void* stream)
     hipStream_t s = (hipStream_t)stream;
     HS_CHECK(refresh_run(P, s));
     LaneSet& ls = P->run;
-    HS_TRY(hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s));
+    HS_TRY(fas_interp(P, ls, s));
     HS_TRY(hsk::fi_march(P->ctl, ls.mg64[0].fine.d, ls.sdc[0].d, ls.sdc[0].nseg(), ls.mg64[0].fine.nblk,
                          P->order[0], 0, P->M[0], -1, 1, s));
     return HS_OK;
@@ -2198,7 +2213,7 @@ hs_status pfasst_predictor(hs_plan* P, hipStream_t s)
         }
         for (int j = 0; j < P->pb.pfasst_pred_sweeps; j++) HS_CHECK(sweep(P, P->single[p], 1, false, false, s, &outcome));
     }
-    HS_TRY(hsk::fas_interp(P->ctl, all.fasf.d, all.fasf.nseg(), all.fasf.nblk, 1, s));
+    HS_TRY(fas_interp(P, all, s));
     HS_TRY(hsk::fi_march(P->ctl, all.mg64[0].fine.d, all.sdc[0].d, all.sdc[0].nseg(), all.mg64[0].fine.nblk,
                          P->order[0], 0, P->M[0], -1, 1, s));
     return HS_OK;
@@ -2316,7 +2331,7 @@ hs_status pipe_fine(hs_plan* P, PipeSync& ps, int nblocks, hipStream_t s)
         if (!ps.wait(ps.c[g], ++got_c[g])) return HS_ESTATE;
         HS_TRY(hipStreamWaitEvent(s, P->ev_c[g], 0));
         const LaneSet& gs = P->grp[g];
-        HS_TRY(hsk::fas_interp(P->ctl, gs.fasf.d, gs.fasf.nseg(), gs.fasf.nblk, 1, s));
+        HS_TRY(fas_interp(P, gs, s));
         HS_TRY(hsk::fi_march(P->ctl, gs.mg64[0].fine.d, gs.sdc[0].d, gs.sdc[0].nseg(), gs.mg64[0].fine.nblk,
                              P->order[0], 0, Mf, -1, 1, s));
         return HS_OK;
@@ -2450,7 +2465,7 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
                 HS_CHECK(sweep(P, P->single[p], 1, false, false, s, &outcome));
             }
             // (iv) interpolation on every slice, node 0 included
-            HS_TRY(hsk::fas_interp(P->ctl, all.fasf.d, all.fasf.nseg(), all.fasf.nblk, 1, s));
+            HS_TRY(fas_interp(P, all, s));
             HS_TRY(hsk::fi_march(P->ctl, all.mg64[0].fine.d, all.sdc[0].d, all.sdc[0].nseg(), all.mg64[0].fine.nblk,
                                  P->order[0], 0, P->M[0], -1, 1, s));
             P->sweep_k++;

@@ -46,7 +46,8 @@ class ProblemDesc(C.Structure):
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("batch", C.c_int32),
                 ("nslices", C.c_int32), ("h_lane_n", C.POINTER(C.c_int32)),
                 ("pfasst_pred_sweeps", C.c_int32), ("lane_memory", C.c_int32),
-                ("sdc_node_parallel", C.c_int32), ("pfasst_groups", C.c_int32)]
+                ("sdc_node_parallel", C.c_int32), ("pfasst_groups", C.c_int32),
+                ("fas_interp", C.c_int32)]
 
 
 class LaneStats(C.Structure):
@@ -240,6 +241,7 @@ class Problem:
     pfasst_pred_sweeps: int = 0
     sdc_node_parallel: int = 0
     pfasst_groups: int = 0
+    fas_interp: int = 0
 
     def desc(self):
         d = ProblemDesc()
@@ -257,6 +259,7 @@ class Problem:
         d.pfasst_pred_sweeps = self.pfasst_pred_sweeps
         d.sdc_node_parallel = self.sdc_node_parallel
         d.pfasst_groups = self.pfasst_groups
+        d.fas_interp = self.fas_interp
         keep = None
         if self.lane_n is not None:
             keep = (C.c_int32 * len(self.lane_n))(*self.lane_n)

@@ -87,12 +87,12 @@ def sdc15(args):
 # configuration 2: two-level MLSDC at 127^3 / 63^3, alpha
 # ----------------------------------------------------------------------------
 
-def _sweep_alpha(hs, nf, nc, dt, reps=3):
+def _sweep_alpha(hs, nf, nc, dt, reps=3, fas_interp=1):
     """alpha = time of one coarse sweep / time of one fine sweep (one lane);
     beta = time of restriction + interpolation / time of one fine sweep."""
     from . import inputs
     pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=1, sweeps=1,
-                    tol=1e-12, max_cycles=60)
+                    tol=1e-12, max_cycles=60, fas_interp=fas_interp)
     plan = hs.Plan(pb)
     plan.set_state(_dev(inputs.sine_product(nf)))
     tf, tc, tr = [], [], []
@@ -107,12 +107,9 @@ def _sweep_alpha(hs, nf, nc, dt, reps=3):
     return c / f, r / f, {"fine_sweep_ms": f * 1e3, "coarse_sweep_ms": c * 1e3, "transfer_ms": r * 1e3}
 
 
-def mlsdc127(args):
-    from . import heatst as hs
-    from . import inputs
-    nf, nc, K, steps = 127, 63, 3, 20
+def _mlsdc127_run(hs, inputs, nf, nc, K, steps, interp):
     pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=0.05, nsteps=steps, sweeps=K,
-                    tol=1e-12, max_cycles=60)
+                    tol=1e-12, max_cycles=60, fas_interp=interp)
     plan = hs.Plan(pb)
     u0 = _dev(inputs.sine_product(nf))
     plan.set_state(u0)
@@ -122,13 +119,31 @@ def mlsdc127(args):
     st, stats = plan.stats()
     hs.check(st, "mlsdc127")
     u = plan.get_state().cpu().numpy().reshape(nf, nf, nf)
-    ex = inputs.sine_product(nf) * np.cos(steps * 0.05)
     del plan
-    alpha, beta, t = _sweep_alpha(hs, nf, nc, 0.05)
+    return el, stats, u
+
+
+def mlsdc127(args):
+    """Config 2: 20 steps of two-level MLSDC, 3 iterations each, with the
+    transfer of the coarse correction chosen by --fas-interp; the other
+    transfer's step time beside it."""
+    from . import heatst as hs
+    from . import inputs
+    nf, nc, K, steps = 127, 63, 3, 20
+    interp = getattr(args, "fas_interp", 3)
+    el, stats, u = _mlsdc127_run(hs, inputs, nf, nc, K, steps, interp)
+    other = 1 if interp == 3 else 3
+    el_o, stats_o, u_o = _mlsdc127_run(hs, inputs, nf, nc, K, steps, other)
+    ex = inputs.sine_product(nf) * np.cos(steps * 0.05)
+    alpha, beta, t = _sweep_alpha(hs, nf, nc, 0.05, fas_interp=interp)
     return {"workload": "mlsdc127", "metric": "DOF-updates/s", "value": nf ** 3 * 4 * K * steps / el,
             "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
             "vcycles": stats[0]["total_cycles"], "solves": stats[0]["total_solves"],
             "error_vs_exact": float(np.abs(u - ex).max() / np.abs(ex).max()),
+            "fas_transfer": "tricubic" if interp == 3 else "trilinear",
+            "other_transfer": {"fas_transfer": "tricubic" if other == 3 else "trilinear",
+                               "ms_per_step": el_o / steps * 1e3, "vcycles": stats_o[0]["total_cycles"],
+                               "error_vs_exact": float(np.abs(u_o - ex).max() / np.abs(ex).max())},
             "alpha_coarse_over_fine_sweep": alpha, **t}
 
 
@@ -157,40 +172,50 @@ def eq10(args):
     K_S = stats[0]["total_sweeps"] / P
     u_sdc = sdc.get_state().cpu().numpy()
     del sdc
-    # serial MLSDC to the same residual (the paper's P_T = 1 point)
-    ml = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P, sweeps=0,
-                            sdc_tol=tol, max_sweeps=30, tol=1e-12, max_cycles=60))
-    ml.set_state(u0)
-    ml.step()
-    ml.set_state(u0)
-    t_ml = _timed(ml.solve)
-    st, mstats = ml.stats()
-    hs.check(st, "eq10 serial MLSDC")
-    del ml
-    alpha, beta, t = _sweep_alpha(hs, nf, nc, dt)
     rows = {}
-    for pred in (0, 1):
-        pf = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P, sweeps=0,
-                                sdc_tol=tol, max_sweeps=args.pfasst_max_iters, tol=1e-12, max_cycles=60, batch=P,
-                                nslices=P, pfasst_pred_sweeps=pred))
-        pf.set_state(u0)
-        pf.pfasst_run()
-        pf.set_state(u0)
-        t_pf = _timed(pf.pfasst_run)
-        st, pstats = pf.stats()
-        hs.check(st, "eq10 PFASST", allow=(hs.HS_ENOCONV,))
-        K_P = pstats[0]["total_sweeps"]
-        u_pf = pf.get_state().cpu().numpy()
-        del pf
-        model = K_S * P / (P * alpha + K_P * (1 + alpha + beta))
-        rows[f"predictor_{pred}"] = {
-            "K_P": K_P, "converged": st == hs.HS_OK, "last_residual": max(x["last_sdc_res"] for x in pstats),
-            "model_speedup_P16": model, "pfasst_seconds": t_pf,
-            "one_gpu_speedup_vs_serial_sdc": t_sdc / t_pf, "one_gpu_speedup_vs_serial_mlsdc": t_ml / t_pf,
-            "rel_diff_vs_serial_sdc": float(np.abs(u_pf - u_sdc).max() / np.abs(u_sdc).max())}
-    return {"workload": "eq10", "P": P, "K_S": K_S, "alpha": alpha, "beta": beta,
-            "serial_sdc_seconds": t_sdc, "serial_mlsdc_seconds": t_ml,
-            "serial_mlsdc_iterations_per_step": mstats[0]["total_sweeps"] / P, **t, **rows,
+    common = None
+    # trilinear transfer of the coarse correction (the default reading), then tricubic
+    for interp, name, preds in ((1, "trilinear", (0, 1)), (3, "tricubic", (1,))):
+        # serial MLSDC to the same residual (the paper's P_T = 1 point)
+        ml = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P, sweeps=0,
+                                sdc_tol=tol, max_sweeps=30, tol=1e-12, max_cycles=60, fas_interp=interp))
+        ml.set_state(u0)
+        ml.step()
+        ml.set_state(u0)
+        t_ml = _timed(ml.solve)
+        st, mstats = ml.stats()
+        hs.check(st, "eq10 serial MLSDC")
+        del ml
+        alpha, beta, t = _sweep_alpha(hs, nf, nc, dt, fas_interp=interp)
+        part = {"alpha": alpha, "beta": beta, "serial_mlsdc_seconds": t_ml,
+                "serial_mlsdc_iterations_per_step": mstats[0]["total_sweeps"] / P, **t}
+        for pred in preds:
+            pf = hs.Plan(hs.Problem(n=nf, order=4, nnodes=5, coarse=(nc, 2, 3), nu=0.1, dt=dt, nsteps=P, sweeps=0,
+                                    sdc_tol=tol, max_sweeps=args.pfasst_max_iters, tol=1e-12, max_cycles=60,
+                                    batch=P, nslices=P, pfasst_pred_sweeps=pred, fas_interp=interp))
+            pf.set_state(u0)
+            pf.pfasst_run()
+            pf.set_state(u0)
+            t_pf = _timed(pf.pfasst_run)
+            st, pstats = pf.stats()
+            hs.check(st, "eq10 PFASST", allow=(hs.HS_ENOCONV,))
+            K_P = pstats[0]["total_sweeps"]
+            u_pf = pf.get_state().cpu().numpy()
+            del pf
+            model = K_S * P / (P * alpha + K_P * (1 + alpha + beta))
+            part[f"predictor_{pred}"] = {
+                "K_P": K_P, "converged": st == hs.HS_OK, "last_residual": max(x["last_sdc_res"] for x in pstats),
+                "model_speedup_P16": model, "pfasst_seconds": t_pf,
+                "one_gpu_speedup_vs_serial_sdc": t_sdc / t_pf, "one_gpu_speedup_vs_serial_mlsdc": t_ml / t_pf,
+                "rel_diff_vs_serial_sdc": float(np.abs(u_pf - u_sdc).max() / np.abs(u_sdc).max())}
+        rows[name] = part
+        if common is None:
+            common = part
+    return {"workload": "eq10", "P": P, "K_S": K_S, "serial_sdc_seconds": t_sdc,
+            # the trilinear (default) figures at the top level, both in full below
+            "alpha": common["alpha"], "beta": common["beta"],
+            "predictor_0": common["predictor_0"], "predictor_1": common["predictor_1"],
+            "fas_transfer": rows,
             "note": "model: eq. (10) for P processors, one slice each; one-GPU ratios: the 16 slices run as "
                     "one batch on a single GPU"}
 

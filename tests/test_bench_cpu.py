@@ -35,6 +35,7 @@ def test_default_workload_is_the_documented_one():
     assert pb.omega == 6.0 / 7.0
     assert (pb.tol, pb.max_cycles) == (1e-12, 60)
     assert (pb.fused_sweeps, pb.cycle_graphs, pb.pfasst_pred_sweeps) == (1, 0, 1)
+    assert (pb.pfasst_groups, pb.fas_interp) == (4, 3)
     assert pb.workspace_bytes() > 16 * 127 ** 3 * 8 * 16
     # value = space-time DOF-updates per second: fine points x substeps x iterations x slices per block
     assert (bench.NF, bench.MF, bench.ITERS, bench.SLICES) == (pb.n, pb.nnodes, pb.sweeps, pb.batch)

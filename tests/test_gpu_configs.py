@@ -81,17 +81,23 @@ def _uneven_tol_ref(i):
 
 
 PF_CASES = {
-    # name: (nf, slices, iterations, fixed cycles, dt, coarse predictor sweeps)
+    # name: (nf, slices, iterations, fixed cycles, dt, coarse predictor sweeps[, FAS transfer])
     "pfasst16_63": (63, 16, 2, 2, 0.01, 0),
     "pfasst16_63_pred": (63, 16, 2, 2, 0.01, 1),
+    "pfasst16_63_pred_cubic": (63, 16, 2, 2, 0.01, 1, 3),
     "pfasst2_127": (127, 2, 1, 2, 0.01, 1),
 }
 
 
+def _pf_case(name):
+    c = PF_CASES[name]
+    return c[:6] + ((c[6],) if len(c) > 6 else (1,))
+
+
 def _pfasst_ref(name):
-    nf, P, K, cyc, dt, pred = PF_CASES[name]
+    nf, P, K, cyc, dt, pred, interp = _pf_case(name)
     pb = oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, dt=dt, nsteps=P, sweeps=K,
-                        mg=oracle.mg_params(fixed_cycles=cyc))
+                        mg=oracle.mg_params(fixed_cycles=cyc), fas_interp=interp)
     return oracle.pfasst(pb, P, inputs.sine_product(nf), pred_sweeps=pred)
 
 
@@ -173,9 +179,10 @@ def test_config3_mixed_255_ten_steps(torch, seed):
 @pytest.mark.parametrize("name", sorted(PF_CASES))
 def test_pfasst_config_sizes_parity(torch, name):
     from paper_1307_7867_amd import heatst as hs
-    nf, P, K, cyc, dt, pred = PF_CASES[name]
+    nf, P, K, cyc, dt, pred, interp = _pf_case(name)
     pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=((nf - 1) // 2, 2, 3), nu=0.1, dt=dt, nsteps=P,
-                    sweeps=K, fixed_cycles=cyc, batch=P, nslices=P, pfasst_pred_sweeps=pred)
+                    sweeps=K, fixed_cycles=cyc, batch=P, nslices=P, pfasst_pred_sweeps=pred,
+                    fas_interp=interp, pfasst_groups=4 if interp == 3 else 0)
     plan = hs.Plan(pb)
     plan.set_state(dev(torch, inputs.sine_product(nf)))
     plan.pfasst_run()
@@ -198,7 +205,7 @@ def test_pfasst_groups_config_size_parity(torch, groups):
     for bit the result without groups."""
     from paper_1307_7867_amd import heatst as hs
     name = "pfasst16_63_pred"
-    nf, P, K, cyc, dt, pred = PF_CASES[name]
+    nf, P, K, cyc, dt, pred, _ = _pf_case(name)
     outs = []
     for g in (0, groups):
         pb = hs.Problem(n=nf, order=4, nnodes=5, coarse=((nf - 1) // 2, 2, 3), nu=0.1, dt=dt, nsteps=P,

@@ -381,11 +381,12 @@ def mlsdc_problem(hs, nf, **kw):
     return hs.Problem(n=nf, order=4, nnodes=5, coarse=((nf - 1) // 2, 2, 3), **kw)
 
 
-def test_fas_transfer_parity(torch):
+@pytest.mark.parametrize("interp", [1, 3])
+def test_fas_transfer_parity(torch, interp):
     hs = heatst_mod()
     nf, nu, dt, t0 = 31, 0.1, 0.05, 0.1
     nc = (nf - 1) // 2
-    plan = hs.Plan(mlsdc_problem(hs, nf, nu=nu, dt=dt, t0=t0, fixed_cycles=4))
+    plan = hs.Plan(mlsdc_problem(hs, nf, nu=nu, dt=dt, t0=t0, fixed_cycles=4, fas_interp=interp))
     u0 = inputs.random_smooth(nf, 9)
     plan.set_state(dev(torch, u0))
     plan.begin_step()
@@ -409,7 +410,7 @@ def test_fas_transfer_parity(torch):
     assert rel(host(gUc).reshape(shp), Uc) <= TOL
     # interpolation
     plan.fas_interp()
-    oracle.fas_interp(lf, lc, nu, Uf, Ff, host(gUc).reshape(shp).copy(), Ut)
+    oracle.fas_interp(lf, lc, nu, Uf, Ff, host(gUc).reshape(shp).copy(), Ut, interp=interp)
     gUf, gFf, _, _ = plan.get_nodes(0)
     assert rel(host(gUf).reshape(Uf.shape), Uf) <= TOL
     assert rel(host(gFf).reshape(Ff.shape), Ff) <= 1e-11
@@ -425,6 +426,47 @@ def test_mlsdc_parity(torch):
     got = host(plan.get_state()).reshape(nf, nf, nf)
     ref, s, _ = oracle.run(oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, dt=0.05, nsteps=2,
                                           sweeps=3, mg=oracle.mg_params(tol=1e-12)), u0)
+    assert rel(got, ref) <= TOL
+
+
+def test_mlsdc_cubic_tolerance_parity(torch):
+    """MLSDC with the tricubic transfer, iterations until the 1e-10 residual:
+    the oracle's result and iteration count."""
+    hs = heatst_mod()
+    nf = 31
+    plan = hs.Plan(mlsdc_problem(hs, nf, nu=0.1, dt=0.01, nsteps=2, sweeps=0, sdc_tol=1e-10, max_sweeps=40,
+                                 tol=1e-12, fas_interp=3))
+    u0 = inputs.sine_product(nf)
+    plan.set_state(dev(torch, u0))
+    plan.solve()
+    got = host(plan.get_state()).reshape(nf, nf, nf)
+    st, stats = plan.stats()
+    assert st == 0
+    pb = oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, dt=0.01, nsteps=2, sweeps=0, sdc_tol=1e-10,
+                        max_sweeps=40, mg=oracle.mg_params(tol=1e-12), fas_interp=3)
+    ref, s, ost = oracle.run(pb, u0)
+    assert s == oracle.OK
+    assert stats[0]["total_sweeps"] == ost.total_sweeps
+    assert rel(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("groups", [0, 2])
+def test_pfasst_cubic_parity(torch, groups):
+    """PFASST with the tricubic transfer and the coarse predictor, over two
+    blocks, one batch or two slice groups: the oracle's result."""
+    hs = heatst_mod()
+    nf, P = 15, 4
+    pb = mlsdc_problem(hs, nf, nu=0.1, dt=0.02, nsteps=2 * P, sweeps=3, tol=1e-12, batch=P, nslices=P,
+                       pfasst_pred_sweeps=1, pfasst_groups=groups, fas_interp=3)
+    plan = hs.Plan(pb)
+    u0 = inputs.random_smooth(nf, 11)
+    plan.set_state(dev(torch, u0))
+    plan.pfasst_run()
+    got = host(plan.get_state()).reshape(nf, nf, nf)
+    ref, s, _ = oracle.pfasst(oracle.problem([(nf, 4, 5), ((nf - 1) // 2, 2, 3)], nu=0.1, dt=0.02,
+                                             nsteps=2 * P, sweeps=3, mg=oracle.mg_params(tol=1e-12),
+                                             fas_interp=3), P, u0, pred_sweeps=1)
+    assert s == oracle.OK
     assert rel(got, ref) <= TOL
 
 
