@@ -144,7 +144,8 @@ typedef struct {
     int32_t fas_interp;      /* MLSDC / PFASST: spatial transfer of the coarse correction to the
                                 fine level (section 1.1 leaves it to the references): 0 or 1
                                 trilinear, 3 tricubic (4-point Lagrange per axis, odd reflection
-                                beyond the walls; a scratch of M_c n_c n_f^2 values per lane) */
+                                beyond the walls; a scratch of M_c n_c n_f (n_c + n_f) values per
+                                lane) */
 } hs_problem;
 
 /* Per-lane statistics (hs_stats_read). */

@@ -114,7 +114,8 @@ struct FasSeg {
     double *Uc, *FIc, *Ut, *tau;  // coarse [Mc][Nc]
     const double* sigf;
     const double* sigc;
-    double* Exy;                  // tricubic transfer: [Mc][nc][nf][nf] xy-interpolated corrections
+    double* Ex;                   // tricubic transfer: [Mc][nc][nc][nf] x-interpolated corrections
+    double* Exy;                  //   and [Mc][nc][nf][nf] xy-interpolated ones
 };
 
 // Exact solve on the coarsest grid (n = 3 or 1) by the discrete sine

@@ -2494,9 +2494,9 @@ __global__ void __launch_bounds__(HS_BLOCK) k_fas_interp(const FasSeg* __restric
 // coincides with a coarse one takes its value, a midpoint the weights
 // (-1, 9, 9, -1)/16 on the two coarse points on either side; a tap on a wall
 // is 0 and a tap one cell beyond a wall the odd reflection of the point one
-// cell inside.  Separable, in two passes: the xy interpolation of every
-// coarse plane into Exy, then per fine point the z interpolation and the
-// Lagrange combination in time of k_fas_interp.
+// cell inside.  Separable, in three passes: along x into Ex, along y into
+// Exy, then per fine point along z and the Lagrange combination in time of
+// k_fas_interp.
 struct Cubic1 {
     int idx[4];
     double w[4];
@@ -2539,11 +2539,42 @@ __device__ __forceinline__ int cubic_fold(int I, int nc, double& sign)
     return I;
 }
 
-// Exy[j][K][fj][fi] = xy interpolation of dU_j = Uc_j - Ut_j on coarse plane K
-// (blocks of the fine table whose plane index is below nc; the rest return)
-__global__ void __launch_bounds__(HS_BLOCK) k_fas_interp3_xy(const FasSeg* __restrict__ segs, int nseg,
-                                                             int nblk, const LaneCtl* __restrict__ ctl,
-                                                             int gate)
+// Ex[j][K][J][fi] = x interpolation of dU_j = Uc_j - Ut_j on coarse row (J, K)
+// (blocks of the fine table whose row and plane indices are below nc; the
+// rest return)
+__global__ void __launch_bounds__(HS_BLOCK) k_fas_interp3_x(const FasSeg* __restrict__ segs, int nseg,
+                                                            int nblk, const LaneCtl* __restrict__ ctl,
+                                                            int gate)
+{
+    int lb = xcd_remap(blockIdx.x, nblk);
+    int si = find_seg(segs, nseg, lb);
+    const FasSeg sg = segs[si];
+    if (gate && ctl[sg.lane].sdc_state != 0) return;
+    const int nf = sg.nf, nc = sg.nc;
+    Pos q = grid_pos(lb - sg.blk_begin, nf);
+    if (!q.in || q.j >= nc || q.k >= nc) return;
+    const long long Nc = (long long)nc * nc * nc, Nx = (long long)nc * nc * nf;
+    const Cubic1 cx = cubic1(q.i);
+    for (int jn = 0; jn < sg.Mc; jn++) {
+        const double* uc = sg.Uc + jn * Nc;
+        const double* ut = sg.Ut + jn * Nc;
+        double sx = 0.0;
+        for (int a = 0; a < cx.cnt; a++) {
+            double sgn = 1.0;
+            const int I = cubic_fold(cx.idx[a], nc, sgn);
+            if (sgn == 0.0) continue;
+            const long long pc = lin(I, q.j, q.k, nc);
+            sx += cx.w[a] * (sgn * (uc[pc] - ut[pc]));
+        }
+        sg.Ex[jn * Nx + ((long long)q.k * nc + q.j) * nf + q.i] = sx;
+    }
+}
+
+// Exy[j][K][fj][fi] = y interpolation of Ex on coarse plane K (blocks of the
+// fine table whose plane index is below nc; the rest return)
+__global__ void __launch_bounds__(HS_BLOCK) k_fas_interp3_y(const FasSeg* __restrict__ segs, int nseg,
+                                                            int nblk, const LaneCtl* __restrict__ ctl,
+                                                            int gate)
 {
     int lb = xcd_remap(blockIdx.x, nblk);
     int si = find_seg(segs, nseg, lb);
@@ -2552,25 +2583,16 @@ __global__ void __launch_bounds__(HS_BLOCK) k_fas_interp3_xy(const FasSeg* __res
     const int nf = sg.nf, nc = sg.nc;
     Pos q = grid_pos(lb - sg.blk_begin, nf);
     if (!q.in || q.k >= nc) return;
-    const long long Nc = (long long)nc * nc * nc, Nxy = (long long)nc * nf * nf;
-    const Cubic1 cx = cubic1(q.i), cy = cubic1(q.j);
+    const long long Nx = (long long)nc * nc * nf, Nxy = (long long)nc * nf * nf;
+    const Cubic1 cy = cubic1(q.j);
     for (int jn = 0; jn < sg.Mc; jn++) {
-        const double* uc = sg.Uc + jn * Nc;
-        const double* ut = sg.Ut + jn * Nc;
+        const double* X = sg.Ex + jn * Nx + (long long)q.k * nc * nf;
         double sy = 0.0;
         for (int b = 0; b < cy.cnt; b++) {
-            double sgy = 1.0;
-            const int J = cubic_fold(cy.idx[b], nc, sgy);
-            if (sgy == 0.0) continue;
-            double sx = 0.0;
-            for (int a = 0; a < cx.cnt; a++) {
-                double sgn = sgy;
-                const int I = cubic_fold(cx.idx[a], nc, sgn);
-                if (sgn == 0.0) continue;
-                const long long pc = lin(I, J, q.k, nc);
-                sx += cx.w[a] * (sgn * (uc[pc] - ut[pc]));
-            }
-            sy += cy.w[b] * sx;
+            double sgn = 1.0;
+            const int J = cubic_fold(cy.idx[b], nc, sgn);
+            if (sgn == 0.0) continue;
+            sy += cy.w[b] * (sgn * X[(long long)J * nf + q.i]);
         }
         sg.Exy[jn * Nxy + ((long long)q.k * nf + q.j) * nf + q.i] = sy;
     }
@@ -3140,8 +3162,11 @@ hipError_t fas_restrict(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, in
 hipError_t fas_interp3(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int gate, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fas_interp3_xy, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, gate);
+    hipLaunchKernelGGL(k_fas_interp3_x, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, gate);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fas_interp3_y, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, gate);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fas_interp3_z, g1(nblk), BLK, 0, s, segs, nseg, nblk, ctl, gate);
     return hipGetLastError();

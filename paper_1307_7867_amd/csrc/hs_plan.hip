@@ -207,7 +207,7 @@ struct LaneBufs {
     long long N[2] = {0, 0};
     double *U[2], *FI[2], *P[2], *rhs[2], *tmp[2];
     double *Ut = nullptr, *tau = nullptr;
-    double* fxy = nullptr;                     // tricubic FAS transfer: xy-interpolated coarse corrections
+    double *fx = nullptr, *fxy = nullptr;      // tricubic FAS transfer: x- and xy-interpolated coarse corrections
     const double* sig[2];
     std::vector<int> grids[2];                 // n of every multigrid grid, finest first
     std::vector<double*> gu[2], gt[2], gb[2];  // FP64 grids (index 0 unused)
@@ -548,6 +548,7 @@ void build_set_host(hs_plan* P, LaneSet& ls)
             f.Uf = lb.U[0]; f.FIf = lb.FI[0];
             f.Uc = lb.U[1]; f.FIc = lb.FI[1]; f.Ut = lb.Ut; f.tau = lb.tau;
             f.sigf = lb.sig[0]; f.sigc = lb.sig[1];
+            f.Ex = lb.fx;
             f.Exy = lb.fxy;
             f.blk_begin = bc; bc += hsk::grid_blocks(f.nc); ls.fasc.h.push_back(f);
             f.blk_begin = bf; bf += hsk::grid_blocks(f.nf); ls.fasf.h.push_back(f);
@@ -625,8 +626,10 @@ void lay_lane(hs_plan* P, int b, Bump& bump)
             }
         }
     }
-    if (P->nlev == 2 && P->pb.fas_interp == 3)
+    if (P->nlev == 2 && P->pb.fas_interp == 3) {
+        lb.fx = bump.arr<double>((size_t)P->M[1] * lb.n[1] * lb.n[1] * lb.n[0]);
         lb.fxy = bump.arr<double>((size_t)P->M[1] * lb.n[1] * lb.n[0] * lb.n[0]);
+    }
 }
 
 // Node-parallel solver lane sl = B + b (M-1) + m - 1: its finest grid is node m

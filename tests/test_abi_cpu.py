@@ -235,12 +235,12 @@ def test_pfasst_groups_add_snapshots_only():
 
 
 def test_fas_interp_validated_and_sized():
-    """The tricubic transfer takes one scratch of M_c n_c n_f^2 values per lane."""
+    """The tricubic transfer takes scratch of M_c n_c n_f (n_c + n_f) values per lane."""
     args = dict(n=31, order=4, nnodes=5, coarse=(15, 2, 3), batch=2)
     b1 = base_problem(**args).workspace_bytes()
     b3 = base_problem(fas_interp=3, **args).workspace_bytes()
-    scratch = 2 * 3 * 15 * 31 * 31 * 8
-    assert b1 + scratch <= b3 <= b1 + scratch + 2 * 256
+    scratch = 2 * 3 * 15 * 31 * (15 + 31) * 8
+    assert b1 + scratch <= b3 <= b1 + scratch + 4 * 256
     with pytest.raises(heatst.HeatstError) as e:
         base_problem(fas_interp=2, **args).workspace_bytes()
     assert e.value.status == heatst.HS_EINVAL
