@@ -2,7 +2,7 @@
 """Benchmark of the space-time heat solver's hot path on one MI355X.
 
 Headline workload (the largest FP64 configuration that runs on one GPU):
-PFASST with 16 concurrent time slices as one batch, two-level MLSDC per
+PFASST with 16 concurrent time slices on one GPU, two-level MLSDC per
 slice -- fine level 127^3 with the wide 4th-order stencil and 5
 Gauss-Lobatto nodes, coarse level 63^3 with the 7-point stencil and 3
 nodes -- nu = 0.1, dt = 0.01, a serial coarse predictor (one coarse sweep
