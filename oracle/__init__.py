@@ -49,7 +49,7 @@ class Problem(C.Structure):
     _fields_ = [("nu", C.c_double), ("t0", C.c_double), ("dt", C.c_double),
                 ("forcing_c", C.c_double), ("nsteps", C.c_int32), ("sweeps", C.c_int32),
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("nlevels", C.c_int32),
-                ("lev", Level * 2), ("mg", MG), ("node_parallel", C.c_int32), ("fas_interp", C.c_int32)]
+                ("lev", Level * 3), ("mg", MG), ("node_parallel", C.c_int32), ("fas_interp", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -95,6 +95,8 @@ def lib():
                                          C.c_double, C.c_double, _D, _D, C.POINTER(Stats)]
         L.or_fas_restrict.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, C.c_double,
                                       C.c_double, C.c_double, _D, _D, _D, _D, _D, _D]
+        L.or_fas_restrict_tau.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, C.c_double,
+                                          C.c_double, C.c_double, _D, _D, _D, _D, _D, _D, _D]
         L.or_fas_interp.argtypes = [C.POINTER(Level), C.POINTER(Level), C.c_double, _D, _D, _D, _D, C.c_int]
         L.or_mlsdc_iter.argtypes = [C.POINTER(Problem), C.c_double, _D, _D, _D, _D, _D, _D,
                                     C.POINTER(Stats)]
@@ -269,12 +271,18 @@ def sdc_sweep_nodes(lv, mg, nu, tn, dt, c, U, FI):
     return s, st
 
 
-def fas_restrict(lf, lc, nu, tn, dt, c, Uf, FIf):
+def fas_restrict(lf, lc, nu, tn, dt, c, Uf, FIf, tauf=None):
+    """Restriction + FAS correction to the next coarser level; tauf is the
+    fine level's own FAS correction (None on the finest level)."""
     nc, Mc = lc.n, lc.M
     Uc = np.empty((Mc, nc, nc, nc)); FIc = np.empty_like(Uc)
     Ut = np.empty_like(Uc); tau = np.empty_like(Uc)
-    lib().or_fas_restrict(C.byref(lf), C.byref(lc), nu, tn, dt, c, _p(_f(Uf)), _p(_f(FIf)),
-                          _p(Uc), _p(FIc), _p(Ut), _p(tau))
+    if tauf is None:
+        lib().or_fas_restrict(C.byref(lf), C.byref(lc), nu, tn, dt, c, _p(_f(Uf)), _p(_f(FIf)),
+                              _p(Uc), _p(FIc), _p(Ut), _p(tau))
+    else:
+        lib().or_fas_restrict_tau(C.byref(lf), C.byref(lc), nu, tn, dt, c, _p(_f(Uf)), _p(_f(FIf)),
+                                  _p(_f(tauf)), _p(Uc), _p(FIc), _p(Ut), _p(tau))
     return Uc, FIc, Ut, tau
 
 
@@ -291,7 +299,7 @@ def mlsdc_iter(pb, tn, Uf, FIf, Uc, FIc, Ut, tau):
 
 
 def run(pb, u0):
-    """SDC (nlevels=1) or MLSDC (nlevels=2) over pb.nsteps steps.  Returns (u, status, Stats)."""
+    """SDC (nlevels=1) or MLSDC (nlevels=2, 3) over pb.nsteps steps.  Returns (u, status, Stats)."""
     u = _f(u0).copy()
     st = Stats()
     s = lib().or_run(C.byref(pb), _p(u), C.byref(st))

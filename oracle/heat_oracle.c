@@ -22,8 +22,10 @@
  * expression is rounded exactly as written.
  *
  * Parity unpinned: the timing of PFASST's fine hand-off in or_pfasst (the
- * previous iteration's end value) is a reading that no test fixes; every
- * other function is pinned by tests/test_oracle_pins.py.
+ * previous iteration's end value) and, with three levels, the sweep on the
+ * middle level on the way up of the MLSDC V-cycle (mlsdc_vcycle) are
+ * readings that no test fixes; every other function is pinned by
+ * tests/test_oracle_pins.py.
  */
 #include <math.h>
 #include <stdint.h>
@@ -36,6 +38,7 @@
 #define OR_ENONFINITE (-4)
 
 #define OR_MAXM 8
+#define OR_MAXLEV 3
 
 typedef struct {
     int32_t nu1, nu2;     /* pre / post smoothing sweeps */
@@ -58,8 +61,8 @@ typedef struct {
     int32_t sweeps;      /* fixed sweeps / MLSDC iterations; 0 = iterate to sdc_tol */
     double sdc_tol;
     int32_t max_sweeps;
-    int32_t nlevels;     /* 1 = SDC, 2 = MLSDC */
-    or_level lev[2];     /* lev[0] fine, lev[1] coarse */
+    int32_t nlevels;     /* 1 = SDC, 2 or 3 = MLSDC */
+    or_level lev[OR_MAXLEV]; /* lev[0] finest, lev[nlevels-1] coarsest */
     or_mg mg;
     int32_t node_parallel; /* single-level SDC: 1 = node-parallel sweeps (or_sdc_sweep_nodes) */
     int32_t fas_interp;    /* MLSDC / PFASST: spatial interpolation of the coarse correction,
@@ -822,15 +825,18 @@ void or_inject(int nf, const double *uf, double *uc)
 static int fine_node_of(int Mf, int Mc, int m) { return m * ((Mf - 1) / (Mc - 1)); }
 
 /*
- * Restriction to the coarse MLSDC level plus FAS correction.
+ * Restriction to the next coarser MLSDC level plus FAS correction.
  * Ut[m] = inj(Uf[fine node of m]) (space: injection; time: node subset),
  * Uc = Ut, FIc = nu L_c Ut, and
- *   tau_m = inj(dt sum_j qf_{m',j} f^f_j) - dt sum_j qc_{m,j} f^c(Ut_j)
- * where m' is the fine node of coarse node m.
+ *   tau_m = inj(dt sum_j qf_{m',j} f^f_j + tauf_{m'}) - dt sum_j qc_{m,j} f^c(Ut_j)
+ * where m' is the fine node of coarse node m and tauf (NULL on the finest
+ * level) is the fine level's own FAS correction: the coarse problem is the
+ * fine level's FAS-corrected collocation problem seen on the coarse nodes and
+ * grid, so a restricted fine solution solves it.
  */
-void or_fas_restrict(const or_level *Lf, const or_level *Lc, double nu, double tn, double dt,
-                     double c, const double *Uf, const double *FIf, double *Uc, double *FIc,
-                     double *Ut, double *tau)
+void or_fas_restrict_tau(const or_level *Lf, const or_level *Lc, double nu, double tn, double dt,
+                         double c, const double *Uf, const double *FIf, const double *tauf, double *Uc,
+                         double *FIc, double *Ut, double *tau)
 {
     int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
     size_t Nf = cube(nf), Nc = cube(nc);
@@ -855,6 +861,7 @@ void or_fas_restrict(const or_level *Lf, const or_level *Lc, double nu, double t
             for (int j = 0; j < Mf; j++)
                 s += Qf[mf * Mf + j] * (FIf[(size_t)j * Nf + p] + FEf[(size_t)j * Nf + p]);
             fint[p] = dt * s;
+            if (tauf) fint[p] += tauf[(size_t)mf * Nf + p];
         }
         or_inject(nf, fint, cint);
         for (size_t p = 0; p < Nc; p++) {
@@ -865,6 +872,14 @@ void or_fas_restrict(const or_level *Lf, const or_level *Lc, double nu, double t
         }
     }
     free(FEf); free(FEc); free(fint); free(cint);
+}
+
+/* Restriction from the finest level (no fine FAS correction). */
+void or_fas_restrict(const or_level *Lf, const or_level *Lc, double nu, double tn, double dt,
+                     double c, const double *Uf, const double *FIf, double *Uc, double *FIc,
+                     double *Ut, double *tau)
+{
+    or_fas_restrict_tau(Lf, Lc, nu, tn, dt, c, Uf, FIf, NULL, Uc, FIc, Ut, tau);
 }
 
 /*
@@ -906,63 +921,137 @@ void or_fas_interp(const or_level *Lf, const or_level *Lc, double nu, double *Uf
     free(dU); free(ec);
 }
 
+/* Node arrays of every MLSDC level of one time step (Ut, tau: levels >= 1). */
+typedef struct {
+    double *U[OR_MAXLEV], *FI[OR_MAXLEV], *Ut[OR_MAXLEV], *tau[OR_MAXLEV];
+} or_hier;
+
+static int hier_alloc(const or_problem *pb, or_hier *H)
+{
+    memset(H, 0, sizeof(*H));
+    for (int l = 0; l < pb->nlevels; l++) {
+        size_t S = (size_t)pb->lev[l].M * cube(pb->lev[l].n);
+        H->U[l] = alloc0(S);
+        H->FI[l] = alloc0(S);
+        if (l > 0) {
+            H->Ut[l] = alloc0(S);
+            H->tau[l] = alloc0(S);
+        }
+    }
+    return OR_OK;
+}
+
+static void hier_free(const or_problem *pb, or_hier *H)
+{
+    for (int l = 0; l < pb->nlevels; l++) {
+        free(H->U[l]); free(H->FI[l]); free(H->Ut[l]); free(H->tau[l]);
+    }
+}
+
+/* Restriction + FAS correction from level l to level l + 1. */
+static void restrict_level(const or_problem *pb, int l, double tn, or_hier *H)
+{
+    or_fas_restrict_tau(&pb->lev[l], &pb->lev[l + 1], pb->nu, tn, pb->dt, pb->forcing_c, H->U[l], H->FI[l],
+                        l > 0 ? H->tau[l] : NULL, H->U[l + 1], H->FI[l + 1], H->Ut[l + 1], H->tau[l + 1]);
+}
+
+/* Interpolation of level l + 1's correction to level l. */
+static void interp_level(const or_problem *pb, int l, or_hier *H)
+{
+    or_fas_interp(&pb->lev[l], &pb->lev[l + 1], pb->nu, H->U[l], H->FI[l], H->U[l + 1], H->Ut[l + 1],
+                  pb->fas_interp);
+}
+
 /*
- * One MLSDC iteration: fine sweep, restriction + FAS correction, coarse
- * sweep with tau, interpolation of the coarse correction.
+ * One MLSDC iteration over the nlevels levels (section 1.1: sweeps on a
+ * hierarchy of levels with fewer nodes and points, tied together by the FAS
+ * correction), as a V-cycle:
+ *   down: sweep on level 0; for l = 0 .. L-2: restriction + FAS correction
+ *         to level l+1, then a sweep there (with its tau);
+ *   up:   for l = L-2 .. 0: interpolation of level l+1's correction to level
+ *         l, then, on the levels between the finest and the coarsest, a
+ *         further sweep (with their tau); no closing sweep on level 0.
+ * With two levels this is fine sweep, restriction, coarse sweep,
+ * interpolation.  The sweep on an intermediate level on the way up is a
+ * reading (the paper defers the details of MLSDC to its references).
+ */
+static int mlsdc_vcycle(const or_problem *pb, double tn, or_hier *H, or_stats *st)
+{
+    const int L = pb->nlevels;
+    int status = or_sdc_sweep(&pb->lev[0], &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, H->U[0], H->FI[0], NULL, st);
+    for (int l = 0; l + 1 < L; l++) {
+        restrict_level(pb, l, tn, H);
+        int s = or_sdc_sweep(&pb->lev[l + 1], &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, H->U[l + 1],
+                             H->FI[l + 1], H->tau[l + 1], NULL);
+        if (s != OR_OK && status == OR_OK) status = s;
+    }
+    for (int l = L - 2; l >= 0; l--) {
+        interp_level(pb, l, H);
+        if (l > 0) {
+            int s = or_sdc_sweep(&pb->lev[l], &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, H->U[l], H->FI[l],
+                                 H->tau[l], NULL);
+            if (s != OR_OK && status == OR_OK) status = s;
+        }
+    }
+    return status;
+}
+
+/*
+ * One two-level MLSDC iteration on caller arrays: fine sweep, restriction +
+ * FAS correction, coarse sweep with tau, interpolation of the coarse
+ * correction (mlsdc_vcycle with two levels).
  */
 int or_mlsdc_iter(const or_problem *pb, double tn, double *Uf, double *FIf, double *Uc,
                   double *FIc, double *Ut, double *tau, or_stats *st)
 {
-    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
-    int status = or_sdc_sweep(Lf, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, NULL, st);
-    or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, Uc, FIc, Ut, tau);
-    int s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc, FIc, tau, NULL);
-    if (s != OR_OK && status == OR_OK) status = s;
-    or_fas_interp(Lf, Lc, pb->nu, Uf, FIf, Uc, Ut, pb->fas_interp);
-    return status;
+    if (pb->nlevels != 2) return OR_EINVAL;
+    or_hier H;
+    memset(&H, 0, sizeof(H));
+    H.U[0] = Uf; H.FI[0] = FIf;
+    H.U[1] = Uc; H.FI[1] = FIc; H.Ut[1] = Ut; H.tau[1] = tau;
+    return mlsdc_vcycle(pb, tn, &H, st);
 }
 
 static int mlsdc_step(const or_problem *pb, double tn, double *u, or_stats *st)
 {
-    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
-    size_t Nf = cube(Lf->n), Nc = cube(Lc->n);
-    double *Uf = alloc0((size_t)Lf->M * Nf), *FIf = alloc0((size_t)Lf->M * Nf);
-    double *Uc = alloc0((size_t)Lc->M * Nc), *FIc = alloc0((size_t)Lc->M * Nc);
-    double *Ut = alloc0((size_t)Lc->M * Nc), *tau = alloc0((size_t)Lc->M * Nc);
-    or_spread(Lf, pb->nu, u, Uf, FIf);
+    const or_level *Lf = &pb->lev[0];
+    size_t Nf = cube(Lf->n);
+    or_hier H;
+    hier_alloc(pb, &H);
+    or_spread(Lf, pb->nu, u, H.U[0], H.FI[0]);
     int status = OR_OK, k;
     for (k = 0;; k++) {
         if (pb->sweeps > 0) {
             if (k >= pb->sweeps) break;
         } else {
-            double R = or_sdc_residual(Lf, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, NULL);
+            double R = or_sdc_residual(Lf, pb->nu, tn, pb->dt, pb->forcing_c, H.U[0], H.FI[0], NULL);
             if (st) st->last_residual = R;
             if (R != R) { status = OR_ENONFINITE; break; }
             if (R <= pb->sdc_tol) break;
             if (k >= pb->max_sweeps) { status = OR_ENOCONV; break; }
         }
-        int s = or_mlsdc_iter(pb, tn, Uf, FIf, Uc, FIc, Ut, tau, st);
+        int s = mlsdc_vcycle(pb, tn, &H, st);
         if (s != OR_OK && status == OR_OK) status = s;
     }
     if (pb->sweeps > 0 && st)
-        st->last_residual = or_sdc_residual(Lf, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, NULL);
+        st->last_residual = or_sdc_residual(Lf, pb->nu, tn, pb->dt, pb->forcing_c, H.U[0], H.FI[0], NULL);
     if (st) st->sweeps = k;
-    memcpy(u, Uf + (size_t)(Lf->M - 1) * Nf, Nf * sizeof(double));
-    free(Uf); free(FIf); free(Uc); free(FIc); free(Ut); free(tau);
+    memcpy(u, H.U[0] + (size_t)(Lf->M - 1) * Nf, Nf * sizeof(double));
+    hier_free(pb, &H);
     return status;
 }
 
 static int check_problem(const or_problem *pb)
 {
-    if (pb->nlevels < 1 || pb->nlevels > 2) return OR_EINVAL;
+    if (pb->nlevels < 1 || pb->nlevels > OR_MAXLEV) return OR_EINVAL;
     for (int l = 0; l < pb->nlevels; l++) {
         const or_level *L = &pb->lev[l];
         if (!valid_n(L->n) || (L->order != 2 && L->order != 4)) return OR_EINVAL;
         if (L->M < 2 || L->M > OR_MAXM) return OR_EINVAL;
     }
-    if (pb->nlevels == 2) {
-        if (pb->lev[1].n != (pb->lev[0].n - 1) / 2) return OR_EINVAL;
-        if ((pb->lev[0].M - 1) % (pb->lev[1].M - 1) != 0) return OR_EINVAL;
+    for (int l = 1; l < pb->nlevels; l++) {
+        if (pb->lev[l - 1].n < 3 || pb->lev[l].n != (pb->lev[l - 1].n - 1) / 2) return OR_EINVAL;
+        if ((pb->lev[l - 1].M - 1) % (pb->lev[l].M - 1) != 0) return OR_EINVAL;
     }
     if (!(pb->dt > 0.0) || !(pb->nu > 0.0) || pb->nsteps < 0) return OR_EINVAL;
     if (pb->node_parallel != 0 && (pb->node_parallel != 1 || pb->nlevels != 1)) return OR_EINVAL;
@@ -972,7 +1061,7 @@ static int check_problem(const or_problem *pb)
 
 /*
  * Run nsteps time steps from u (overwritten with the final value), single
- * level SDC or two-level MLSDC depending on nlevels.  t_n = t0 + n dt.
+ * level SDC or MLSDC over 2 or 3 levels depending on nlevels.  t_n = t0 + n dt.
  */
 int or_run(const or_problem *pb, double *u, or_stats *st)
 {
@@ -1002,12 +1091,13 @@ int or_run(const or_problem *pb, double *u, or_stats *st)
  *  - every slice starts with u spread over all of its fine nodes;
  *  - optional coarse predictor (pred_sweeps > 0; also a reading: the paper
  *    leaves PFASST's start to its references and notes that early
- *    iterations on later slices start from inaccurate values): the coarse
+ *    iterations on later slices start from inaccurate values): the coarsest
  *    level is run serially through the slices without the FAS correction.
- *    Slice p restricts its fine values; for p >= 1 its coarse nodes all take
- *    the coarse end value of slice p-1 (spread, as a time step starts);
- *    then pred_sweeps coarse sweeps.  Every slice then interpolates its
- *    coarse correction (node 0 included) to the fine level.  The coarse
+ *    Slice p restricts its fine values down to the coarsest level; for
+ *    p >= 1 its coarsest nodes all take the coarsest end value of slice p-1
+ *    (spread, as a time step starts); then pred_sweeps coarse sweeps.  Every
+ *    slice then interpolates its coarse correction (node 0 included) level
+ *    by level to the finest level, without sweeps in between.  The coarse
  *    values this leaves are those of a serial coarse SDC run over the P
  *    steps with pred_sweeps sweeps each;
  *  - iteration: (i) for p >= 1, fine node 0 of slice p takes the fine end
@@ -1015,10 +1105,15 @@ int or_run(const or_problem *pb, double *u, or_stats *st)
  *    (the predictor's result before the first) -- parity unpinned: no pin
  *    distinguishes this timing from taking the end value of the current
  *    iteration; fine sweep on every slice;
- *    (ii) restriction + tau on every slice; (iii) slices in order
- *    p = 0..P-1: for p >= 1 coarse node 0 takes the coarse end value slice
- *    p-1 has just computed, then the coarse sweep; (iv) interpolation on
- *    every slice, node 0 included;
+ *    (ii) restriction + tau on every slice, level by level down to the
+ *    coarsest, with a sweep on every slice of each intermediate level;
+ *    (iii) slices in order p = 0..P-1: for p >= 1 coarse node 0 takes the
+ *    coarse end value slice p-1 has just computed, then the coarse sweep;
+ *    (iv) interpolation on every slice, node 0 included, level by level up
+ *    to the finest, with a sweep on every slice of each intermediate level
+ *    (three levels: the same V-cycle as mlsdc_vcycle; an intermediate
+ *    level's node 0 is the restriction of the fine one, it has no hand-off
+ *    of its own);
  *  - pb->sweeps > 0: exactly that many iterations.  pb->sweeps == 0: after
  *    the fine hand-off of every iteration the collocation residual of every
  *    slice is taken (eq. (6) moved to one side, max norm, absolute, as in
@@ -1033,53 +1128,52 @@ int or_pfasst(const or_problem *pb, int P, int pred_sweeps, double *u, or_stats 
 {
     int s = check_problem(pb);
     if (s != OR_OK) return s;
-    if (pb->nlevels != 2 || P < 1 || pb->nsteps % P != 0 || pb->sweeps < 0 || pred_sweeps < 0)
+    if (pb->nlevels < 2 || P < 1 || pb->nsteps % P != 0 || pb->sweeps < 0 || pred_sweeps < 0)
         return OR_EINVAL;
-    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
+    const int NL = pb->nlevels, C = NL - 1;   /* C: the coarsest level */
+    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[C];
     int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
     size_t Nf = cube(nf), Nc = cube(nc);
-    size_t SF = (size_t)Mf * Nf, SC = (size_t)Mc * Nc;
-    double *Uf = alloc0(P * SF), *FIf = alloc0(P * SF);
-    double *Uc = alloc0(P * SC), *FIc = alloc0(P * SC), *Ut = alloc0(P * SC), *tau = alloc0(P * SC);
+    or_hier *H = (or_hier *)calloc((size_t)P, sizeof(or_hier));
+    for (int p = 0; p < P; p++) hier_alloc(pb, &H[p]);
     double *ends = alloc0((size_t)P * Nf);
     if (st) memset(st, 0, sizeof(*st));
     int status = OR_OK, k = 0;
     for (int blk = 0; blk < pb->nsteps / P; blk++) {
         double tb = pb->t0 + (double)(blk * P) * pb->dt;
-        for (int p = 0; p < P; p++) or_spread(Lf, pb->nu, u, Uf + p * SF, FIf + p * SF);
+        for (int p = 0; p < P; p++) or_spread(Lf, pb->nu, u, H[p].U[0], H[p].FI[0]);
         if (pred_sweeps > 0) {
             for (int p = 0; p < P; p++) {
                 double tn = tb + p * pb->dt;
-                or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf + p * SF, FIf + p * SF,
-                                Uc + p * SC, FIc + p * SC, Ut + p * SC, tau + p * SC);
+                for (int l = 0; l < C; l++) restrict_level(pb, l, tn, &H[p]);
                 if (p >= 1) {
                     /* the coarse step starts from slice p-1's end value, spread */
-                    memcpy(ends, Uc + (p - 1) * SC + (size_t)(Mc - 1) * Nc, Nc * sizeof(double));
-                    or_spread(Lc, pb->nu, ends, Uc + p * SC, FIc + p * SC);
+                    memcpy(ends, H[p - 1].U[C] + (size_t)(Mc - 1) * Nc, Nc * sizeof(double));
+                    or_spread(Lc, pb->nu, ends, H[p].U[C], H[p].FI[C]);
                 }
                 for (int j = 0; j < pred_sweeps; j++) {
-                    s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc + p * SC, FIc + p * SC,
+                    s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, H[p].U[C], H[p].FI[C],
                                      NULL, NULL);
                     if (s != OR_OK && status == OR_OK) status = s;
                 }
             }
             for (int p = 0; p < P; p++)
-                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC, pb->fas_interp);
+                for (int l = C - 1; l >= 0; l--) interp_level(pb, l, &H[p]);
         }
         for (k = 0;; k++) {
             if (pb->sweeps > 0 && k >= pb->sweeps) break;
             /* (i) fine hand-off from the previous iteration's end values */
             for (int p = 0; p < P; p++)
-                memcpy(ends + (size_t)p * Nf, Uf + p * SF + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
+                memcpy(ends + (size_t)p * Nf, H[p].U[0] + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
             for (int p = 1; p < P; p++) {
-                memcpy(Uf + p * SF, ends + (size_t)(p - 1) * Nf, Nf * sizeof(double));
-                or_lap_apply(nf, Lf->order, 0.0, pb->nu, Uf + p * SF, FIf + p * SF);
+                memcpy(H[p].U[0], ends + (size_t)(p - 1) * Nf, Nf * sizeof(double));
+                or_lap_apply(nf, Lf->order, 0.0, pb->nu, H[p].U[0], H[p].FI[0]);
             }
             if (pb->sweeps == 0) {
                 double R = 0.0;
                 for (int p = 0; p < P; p++) {
-                    double r = or_sdc_residual(Lf, pb->nu, tb + p * pb->dt, pb->dt, pb->forcing_c, Uf + p * SF,
-                                               FIf + p * SF, NULL);
+                    double r = or_sdc_residual(Lf, pb->nu, tb + p * pb->dt, pb->dt, pb->forcing_c, H[p].U[0],
+                                               H[p].FI[0], NULL);
                     if (r > R || r != r) R = r;
                 }
                 if (st) st->last_residual = R;
@@ -1089,34 +1183,49 @@ int or_pfasst(const or_problem *pb, int P, int pred_sweeps, double *u, or_stats 
             }
             for (int p = 0; p < P; p++) {
                 double tn = tb + p * pb->dt;
-                s = or_sdc_sweep(Lf, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uf + p * SF, FIf + p * SF, NULL, st);
+                s = or_sdc_sweep(Lf, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, H[p].U[0], H[p].FI[0], NULL, st);
                 if (s != OR_OK && status == OR_OK) status = s;
             }
-            /* (ii) restriction and tau */
-            for (int p = 0; p < P; p++) {
-                double tn = tb + p * pb->dt;
-                or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf + p * SF, FIf + p * SF,
-                                Uc + p * SC, FIc + p * SC, Ut + p * SC, tau + p * SC);
-            }
+            /* (ii) restriction and tau down to the coarsest level, with a sweep
+               on every intermediate level on the way */
+            for (int l = 0; l < C; l++)
+                for (int p = 0; p < P; p++) {
+                    double tn = tb + p * pb->dt;
+                    restrict_level(pb, l, tn, &H[p]);
+                    if (l + 1 < C) {
+                        s = or_sdc_sweep(&pb->lev[l + 1], &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c,
+                                         H[p].U[l + 1], H[p].FI[l + 1], H[p].tau[l + 1], NULL);
+                        if (s != OR_OK && status == OR_OK) status = s;
+                    }
+                }
             /* (iii) coarse pipeline */
             for (int p = 0; p < P; p++) {
                 double tn = tb + p * pb->dt;
                 if (p >= 1) {
-                    memcpy(Uc + p * SC, Uc + (p - 1) * SC + (size_t)(Mc - 1) * Nc, Nc * sizeof(double));
-                    or_lap_apply(nc, Lc->order, 0.0, pb->nu, Uc + p * SC, FIc + p * SC);
+                    memcpy(H[p].U[C], H[p - 1].U[C] + (size_t)(Mc - 1) * Nc, Nc * sizeof(double));
+                    or_lap_apply(nc, Lc->order, 0.0, pb->nu, H[p].U[C], H[p].FI[C]);
                 }
-                s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc + p * SC, FIc + p * SC,
-                                 tau + p * SC, NULL);
+                s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, H[p].U[C], H[p].FI[C],
+                                 H[p].tau[C], NULL);
                 if (s != OR_OK && status == OR_OK) status = s;
             }
-            /* (iv) interpolation */
-            for (int p = 0; p < P; p++)
-                or_fas_interp(Lf, Lc, pb->nu, Uf + p * SF, FIf + p * SF, Uc + p * SC, Ut + p * SC, pb->fas_interp);
+            /* (iv) interpolation up to the finest level, node 0 included, with a
+               sweep on every intermediate level on the way */
+            for (int l = C - 1; l >= 0; l--)
+                for (int p = 0; p < P; p++) {
+                    interp_level(pb, l, &H[p]);
+                    if (l > 0) {
+                        s = or_sdc_sweep(&pb->lev[l], &pb->mg, pb->nu, tb + p * pb->dt, pb->dt, pb->forcing_c,
+                                         H[p].U[l], H[p].FI[l], H[p].tau[l], NULL);
+                        if (s != OR_OK && status == OR_OK) status = s;
+                    }
+                }
         }
-        memcpy(u, Uf + (size_t)(P - 1) * SF + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
+        memcpy(u, H[P - 1].U[0] + (size_t)(Mf - 1) * Nf, Nf * sizeof(double));
     }
     if (st) { st->status = status; st->sweeps = k; }
-    free(Uf); free(FIf); free(Uc); free(FIc); free(Ut); free(tau); free(ends);
+    for (int p = 0; p < P; p++) hier_free(pb, &H[p]);
+    free(H); free(ends);
     return status;
 }
 

@@ -799,3 +799,127 @@ def test_invalid_fas_interp_rejected():
     pb.fas_interp = 2
     _, s, _ = oracle.run(pb, inputs.sine_product(7))
     assert s == oracle.EINVAL
+
+
+# ----------------------------------------------------------------------------
+# Three-level MLSDC / PFASST (sec. 1.1: a hierarchy of levels tied by FAS)
+# ----------------------------------------------------------------------------
+
+def three_level(nf=15, nsteps=1, sweeps=3, dt=0.05, c=3.0, mg=None, t0=0.0, M=(5, 3, 2)):
+    n1 = (nf - 1) // 2
+    return oracle.problem([(nf, 4, M[0]), (n1, 2, M[1]), ((n1 - 1) // 2, 2, M[2])], nu=0.1, t0=t0, dt=dt,
+                          nsteps=nsteps, sweeps=sweeps, forcing_c=c, mg=mg if mg is not None else TIGHT)
+
+
+def test_three_level_fas_fixed_point():
+    """If the finest level holds its collocation solution, each coarser level's
+    FAS problem is solved by the restricted values: the middle level's with
+    its own tau, the coarsest level's with a tau that carries the middle
+    level's (the restriction of the FAS-corrected integral), so no sweep
+    moves and both corrections are 0."""
+    pb = three_level(nf=15, dt=0.1)
+    u0 = inputs.random_smooth(15, 4)
+    tn = 0.2
+    U0, F0 = fine_collocation(pb, u0, tn)
+    l0, l1, l2 = pb.lev[0], pb.lev[1], pb.lev[2]
+    args = (pb.nu, tn, pb.dt, pb.forcing_c)
+    U1, F1, Ut1, tau1 = oracle.fas_restrict(l0, l1, *args, U0, F0)
+    oracle.sdc_sweep(l1, pb.mg, *args, U1, F1, tau1)
+    assert np.abs(U1 - Ut1).max() < 1e-12
+    U2, F2, Ut2, tau2 = oracle.fas_restrict(l1, l2, *args, U1, F1, tauf=tau1)
+    assert oracle.sdc_residual(l2, *args, U2, F2, tau2) < 1e-12
+    oracle.sdc_sweep(l2, pb.mg, *args, U2, F2, tau2)
+    assert np.abs(U2 - Ut2).max() < 1e-12
+    V1, G1 = U1.copy(), F1.copy()
+    oracle.fas_interp(l1, l2, pb.nu, V1, G1, U2, Ut2)
+    assert np.abs(V1 - U1).max() < 1e-12
+    V0, G0 = U0.copy(), F0.copy()
+    oracle.fas_interp(l0, l1, pb.nu, V0, G0, V1, Ut1)
+    assert np.abs(V0 - U0).max() < 1e-12
+
+
+def test_three_level_restriction_needs_the_middle_tau():
+    """Control for the pin above: restricting the middle level without its
+    own tau leaves the coarsest FAS problem unsolved by the restricted values."""
+    pb = three_level(nf=15, dt=0.1)
+    u0 = inputs.random_smooth(15, 4)
+    U0, F0 = fine_collocation(pb, u0, 0.2)
+    args = (pb.nu, 0.2, pb.dt, pb.forcing_c)
+    U1, F1, Ut1, tau1 = oracle.fas_restrict(pb.lev[0], pb.lev[1], *args, U0, F0)
+    assert np.abs(tau1[1:]).max() > 1e-6
+    U2, F2, Ut2, tau2 = oracle.fas_restrict(pb.lev[1], pb.lev[2], *args, U1, F1)
+    assert oracle.sdc_residual(pb.lev[2], *args, U2, F2, tau2) > 1e-6
+
+
+def test_mlsdc3_converges_to_fine_collocation():
+    pb = three_level(nf=15, sweeps=40, dt=0.1)
+    u0 = inputs.random_smooth(15, 6)
+    u, st, _ = oracle.run(pb, u0)
+    assert st == oracle.OK
+    Uf, _ = fine_collocation(pb, u0, 0.0)
+    assert np.abs(u - Uf[-1]).max() < 1e-11
+
+
+def test_mlsdc3_tolerance_mode_stops_on_the_fine_residual():
+    pb = three_level(nf=15, sweeps=0, dt=0.1, nsteps=2)
+    pb.sdc_tol, pb.max_sweeps = 1e-8, 60
+    u0 = inputs.random_smooth(15, 6)
+    u, st, stats = oracle.run(pb, u0)
+    assert st == oracle.OK and 1 <= stats.sweeps < 60 and stats.last_residual <= 1e-8
+    pb.max_sweeps = stats.sweeps - 1     # one iteration fewer does not reach it
+    assert oracle.run(pb, u0)[1] == oracle.ENOCONV
+
+
+def test_pfasst3_one_slice_is_mlsdc3():
+    pb = three_level(nf=15, nsteps=2, sweeps=3)
+    u0 = inputs.random_smooth(15, 7)
+    a, s1, _ = oracle.run(pb, u0)
+    b, s2, _ = oracle.pfasst_run(pb, 1, u0)
+    assert s1 == s2 == oracle.OK
+    assert np.array_equal(a, b)
+
+
+def test_pfasst3_converges_to_serial_composite_collocation():
+    P = 4
+    pb = three_level(nf=15, nsteps=P, sweeps=40, dt=0.05)
+    u0 = inputs.random_smooth(15, 8)
+    u, st, _ = oracle.pfasst_run(pb, P, u0)
+    assert st == oracle.OK
+    ref = u0.copy()
+    for p in range(P):
+        Uf, _ = fine_collocation(pb, ref, p * pb.dt)
+        ref = Uf[-1].copy()
+    assert np.abs(u - ref).max() < 1e-11
+
+
+@pytest.mark.parametrize("pred", [1, 2])
+def test_pfasst3_predictor_is_serial_coarsest_sdc(pred):
+    """With three levels the predictor runs the coarsest level serially: the
+    fine end value after it is u0 plus the prolongation, through the middle
+    grid, of a single-level coarsest SDC run's change from the injected
+    initial value (a tolerance so loose that the first residual test stops
+    the run returns exactly that)."""
+    P, nf = 4, 15
+    pb = three_level(nf=nf, nsteps=P, sweeps=0, dt=0.05)
+    pb.sdc_tol, pb.max_sweeps = 1e300, 10
+    u0 = inputs.random_smooth(nf, 13)
+    got, s, st = oracle.pfasst(pb, P, u0, pred_sweeps=pred)
+    assert s == oracle.OK and st.sweeps == 0
+    u1 = oracle.inject(u0)
+    u2 = oracle.inject(u1)
+    n2 = pb.lev[2].n
+    cpb = oracle.problem([(n2, 2, 2)], nu=pb.nu, dt=pb.dt, nsteps=P, sweeps=pred, forcing_c=pb.forcing_c,
+                         mg=pb.mg)
+    uc, s2, _ = oracle.run(cpb, u2)
+    assert s2 == oracle.OK
+    mid = oracle.prolong_add(uc - u2, u1)
+    expect = oracle.prolong_add(mid - u1, u0)
+    assert np.array_equal(got, expect)
+
+
+def test_three_levels_validated():
+    u0 = inputs.random_smooth(15, 1)
+    bad = oracle.problem([(15, 4, 5), (7, 2, 3), (5, 2, 2)], sweeps=1)      # n2 != (n1 - 1) / 2
+    assert oracle.run(bad, u0)[1] == oracle.EINVAL
+    bad = oracle.problem([(15, 4, 5), (7, 2, 3), (3, 2, 4)], sweeps=1)      # M1 - 1 not a multiple of M2 - 1
+    assert oracle.run(bad, u0)[1] == oracle.EINVAL
