@@ -115,8 +115,10 @@ typedef struct {
     double t0, dt;           /* start time, step size */
     double forcing_c;        /* c of the forcing: 3 consistent, 1 as printed, 0 for s(x) sin t */
     int32_t nsteps;
-    int32_t nlevels;         /* 1 = SDC, 2 = MLSDC / PFASST */
-    hs_level_desc lev[2];    /* lev[0] fine; lev[1] coarse: n = (n_f - 1)/2, order 2 */
+    int32_t nlevels;         /* 1 = SDC; 2 or 3 = MLSDC / PFASST (section 1.1: a hierarchy of
+                                levels with fewer nodes and points, tied by the FAS correction) */
+    hs_level_desc lev[3];    /* lev[0] finest .. lev[nlevels-1] coarsest: n_l = (n_{l-1} - 1)/2,
+                                nnodes_{l-1} - 1 a multiple of nnodes_l - 1 */
     hs_mg_desc mg;
     int32_t sweeps;          /* fixed sweeps (SDC) / iterations (MLSDC, PFASST); 0 = until sdc_tol */
     double sdc_tol;          /* absolute max-norm collocation residual target */
@@ -140,7 +142,7 @@ typedef struct {
                                 one batch, then the coarse pipeline; G >= 2 (dividing nslices)
                                 splits the slices into G groups of consecutive slices whose fine
                                 sweeps and coarse pipeline overlap (see hs_pfasst_run); same
-                                results */
+                                results; two levels only */
     int32_t fas_interp;      /* MLSDC / PFASST: spatial transfer of the coarse correction to the
                                 fine level (section 1.1 leaves it to the references): 0 or 1
                                 trilinear, 3 tricubic (4-point Lagrange per axis, odd reflection
@@ -159,7 +161,7 @@ typedef struct {
     int32_t failed_solves;
     double last_rho;         /* relative residual of the last solve */
     double last_sdc_res;     /* last collocation residual taken */
-    int64_t level_cycles[2]; /* total_cycles split by SDC level (fine, coarse) */
+    int64_t level_cycles[3]; /* total_cycles split by SDC level (finest first) */
 } hs_lane_stats;
 
 typedef struct hs_plan hs_plan;
@@ -275,9 +277,16 @@ hs_status hs_set_nodes(hs_plan* plan, int32_t level, const double* d_U, const do
 /* Step-level calls, in the order a time step uses them:
  *   hs_begin_step : step coefficients, predictor (spread the state to all nodes)
  *   hs_sdc_sweep  : one IMEX SDC sweep of SDC level `level` (eq. (7)); on
- *                   the coarse level of an MLSDC plan it includes tau
- *   hs_fas_restrict / hs_fas_interp : FAS transfer between the levels
- *   hs_mlsdc_iter : fine sweep, restriction + tau, coarse sweep, interpolation
+ *                   the coarser levels of an MLSDC plan it includes tau
+ *   hs_fas_restrict / hs_fas_interp : FAS transfer between levels 0 and 1
+ *   hs_mlsdc_iter : one MLSDC iteration as a V-cycle over the levels (section
+ *                   1.1): a sweep on level 0; per level, restriction + tau
+ *                   (which carries the finer level's own tau below level 1)
+ *                   and a sweep, down to the coarsest; on the way up,
+ *                   interpolation to each level and, on a level between the
+ *                   finest and the coarsest, another sweep; no closing sweep
+ *                   on level 0.  Two levels: fine sweep, restriction + tau,
+ *                   coarse sweep, interpolation.
  *   hs_end_step   : the last node becomes the state (eq. (9)). */
 hs_status hs_begin_step(hs_plan* plan, void* stream);
 hs_status hs_sdc_sweep(hs_plan* plan, int32_t level, void* stream);
@@ -290,16 +299,20 @@ hs_status hs_end_step(hs_plan* plan, void* stream);
 hs_status hs_step(hs_plan* plan, void* stream);
 hs_status hs_solve(hs_plan* plan, void* stream);
 
-/* PFASST (section 1.1; nslices = batch = P, nlevels = 2): nsteps / P blocks
- * of P time slices.  Every slice starts from the block's initial value
- * spread over its nodes.  With pfasst_pred_sweeps > 0 a coarse predictor
- * runs first: the coarse level goes serially through the slices without
- * the FAS correction (slice p starts from slice p-1's coarse end value,
- * spread, and does pfasst_pred_sweeps coarse sweeps), then every slice
- * interpolates its coarse correction to the fine level.  Each iteration:
- * fine hand-off (slice p takes slice p-1's fine end value of the previous
- * iteration), fine sweeps of all slices as one batch, FAS restriction,
- * the coarse sweeps as a blocking pipeline p = 0..P-1, interpolation.
+/* PFASST (section 1.1; nslices = batch = P, nlevels = 2 or 3): nsteps / P
+ * blocks of P time slices.  Every slice starts from the block's initial
+ * value spread over its nodes.  With pfasst_pred_sweeps > 0 a coarse
+ * predictor runs first: the coarsest level goes serially through the slices
+ * without the FAS correction (slice p starts from slice p-1's coarse end
+ * value, spread, and does pfasst_pred_sweeps coarse sweeps), then every
+ * slice interpolates its coarse correction level by level to the finest.
+ * Each iteration: fine hand-off (slice p takes slice p-1's fine end value
+ * of the previous iteration), fine sweeps of all slices as one batch, FAS
+ * restriction level by level (three levels: with a batched sweep of the
+ * middle level in between), the coarsest sweeps as a blocking pipeline
+ * p = 0..P-1, interpolation level by level (three levels: with a batched
+ * middle-level sweep in between); the middle level of a slice has no
+ * hand-off of its own, its node 0 comes from the restriction.
  * sweeps > 0: that many iterations.  sweeps = 0: iterate until every
  * slice's collocation residual, taken after the hand-off, is <= sdc_tol
  * (the paper's PFASST threshold, section 2), at most max_sweeps
@@ -307,7 +320,7 @@ hs_status hs_solve(hs_plan* plan, void* stream);
  * count the iterations.  Synchronises once per iteration in the
  * tolerance mode.
  *
- * pfasst_groups = G >= 2 (fixed iterations): the same operations in a
+ * pfasst_groups = G >= 2 (fixed iterations, two levels): the same operations in a
  * pipelined order.  The slices form G groups of P/G consecutive slices;
  * the fine sweep of one group runs as one batch on `stream` while the
  * coarse pipeline of the group before it runs on a second stream of the

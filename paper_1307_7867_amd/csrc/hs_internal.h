@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #define HS_MAXM 5          // collocation nodes per SDC level (3 and 5 are used)
+#define HS_MAXLEV 3        // SDC levels of an MLSDC hierarchy
 #define HS_MAXTAIL 5       // grids inside the single-workgroup coarse tail (15, 7, 3, 1)
 #define HS_TAIL_N 15       // grids with n <= HS_TAIL_N are handled by the tail kernel
 #define HS_BLOCK 512       // threads per block of the grid kernels (HS_TX x HS_TY)
@@ -23,8 +24,8 @@ struct LaneCtl {
     int32_t active, pad0;        // 1 = lane holds a live problem
     // coefficients of the current step, per SDC level
     double tn;
-    double a[2][HS_MAXM];        // nu * dt_m (substep m)
-    double g[2][HS_MAXM];        // forcing time factor -(sin t_j - c nu pi^2 cos t_j)
+    double a[HS_MAXLEV][HS_MAXM];  // nu * dt_m (substep m)
+    double g[HS_MAXLEV][HS_MAXM];  // forcing time factor -(sin t_j - c nu pi^2 cos t_j)
     double a_user;               // coefficient for stand-alone solves
     // control
     int32_t sdc_state;           // 0 iterate, 1 converged, 2 failed, 3 idle
@@ -43,11 +44,11 @@ struct LaneCtl {
     int32_t total_solves, max_cycles, total_sweeps, sweeps_step;
     int32_t failed_solves;
     int32_t parent;              // node-parallel solver lane: its SDC lane, else -1
-    long long level_cycles[2];   // cycles of the solves on SDC level 0 / 1
+    long long level_cycles[HS_MAXLEV];  // cycles of the solves per SDC level
     // Every lane's state fills whole 256-byte blocks: lanes that kernels on
     // different streams update at the same time (PFASST slice groups) never
     // share a cache line.
-    char pad_[160];
+    char pad_[72];
 };
 static_assert(sizeof(LaneCtl) % 256 == 0, "lane states must not share cache lines");
 
@@ -116,6 +117,8 @@ struct FasSeg {
     const double* sigc;
     double* Ex;                   // tricubic transfer: [Mc][nc][nc][nf] x-interpolated corrections
     double* Exy;                  //   and [Mc][nc][nf][nf] xy-interpolated ones
+    const double* tauf;           // the fine level's own FAS correction [Mf][Nf] (null on level 0)
+    int32_t lf, pad;              // SDC level of the fine side (the coarse side is lf + 1)
 };
 
 // Exact solve on the coarsest grid (n = 3 or 1) by the discrete sine
@@ -279,7 +282,7 @@ hipError_t fas_interp(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int 
                       hipStream_t s);
 
 // lane bookkeeping
-hipError_t begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int M1, hipStream_t s);
+hipError_t begin_step(LaneCtl* ctl, int nlanes, int nlevels, const int* M, hipStream_t s);
 hipError_t end_step(LaneCtl* ctl, int nlanes, hipStream_t s);
 // lane states first .. first + nlanes - 1
 hipError_t begin_solve(LaneCtl* ctl, int first, int nlanes, hipStream_t s);

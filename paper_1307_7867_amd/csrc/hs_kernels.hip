@@ -238,7 +238,7 @@ __device__ __forceinline__ void finish_solve(LaneCtl& c, int cycle, int state, i
     c.mg_state = state;
     c.mg_cycle = cycle;
     c.total_cycles += cycle;
-    c.level_cycles[level & 1] += cycle;
+    if (level >= 0 && level < HS_MAXLEV) c.level_cycles[level] += cycle;
     c.total_solves += 1;
     if (cycle > c.max_cycles) c.max_cycles = cycle;
     if (state == 2) c.failed_solves += 1;
@@ -2382,10 +2382,12 @@ __global__ void __launch_bounds__(HS_BLOCK) k_handoff(const SdcSeg* __restrict__
     d.FI[p] = ctl[d.lane].nu * (lap_scale<ORDER, double>(n) * lap_sum<ORDER, double>(ld, q.i, q.j, q.k, n, c));
 }
 
-// FAS restriction, one thread per coarse point:
+// FAS restriction from SDC level lf to lf + 1, one thread per coarse point:
 //   Ut_m = Uc_m = inj(Uf_{m'}),  FIc_m = nu Lc Ut_m,
-//   tau_m = inj(dt sum_j Qf_{m'j} Ff_j) - dt sum_j Qc_{mj} Fc_j
-// where m' is the fine node of coarse node m and F = FI + g s.
+//   tau_m = inj(dt sum_j Qf_{m'j} Ff_j + tauf_{m'}) - dt sum_j Qc_{mj} Fc_j
+// where m' is the fine node of coarse node m, F = FI + g s, and tauf is the
+// fine level's own FAS correction when it is not the finest level (the
+// coarse problem is the fine level's FAS-corrected collocation problem).
 template <int CORDER>
 __global__ void __launch_bounds__(HS_BLOCK) k_fas_restrict(const FasSeg* __restrict__ segs, int nseg,
                                                            int nblk, const LaneCtl* __restrict__ ctl,
@@ -2418,16 +2420,18 @@ __global__ void __launch_bounds__(HS_BLOCK) k_fas_restrict(const FasSeg* __restr
         sg.Ut[m * Nc + pc] = ut;
         sg.Uc[m * Nc + pc] = ut;
         sg.FIc[m * Nc + pc] = fi;
-        Fc[m] = fi + c.g[1][m] * sc_;
+        Fc[m] = fi + c.g[sg.lf + 1][m] * sc_;
     }
     double Ff[HS_MAXM];
-    for (int j = 0; j < sg.Mf; j++) Ff[j] = sg.FIf[j * Nf + pf] + c.g[0][j] * sf_;
+    for (int j = 0; j < sg.Mf; j++) Ff[j] = sg.FIf[j * Nf + pf] + c.g[sg.lf][j] * sf_;
     for (int m = 0; m < sg.Mc; m++) {
         int mf = m * stride;
         double fa = 0.0, ca = 0.0;
         for (int j = 0; j < sg.Mf; j++) fa += KF.Q[mf][j] * Ff[j];
         for (int j = 0; j < sg.Mc; j++) ca += KC.Q[m][j] * Fc[j];
-        sg.tau[m * Nc + pc] = dt * fa - dt * ca;
+        double fint = dt * fa;
+        if (sg.tauf) fint += sg.tauf[mf * Nf + pf];
+        sg.tau[m * Nc + pc] = fint - dt * ca;
     }
 }
 
@@ -2645,7 +2649,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_fas_interp3_z(const FasSeg* __rest
 
 // Step coefficients: t_n = t0 + step dt; a[L][m] = nu dt (tau_{m+1} - tau_m);
 // g[L][j] = -(sin t_j - c nu pi^2 cos t_j) at t_j = t_n + dt tau_j (eq. (3)).
-__global__ void k_begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int M1)
+__global__ void k_begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int M1, int M2)
 {
     int lane = blockIdx.x * blockDim.x + threadIdx.x;
     if (lane >= nlanes) return;
@@ -2656,7 +2660,7 @@ __global__ void k_begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int 
     c.tn = c.t0 + (double)c.step * c.dt;
     const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;
     for (int L = 0; L < nlevels; L++) {
-        const SdcConst& K = c_lc.sdc[L == 0 ? M0 : M1];
+        const SdcConst& K = c_lc.sdc[L == 0 ? M0 : L == 1 ? M1 : M2];
         for (int m = 0; m < K.M; m++) {
             double tj = c.tn + c.dt * K.tau[m];
             c.g[L][m] = -(sin(tj) - c.forcing_c * c.nu * pi2 * cos(tj));
@@ -2702,7 +2706,7 @@ __global__ void k_np_lanes(LaneCtl* ctl, int nlanes, int M, int mode)
         c.bnorm = c.mg_rho = c.sdc_res = 0.0;
         c.total_cycles = 0; c.total_solves = 0; c.max_cycles = 0; c.total_sweeps = 0;
         c.sweeps_step = 0; c.failed_solves = 0;
-        c.level_cycles[0] = c.level_cycles[1] = 0;
+        for (int l = 0; l < HS_MAXLEV; l++) c.level_cycles[l] = 0;
         c.a_user = 0.0;
     } else {
         const LaneCtl& p = ctl[b];
@@ -2767,7 +2771,7 @@ __global__ void k_set_lane(LaneCtl* ctl, int lane, double nu, double dt, double 
     c.bnorm = c.mg_rho = c.sdc_res = 0.0;
     c.total_cycles = 0; c.total_solves = 0; c.max_cycles = 0; c.total_sweeps = 0;
     c.sweeps_step = 0; c.failed_solves = 0; c.a_user = 0.0;
-    c.level_cycles[0] = c.level_cycles[1] = 0;
+    for (int l = 0; l < HS_MAXLEV; l++) c.level_cycles[l] = 0;
     c.parent = -1;
 }
 
@@ -3182,9 +3186,10 @@ hipError_t fas_interp(LaneCtl* ctl, const FasSeg* segs, int nseg, int nblk, int 
 
 static inline dim3 lanes_grid(int n) { return dim3((unsigned)((n + 63) / 64)); }
 
-hipError_t begin_step(LaneCtl* ctl, int nlanes, int nlevels, int M0, int M1, hipStream_t s)
+hipError_t begin_step(LaneCtl* ctl, int nlanes, int nlevels, const int* M, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin_step, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes, nlevels, M0, M1);
+    hipLaunchKernelGGL(k_begin_step, lanes_grid(nlanes), dim3(64), 0, s, ctl, nlanes, nlevels, M[0],
+                       nlevels > 1 ? M[1] : M[0], nlevels > 2 ? M[2] : M[0]);
     return hipGetLastError();
 }
 

@@ -197,21 +197,22 @@ struct MgSet {
 struct LaneSet {
     std::vector<int> lanes;
     int first = 0, span = 0;                   // lanes[] lie in first .. first + span - 1
-    MgSet mg64[2], mg32[2];
-    Table<SdcSeg> sdc[2];
-    Table<FasSeg> fasc, fasf;
+    MgSet mg64[HS_MAXLEV], mg32[HS_MAXLEV];
+    Table<SdcSeg> sdc[HS_MAXLEV];
+    Table<FasSeg> fasc[HS_MAXLEV - 1], fasf[HS_MAXLEV - 1];   // level l -> l + 1, by coarse / fine points
 };
 
 struct LaneBufs {
-    int n[2] = {0, 0};
-    long long N[2] = {0, 0};
-    double *U[2], *FI[2], *P[2], *rhs[2], *tmp[2];
-    double *Ut = nullptr, *tau = nullptr;
-    double *fx = nullptr, *fxy = nullptr;      // tricubic FAS transfer: x- and xy-interpolated coarse corrections
-    const double* sig[2];
-    std::vector<int> grids[2];                 // n of every multigrid grid, finest first
-    std::vector<double*> gu[2], gt[2], gb[2];  // FP64 grids (index 0 unused)
-    std::vector<float*> fu[2], ft[2], fb[2];   // FP32 grids (mixed precision)
+    int n[HS_MAXLEV] = {};
+    long long N[HS_MAXLEV] = {};
+    double *U[HS_MAXLEV] = {}, *FI[HS_MAXLEV] = {}, *P[HS_MAXLEV] = {}, *rhs[HS_MAXLEV] = {}, *tmp[HS_MAXLEV] = {};
+    double *Ut[HS_MAXLEV] = {}, *tau[HS_MAXLEV] = {};   // levels >= 1: restricted values, FAS correction
+    double *fx[HS_MAXLEV - 1] = {}, *fxy[HS_MAXLEV - 1] = {};   // tricubic FAS transfer l+1 -> l: x- and
+                                                                // xy-interpolated coarse corrections
+    const double* sig[HS_MAXLEV] = {};
+    std::vector<int> grids[HS_MAXLEV];                 // n of every multigrid grid, finest first
+    std::vector<double*> gu[HS_MAXLEV], gt[HS_MAXLEV], gb[HS_MAXLEV];  // FP64 grids (index 0 unused)
+    std::vector<float*> fu[HS_MAXLEV], ft[HS_MAXLEV], fb[HS_MAXLEV];   // FP32 grids (mixed precision)
 };
 
 }  // namespace
@@ -222,7 +223,7 @@ struct hs_plan {
     int B = 0, nlev = 1;
     int nctl = 0;                              // lane states: B SDC lanes, then node-parallel solver lanes
     bool np = false;                           // node-parallel SDC sweeps (pb.sdc_node_parallel)
-    int order[2] = {2, 2}, M[2] = {3, 3};
+    int order[HS_MAXLEV] = {2, 2, 2}, M[HS_MAXLEV] = {3, 3, 3};
     bool mixed = false;
     size_t bytes = 0;
     char* ws = nullptr;
@@ -238,15 +239,15 @@ struct hs_plan {
     bool run_dirty = true;
     // device storage for the run set's tables, room for every lane in each
     struct RunStore {
-        std::vector<GridSeg*> grid[2][2];      // [level][fp32]: jac/pro/rfw per stage, then fine
-        TailSeg* tail[2][2];
-        SdcSeg* sdc[2];
-        FasSeg *fasc, *fasf;
+        std::vector<GridSeg*> grid[HS_MAXLEV][2];   // [level][fp32]: jac/pro/rfw per stage, then fine
+        TailSeg* tail[HS_MAXLEV][2];
+        SdcSeg* sdc[HS_MAXLEV];
+        FasSeg *fasc[HS_MAXLEV - 1], *fasf[HS_MAXLEV - 1];
     } store;
     std::vector<LaneSet> single;               // PFASST coarse pipeline, one lane each
     Table<SdcSeg> hf_dst, hf_src;              // PFASST fine hand-off p-1 -> p
     std::vector<Table<SdcSeg>> hc_dst, hc_src; // PFASST coarse hand-off, per slice
-    Table<long long> offs[2];                  // lane-major packing offsets per SDC level
+    Table<long long> offs[HS_MAXLEV];          // lane-major packing offsets per SDC level
     Table<GridSeg> user;                       // hs_smooth on caller arrays
     double* partials = nullptr;                // per-block maxima of the reductions
     const void* user_key[3] = {nullptr, nullptr, nullptr};
@@ -256,7 +257,7 @@ struct hs_plan {
     // warm start improves from one iteration to the next, so the first
     // iteration of a step needs more cycles than the last one of the step before
     static constexpr int PRED_K = 4;
-    int cpred[2][HS_MAXM][PRED_K];
+    int cpred[HS_MAXLEV][HS_MAXM][PRED_K];
     int sweep_k = 0;                           // iterations (fine sweeps) done in this step
     int cpred_user = 0;
     int state_ready = 0;
@@ -507,8 +508,8 @@ SdcSeg sdc_seg(hs_plan* P, int b, int L)
     s.n = lb.n[L];
     s.M = P->M[L];
     s.U = lb.U[L]; s.FI = lb.FI[L]; s.P = lb.P[L]; s.rhs = lb.rhs[L];
-    s.Ut = L == 1 ? lb.Ut : nullptr;
-    s.tau = L == 1 ? lb.tau : nullptr;
+    s.Ut = lb.Ut[L];
+    s.tau = lb.tau[L];
     s.sig = lb.sig[L];
     s.level = L;
     return s;
@@ -534,27 +535,28 @@ void build_set_host(hs_plan* P, LaneSet& ls)
         build_mg<double>(P, ls, L, false, ls.mg64[L]);
         if (P->mixed) build_mg<float>(P, ls, L, true, ls.mg32[L]);
     }
-    if (P->nlev == 2) {
+    for (int l = 0; l + 1 < P->nlev; l++) {
         int bc = 0, bf = 0;
-        ls.fasc.h.clear();
-        ls.fasf.h.clear();
+        ls.fasc[l].h.clear();
+        ls.fasf[l].h.clear();
         for (int b : ls.lanes) {
             const LaneBufs& lb = P->lanes[b];
             FasSeg f;
             std::memset(&f, 0, sizeof(f));
             f.lane = b;
-            f.nf = lb.n[0]; f.nc = lb.n[1];
-            f.Mf = P->M[0]; f.Mc = P->M[1];
-            f.Uf = lb.U[0]; f.FIf = lb.FI[0];
-            f.Uc = lb.U[1]; f.FIc = lb.FI[1]; f.Ut = lb.Ut; f.tau = lb.tau;
-            f.sigf = lb.sig[0]; f.sigc = lb.sig[1];
-            f.Ex = lb.fx;
-            f.Exy = lb.fxy;
-            f.blk_begin = bc; bc += hsk::grid_blocks(f.nc); ls.fasc.h.push_back(f);
-            f.blk_begin = bf; bf += hsk::grid_blocks(f.nf); ls.fasf.h.push_back(f);
+            f.lf = l;
+            f.nf = lb.n[l]; f.nc = lb.n[l + 1];
+            f.Mf = P->M[l]; f.Mc = P->M[l + 1];
+            f.Uf = lb.U[l]; f.FIf = lb.FI[l]; f.tauf = lb.tau[l];
+            f.Uc = lb.U[l + 1]; f.FIc = lb.FI[l + 1]; f.Ut = lb.Ut[l + 1]; f.tau = lb.tau[l + 1];
+            f.sigf = lb.sig[l]; f.sigc = lb.sig[l + 1];
+            f.Ex = lb.fx[l];
+            f.Exy = lb.fxy[l];
+            f.blk_begin = bc; bc += hsk::grid_blocks(f.nc); ls.fasc[l].h.push_back(f);
+            f.blk_begin = bf; bf += hsk::grid_blocks(f.nf); ls.fasf[l].h.push_back(f);
         }
-        ls.fasc.nblk = bc;
-        ls.fasf.nblk = bf;
+        ls.fasc[l].nblk = bc;
+        ls.fasf[l].nblk = bf;
     }
 }
 
@@ -572,9 +574,9 @@ void build_set(hs_plan* P, LaneSet& ls, Bump& bump)
             finish_table(S->fine, bump);
         }
     }
-    if (P->nlev == 2) {
-        finish_table(ls.fasc, bump);
-        finish_table(ls.fasf, bump);
+    for (int l = 0; l + 1 < P->nlev; l++) {
+        finish_table(ls.fasc[l], bump);
+        finish_table(ls.fasf[l], bump);
     }
 }
 
@@ -587,7 +589,7 @@ void lay_lane(hs_plan* P, int b, Bump& bump)
     lb = LaneBufs();
     const hs_mg_desc& mg = P->pb.mg;
     for (int L = 0; L < P->nlev; L++) {
-        int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
+        int n = L == 0 ? P->lane_n[b] : (lb.n[L - 1] - 1) / 2;
         long long N = cube(n);
         int M = P->M[L];
         lb.n[L] = n;
@@ -604,9 +606,9 @@ void lay_lane(hs_plan* P, int b, Bump& bump)
             lb.rhs[L] = bump.arr<double>(N);
         }
         lb.tmp[L] = bump.arr<double>(N);
-        if (L == 1) {
-            lb.Ut = bump.arr<double>(M * N);
-            lb.tau = bump.arr<double>(M * N);
+        if (L >= 1) {
+            lb.Ut[L] = bump.arr<double>(M * N);
+            lb.tau[L] = bump.arr<double>(M * N);
         }
         lb.grids[L] = mg_grids(n, mg.n_coarsest);
         size_t G = lb.grids[L].size();
@@ -626,10 +628,11 @@ void lay_lane(hs_plan* P, int b, Bump& bump)
             }
         }
     }
-    if (P->nlev == 2 && P->pb.fas_interp == 3) {
-        lb.fx = bump.arr<double>((size_t)P->M[1] * lb.n[1] * lb.n[1] * lb.n[0]);
-        lb.fxy = bump.arr<double>((size_t)P->M[1] * lb.n[1] * lb.n[0] * lb.n[0]);
-    }
+    if (P->pb.fas_interp == 3)
+        for (int l = 0; l + 1 < P->nlev; l++) {
+            lb.fx[l] = bump.arr<double>((size_t)P->M[l + 1] * lb.n[l + 1] * lb.n[l + 1] * lb.n[l]);
+            lb.fxy[l] = bump.arr<double>((size_t)P->M[l + 1] * lb.n[l + 1] * lb.n[l] * lb.n[l]);
+        }
 }
 
 // Node-parallel solver lane sl = B + b (M-1) + m - 1: its finest grid is node m
@@ -692,10 +695,8 @@ void layout(hs_plan* P, char* base)
     // sine tables, one per distinct n
     P->sig.clear();
     for (int b = 0; b < P->B; b++)
-        for (int L = 0; L < P->nlev; L++) {
-            int n = L == 0 ? P->lane_n[b] : (P->lane_n[b] - 1) / 2;
+        for (int L = 0, n = P->lane_n[b]; L < P->nlev; L++, n = (n - 1) / 2)
             if (!P->sig.count(n)) P->sig[n] = bump.arr<double>(n);
-        }
     P->lanes.assign(P->nctl, LaneBufs());
     if (P->lane_base.size() != (size_t)P->B) P->lane_base.assign(P->B, nullptr);
     for (int b = 0; b < P->B; b++) {
@@ -748,8 +749,10 @@ void layout(hs_plan* P, char* base)
         }
         P->store.sdc[L] = bump.arr<SdcSeg>(P->B);
     }
-    P->store.fasc = bump.arr<FasSeg>(P->B);
-    P->store.fasf = bump.arr<FasSeg>(P->B);
+    for (int l = 0; l + 1 < HS_MAXLEV; l++) {
+        P->store.fasc[l] = l + 1 < P->nlev ? bump.arr<FasSeg>(P->B) : nullptr;
+        P->store.fasf[l] = l + 1 < P->nlev ? bump.arr<FasSeg>(P->B) : nullptr;
+    }
     P->active.assign(P->B, 1);
     P->run_dirty = true;
     P->single.clear();
@@ -776,8 +779,9 @@ void layout(hs_plan* P, char* base)
         finish_table(P->hf_src, bump);
         P->hc_dst.resize(P->B);
         P->hc_src.resize(P->B);
+        const int C = P->nlev - 1;   // the coarsest level runs the serial pipeline
         for (int p = 1; p < P->B; p++) {
-            SdcSeg d = sdc_seg(P, p, 1), s = sdc_seg(P, p - 1, 1);
+            SdcSeg d = sdc_seg(P, p, C), s = sdc_seg(P, p - 1, C);
             d.blk_begin = s.blk_begin = 0;
             P->hc_dst[p].h.push_back(d);
             P->hc_src[p].h.push_back(s);
@@ -882,9 +886,9 @@ hipError_t upload_set(hs_plan* P, const LaneSet& ls, hipStream_t s)
             if ((e = upload(S->fine, s)) != hipSuccess) return e;
         }
     }
-    if (P->nlev == 2) {
-        if ((e = upload(ls.fasc, s)) != hipSuccess) return e;
-        if ((e = upload(ls.fasf, s)) != hipSuccess) return e;
+    for (int l = 0; l + 1 < P->nlev; l++) {
+        if ((e = upload(ls.fasc[l], s)) != hipSuccess) return e;
+        if ((e = upload(ls.fasf[l], s)) != hipSuccess) return e;
     }
     return e;
 }
@@ -892,7 +896,7 @@ hipError_t upload_set(hs_plan* P, const LaneSet& ls, hipStream_t s)
 hs_status validate(const hs_problem* pb)
 {
     if (!pb) return HS_EINVAL;
-    if (pb->nlevels < 1 || pb->nlevels > 2) return HS_EINVAL;
+    if (pb->nlevels < 1 || pb->nlevels > HS_MAXLEV) return HS_EINVAL;
     if (pb->batch < 1 || pb->batch > 4096) return HS_EINVAL;
     if (!(pb->nu > 0.0) || !(pb->dt > 0.0) || pb->nsteps < 0) return HS_EINVAL;
     if (!std::isfinite(pb->t0) || !std::isfinite(pb->forcing_c)) return HS_EINVAL;
@@ -907,8 +911,8 @@ hs_status validate(const hs_problem* pb)
         for (int b = 0; b < pb->batch; b++)
             if (!valid_n(pb->h_lane_n[b])) return HS_EINVAL;
     }
-    if (pb->nlevels == 2) {
-        const hs_level_desc &f = pb->lev[0], &c = pb->lev[1];
+    for (int L = 1; L < pb->nlevels; L++) {
+        const hs_level_desc &f = pb->lev[L - 1], &c = pb->lev[L];
         if (f.n < 3 || c.n != (f.n - 1) / 2) return HS_EINVAL;
         if ((f.nnodes - 1) % (c.nnodes - 1) != 0) return HS_EINVAL;
     }
@@ -934,10 +938,10 @@ hs_status validate(const hs_problem* pb)
     if (pb->pfasst_groups < 0 || pb->pfasst_groups > pb->nslices) return HS_EINVAL;
     if (pb->fas_interp != 0 && pb->fas_interp != 1 && pb->fas_interp != 3) return HS_EINVAL;
     if (pb->pfasst_groups >= 2 &&
-        (pb->nslices % pb->pfasst_groups != 0 || pb->sweeps <= 0 || pb->mg.cycle_graphs))
+        (pb->nslices % pb->pfasst_groups != 0 || pb->sweeps <= 0 || pb->mg.cycle_graphs || pb->nlevels != 2))
         return HS_EINVAL;
     if (pb->nslices > 1) {
-        if (pb->nslices != pb->batch || pb->nlevels != 2) return HS_EINVAL;
+        if (pb->nslices != pb->batch || pb->nlevels < 2) return HS_EINVAL;
         if (pb->nsteps % pb->nslices != 0) return HS_EINVAL;
     } else if (pb->pfasst_pred_sweeps != 0) {
         return HS_EINVAL;
@@ -1425,26 +1429,51 @@ hs_status sweep(hs_plan* P, LaneSet& ls, int L, bool with_resid, bool count, hip
     return HS_OK;
 }
 
-// Interpolation of the coarse corrections of ls's lanes to their fine nodes:
-// trilinear, or tricubic with pb.fas_interp = 3 (section 1.1 leaves the
-// transfer to the references).
-hipError_t fas_interp(hs_plan* P, const LaneSet& ls, hipStream_t s)
+// Restriction + FAS correction of ls's lanes from SDC level l to l + 1.
+hipError_t fas_restrict(hs_plan* P, const LaneSet& ls, int l, hipStream_t s)
 {
-    if (P->pb.fas_interp == 3)
-        return hsk::fas_interp3(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s);
-    return hsk::fas_interp(P->ctl, ls.fasf.d, ls.fasf.nseg(), ls.fasf.nblk, 1, s);
+    const Table<FasSeg>& T = ls.fasc[l];
+    return hsk::fas_restrict(P->ctl, T.d, T.nseg(), T.nblk, P->order[l + 1], 1, s);
 }
 
+// Interpolation of the coarse corrections of ls's lanes from level l + 1 to
+// the nodes of level l: trilinear, or tricubic with pb.fas_interp = 3
+// (section 1.1 leaves the transfer to the references).
+hipError_t fas_interp(hs_plan* P, const LaneSet& ls, int l, hipStream_t s)
+{
+    const Table<FasSeg>& T = ls.fasf[l];
+    if (P->pb.fas_interp == 3) return hsk::fas_interp3(P->ctl, T.d, T.nseg(), T.nblk, 1, s);
+    return hsk::fas_interp(P->ctl, T.d, T.nseg(), T.nblk, 1, s);
+}
+
+// fas_interp to level l, then F_I recomputed at every node of level l.
+hipError_t interp_level(hs_plan* P, const LaneSet& ls, int l, hipStream_t s)
+{
+    hipError_t e = fas_interp(P, ls, l, s);
+    if (e != hipSuccess) return e;
+    return hsk::fi_march(P->ctl, ls.mg64[l].fine.d, ls.sdc[l].d, ls.sdc[l].nseg(), ls.mg64[l].fine.nblk,
+                         P->order[l], 0, P->M[l], -1, 1, s);
+}
+
+// One MLSDC iteration as a V-cycle over the nlev levels: a sweep on level 0,
+// then per level restriction + FAS correction and a sweep (with tau) down to
+// the coarsest; on the way up interpolation to each level and, on the levels
+// between the finest and the coarsest, another sweep; no closing sweep on
+// level 0 (section 1.1; with two levels: fine sweep, restriction, coarse
+// sweep, interpolation).
 hs_status mlsdc_iter(hs_plan* P, LaneSet& ls, bool with_resid, hipStream_t s, int* outcome)
 {
     HS_CHECK(sweep(P, ls, 0, with_resid, true, s, outcome));
     if (*outcome == SWEEP_DONE) return HS_OK;
-    HS_TRY(hsk::fas_restrict(P->ctl, ls.fasc.d, ls.fasc.nseg(), ls.fasc.nblk, P->order[1], 1, s));
     int o2;
-    HS_CHECK(sweep(P, ls, 1, false, false, s, &o2));
-    HS_TRY(fas_interp(P, ls, s));
-    HS_TRY(hsk::fi_march(P->ctl, ls.mg64[0].fine.d, ls.sdc[0].d, ls.sdc[0].nseg(), ls.mg64[0].fine.nblk,
-                         P->order[0], 0, P->M[0], -1, 1, s));
+    for (int l = 0; l + 1 < P->nlev; l++) {
+        HS_TRY(fas_restrict(P, ls, l, s));
+        HS_CHECK(sweep(P, ls, l + 1, false, false, s, &o2));
+    }
+    for (int l = P->nlev - 2; l >= 0; l--) {
+        HS_TRY(interp_level(P, ls, l, s));
+        if (l > 0) HS_CHECK(sweep(P, ls, l, false, false, s, &o2));
+    }
     P->sweep_k++;
     return HS_OK;
 }
@@ -1478,9 +1507,9 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
         }
         ls.sdc[L].d = ls.sdc[L].h.empty() ? nullptr : P->store.sdc[L];
     }
-    if (P->nlev == 2) {
-        ls.fasc.d = ls.fasc.h.empty() ? nullptr : P->store.fasc;
-        ls.fasf.d = ls.fasf.h.empty() ? nullptr : P->store.fasf;
+    for (int l = 0; l + 1 < P->nlev; l++) {
+        ls.fasc[l].d = ls.fasc[l].h.empty() ? nullptr : P->store.fasc[l];
+        ls.fasf[l].d = ls.fasf[l].h.empty() ? nullptr : P->store.fasf[l];
     }
     HS_TRY(upload_set(P, ls, s));
     HS_TRY(hipStreamSynchronize(s));
@@ -1493,7 +1522,7 @@ hs_status begin_step(hs_plan* P, hipStream_t s)
 {
     HS_CHECK(refresh_run(P, s));
     P->sweep_k = 0;
-    HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M[0], P->nlev > 1 ? P->M[1] : P->M[0], s));
+    HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M, s));
     if (P->np) HS_TRY(hsk::np_lanes(P->ctl, P->B, P->M[0], 1, s));
     const Table<SdcSeg>& T = P->run.sdc[0];
     HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[0], P->M[0] - 1, s));
@@ -1617,7 +1646,7 @@ static void init_plan(hs_plan* P, const hs_problem* pb)
     P->pb = *pb;
     P->B = pb->batch;
     P->nlev = pb->nlevels;
-    for (int L = 0; L < 2; L++) {
+    for (int L = 0; L < HS_MAXLEV; L++) {
         P->order[L] = L < pb->nlevels ? pb->lev[L].order : 2;
         P->M[L] = L < pb->nlevels ? pb->lev[L].nnodes : 2;
     }
@@ -1628,7 +1657,7 @@ static void init_plan(hs_plan* P, const hs_problem* pb)
     P->np = pb->sdc_node_parallel != 0;
     P->nctl = P->B + (P->np ? P->B * (P->M[0] - 1) : 0);
     P->pb.h_lane_n = nullptr;
-    for (int L = 0; L < 2; L++)
+    for (int L = 0; L < HS_MAXLEV; L++)
         for (int m = 0; m < HS_MAXM; m++)
             for (int k = 0; k < hs_plan::PRED_K; k++) P->cpred[L][m][k] = 1;
     P->cpred_user = 1;
@@ -2055,7 +2084,7 @@ hs_status hs_get_nodes(hs_plan* P, int32_t level, double* d_U, double* d_FI, dou
     HS_CHECK(check_bound(P));
     if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
-    if ((d_Ut || d_tau) && level != 1) return HS_EINVAL;
+    if ((d_Ut || d_tau) && level < 1) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     int M = P->M[level];
     for (int b = 0; b < P->B; b++) {
@@ -2063,8 +2092,8 @@ hs_status hs_get_nodes(hs_plan* P, int32_t level, double* d_U, double* d_FI, dou
         long long sz = M * lb.N[level], o = M * P->offs[level].h[b];
         if (d_U) HS_TRY(hipMemcpyAsync(d_U + o, lb.U[level], sz * 8, hipMemcpyDeviceToDevice, s));
         if (d_FI) HS_TRY(hipMemcpyAsync(d_FI + o, lb.FI[level], sz * 8, hipMemcpyDeviceToDevice, s));
-        if (d_Ut) HS_TRY(hipMemcpyAsync(d_Ut + o, lb.Ut, sz * 8, hipMemcpyDeviceToDevice, s));
-        if (d_tau) HS_TRY(hipMemcpyAsync(d_tau + o, lb.tau, sz * 8, hipMemcpyDeviceToDevice, s));
+        if (d_Ut) HS_TRY(hipMemcpyAsync(d_Ut + o, lb.Ut[level], sz * 8, hipMemcpyDeviceToDevice, s));
+        if (d_tau) HS_TRY(hipMemcpyAsync(d_tau + o, lb.tau[level], sz * 8, hipMemcpyDeviceToDevice, s));
     }
     return HS_OK;
 }
@@ -2103,31 +2132,26 @@ hs_status hs_sdc_sweep(hs_plan* P, int32_t level, void* stream)
 hs_status hs_fas_restrict(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
-    if (P->nlev != 2) return HS_EINVAL;
+    if (P->nlev < 2) return HS_EINVAL;
     HS_CHECK(refresh_run(P, (hipStream_t)stream));
-    LaneSet& ls = P->run;
-    HS_TRY(hsk::fas_restrict(P->ctl, ls.fasc.d, ls.fasc.nseg(), ls.fasc.nblk, P->order[1], 1,
-                             (hipStream_t)stream));
+    HS_TRY(fas_restrict(P, P->run, 0, (hipStream_t)stream));
     return HS_OK;
 }
 
 hs_status hs_fas_interp(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
-    if (P->nlev != 2) return HS_EINVAL;
+    if (P->nlev < 2) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     HS_CHECK(refresh_run(P, s));
-    LaneSet& ls = P->run;
-    HS_TRY(fas_interp(P, ls, s));
-    HS_TRY(hsk::fi_march(P->ctl, ls.mg64[0].fine.d, ls.sdc[0].d, ls.sdc[0].nseg(), ls.mg64[0].fine.nblk,
-                         P->order[0], 0, P->M[0], -1, 1, s));
+    HS_TRY(interp_level(P, P->run, 0, s));
     return HS_OK;
 }
 
 hs_status hs_mlsdc_iter(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
-    if (P->nlev != 2) return HS_EINVAL;
+    if (P->nlev < 2) return HS_EINVAL;
     int outcome;
     HS_CHECK(refresh_run(P, (hipStream_t)stream));
     return mlsdc_iter(P, P->run, false, (hipStream_t)stream, &outcome);
@@ -2199,26 +2223,27 @@ __global__ void k_pfasst_block(LaneCtl* ctl, int P, double t0, double dt, int bl
 namespace {
 
 // Coarse predictor of PFASST (see hs_pfasst_run): restriction of the spread
-// fine values, the coarse level run serially through the slices without the
-// FAS correction, interpolation of the coarse correction.
+// fine values down to the coarsest level, that level run serially through the
+// slices without the FAS correction, interpolation of the coarse correction
+// level by level back to the finest.
 hs_status pfasst_predictor(hs_plan* P, hipStream_t s)
 {
     LaneSet& all = P->all;
-    HS_TRY(hsk::fas_restrict(P->ctl, all.fasc.d, all.fasc.nseg(), all.fasc.nblk, P->order[1], 1, s));
-    for (int b = 0; b < P->B; b++) HS_TRY(hsk::fill(P->lanes[b].tau, (long long)P->M[1] * P->lanes[b].N[1], 0.0, s));
+    const int C = P->nlev - 1;
+    for (int l = 0; l < C; l++) HS_TRY(fas_restrict(P, all, l, s));
+    for (int b = 0; b < P->B; b++)
+        HS_TRY(hsk::fill(P->lanes[b].tau[C], (long long)P->M[C] * P->lanes[b].N[C], 0.0, s));
     int outcome;
     for (int p = 0; p < P->B; p++) {
         if (p > 0) {
             // slice p's coarse step starts from slice p-1's coarse end value, spread over its nodes
-            HS_TRY(hsk::handoff(P->ctl, P->hc_dst[p].d, P->hc_src[p].d, 1, P->hc_dst[p].nblk, P->order[1], s));
-            const Table<SdcSeg>& T = P->single[p].sdc[1];
-            HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[1], 0, s));
+            HS_TRY(hsk::handoff(P->ctl, P->hc_dst[p].d, P->hc_src[p].d, 1, P->hc_dst[p].nblk, P->order[C], s));
+            const Table<SdcSeg>& T = P->single[p].sdc[C];
+            HS_TRY(hsk::spread(P->ctl, T.d, T.nseg(), T.nblk, P->order[C], 0, s));
         }
-        for (int j = 0; j < P->pb.pfasst_pred_sweeps; j++) HS_CHECK(sweep(P, P->single[p], 1, false, false, s, &outcome));
+        for (int j = 0; j < P->pb.pfasst_pred_sweeps; j++) HS_CHECK(sweep(P, P->single[p], C, false, false, s, &outcome));
     }
-    HS_TRY(fas_interp(P, all, s));
-    HS_TRY(hsk::fi_march(P->ctl, all.mg64[0].fine.d, all.sdc[0].d, all.sdc[0].nseg(), all.mg64[0].fine.nblk,
-                         P->order[0], 0, P->M[0], -1, 1, s));
+    for (int l = C - 1; l >= 0; l--) HS_TRY(interp_level(P, all, l, s));
     return HS_OK;
 }
 
@@ -2333,10 +2358,7 @@ hs_status pipe_fine(hs_plan* P, PipeSync& ps, int nblocks, hipStream_t s)
     auto interp = [&](int g) -> hs_status {
         if (!ps.wait(ps.c[g], ++got_c[g])) return HS_ESTATE;
         HS_TRY(hipStreamWaitEvent(s, P->ev_c[g], 0));
-        const LaneSet& gs = P->grp[g];
-        HS_TRY(fas_interp(P, gs, s));
-        HS_TRY(hsk::fi_march(P->ctl, gs.mg64[0].fine.d, gs.sdc[0].d, gs.sdc[0].nseg(), gs.mg64[0].fine.nblk,
-                             P->order[0], 0, Mf, -1, 1, s));
+        HS_TRY(interp_level(P, P->grp[g], 0, s));
         return HS_OK;
     };
     for (int blk = 0; blk < nblocks; blk++) {
@@ -2355,10 +2377,9 @@ hs_status pipe_fine(hs_plan* P, PipeSync& ps, int nblocks, hipStream_t s)
         HS_CHECK(begin_step(P, s));
         if (pred) {
             // the predictor's restriction of the spread values, without the FAS correction
-            const LaneSet& all = P->all;
-            HS_TRY(hsk::fas_restrict(P->ctl, all.fasc.d, all.fasc.nseg(), all.fasc.nblk, P->order[1], 1, s));
+            HS_TRY(fas_restrict(P, P->all, 0, s));
             for (int b = 0; b < P->B; b++)
-                HS_TRY(hsk::fill(P->lanes[b].tau, (long long)P->M[1] * P->lanes[b].N[1], 0.0, s));
+                HS_TRY(hsk::fill(P->lanes[b].tau[1], (long long)P->M[1] * P->lanes[b].N[1], 0.0, s));
         }
         HS_TRY(hipEventRecord(P->ev_go, s));
         ps.post(ps.go);
@@ -2372,7 +2393,7 @@ hs_status pipe_fine(hs_plan* P, PipeSync& ps, int nblocks, hipStream_t s)
                                         P->gh_dst[g].nblk, P->order[0], s));
                 int outcome;
                 HS_CHECK(sweep(P, gs, 0, false, true, s, &outcome));
-                HS_TRY(hsk::fas_restrict(P->ctl, gs.fasc.d, gs.fasc.nseg(), gs.fasc.nblk, P->order[1], 1, s));
+                HS_TRY(fas_restrict(P, gs, 0, s));
                 HS_TRY(hipEventRecord(P->ev_r[g], s));
                 ps.post(ps.r[g]);
             }
@@ -2414,6 +2435,7 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
     hipStream_t s = (hipStream_t)stream;
     if (P->G >= 2) return pfasst_pipelined(P, P->pb.nsteps / P->B, s);
     int Pn = P->B, Mf = P->M[0];
+    const int C = P->nlev - 1;   // the coarsest level
     int nblocks = P->pb.nsteps / Pn;
     const bool fixed = P->pb.sweeps > 0;
     LaneSet& all = P->all;
@@ -2458,19 +2480,25 @@ extern "C" hs_status hs_pfasst_run(hs_plan* P, void* stream)
             }
             int outcome;
             HS_CHECK(sweep(P, all, 0, false, true, s, &outcome, prep_done));
-            // (ii) restriction and FAS correction on every slice
-            HS_TRY(hsk::fas_restrict(P->ctl, all.fasc.d, all.fasc.nseg(), all.fasc.nblk, P->order[1], 1, s));
+            // (ii) restriction and FAS correction on every slice, level by level down to
+            // the coarsest, with a sweep of every slice on each intermediate level
+            for (int l = 0; l < C; l++) {
+                HS_TRY(fas_restrict(P, all, l, s));
+                if (l + 1 < C) HS_CHECK(sweep(P, all, l + 1, false, false, s, &outcome));
+            }
             // (iii) coarse pipeline: slice p starts from slice p-1's new coarse end value
             for (int p = 0; p < Pn; p++) {
                 if (p > 0)
                     HS_TRY(hsk::handoff(P->ctl, P->hc_dst[p].d, P->hc_src[p].d, 1, P->hc_dst[p].nblk,
-                                        P->order[1], s));
-                HS_CHECK(sweep(P, P->single[p], 1, false, false, s, &outcome));
+                                        P->order[C], s));
+                HS_CHECK(sweep(P, P->single[p], C, false, false, s, &outcome));
             }
-            // (iv) interpolation on every slice, node 0 included
-            HS_TRY(fas_interp(P, all, s));
-            HS_TRY(hsk::fi_march(P->ctl, all.mg64[0].fine.d, all.sdc[0].d, all.sdc[0].nseg(), all.mg64[0].fine.nblk,
-                                 P->order[0], 0, P->M[0], -1, 1, s));
+            // (iv) interpolation on every slice, node 0 included, level by level up to
+            // the finest, with a sweep of every slice on each intermediate level
+            for (int l = C - 1; l >= 0; l--) {
+                HS_TRY(interp_level(P, all, l, s));
+                if (l > 0) HS_CHECK(sweep(P, all, l, false, false, s, &outcome));
+            }
             P->sweep_k++;
         }
         HS_TRY(hsk::end_step(P->ctl, P->B, s));
@@ -2657,8 +2685,7 @@ extern "C" hs_status hs_stats_read(hs_plan* P, hs_lane_stats* out, void* stream)
         o.failed_solves = c.failed_solves;
         o.last_rho = c.mg_rho;
         o.last_sdc_res = c.sdc_res;
-        o.level_cycles[0] = c.level_cycles[0];
-        o.level_cycles[1] = c.level_cycles[1];
+        for (int l = 0; l < HS_MAXLEV; l++) o.level_cycles[l] = c.level_cycles[l];
     }
     return lanes_status(P);
 }

@@ -42,7 +42,7 @@ class MgDesc(C.Structure):
 class ProblemDesc(C.Structure):
     _fields_ = [("nu", C.c_double), ("t0", C.c_double), ("dt", C.c_double),
                 ("forcing_c", C.c_double), ("nsteps", C.c_int32), ("nlevels", C.c_int32),
-                ("lev", LevelDesc * 2), ("mg", MgDesc), ("sweeps", C.c_int32),
+                ("lev", LevelDesc * 3), ("mg", MgDesc), ("sweeps", C.c_int32),
                 ("sdc_tol", C.c_double), ("max_sweeps", C.c_int32), ("batch", C.c_int32),
                 ("nslices", C.c_int32), ("h_lane_n", C.POINTER(C.c_int32)),
                 ("pfasst_pred_sweeps", C.c_int32), ("lane_memory", C.c_int32),
@@ -55,7 +55,7 @@ class LaneStats(C.Structure):
                 ("total_solves", C.c_int32), ("total_cycles", C.c_int64),
                 ("max_cycles", C.c_int32), ("failed_solves", C.c_int32),
                 ("last_rho", C.c_double), ("last_sdc_res", C.c_double),
-                ("level_cycles", C.c_int64 * 2)]
+                ("level_cycles", C.c_int64 * 3)]
 
 
 class ServerDesc(C.Structure):
@@ -220,6 +220,7 @@ class Problem:
     forcing_c: float = 3.0
     nsteps: int = 1
     coarse: tuple | None = None          # (n, order, nnodes) of the coarse MLSDC level
+    coarse2: tuple | None = None         # (n, order, nnodes) of a third, coarsest level
     nu1: int = 2
     nu2: int = 1
     omega: float = 6.0 / 7.0
@@ -247,10 +248,12 @@ class Problem:
         d = ProblemDesc()
         d.nu, d.t0, d.dt, d.forcing_c = self.nu, self.t0, self.dt, self.forcing_c
         d.nsteps = self.nsteps
-        d.nlevels = 2 if self.coarse else 1
+        d.nlevels = (3 if self.coarse2 else 2) if self.coarse else 1
         d.lev[0] = LevelDesc(self.n, self.order, self.nnodes)
         if self.coarse:
             d.lev[1] = LevelDesc(*self.coarse)
+        if self.coarse and self.coarse2:
+            d.lev[2] = LevelDesc(*self.coarse2)
         d.mg = MgDesc(self.nu1, self.nu2, self.omega, self.n_coarsest, self.tol, self.max_cycles,
                       self.fixed_cycles, self.precision, self.inner_nu1, self.inner_nu2,
                       self.fused_sweeps, self.cycle_graphs)

@@ -244,3 +244,23 @@ def test_fas_interp_validated_and_sized():
     with pytest.raises(heatst.HeatstError) as e:
         base_problem(fas_interp=2, **args).workspace_bytes()
     assert e.value.status == heatst.HS_EINVAL
+
+
+def test_three_levels_validated_and_sized():
+    """A third level adds its node arrays (U, FI, P, rhs, Ut, tau), its
+    multigrid hierarchy and its tables; the pipelined order is two-level only;
+    level sizes and node counts must nest."""
+    args = dict(n=31, order=4, nnodes=5, coarse=(15, 2, 3), batch=2, sweeps=2)
+    b2 = base_problem(**args).workspace_bytes()
+    b3 = base_problem(coarse2=(7, 2, 2), **args).workspace_bytes()
+    nodes = 2 * (2 + 2 + 1 + 1 + 2 + 2) * 7 ** 3 * 8   # per lane: U, FI (M), P (M-1), rhs, tmp, Ut, tau (M)
+    assert b2 + nodes <= b3 <= b2 + nodes + (1 << 20)
+    for bad in (dict(coarse2=(5, 2, 2)), dict(coarse2=(7, 2, 4)), dict(coarse2=(7, 3, 2))):
+        with pytest.raises(heatst.HeatstError) as e:
+            base_problem(**{**args, **bad}).workspace_bytes()
+        assert e.value.status == heatst.HS_EINVAL
+    pf = dict(args, batch=4, nslices=4, nsteps=4, coarse2=(7, 2, 2))
+    assert base_problem(**pf).workspace_bytes() > 0
+    with pytest.raises(heatst.HeatstError) as e:
+        base_problem(pfasst_groups=2, **pf).workspace_bytes()
+    assert e.value.status == heatst.HS_EINVAL
