@@ -221,6 +221,71 @@ def eq10(args):
 
 
 # ----------------------------------------------------------------------------
+# three levels against two
+# ----------------------------------------------------------------------------
+
+def levels3(args):
+    """Two against three MLSDC levels on the 127^3 problem (fine 127^3, 4th
+    order, 5 nodes; 63^3, 2nd order, 3 nodes; third level 31^3, 2nd order,
+    with 2 or with 3 nodes), tricubic transfer, nu 0.1: serial MLSDC over
+    16 steps of dt 0.01 to the 1e-10 residual, 16 PFASST slices in one batch
+    with the coarse predictor to the same residual, and the 20-step MLSDC
+    run of dt 0.05 with 3 iterations per step."""
+    from . import heatst as hs
+    from . import inputs
+    nf, P, dt, tol = 127, 16, 0.01, 1e-10
+    u0 = _dev(inputs.sine_product(nf))
+    lv = {"levels_2": (2, dict(coarse=(63, 2, 3))),
+          "levels_3_m2": (3, dict(coarse=(63, 2, 3), coarse2=(31, 2, 2))),
+          "levels_3_m3": (3, dict(coarse=(63, 2, 3), coarse2=(31, 2, 3)))}
+    out = {}
+    for key, (L, kw) in lv.items():
+        _log(f"levels3: {key}")
+        base = dict(n=nf, order=4, nnodes=5, nu=0.1, tol=1e-12, max_cycles=60, fas_interp=3, **kw)
+        ml = hs.Plan(hs.Problem(dt=dt, nsteps=P, sweeps=0, sdc_tol=tol, max_sweeps=30, **base))
+        ml.set_state(u0)
+        ml.step()
+        ml.set_state(u0)
+        t_ml = _timed(ml.solve)
+        st, mstats = ml.stats()
+        hs.check(st, f"levels3 serial MLSDC, {L} levels")
+        u_ml = ml.get_state().cpu().numpy()
+        del ml
+        pf = hs.Plan(hs.Problem(dt=dt, nsteps=P, sweeps=0, sdc_tol=tol, max_sweeps=args.pfasst_max_iters,
+                                batch=P, nslices=P, pfasst_pred_sweeps=1, **base))
+        pf.set_state(u0)
+        pf.pfasst_run()
+        pf.set_state(u0)
+        t_pf = _timed(pf.pfasst_run)
+        st, pstats = pf.stats()
+        hs.check(st, f"levels3 PFASST, {L} levels", allow=(hs.HS_ENOCONV,))
+        u_pf = pf.get_state().cpu().numpy()
+        del pf
+        c2 = hs.Plan(hs.Problem(dt=0.05, nsteps=20, sweeps=3, **base))
+        c2.set_state(u0)
+        c2.step()
+        c2.set_state(u0)
+        t_c2 = _timed(c2.solve)
+        st, cstats = c2.stats()
+        hs.check(st, f"levels3 MLSDC 20 steps, {L} levels")
+        u_c2 = c2.get_state().cpu().numpy().reshape(nf, nf, nf)
+        del c2
+        ex = inputs.sine_product(nf) * np.cos(20 * 0.05)
+        out[key] = {
+            "serial_mlsdc": {"seconds": t_ml, "iterations_per_step": mstats[0]["total_sweeps"] / P,
+                             "level_cycles": mstats[0]["level_cycles"][:L]},
+            "pfasst16": {"seconds": t_pf, "K_P": pstats[0]["total_sweeps"], "converged": st == hs.HS_OK,
+                         "last_residual": max(x["last_sdc_res"] for x in pstats),
+                         "rel_diff_vs_serial_mlsdc": float(np.abs(u_pf - u_ml).max() / np.abs(u_ml).max()),
+                         "speedup_vs_serial_mlsdc": t_ml / t_pf},
+            "mlsdc_dt0.05_3it": {"ms_per_step": t_c2 / 20 * 1e3,
+                                 "error_vs_exact": float(np.abs(u_c2 - ex).max() / np.abs(ex).max())}}
+    return {"workload": "levels3", "P": P, "dt": dt, "sdc_tol": tol, "fas_transfer": "tricubic", **out,
+            "note": "PFASST slices run as one batch on one GPU; with three levels the serial pipeline runs on "
+                    "the 31^3 grids (levels_3_m2: 2 nodes, levels_3_m3: 3 nodes)"}
+
+
+# ----------------------------------------------------------------------------
 # node-parallel against sequential SDC sweeps
 # ----------------------------------------------------------------------------
 
