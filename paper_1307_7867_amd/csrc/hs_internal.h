@@ -305,9 +305,9 @@ hipError_t np_lanes(LaneCtl* ctl, int nlanes, int M, int mode, hipStream_t s);
 hipError_t np_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, hipStream_t s);
 
 // kernel-level calls of the public ABI on lane-major packed user arrays
-hipError_t lap_apply(const SdcSeg* segs, int nseg, int nblk, int order, double alpha, double beta,
+hipError_t lap_apply(const GridSeg* segs, int nseg, int nblk, int order, double alpha, double beta,
                      const double* u, double* y, const long long* offs, hipStream_t s);
-hipError_t heat_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order,
+hipError_t heat_rhs(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int nseg, int nblk, int order,
                     const double* u, const double* t, double* fi, double* fe,
                     const long long* offs, hipStream_t s);
 

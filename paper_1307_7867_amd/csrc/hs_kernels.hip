@@ -2807,28 +2807,35 @@ __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst,
 
 // y = alpha u + beta L u on user arrays (lane-major packing, offset pack_off)
 template <int ORDER>
-__global__ void __launch_bounds__(HS_BLOCK) k_lap_apply(const SdcSeg* __restrict__ segs, int nseg,
+__global__ void __launch_bounds__(HS_BLOCK) k_lap_apply(const GridSeg* __restrict__ segs, int nseg,
                                                         int nblk, double alpha, double beta,
                                                         const double* __restrict__ u,
                                                         double* __restrict__ y,
                                                         const long long* __restrict__ offs)
 {
-    int lb = xcd_remap(blockIdx.x, nblk);
-    int si = find_seg(segs, nseg, lb);
-    const SdcSeg sg = segs[si];
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
-    if (!q.in) return;
-    const double* ul = u + offs[si];
-    long long p = lin(q.i, q.j, q.k, n);
-    Ld3<double> ld{ul, n};
-    double c = ul[p];
-    y[offs[si] + p] = alpha * c + beta * (lap_scale<ORDER, double>(n) * lap_sum<ORDER, double>(ld, q.i, q.j, q.k, n, c));
+    // y = alpha u + beta L_h u on the caller's lane-major arrays, as a plane
+    // march over the z-chunks of the lanes' grid table (the same march as the
+    // sweeps)
+    const int lb = xcd_remap(blockIdx.x, nblk);
+    const int si = find_seg(segs, nseg, lb);
+    const GridSeg sg = segs[si];
+    const int n = sg.n;
+    const PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
+    struct Op {
+        HS_G double* y;
+        double al, be;
+        __device__ __forceinline__ void operator()(long long p, int, double c, double L) { y[p] = al * c + be * L; }
+    } op{(HS_G double*)y + offs[si], alpha, beta};
+    __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
+    lds_march<ORDER, double>((const HS_G double*)u + offs[si], n, q.i - (int)(threadIdx.x % HS_TX),
+                             q.j - (int)(threadIdx.x / HS_TX), q.z0, q.z1, pl, op);
 }
 
-// f_impl = nu L u, f_expl = f(x, t) (eq. (3)) on user arrays
+// f_impl = nu L u, f_expl = f(x, t) (eq. (3)) on user arrays; gsegs gives the
+// march's blocks, ssegs (same lanes, same order) the sine tables
 template <int ORDER>
-__global__ void __launch_bounds__(HS_BLOCK) k_heat_rhs(const SdcSeg* __restrict__ segs, int nseg,
+__global__ void __launch_bounds__(HS_BLOCK) k_heat_rhs(const GridSeg* __restrict__ gsegs,
+                                                       const SdcSeg* __restrict__ ssegs, int nseg,
                                                        int nblk, const LaneCtl* __restrict__ ctl,
                                                        const double* __restrict__ u,
                                                        const double* __restrict__ t,
@@ -2836,25 +2843,27 @@ __global__ void __launch_bounds__(HS_BLOCK) k_heat_rhs(const SdcSeg* __restrict_
                                                        double* __restrict__ fe,
                                                        const long long* __restrict__ offs)
 {
-    int lb = xcd_remap(blockIdx.x, nblk);
-    int si = find_seg(segs, nseg, lb);
-    const SdcSeg sg = segs[si];
-    int n = sg.n;
-    Pos q = grid_pos(lb - sg.blk_begin, n);
-    if (!q.in) return;
+    const int lb = xcd_remap(blockIdx.x, nblk);
+    const int si = find_seg(gsegs, nseg, lb);
+    const GridSeg sg = gsegs[si];
+    const double* sig = ssegs[si].sig;
+    const int n = sg.n;
+    const PosZ q = grid_pos_z(lb - sg.blk_begin, n, sg.zb);
     const LaneCtl& c = ctl[sg.lane];
-    long long p = lin(q.i, q.j, q.k, n);
+    const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;
+    const double g = -(sin(t[si]) - c.forcing_c * c.nu * pi2 * cos(t[si]));
     if (fi) {
-        const double* ul = u + offs[si];
-        Ld3<double> ld{ul, n};
-        fi[offs[si] + p] = c.nu * (lap_scale<ORDER, double>(n) * lap_sum<ORDER, double>(ld, q.i, q.j, q.k, n, ul[p]));
+        struct Op {
+            HS_G double* fi;
+            double nu;
+            __device__ __forceinline__ void operator()(long long p, int, double, double L) { fi[p] = nu * L; }
+        } op{(HS_G double*)fi + offs[si], c.nu};
+        __shared__ double pl[2][Halo<ORDER>::LH][Halo<ORDER>::LW];
+        lds_march<ORDER, double>((const HS_G double*)u + offs[si], n, q.i - (int)(threadIdx.x % HS_TX),
+                                 q.j - (int)(threadIdx.x / HS_TX), q.z0, q.z1, pl, op);
     }
-    if (fe) {
-        const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;
-        double tt = t[si];
-        double g = -(sin(tt) - c.forcing_c * c.nu * pi2 * cos(tt));
-        fe[offs[si] + p] = sval(sg.sig, q.i, q.j, q.k) * g;
-    }
+    if (fe && q.in)
+        for (int z = q.z0; z < q.z1; z++) fe[offs[si] + lin(q.i, q.j, z, n)] = sval(sig, q.i, q.j, z) * g;
 }
 
 }  // namespace
@@ -3273,7 +3282,7 @@ hipError_t sdc_reopen(LaneCtl* ctl, int nlanes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t lap_apply(const SdcSeg* segs, int nseg, int nblk, int order, double alpha, double beta,
+hipError_t lap_apply(const GridSeg* segs, int nseg, int nblk, int order, double alpha, double beta,
                      const double* u, double* y, const long long* offs, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
@@ -3282,12 +3291,12 @@ hipError_t lap_apply(const SdcSeg* segs, int nseg, int nblk, int order, double a
     return hipGetLastError();
 }
 
-hipError_t heat_rhs(LaneCtl* ctl, const SdcSeg* segs, int nseg, int nblk, int order,
+hipError_t heat_rhs(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int nseg, int nblk, int order,
                     const double* u, const double* t, double* fi, double* fe,
                     const long long* offs, hipStream_t s)
 {
     if (nblk <= 0) return hipSuccess;
-    HS_ORDER_DISPATCH(order, (k_heat_rhs<2>), (k_heat_rhs<4>), g1(nblk), BLK, 0, segs, nseg, nblk,
+    HS_ORDER_DISPATCH(order, (k_heat_rhs<2>), (k_heat_rhs<4>), g1(nblk), BLK, 0, gsegs, ssegs, nseg, nblk,
                       ctl, u, t, fi, fe, offs);
     return hipGetLastError();
 }

@@ -1853,7 +1853,7 @@ hs_status hs_lap_apply(hs_plan* P, int32_t level, double alpha, double beta, con
     HS_CHECK(check_bound(P));
     if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || !d_u || !d_y) return HS_EINVAL;
-    const Table<SdcSeg>& T = P->all.sdc[level];
+    const Table<GridSeg>& T = P->all.mg64[level].fine;   // the lanes' finest grids, z-chunked
     HS_TRY(hsk::lap_apply(T.d, T.nseg(), T.nblk, P->order[level], alpha, beta, d_u, d_y,
                           P->offs[level].d, (hipStream_t)stream));
     return HS_OK;
@@ -1870,9 +1870,9 @@ hs_status hs_heat_rhs(hs_plan* P, int32_t level, const double* d_u, const double
     if (h_t)
         for (int b = 0; b < P->B; b++) t[b] = h_t[b];
     HS_TRY(hipMemcpyAsync(P->d_times, t.data(), sizeof(double) * P->B, hipMemcpyHostToDevice, s));
-    const Table<SdcSeg>& T = P->all.sdc[level];
-    HS_TRY(hsk::heat_rhs(P->ctl, T.d, T.nseg(), T.nblk, P->order[level], d_u, P->d_times, d_fi, d_fe,
-                         P->offs[level].d, s));
+    const Table<GridSeg>& T = P->all.mg64[level].fine;   // same lanes, same order as all.sdc[level]
+    HS_TRY(hsk::heat_rhs(P->ctl, T.d, P->all.sdc[level].d, T.nseg(), T.nblk, P->order[level], d_u, P->d_times,
+                         d_fi, d_fe, P->offs[level].d, s));
     HS_TRY(hipStreamSynchronize(s));
     return HS_OK;
 }
