@@ -22,6 +22,7 @@ _SRC = os.path.join(_HERE, "heat_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_heat.so")
 
 OK, EINVAL, ENOCONV, ENONFINITE = 0, -1, -3, -4
+COMPACT = -4   # level order code of the compact 4th-order scheme (or_compact_apply)
 
 
 def build(force: bool = False) -> str:
@@ -72,6 +73,13 @@ def lib():
         L.or_laplacian.argtypes = [C.c_int, C.c_int, _D, _D]
         L.or_lap_apply.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _D, _D]
         L.or_heat_op.argtypes = [C.c_int, C.c_int, C.c_double, _D, _D]
+        L.or_compact_apply.argtypes = [C.c_int, C.c_double, C.c_double, _D, _D]
+        L.or_sdc_residual_compact.restype = C.c_double
+        L.or_sdc_residual_compact.argtypes = [C.POINTER(Level), C.c_double, C.c_double, C.c_double, C.c_double,
+                                              _D, _D]
+        L.or_spread_compact.argtypes = [C.POINTER(Level), C.c_double, _D, _D, _D]
+        L.or_sdc_sweep_compact.argtypes = [C.POINTER(Level), C.POINTER(MG), C.c_double, C.c_double, C.c_double,
+                                           C.c_double, _D, _D, C.POINTER(Stats)]
         L.or_residual.argtypes = [C.c_int, C.c_int, C.c_double, _D, _D, _D]
         L.or_jacobi.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _D, _D, _D]
         L.or_restrict_fw.argtypes = [C.c_int, _D, _D]
@@ -172,6 +180,33 @@ def jacobi(u, b, order, a, omega=6.0 / 7.0):
     u = _f(u); b = _f(b); out = np.empty_like(u)
     lib().or_jacobi(u.shape[0], order, a, omega, _p(u), _p(b), _p(out))
     return out
+
+
+def compact_apply(u, alpha, beta):
+    """alpha B_h u + beta A_h u with the compact pair (or_compact_apply)."""
+    u = _f(u)
+    n = u.shape[-1]
+    y = np.empty_like(u)
+    lib().or_compact_apply(n, alpha, beta, _p(u), _p(y))
+    return y
+
+
+def spread_compact(lv, nu, u0):
+    n, M = lv.n, lv.M
+    U = np.empty((M, n, n, n)); G = np.empty_like(U)
+    lib().or_spread_compact(C.byref(lv), nu, _p(_f(u0)), _p(U), _p(G))
+    return U, G
+
+
+def sdc_residual_compact(lv, nu, tn, dt, c, U, G):
+    return lib().or_sdc_residual_compact(C.byref(lv), nu, tn, dt, c, _p(_f(U)), _p(_f(G)))
+
+
+def sdc_sweep_compact(lv, mg, nu, tn, dt, c, U, G):
+    """In-place compact sweep on U, G (G = nu A_h U at every node)."""
+    st = Stats()
+    s = lib().or_sdc_sweep_compact(C.byref(lv), C.byref(mg), nu, tn, dt, c, _p(U), _p(G), C.byref(st))
+    return s, st
 
 
 def restrict_fw(rf):

@@ -39,6 +39,7 @@
 
 #define OR_MAXM 8
 #define OR_MAXLEV 3
+#define OR_ORDER_COMPACT (-4)   /* level order code of the compact 4th-order scheme */
 
 typedef struct {
     int32_t nu1, nu2;     /* pre / post smoothing sweeps */
@@ -51,7 +52,7 @@ typedef struct {
 
 typedef struct {
     int32_t n;      /* interior points per axis */
-    int32_t order;  /* 2 or 4 */
+    int32_t order;  /* 2 or 4, or OR_ORDER_COMPACT (single-level SDC only) */
     int32_t M;      /* collocation nodes including both ends */
 } or_level;
 
@@ -171,25 +172,70 @@ void or_lap_apply(int n, int order, double alpha, double beta, const double *u, 
     free(L);
 }
 
+/* u at (i, j, k), 0 outside the grid (the walls and beyond, eq. (2)) */
+static double val3(const double *u, int n, int i, int j, int k)
+{
+    if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return 0.0;
+    return u[((size_t)k * n + j) * n + i];
+}
+
+/*
+ * The compact fourth-order pair of the fine level (section 1 names a
+ * fourth-order compact stencil there, and sec. 1.2 a weighting matrix that
+ * the multigrid solver inverts for the FAS correction; the paper gives
+ * neither, so this is the reading: the 19-point Mehrstellen pair)
+ *   A_h u = (2 (sum of the 6 face neighbours) + (sum of the 12 edge
+ *            neighbours) - 24 u) / (6 h^2),
+ *   B_h u = u / 2 + (sum of the 6 face neighbours) / 12 = (I + h^2/12 D_h) u
+ * with the 7-point D_h, for which A_h u = B_h f is fourth-order accurate for
+ * Laplace(u) = f.  y = alpha B_h u + beta A_h u, zero Dirichlet walls.
+ * Sums: faces x, y, z (minus before plus); edges of the xy, xz, yz planes.
+ */
+void or_compact_apply(int n, double alpha, double beta, const double *u, double *y)
+{
+    double h = or_grid_h(n);
+    double ih2 = 1.0 / (h * h);
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                double c = val3(u, n, i, j, k);
+                double faces = ((val3(u, n, i - 1, j, k) + val3(u, n, i + 1, j, k)) +
+                                (val3(u, n, i, j - 1, k) + val3(u, n, i, j + 1, k))) +
+                               (val3(u, n, i, j, k - 1) + val3(u, n, i, j, k + 1));
+                double exy = (val3(u, n, i - 1, j - 1, k) + val3(u, n, i + 1, j - 1, k)) +
+                             (val3(u, n, i - 1, j + 1, k) + val3(u, n, i + 1, j + 1, k));
+                double exz = (val3(u, n, i - 1, j, k - 1) + val3(u, n, i + 1, j, k - 1)) +
+                             (val3(u, n, i - 1, j, k + 1) + val3(u, n, i + 1, j, k + 1));
+                double eyz = (val3(u, n, i, j - 1, k - 1) + val3(u, n, i, j + 1, k - 1)) +
+                             (val3(u, n, i, j - 1, k + 1) + val3(u, n, i, j + 1, k + 1));
+                double A = ((2.0 * faces + ((exy + exz) + eyz)) - 24.0 * c) * ih2 / 6.0;
+                double B = 0.5 * c + faces / 12.0;
+                y[((size_t)k * n + j) * n + i] = alpha * B + beta * A;
+            }
+}
+
 /*
  * The implicit-Euler substep operator A_a = I - a L_h with a = nu * dt_m
- * (eq. (7): the implicit part of the IMEX sweep moved to the left).
+ * (eq. (7): the implicit part of the IMEX sweep moved to the left); for the
+ * compact scheme B_h - a A_h (the weighting matrix multiplies eq. (7)).
  */
 void or_heat_op(int n, int order, double a, const double *u, double *y)
 {
-    or_lap_apply(n, order, 1.0, -a, u, y);
+    if (order == OR_ORDER_COMPACT) or_compact_apply(n, 1.0, -a, u, y);
+    else or_lap_apply(n, order, 1.0, -a, u, y);
 }
 
 /*
  * Diagonal of A_a, from the stencil weights: the centre weight of L_h per
  * axis is -2/h^2 (order 2) and -30/(12 h^2) (order 4), except that with the
  * odd reflection a wall-adjacent point also picks up +1/(12 h^2) from its
- * reflected far neighbour.
+ * reflected far neighbour.  Compact scheme: 1/2 - a (-24/(6 h^2)).
  */
 static double diag_op(int n, int order, double a, int i, int j, int k)
 {
     double h = or_grid_h(n);
     double ih2 = 1.0 / (h * h);
+    if (order == OR_ORDER_COMPACT) return 0.5 + a * 24.0 * ih2 / 6.0;   /* B_h: 1/2, A_h: -24/(6 h^2) */
     int c[3] = {i, j, k};
     double centre = 0.0;
     for (int ax = 0; ax < 3; ax++) {
@@ -448,7 +494,7 @@ static double maxabs(const double *v, size_t N)
 int or_mg_solve(int n, int order, double a, const or_mg *p, double *u, const double *b,
                 int *cycles_out, double *rho_out)
 {
-    if (!valid_n(n) || (order != 2 && order != 4)) return OR_EINVAL;
+    if (!valid_n(n) || (order != 2 && order != 4 && order != OR_ORDER_COMPACT)) return OR_EINVAL;
     size_t N = cube(n);
     double *r = alloc0(N);
     double bn = maxabs(b, N);
@@ -807,6 +853,153 @@ static int sdc_step(const or_problem *pb, double tn, double *u, or_stats *st)
 }
 
 /* ------------------------------------------------------------------ */
+/* SDC with the compact scheme (single level)                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * With the compact pair the semi-discrete heat equation is
+ *   B_h u' = nu A_h u + B_h f,
+ * and the collocation problem (eq. (6)) multiplied by B_h reads
+ *   B U_m = B U_0 + dt sum_j q_{m,j} Ft_j,   Ft_j = nu A U_j + B f(t_j).
+ * The IMEX sweep (eq. (7)) in this form needs no inverse of B:
+ *   (B - dt_m nu A) U^{k+1}_{m+1} = B U^{k+1}_m - dt_m nu A U^k_{m+1} + dt S^k_m,
+ *   dt S^k_m = dt sum_j (q_{m+1,j} - q_{m,j}) Ft(U^k_j, t_j),
+ * each substep solved by or_mg_solve with the compact operator (multigrid on
+ * B - a A, rediscretised on the coarser grids) from the guess U^k_{m+1}.
+ * G holds nu A U at every node (Ft without the forcing).  The residual that
+ * stops the sweeps is the one of this form, max over m = 1..M-1 and the
+ * grid of |B U_0 + dt sum_j q_{m,j} Ft_j - B U_m| (a reading: the paper does
+ * not say which residual it thresholds; without B^{-1} it is the one the
+ * sweeps can evaluate).
+ */
+void or_spread_compact(const or_level *L, double nu, const double *u0, double *U, double *G)
+{
+    size_t N = cube(L->n);
+    for (int m = 0; m < L->M; m++) {
+        memcpy(U + (size_t)m * N, u0, N * sizeof(double));
+        or_compact_apply(L->n, 0.0, nu, u0, G + (size_t)m * N);
+    }
+}
+
+/* B f(t_j) at every node, the forcing's part of Ft */
+static double **compact_forcing(const or_level *L, double nu, double tn, double dt, double c)
+{
+    int M = L->M;
+    size_t N = cube(L->n);
+    double nodes[OR_MAXM];
+    or_lobatto_nodes(M, nodes);
+    double **BF = (double **)malloc(M * sizeof(double *));
+    double *f = alloc0(N);
+    for (int j = 0; j < M; j++) {
+        BF[j] = alloc0(N);
+        or_forcing(L->n, nu, c, tn + dt * nodes[j], f);
+        or_compact_apply(L->n, 1.0, 0.0, f, BF[j]);
+    }
+    free(f);
+    return BF;
+}
+
+static void free_rows(double **r, int M)
+{
+    for (int j = 0; j < M; j++) free(r[j]);
+    free(r);
+}
+
+double or_sdc_residual_compact(const or_level *L, double nu, double tn, double dt, double c, const double *U,
+                               const double *G)
+{
+    int M = L->M;
+    size_t N = cube(L->n);
+    double Q[OR_MAXM * OR_MAXM];
+    or_collocation_matrix(M, Q);
+    double **BF = compact_forcing(L, nu, tn, dt, c);
+    double *BU0 = alloc0(N), *BUm = alloc0(N);
+    or_compact_apply(L->n, 1.0, 0.0, U, BU0);
+    double R = 0.0;
+    for (int m = 1; m < M; m++) {
+        or_compact_apply(L->n, 1.0, 0.0, U + (size_t)m * N, BUm);
+        for (size_t p = 0; p < N; p++) {
+            double integral = 0.0;
+            for (int j = 0; j < M; j++) integral += Q[m * M + j] * (G[(size_t)j * N + p] + BF[j][p]);
+            double x = fabs((BU0[p] + dt * integral) - BUm[p]);
+            if (x > R || x != x) R = x;
+        }
+    }
+    free(BU0); free(BUm);
+    free_rows(BF, M);
+    return R;
+}
+
+int or_sdc_sweep_compact(const or_level *L, const or_mg *mg, double nu, double tn, double dt, double c,
+                         double *U, double *G, or_stats *st)
+{
+    int M = L->M, n = L->n;
+    size_t N = cube(n);
+    double Q[OR_MAXM * OR_MAXM], nodes[OR_MAXM];
+    or_collocation_matrix(M, Q);
+    or_lobatto_nodes(M, nodes);
+    double **BF = compact_forcing(L, nu, tn, dt, c);
+    /* dt S^k_m from iterate k, before any node is updated */
+    double *SF = alloc0((size_t)(M - 1) * N);
+    for (int m = 0; m + 1 < M; m++)
+        for (size_t p = 0; p < N; p++) {
+            double s = 0.0;
+            for (int j = 0; j < M; j++)
+                s += (Q[(m + 1) * M + j] - Q[m * M + j]) * (G[(size_t)j * N + p] + BF[j][p]);
+            SF[(size_t)m * N + p] = dt * s;
+        }
+    double *rhs = alloc0(N), *BUm = alloc0(N);
+    int status = OR_OK;
+    for (int m = 0; m + 1 < M; m++) {
+        double dtm = dt * (nodes[m + 1] - nodes[m]);
+        or_compact_apply(n, 1.0, 0.0, U + (size_t)m * N, BUm);
+        for (size_t p = 0; p < N; p++)
+            rhs[p] = (BUm[p] - dtm * G[(size_t)(m + 1) * N + p]) + SF[(size_t)m * N + p];
+        int cycles = 0;
+        double rho = 0.0;
+        int s = or_mg_solve(n, OR_ORDER_COMPACT, nu * dtm, mg, U + (size_t)(m + 1) * N, rhs, &cycles, &rho);
+        if (st) {
+            st->total_solves++;
+            st->total_cycles += cycles;
+            if (cycles > st->max_cycles_seen) st->max_cycles_seen = cycles;
+        }
+        if (s != OR_OK && status == OR_OK) status = s;
+        or_compact_apply(n, 0.0, nu, U + (size_t)(m + 1) * N, G + (size_t)(m + 1) * N);
+    }
+    if (st) st->total_sweeps++;
+    free(rhs); free(BUm); free(SF);
+    free_rows(BF, M);
+    return status;
+}
+
+static int sdc_step_compact(const or_problem *pb, double tn, double *u, or_stats *st)
+{
+    const or_level *L = &pb->lev[0];
+    size_t N = cube(L->n);
+    double *U = alloc0((size_t)L->M * N), *G = alloc0((size_t)L->M * N);
+    or_spread_compact(L, pb->nu, u, U, G);
+    int status = OR_OK, k = 0;
+    for (k = 0;; k++) {
+        if (pb->sweeps > 0) {
+            if (k >= pb->sweeps) break;
+        } else {
+            double R = or_sdc_residual_compact(L, pb->nu, tn, pb->dt, pb->forcing_c, U, G);
+            if (st) st->last_residual = R;
+            if (R != R) { status = OR_ENONFINITE; break; }
+            if (R <= pb->sdc_tol) break;
+            if (k >= pb->max_sweeps) { status = OR_ENOCONV; break; }
+        }
+        int s = or_sdc_sweep_compact(L, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, U, G, st);
+        if (s != OR_OK && status == OR_OK) status = s;
+    }
+    if (pb->sweeps > 0 && st) st->last_residual = or_sdc_residual_compact(L, pb->nu, tn, pb->dt, pb->forcing_c, U, G);
+    if (st) st->sweeps = k;
+    memcpy(u, U + (size_t)(L->M - 1) * N, N * sizeof(double));
+    free(U); free(G);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
 /* MLSDC with FAS (section 1.1; space-time coarsening in the intro)    */
 /* ------------------------------------------------------------------ */
 
@@ -1046,7 +1239,8 @@ static int check_problem(const or_problem *pb)
     if (pb->nlevels < 1 || pb->nlevels > OR_MAXLEV) return OR_EINVAL;
     for (int l = 0; l < pb->nlevels; l++) {
         const or_level *L = &pb->lev[l];
-        if (!valid_n(L->n) || (L->order != 2 && L->order != 4)) return OR_EINVAL;
+        if (!valid_n(L->n) || (L->order != 2 && L->order != 4 && L->order != OR_ORDER_COMPACT)) return OR_EINVAL;
+        if (L->order == OR_ORDER_COMPACT && (pb->nlevels != 1 || pb->node_parallel)) return OR_EINVAL;
         if (L->M < 2 || L->M > OR_MAXM) return OR_EINVAL;
     }
     for (int l = 1; l < pb->nlevels; l++) {
@@ -1071,7 +1265,8 @@ int or_run(const or_problem *pb, double *u, or_stats *st)
     int status = OR_OK;
     for (int step = 0; step < pb->nsteps; step++) {
         double tn = pb->t0 + step * pb->dt;
-        s = pb->nlevels == 1 ? sdc_step(pb, tn, u, st) : mlsdc_step(pb, tn, u, st);
+        s = pb->nlevels > 1 ? mlsdc_step(pb, tn, u, st)
+            : pb->lev[0].order == OR_ORDER_COMPACT ? sdc_step_compact(pb, tn, u, st) : sdc_step(pb, tn, u, st);
         if (s != OR_OK && status == OR_OK) status = s;
     }
     if (st) st->status = status;

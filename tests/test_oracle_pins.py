@@ -923,3 +923,156 @@ def test_three_levels_validated():
     assert oracle.run(bad, u0)[1] == oracle.EINVAL
     bad = oracle.problem([(15, 4, 5), (7, 2, 3), (3, 2, 4)], sweeps=1)      # M1 - 1 not a multiple of M2 - 1
     assert oracle.run(bad, u0)[1] == oracle.EINVAL
+
+
+# ----------------------------------------------------------------------------
+# Compact fourth-order scheme (sec. 1: the fine level's compact stencil and its
+# weighting matrix; reading: the 19-point Mehrstellen pair A_h, B_h)
+# ----------------------------------------------------------------------------
+
+def _sine(n, k):
+    x = np.arange(1, n + 1) / (n + 1)
+    s = [np.sin(kk * np.pi * x) for kk in k]
+    return s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
+
+
+def _compact_eigs(n, k):
+    h = 1.0 / (n + 1)
+    c = [math.cos(kk * math.pi * h) for kk in k]
+    lam_a = (4 * sum(c) + 4 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2]) - 24) / (6 * h * h)
+    lam_b = 0.5 + sum(c) / 6
+    return lam_a, lam_b
+
+
+@pytest.mark.parametrize("n", [7, 15])
+def test_compact_pair_eigenvalues_on_sine_modes(n):
+    """Every discrete sine mode is an eigenvector of both matrices, with the
+    closed-form eigenvalues of the 19-point A_h and the 7-point B_h."""
+    rng = np.random.default_rng(n)
+    for _ in range(6):
+        k = tuple(int(v) for v in rng.integers(1, n + 1, size=3))
+        phi = _sine(n, k)
+        la, lb = _compact_eigs(n, k)
+        assert np.abs(oracle.compact_apply(phi, 0.0, 1.0) - la * phi).max() <= 1e-12 * abs(la)
+        assert np.abs(oracle.compact_apply(phi, 1.0, 0.0) - lb * phi).max() <= 1e-14
+
+
+@pytest.mark.parametrize("n", [15, 127])
+def test_compact_weighting_matrix_is_ill_conditioned_in_3d(n):
+    """B_h's smallest eigenvalue is (1 - cos(pi h))/2, about pi^2 h^2 / 4 (on the
+    checkerboard mode (n, n, n)); its largest (1 + cos(pi h))/2."""
+    h = 1.0 / (n + 1)
+    lo, hi = _compact_eigs(n, (n, n, n))[1], _compact_eigs(n, (1, 1, 1))[1]
+    assert lo == pytest.approx((1 - math.cos(math.pi * h)) / 2, rel=1e-9)
+    assert lo == pytest.approx(math.pi ** 2 * h * h / 4, rel=h * h)   # 1 - cos x = x^2/2 - x^4/24 + ...
+    assert hi == pytest.approx((1 + math.cos(math.pi * h)) / 2, rel=1e-12)
+    if n == 15:
+        phi = _sine(n, (n, n, n))
+        assert np.abs(oracle.compact_apply(phi, 1.0, 0.0) - lo * phi).max() <= 1e-15
+
+
+def _poly(n, coeffs):
+    x = np.arange(1, n + 1) / (n + 1)
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    p = np.zeros((n, n, n))
+    lap = np.zeros((n, n, n))
+    for (a, b, c), w in coeffs.items():
+        p = p + w * X ** a * Y ** b * Z ** c
+        if a >= 2: lap = lap + w * a * (a - 1) * X ** (a - 2) * Y ** b * Z ** c
+        if b >= 2: lap = lap + w * b * (b - 1) * X ** a * Y ** (b - 2) * Z ** c
+        if c >= 2: lap = lap + w * c * (c - 1) * X ** a * Y ** b * Z ** (c - 2)
+    return p, lap
+
+
+def test_compact_pair_is_exact_on_quintics():
+    """A_h p = B_h Laplace(p) exactly for every polynomial of degree <= 5 (the
+    Mehrstellen consistency that makes the pair fourth-order), checked where
+    neither stencil reaches a wall; a degree-6 term breaks it."""
+    n = 15
+    rng = np.random.default_rng(3)
+    coeffs = {(a, b, c): float(rng.standard_normal()) for a in range(6) for b in range(6) for c in range(6)
+              if a + b + c <= 5}
+    p, lap = _poly(n, coeffs)
+    inner = (slice(1, n - 1),) * 3
+    lhs = oracle.compact_apply(p, 0.0, 1.0)[inner]
+    rhs = oracle.compact_apply(lap, 1.0, 0.0)[inner]
+    assert np.abs(lhs - rhs).max() <= 1e-9 * np.abs(rhs).max()
+    p6, lap6 = _poly(n, {(6, 0, 0): 1.0, (2, 2, 2): 1.0})
+    d6 = oracle.compact_apply(p6, 0.0, 1.0)[inner] - oracle.compact_apply(lap6, 1.0, 0.0)[inner]
+    assert np.abs(d6).max() > 1e-6
+
+
+@pytest.mark.parametrize("n", [3, 7])
+def test_compact_multigrid_matches_dense_solve(n):
+    a = 0.004
+    b = inputs.random_smooth(n, 2)
+    x = oracle.dense_solve(b, oracle.COMPACT, a)
+    u, st, cyc, _ = oracle.mg_solve(b, oracle.COMPACT, a, mg=oracle.mg_params(tol=1e-14, max_cycles=200))
+    assert st == oracle.OK and cyc >= 1
+    assert np.abs(u - x).max() <= 1e-12 * np.abs(x).max()
+
+
+def _compact_problem(n, M=5, **kw):
+    return oracle.problem([(n, oracle.COMPACT, M)], mg=TIGHT, **kw)
+
+
+def _compact_collocation(n, M, nu, dt, nsteps, u0_modes, c=3.0):
+    """Per-mode collocation solution of u' = nu (lam_A / lam_B) u + f, the compact
+    semi-discrete system B u' = nu A u + B f on sine modes."""
+    Q = oracle.collocation_matrix(M)
+    tau = oracle.lobatto_nodes(M)
+    amp = dict(u0_modes)
+    amp.setdefault((1, 1, 1), 0.0)
+    out = np.zeros((n, n, n))
+    for k, a in amp.items():
+        la, lb = _compact_eigs(n, k)
+        mu = nu * la / lb
+        A = np.eye(M) - dt * mu * Q
+        for s in range(nsteps):
+            t = s * dt + dt * tau
+            g = -(np.sin(t) - c * nu * math.pi ** 2 * np.cos(t)) if k == (1, 1, 1) else np.zeros(M)
+            a = np.linalg.solve(A, a * np.ones(M) + dt * Q @ g)[-1]
+        out += a * _sine(n, k)
+    return out
+
+
+@pytest.mark.parametrize("M", [3, 5])
+def test_compact_sdc_converges_to_compact_collocation(M):
+    n, nu, dt, steps = 15, 0.1, 0.05, 2
+    modes = {(1, 1, 1): 1.0, (2, 1, 3): 0.5, (5, 4, 2): -0.25}
+    u0 = sum(a * _sine(n, k) for k, a in modes.items())
+    u, st, _ = oracle.run(_compact_problem(n, M, nu=nu, dt=dt, nsteps=steps, sweeps=40), u0)
+    assert st == oracle.OK
+    ref = _compact_collocation(n, M, nu, dt, steps, modes)
+    assert np.abs(u - ref).max() <= 1e-11
+
+
+def test_compact_scheme_is_fourth_order_in_space():
+    """Converged compact SDC against u(T) = s(x) cos T (eq. (4), c = 3): the
+    error falls 16-fold when h halves."""
+    errs = []
+    for n in (7, 15):
+        T, steps = 0.2, 2
+        u, st, _ = oracle.run(_compact_problem(n, 5, nu=0.1, dt=T / steps, nsteps=steps, sweeps=30), _sine(n, (1, 1, 1)))
+        assert st == oracle.OK
+        errs.append(np.abs(u - _sine(n, (1, 1, 1)) * math.cos(T)).max())
+    assert 13.0 < errs[0] / errs[1] < 19.0
+
+
+def test_compact_sdc_tolerance_mode_and_residual():
+    n = 15
+    pb = _compact_problem(n, 5, nu=0.1, dt=0.05, nsteps=1, sweeps=0)
+    pb.sdc_tol, pb.max_sweeps = 1e-9, 40
+    u0 = inputs.random_smooth(n, 4)
+    u, st, stats = oracle.run(pb, u0)
+    assert st == oracle.OK and 1 <= stats.sweeps < 40 and stats.last_residual <= 1e-9
+    # the residual of the spread start is the full one-step change: far above the tolerance
+    lv = pb.lev[0]
+    U, G = oracle.spread_compact(lv, 0.1, u0)
+    assert oracle.sdc_residual_compact(lv, 0.1, 0.0, 0.05, 3.0, U, G) > 1e-4
+
+
+def test_compact_is_single_level_only():
+    u0 = inputs.random_smooth(15, 1)
+    bad = oracle.problem([(15, oracle.COMPACT, 5), (7, 2, 3)], sweeps=1)
+    assert oracle.run(bad, u0)[1] == oracle.EINVAL
