@@ -216,6 +216,22 @@ hs_status hs_lap_apply(hs_plan* plan, int32_t level, double alpha, double beta,
 hs_status hs_heat_rhs(hs_plan* plan, int32_t level, const double* d_u, const double* h_t,
                       double* d_fi, double* d_fe, void* stream);
 
+/* The compact fourth-order pair of the fine level (section 1 names a
+ * fourth-order compact stencil there, section 1.2 a weighting matrix that
+ * the multigrid solver inverts for the FAS correction; neither is given, and
+ * the reading is the 19-point Mehrstellen pair):
+ *   d_y = alpha B_h d_u + beta A_h d_u,
+ *   A_h u = (2 (sum of the 6 face neighbours) + (sum of the 12 edge
+ *            neighbours) - 24 u) / (6 h^2),
+ *   B_h u = u / 2 + (sum of the 6 face neighbours) / 12,
+ * zero beyond the walls (eq. (2)), on `batch` grids of n^3 points packed
+ * lane-major ([grid][z][y][x], caller-owned device memory; d_u and d_y must
+ * not overlap).  alpha = 1, beta = -a gives the implicit operator B_h - a A_h.
+ * Stateless (no plan).  HS_EINVAL unless n = 2^k - 1 <= 511, batch >= 1 and
+ * both pointers are non-null.  Asynchronous on `stream`. */
+hs_status hs_compact_apply(int32_t n, int32_t batch, double alpha, double beta, const double* d_u,
+                           double* d_y, void* stream);
+
 /* Multigrid solve (I - a_l L_h) u = b per lane l of SDC level `level` as
  * configured in the plan's hs_mg_desc, from the initial guess in d_u
  * (overwritten with the solution).  h_a: host array of per-lane a.

@@ -310,5 +310,7 @@ hipError_t lap_apply(const GridSeg* segs, int nseg, int nblk, int order, double 
 hipError_t heat_rhs(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int nseg, int nblk, int order,
                     const double* u, const double* t, double* fi, double* fe,
                     const long long* offs, hipStream_t s);
+// y = alpha B_h u + beta A_h u (compact pair) on `batch` packed n^3 grids
+hipError_t compact_apply(int n, int batch, double alpha, double beta, const double* u, double* y, hipStream_t s);
 
 }  // namespace hsk

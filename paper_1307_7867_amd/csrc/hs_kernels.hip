@@ -2866,6 +2866,102 @@ __global__ void __launch_bounds__(HS_BLOCK) k_heat_rhs(const GridSeg* __restrict
         for (int z = q.z0; z < q.z1; z++) fe[offs[si] + lin(q.i, q.j, z, n)] = sval(sig, q.i, q.j, z) * g;
 }
 
+// ---------------------------------------------------------------------------
+// Compact fourth-order pair (the fine level's compact stencil of section 1
+// and its weighting matrix, section 1.2; the Mehrstellen reading):
+//   A_h u = (2 (6 face neighbours) + (12 edge neighbours) - 24 u) / (6 h^2),
+//   B_h u = u / 2 + (6 face neighbours) / 12,
+// zero beyond the walls.  The 19-point stencil reaches the in-plane
+// neighbours of planes z - 1 and z + 1, so the march keeps three planes of
+// the 64 x 8 tile with a one-point halo (corners included) in a ring of four
+// LDS planes and loads plane z + 2 into the fourth while plane z is formed:
+// one barrier per plane.
+// ---------------------------------------------------------------------------
+struct CmpTile {
+    static constexpr int LW = HS_TX + 2, LH = HS_TY + 2;
+    static constexpr int NH = LW * LH - HS_TX * HS_TY;   // halo cells per plane (148)
+};
+
+// op(p, c, faces, edges) at every grid point of planes z0..z1-1 of the
+// column tile at (i0, j0); all threads of the block must call it
+template <class Op>
+__device__ __forceinline__ void cmp_march(const HS_G double* __restrict__ u, int n, int i0, int j0, int z0,
+                                          int z1, double (*ring)[CmpTile::LH][CmpTile::LW], Op& op)
+{
+    using C = CmpTile;
+    const int t = (int)threadIdx.x;
+    const int lx = t % HS_TX, ly = t / HS_TX;
+    const int i = i0 + lx, j = j0 + ly;
+    const bool in = i < n && j < n;
+    // this thread's halo cell, if any: row 0, row LH-1, then the side columns
+    int hr = -1, hc = 0;
+    if (t < C::NH) {
+        if (t < C::LW) { hr = 0; hc = t; }
+        else if (t < 2 * C::LW) { hr = C::LH - 1; hc = t - C::LW; }
+        else { const int q = t - 2 * C::LW; hr = 1 + q / 2; hc = (q & 1) ? C::LW - 1 : 0; }
+    }
+    const int hi = i0 + hc - 1, hj = j0 + hr - 1;
+    const bool hin = hr >= 0 && hi >= 0 && hi < n && hj >= 0 && hj < n;
+    const long long nn = (long long)n * n;
+    const long long pij = in ? (long long)j * n + i : 0, hoff = hin ? (long long)hj * n + hi : 0;
+    auto ld = [&](bool ok, long long off, int z) -> double {
+        return (ok && z >= 0 && z < n) ? u[(long long)z * nn + off] : 0.0;
+    };
+    auto slot = [](int z) { return (z + 4) & 3; };
+    // planes z0-1, z0, z0+1
+    for (int d = -1; d <= 1; d++) {
+        const int z = z0 + d;
+        const double cv = ld(in, pij, z), hv = ld(hin, hoff, z);
+        ring[slot(z)][ly + 1][lx + 1] = cv;
+        if (hr >= 0) ring[slot(z)][hr][hc] = hv;
+    }
+    __syncthreads();
+    const double ih2 = (double)(n + 1) * (double)(n + 1);
+    for (int z = z0; z < z1; z++) {
+        const bool more = z + 1 < z1;
+        const double cn = more ? ld(in, pij, z + 2) : 0.0, hn = more ? ld(hin, hoff, z + 2) : 0.0;
+        if (in) {
+            const double (*m)[C::LW] = ring[slot(z - 1)];
+            const double (*o)[C::LW] = ring[slot(z)];
+            const double (*q)[C::LW] = ring[slot(z + 1)];
+            const int x = lx + 1, y = ly + 1;
+            const double c = o[y][x];
+            const double faces = ((o[y][x - 1] + o[y][x + 1]) + (o[y - 1][x] + o[y + 1][x])) + (m[y][x] + q[y][x]);
+            const double exy = (o[y - 1][x - 1] + o[y - 1][x + 1]) + (o[y + 1][x - 1] + o[y + 1][x + 1]);
+            const double exz = (m[y][x - 1] + m[y][x + 1]) + (q[y][x - 1] + q[y][x + 1]);
+            const double eyz = (m[y - 1][x] + m[y + 1][x]) + (q[y - 1][x] + q[y + 1][x]);
+            const double A = ((2.0 * faces + ((exy + exz) + eyz)) - 24.0 * c) * ih2 / 6.0;
+            const double B = 0.5 * c + faces / 12.0;
+            op((long long)z * nn + pij, c, A, B);
+        }
+        if (more) {
+            ring[slot(z + 2)][ly + 1][lx + 1] = cn;
+            if (hr >= 0) ring[slot(z + 2)][hr][hc] = hn;
+        }
+        __syncthreads();
+    }
+}
+
+// y = alpha B_h u + beta A_h u on `batch` packed n^3 grids; block b covers
+// column tile b % tiles of z chunk (b / tiles) % nz of grid b / (tiles nz)
+__global__ void __launch_bounds__(HS_BLOCK) k_compact_apply(int n, int zb, int nz, double alpha, double beta,
+                                                            const double* __restrict__ u, double* __restrict__ y)
+{
+    const int tx = tiles_x(n), tiles = tx * tiles_y(n);
+    const int b = (int)blockIdx.x;
+    const int tile = b % tiles, zc = (b / tiles) % nz, g = b / (tiles * nz);
+    const long long N = (long long)n * n * n;
+    const int i0 = (tile % tx) * HS_TX, j0 = (tile / tx) * HS_TY;
+    const int z0 = zc * zb, z1 = min(z0 + zb, n);
+    struct Op {
+        HS_G double* y;
+        double al, be;
+        __device__ __forceinline__ void operator()(long long p, double, double A, double B) { y[p] = al * B + be * A; }
+    } op{(HS_G double*)y + g * N, alpha, beta};
+    __shared__ double ring[4][CmpTile::LH][CmpTile::LW];
+    cmp_march((const HS_G double*)u + g * N, n, i0, j0, z0, z1, ring, op);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -3298,6 +3394,18 @@ hipError_t heat_rhs(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int
     if (nblk <= 0) return hipSuccess;
     HS_ORDER_DISPATCH(order, (k_heat_rhs<2>), (k_heat_rhs<4>), g1(nblk), BLK, 0, gsegs, ssegs, nseg, nblk,
                       ctl, u, t, fi, fe, offs);
+    return hipGetLastError();
+}
+
+hipError_t compact_apply(int n, int batch, double alpha, double beta, const double* u, double* y, hipStream_t s)
+{
+    if (batch <= 0) return hipSuccess;
+    const int tiles = tiles_x(n) * tiles_y(n);
+    int zb = 32;   // z chunks: enough blocks for the chip, long enough marches
+    while (zb > 2 && (long long)batch * tiles * ((n + zb - 1) / zb) < 1024) zb /= 2;
+    const int nz = (n + zb - 1) / zb;
+    hipLaunchKernelGGL(k_compact_apply, dim3((unsigned)(batch * tiles * nz)), BLK, 0, s, n, zb, nz, alpha, beta, u,
+                       y);
     return hipGetLastError();
 }
 

@@ -1859,6 +1859,15 @@ hs_status hs_lap_apply(hs_plan* P, int32_t level, double alpha, double beta, con
     return HS_OK;
 }
 
+hs_status hs_compact_apply(int32_t n, int32_t batch, double alpha, double beta, const double* d_u, double* d_y,
+                           void* stream)
+{
+    if (!valid_n(n) || batch < 1 || batch > 65536 || !d_u || !d_y) return HS_EINVAL;
+    if ((long long)batch * cube(n) > (1LL << 34)) return HS_EINVAL;
+    HS_TRY(hsk::compact_apply(n, batch, alpha, beta, d_u, d_y, (hipStream_t)stream));
+    return HS_OK;
+}
+
 hs_status hs_heat_rhs(hs_plan* P, int32_t level, const double* d_u, const double* h_t, double* d_fi,
                       double* d_fe, void* stream)
 {

@@ -100,6 +100,7 @@ def lib():
         "hs_mg_vcycle": [_V, C.c_int32, _V, _V, _V, _V],
         "hs_smooth": [_V, C.c_int32, _V, _V, _V, _V, C.c_int32, _V],
         "hs_mg_solve_static": [C.c_int32, C.c_int32, C.c_double, _V, _V, _V, _V],
+        "hs_compact_apply": [C.c_int32, C.c_int32, C.c_double, C.c_double, _V, _V, _V],
         "hs_plan_timer": [_V, C.c_int32, C.c_int32],
         "hs_plan_timer_read": [_V, _P(C.c_int32), _P(C.c_double)],
         "hs_tune_set": [C.c_int32] * 6,
@@ -206,6 +207,12 @@ def mg_solve_static(u, b, a, n, order, nu1=2, nu2=1, omega=6.0 / 7.0, n_coarsest
     d = MgDesc(nu1, nu2, omega, n_coarsest, tol, max_cycles, fixed_cycles, precision, inner[0], inner[1], 1, 0)
     s = lib().hs_mg_solve_static(n, order, a, C.byref(d), _ptr(u), _ptr(b), _stream(stream))
     return check(s, "hs_mg_solve_static", allow=allow)
+
+
+def compact_apply(u, y, n, batch, alpha, beta, stream=None):
+    """hs_compact_apply: y = alpha B_h u + beta A_h u (the compact pair) on
+    `batch` packed n^3 grids of the device tensors u and y."""
+    check(lib().hs_compact_apply(n, batch, alpha, beta, _ptr(u), _ptr(y), _stream(stream)), "hs_compact_apply")
 
 
 @dataclass

@@ -437,7 +437,8 @@ def micro511(args):
     """Finest-grid kernels in the solver's own launches: fixed-cycle V(2,1)
     solves (FP64) and refinement iterations with FP32 V(2,2) cycles (mixed),
     4th order, at 511^3 and on a batch of two 255^3 grids; the Jacobi sweep
-    and the operator application alone through hs_smooth / hs_lap_apply."""
+    and the operator application alone through hs_smooth / hs_lap_apply, and
+    the compact pair B_h - a A_h through hs_compact_apply."""
     import torch
     from . import heatst as hs
     from . import inputs
@@ -463,6 +464,7 @@ def micro511(args):
                 tmp = torch.empty_like(b)
                 s = torch.cuda.current_stream()
                 for name, fn, bpp in (("lap_apply", lambda: plan.lap_apply(u, 1.0, -a, out=y), 16.0),
+                                      ("compact_apply", lambda: hs.compact_apply(b, y, n, batch, 1.0, -a), 16.0),
                                       ("jacobi", lambda: plan.smooth(u, b, tmp, a, 2), 24.0)):
                     fn()
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -2,6 +2,7 @@
 and exports every entry point of include/heatst.h, the problem validation
 and workspace sizing behave, and the collocation data the GPU path uses
 (computed independently of the oracle) matches the exact values."""
+import ctypes as C
 import json
 import math
 import os
@@ -264,3 +265,12 @@ def test_three_levels_validated_and_sized():
     with pytest.raises(heatst.HeatstError) as e:
         base_problem(pfasst_groups=2, **pf).workspace_bytes()
     assert e.value.status == heatst.HS_EINVAL
+
+
+def test_compact_apply_rejects_invalid_arguments():
+    """hs_compact_apply validates on the host before any launch."""
+    L = heatst.lib()
+    one = C.c_void_p(1)
+    for n, batch, u, y in ((4, 1, one, one), (0, 1, one, one), (513, 1, one, one), (15, 0, one, one),
+                           (15, 1, None, one), (15, 1, one, None)):
+        assert L.hs_compact_apply(n, batch, 1.0, 0.0, u, y, None) == heatst.HS_EINVAL
