@@ -68,10 +68,26 @@ typedef enum {
 
 typedef enum { HS_FP64 = 0, HS_MIXED = 1 } hs_precision;
 
+/*
+ * Level order code of the compact fourth-order pair (hs_compact_apply):
+ * the semi-discrete equation B_h u' = nu A_h u + B_h f and eqs. (6)-(7)
+ * multiplied by B_h, each substep (B_h - a A_h) U = rhs solved by the
+ * multigrid below with the compact operator on every grid (Jacobi diagonal
+ * 1/2 + 4 a / h^2, exact sine-basis solve on the coarsest grid).  The SDC
+ * residual is the B-weighted one, max over m of
+ * |B U_0 + dt sum_j q_mj (nu A U_j + B f_j) - B U_m|.  Single-level FP64
+ * plans only (nlevels 1, nslices 1, no node-parallel sweeps, no lane
+ * memory); such a plan supports hs_set_state / hs_get_state, hs_step,
+ * hs_solve, hs_begin_step, hs_sdc_sweep (level 0), hs_end_step and the
+ * statistics, and rejects hs_lap_apply, hs_heat_rhs, hs_mg_vcycle and
+ * hs_solve_graph (HS_EINVAL).  Its lanes run one after another.
+ */
+#define HS_ORDER_COMPACT (-4)
+
 /* One SDC level: grid, Laplacian order, collocation nodes. */
 typedef struct {
     int32_t n;        /* interior points per axis, 2^k - 1, 1..511 */
-    int32_t order;    /* 2 or 4 */
+    int32_t order;    /* 2 or 4; level 0 also HS_ORDER_COMPACT */
     int32_t nnodes;   /* Gauss-Lobatto nodes incl. both ends, 2..5 */
 } hs_level_desc;
 

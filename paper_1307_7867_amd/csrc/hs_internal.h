@@ -312,5 +312,18 @@ hipError_t heat_rhs(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int
                     const long long* offs, hipStream_t s);
 // y = alpha B_h u + beta A_h u (compact pair) on `batch` packed n^3 grids
 hipError_t compact_apply(int n, int batch, double alpha, double beta, const double* u, double* y, hipStream_t s);
+// single-level SDC with the compact pair, one lane per launch
+int compact_blocks(int n);
+// mode 0 Jacobi, 1 residual, 2 substep rhs, 3 nu A, 4 norm partials (see k_cmp)
+hipError_t compact_op(int mode, int n, const double* src, double* dst, const double* b, const double* g2,
+                      const LaneCtl* ctl, int lane, double dtau, double omega, double* partials, hipStream_t s);
+hipError_t compact_fw(int nf, const double* rf, double* bc, hipStream_t s);
+hipError_t compact_prolong(int nc, const double* ec, double* uf, hipStream_t s);
+hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau,
+                         hipStream_t s);
+hipError_t compact_quad(int n, int M, int m, const double* G, const double* base, double* dst, const double* sig,
+                        const LaneCtl* ctl, int lane, int L, hipStream_t s);
+hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int lane, int sdc, hipStream_t s);
+hipError_t compact_ctl(LaneCtl* ctl, int lane, int op, int cycles, int state, int level, int status, hipStream_t s);
 
 }  // namespace hsk

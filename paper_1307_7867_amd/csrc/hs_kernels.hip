@@ -2962,6 +2962,211 @@ __global__ void __launch_bounds__(HS_BLOCK) k_compact_apply(int n, int zb, int n
     cmp_march((const HS_G double*)u + g * N, n, i0, j0, z0, z1, ring, op);
 }
 
+// Multigrid and SDC with the compact pair, one lane per launch.  MODE:
+//   0  weighted Jacobi  dst = c + omega / D (b - (B - a A) c),  D = 1/2 + 4 a / h^2
+//   1  residual         dst = b - (B - a A) c
+//   2  substep rhs      dst = (B c - dt_m g2) + b   (b: dt S_m F, g2: nu A U_{m+1})
+//   3  implicit part    dst = nu A c
+//   4  norms            per-block maxima of |b - (B - a A) c| and |b| into partials
+// with dt_m = dt dtau (dtau = tau_{m+1} - tau_m of the substep, 0 for B alone)
+// and a = nu dt_m, dt and nu of the lane.
+template <int MODE>
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp(int n, int zb, const double* __restrict__ src,
+                                                  double* __restrict__ dst, const double* __restrict__ b,
+                                                  const double* __restrict__ g2, const LaneCtl* __restrict__ ctl,
+                                                  int lane, double dtau, double omega, double* __restrict__ partials)
+{
+    const int tx = tiles_x(n), tiles = tx * tiles_y(n);
+    const int tile = (int)blockIdx.x % tiles, zc = (int)blockIdx.x / tiles;
+    const int i0 = (tile % tx) * HS_TX, j0 = (tile / tx) * HS_TY;
+    const int z0 = zc * zb, z1 = min(z0 + zb, n);
+    const LaneCtl& c = ctl[lane];
+    const double dtm = c.dt * dtau, a = c.nu * dtm;
+    const double ih2 = (double)(n + 1) * (double)(n + 1);
+    const double D = 0.5 + a * 24.0 * ih2 / 6.0;
+    struct Op {
+        HS_G double* dst;
+        const HS_G double* b;
+        const HS_G double* g2;
+        double a, D, omega, nu, dtm;
+        double rmax, bmax;
+        __device__ __forceinline__ void operator()(long long p, double cv, double A, double B)
+        {
+            if (MODE == 0) dst[p] = cv + omega * (b[p] - (B - a * A)) / D;
+            else if (MODE == 1) dst[p] = b[p] - (B - a * A);
+            else if (MODE == 2) dst[p] = (B - dtm * g2[p]) + b[p];
+            else if (MODE == 3) dst[p] = nu * A;
+            else {
+                const double bp = b[p];
+                rmax = nmax(rmax, fabs(bp - (B - a * A)));
+                bmax = nmax(bmax, fabs(bp));
+            }
+        }
+    } op{(HS_G double*)dst, (const HS_G double*)b, (const HS_G double*)g2, a, D, omega, c.nu, dtm, 0.0, 0.0};
+    __shared__ double ring[4][CmpTile::LH][CmpTile::LW];
+    cmp_march((const HS_G double*)src, n, i0, j0, z0, z1, ring, op);
+    if (MODE == 4) {
+        double r = op.rmax, bb = op.bmax;
+        block_max2(r, bb);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = r;
+            partials[2 * blockIdx.x + 1] = bb;
+        }
+    }
+}
+
+// full weighting of a fine residual onto the coarse right-hand side, one
+// thread per coarse point (weights (1/4, 1/2, 1/4) per axis; every tap is
+// inside the fine grid)
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp_fw(int nf, const double* __restrict__ rf, double* __restrict__ bc)
+{
+    const int nc = (nf - 1) / 2;
+    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
+    if (q >= (long long)nc * nc * nc) return;
+    const int I = (int)(q % nc), J = (int)((q / nc) % nc), K = (int)(q / ((long long)nc * nc));
+    const double w[3] = {0.25, 0.5, 0.25};
+    double s = 0.0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                const int i = 2 * I + 1 + dx, j = 2 * J + 1 + dy, k = 2 * K + 1 + dz;
+                s += w[dx + 1] * w[dy + 1] * w[dz + 1] * rf[((long long)k * nf + j) * nf + i];
+            }
+    bc[q] = s;
+}
+
+// uf += trilinear prolongation of ec (zero walls), one thread per fine point
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp_prolong(int nc, const double* __restrict__ ec,
+                                                          double* __restrict__ uf)
+{
+    const int nf = 2 * nc + 1;
+    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
+    if (q >= (long long)nf * nf * nf) return;
+    const int i = (int)(q % nf), j = (int)((q / nf) % nf), k = (int)(q / ((long long)nf * nf));
+    int ix[2], iy[2], iz[2];
+    double wx[2], wy[2], wz[2];
+    int cx, cy, cz;
+    auto wts = [](int f, int* idx, double* wt, int* cnt) {
+        if (f & 1) { idx[0] = (f - 1) >> 1; wt[0] = 1.0; *cnt = 1; }
+        else { idx[0] = (f >> 1) - 1; wt[0] = 0.5; idx[1] = f >> 1; wt[1] = 0.5; *cnt = 2; }
+    };
+    wts(i, ix, wx, &cx);
+    wts(j, iy, wy, &cy);
+    wts(k, iz, wz, &cz);
+    double s = 0.0;
+    for (int c = 0; c < cz; c++)
+        for (int b = 0; b < cy; b++)
+            for (int a = 0; a < cx; a++) {
+                const int I = ix[a], J = iy[b], K = iz[c];
+                if (I < 0 || I >= nc || J < 0 || J >= nc || K < 0 || K >= nc) continue;
+                s += wx[a] * wy[b] * wz[c] * ec[((long long)K * nc + J) * nc + I];
+            }
+    uf[q] += s;
+}
+
+// exact solve of (B - a A) x = b on the coarsest grid (n = 1 or 3) in the
+// sine basis: x = S diag(1 / (lam_B - a lam_A)) S b, S the orthonormal DST-I
+__global__ void __launch_bounds__(64) k_cmp_exact(int n, const double* __restrict__ b, double* __restrict__ x,
+                                                  const LaneCtl* __restrict__ ctl, int lane, double dtau)
+{
+    __shared__ double bh[27];
+    __shared__ double S[3][3], cs[3];
+    const int t = (int)threadIdx.x, N3 = n * n * n;
+    const double pi = 3.14159265358979323846;
+    if (t < n * n) S[t / n][t % n] = sqrt(2.0 / (n + 1)) * sin(pi * (t % n + 1) * (t / n + 1) / (n + 1));
+    if (t < n) cs[t] = cos(pi * (t + 1) / (n + 1));
+    __syncthreads();
+    const double a = ctl[lane].nu * (ctl[lane].dt * dtau);
+    const double ih2 = (double)(n + 1) * (double)(n + 1);
+    if (t < N3) {
+        const int p = t % n, q = (t / n) % n, r = t / (n * n);
+        double s = 0.0;
+        for (int k = 0; k < n; k++)
+            for (int j = 0; j < n; j++)
+                for (int i = 0; i < n; i++) s += S[r][k] * S[q][j] * S[p][i] * b[(k * n + j) * n + i];
+        const double sc = cs[p] + cs[q] + cs[r], pc = cs[p] * cs[q] + cs[p] * cs[r] + cs[q] * cs[r];
+        const double la = (4.0 * sc + 4.0 * pc - 24.0) * ih2 / 6.0, lb = 0.5 + sc / 6.0;
+        bh[t] = s / (lb - a * la);
+    }
+    __syncthreads();
+    if (t < N3) {
+        const int i = t % n, j = (t / n) % n, k = t / (n * n);
+        double s = 0.0;
+        for (int r = 0; r < n; r++)
+            for (int q = 0; q < n; q++)
+                for (int p = 0; p < n; p++) s += S[r][k] * S[q][j] * S[p][i] * bh[(r * n + q) * n + p];
+        x[t] = s;
+    }
+}
+
+// Quadratures of the compact sweep over F_j = G_j + lam_B g_j s(x), the
+// B-weighted right-hand side at node j (G_j = nu A U_j; for the forcing's
+// sine mode B f = lam_B f, lam_B = 1/2 + cos(pi h) / 2).  One thread per point.
+//   m < 0:  dst[mm N + p] = dt sum_j S_mm,j F_j for mm = 0..M-2 (iterate k)
+//   m >= 0: dst[p] = base[p] + dt sum_j Q_m,j F_j (B U_0 plus the integral to tau_m)
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp_quad(int n, int M, int m, const double* __restrict__ G,
+                                                       const double* __restrict__ base, double* __restrict__ dst,
+                                                       const double* __restrict__ sig,
+                                                       const LaneCtl* __restrict__ ctl, int lane, int L)
+{
+    const long long N = (long long)n * n * n;
+    const long long p = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
+    if (p >= N) return;
+    const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long long)n * n));
+    const LaneCtl& c = ctl[lane];
+    const SdcConst& K = c_lc.sdc[M];
+    const double lamb = 0.5 + 0.5 * cos(3.14159265358979323846 / (n + 1));
+    const double s = sval(sig, i, j, k);
+    double F[HS_MAXM];
+    for (int q = 0; q < M; q++) F[q] = G[q * N + p] + lamb * (c.g[L][q] * s);
+    if (m < 0) {
+        for (int mm = 0; mm + 1 < M; mm++) {
+            double acc = 0.0;
+            for (int q = 0; q < M; q++) acc += K.S[mm][q] * F[q];
+            dst[mm * N + p] = c.dt * acc;
+        }
+    } else {
+        double acc = 0.0;
+        for (int q = 0; q < M; q++) acc += K.Q[m][q] * F[q];
+        dst[p] = base[p] + c.dt * acc;
+    }
+}
+
+// Maxima of the norm partials of one launch (pairs |r|, |b| per block) into
+// the lane state: mg_rho = max|r| / max|b| (max|b| = 0 counts as 1) and
+// bnorm = max|b|; with sdc = 1 sdc_res = max|r| instead, with sdc = 2 the
+// larger of sdc_res and max|r|.
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp_reduce(const double* __restrict__ partials, int nblk,
+                                                         LaneCtl* __restrict__ ctl, int lane, int sdc)
+{
+    double r = 0.0, bb = 0.0;
+    for (int q = (int)threadIdx.x; q < nblk; q += HS_BLOCK) {
+        r = nmax(r, partials[2 * q]);
+        bb = nmax(bb, partials[2 * q + 1]);
+    }
+    block_max2(r, bb);
+    if (threadIdx.x != 0) return;
+    LaneCtl& c = ctl[lane];
+    if (sdc) {
+        c.sdc_res = sdc == 1 ? r : nmax(c.sdc_res, r);
+    } else {
+        c.bnorm = bb;
+        c.mg_rho = r / (bb > 0.0 ? bb : 1.0);
+    }
+}
+
+// Lane bookkeeping of the compact path: op 0 ends a solve (finish_solve with
+// cycles / state), op 1 sets the SDC state; a negative status is kept if the
+// lane has none yet.
+__global__ void k_cmp_ctl(LaneCtl* ctl, int lane, int op, int cycles, int state, int level, int status)
+{
+    if (threadIdx.x != 0) return;
+    LaneCtl& c = ctl[lane];
+    if (op == 0) finish_solve(c, cycles, state, level);
+    else c.sdc_state = state;
+    if (status < 0 && c.status == 0) c.status = status;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -3406,6 +3611,82 @@ hipError_t compact_apply(int n, int batch, double alpha, double beta, const doub
     const int nz = (n + zb - 1) / zb;
     hipLaunchKernelGGL(k_compact_apply, dim3((unsigned)(batch * tiles * nz)), BLK, 0, s, n, zb, nz, alpha, beta, u,
                        y);
+    return hipGetLastError();
+}
+
+static void cmp_shape(int n, int* zb, int* nz)
+{
+    const int tiles = tiles_x(n) * tiles_y(n);
+    int z = 32;
+    while (z > 2 && (long long)tiles * ((n + z - 1) / z) < 512) z /= 2;
+    *zb = z;
+    *nz = (n + z - 1) / z;
+}
+
+int compact_blocks(int n)
+{
+    int zb, nz;
+    cmp_shape(n, &zb, &nz);
+    return tiles_x(n) * tiles_y(n) * nz;
+}
+
+hipError_t compact_op(int mode, int n, const double* src, double* dst, const double* b, const double* g2,
+                      const LaneCtl* ctl, int lane, double dtau, double omega, double* partials, hipStream_t s)
+{
+    int zb, nz;
+    cmp_shape(n, &zb, &nz);
+    const dim3 grid((unsigned)(tiles_x(n) * tiles_y(n) * nz));
+    switch (mode) {
+    case 0: hipLaunchKernelGGL(k_cmp<0>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
+    case 1: hipLaunchKernelGGL(k_cmp<1>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
+    case 2: hipLaunchKernelGGL(k_cmp<2>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
+    case 3: hipLaunchKernelGGL(k_cmp<3>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
+    default: hipLaunchKernelGGL(k_cmp<4>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t compact_fw(int nf, const double* rf, double* bc, hipStream_t s)
+{
+    const long long nc = (nf - 1) / 2, N = nc * nc * nc;
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cmp_fw, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nf, rf, bc);
+    return hipGetLastError();
+}
+
+hipError_t compact_prolong(int nc, const double* ec, double* uf, hipStream_t s)
+{
+    const long long nf = 2 * nc + 1, N = nf * nf * nf;
+    hipLaunchKernelGGL(k_cmp_prolong, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nc, ec, uf);
+    return hipGetLastError();
+}
+
+hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau,
+                         hipStream_t s)
+{
+    if (n < 1 || n > 3) return hipErrorInvalidValue;   // one block of 64 threads holds n^3 <= 27
+    hipLaunchKernelGGL(k_cmp_exact, dim3(1), dim3(64), 0, s, n, b, x, ctl, lane, dtau);
+    return hipGetLastError();
+}
+
+hipError_t compact_quad(int n, int M, int m, const double* G, const double* base, double* dst, const double* sig,
+                        const LaneCtl* ctl, int lane, int L, hipStream_t s)
+{
+    const long long N = (long long)n * n * n;
+    hipLaunchKernelGGL(k_cmp_quad, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, n, M, m, G, base, dst,
+                       sig, ctl, lane, L);
+    return hipGetLastError();
+}
+
+hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int lane, int sdc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cmp_reduce, dim3(1), BLK, 0, s, partials, nblk, ctl, lane, sdc);
+    return hipGetLastError();
+}
+
+hipError_t compact_ctl(LaneCtl* ctl, int lane, int op, int cycles, int state, int level, int status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cmp_ctl, dim3(1), dim3(64), 0, s, ctl, lane, op, cycles, state, level, status);
     return hipGetLastError();
 }
 

@@ -133,6 +133,12 @@ LibConst make_libconst()
 std::mutex g_const_mu;
 std::set<int> g_const_devices;
 
+const LibConst& host_consts()
+{
+    static const LibConst lc = make_libconst();
+    return lc;
+}
+
 hipError_t ensure_constants()
 {
     int dev = 0;
@@ -140,8 +146,7 @@ hipError_t ensure_constants()
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lk(g_const_mu);
     if (g_const_devices.count(dev)) return hipSuccess;
-    static const LibConst lc = make_libconst();
-    e = hsk::set_constants(lc);
+    e = hsk::set_constants(host_consts());
     if (e == hipSuccess) g_const_devices.insert(dev);
     return e;
 }
@@ -224,6 +229,8 @@ struct hs_plan {
     int nctl = 0;                              // lane states: B SDC lanes, then node-parallel solver lanes
     bool np = false;                           // node-parallel SDC sweeps (pb.sdc_node_parallel)
     int order[HS_MAXLEV] = {2, 2, 2}, M[HS_MAXLEV] = {3, 3, 3};
+    bool compact = false;                      // the compact pair (single level); the multigrid
+                                               // tables are then built for order 2 and not used
     bool mixed = false;
     size_t bytes = 0;
     char* ws = nullptr;
@@ -861,6 +868,8 @@ void layout(hs_plan* P, char* base)
         for (auto& t : S->pro) upd(t.nblk);
     }
     for (auto& ls : P->grp) scan(ls);
+    if (P->compact)   // norm launches of the compact path, one lane at a time
+        for (int b = 0; b < P->B; b++) upd(hsk::compact_blocks(P->lane_n[b]));
     P->partials = bump.arr<double>(2 * (size_t)maxblk);
     P->partials2 = P->G ? bump.arr<double>(2 * (size_t)maxblk) : nullptr;
     P->bytes = (bump.off + 255) & ~(size_t)255;
@@ -902,7 +911,7 @@ hs_status validate(const hs_problem* pb)
     if (!std::isfinite(pb->t0) || !std::isfinite(pb->forcing_c)) return HS_EINVAL;
     for (int L = 0; L < pb->nlevels; L++) {
         const hs_level_desc& d = pb->lev[L];
-        if (d.order != 2 && d.order != 4) return HS_EINVAL;
+        if (d.order != 2 && d.order != 4 && !(d.order == HS_ORDER_COMPACT && L == 0)) return HS_EINVAL;
         if (d.nnodes < 2 || d.nnodes > HS_MAXM) return HS_EINVAL;
         if (L == 0 && !pb->h_lane_n && !valid_n(d.n)) return HS_EINVAL;
     }
@@ -939,6 +948,11 @@ hs_status validate(const hs_problem* pb)
     if (pb->fas_interp != 0 && pb->fas_interp != 1 && pb->fas_interp != 3) return HS_EINVAL;
     if (pb->pfasst_groups >= 2 &&
         (pb->nslices % pb->pfasst_groups != 0 || pb->sweeps <= 0 || pb->mg.cycle_graphs || pb->nlevels != 2))
+        return HS_EINVAL;
+    // the compact pair: single-level FP64 SDC, one lane after another
+    if (pb->lev[0].order == HS_ORDER_COMPACT &&
+        (pb->nlevels != 1 || pb->nslices != 1 || mg.precision != HS_FP64 || pb->sdc_node_parallel ||
+         pb->lane_memory))
         return HS_EINVAL;
     if (pb->nslices > 1) {
         if (pb->nslices != pb->batch || pb->nlevels < 2) return HS_EINVAL;
@@ -1518,8 +1532,191 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
     return HS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Single-level SDC with the compact pair (B-weighted form of eqs. (6)-(7)):
+// every substep solves (B - a A) U_{m+1} = rhs by V-cycles on the compact
+// operator, rediscretised on each coarser grid.  The lanes are taken one at a
+// time with launches over one grid; the host reads each solve's residual norm
+// back to stop it (the same rule as the second-order/fourth-order solves).
+// ---------------------------------------------------------------------------
+
+// One V(nu1, nu2) cycle on grid l of lane `lane`'s hierarchy: u, b its iterate
+// and right-hand side, t a scratch grid of the same size.
+hs_status cmp_vcycle(hs_plan* P, int lane, int l, double* u, const double* b, double* t, double dtau, hipStream_t s)
+{
+    const hs_mg_desc& mg = P->pb.mg;
+    const LaneBufs& lb = P->lanes[lane];
+    const int n = lb.grids[0][l];
+    if (n <= mg.n_coarsest || l + 1 >= (int)lb.grids[0].size()) {
+        HS_TRY(hsk::compact_exact(n, b, u, P->ctl, lane, dtau, s));
+        return HS_OK;
+    }
+    auto smooth = [&](int k) -> hs_status {
+        double *x = u, *y = t;
+        for (int q = 0; q < k; q++) {
+            HS_TRY(hsk::compact_op(0, n, x, y, b, nullptr, P->ctl, lane, dtau, mg.omega, nullptr, s));
+            std::swap(x, y);
+        }
+        if (x != u) HS_TRY(hipMemcpyAsync(u, x, cube(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return HS_OK;
+    };
+    HS_CHECK(smooth(mg.nu1));
+    HS_TRY(hsk::compact_op(1, n, u, t, b, nullptr, P->ctl, lane, dtau, 0.0, nullptr, s));
+    const int nc = lb.grids[0][l + 1];
+    double *cu = lb.gu[0][l + 1], *ct = lb.gt[0][l + 1], *cb = lb.gb[0][l + 1];
+    HS_TRY(hsk::compact_fw(n, t, cb, s));
+    HS_TRY(hipMemsetAsync(cu, 0, cube(nc) * sizeof(double), s));
+    HS_CHECK(cmp_vcycle(P, lane, l + 1, cu, cb, ct, dtau, s));
+    HS_TRY(hsk::compact_prolong(nc, cu, u, s));
+    HS_CHECK(smooth(mg.nu2));
+    return HS_OK;
+}
+
+// Solve (B - a A) u = b on the lane's finest grid from the guess in u, a = nu dt dtau.
+hs_status cmp_solve(hs_plan* P, int lane, double dtau, double* u, const double* b, hipStream_t s)
+{
+    const hs_mg_desc& mg = P->pb.mg;
+    const LaneBufs& lb = P->lanes[lane];
+    const int n = lb.n[0];
+    const Issuer I = issuer(P, s);
+    double rho = 0.0;
+    auto norm = [&]() -> hs_status {
+        HS_TRY(hsk::compact_op(4, n, u, nullptr, b, nullptr, P->ctl, lane, dtau, 0.0, I.partials, s));
+        HS_TRY(hsk::compact_reduce(I.partials, hsk::compact_blocks(n), P->ctl, lane, 0, s));
+        HS_CHECK(read_ctl(P, s, &P->run));
+        rho = I.h_ctl[lane].mg_rho;
+        return HS_OK;
+    };
+    int c = 0, state = 1, status = HS_OK;
+    if (mg.fixed_cycles > 0) {
+        for (c = 0; c < mg.fixed_cycles; c++) HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, s));
+        HS_CHECK(norm());
+        if (rho != rho) { state = 2; status = HS_ENONFINITE; }
+    } else {
+        for (c = 0;; c++) {
+            HS_CHECK(norm());
+            if (rho != rho) { state = 2; status = HS_ENONFINITE; break; }
+            if (rho <= mg.tol) break;
+            if (c >= mg.max_cycles) { state = 2; status = HS_ENOCONV; break; }
+            HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, s));
+        }
+    }
+    HS_TRY(hsk::compact_ctl(P->ctl, lane, 0, c, state, 0, status, s));
+    return HS_OK;
+}
+
+// Collocation residual of the B-weighted form,
+//   R = max over m = 1..M-1 of |B U_0 + dt sum_j Q_mj F_j - B U_m|,
+// into the lane's sdc_res (read back into *R).
+hs_status cmp_residual(hs_plan* P, int lane, hipStream_t s, double* R)
+{
+    const LaneBufs& lb = P->lanes[lane];
+    const int n = lb.n[0], M = P->M[0];
+    const long long N = lb.N[0];
+    const Issuer I = issuer(P, s);
+    HS_TRY(hsk::compact_apply(n, 1, 1.0, 0.0, lb.U[0], lb.tmp[0], s));
+    for (int m = 1; m < M; m++) {
+        HS_TRY(hsk::compact_quad(n, M, m, lb.FI[0], lb.tmp[0], lb.rhs[0], lb.sig[0], P->ctl, lane, 0, s));
+        HS_TRY(hsk::compact_op(4, n, lb.U[0] + m * N, nullptr, lb.rhs[0], nullptr, P->ctl, lane, 0.0, 0.0,
+                               I.partials, s));
+        HS_TRY(hsk::compact_reduce(I.partials, hsk::compact_blocks(n), P->ctl, lane, m == 1 ? 1 : 2, s));
+    }
+    HS_CHECK(read_ctl(P, s, &P->run));
+    *R = I.h_ctl[lane].sdc_res;
+    return HS_OK;
+}
+
+// One compact IMEX sweep of a lane: dt S^k F from iterate k, then per substep
+// rhs = B U_m - dt_m G_{m+1} + dt S^k_m F, the solve for U_{m+1} from its
+// old value, and G_{m+1} = nu A U_{m+1}.
+hs_status cmp_sweep(hs_plan* P, int lane, hipStream_t s)
+{
+    const LaneBufs& lb = P->lanes[lane];
+    const int n = lb.n[0], M = P->M[0];
+    const long long N = lb.N[0];
+    const SdcConst& K = host_consts().sdc[M];
+    double *U = lb.U[0], *G = lb.FI[0];
+    HS_TRY(hsk::begin_sweep(P->ctl, lane, 1, s));
+    HS_TRY(hsk::compact_quad(n, M, -1, G, nullptr, lb.P[0], lb.sig[0], P->ctl, lane, 0, s));
+    for (int m = 0; m + 1 < M; m++) {
+        HS_TRY(hsk::compact_op(2, n, U + m * N, lb.rhs[0], lb.P[0] + m * N, G + (m + 1) * N, P->ctl, lane,
+                               K.dtau[m], 0.0, nullptr, s));
+        HS_CHECK(cmp_solve(P, lane, K.dtau[m], U + (m + 1) * N, lb.rhs[0], s));
+        HS_TRY(hsk::compact_op(3, n, U + (m + 1) * N, G + (m + 1) * N, nullptr, nullptr, P->ctl, lane, 0.0, 0.0,
+                               nullptr, s));
+    }
+    return HS_OK;
+}
+
+// The run set's lanes that iterate in the current step (host view).
+std::vector<int> cmp_live(hs_plan* P, hipStream_t s)
+{
+    std::vector<int> live;
+    const LaneCtl* h = issuer(P, s).h_ctl;
+    for (int b : P->run.lanes)
+        if (h[b].sdc_state == 0) live.push_back(b);
+    return live;
+}
+
+// Start a step: coefficients, then every node's U = U_{M-1} (the state) and G = nu A U.
+hs_status cmp_begin_step(hs_plan* P, hipStream_t s)
+{
+    HS_CHECK(refresh_run(P, s));
+    P->sweep_k = 0;
+    HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M, s));
+    HS_CHECK(read_ctl(P, s));
+    const int M = P->M[0];
+    for (int b : cmp_live(P, s)) {
+        const LaneBufs& lb = P->lanes[b];
+        const long long N = lb.N[0];
+        double *U = lb.U[0], *G = lb.FI[0];
+        HS_TRY(hsk::compact_op(3, lb.n[0], U + (M - 1) * N, G + (M - 1) * N, nullptr, nullptr, P->ctl, b, 0.0, 0.0,
+                               nullptr, s));
+        for (int m = 0; m + 1 < M; m++) {
+            HS_TRY(hipMemcpyAsync(U + m * N, U + (M - 1) * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            HS_TRY(hipMemcpyAsync(G + m * N, G + (M - 1) * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+    }
+    return HS_OK;
+}
+
+// One sweep of every live lane (read back first: a lane whose SDC
+// iteration has ended is left alone).
+hs_status cmp_sweep_all(hs_plan* P, hipStream_t s)
+{
+    HS_CHECK(read_ctl(P, s));
+    for (int b : cmp_live(P, s)) HS_CHECK(cmp_sweep(P, b, s));
+    return HS_OK;
+}
+
+hs_status cmp_step(hs_plan* P, hipStream_t s)
+{
+    HS_CHECK(cmp_begin_step(P, s));
+    const hs_problem& pb = P->pb;
+    for (int b : cmp_live(P, s)) {
+        int state = 1, status = HS_OK;
+        double R = 0.0;
+        for (int k = 0;; k++) {
+            if (pb.sweeps > 0) {
+                if (k >= pb.sweeps) break;
+            } else {
+                HS_CHECK(cmp_residual(P, b, s, &R));
+                if (R != R) { state = 2; status = HS_ENONFINITE; break; }
+                if (R <= pb.sdc_tol) break;
+                if (k >= pb.max_sweeps) { state = 2; status = HS_ENOCONV; break; }
+            }
+            HS_CHECK(cmp_sweep(P, b, s));
+        }
+        if (pb.sweeps > 0) HS_CHECK(cmp_residual(P, b, s, &R));
+        HS_TRY(hsk::compact_ctl(P->ctl, b, 1, 0, state, 0, status, s));
+    }
+    HS_TRY(hsk::end_step(P->ctl, P->B, s));
+    return HS_OK;
+}
+
 hs_status begin_step(hs_plan* P, hipStream_t s)
 {
+    if (P->compact) return cmp_begin_step(P, s);
     HS_CHECK(refresh_run(P, s));
     P->sweep_k = 0;
     HS_TRY(hsk::begin_step(P->ctl, P->B, P->nlev, P->M, s));
@@ -1531,6 +1728,7 @@ hs_status begin_step(hs_plan* P, hipStream_t s)
 
 hs_status step(hs_plan* P, hipStream_t s)
 {
+    if (P->compact) return cmp_step(P, s);
     HS_CHECK(begin_step(P, s));
     const hs_problem& pb = P->pb;
     int outcome;
@@ -1647,9 +1845,10 @@ static void init_plan(hs_plan* P, const hs_problem* pb)
     P->B = pb->batch;
     P->nlev = pb->nlevels;
     for (int L = 0; L < HS_MAXLEV; L++) {
-        P->order[L] = L < pb->nlevels ? pb->lev[L].order : 2;
+        P->order[L] = L < pb->nlevels && pb->lev[L].order != HS_ORDER_COMPACT ? pb->lev[L].order : 2;
         P->M[L] = L < pb->nlevels ? pb->lev[L].nnodes : 2;
     }
+    P->compact = pb->lev[0].order == HS_ORDER_COMPACT;
     P->mixed = pb->mg.precision == HS_MIXED;
     P->lane_n.assign(P->B, pb->lev[0].n);
     if (pb->h_lane_n)
@@ -1851,6 +2050,7 @@ hs_status hs_lap_apply(hs_plan* P, int32_t level, double alpha, double beta, con
                        double* d_y, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->compact) return HS_EINVAL;   // operators of orders 2 and 4 only
     if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || !d_u || !d_y) return HS_EINVAL;
     const Table<GridSeg>& T = P->all.mg64[level].fine;   // the lanes' finest grids, z-chunked
@@ -1872,6 +2072,7 @@ hs_status hs_heat_rhs(hs_plan* P, int32_t level, const double* d_u, const double
                       double* d_fe, void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->compact) return HS_EINVAL;   // operators of orders 2 and 4 only
     if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || (d_fi && !d_u) || (d_fe && !h_t)) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -1890,6 +2091,7 @@ hs_status hs_mg_vcycle(hs_plan* P, int32_t level, const double* h_a, double* d_u
                        void* stream)
 {
     HS_CHECK(check_bound(P));
+    if (P->compact) return HS_EINVAL;   // operators of orders 2 and 4 only
     if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev || !h_a || !d_u || !d_b) return HS_EINVAL;
     for (int b = 0; b < P->B; b++)
@@ -1931,6 +2133,7 @@ hs_status hs_mg_solve_static(int32_t n, int32_t order, double a, const hs_mg_des
     pb.dt = 1.0;
     pb.nlevels = 1;
     pb.lev[0].n = n;
+    if (order != 2 && order != 4) return HS_EINVAL;
     pb.lev[0].order = order;
     pb.lev[0].nnodes = 2;
     pb.mg = *mg;
@@ -2135,6 +2338,7 @@ hs_status hs_sdc_sweep(hs_plan* P, int32_t level, void* stream)
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
     int outcome;
     HS_CHECK(refresh_run(P, (hipStream_t)stream));
+    if (P->compact) return cmp_sweep_all(P, (hipStream_t)stream);
     return sweep(P, P->run, level, false, level == 0, (hipStream_t)stream, &outcome);
 }
 
@@ -2193,6 +2397,7 @@ hs_status hs_solve_graph(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
     if (P->pb.lane_memory) return HS_EINVAL;
+    if (P->compact) return HS_EINVAL;
     if (P->pb.nslices > 1 || P->pb.sweeps <= 0 || P->pb.mg.fixed_cycles <= 0) return HS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     // table uploads are not allowed inside a capture: bring them up to date first

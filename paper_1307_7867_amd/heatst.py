@@ -20,6 +20,7 @@ TUNE_CACHE = os.path.join(HERE, "tune_cache.json")
 HS_OK, HS_EINVAL, HS_ENOMEM, HS_ENOCONV, HS_ENONFINITE, HS_EDEVICE, HS_ESTATE, HS_PENDING = \
     0, -1, -2, -3, -4, -5, -6, 1
 HS_FP64, HS_MIXED = 0, 1
+HS_ORDER_COMPACT = -4   # level order code of the compact fourth-order pair
 
 
 class HeatstError(RuntimeError):

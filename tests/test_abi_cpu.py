@@ -274,3 +274,27 @@ def test_compact_apply_rejects_invalid_arguments():
     for n, batch, u, y in ((4, 1, one, one), (0, 1, one, one), (513, 1, one, one), (15, 0, one, one),
                            (15, 1, None, one), (15, 1, one, None)):
         assert L.hs_compact_apply(n, batch, 1.0, 0.0, u, y, None) == heatst.HS_EINVAL
+
+
+@pytest.mark.parametrize("kw", [
+    dict(coarse=(7, 2, 3)),                                  # single level only
+    dict(precision=heatst.HS_MIXED),                         # FP64 only
+    dict(sdc_node_parallel=1),
+    dict(batch=2, nslices=2, nsteps=2, coarse=(7, 2, 3)),
+])
+def test_compact_plans_validated(kw):
+    args = dict(n=15, order=heatst.HS_ORDER_COMPACT, nnodes=3)
+    args.update(kw)
+    with pytest.raises(heatst.HeatstError) as e:
+        base_problem(**args).workspace_bytes()
+    assert e.value.status == heatst.HS_EINVAL
+
+
+def test_compact_plan_sized_and_coarse_level_rejected():
+    """A compact single-level plan lays out like the order-2 one of the same
+    grids; the compact code is not accepted below the finest level."""
+    b = base_problem(n=31, order=heatst.HS_ORDER_COMPACT, nnodes=3).workspace_bytes()
+    assert b == base_problem(n=31, order=2, nnodes=3).workspace_bytes()
+    with pytest.raises(heatst.HeatstError) as e:
+        base_problem(n=31, order=4, nnodes=3, coarse=(15, heatst.HS_ORDER_COMPACT, 3)).workspace_bytes()
+    assert e.value.status == heatst.HS_EINVAL

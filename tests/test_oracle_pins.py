@@ -1076,3 +1076,36 @@ def test_compact_is_single_level_only():
     u0 = inputs.random_smooth(15, 1)
     bad = oracle.problem([(15, oracle.COMPACT, 5), (7, 2, 3)], sweeps=1)
     assert oracle.run(bad, u0)[1] == oracle.EINVAL
+
+
+def test_compact_sdc_sine_mode_scalar_recursion():
+    """Started on the sine mode s(x), compact SDC keeps the state a multiple
+    of s(x) (A_h and B_h act on it as their eigenvalues and the forcing is
+    the same mode), and the amplitude follows the B-weighted sweep of the
+    scalar problem, written out here with exact substep solves: a pin of the
+    sweep's signs, node spacings and quadrature against the closed form."""
+    n, M, nu, dt, c, nsteps, sweeps = 15, 3, 0.1, 0.05, 3.0, 2, 3
+    h = 1.0 / (n + 1)
+    cs = math.cos(math.pi * h)
+    lam_a = (12.0 * cs + 12.0 * cs * cs - 24.0) / (6.0 * h * h)
+    lam_b = 0.5 + cs / 2.0
+    tau, Q = oracle.lobatto_nodes(M), oracle.collocation_matrix(M)
+    amp = 1.0
+    for k in range(nsteps):
+        tn = k * dt
+        g = np.array([-(math.sin(tn + dt * t) - c * nu * math.pi ** 2 * math.cos(tn + dt * t)) for t in tau])
+        U = np.full(M, amp)
+        for _ in range(sweeps):
+            F = nu * lam_a * U + lam_b * g
+            new = U.copy()
+            for m in range(M - 1):
+                dtm = dt * (tau[m + 1] - tau[m])
+                sf = dt * ((Q[m + 1] - Q[m]) @ F)
+                new[m + 1] = (lam_b * new[m] - dtm * nu * lam_a * U[m + 1] + sf) / (lam_b - dtm * nu * lam_a)
+            U = new
+        amp = U[-1]
+    s = inputs.sine_product(n)
+    u, st, _ = oracle.run(oracle.problem([(n, oracle.COMPACT, M)], nu=nu, dt=dt, nsteps=nsteps, sweeps=sweeps,
+                                         forcing_c=c, mg=oracle.mg_params(tol=1e-13)), s)
+    assert st == oracle.OK
+    assert np.abs(u - amp * s).max() <= 1e-11
