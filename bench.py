@@ -299,7 +299,7 @@ def main():
                     help="serving: skip the closing all-at-once stream")
     ap.add_argument("--workload", default="pfasst16",
                     choices=["pfasst16", "sdc15", "mlsdc127", "mixed255", "uneven64", "serving", "micro511",
-                             "eq10", "levels3", "sdcnp127"],
+                             "eq10", "levels3", "sdcnp127", "compact127"],
                     help="pfasst16 (default): the headline line with every other workload as an extra; "
                          "any other name runs that workload alone")
     ap.add_argument("--seeds", default="0", help="mixed255: comma-separated seeds")
@@ -339,8 +339,8 @@ def main():
     out = headline(args, torch, hs, inputs)
     if not args.no_extras:
         extra = {}
-        for name in ("sdc15", "mlsdc127", "eq10", "levels3", "sdcnp127", "mixed255", "uneven64", "micro511",
-                     "serving"):
+        for name in ("sdc15", "mlsdc127", "eq10", "levels3", "sdcnp127", "compact127", "mixed255", "uneven64",
+                     "micro511", "serving"):
             log(f"extra: {name}")
             t0 = time.perf_counter()
             extra[name] = getattr(workloads, name)(args)

@@ -22,6 +22,10 @@ host and copied to HBM before any timed region.
             collocation residual is below --sdc-tol (1e-10).
   uneven64  64 independent instances with n drawn from {31, 63, 127}: one
             batched plan against one plan per instance run in turn.
+  compact127 127^3, 5 nodes, nu 0.1, dt 0.05, 4 steps from u = s(x), sweeps
+            until the collocation residual is <= 1e-10, V(2,1) to 1e-12: the
+            compact fourth-order pair against the wide 13-point stencil, time
+            per step and the error against the exact solution s(x) cos t.
   micro511  single-kernel rates on the finest grid of the 511^3 hierarchy
             (FP64 and the FP32 inner cycles of mixed precision) and of a
             batch of two 255^3 grids, from HIP events on each launch.
@@ -317,6 +321,42 @@ def sdcnp127(args):
     return {"workload": "sdcnp127", "metric": "ms per step", "value": res["node_parallel"]["ms_per_step"],
             "unit": "ms", **res, "speedup_node_parallel": res["sequential"]["seconds"] / res["node_parallel"]["seconds"],
             "rel_diff": diff}
+
+
+# ----------------------------------------------------------------------------
+# compact fourth-order pair against the wide fourth-order stencil
+# ----------------------------------------------------------------------------
+
+def compact127(args):
+    """Both schemes from the sine mode with the forcing that makes s(x) cos t
+    the exact solution (c = 3): the compact pair's smaller error constant
+    against its cost (one lane, a host check per cycle)."""
+    import math
+    from . import heatst as hs
+    from . import inputs
+    n, M, dt, steps = 127, 5, 0.05, 4
+    s = inputs.sine_product(n)
+    u0 = _dev(s)
+    exact = s * math.cos(steps * dt)
+    res = {}
+    for name, order in (("compact", hs.HS_ORDER_COMPACT), ("wide", 4)):
+        _log(f"compact127: {name}")
+        plan = hs.Plan(hs.Problem(n=n, order=order, nnodes=M, nu=0.1, dt=dt, nsteps=steps, sweeps=0, sdc_tol=1e-10,
+                                  max_sweeps=40, tol=1e-12, max_cycles=60))
+        plan.set_state(u0)
+        plan.solve()
+        plan.set_state(u0)
+        el = _timed(plan.solve)
+        st, stats = plan.stats()
+        hs.check(st, f"compact127 {name}")
+        got = plan.get_state().cpu().numpy().reshape(n, n, n)
+        res[name] = {"ms_per_step": el / steps * 1e3, "sweeps_per_step": stats[0]["total_sweeps"] / steps,
+                     "vcycles_per_solve": stats[0]["total_cycles"] / stats[0]["total_solves"],
+                     "max_error_vs_exact": float(np.abs(got - exact).max())}
+        del plan
+    return {"workload": "compact127", "metric": "ms per step (compact)", "value": res["compact"]["ms_per_step"],
+            "unit": "ms", "n": n, "nodes": M, "dt": dt, "steps": steps, **res,
+            "error_ratio_wide_over_compact": res["wide"]["max_error_vs_exact"] / res["compact"]["max_error_vs_exact"]}
 
 
 # ----------------------------------------------------------------------------
