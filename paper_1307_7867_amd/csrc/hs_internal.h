@@ -312,18 +312,31 @@ hipError_t heat_rhs(LaneCtl* ctl, const GridSeg* gsegs, const SdcSeg* ssegs, int
                     const long long* offs, hipStream_t s);
 // y = alpha B_h u + beta A_h u (compact pair) on `batch` packed n^3 grids
 hipError_t compact_apply(int n, int batch, double alpha, double beta, const double* u, double* y, hipStream_t s);
-// single-level SDC with the compact pair, one lane per launch
+// single-level SDC with the compact pair, one lane per launch; gate: skip
+// the launch once the lane's solve has stopped
 int compact_blocks(int n);
 // mode 0 Jacobi, 1 residual, 2 substep rhs, 3 nu A, 4 norm partials (see k_cmp)
 hipError_t compact_op(int mode, int n, const double* src, double* dst, const double* b, const double* g2,
-                      const LaneCtl* ctl, int lane, double dtau, double omega, double* partials, hipStream_t s);
-hipError_t compact_fw(int nf, const double* rf, double* bc, hipStream_t s);
-hipError_t compact_prolong(int nc, const double* ec, double* uf, hipStream_t s);
-hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau,
+                      const LaneCtl* ctl, int lane, double dtau, double omega, double* partials, int gate,
+                      hipStream_t s);
+hipError_t compact_fw(int nf, const double* rf, double* bc, const LaneCtl* ctl, int lane, int gate, hipStream_t s);
+// dst = src + P ec (dst may be src)
+hipError_t compact_prolong(int nc, const double* ec, const double* src, double* dst, const LaneCtl* ctl, int lane,
+                           int gate, hipStream_t s);
+// first Jacobi sweep from a zero iterate: dst = omega b / D
+hipError_t compact_zsweep(int n, const double* b, double* dst, const LaneCtl* ctl, int lane, double dtau,
+                          double omega, int gate, hipStream_t s);
+hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau, int gate,
                          hipStream_t s);
+// the V-cycle below a top grid n0 <= HS_TAIL_N in one workgroup (LDS bytes: compact_tail_lds)
+size_t compact_tail_lds(int n0, int n_coarsest);
+hipError_t compact_tail(int n0, double* u, const double* b, int zero_guess, const LaneCtl* ctl, int lane, double dtau,
+                        double omega, int nu1, int nu2, int n_coarsest, int gate, hipStream_t s);
 hipError_t compact_quad(int n, int M, int m, const double* G, const double* base, double* dst, const double* sig,
                         const LaneCtl* ctl, int lane, int L, hipStream_t s);
-hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int lane, int sdc, hipStream_t s);
+// mode 0 solve norm, 1 / 2 SDC residual (set / max), 3 solve norm and stopping test before `cycle`
+hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int lane, int mode, int cycle, double tol,
+                          int max_cycles, hipStream_t s);
 hipError_t compact_ctl(LaneCtl* ctl, int lane, int op, int cycles, int state, int level, int status, hipStream_t s);
 
 }  // namespace hsk

@@ -2969,18 +2969,21 @@ __global__ void __launch_bounds__(HS_BLOCK) k_compact_apply(int n, int zb, int n
 //   3  implicit part    dst = nu A c
 //   4  norms            per-block maxima of |b - (B - a A) c| and |b| into partials
 // with dt_m = dt dtau (dtau = tau_{m+1} - tau_m of the substep, 0 for B alone)
-// and a = nu dt_m, dt and nu of the lane.
+// and a = nu dt_m, dt and nu of the lane.  With gate set the launch does
+// nothing once the lane's solve has stopped (mg_state != 0).
 template <int MODE>
 __global__ void __launch_bounds__(HS_BLOCK) k_cmp(int n, int zb, const double* __restrict__ src,
                                                   double* __restrict__ dst, const double* __restrict__ b,
                                                   const double* __restrict__ g2, const LaneCtl* __restrict__ ctl,
-                                                  int lane, double dtau, double omega, double* __restrict__ partials)
+                                                  int lane, double dtau, double omega, double* __restrict__ partials,
+                                                  int gate)
 {
+    const LaneCtl& c = ctl[lane];
+    if (gate && c.mg_state != 0) return;
     const int tx = tiles_x(n), tiles = tx * tiles_y(n);
     const int tile = (int)blockIdx.x % tiles, zc = (int)blockIdx.x / tiles;
     const int i0 = (tile % tx) * HS_TX, j0 = (tile / tx) * HS_TY;
     const int z0 = zc * zb, z1 = min(z0 + zb, n);
-    const LaneCtl& c = ctl[lane];
     const double dtm = c.dt * dtau, a = c.nu * dtm;
     const double ih2 = (double)(n + 1) * (double)(n + 1);
     const double D = 0.5 + a * 24.0 * ih2 / 6.0;
@@ -3015,15 +3018,10 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp(int n, int zb, const double* _
     }
 }
 
-// full weighting of a fine residual onto the coarse right-hand side, one
-// thread per coarse point (weights (1/4, 1/2, 1/4) per axis; every tap is
-// inside the fine grid)
-__global__ void __launch_bounds__(HS_BLOCK) k_cmp_fw(int nf, const double* __restrict__ rf, double* __restrict__ bc)
+// full weighting of the fine residual at coarse point (I, J, K) (weights
+// (1/4, 1/2, 1/4) per axis; every tap is inside the fine grid)
+__device__ __forceinline__ double cmp_fw_at(const double* rf, int nf, int I, int J, int K)
 {
-    const int nc = (nf - 1) / 2;
-    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
-    if (q >= (long long)nc * nc * nc) return;
-    const int I = (int)(q % nc), J = (int)((q / nc) % nc), K = (int)(q / ((long long)nc * nc));
     const double w[3] = {0.25, 0.5, 0.25};
     double s = 0.0;
     for (int dz = -1; dz <= 1; dz++)
@@ -3032,17 +3030,12 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp_fw(int nf, const double* __res
                 const int i = 2 * I + 1 + dx, j = 2 * J + 1 + dy, k = 2 * K + 1 + dz;
                 s += w[dx + 1] * w[dy + 1] * w[dz + 1] * rf[((long long)k * nf + j) * nf + i];
             }
-    bc[q] = s;
+    return s;
 }
 
-// uf += trilinear prolongation of ec (zero walls), one thread per fine point
-__global__ void __launch_bounds__(HS_BLOCK) k_cmp_prolong(int nc, const double* __restrict__ ec,
-                                                          double* __restrict__ uf)
+// trilinear prolongation of ec (zero walls) at fine point (i, j, k)
+__device__ __forceinline__ double cmp_prolong_at(const double* ec, int nc, int i, int j, int k)
 {
-    const int nf = 2 * nc + 1;
-    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
-    if (q >= (long long)nf * nf * nf) return;
-    const int i = (int)(q % nf), j = (int)((q / nf) % nf), k = (int)(q / ((long long)nf * nf));
     int ix[2], iy[2], iz[2];
     double wx[2], wy[2], wz[2];
     int cx, cy, cz;
@@ -3061,22 +3054,21 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp_prolong(int nc, const double* 
                 if (I < 0 || I >= nc || J < 0 || J >= nc || K < 0 || K >= nc) continue;
                 s += wx[a] * wy[b] * wz[c] * ec[((long long)K * nc + J) * nc + I];
             }
-    uf[q] += s;
+    return s;
 }
 
-// exact solve of (B - a A) x = b on the coarsest grid (n = 1 or 3) in the
-// sine basis: x = S diag(1 / (lam_B - a lam_A)) S b, S the orthonormal DST-I
-__global__ void __launch_bounds__(64) k_cmp_exact(int n, const double* __restrict__ b, double* __restrict__ x,
-                                                  const LaneCtl* __restrict__ ctl, int lane, double dtau)
+// exact solve of (B - a A) x = b for n <= 3 in the sine basis,
+// x = S diag(1 / (lam_B - a lam_A)) S b with S the orthonormal DST-I; called
+// by every thread of the block (t = threadIdx.x), bh a 27-entry scratch.
+// With pad, x is stored with a zero frame of one cell ((n+2)^3 layout).
+__device__ void cmp_exact_dev(int n, const double* b, double* x, double a, double* bh, double (*S)[3], double* cs,
+                              bool pad = false)
 {
-    __shared__ double bh[27];
-    __shared__ double S[3][3], cs[3];
     const int t = (int)threadIdx.x, N3 = n * n * n;
     const double pi = 3.14159265358979323846;
     if (t < n * n) S[t / n][t % n] = sqrt(2.0 / (n + 1)) * sin(pi * (t % n + 1) * (t / n + 1) / (n + 1));
     if (t < n) cs[t] = cos(pi * (t + 1) / (n + 1));
     __syncthreads();
-    const double a = ctl[lane].nu * (ctl[lane].dt * dtau);
     const double ih2 = (double)(n + 1) * (double)(n + 1);
     if (t < N3) {
         const int p = t % n, q = (t / n) % n, r = t / (n * n);
@@ -3095,7 +3087,217 @@ __global__ void __launch_bounds__(64) k_cmp_exact(int n, const double* __restric
         for (int r = 0; r < n; r++)
             for (int q = 0; q < n; q++)
                 for (int p = 0; p < n; p++) s += S[r][k] * S[q][j] * S[p][i] * bh[(r * n + q) * n + p];
-        x[t] = s;
+        if (pad) x[((k + 1) * (n + 2) + (j + 1)) * (n + 2) + (i + 1)] = s;
+        else x[t] = s;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp_fw(int nf, const double* __restrict__ rf, double* __restrict__ bc,
+                                                     const LaneCtl* __restrict__ ctl, int lane, int gate)
+{
+    if (gate && ctl[lane].mg_state != 0) return;
+    const int nc = (nf - 1) / 2;
+    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
+    if (q >= (long long)nc * nc * nc) return;
+    bc[q] = cmp_fw_at(rf, nf, (int)(q % nc), (int)((q / nc) % nc), (int)(q / ((long long)nc * nc)));
+}
+
+// dst = src + trilinear prolongation of ec, one thread per fine point (dst
+// may be src: the correction added in place)
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp_prolong(int nc, const double* __restrict__ ec, const double* src,
+                                                          double* dst, const LaneCtl* __restrict__ ctl, int lane,
+                                                          int gate)
+{
+    if (gate && ctl[lane].mg_state != 0) return;
+    const int nf = 2 * nc + 1;
+    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
+    if (q >= (long long)nf * nf * nf) return;
+    dst[q] = src[q] + cmp_prolong_at(ec, nc, (int)(q % nf), (int)((q / nf) % nf), (int)(q / ((long long)nf * nf)));
+}
+
+// the first Jacobi sweep from a zero iterate: dst = omega b / D (the residual
+// of a zero iterate is b), one thread per point
+__global__ void __launch_bounds__(HS_BLOCK) k_cmp_zsweep(int n, const double* __restrict__ b, double* __restrict__ dst,
+                                                         const LaneCtl* __restrict__ ctl, int lane, double dtau,
+                                                         double omega, int gate)
+{
+    const LaneCtl& c = ctl[lane];
+    if (gate && c.mg_state != 0) return;
+    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
+    if (q >= (long long)n * n * n) return;
+    const double a = c.nu * (c.dt * dtau), ih2 = (double)(n + 1) * (double)(n + 1);
+    dst[q] = omega * b[q] / (0.5 + a * 24.0 * ih2 / 6.0);
+}
+
+__global__ void __launch_bounds__(64) k_cmp_exact(int n, const double* __restrict__ b, double* __restrict__ x,
+                                                  const LaneCtl* __restrict__ ctl, int lane, double dtau, int gate)
+{
+    if (gate && ctl[lane].mg_state != 0) return;
+    __shared__ double bh[27];
+    __shared__ double S[3][3], cs[3];
+    cmp_exact_dev(n, b, x, ctl[lane].nu * (ctl[lane].dt * dtau), bh, S, cs);
+}
+
+// The grids of one compact V-cycle from n <= HS_TAIL_N down, in one
+// workgroup with every field in LDS, the same operations in the same order
+// as the per-grid launches.  Iterates carry a zero frame of one cell
+// ((n+2)^3 values, the walls), so the 19-point stencil and the prolongation
+// read their neighbours without bounds tests; right-hand sides are n^3.
+// Threads: x = tid % 16, y = tid / 16 % 16, z = tid / 256 + 4 r.  The top
+// grid's iterate comes from u (or starts at zero) and goes back to u; b is
+// its right-hand side.  Dynamic LDS: compact_tail_lds bytes.
+__global__ void __launch_bounds__(HS_TAIL_THREADS) k_cmp_tail(int n0, double* __restrict__ ug,
+                                                              const double* __restrict__ bg, int zero_guess,
+                                                              const LaneCtl* __restrict__ ctl, int lane, double dtau,
+                                                              double omega, int nu1, int nu2, int n_coarsest, int gate)
+{
+    if (gate && ctl[lane].mg_state != 0) return;
+    extern __shared__ double lds[];
+    __shared__ double bh[27];
+    __shared__ double Sm[3][3], cs[3];
+    const int tid = (int)threadIdx.x;
+    const int tx = tid & 15, ty = (tid >> 4) & 15, tz = tid >> 8;
+    const double a = ctl[lane].nu * (ctl[lane].dt * dtau);
+    int ns[HS_MAXTAIL];
+    int L = 0;
+    ns[0] = n0;
+    while (ns[L] > n_coarsest && ns[L] > 1 && L + 1 < HS_MAXTAIL) {
+        ns[L + 1] = (ns[L] - 1) / 2;
+        L++;
+    }
+    // per level: X, Y (padded iterates, ping-pong), R (right-hand side)
+    double *X[HS_MAXTAIL], *Y[HS_MAXTAIL], *R[HS_MAXTAIL];
+    int total = 0;
+    {
+        double* q = lds;
+        for (int l = 0; l <= L; l++) {
+            const int P = ns[l] + 2, NP = P * P * P, N = ns[l] * ns[l] * ns[l];
+            X[l] = q; Y[l] = q + NP; R[l] = q + 2 * NP;
+            q += 2 * NP + N;
+            total += 2 * NP + N;
+        }
+    }
+    for (int p = tid; p < total; p += HS_TAIL_THREADS) lds[p] = 0.0;
+    __syncthreads();
+    {
+        const int n = n0, P = n + 2;
+        if (tx < n && ty < n)
+            for (int z = tz; z < n; z += 4) {
+                const int g = (z * n + ty) * n + tx;
+                if (!zero_guess) X[0][((z + 1) * P + ty + 1) * P + tx + 1] = ug[g];
+                R[0][g] = bg[g];
+            }
+    }
+    __syncthreads();
+    // one Jacobi sweep x -> y on level l (x null: from zero)
+    auto sweep = [&](int l, const double* x, double* y) {
+        const int n = ns[l], P = n + 2, PP = P * P;
+        const double ih2 = (double)(n + 1) * (double)(n + 1);
+        const double D = 0.5 + a * 24.0 * ih2 / 6.0;
+        if (tx < n && ty < n)
+            for (int z = tz; z < n; z += 4) {
+                const int c = ((z + 1) * P + ty + 1) * P + tx + 1;
+                const double bv = R[l][(z * n + ty) * n + tx];
+                if (!x) {
+                    y[c] = omega * bv / D;
+                    continue;
+                }
+                const double cv = x[c];
+                const double faces = ((x[c - 1] + x[c + 1]) + (x[c - P] + x[c + P])) + (x[c - PP] + x[c + PP]);
+                const double exy = (x[c - P - 1] + x[c - P + 1]) + (x[c + P - 1] + x[c + P + 1]);
+                const double exz = (x[c - PP - 1] + x[c - PP + 1]) + (x[c + PP - 1] + x[c + PP + 1]);
+                const double eyz = (x[c - PP - P] + x[c - PP + P]) + (x[c + PP - P] + x[c + PP + P]);
+                const double A = ((2.0 * faces + ((exy + exz) + eyz)) - 24.0 * cv) * ih2 / 6.0;
+                const double B = 0.5 * cv + faces / 12.0;
+                y[c] = cv + omega * (bv - (B - a * A)) / D;
+            }
+        __syncthreads();
+    };
+    // where each level's iterate is: cur[l] (X or Y)
+    double* cur[HS_MAXTAIL];
+    for (int l = 0; l < L; l++) {
+        const int n = ns[l], P = n + 2, PP = P * P, nc = ns[l + 1];
+        const double ih2 = (double)(n + 1) * (double)(n + 1);
+        double *x = X[l], *y = Y[l];
+        const bool zg = l > 0 || zero_guess;
+        for (int q = 0; q < nu1; q++) {
+            sweep(l, (q == 0 && zg) ? nullptr : x, y);
+            double* w = x; x = y; y = w;
+        }
+        cur[l] = x;
+        // residual into y (interior), then full weighting into R[l + 1]
+        if (tx < n && ty < n)
+            for (int z = tz; z < n; z += 4) {
+                const int c = ((z + 1) * P + ty + 1) * P + tx + 1;
+                const double cv = x[c];
+                const double faces = ((x[c - 1] + x[c + 1]) + (x[c - P] + x[c + P])) + (x[c - PP] + x[c + PP]);
+                const double exy = (x[c - P - 1] + x[c - P + 1]) + (x[c + P - 1] + x[c + P + 1]);
+                const double exz = (x[c - PP - 1] + x[c - PP + 1]) + (x[c + PP - 1] + x[c + PP + 1]);
+                const double eyz = (x[c - PP - P] + x[c - PP + P]) + (x[c + PP - P] + x[c + PP + P]);
+                const double A = ((2.0 * faces + ((exy + exz) + eyz)) - 24.0 * cv) * ih2 / 6.0;
+                const double B = 0.5 * cv + faces / 12.0;
+                y[c] = R[l][(z * n + ty) * n + tx] - (B - a * A);
+            }
+        __syncthreads();
+        if (tx < nc && ty < nc)
+            for (int z = tz; z < nc; z += 4) {
+                const double w[3] = {0.25, 0.5, 0.25};
+                double sacc = 0.0;
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++)
+                            sacc += w[dx + 1] * w[dy + 1] * w[dz + 1] *
+                                    y[((2 * z + 2 + dz) * P + (2 * ty + 2 + dy)) * P + (2 * tx + 2 + dx)];
+                R[l + 1][(z * nc + ty) * nc + tx] = sacc;
+            }
+        __syncthreads();
+    }
+    cmp_exact_dev(ns[L], R[L], X[L], a, bh, Sm, cs, true);
+    cur[L] = X[L];
+    for (int l = L - 1; l >= 0; l--) {
+        const int n = ns[l], P = n + 2, nc = ns[l + 1], Pc = nc + 2;
+        const double* ec = cur[l + 1];
+        // the corrected iterate goes where the post-sweeps end in X[l]
+        double* src = cur[l];
+        double* dst = (nu2 & 1) ? Y[l] : X[l];
+        if (tx < n && ty < n)
+            for (int z = tz; z < n; z += 4) {
+                const int i = tx, j = ty, k = z;
+                int ix0, ix1, iy0, iy1, iz0, iz1;
+                double wx0, wx1, wy0, wy1, wz0, wz1;
+                int cx, cy, cz;
+                // per axis: odd i on coarse (i-1)/2; even i between i/2-1 and i/2
+                // (padded coarse index +1; the frame supplies the zero walls)
+                if (i & 1) { ix0 = (i - 1) / 2 + 1; wx0 = 1.0; cx = 1; ix1 = ix0; wx1 = 0.0; }
+                else { ix0 = i / 2; wx0 = 0.5; ix1 = i / 2 + 1; wx1 = 0.5; cx = 2; }
+                if (j & 1) { iy0 = (j - 1) / 2 + 1; wy0 = 1.0; cy = 1; iy1 = iy0; wy1 = 0.0; }
+                else { iy0 = j / 2; wy0 = 0.5; iy1 = j / 2 + 1; wy1 = 0.5; cy = 2; }
+                if (k & 1) { iz0 = (k - 1) / 2 + 1; wz0 = 1.0; cz = 1; iz1 = iz0; wz1 = 0.0; }
+                else { iz0 = k / 2; wz0 = 0.5; iz1 = k / 2 + 1; wz1 = 0.5; cz = 2; }
+                const int IX[2] = {ix0, ix1}, IY[2] = {iy0, iy1}, IZ[2] = {iz0, iz1};
+                const double WX[2] = {wx0, wx1}, WY[2] = {wy0, wy1}, WZ[2] = {wz0, wz1};
+                double sacc = 0.0;
+                for (int c3 = 0; c3 < cz; c3++)
+                    for (int b3 = 0; b3 < cy; b3++)
+                        for (int a3 = 0; a3 < cx; a3++)
+                            sacc += WX[a3] * WY[b3] * WZ[c3] * ec[(IZ[c3] * Pc + IY[b3]) * Pc + IX[a3]];
+                const int c = ((k + 1) * P + j + 1) * P + i + 1;
+                dst[c] = src[c] + sacc;
+            }
+        __syncthreads();
+        double *x = dst, *y = (dst == X[l]) ? Y[l] : X[l];
+        for (int q = 0; q < nu2; q++) {
+            sweep(l, x, y);
+            double* w = x; x = y; y = w;
+        }
+        cur[l] = x;   // X[l]
+    }
+    {
+        const int n = n0, P = n + 2;
+        const double* x = cur[0];
+        if (tx < n && ty < n)
+            for (int z = tz; z < n; z += 4) ug[(z * n + ty) * n + tx] = x[((z + 1) * P + ty + 1) * P + tx + 1];
     }
 }
 
@@ -3132,13 +3334,18 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp_quad(int n, int M, int m, cons
     }
 }
 
-// Maxima of the norm partials of one launch (pairs |r|, |b| per block) into
-// the lane state: mg_rho = max|r| / max|b| (max|b| = 0 counts as 1) and
-// bnorm = max|b|; with sdc = 1 sdc_res = max|r| instead, with sdc = 2 the
-// larger of sdc_res and max|r|.
+// Maxima of the norm partials of one launch (pairs |r|, |b| per block).
+//   mode 0: mg_rho = max|r| / max|b| (max|b| = 0 counts as 1), bnorm = max|b|
+//   mode 1: sdc_res = max|r|;  mode 2: sdc_res = max(sdc_res, max|r|)
+//   mode 3: the stopping test of a solve before its cycle `cycle`, as mode 0
+//           and then: stop (state 1) when rho <= tol, fail (state 2) when
+//           rho is not finite (status st_nonfinite) or cycle >= max_cycles
+//           (status st_noconv); skipped once the solve has stopped
 __global__ void __launch_bounds__(HS_BLOCK) k_cmp_reduce(const double* __restrict__ partials, int nblk,
-                                                         LaneCtl* __restrict__ ctl, int lane, int sdc)
+                                                         LaneCtl* __restrict__ ctl, int lane, int mode, int cycle,
+                                                         double tol, int max_cycles, int st_noconv, int st_nonfinite)
 {
+    if (mode == 3 && ctl[lane].mg_state != 0) return;
     double r = 0.0, bb = 0.0;
     for (int q = (int)threadIdx.x; q < nblk; q += HS_BLOCK) {
         r = nmax(r, partials[2 * q]);
@@ -3147,11 +3354,23 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp_reduce(const double* __restric
     block_max2(r, bb);
     if (threadIdx.x != 0) return;
     LaneCtl& c = ctl[lane];
-    if (sdc) {
-        c.sdc_res = sdc == 1 ? r : nmax(c.sdc_res, r);
-    } else {
-        c.bnorm = bb;
-        c.mg_rho = r / (bb > 0.0 ? bb : 1.0);
+    if (mode == 1 || mode == 2) {
+        c.sdc_res = mode == 1 ? r : nmax(c.sdc_res, r);
+        return;
+    }
+    c.bnorm = bb;
+    const double rho = r / (bb > 0.0 ? bb : 1.0);
+    c.mg_rho = rho;
+    if (mode != 3) return;
+    c.mg_cycle = cycle;
+    if (rho != rho) {
+        finish_solve(c, cycle, 2, 0);
+        if (c.status == 0) c.status = st_nonfinite;
+    } else if (rho <= tol) {
+        finish_solve(c, cycle, 1, 0);
+    } else if (cycle >= max_cycles) {
+        finish_solve(c, cycle, 2, 0);
+        if (c.status == 0) c.status = st_noconv;
     }
 }
 
@@ -3631,41 +3850,94 @@ int compact_blocks(int n)
 }
 
 hipError_t compact_op(int mode, int n, const double* src, double* dst, const double* b, const double* g2,
-                      const LaneCtl* ctl, int lane, double dtau, double omega, double* partials, hipStream_t s)
+                      const LaneCtl* ctl, int lane, double dtau, double omega, double* partials, int gate,
+                      hipStream_t s)
 {
     int zb, nz;
     cmp_shape(n, &zb, &nz);
     const dim3 grid((unsigned)(tiles_x(n) * tiles_y(n) * nz));
+#define HS_CMP_LAUNCH(MD) \
+    hipLaunchKernelGGL(k_cmp<MD>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials, gate)
     switch (mode) {
-    case 0: hipLaunchKernelGGL(k_cmp<0>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
-    case 1: hipLaunchKernelGGL(k_cmp<1>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
-    case 2: hipLaunchKernelGGL(k_cmp<2>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
-    case 3: hipLaunchKernelGGL(k_cmp<3>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
-    default: hipLaunchKernelGGL(k_cmp<4>, grid, BLK, 0, s, n, zb, src, dst, b, g2, ctl, lane, dtau, omega, partials); break;
+    case 0: HS_CMP_LAUNCH(0); break;
+    case 1: HS_CMP_LAUNCH(1); break;
+    case 2: HS_CMP_LAUNCH(2); break;
+    case 3: HS_CMP_LAUNCH(3); break;
+    default: HS_CMP_LAUNCH(4); break;
     }
+#undef HS_CMP_LAUNCH
     return hipGetLastError();
 }
 
-hipError_t compact_fw(int nf, const double* rf, double* bc, hipStream_t s)
+hipError_t compact_fw(int nf, const double* rf, double* bc, const LaneCtl* ctl, int lane, int gate, hipStream_t s)
 {
     const long long nc = (nf - 1) / 2, N = nc * nc * nc;
     if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cmp_fw, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nf, rf, bc);
+    hipLaunchKernelGGL(k_cmp_fw, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nf, rf, bc, ctl, lane,
+                       gate);
     return hipGetLastError();
 }
 
-hipError_t compact_prolong(int nc, const double* ec, double* uf, hipStream_t s)
+hipError_t compact_prolong(int nc, const double* ec, const double* src, double* dst, const LaneCtl* ctl, int lane,
+                           int gate, hipStream_t s)
 {
     const long long nf = 2 * nc + 1, N = nf * nf * nf;
-    hipLaunchKernelGGL(k_cmp_prolong, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nc, ec, uf);
+    hipLaunchKernelGGL(k_cmp_prolong, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nc, ec, src, dst,
+                       ctl, lane, gate);
     return hipGetLastError();
 }
 
-hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau,
+hipError_t compact_zsweep(int n, const double* b, double* dst, const LaneCtl* ctl, int lane, double dtau,
+                          double omega, int gate, hipStream_t s)
+{
+    const long long N = (long long)n * n * n;
+    hipLaunchKernelGGL(k_cmp_zsweep, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, n, b, dst, ctl, lane,
+                       dtau, omega, gate);
+    return hipGetLastError();
+}
+
+hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau, int gate,
                          hipStream_t s)
 {
     if (n < 1 || n > 3) return hipErrorInvalidValue;   // one block of 64 threads holds n^3 <= 27
-    hipLaunchKernelGGL(k_cmp_exact, dim3(1), dim3(64), 0, s, n, b, x, ctl, lane, dtau);
+    hipLaunchKernelGGL(k_cmp_exact, dim3(1), dim3(64), 0, s, n, b, x, ctl, lane, dtau, gate);
+    return hipGetLastError();
+}
+
+size_t compact_tail_lds(int n0, int n_coarsest)
+{
+    size_t pts = 0;
+    int n = n0, l = 0;
+    for (;;) {
+        pts += 2 * (size_t)(n + 2) * (n + 2) * (n + 2) + (size_t)n * n * n;
+        if (!(n > n_coarsest && n > 1 && l + 1 < HS_MAXTAIL)) break;
+        n = (n - 1) / 2;
+        l++;
+    }
+    return 8 * pts;
+}
+
+hipError_t compact_tail(int n0, double* u, const double* b, int zero_guess, const LaneCtl* ctl, int lane, double dtau,
+                        double omega, int nu1, int nu2, int n_coarsest, int gate, hipStream_t s)
+{
+    if (n0 < 1 || n0 > HS_TAIL_N) return hipErrorInvalidValue;
+    const size_t lds = compact_tail_lds(n0, n_coarsest);
+    if (lds > 65536) {   // a 15^3 top grid needs about 104 KB; raised once per device
+        static std::mutex mu;
+        static std::map<int, size_t> allowed;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        std::lock_guard<std::mutex> lock(mu);
+        size_t& al = allowed[dev];
+        if (lds > al) {
+            e = hipFuncSetAttribute((const void*)k_cmp_tail, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            al = lds;
+        }
+    }
+    hipLaunchKernelGGL(k_cmp_tail, dim3(1), dim3(HS_TAIL_THREADS), (unsigned)lds, s, n0, u, b, zero_guess, ctl, lane,
+                       dtau, omega, nu1, nu2, n_coarsest, gate);
     return hipGetLastError();
 }
 
@@ -3678,9 +3950,11 @@ hipError_t compact_quad(int n, int M, int m, const double* G, const double* base
     return hipGetLastError();
 }
 
-hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int lane, int sdc, hipStream_t s)
+hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int lane, int mode, int cycle, double tol,
+                          int max_cycles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cmp_reduce, dim3(1), BLK, 0, s, partials, nblk, ctl, lane, sdc);
+    hipLaunchKernelGGL(k_cmp_reduce, dim3(1), BLK, 0, s, partials, nblk, ctl, lane, mode, cycle, tol, max_cycles,
+                       -3, -4);   // HS_ENOCONV, HS_ENONFINITE
     return hipGetLastError();
 }
 

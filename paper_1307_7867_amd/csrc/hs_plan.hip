@@ -231,6 +231,7 @@ struct hs_plan {
     int order[HS_MAXLEV] = {2, 2, 2}, M[HS_MAXLEV] = {3, 3, 3};
     bool compact = false;                      // the compact pair (single level); the multigrid
                                                // tables are then built for order 2 and not used
+    std::vector<int> cmp_pred;                 // compact solves: last cycle count per lane and substep
     bool mixed = false;
     size_t bytes = 0;
     char* ws = nullptr;
@@ -1541,68 +1542,86 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
 // ---------------------------------------------------------------------------
 
 // One V(nu1, nu2) cycle on grid l of lane `lane`'s hierarchy: u, b its iterate
-// and right-hand side, t a scratch grid of the same size.
-hs_status cmp_vcycle(hs_plan* P, int lane, int l, double* u, const double* b, double* t, double dtau, hipStream_t s)
+// and right-hand side (u taken as zero with `zero`), t a scratch grid of the
+// same size.  Grids with n <= HS_TAIL_N run as one LDS-resident workgroup.
+hs_status cmp_vcycle(hs_plan* P, int lane, int l, double* u, const double* b, double* t, double dtau, bool zero,
+                     int gate, hipStream_t s)
 {
     const hs_mg_desc& mg = P->pb.mg;
     const LaneBufs& lb = P->lanes[lane];
     const int n = lb.grids[0][l];
-    if (n <= mg.n_coarsest || l + 1 >= (int)lb.grids[0].size()) {
-        HS_TRY(hsk::compact_exact(n, b, u, P->ctl, lane, dtau, s));
+    if (n <= HS_TAIL_N) {
+        HS_TRY(hsk::compact_tail(n, u, b, zero ? 1 : 0, P->ctl, lane, dtau, mg.omega, mg.nu1, mg.nu2, mg.n_coarsest,
+                                 gate, s));
         return HS_OK;
     }
-    auto smooth = [&](int k) -> hs_status {
-        double *x = u, *y = t;
-        for (int q = 0; q < k; q++) {
-            HS_TRY(hsk::compact_op(0, n, x, y, b, nullptr, P->ctl, lane, dtau, mg.omega, nullptr, s));
-            std::swap(x, y);
-        }
-        if (x != u) HS_TRY(hipMemcpyAsync(u, x, cube(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
-        return HS_OK;
-    };
-    HS_CHECK(smooth(mg.nu1));
-    HS_TRY(hsk::compact_op(1, n, u, t, b, nullptr, P->ctl, lane, dtau, 0.0, nullptr, s));
+    // the iterate moves between u and t; the prolongation writes it where the
+    // post-sweeps end in u (no copies), and a zero iterate's first sweep reads
+    // only b (no clearing)
+    double *cur = u, *oth = t;
+    for (int q = 0; q < mg.nu1; q++) {
+        if (q == 0 && zero) HS_TRY(hsk::compact_zsweep(n, b, oth, P->ctl, lane, dtau, mg.omega, gate, s));
+        else HS_TRY(hsk::compact_op(0, n, cur, oth, b, nullptr, P->ctl, lane, dtau, mg.omega, nullptr, gate, s));
+        std::swap(cur, oth);
+    }
+    HS_TRY(hsk::compact_op(1, n, cur, oth, b, nullptr, P->ctl, lane, dtau, 0.0, nullptr, gate, s));
     const int nc = lb.grids[0][l + 1];
     double *cu = lb.gu[0][l + 1], *ct = lb.gt[0][l + 1], *cb = lb.gb[0][l + 1];
-    HS_TRY(hsk::compact_fw(n, t, cb, s));
-    HS_TRY(hipMemsetAsync(cu, 0, cube(nc) * sizeof(double), s));
-    HS_CHECK(cmp_vcycle(P, lane, l + 1, cu, cb, ct, dtau, s));
-    HS_TRY(hsk::compact_prolong(nc, cu, u, s));
-    HS_CHECK(smooth(mg.nu2));
+    HS_TRY(hsk::compact_fw(n, oth, cb, P->ctl, lane, gate, s));
+    HS_CHECK(cmp_vcycle(P, lane, l + 1, cu, cb, ct, dtau, true, gate, s));
+    double* dst = (mg.nu2 & 1) ? t : u;
+    HS_TRY(hsk::compact_prolong(nc, cu, cur, dst, P->ctl, lane, gate, s));
+    cur = dst;
+    oth = dst == u ? t : u;
+    for (int q = 0; q < mg.nu2; q++) {
+        HS_TRY(hsk::compact_op(0, n, cur, oth, b, nullptr, P->ctl, lane, dtau, mg.omega, nullptr, gate, s));
+        std::swap(cur, oth);
+    }
     return HS_OK;
 }
 
-// Solve (B - a A) u = b on the lane's finest grid from the guess in u, a = nu dt dtau.
-hs_status cmp_solve(hs_plan* P, int lane, double dtau, double* u, const double* b, hipStream_t s)
+// Solve (B - a A) u = b on the lane's finest grid from the guess in u,
+// a = nu dt dtau (substep m).  Fixed cycles: the cycles, then the residual
+// norm.  Tolerance mode: before each cycle the norm and the stopping test run
+// on the device and the cycles after a stop are skipped there; the host reads
+// the lane state at the cycle count of the lane's last solve of this substep,
+// then after every cycle.
+hs_status cmp_solve(hs_plan* P, int lane, int m, double dtau, double* u, const double* b, hipStream_t s)
 {
     const hs_mg_desc& mg = P->pb.mg;
     const LaneBufs& lb = P->lanes[lane];
-    const int n = lb.n[0];
+    const int n = lb.n[0], nb = hsk::compact_blocks(n);
     const Issuer I = issuer(P, s);
-    double rho = 0.0;
-    auto norm = [&]() -> hs_status {
-        HS_TRY(hsk::compact_op(4, n, u, nullptr, b, nullptr, P->ctl, lane, dtau, 0.0, I.partials, s));
-        HS_TRY(hsk::compact_reduce(I.partials, hsk::compact_blocks(n), P->ctl, lane, 0, s));
-        HS_CHECK(read_ctl(P, s, &P->run));
-        rho = I.h_ctl[lane].mg_rho;
-        return HS_OK;
-    };
-    int c = 0, state = 1, status = HS_OK;
+    HS_TRY(hsk::begin_solve(P->ctl, lane, 1, s));
     if (mg.fixed_cycles > 0) {
-        for (c = 0; c < mg.fixed_cycles; c++) HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, s));
-        HS_CHECK(norm());
-        if (rho != rho) { state = 2; status = HS_ENONFINITE; }
-    } else {
-        for (c = 0;; c++) {
-            HS_CHECK(norm());
-            if (rho != rho) { state = 2; status = HS_ENONFINITE; break; }
-            if (rho <= mg.tol) break;
-            if (c >= mg.max_cycles) { state = 2; status = HS_ENOCONV; break; }
-            HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, s));
-        }
+        for (int c = 0; c < mg.fixed_cycles; c++)
+            HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, false, 0, s));
+        HS_TRY(hsk::compact_op(4, n, u, nullptr, b, nullptr, P->ctl, lane, dtau, 0.0, I.partials, 0, s));
+        HS_TRY(hsk::compact_reduce(I.partials, nb, P->ctl, lane, 0, 0, 0.0, 0, s));
+        HS_CHECK(read_ctl(P, s, &P->run));
+        const double rho = I.h_ctl[lane].mg_rho;
+        const bool bad = rho != rho;
+        HS_TRY(hsk::compact_ctl(P->ctl, lane, 0, mg.fixed_cycles, bad ? 2 : 1, 0, bad ? HS_ENONFINITE : HS_OK, s));
+        return HS_OK;
     }
-    HS_TRY(hsk::compact_ctl(P->ctl, lane, 0, c, state, 0, status, s));
-    return HS_OK;
+    if (P->cmp_pred.size() != (size_t)P->B * HS_MAXM) P->cmp_pred.assign((size_t)P->B * HS_MAXM, 1);
+    int& pred = P->cmp_pred[(size_t)lane * HS_MAXM + m];
+    int next = pred;
+    for (int c = 0;; c++) {
+        HS_TRY(hsk::compact_op(4, n, u, nullptr, b, nullptr, P->ctl, lane, dtau, 0.0, I.partials, 1, s));
+        HS_TRY(hsk::compact_reduce(I.partials, nb, P->ctl, lane, 3, c, mg.tol, mg.max_cycles, s));
+        if (c >= next || c >= mg.max_cycles) {
+            HS_CHECK(read_ctl(P, s, &P->run));
+            const LaneCtl& h = I.h_ctl[lane];
+            if (h.mg_state != 0) {
+                pred = std::max(1, h.mg_cycle);
+                return HS_OK;
+            }
+            if (c >= mg.max_cycles) return HS_EDEVICE;   // the test at max_cycles always stops the solve
+            next = c + 1;
+        }
+        HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, false, 1, s));
+    }
 }
 
 // Collocation residual of the B-weighted form,
@@ -1618,8 +1637,8 @@ hs_status cmp_residual(hs_plan* P, int lane, hipStream_t s, double* R)
     for (int m = 1; m < M; m++) {
         HS_TRY(hsk::compact_quad(n, M, m, lb.FI[0], lb.tmp[0], lb.rhs[0], lb.sig[0], P->ctl, lane, 0, s));
         HS_TRY(hsk::compact_op(4, n, lb.U[0] + m * N, nullptr, lb.rhs[0], nullptr, P->ctl, lane, 0.0, 0.0,
-                               I.partials, s));
-        HS_TRY(hsk::compact_reduce(I.partials, hsk::compact_blocks(n), P->ctl, lane, m == 1 ? 1 : 2, s));
+                               I.partials, 0, s));
+        HS_TRY(hsk::compact_reduce(I.partials, hsk::compact_blocks(n), P->ctl, lane, m == 1 ? 1 : 2, 0, 0.0, 0, s));
     }
     HS_CHECK(read_ctl(P, s, &P->run));
     *R = I.h_ctl[lane].sdc_res;
@@ -1640,10 +1659,10 @@ hs_status cmp_sweep(hs_plan* P, int lane, hipStream_t s)
     HS_TRY(hsk::compact_quad(n, M, -1, G, nullptr, lb.P[0], lb.sig[0], P->ctl, lane, 0, s));
     for (int m = 0; m + 1 < M; m++) {
         HS_TRY(hsk::compact_op(2, n, U + m * N, lb.rhs[0], lb.P[0] + m * N, G + (m + 1) * N, P->ctl, lane,
-                               K.dtau[m], 0.0, nullptr, s));
-        HS_CHECK(cmp_solve(P, lane, K.dtau[m], U + (m + 1) * N, lb.rhs[0], s));
+                               K.dtau[m], 0.0, nullptr, 0, s));
+        HS_CHECK(cmp_solve(P, lane, m, K.dtau[m], U + (m + 1) * N, lb.rhs[0], s));
         HS_TRY(hsk::compact_op(3, n, U + (m + 1) * N, G + (m + 1) * N, nullptr, nullptr, P->ctl, lane, 0.0, 0.0,
-                               nullptr, s));
+                               nullptr, 0, s));
     }
     return HS_OK;
 }
@@ -1671,7 +1690,7 @@ hs_status cmp_begin_step(hs_plan* P, hipStream_t s)
         const long long N = lb.N[0];
         double *U = lb.U[0], *G = lb.FI[0];
         HS_TRY(hsk::compact_op(3, lb.n[0], U + (M - 1) * N, G + (M - 1) * N, nullptr, nullptr, P->ctl, b, 0.0, 0.0,
-                               nullptr, s));
+                               nullptr, 0, s));
         for (int m = 0; m + 1 < M; m++) {
             HS_TRY(hipMemcpyAsync(U + m * N, U + (M - 1) * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
             HS_TRY(hipMemcpyAsync(G + m * N, G + (M - 1) * N, N * sizeof(double), hipMemcpyDeviceToDevice, s));
