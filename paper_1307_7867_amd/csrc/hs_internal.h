@@ -315,7 +315,8 @@ hipError_t compact_apply(int n, int batch, double alpha, double beta, const doub
 // single-level SDC with the compact pair, one lane per launch; gate: skip
 // the launch once the lane's solve has stopped
 int compact_blocks(int n);
-// mode 0 Jacobi, 1 residual, 2 substep rhs, 3 nu A, 4 norm partials (see k_cmp)
+// mode 0 Jacobi, 1 residual, 2 substep rhs, 3 nu A, 4 norm partials, 5 Jacobi with
+// the norm partials (see k_cmp)
 hipError_t compact_op(int mode, int n, const double* src, double* dst, const double* b, const double* g2,
                       const LaneCtl* ctl, int lane, double dtau, double omega, double* partials, int gate,
                       hipStream_t s);

@@ -2877,13 +2877,37 @@ __global__ void __launch_bounds__(HS_BLOCK) k_heat_rhs(const GridSeg* __restrict
 // LDS planes and loads plane z + 2 into the fourth while plane z is formed:
 // one barrier per plane.
 // ---------------------------------------------------------------------------
+// trilinear prolongation of ec (zero walls) at fine point (i, j, k)
+__device__ __forceinline__ double cmp_prolong_at(const double* ec, int nc, int i, int j, int k)
+{
+    int ix[2], iy[2], iz[2];
+    double wx[2], wy[2], wz[2];
+    int cx, cy, cz;
+    auto wts = [](int f, int* idx, double* wt, int* cnt) {
+        if (f & 1) { idx[0] = (f - 1) >> 1; wt[0] = 1.0; *cnt = 1; }
+        else { idx[0] = (f >> 1) - 1; wt[0] = 0.5; idx[1] = f >> 1; wt[1] = 0.5; *cnt = 2; }
+    };
+    wts(i, ix, wx, &cx);
+    wts(j, iy, wy, &cy);
+    wts(k, iz, wz, &cz);
+    double s = 0.0;
+    for (int c = 0; c < cz; c++)
+        for (int b = 0; b < cy; b++)
+            for (int a = 0; a < cx; a++) {
+                const int I = ix[a], J = iy[b], K = iz[c];
+                if (I < 0 || I >= nc || J < 0 || J >= nc || K < 0 || K >= nc) continue;
+                s += wx[a] * wy[b] * wz[c] * ec[((long long)K * nc + J) * nc + I];
+            }
+    return s;
+}
+
 struct CmpTile {
     static constexpr int LW = HS_TX + 2, LH = HS_TY + 2;
     static constexpr int NH = LW * LH - HS_TX * HS_TY;   // halo cells per plane (148)
 };
 
-// op(p, c, faces, edges) at every grid point of planes z0..z1-1 of the
-// column tile at (i0, j0); all threads of the block must call it
+// op(p, c, A, B) at every grid point of planes z0..z1-1 of the column tile
+// at (i0, j0); all threads of the block must call it
 template <class Op>
 __device__ __forceinline__ void cmp_march(const HS_G double* __restrict__ u, int n, int i0, int j0, int z0,
                                           int z1, double (*ring)[CmpTile::LH][CmpTile::LW], Op& op)
@@ -2968,6 +2992,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_compact_apply(int n, int zb, int n
 //   2  substep rhs      dst = (B c - dt_m g2) + b   (b: dt S_m F, g2: nu A U_{m+1})
 //   3  implicit part    dst = nu A c
 //   4  norms            per-block maxima of |b - (B - a A) c| and |b| into partials
+//   5  Jacobi as 0 with the norms of 4 (of the iterate before the sweep)
 // with dt_m = dt dtau (dtau = tau_{m+1} - tau_m of the substep, 0 for B alone)
 // and a = nu dt_m, dt and nu of the lane.  With gate set the launch does
 // nothing once the lane's solve has stopped (mg_state != 0).
@@ -2996,6 +3021,12 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp(int n, int zb, const double* _
         __device__ __forceinline__ void operator()(long long p, double cv, double A, double B)
         {
             if (MODE == 0) dst[p] = cv + omega * (b[p] - (B - a * A)) / D;
+            else if (MODE == 5) {
+                const double bp = b[p], r = bp - (B - a * A);
+                dst[p] = cv + omega * r / D;
+                rmax = nmax(rmax, fabs(r));
+                bmax = nmax(bmax, fabs(bp));
+            }
             else if (MODE == 1) dst[p] = b[p] - (B - a * A);
             else if (MODE == 2) dst[p] = (B - dtm * g2[p]) + b[p];
             else if (MODE == 3) dst[p] = nu * A;
@@ -3008,7 +3039,7 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp(int n, int zb, const double* _
     } op{(HS_G double*)dst, (const HS_G double*)b, (const HS_G double*)g2, a, D, omega, c.nu, dtm, 0.0, 0.0};
     __shared__ double ring[4][CmpTile::LH][CmpTile::LW];
     cmp_march((const HS_G double*)src, n, i0, j0, z0, z1, ring, op);
-    if (MODE == 4) {
+    if (MODE == 4 || MODE == 5) {
         double r = op.rmax, bb = op.bmax;
         block_max2(r, bb);
         if (threadIdx.x == 0) {
@@ -3029,30 +3060,6 @@ __device__ __forceinline__ double cmp_fw_at(const double* rf, int nf, int I, int
             for (int dx = -1; dx <= 1; dx++) {
                 const int i = 2 * I + 1 + dx, j = 2 * J + 1 + dy, k = 2 * K + 1 + dz;
                 s += w[dx + 1] * w[dy + 1] * w[dz + 1] * rf[((long long)k * nf + j) * nf + i];
-            }
-    return s;
-}
-
-// trilinear prolongation of ec (zero walls) at fine point (i, j, k)
-__device__ __forceinline__ double cmp_prolong_at(const double* ec, int nc, int i, int j, int k)
-{
-    int ix[2], iy[2], iz[2];
-    double wx[2], wy[2], wz[2];
-    int cx, cy, cz;
-    auto wts = [](int f, int* idx, double* wt, int* cnt) {
-        if (f & 1) { idx[0] = (f - 1) >> 1; wt[0] = 1.0; *cnt = 1; }
-        else { idx[0] = (f >> 1) - 1; wt[0] = 0.5; idx[1] = f >> 1; wt[1] = 0.5; *cnt = 2; }
-    };
-    wts(i, ix, wx, &cx);
-    wts(j, iy, wy, &cy);
-    wts(k, iz, wz, &cz);
-    double s = 0.0;
-    for (int c = 0; c < cz; c++)
-        for (int b = 0; b < cy; b++)
-            for (int a = 0; a < cx; a++) {
-                const int I = ix[a], J = iy[b], K = iz[c];
-                if (I < 0 || I >= nc || J < 0 || J >= nc || K < 0 || K >= nc) continue;
-                s += wx[a] * wy[b] * wz[c] * ec[((long long)K * nc + J) * nc + I];
             }
     return s;
 }
@@ -3093,27 +3100,32 @@ __device__ void cmp_exact_dev(int n, const double* b, double* x, double a, doubl
     __syncthreads();
 }
 
+// grid: x over the points of one coarse plane, y the plane (32-bit index math)
 __global__ void __launch_bounds__(HS_BLOCK) k_cmp_fw(int nf, const double* __restrict__ rf, double* __restrict__ bc,
                                                      const LaneCtl* __restrict__ ctl, int lane, int gate)
 {
     if (gate && ctl[lane].mg_state != 0) return;
     const int nc = (nf - 1) / 2;
-    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
-    if (q >= (long long)nc * nc * nc) return;
-    bc[q] = cmp_fw_at(rf, nf, (int)(q % nc), (int)((q / nc) % nc), (int)(q / ((long long)nc * nc)));
+    const int q = (int)(blockIdx.x * HS_BLOCK + threadIdx.x), K = (int)blockIdx.y;
+    if (q >= nc * nc) return;
+    const int J = q / nc, I = q - J * nc;
+    bc[((long long)K * nc + J) * nc + I] = cmp_fw_at(rf, nf, I, J, K);
 }
 
 // dst = src + trilinear prolongation of ec, one thread per fine point (dst
-// may be src: the correction added in place)
+// may be src: the correction added in place); grid: x over the points of
+// one fine plane, y the plane
 __global__ void __launch_bounds__(HS_BLOCK) k_cmp_prolong(int nc, const double* __restrict__ ec, const double* src,
                                                           double* dst, const LaneCtl* __restrict__ ctl, int lane,
                                                           int gate)
 {
     if (gate && ctl[lane].mg_state != 0) return;
     const int nf = 2 * nc + 1;
-    const long long q = (long long)blockIdx.x * HS_BLOCK + threadIdx.x;
-    if (q >= (long long)nf * nf * nf) return;
-    dst[q] = src[q] + cmp_prolong_at(ec, nc, (int)(q % nf), (int)((q / nf) % nf), (int)(q / ((long long)nf * nf)));
+    const int q = (int)(blockIdx.x * HS_BLOCK + threadIdx.x), k = (int)blockIdx.y;
+    if (q >= nf * nf) return;
+    const int j = q / nf, i = q - j * nf;
+    const long long p = ((long long)k * nf + j) * nf + i;
+    dst[p] = src[p] + cmp_prolong_at(ec, nc, i, j, k);
 }
 
 // the first Jacobi sweep from a zero iterate: dst = omega b / D (the residual
@@ -3863,7 +3875,8 @@ hipError_t compact_op(int mode, int n, const double* src, double* dst, const dou
     case 1: HS_CMP_LAUNCH(1); break;
     case 2: HS_CMP_LAUNCH(2); break;
     case 3: HS_CMP_LAUNCH(3); break;
-    default: HS_CMP_LAUNCH(4); break;
+    case 4: HS_CMP_LAUNCH(4); break;
+    default: HS_CMP_LAUNCH(5); break;
     }
 #undef HS_CMP_LAUNCH
     return hipGetLastError();
@@ -3871,19 +3884,19 @@ hipError_t compact_op(int mode, int n, const double* src, double* dst, const dou
 
 hipError_t compact_fw(int nf, const double* rf, double* bc, const LaneCtl* ctl, int lane, int gate, hipStream_t s)
 {
-    const long long nc = (nf - 1) / 2, N = nc * nc * nc;
-    if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cmp_fw, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nf, rf, bc, ctl, lane,
-                       gate);
+    const int nc = (nf - 1) / 2;
+    if (nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cmp_fw, dim3((unsigned)((nc * nc + HS_BLOCK - 1) / HS_BLOCK), (unsigned)nc), BLK, 0, s, nf,
+                       rf, bc, ctl, lane, gate);
     return hipGetLastError();
 }
 
 hipError_t compact_prolong(int nc, const double* ec, const double* src, double* dst, const LaneCtl* ctl, int lane,
                            int gate, hipStream_t s)
 {
-    const long long nf = 2 * nc + 1, N = nf * nf * nf;
-    hipLaunchKernelGGL(k_cmp_prolong, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, nc, ec, src, dst,
-                       ctl, lane, gate);
+    const int nf = 2 * nc + 1;
+    hipLaunchKernelGGL(k_cmp_prolong, dim3((unsigned)((nf * nf + HS_BLOCK - 1) / HS_BLOCK), (unsigned)nf), BLK, 0, s,
+                       nc, ec, src, dst, ctl, lane, gate);
     return hipGetLastError();
 }
 

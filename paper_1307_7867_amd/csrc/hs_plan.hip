@@ -1541,61 +1541,80 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
 // back to stop it (the same rule as the second-order/fourth-order solves).
 // ---------------------------------------------------------------------------
 
-// One V(nu1, nu2) cycle on grid l of lane `lane`'s hierarchy: u, b its iterate
-// and right-hand side (u taken as zero with `zero`), t a scratch grid of the
-// same size.  Grids with n <= HS_TAIL_N run as one LDS-resident workgroup.
-hs_status cmp_vcycle(hs_plan* P, int lane, int l, double* u, const double* b, double* t, double dtau, bool zero,
-                     int gate, hipStream_t s)
+// One V(nu1, nu2) cycle on grid l of lane `lane`'s hierarchy: the iterate in
+// cur (taken as zero with `zero`), oth a scratch grid of the same size, b the
+// right-hand side; *res receives the buffer (cur or oth) that holds the
+// iterate after the cycle.  The sweeps ping-pong between the two buffers and
+// the coarse correction is added in place.
+// With `cycle` >= 0 the first pre-sweep also takes the residual norms of the
+// incoming iterate and the stopping test before that cycle runs on the
+// device (the rest of the cycle is gated off when the solve stops there).
+// Grids with n <= HS_TAIL_N run as one LDS-resident workgroup, in place.
+hs_status cmp_vcycle(hs_plan* P, int lane, int l, double* cur, double* oth, const double* b, double dtau, bool zero,
+                     int gate, int cycle, hipStream_t s, double** res)
 {
     const hs_mg_desc& mg = P->pb.mg;
     const LaneBufs& lb = P->lanes[lane];
     const int n = lb.grids[0][l];
     if (n <= HS_TAIL_N) {
-        HS_TRY(hsk::compact_tail(n, u, b, zero ? 1 : 0, P->ctl, lane, dtau, mg.omega, mg.nu1, mg.nu2, mg.n_coarsest,
-                                 gate, s));
+        HS_TRY(hsk::compact_tail(n, cur, b, zero ? 1 : 0, P->ctl, lane, dtau, mg.omega, mg.nu1, mg.nu2,
+                                 mg.n_coarsest, gate, s));
+        *res = cur;
         return HS_OK;
     }
-    // the iterate moves between u and t; the prolongation writes it where the
-    // post-sweeps end in u (no copies), and a zero iterate's first sweep reads
-    // only b (no clearing)
-    double *cur = u, *oth = t;
+    double* const part = issuer(P, s).partials;
     for (int q = 0; q < mg.nu1; q++) {
-        if (q == 0 && zero) HS_TRY(hsk::compact_zsweep(n, b, oth, P->ctl, lane, dtau, mg.omega, gate, s));
-        else HS_TRY(hsk::compact_op(0, n, cur, oth, b, nullptr, P->ctl, lane, dtau, mg.omega, nullptr, gate, s));
+        if (q == 0 && zero) {
+            HS_TRY(hsk::compact_zsweep(n, b, oth, P->ctl, lane, dtau, mg.omega, gate, s));
+        } else if (q == 0 && cycle >= 0) {
+            HS_TRY(hsk::compact_op(5, n, cur, oth, b, nullptr, P->ctl, lane, dtau, mg.omega, part, gate, s));
+            HS_TRY(hsk::compact_reduce(part, hsk::compact_blocks(n), P->ctl, lane, 3, cycle, mg.tol, mg.max_cycles, s));
+        } else {
+            HS_TRY(hsk::compact_op(0, n, cur, oth, b, nullptr, P->ctl, lane, dtau, mg.omega, nullptr, gate, s));
+        }
         std::swap(cur, oth);
     }
     HS_TRY(hsk::compact_op(1, n, cur, oth, b, nullptr, P->ctl, lane, dtau, 0.0, nullptr, gate, s));
     const int nc = lb.grids[0][l + 1];
-    double *cu = lb.gu[0][l + 1], *ct = lb.gt[0][l + 1], *cb = lb.gb[0][l + 1];
+    double* cb = lb.gb[0][l + 1];
     HS_TRY(hsk::compact_fw(n, oth, cb, P->ctl, lane, gate, s));
-    HS_CHECK(cmp_vcycle(P, lane, l + 1, cu, cb, ct, dtau, true, gate, s));
-    double* dst = (mg.nu2 & 1) ? t : u;
-    HS_TRY(hsk::compact_prolong(nc, cu, cur, dst, P->ctl, lane, gate, s));
-    cur = dst;
-    oth = dst == u ? t : u;
+    double* ec = nullptr;
+    HS_CHECK(cmp_vcycle(P, lane, l + 1, lb.gu[0][l + 1], lb.gt[0][l + 1], cb, dtau, true, gate, -1, s, &ec));
+    HS_TRY(hsk::compact_prolong(nc, ec, cur, cur, P->ctl, lane, gate, s));
     for (int q = 0; q < mg.nu2; q++) {
         HS_TRY(hsk::compact_op(0, n, cur, oth, b, nullptr, P->ctl, lane, dtau, mg.omega, nullptr, gate, s));
         std::swap(cur, oth);
     }
+    *res = cur;
     return HS_OK;
 }
 
 // Solve (B - a A) u = b on the lane's finest grid from the guess in u,
 // a = nu dt dtau (substep m).  Fixed cycles: the cycles, then the residual
-// norm.  Tolerance mode: before each cycle the norm and the stopping test run
-// on the device and the cycles after a stop are skipped there; the host reads
-// the lane state at the cycle count of the lane's last solve of this substep,
-// then after every cycle.
+// norm.  Tolerance mode: the norm and the stopping test before each cycle run
+// on the device (fused with the cycle's first sweep) and the cycles after a
+// stop are skipped there; the host reads the lane state at the cycle count of
+// the lane's last solve of this substep, then after every cycle.  The
+// iterate moves between u and the lane's scratch grid; the final one is
+// copied back to u if it ends in the scratch grid.
 hs_status cmp_solve(hs_plan* P, int lane, int m, double dtau, double* u, const double* b, hipStream_t s)
 {
     const hs_mg_desc& mg = P->pb.mg;
     const LaneBufs& lb = P->lanes[lane];
     const int n = lb.n[0], nb = hsk::compact_blocks(n);
+    const long long N = lb.N[0];
     const Issuer I = issuer(P, s);
+    const bool tail = n <= HS_TAIL_N;   // the whole hierarchy in one workgroup, in place in u
     HS_TRY(hsk::begin_solve(P->ctl, lane, 1, s));
+    double *cur = u, *oth = lb.tmp[0];
     if (mg.fixed_cycles > 0) {
-        for (int c = 0; c < mg.fixed_cycles; c++)
-            HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, false, 0, s));
+        for (int c = 0; c < mg.fixed_cycles; c++) {
+            double* r = nullptr;
+            HS_CHECK(cmp_vcycle(P, lane, 0, cur, oth, b, dtau, false, 0, -1, s, &r));
+            oth = r == cur ? oth : cur;
+            cur = r;
+        }
+        if (cur != u) HS_TRY(hipMemcpyAsync(u, cur, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         HS_TRY(hsk::compact_op(4, n, u, nullptr, b, nullptr, P->ctl, lane, dtau, 0.0, I.partials, 0, s));
         HS_TRY(hsk::compact_reduce(I.partials, nb, P->ctl, lane, 0, 0, 0.0, 0, s));
         HS_CHECK(read_ctl(P, s, &P->run));
@@ -1607,20 +1626,31 @@ hs_status cmp_solve(hs_plan* P, int lane, int m, double dtau, double* u, const d
     if (P->cmp_pred.size() != (size_t)P->B * HS_MAXM) P->cmp_pred.assign((size_t)P->B * HS_MAXM, 1);
     int& pred = P->cmp_pred[(size_t)lane * HS_MAXM + m];
     int next = pred;
+    std::vector<double*> at{cur};   // at[c]: the buffer holding the iterate before cycle c
     for (int c = 0;; c++) {
-        HS_TRY(hsk::compact_op(4, n, u, nullptr, b, nullptr, P->ctl, lane, dtau, 0.0, I.partials, 1, s));
-        HS_TRY(hsk::compact_reduce(I.partials, nb, P->ctl, lane, 3, c, mg.tol, mg.max_cycles, s));
+        if (tail) {
+            HS_TRY(hsk::compact_op(4, n, cur, nullptr, b, nullptr, P->ctl, lane, dtau, 0.0, I.partials, 1, s));
+            HS_TRY(hsk::compact_reduce(I.partials, nb, P->ctl, lane, 3, c, mg.tol, mg.max_cycles, s));
+        }
+        // cycle c (its first sweep decides first when the hierarchy is not all tail)
+        double* r = nullptr;
+        HS_CHECK(cmp_vcycle(P, lane, 0, cur, oth, b, dtau, false, 1, tail ? -1 : c, s, &r));
+        oth = r == cur ? oth : cur;
+        cur = r;
+        at.push_back(cur);
         if (c >= next || c >= mg.max_cycles) {
             HS_CHECK(read_ctl(P, s, &P->run));
             const LaneCtl& h = I.h_ctl[lane];
             if (h.mg_state != 0) {
-                pred = std::max(1, h.mg_cycle);
+                const int k = h.mg_cycle;
+                if (k < 0 || k > c) return HS_EDEVICE;
+                if (at[k] != u) HS_TRY(hipMemcpyAsync(u, at[k], N * sizeof(double), hipMemcpyDeviceToDevice, s));
+                pred = std::max(1, k);
                 return HS_OK;
             }
             if (c >= mg.max_cycles) return HS_EDEVICE;   // the test at max_cycles always stops the solve
             next = c + 1;
         }
-        HS_CHECK(cmp_vcycle(P, lane, 0, u, b, lb.tmp[0], dtau, false, 1, s));
     }
 }
 
