@@ -3171,87 +3171,92 @@ __global__ void __launch_bounds__(HS_TAIL_THREADS) k_cmp_tail(int n0, double* __
     const int tid = (int)threadIdx.x;
     const int tx = tid & 15, ty = (tid >> 4) & 15, tz = tid >> 8;
     const double a = ctl[lane].nu * (ctl[lane].dt * dtau);
-    int ns[HS_MAXTAIL];
+    // grids n_l = n0 >> l (n0 = 2^k - 1) down to the first with n <= n_coarsest
+    // or n = 1; no arrays indexed at run time (they would live in scratch)
     int L = 0;
-    ns[0] = n0;
-    while (ns[L] > n_coarsest && ns[L] > 1 && L + 1 < HS_MAXTAIL) {
-        ns[L + 1] = (ns[L] - 1) / 2;
-        L++;
-    }
-    // per level: X, Y (padded iterates, ping-pong), R (right-hand side)
-    double *X[HS_MAXTAIL], *Y[HS_MAXTAIL], *R[HS_MAXTAIL];
-    int total = 0;
-    {
-        double* q = lds;
-        for (int l = 0; l <= L; l++) {
-            const int P = ns[l] + 2, NP = P * P * P, N = ns[l] * ns[l] * ns[l];
-            X[l] = q; Y[l] = q + NP; R[l] = q + 2 * NP;
-            q += 2 * NP + N;
-            total += 2 * NP + N;
+    while ((n0 >> L) > n_coarsest && (n0 >> L) > 1 && L + 1 < HS_MAXTAIL) L++;
+    // level l's fields: X (padded iterate), Y (its ping-pong partner), R (rhs)
+    auto base = [&](int l) -> double* {
+        int o = 0;
+        for (int j = 0; j < l; j++) {
+            const int n = n0 >> j, P = n + 2;
+            o += 2 * P * P * P + n * n * n;
         }
+        return lds + o;
+    };
+    auto fieldX = [&](int l) -> double* { return base(l); };
+    auto fieldY = [&](int l) -> double* { const int P = (n0 >> l) + 2; return base(l) + P * P * P; };
+    auto fieldR = [&](int l) -> double* { const int P = (n0 >> l) + 2; return base(l) + 2 * P * P * P; };
+    {
+        double* end = fieldR(L) + (n0 >> L) * (n0 >> L) * (n0 >> L);
+        const int total = (int)(end - lds);
+        for (int p = tid; p < total; p += HS_TAIL_THREADS) lds[p] = 0.0;
     }
-    for (int p = tid; p < total; p += HS_TAIL_THREADS) lds[p] = 0.0;
     __syncthreads();
     {
         const int n = n0, P = n + 2;
+        double *X0 = fieldX(0), *R0 = fieldR(0);
         if (tx < n && ty < n)
             for (int z = tz; z < n; z += 4) {
                 const int g = (z * n + ty) * n + tx;
-                if (!zero_guess) X[0][((z + 1) * P + ty + 1) * P + tx + 1] = ug[g];
-                R[0][g] = bg[g];
+                if (!zero_guess) X0[((z + 1) * P + ty + 1) * P + tx + 1] = ug[g];
+                R0[g] = bg[g];
             }
     }
     __syncthreads();
+    // the 19-point pair at padded cell c of x (the same sums as cmp_march)
+    auto pairAB = [](const double* x, int c, int P, double ih2, double* A, double* B) {
+        const int PP = P * P;
+        const double cv = x[c];
+        const double faces = ((x[c - 1] + x[c + 1]) + (x[c - P] + x[c + P])) + (x[c - PP] + x[c + PP]);
+        const double exy = (x[c - P - 1] + x[c - P + 1]) + (x[c + P - 1] + x[c + P + 1]);
+        const double exz = (x[c - PP - 1] + x[c - PP + 1]) + (x[c + PP - 1] + x[c + PP + 1]);
+        const double eyz = (x[c - PP - P] + x[c - PP + P]) + (x[c + PP - P] + x[c + PP + P]);
+        *A = ((2.0 * faces + ((exy + exz) + eyz)) - 24.0 * cv) * ih2 / 6.0;
+        *B = 0.5 * cv + faces / 12.0;
+    };
     // one Jacobi sweep x -> y on level l (x null: from zero)
     auto sweep = [&](int l, const double* x, double* y) {
-        const int n = ns[l], P = n + 2, PP = P * P;
+        const int n = n0 >> l, P = n + 2;
         const double ih2 = (double)(n + 1) * (double)(n + 1);
         const double D = 0.5 + a * 24.0 * ih2 / 6.0;
+        const double* R = fieldR(l);
         if (tx < n && ty < n)
             for (int z = tz; z < n; z += 4) {
                 const int c = ((z + 1) * P + ty + 1) * P + tx + 1;
-                const double bv = R[l][(z * n + ty) * n + tx];
+                const double bv = R[(z * n + ty) * n + tx];
                 if (!x) {
                     y[c] = omega * bv / D;
-                    continue;
+                } else {
+                    double A, B;
+                    pairAB(x, c, P, ih2, &A, &B);
+                    y[c] = x[c] + omega * (bv - (B - a * A)) / D;
                 }
-                const double cv = x[c];
-                const double faces = ((x[c - 1] + x[c + 1]) + (x[c - P] + x[c + P])) + (x[c - PP] + x[c + PP]);
-                const double exy = (x[c - P - 1] + x[c - P + 1]) + (x[c + P - 1] + x[c + P + 1]);
-                const double exz = (x[c - PP - 1] + x[c - PP + 1]) + (x[c + PP - 1] + x[c + PP + 1]);
-                const double eyz = (x[c - PP - P] + x[c - PP + P]) + (x[c + PP - P] + x[c + PP + P]);
-                const double A = ((2.0 * faces + ((exy + exz) + eyz)) - 24.0 * cv) * ih2 / 6.0;
-                const double B = 0.5 * cv + faces / 12.0;
-                y[c] = cv + omega * (bv - (B - a * A)) / D;
             }
         __syncthreads();
     };
-    // where each level's iterate is: cur[l] (X or Y)
-    double* cur[HS_MAXTAIL];
+    unsigned inY = 0;   // bit l: level l's iterate is in Y (else X)
     for (int l = 0; l < L; l++) {
-        const int n = ns[l], P = n + 2, PP = P * P, nc = ns[l + 1];
+        const int n = n0 >> l, P = n + 2, nc = n0 >> (l + 1);
         const double ih2 = (double)(n + 1) * (double)(n + 1);
-        double *x = X[l], *y = Y[l];
+        double *x = fieldX(l), *y = fieldY(l);
+        const double* R = fieldR(l);
         const bool zg = l > 0 || zero_guess;
         for (int q = 0; q < nu1; q++) {
             sweep(l, (q == 0 && zg) ? nullptr : x, y);
             double* w = x; x = y; y = w;
         }
-        cur[l] = x;
-        // residual into y (interior), then full weighting into R[l + 1]
+        if (nu1 & 1) inY |= 1u << l;
+        // residual into y (interior), then full weighting into the next level's rhs
         if (tx < n && ty < n)
             for (int z = tz; z < n; z += 4) {
                 const int c = ((z + 1) * P + ty + 1) * P + tx + 1;
-                const double cv = x[c];
-                const double faces = ((x[c - 1] + x[c + 1]) + (x[c - P] + x[c + P])) + (x[c - PP] + x[c + PP]);
-                const double exy = (x[c - P - 1] + x[c - P + 1]) + (x[c + P - 1] + x[c + P + 1]);
-                const double exz = (x[c - PP - 1] + x[c - PP + 1]) + (x[c + PP - 1] + x[c + PP + 1]);
-                const double eyz = (x[c - PP - P] + x[c - PP + P]) + (x[c + PP - P] + x[c + PP + P]);
-                const double A = ((2.0 * faces + ((exy + exz) + eyz)) - 24.0 * cv) * ih2 / 6.0;
-                const double B = 0.5 * cv + faces / 12.0;
-                y[c] = R[l][(z * n + ty) * n + tx] - (B - a * A);
+                double A, B;
+                pairAB(x, c, P, ih2, &A, &B);
+                y[c] = R[(z * n + ty) * n + tx] - (B - a * A);
             }
         __syncthreads();
+        double* Rc = fieldR(l + 1);
         if (tx < nc && ty < nc)
             for (int z = tz; z < nc; z += 4) {
                 const double w[3] = {0.25, 0.5, 0.25};
@@ -3261,53 +3266,45 @@ __global__ void __launch_bounds__(HS_TAIL_THREADS) k_cmp_tail(int n0, double* __
                         for (int dx = -1; dx <= 1; dx++)
                             sacc += w[dx + 1] * w[dy + 1] * w[dz + 1] *
                                     y[((2 * z + 2 + dz) * P + (2 * ty + 2 + dy)) * P + (2 * tx + 2 + dx)];
-                R[l + 1][(z * nc + ty) * nc + tx] = sacc;
+                Rc[(z * nc + ty) * nc + tx] = sacc;
             }
         __syncthreads();
     }
-    cmp_exact_dev(ns[L], R[L], X[L], a, bh, Sm, cs, true);
-    cur[L] = X[L];
+    cmp_exact_dev(n0 >> L, fieldR(L), fieldX(L), a, bh, Sm, cs, true);
     for (int l = L - 1; l >= 0; l--) {
-        const int n = ns[l], P = n + 2, nc = ns[l + 1], Pc = nc + 2;
-        const double* ec = cur[l + 1];
-        // the corrected iterate goes where the post-sweeps end in X[l]
-        double* src = cur[l];
-        double* dst = (nu2 & 1) ? Y[l] : X[l];
+        const int n = n0 >> l, P = n + 2, Pc = (n0 >> (l + 1)) + 2;
+        const double* ec = ((inY >> (l + 1)) & 1u) ? fieldY(l + 1) : fieldX(l + 1);
+        double* src = ((inY >> l) & 1u) ? fieldY(l) : fieldX(l);
+        // the corrected iterate goes where the post-sweeps end in X
+        double* dst = (nu2 & 1) ? fieldY(l) : fieldX(l);
         if (tx < n && ty < n)
             for (int z = tz; z < n; z += 4) {
                 const int i = tx, j = ty, k = z;
-                int ix0, ix1, iy0, iy1, iz0, iz1;
-                double wx0, wx1, wy0, wy1, wz0, wz1;
-                int cx, cy, cz;
                 // per axis: odd i on coarse (i-1)/2; even i between i/2-1 and i/2
                 // (padded coarse index +1; the frame supplies the zero walls)
-                if (i & 1) { ix0 = (i - 1) / 2 + 1; wx0 = 1.0; cx = 1; ix1 = ix0; wx1 = 0.0; }
-                else { ix0 = i / 2; wx0 = 0.5; ix1 = i / 2 + 1; wx1 = 0.5; cx = 2; }
-                if (j & 1) { iy0 = (j - 1) / 2 + 1; wy0 = 1.0; cy = 1; iy1 = iy0; wy1 = 0.0; }
-                else { iy0 = j / 2; wy0 = 0.5; iy1 = j / 2 + 1; wy1 = 0.5; cy = 2; }
-                if (k & 1) { iz0 = (k - 1) / 2 + 1; wz0 = 1.0; cz = 1; iz1 = iz0; wz1 = 0.0; }
-                else { iz0 = k / 2; wz0 = 0.5; iz1 = k / 2 + 1; wz1 = 0.5; cz = 2; }
-                const int IX[2] = {ix0, ix1}, IY[2] = {iy0, iy1}, IZ[2] = {iz0, iz1};
-                const double WX[2] = {wx0, wx1}, WY[2] = {wy0, wy1}, WZ[2] = {wz0, wz1};
+                const int cx = (i & 1) ? 1 : 2, cy = (j & 1) ? 1 : 2, cz = (k & 1) ? 1 : 2;
+                const int ix0 = (i & 1) ? (i - 1) / 2 + 1 : i / 2, iy0 = (j & 1) ? (j - 1) / 2 + 1 : j / 2;
+                const int iz0 = (k & 1) ? (k - 1) / 2 + 1 : k / 2;
+                const double wx = (i & 1) ? 1.0 : 0.5, wy = (j & 1) ? 1.0 : 0.5, wz = (k & 1) ? 1.0 : 0.5;
                 double sacc = 0.0;
                 for (int c3 = 0; c3 < cz; c3++)
                     for (int b3 = 0; b3 < cy; b3++)
                         for (int a3 = 0; a3 < cx; a3++)
-                            sacc += WX[a3] * WY[b3] * WZ[c3] * ec[(IZ[c3] * Pc + IY[b3]) * Pc + IX[a3]];
+                            sacc += wx * wy * wz * ec[((iz0 + c3) * Pc + iy0 + b3) * Pc + ix0 + a3];
                 const int c = ((k + 1) * P + j + 1) * P + i + 1;
                 dst[c] = src[c] + sacc;
             }
         __syncthreads();
-        double *x = dst, *y = (dst == X[l]) ? Y[l] : X[l];
+        double *x = dst, *y = (nu2 & 1) ? fieldX(l) : fieldY(l);
         for (int q = 0; q < nu2; q++) {
             sweep(l, x, y);
             double* w = x; x = y; y = w;
         }
-        cur[l] = x;   // X[l]
+        inY &= ~(1u << l);   // X again
     }
     {
         const int n = n0, P = n + 2;
-        const double* x = cur[0];
+        const double* x = fieldX(0);
         if (tx < n && ty < n)
             for (int z = tz; z < n; z += 4) ug[(z * n + ty) * n + tx] = x[((z + 1) * P + ty + 1) * P + tx + 1];
     }
