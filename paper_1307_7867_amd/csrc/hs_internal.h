@@ -327,8 +327,6 @@ hipError_t compact_prolong(int nc, const double* ec, const double* src, double* 
 // first Jacobi sweep from a zero iterate: dst = omega b / D
 hipError_t compact_zsweep(int n, const double* b, double* dst, const LaneCtl* ctl, int lane, double dtau,
                           double omega, int gate, hipStream_t s);
-hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau, int gate,
-                         hipStream_t s);
 // the V-cycle below a top grid n0 <= HS_TAIL_N in one workgroup (LDS bytes: compact_tail_lds)
 size_t compact_tail_lds(int n0, int n_coarsest);
 hipError_t compact_tail(int n0, double* u, const double* b, int zero_guess, const LaneCtl* ctl, int lane, double dtau,

@@ -3066,10 +3066,9 @@ __device__ __forceinline__ double cmp_fw_at(const double* rf, int nf, int I, int
 
 // exact solve of (B - a A) x = b for n <= 3 in the sine basis,
 // x = S diag(1 / (lam_B - a lam_A)) S b with S the orthonormal DST-I; called
-// by every thread of the block (t = threadIdx.x), bh a 27-entry scratch.
-// With pad, x is stored with a zero frame of one cell ((n+2)^3 layout).
-__device__ void cmp_exact_dev(int n, const double* b, double* x, double a, double* bh, double (*S)[3], double* cs,
-                              bool pad = false)
+// by every thread of the block (t = threadIdx.x), bh a 27-entry scratch;
+// x has a zero frame of one cell ((n+2)^3 layout), b none.
+__device__ void cmp_exact_dev(int n, const double* b, double* x, double a, double* bh, double (*S)[3], double* cs)
 {
     const int t = (int)threadIdx.x, N3 = n * n * n;
     const double pi = 3.14159265358979323846;
@@ -3094,8 +3093,7 @@ __device__ void cmp_exact_dev(int n, const double* b, double* x, double a, doubl
         for (int r = 0; r < n; r++)
             for (int q = 0; q < n; q++)
                 for (int p = 0; p < n; p++) s += S[r][k] * S[q][j] * S[p][i] * bh[(r * n + q) * n + p];
-        if (pad) x[((k + 1) * (n + 2) + (j + 1)) * (n + 2) + (i + 1)] = s;
-        else x[t] = s;
+        x[((k + 1) * (n + 2) + (j + 1)) * (n + 2) + (i + 1)] = s;
     }
     __syncthreads();
 }
@@ -3140,15 +3138,6 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp_zsweep(int n, const double* __
     if (q >= (long long)n * n * n) return;
     const double a = c.nu * (c.dt * dtau), ih2 = (double)(n + 1) * (double)(n + 1);
     dst[q] = omega * b[q] / (0.5 + a * 24.0 * ih2 / 6.0);
-}
-
-__global__ void __launch_bounds__(64) k_cmp_exact(int n, const double* __restrict__ b, double* __restrict__ x,
-                                                  const LaneCtl* __restrict__ ctl, int lane, double dtau, int gate)
-{
-    if (gate && ctl[lane].mg_state != 0) return;
-    __shared__ double bh[27];
-    __shared__ double S[3][3], cs[3];
-    cmp_exact_dev(n, b, x, ctl[lane].nu * (ctl[lane].dt * dtau), bh, S, cs);
 }
 
 // The grids of one compact V-cycle from n <= HS_TAIL_N down, in one
@@ -3270,7 +3259,7 @@ __global__ void __launch_bounds__(HS_TAIL_THREADS) k_cmp_tail(int n0, double* __
             }
         __syncthreads();
     }
-    cmp_exact_dev(n0 >> L, fieldR(L), fieldX(L), a, bh, Sm, cs, true);
+    cmp_exact_dev(n0 >> L, fieldR(L), fieldX(L), a, bh, Sm, cs);
     for (int l = L - 1; l >= 0; l--) {
         const int n = n0 >> l, P = n + 2, Pc = (n0 >> (l + 1)) + 2;
         const double* ec = ((inY >> (l + 1)) & 1u) ? fieldY(l + 1) : fieldX(l + 1);
@@ -3903,14 +3892,6 @@ hipError_t compact_zsweep(int n, const double* b, double* dst, const LaneCtl* ct
     const long long N = (long long)n * n * n;
     hipLaunchKernelGGL(k_cmp_zsweep, dim3((unsigned)((N + HS_BLOCK - 1) / HS_BLOCK)), BLK, 0, s, n, b, dst, ctl, lane,
                        dtau, omega, gate);
-    return hipGetLastError();
-}
-
-hipError_t compact_exact(int n, const double* b, double* x, const LaneCtl* ctl, int lane, double dtau, int gate,
-                         hipStream_t s)
-{
-    if (n < 1 || n > 3) return hipErrorInvalidValue;   // one block of 64 threads holds n^3 <= 27
-    hipLaunchKernelGGL(k_cmp_exact, dim3(1), dim3(64), 0, s, n, b, x, ctl, lane, dtau, gate);
     return hipGetLastError();
 }
 
