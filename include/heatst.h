@@ -78,9 +78,10 @@ typedef enum { HS_FP64 = 0, HS_MIXED = 1 } hs_precision;
  * |B U_0 + dt sum_j q_mj (nu A U_j + B f_j) - B U_m|.  Single-level FP64
  * plans only (nlevels 1, nslices 1, no node-parallel sweeps, no lane
  * memory); such a plan supports hs_set_state / hs_get_state, hs_step,
- * hs_solve, hs_begin_step, hs_sdc_sweep (level 0), hs_end_step and the
- * statistics, and rejects hs_lap_apply, hs_heat_rhs, hs_mg_vcycle and
- * hs_solve_graph (HS_EINVAL).  Its lanes run one after another.
+ * hs_solve, hs_begin_step, hs_sdc_sweep (level 0), hs_end_step,
+ * hs_set_nodes with node values only, and the statistics, and rejects
+ * hs_lap_apply, hs_heat_rhs, hs_mg_vcycle, hs_solve_graph and hs_set_nodes
+ * with d_FI (HS_EINVAL).  Its lanes run one after another.
  */
 #define HS_ORDER_COMPACT (-4)
 

@@ -2364,6 +2364,7 @@ hs_status hs_set_nodes(hs_plan* P, int32_t level, const double* d_U, const doubl
     HS_CHECK(check_bound(P));
     if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
+    if (P->compact && d_FI) return HS_EINVAL;   // its node array holds nu A_h U, set by the step itself
     hipStream_t s = (hipStream_t)stream;
     int M = P->M[level];
     for (int b = 0; b < P->B; b++) {

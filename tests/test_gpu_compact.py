@@ -226,3 +226,39 @@ def test_compact_sdc_sine_mode_at_255(torch):
     assert st == 0
     amp = _scalar_sdc(n, M, 0.1, 0.05, 3.0, 0.0, nsteps, sweeps, 1.0)
     assert np.abs(got - amp * s).max() <= 1e-10 * abs(amp)
+
+
+def test_compact_plan_rejects_order_specific_calls(torch):
+    """A compact plan refuses the calls that apply the order-2/4 operators
+    and an F_I array from outside (HS_EINVAL), and accepts node values."""
+    from paper_1307_7867_amd import heatst as hs
+    n, M = 7, 3
+    plan = hs.Plan(hs.Problem(n=n, order=hs.HS_ORDER_COMPACT, nnodes=M, sweeps=1))
+    u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    U = torch.zeros(M * n ** 3, dtype=torch.float64, device="cuda")
+    for call in (lambda: plan.lap_apply(u, 1.0, 0.0), lambda: plan.heat_rhs(u, 0.0),
+                 lambda: plan.mg_vcycle(u, u.clone(), 0.01), lambda: plan.set_nodes(0, U, U.clone()),
+                 lambda: plan.solve_graph()):
+        with pytest.raises(hs.HeatstError) as e:
+            call()
+        assert e.value.status == hs.HS_EINVAL
+    plan.set_nodes(0, U, None)
+
+
+def test_compact_step_level_calls_match_solve(torch):
+    """begin_step, sweeps and end_step through the ABI give the state that
+    hs_step gives, bit for bit."""
+    from paper_1307_7867_amd import heatst as hs
+    n, M, K = 15, 3, 2
+    u0 = torch.from_numpy(inputs.random_smooth(n, 9).ravel().copy()).cuda()
+    pb = hs.Problem(n=n, order=hs.HS_ORDER_COMPACT, nnodes=M, sweeps=K, nsteps=1, tol=1e-12)
+    a = hs.Plan(pb)
+    a.set_state(u0)
+    a.step()
+    b = hs.Plan(pb)
+    b.set_state(u0)
+    b.begin_step()
+    for _ in range(K):
+        b.sdc_sweep(0)
+    b.end_step()
+    assert torch.equal(a.get_state(), b.get_state())
