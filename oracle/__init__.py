@@ -78,6 +78,9 @@ def lib():
         L.or_sdc_residual_compact.argtypes = [C.POINTER(Level), C.c_double, C.c_double, C.c_double, C.c_double,
                                               _D, _D]
         L.or_spread_compact.argtypes = [C.POINTER(Level), C.c_double, _D, _D, _D]
+        L.or_compact_binv.argtypes = [C.c_int, _D, _D]
+        L.or_mlsdc_iter_compact.argtypes = [C.POINTER(Problem), C.c_double, _D, _D, _D, _D, _D, _D, _D,
+                                            C.POINTER(Stats)]
         L.or_sdc_sweep_compact.argtypes = [C.POINTER(Level), C.POINTER(MG), C.c_double, C.c_double, C.c_double,
                                            C.c_double, _D, _D, C.POINTER(Stats)]
         L.or_residual.argtypes = [C.c_int, C.c_int, C.c_double, _D, _D, _D]
@@ -189,6 +192,24 @@ def compact_apply(u, alpha, beta):
     y = np.empty_like(u)
     lib().or_compact_apply(n, alpha, beta, _p(u), _p(y))
     return y
+
+
+def compact_binv(y):
+    """B_h^{-1} y, exactly, in the sine basis (or_compact_binv)."""
+    y = _f(y)
+    x = np.empty_like(y)
+    lib().or_compact_binv(y.shape[-1], _p(y), _p(x))
+    return x
+
+
+def mlsdc_iter_compact(pb, tn, Uf, G, Uc, FIc, Ut, tau):
+    """One two-level MLSDC iteration with the compact fine level, in place
+    (or_mlsdc_iter_compact); returns (status, B^{-1} G used for the FAS restriction)."""
+    FIf = np.empty_like(Uf)
+    st = Stats()
+    s = lib().or_mlsdc_iter_compact(C.byref(pb), tn, _p(Uf), _p(G), _p(FIf), _p(Uc), _p(FIc), _p(Ut), _p(tau),
+                                    C.byref(st))
+    return s, FIf
 
 
 def spread_compact(lv, nu, u0):

@@ -215,6 +215,52 @@ void or_compact_apply(int n, double alpha, double beta, const double *u, double 
 }
 
 /*
+ * x = B_h^{-1} y, exactly, in the sine basis: every discrete sine mode is an
+ * eigenvector of B_h with eigenvalue 1/2 + (cos(pi p h) + cos(pi q h) +
+ * cos(pi r h))/6, so B_h = S diag(lambda) S with S the orthonormal DST-I
+ * (S_ab = sqrt(2/(n+1)) sin(pi (a+1)(b+1)/(n+1)), applied along each axis;
+ * S S = I).  Section 1.2 has the multigrid solver invert B_h for the FAS
+ * correction; B_h is too ill-conditioned for that in 3-D (its smallest
+ * eigenvalue is about pi^2 h^2 / 4), so the inverse is taken exactly (a
+ * reading).
+ */
+static void dst_axis(int n, const double *S, const double *in, double *out, int axis)
+{
+    size_t st = axis == 0 ? 1 : axis == 1 ? (size_t)n : (size_t)n * n;
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                int c[3] = {i, j, k};
+                size_t p = ((size_t)k * n + j) * n + i;
+                size_t base = p - (size_t)c[axis] * st;
+                double sum = 0.0;
+                for (int q = 0; q < n; q++) sum += S[(size_t)c[axis] * n + q] * in[base + (size_t)q * st];
+                out[p] = sum;
+            }
+}
+
+void or_compact_binv(int n, const double *y, double *x)
+{
+    size_t N = cube(n);
+    double *S = alloc0((size_t)n * n), *cs = alloc0(n), *t1 = alloc0(N), *t2 = alloc0(N);
+    for (int a = 0; a < n; a++) {
+        cs[a] = cos(M_PI * (a + 1) / (n + 1));
+        for (int b = 0; b < n; b++) S[(size_t)a * n + b] = sqrt(2.0 / (n + 1)) * sin(M_PI * (a + 1) * (b + 1) / (n + 1));
+    }
+    dst_axis(n, S, y, t1, 0);
+    dst_axis(n, S, t1, t2, 1);
+    dst_axis(n, S, t2, t1, 2);
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++)
+                t1[((size_t)k * n + j) * n + i] /= 0.5 + ((cs[i] + cs[j]) + cs[k]) / 6.0;
+    dst_axis(n, S, t1, t2, 0);
+    dst_axis(n, S, t2, t1, 1);
+    dst_axis(n, S, t1, x, 2);
+    free(S); free(cs); free(t1); free(t2);
+}
+
+/*
  * The implicit-Euler substep operator A_a = I - a L_h with a = nu * dt_m
  * (eq. (7): the implicit part of the IMEX sweep moved to the left); for the
  * compact scheme B_h - a A_h (the weighting matrix multiplies eq. (7)).
@@ -1084,8 +1130,8 @@ void or_fas_restrict(const or_level *Lf, const or_level *Lc, double nu, double t
  * or tricubic (interp 3) in space.  Then f^I is recomputed on the fine
  * level at every node.
  */
-void or_fas_interp(const or_level *Lf, const or_level *Lc, double nu, double *Uf, double *FIf,
-                   const double *Uc, const double *Ut, int interp)
+static void fas_interp_correction(const or_level *Lf, const or_level *Lc, double *Uf, const double *Uc,
+                                  const double *Ut, int interp)
 {
     int Mf = Lf->M, Mc = Lc->M, nf = Lf->n, nc = Lc->n;
     size_t Nf = cube(nf), Nc = cube(nc);
@@ -1109,9 +1155,16 @@ void or_fas_interp(const or_level *Lf, const or_level *Lc, double nu, double *Uf
         if (interp == 3) or_prolong_add_cubic(nc, ec, Uf + (size_t)mf * Nf);
         else or_prolong_add(nc, ec, Uf + (size_t)mf * Nf);
     }
-    for (int mf = 0; mf < Mf; mf++)
-        or_lap_apply(nf, Lf->order, 0.0, nu, Uf + (size_t)mf * Nf, FIf + (size_t)mf * Nf);
     free(dU); free(ec);
+}
+
+void or_fas_interp(const or_level *Lf, const or_level *Lc, double nu, double *Uf, double *FIf,
+                   const double *Uc, const double *Ut, int interp)
+{
+    size_t Nf = cube(Lf->n);
+    fas_interp_correction(Lf, Lc, Uf, Uc, Ut, interp);
+    for (int mf = 0; mf < Lf->M; mf++)
+        or_lap_apply(Lf->n, Lf->order, 0.0, nu, Uf + (size_t)mf * Nf, FIf + (size_t)mf * Nf);
 }
 
 /* Node arrays of every MLSDC level of one time step (Ut, tau: levels >= 1). */
@@ -1197,7 +1250,7 @@ static int mlsdc_vcycle(const or_problem *pb, double tn, or_hier *H, or_stats *s
 int or_mlsdc_iter(const or_problem *pb, double tn, double *Uf, double *FIf, double *Uc,
                   double *FIc, double *Ut, double *tau, or_stats *st)
 {
-    if (pb->nlevels != 2) return OR_EINVAL;
+    if (pb->nlevels != 2 || pb->lev[0].order == OR_ORDER_COMPACT) return OR_EINVAL;
     or_hier H;
     memset(&H, 0, sizeof(H));
     H.U[0] = Uf; H.FI[0] = FIf;
@@ -1234,13 +1287,70 @@ static int mlsdc_step(const or_problem *pb, double tn, double *u, or_stats *st)
     return status;
 }
 
+/*
+ * Two-level MLSDC with the compact scheme on the fine level (a reading:
+ * sec. 1.2 has B_h inverted for the FAS correction).  The fine sweeps are
+ * the B-weighted ones (G = nu A_h U at the nodes); the FAS restriction needs
+ * the fine integral in the plain form, whose implicit part is
+ * f^I = nu B_h^{-1} A_h U = B_h^{-1} G, so FIf is formed from G by the exact
+ * inverse first.  Coarse sweep and interpolation as for the other schemes;
+ * after the interpolation G is recomputed.  One iteration on caller arrays:
+ * Uf, G [Mf][Nf]; FIf [Mf][Nf] scratch for B^{-1} G; coarse as or_mlsdc_iter.
+ */
+int or_mlsdc_iter_compact(const or_problem *pb, double tn, double *Uf, double *G, double *FIf, double *Uc,
+                          double *FIc, double *Ut, double *tau, or_stats *st)
+{
+    if (pb->nlevels != 2 || pb->lev[0].order != OR_ORDER_COMPACT) return OR_EINVAL;
+    const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[1];
+    size_t Nf = cube(Lf->n);
+    int status = or_sdc_sweep_compact(Lf, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uf, G, st);
+    for (int j = 0; j < Lf->M; j++) or_compact_binv(Lf->n, G + (size_t)j * Nf, FIf + (size_t)j * Nf);
+    or_fas_restrict(Lf, Lc, pb->nu, tn, pb->dt, pb->forcing_c, Uf, FIf, Uc, FIc, Ut, tau);
+    int s = or_sdc_sweep(Lc, &pb->mg, pb->nu, tn, pb->dt, pb->forcing_c, Uc, FIc, tau, NULL);
+    if (s != OR_OK && status == OR_OK) status = s;
+    fas_interp_correction(Lf, Lc, Uf, Uc, Ut, pb->fas_interp);
+    for (int j = 0; j < Lf->M; j++) or_compact_apply(Lf->n, 0.0, pb->nu, Uf + (size_t)j * Nf, G + (size_t)j * Nf);
+    return status;
+}
+
+static int mlsdc_step_compact(const or_problem *pb, double tn, double *u, or_stats *st)
+{
+    const or_level *Lf = &pb->lev[0];
+    size_t Nf = cube(Lf->n);
+    or_hier H;
+    hier_alloc(pb, &H);
+    double *G = alloc0((size_t)Lf->M * Nf);
+    or_spread_compact(Lf, pb->nu, u, H.U[0], G);
+    int status = OR_OK, k;
+    for (k = 0;; k++) {
+        if (pb->sweeps > 0) {
+            if (k >= pb->sweeps) break;
+        } else {
+            double R = or_sdc_residual_compact(Lf, pb->nu, tn, pb->dt, pb->forcing_c, H.U[0], G);
+            if (st) st->last_residual = R;
+            if (R != R) { status = OR_ENONFINITE; break; }
+            if (R <= pb->sdc_tol) break;
+            if (k >= pb->max_sweeps) { status = OR_ENOCONV; break; }
+        }
+        int s = or_mlsdc_iter_compact(pb, tn, H.U[0], G, H.FI[0], H.U[1], H.FI[1], H.Ut[1], H.tau[1], st);
+        if (s != OR_OK && status == OR_OK) status = s;
+    }
+    if (pb->sweeps > 0 && st)
+        st->last_residual = or_sdc_residual_compact(Lf, pb->nu, tn, pb->dt, pb->forcing_c, H.U[0], G);
+    if (st) st->sweeps = k;
+    memcpy(u, H.U[0] + (size_t)(Lf->M - 1) * Nf, Nf * sizeof(double));
+    free(G);
+    hier_free(pb, &H);
+    return status;
+}
+
 static int check_problem(const or_problem *pb)
 {
     if (pb->nlevels < 1 || pb->nlevels > OR_MAXLEV) return OR_EINVAL;
     for (int l = 0; l < pb->nlevels; l++) {
         const or_level *L = &pb->lev[l];
         if (!valid_n(L->n) || (L->order != 2 && L->order != 4 && L->order != OR_ORDER_COMPACT)) return OR_EINVAL;
-        if (L->order == OR_ORDER_COMPACT && (pb->nlevels != 1 || pb->node_parallel)) return OR_EINVAL;
+        if (L->order == OR_ORDER_COMPACT && (l != 0 || pb->nlevels > 2 || pb->node_parallel)) return OR_EINVAL;
         if (L->M < 2 || L->M > OR_MAXM) return OR_EINVAL;
     }
     for (int l = 1; l < pb->nlevels; l++) {
@@ -1265,8 +1375,9 @@ int or_run(const or_problem *pb, double *u, or_stats *st)
     int status = OR_OK;
     for (int step = 0; step < pb->nsteps; step++) {
         double tn = pb->t0 + step * pb->dt;
-        s = pb->nlevels > 1 ? mlsdc_step(pb, tn, u, st)
-            : pb->lev[0].order == OR_ORDER_COMPACT ? sdc_step_compact(pb, tn, u, st) : sdc_step(pb, tn, u, st);
+        const int cmp = pb->lev[0].order == OR_ORDER_COMPACT;
+        s = pb->nlevels > 1 ? (cmp ? mlsdc_step_compact(pb, tn, u, st) : mlsdc_step(pb, tn, u, st))
+            : cmp ? sdc_step_compact(pb, tn, u, st) : sdc_step(pb, tn, u, st);
         if (s != OR_OK && status == OR_OK) status = s;
     }
     if (st) st->status = status;
@@ -1323,7 +1434,8 @@ int or_pfasst(const or_problem *pb, int P, int pred_sweeps, double *u, or_stats 
 {
     int s = check_problem(pb);
     if (s != OR_OK) return s;
-    if (pb->nlevels < 2 || P < 1 || pb->nsteps % P != 0 || pb->sweeps < 0 || pred_sweeps < 0)
+    if (pb->nlevels < 2 || P < 1 || pb->nsteps % P != 0 || pb->sweeps < 0 || pred_sweeps < 0 ||
+        pb->lev[0].order == OR_ORDER_COMPACT)
         return OR_EINVAL;
     const int NL = pb->nlevels, C = NL - 1;   /* C: the coarsest level */
     const or_level *Lf = &pb->lev[0], *Lc = &pb->lev[C];

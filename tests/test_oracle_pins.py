@@ -1072,10 +1072,81 @@ def test_compact_sdc_tolerance_mode_and_residual():
     assert oracle.sdc_residual_compact(lv, 0.1, 0.0, 0.05, 3.0, U, G) > 1e-4
 
 
-def test_compact_is_single_level_only():
+def test_compact_levels_validated():
+    """The compact scheme is accepted on the finest of one or two levels only,
+    and not in PFASST."""
     u0 = inputs.random_smooth(15, 1)
-    bad = oracle.problem([(15, oracle.COMPACT, 5), (7, 2, 3)], sweeps=1)
-    assert oracle.run(bad, u0)[1] == oracle.EINVAL
+    for levels in ([(15, 2, 5), (7, oracle.COMPACT, 3)],
+                   [(15, oracle.COMPACT, 5), (7, 2, 3), (3, 2, 2)]):
+        assert oracle.run(oracle.problem(levels, sweeps=1), u0)[1] == oracle.EINVAL
+    two = oracle.problem([(15, oracle.COMPACT, 5), (7, 2, 3)], sweeps=1, nsteps=2)
+    assert oracle.run(two, u0)[1] == oracle.OK
+    assert oracle.pfasst_run(two, 2, u0)[1] == oracle.EINVAL
+
+
+@pytest.mark.parametrize("n", [3, 7, 15])
+def test_compact_binv_inverts_the_weighting_matrix(n):
+    """B_h (B_h^{-1} y) = y through the stencil, and on a sine mode the
+    inverse divides by the closed-form eigenvalue."""
+    y = np.random.default_rng(n).standard_normal((n, n, n))
+    x = oracle.compact_binv(y)
+    assert np.abs(oracle.compact_apply(x, 1.0, 0.0) - y).max() <= 1e-12 * np.abs(y).max()
+    k = (1, 2, n)
+    phi = _sine(n, k)
+    assert np.abs(oracle.compact_binv(phi) - phi / _compact_eigs(n, k)[1]).max() <= 1e-12
+
+
+def _compact_collocation_nodes(n, M, tol=1e-13):
+    """Node values and G = nu A U of the compact B-weighted collocation
+    solution of one step from random data (single-level sweeps to tol)."""
+    lv = oracle.Level(n, oracle.COMPACT, M)
+    mg = oracle.mg_params(tol=1e-14)
+    U, G = oracle.spread_compact(lv, 0.1, inputs.random_smooth(n, 3))
+    for _ in range(80):
+        if oracle.sdc_residual_compact(lv, 0.1, 0.0, 0.05, 3.0, U, G) <= tol:
+            break
+        oracle.sdc_sweep_compact(lv, mg, 0.1, 0.0, 0.05, 3.0, U, G)
+    assert oracle.sdc_residual_compact(lv, 0.1, 0.0, 0.05, 3.0, U, G) <= tol
+    return lv, mg, U, G
+
+
+def test_compact_fas_correction_needs_the_inverse():
+    """At the compact collocation solution the FAS-corrected coarse problem is
+    solved by the restricted values when the fine integral uses
+    f^I = B_h^{-1} (nu A_h U): a coarse sweep from them stays put.  Control:
+    with nu A_h U itself in place of f^I (no inverse) it moves."""
+    nf, nc, Mf, Mc = 15, 7, 5, 3
+    lf, mg, U, G = _compact_collocation_nodes(nf, Mf)
+    lc = oracle.Level(nc, 2, Mc)
+    moved = {}
+    for name, FIf in (("inverse", np.stack([oracle.compact_binv(g) for g in G])), ("control", G.copy())):
+        Uc, FIc, Ut, tau = oracle.fas_restrict(lf, lc, 0.1, 0.0, 0.05, 3.0, U, FIf)
+        oracle.sdc_sweep(lc, mg, 0.1, 0.0, 0.05, 3.0, Uc, FIc, tau)
+        moved[name] = np.abs(Uc - Ut).max() / np.abs(Ut).max()
+    assert moved["inverse"] <= 1e-11
+    assert moved["control"] >= 1e-4
+
+
+def test_compact_mlsdc_fixed_point_and_convergence():
+    """One compact MLSDC iteration leaves the compact collocation solution
+    where it is; from a spread start, MLSDC converges to the same collocation
+    solution as single-level compact SDC."""
+    nf, nc, Mf, Mc = 15, 7, 5, 3
+    lf, mg, U, G = _compact_collocation_nodes(nf, Mf)
+    pb = oracle.problem([(nf, oracle.COMPACT, Mf), (nc, 2, Mc)], nu=0.1, dt=0.05, sweeps=1,
+                        mg=oracle.mg_params(tol=1e-14))
+    Uf, Gf = U.copy(), G.copy()
+    Uc = np.empty((Mc, nc, nc, nc)); FIc = np.empty_like(Uc); Ut = np.empty_like(Uc); tau = np.empty_like(Uc)
+    s, _ = oracle.mlsdc_iter_compact(pb, 0.0, Uf, Gf, Uc, FIc, Ut, tau)
+    assert s == oracle.OK
+    assert np.abs(Uf - U).max() <= 1e-11 * np.abs(U).max()
+    u0 = inputs.random_smooth(nf, 3)
+    kw = dict(nu=0.1, dt=0.05, sweeps=0, sdc_tol=1e-12, max_sweeps=60, mg=oracle.mg_params(tol=1e-14))
+    one, s1, st1 = oracle.run(oracle.problem([(nf, oracle.COMPACT, Mf)], **kw), u0)
+    two, s2, st2 = oracle.run(oracle.problem([(nf, oracle.COMPACT, Mf), (nc, 2, Mc)], **kw), u0)
+    assert s1 == oracle.OK and s2 == oracle.OK
+    assert np.abs(two - one).max() <= 1e-10 * np.abs(one).max()
+    assert np.abs(two - U[-1]).max() <= 1e-10 * np.abs(one).max()
 
 
 def test_compact_sdc_sine_mode_scalar_recursion():
