@@ -75,13 +75,17 @@ typedef enum { HS_FP64 = 0, HS_MIXED = 1 } hs_precision;
  * multigrid below with the compact operator on every grid (Jacobi diagonal
  * 1/2 + 4 a / h^2, exact sine-basis solve on the coarsest grid).  The SDC
  * residual is the B-weighted one, max over m of
- * |B U_0 + dt sum_j q_mj (nu A U_j + B f_j) - B U_m|.  Single-level FP64
- * plans only (nlevels 1, nslices 1, no node-parallel sweeps, no lane
- * memory); such a plan supports hs_set_state / hs_get_state, hs_step,
- * hs_solve, hs_begin_step, hs_sdc_sweep (level 0), hs_end_step,
+ * |B U_0 + dt sum_j q_mj (nu A U_j + B f_j) - B U_m|.  With a second level
+ * (order 2 or 4) the plan runs two-level MLSDC: the FAS restriction takes the
+ * fine integral with f^I = B_h^{-1}(nu A_h U) (section 1.2 has B_h inverted
+ * for the FAS correction; the inverse is exact, through the sine basis).
+ * FP64 plans with nlevels 1 or 2, nslices 1, no node-parallel sweeps, no
+ * lane memory; such a plan supports hs_set_state / hs_get_state, hs_step,
+ * hs_solve, hs_begin_step, hs_sdc_sweep, hs_mlsdc_iter, hs_end_step,
  * hs_set_nodes with node values only, and the statistics, and rejects
- * hs_lap_apply, hs_heat_rhs, hs_mg_vcycle, hs_solve_graph and hs_set_nodes
- * with d_FI (HS_EINVAL).  Its lanes run one after another.
+ * hs_lap_apply, hs_heat_rhs, hs_mg_vcycle, hs_solve_graph, hs_fas_restrict,
+ * hs_fas_interp and hs_set_nodes with d_FI (HS_EINVAL).  Its lanes run one
+ * after another.
  */
 #define HS_ORDER_COMPACT (-4)
 

@@ -337,5 +337,8 @@ hipError_t compact_quad(int n, int M, int m, const double* G, const double* base
 hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int lane, int mode, int cycle, double tol,
                           int max_cycles, hipStream_t s);
 hipError_t compact_ctl(LaneCtl* ctl, int lane, int op, int cycles, int state, int level, int status, hipStream_t s);
+// x = B_h^{-1} y exactly, through the sine basis (tab: the transposed DST-I
+// matrix, then cos(pi (i+1) h)); t0, t1 scratch grids; x may be y
+hipError_t compact_binv(int n, const double* tab, const double* y, double* x, double* t0, double* t1, hipStream_t s);
 
 }  // namespace hsk

@@ -3372,6 +3372,36 @@ __global__ void __launch_bounds__(HS_BLOCK) k_cmp_reduce(const double* __restric
     }
 }
 
+// B_h^{-1} in the sine basis (the FAS correction of MLSDC with the compact
+// fine level): B_h = S diag(lambda) S with S the orthonormal DST-I along each
+// axis.  One axis of the transform, one thread per output value:
+//   out[(a n + i) C + c] = sum_q S_iq in[(a n + q) C + c]
+// with C the axis stride (1, n, n^2); tab holds S transposed (tab[q n + i] =
+// S_iq, so that the threads of a row read consecutive entries) followed by
+// cos(pi (i+1) h), i < n.
+__global__ void __launch_bounds__(HS_BLOCK) k_dst_axis(int n, int C, const double* __restrict__ tab,
+                                                       const double* __restrict__ in, double* __restrict__ out)
+{
+    const int idx = (int)(blockIdx.x * HS_BLOCK + threadIdx.x);
+    if (idx >= n * n * n) return;
+    const int c = idx % C, r = idx / C, i = r % n, a = r / n;
+    const double* src = in + (long long)a * n * C + c;
+    double sum = 0.0;
+    for (int q = 0; q < n; q++) sum += tab[q * n + i] * src[(long long)q * C];
+    out[idx] = sum;
+}
+
+// x /= 1/2 + (cos(pi (i+1) h) + cos(pi (j+1) h) + cos(pi (k+1) h)) / 6, B_h's
+// eigenvalue on sine mode (i, j, k)
+__global__ void __launch_bounds__(HS_BLOCK) k_binv_scale(int n, const double* __restrict__ tab, double* __restrict__ x)
+{
+    const int idx = (int)(blockIdx.x * HS_BLOCK + threadIdx.x);
+    if (idx >= n * n * n) return;
+    const double* cs = tab + n * n;
+    const int i = idx % n, j = (idx / n) % n, k = idx / (n * n);
+    x[idx] /= 0.5 + ((cs[i] + cs[j]) + cs[k]) / 6.0;
+}
+
 // Lane bookkeeping of the compact path: op 0 ends a solve (finish_solve with
 // cycles / state), op 1 sets the SDC state; a negative status is kept if the
 // lane has none yet.
@@ -3946,6 +3976,26 @@ hipError_t compact_reduce(const double* partials, int nblk, LaneCtl* ctl, int la
 {
     hipLaunchKernelGGL(k_cmp_reduce, dim3(1), BLK, 0, s, partials, nblk, ctl, lane, mode, cycle, tol, max_cycles,
                        -3, -4);   // HS_ENOCONV, HS_ENONFINITE
+    return hipGetLastError();
+}
+
+hipError_t compact_binv(int n, const double* tab, const double* y, double* x, double* t0, double* t1, hipStream_t s)
+{
+    const unsigned g = (unsigned)(((long long)n * n * n + HS_BLOCK - 1) / HS_BLOCK);
+    const int C[3] = {1, n, n * n};
+    const double* src = y;
+    double* bufs[2] = {t0, t1};
+    // S3 y into t0 (x, y, z axes: y -> t0 -> t1 -> t0)
+    for (int ax = 0; ax < 3; ax++) {
+        double* dst = bufs[ax & 1];
+        hipLaunchKernelGGL(k_dst_axis, dim3(g), BLK, 0, s, n, C[ax], tab, src, dst);
+        src = dst;
+    }
+    hipLaunchKernelGGL(k_binv_scale, dim3(g), BLK, 0, s, n, tab, t0);
+    // S3 of the scaled values: t0 -> t1 -> t0 -> x
+    hipLaunchKernelGGL(k_dst_axis, dim3(g), BLK, 0, s, n, C[0], tab, (const double*)t0, t1);
+    hipLaunchKernelGGL(k_dst_axis, dim3(g), BLK, 0, s, n, C[1], tab, (const double*)t1, t0);
+    hipLaunchKernelGGL(k_dst_axis, dim3(g), BLK, 0, s, n, C[2], tab, (const double*)t0, x);
     return hipGetLastError();
 }
 

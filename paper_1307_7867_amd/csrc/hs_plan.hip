@@ -291,6 +291,7 @@ struct hs_plan {
     const double* ext_b = nullptr;
     // sine tables per grid size; lanes' own memory (pb.lane_memory)
     std::map<int, double*> sig;
+    std::map<int, double*> dst_tab;            // compact MLSDC: transposed DST-I matrix + cosines per fine n
     std::vector<void*> lane_base;
     // launch timer (hs_plan_timer): start / stop event pairs of the timed kind
     int timer_kind = 0;
@@ -705,6 +706,11 @@ void layout(hs_plan* P, char* base)
     for (int b = 0; b < P->B; b++)
         for (int L = 0, n = P->lane_n[b]; L < P->nlev; L++, n = (n - 1) / 2)
             if (!P->sig.count(n)) P->sig[n] = bump.arr<double>(n);
+    P->dst_tab.clear();
+    if (P->compact && P->nlev == 2)
+        for (int b = 0; b < P->B; b++)
+            if (!P->dst_tab.count(P->lane_n[b]))
+                P->dst_tab[P->lane_n[b]] = bump.arr<double>((size_t)P->lane_n[b] * (P->lane_n[b] + 1));
     P->lanes.assign(P->nctl, LaneBufs());
     if (P->lane_base.size() != (size_t)P->B) P->lane_base.assign(P->B, nullptr);
     for (int b = 0; b < P->B; b++) {
@@ -950,9 +956,9 @@ hs_status validate(const hs_problem* pb)
     if (pb->pfasst_groups >= 2 &&
         (pb->nslices % pb->pfasst_groups != 0 || pb->sweeps <= 0 || pb->mg.cycle_graphs || pb->nlevels != 2))
         return HS_EINVAL;
-    // the compact pair: single-level FP64 SDC, one lane after another
+    // the compact pair: FP64 SDC or two-level MLSDC, one lane after another
     if (pb->lev[0].order == HS_ORDER_COMPACT &&
-        (pb->nlevels != 1 || pb->nslices != 1 || mg.precision != HS_FP64 || pb->sdc_node_parallel ||
+        (pb->nlevels > 2 || pb->nslices != 1 || mg.precision != HS_FP64 || pb->sdc_node_parallel ||
          pb->lane_memory))
         return HS_EINVAL;
     if (pb->nslices > 1) {
@@ -1763,6 +1769,75 @@ hs_status cmp_step(hs_plan* P, hipStream_t s)
     return HS_OK;
 }
 
+// One two-level MLSDC iteration with the compact fine level over the live
+// lanes: the fine B-weighted sweeps (lane by lane); f^I = B_h^{-1} G at every
+// fine node, in place of G, for the FAS restriction (which then reads it as
+// the fine level's F_I); restriction, coarse sweep and interpolation of the
+// coarse correction over the lane set; G = nu A_h U again at every fine node.
+hs_status cmp_mlsdc_iter(hs_plan* P, hipStream_t s)
+{
+    HS_CHECK(read_ctl(P, s));
+    const std::vector<int> live = cmp_live(P, s);
+    if (live.empty()) return HS_OK;
+    const int M = P->M[0];
+    for (int b : live) HS_CHECK(cmp_sweep(P, b, s));
+    for (int b : live) {
+        const LaneBufs& lb = P->lanes[b];
+        const long long N = lb.N[0];
+        const double* tab = P->dst_tab.at(lb.n[0]);
+        for (int j = 0; j < M; j++)
+            HS_TRY(hsk::compact_binv(lb.n[0], tab, lb.FI[0] + j * N, lb.FI[0] + j * N, lb.tmp[0], lb.rhs[0], s));
+    }
+    LaneSet& ls = P->run;
+    HS_TRY(fas_restrict(P, ls, 0, s));
+    int outcome;
+    HS_CHECK(sweep(P, ls, 1, false, false, s, &outcome));
+    HS_TRY(fas_interp(P, ls, 0, s));
+    for (int b : live) {
+        const LaneBufs& lb = P->lanes[b];
+        const long long N = lb.N[0];
+        for (int j = 0; j < M; j++)
+            HS_TRY(hsk::compact_op(3, lb.n[0], lb.U[0] + j * N, lb.FI[0] + j * N, nullptr, nullptr, P->ctl, b, 0.0,
+                                   0.0, nullptr, 0, s));
+    }
+    return HS_OK;
+}
+
+// A step of two-level MLSDC with the compact fine level: `sweeps`
+// iterations, or iterations until each lane's B-weighted fine residual meets
+// sdc_tol (a lane that has stopped is left out of the later iterations).
+hs_status cmp_mlsdc_step(hs_plan* P, hipStream_t s)
+{
+    HS_CHECK(cmp_begin_step(P, s));
+    const hs_problem& pb = P->pb;
+    if (pb.sweeps > 0) {
+        for (int k = 0; k < pb.sweeps; k++) HS_CHECK(cmp_mlsdc_iter(P, s));
+        for (int b : cmp_live(P, s)) {
+            double R = 0.0;
+            HS_CHECK(cmp_residual(P, b, s, &R));
+            HS_TRY(hsk::compact_ctl(P->ctl, b, 1, 0, 1, 0, HS_OK, s));
+        }
+    } else {
+        for (int k = 0;; k++) {
+            HS_CHECK(read_ctl(P, s));
+            const std::vector<int> live = cmp_live(P, s);
+            if (live.empty()) break;
+            for (int b : live) {
+                double R = 0.0;
+                HS_CHECK(cmp_residual(P, b, s, &R));
+                int state = 0, status = HS_OK;
+                if (R != R) { state = 2; status = HS_ENONFINITE; }
+                else if (R <= pb.sdc_tol) state = 1;
+                else if (k >= pb.max_sweeps) { state = 2; status = HS_ENOCONV; }
+                if (state != 0) HS_TRY(hsk::compact_ctl(P->ctl, b, 1, 0, state, 0, status, s));
+            }
+            HS_CHECK(cmp_mlsdc_iter(P, s));
+        }
+    }
+    HS_TRY(hsk::end_step(P->ctl, P->B, s));
+    return HS_OK;
+}
+
 hs_status begin_step(hs_plan* P, hipStream_t s)
 {
     if (P->compact) return cmp_begin_step(P, s);
@@ -1777,7 +1852,7 @@ hs_status begin_step(hs_plan* P, hipStream_t s)
 
 hs_status step(hs_plan* P, hipStream_t s)
 {
-    if (P->compact) return cmp_step(P, s);
+    if (P->compact) return P->nlev == 2 ? cmp_mlsdc_step(P, s) : cmp_step(P, s);
     HS_CHECK(begin_step(P, s));
     const hs_problem& pb = P->pb;
     int outcome;
@@ -1959,6 +2034,18 @@ hs_status hs_plan_bind(hs_plan* P, void* d_ws, size_t bytes, void* stream)
             keep.back()[i] = std::sin(3.14159265358979323846 * (double)(i + 1) / (double)(n + 1));
         HS_TRY(hipMemcpyAsync((void*)kv.first, keep.back().data(), n * sizeof(double),
                               hipMemcpyHostToDevice, s));
+    }
+    // B_h^{-1} tables of the compact MLSDC: tab[q n + i] = S_iq, S_iq = sqrt(2/(n+1)) sin(pi (i+1)(q+1)/(n+1)),
+    // then cos(pi (i+1)/(n+1))
+    for (auto& kv : P->dst_tab) {
+        const int n = kv.first;
+        keep.emplace_back((size_t)n * (n + 1));
+        std::vector<double>& t = keep.back();
+        for (int q = 0; q < n; q++)
+            for (int i = 0; i < n; i++)
+                t[(size_t)q * n + i] = std::sqrt(2.0 / (n + 1)) * std::sin(M_PI * (i + 1) * (q + 1) / (n + 1));
+        for (int i = 0; i < n; i++) t[(size_t)n * n + i] = std::cos(M_PI * (i + 1) / (n + 1));
+        HS_TRY(hipMemcpyAsync((void*)kv.second, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s));
     }
     if (!P->pb.lane_memory) HS_TRY(upload_set(P, P->all, s));   // else the lanes' pointers come later
     for (const MgSet* S : {&P->np_set.mg64[0], &P->np_set.mg32[0]}) {
@@ -2395,7 +2482,7 @@ hs_status hs_sdc_sweep(hs_plan* P, int32_t level, void* stream)
 hs_status hs_fas_restrict(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
-    if (P->nlev < 2) return HS_EINVAL;
+    if (P->nlev < 2 || P->compact) return HS_EINVAL;   // compact: inside hs_mlsdc_iter only
     HS_CHECK(refresh_run(P, (hipStream_t)stream));
     HS_TRY(fas_restrict(P, P->run, 0, (hipStream_t)stream));
     return HS_OK;
@@ -2404,7 +2491,7 @@ hs_status hs_fas_restrict(hs_plan* P, void* stream)
 hs_status hs_fas_interp(hs_plan* P, void* stream)
 {
     HS_CHECK(check_bound(P));
-    if (P->nlev < 2) return HS_EINVAL;
+    if (P->nlev < 2 || P->compact) return HS_EINVAL;   // compact: inside hs_mlsdc_iter only
     hipStream_t s = (hipStream_t)stream;
     HS_CHECK(refresh_run(P, s));
     HS_TRY(interp_level(P, P->run, 0, s));
@@ -2417,6 +2504,7 @@ hs_status hs_mlsdc_iter(hs_plan* P, void* stream)
     if (P->nlev < 2) return HS_EINVAL;
     int outcome;
     HS_CHECK(refresh_run(P, (hipStream_t)stream));
+    if (P->compact) return cmp_mlsdc_iter(P, (hipStream_t)stream);
     return mlsdc_iter(P, P->run, false, (hipStream_t)stream, &outcome);
 }
 

@@ -25,7 +25,9 @@ host and copied to HBM before any timed region.
   compact127 127^3, 5 nodes, nu 0.1, dt 0.05, 4 steps from u = s(x), sweeps
             until the collocation residual is <= 1e-10, V(2,1) to 1e-12: the
             compact fourth-order pair against the wide 13-point stencil, time
-            per step and the error against the exact solution s(x) cos t.
+            per step and the error against the exact solution s(x) cos t;
+            and two-level MLSDC with the compact fine level (coarse 63^3,
+            2nd order, 3 nodes, tricubic transfer).
   micro511  single-kernel rates on the finest grid of the 511^3 hierarchy
             (FP64 and the FP32 inner cycles of mixed precision) and of a
             batch of two 255^3 grids, from HIP events on each launch.
@@ -339,10 +341,11 @@ def compact127(args):
     u0 = _dev(s)
     exact = s * math.cos(steps * dt)
     res = {}
-    for name, order in (("compact", hs.HS_ORDER_COMPACT), ("wide", 4)):
+    for name, order, coarse in (("compact", hs.HS_ORDER_COMPACT, None), ("wide", 4, None),
+                                ("compact_mlsdc", hs.HS_ORDER_COMPACT, (63, 2, 3))):
         _log(f"compact127: {name}")
         plan = hs.Plan(hs.Problem(n=n, order=order, nnodes=M, nu=0.1, dt=dt, nsteps=steps, sweeps=0, sdc_tol=1e-10,
-                                  max_sweeps=40, tol=1e-12, max_cycles=60))
+                                  max_sweeps=40, tol=1e-12, max_cycles=60, coarse=coarse, fas_interp=3))
         plan.set_state(u0)
         plan.solve()
         plan.set_state(u0)

@@ -277,7 +277,7 @@ def test_compact_apply_rejects_invalid_arguments():
 
 
 @pytest.mark.parametrize("kw", [
-    dict(coarse=(7, 2, 3)),                                  # single level only
+    dict(coarse=(7, 2, 3), coarse2=(3, 2, 2)),              # one or two levels only
     dict(precision=heatst.HS_MIXED),                         # FP64 only
     dict(sdc_node_parallel=1),
     dict(batch=2, nslices=2, nsteps=2, coarse=(7, 2, 3)),
@@ -298,3 +298,14 @@ def test_compact_plan_sized_and_coarse_level_rejected():
     with pytest.raises(heatst.HeatstError) as e:
         base_problem(n=31, order=4, nnodes=3, coarse=(15, heatst.HS_ORDER_COMPACT, 3)).workspace_bytes()
     assert e.value.status == heatst.HS_EINVAL
+
+
+def test_compact_mlsdc_plan_adds_the_sine_table():
+    """Two-level MLSDC with the compact fine level lays out like the order-2
+    plan of the same levels plus one table for B_h^{-1}: the DST-I matrix and
+    the cosines, n (n + 1) values."""
+    n = 31
+    b = base_problem(n=n, order=heatst.HS_ORDER_COMPACT, nnodes=5, coarse=(15, 2, 3)).workspace_bytes()
+    b2 = base_problem(n=n, order=2, nnodes=5, coarse=(15, 2, 3)).workspace_bytes()
+    tab = (n * (n + 1) * 8 + 255) // 256 * 256
+    assert b2 + tab - 256 <= b <= b2 + tab + 256
