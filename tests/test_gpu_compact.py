@@ -318,3 +318,16 @@ def test_compact_mlsdc_tolerance_mode_parity(torch):
     assert stats[0]["total_sweeps"] == ost.total_sweeps > 2
     assert rel(got[0], ref) <= SDC_TOL
     assert stats[0]["last_sdc_res"] <= 1e-8
+
+
+def test_compact_mlsdc_127_one_iteration_parity(torch):
+    """The full 127^3/63^3 hierarchy: one compact MLSDC iteration (B_h^{-1}
+    through the sine basis at 127^3, two row tiles of its transform)."""
+    u0 = inputs.random_smooth(127, 15)
+    st, stats, got, refs = _compact_mlsdc_pair(torch, 127, 3, 63, 2, [u0], nsteps=1, sweeps=1, fas_interp=3)
+    ref, s, ost = refs[0]
+    assert np.isfinite(got[0]).all(), int((~np.isfinite(got[0])).sum())
+    print(f"rel {rel(got[0], ref):.3e}", flush=True)
+    assert st == 0 and s == oracle.OK
+    assert rel(got[0], ref) <= SDC_TOL
+    assert stats[0]["level_cycles"][0] == ost.total_cycles
