@@ -84,8 +84,8 @@ typedef enum { HS_FP64 = 0, HS_MIXED = 1 } hs_precision;
  * hs_solve, hs_begin_step, hs_sdc_sweep, hs_mlsdc_iter, hs_end_step,
  * hs_set_nodes with node values only, and the statistics, and rejects
  * hs_lap_apply, hs_heat_rhs, hs_mg_vcycle, hs_solve_graph, hs_fas_restrict,
- * hs_fas_interp and hs_set_nodes with d_FI (HS_EINVAL).  Its lanes run one
- * after another.
+ * hs_fas_interp and hs_set_nodes with d_FI on level 0 (HS_EINVAL).  Its lanes
+ * run one after another.
  */
 #define HS_ORDER_COMPACT (-4)
 

@@ -2451,7 +2451,7 @@ hs_status hs_set_nodes(hs_plan* P, int32_t level, const double* d_U, const doubl
     HS_CHECK(check_bound(P));
     if (P->pb.lane_memory) return HS_EINVAL;
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
-    if (P->compact && d_FI) return HS_EINVAL;   // its node array holds nu A_h U, set by the step itself
+    if (P->compact && level == 0 && d_FI) return HS_EINVAL;   // its node array holds nu A_h U, set by the step
     hipStream_t s = (hipStream_t)stream;
     int M = P->M[level];
     for (int b = 0; b < P->B; b++) {
@@ -2475,7 +2475,7 @@ hs_status hs_sdc_sweep(hs_plan* P, int32_t level, void* stream)
     if (level < 0 || level >= P->nlev) return HS_EINVAL;
     int outcome;
     HS_CHECK(refresh_run(P, (hipStream_t)stream));
-    if (P->compact) return cmp_sweep_all(P, (hipStream_t)stream);
+    if (P->compact && level == 0) return cmp_sweep_all(P, (hipStream_t)stream);
     return sweep(P, P->run, level, false, level == 0, (hipStream_t)stream, &outcome);
 }
 

@@ -331,3 +331,26 @@ def test_compact_mlsdc_127_one_iteration_parity(torch):
     assert st == 0 and s == oracle.OK
     assert rel(got[0], ref) <= SDC_TOL
     assert stats[0]["level_cycles"][0] == ost.total_cycles
+
+
+def test_compact_mlsdc_step_level_calls_match_solve(torch):
+    """begin_step, K hs_mlsdc_iter calls and end_step give the state that
+    hs_step gives with K iterations, bit for bit."""
+    from paper_1307_7867_amd import heatst as hs
+    nf, K = 15, 2
+    u0 = torch.from_numpy(inputs.random_smooth(nf, 16).ravel().copy()).cuda()
+    pb = hs.Problem(n=nf, order=hs.HS_ORDER_COMPACT, nnodes=5, coarse=(7, 2, 3), sweeps=K, nsteps=1, tol=1e-12)
+    a = hs.Plan(pb)
+    a.set_state(u0)
+    a.step()
+    b = hs.Plan(pb)
+    b.set_state(u0)
+    b.begin_step()
+    for _ in range(K):
+        b.mlsdc_iter()
+    b.end_step()
+    assert torch.equal(a.get_state(), b.get_state())
+    for call in (lambda: b.fas_restrict(), lambda: b.fas_interp()):
+        with pytest.raises(hs.HeatstError) as e:
+            call()
+        assert e.value.status == hs.HS_EINVAL
