@@ -52,7 +52,7 @@ typedef struct {
 
 typedef struct {
     int32_t n;      /* interior points per axis */
-    int32_t order;  /* 2 or 4, or OR_ORDER_COMPACT (single-level SDC only) */
+    int32_t order;  /* 2 or 4, or OR_ORDER_COMPACT (finest level of SDC or two-level MLSDC) */
     int32_t M;      /* collocation nodes including both ends */
 } or_level;
 
