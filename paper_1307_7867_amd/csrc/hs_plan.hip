@@ -1540,11 +1540,13 @@ hs_status refresh_run(hs_plan* P, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Single-level SDC with the compact pair (B-weighted form of eqs. (6)-(7)):
-// every substep solves (B - a A) U_{m+1} = rhs by V-cycles on the compact
-// operator, rediscretised on each coarser grid.  The lanes are taken one at a
-// time with launches over one grid; the host reads each solve's residual norm
-// back to stop it (the same rule as the second-order/fourth-order solves).
+// SDC with the compact pair (B-weighted form of eqs. (6)-(7)), and two-level
+// MLSDC with it on the fine level: every substep solves (B - a A) U_{m+1} =
+// rhs by V-cycles on the compact operator, rediscretised on each coarser grid.
+// The lanes are taken one at a time with launches over one grid; the stopping
+// test of each solve (the same rule as the second-order/fourth-order solves)
+// runs on the device, and the host reads the lane state at the predicted
+// cycle count.
 // ---------------------------------------------------------------------------
 
 // One V(nu1, nu2) cycle on grid l of lane `lane`'s hierarchy: the iterate in
